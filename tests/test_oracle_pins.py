@@ -1,0 +1,417 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test states the closed form, invariant or independent exact computation
+it uses.  None of them re-types the oracle's own formula.
+"""
+from __future__ import annotations
+
+from fractions import Fraction as Q
+
+import numpy as np
+import pytest
+
+import workloads as W
+from tests import exact_geometry as X
+
+CUBE_V = np.array([[0, 0, 0], [1, 0, 0], [1, 1, 0], [0, 1, 0],
+                   [0, 0, 1], [1, 0, 1], [1, 1, 1], [0, 1, 1]], float)
+CUBE_F = [[0, 3, 2, 1], [4, 5, 6, 7], [0, 1, 5, 4], [2, 3, 7, 6], [1, 2, 6, 5], [0, 4, 7, 3]]
+TET_F = [[1, 2, 3], [0, 3, 2], [0, 1, 3], [0, 2, 1]]
+
+
+# --------------------------------------------------------------------------
+# plane clipping and capping (Section 2.1)
+# --------------------------------------------------------------------------
+
+def test_clip_truncated_cube_closed_form(oracle_mod):
+    """|cube ∩ {m.x <= s}| = sum_v (-1)^{#upper} (s - m.v)_+^3 / (6 m1 m2 m3)."""
+    rng = np.random.default_rng(1)
+    for _ in range(200):
+        m = rng.integers(-7, 8, size=3)
+        m[m == 0] = 3
+        lo = sum(min(0, x) for x in m)
+        hi = sum(max(0, x) for x in m)
+        s = Q(int(rng.integers(0, 64)), 64) * (hi - lo) + lo
+        exact = X.truncated_box_volume(m, s)
+        got = oracle_mod.clip_volume(CUBE_V, CUBE_F, [list(m) + [float(s)]])
+        assert abs(got - float(exact)) <= 1e-15, (m, s, got, exact)
+
+
+def test_clip_degenerate_planes(oracle_mod):
+    """Planes through faces, edges and vertices: closed half-spaces."""
+    cases = [([1, 0, 0, 1.0], 1.0), ([1, 0, 0, 0.0], 0.0), ([-1, 0, 0, 0.0], 1.0),
+             ([1, 1, 0, 1.0], 0.5), ([1, 1, 1, 0.0], 0.0), ([1, 1, 1, 3.0], 1.0),
+             ([0, 0, 1, 0.5], 0.5)]
+    for pl, v in cases:
+        assert oracle_mod.clip_volume(CUBE_V, CUBE_F, [pl]) == pytest.approx(v, abs=1e-15)
+
+
+def test_clip_tet_halfspace_divided_differences(oracle_mod):
+    """|T ∩ {n.x <= s}| / |T| = sum_i (s - h_i)_+^3 / prod_{j!=i} (h_j - h_i)
+    with h_i = n.v_i distinct (the B-spline / divided-difference form)."""
+    rng = np.random.default_rng(2)
+    for _ in range(200):
+        T = rng.random((4, 3))
+        if np.linalg.det(T[1:] - T[0]) < 0:
+            T[[1, 2]] = T[[2, 1]]
+        n = rng.normal(size=3)
+        h = T @ n
+        s = rng.uniform(h.min(), h.max())
+        frac = 0.0
+        for i in range(4):
+            den = np.prod([h[j] - h[i] for j in range(4) if j != i])
+            frac += max(0.0, s - h[i]) ** 3 / den
+        vol = abs(np.linalg.det(T[1:] - T[0])) / 6
+        got = oracle_mod.clip_volume(T, TET_F, [list(n) + [s]])
+        assert got == pytest.approx(frac * vol, rel=1e-9, abs=1e-15)
+
+
+def test_clip_tet_by_box_exact_rational(oracle_mod):
+    """Tet ∩ box on dyadic data against the exact rational tet-splitting clipper."""
+    rng = np.random.default_rng(3)
+    for _ in range(60):
+        T = rng.integers(-8, 24, size=(4, 3)) / 16.0
+        d = np.linalg.det(T[1:] - T[0])
+        if d == 0:
+            continue
+        if d < 0:
+            T[[1, 2]] = T[[2, 1]]
+        lo = rng.integers(0, 8, size=3) / 16.0
+        hi = lo + rng.integers(2, 12, size=3) / 16.0
+        planes = X.box_planes(lo, hi)
+        exact = X.tet_halfspaces_volume(T, planes)
+        got = oracle_mod.clip_volume(T, TET_F, planes)
+        assert abs(got - float(exact)) <= 1e-15 * max(1.0, float(exact)), (T, lo, hi)
+        # and with an extra oblique plane
+        pl = [int(x) for x in rng.integers(-3, 4, size=3)] + [float(rng.integers(-8, 24) / 16.0)]
+        if any(pl[:3]):
+            exact2 = X.tet_halfspaces_volume(T, planes + [pl])
+            got2 = oracle_mod.clip_volume(T, TET_F, planes + [pl])
+            assert abs(got2 - float(exact2)) <= 1e-15, (T, lo, hi, pl)
+
+
+# --------------------------------------------------------------------------
+# mesh geometry and IDW (Section 2, eqs. 2.6-2.7)
+# --------------------------------------------------------------------------
+
+def test_geometry_boxes_and_tets(oracle_mod):
+    m = W.hex_mesh(3, 4, 5, (0, 0, 0), (1.5, 1.0, 0.5))
+    o = oracle_mod.Oracle(m)
+    V, xc, S, cf = o.geometry()
+    assert np.allclose(V, (1.5 / 3) * (1.0 / 4) * (0.5 / 5), rtol=1e-14)
+    assert np.allclose(xc, 0.5 * (m.cell_lo + m.cell_hi), atol=1e-15)
+    t = W.kuhn_tet_mesh(3, 0.2, 7)
+    ot = oracle_mod.Oracle(t)
+    V, xc, S, cf = ot.geometry()
+    P = t.points[t.cell_verts]
+    vol = np.einsum("ij,ij->i", P[:, 1] - P[:, 0],
+                    np.cross(P[:, 2] - P[:, 0], P[:, 3] - P[:, 0])) / 6
+    assert (vol > 0).all()
+    assert np.allclose(V, vol, rtol=1e-12)
+    assert np.allclose(xc, P.mean(1), atol=1e-14)
+    assert V.sum() == pytest.approx(1.0, rel=1e-13)
+    # closed cells: sum of signed outward area vectors vanishes
+    acc = np.zeros((t.n_cells, 3))
+    np.add.at(acc, t.owner, S)
+    np.add.at(acc, t.neighbour, -S[:t.n_internal])
+    assert np.abs(acc).max() < 1e-15
+    # owner -> neighbour orientation
+    d = xc[t.neighbour] - xc[t.owner[:t.n_internal]]
+    assert ((d * S[:t.n_internal]).sum(1) > 0).all()
+
+
+def test_idw_constant_and_symmetric(oracle_mod):
+    m = W.hex_mesh(4, 4, 4)
+    o = oracle_mod.Oracle(m)
+    Up = o.set_velocity(np.tile([0.3, -1.25, 2.0], (m.n_cells, 1)), np.zeros(m.n_faces))
+    assert np.abs(Up - [0.3, -1.25, 2.0]).max() <= 4 * 2.0 * np.finfo(float).eps
+    # interior point of a uniform grid: 8 equidistant cells, linear field exact
+    V, xc, S, cf = o.geometry()
+    phi = 0.7 + xc @ np.array([1.0, -2.0, 0.5])
+    pv = o.point_values(phi)
+    interior = np.all((m.points > 1e-9) & (m.points < 1 - 1e-9), axis=1)
+    exact = 0.7 + m.points @ np.array([1.0, -2.0, 0.5])
+    assert np.abs(pv[interior] - exact[interior]).max() < 1e-14
+
+
+def test_nag_exact_for_linear_fields(oracle_mod):
+    """Eqs. 2.6-2.12 reproduce the gradient of a linear field on uniform-hex
+    cells whose points are all interior (symmetric IDW, centroid face values)."""
+    m = W.hex_mesh(6, 6, 6)
+    o = oracle_mod.Oracle(m)
+    V, xc, S, cf = o.geometry()
+    g = np.array([0.3, -1.7, 2.2])
+    phi = 0.1 + xc @ g
+    G = o.nag_gradient(phi)
+    inner = np.all((m.cell_lo > 1e-9) & (m.cell_hi < 1 - 1e-9), axis=1)
+    assert np.abs(G[inner] - g).max() < 1e-12
+
+
+# --------------------------------------------------------------------------
+# flux polyhedra (eqs. 2.16-2.19) and flux correction (Section 2.3)
+# --------------------------------------------------------------------------
+
+def test_uniform_translation_prism(oracle_mod):
+    """Uniform translation sweeps exact prisms: V_f(lam) = lam dt U.S_f."""
+    t = W.kuhn_tet_mesh(3, 0.2, 11)
+    o = oracle_mod.Oracle(t)
+    V, xc, S, cf = o.geometry()
+    U = np.array([0.4, -0.9, 0.25])
+    o.set_point_velocity(np.tile(U, (t.n_points, 1)), S @ U)
+    for f in range(0, t.n_faces, 7):
+        for lam in (0.3, 1.0, 1.7):
+            v = o.flux_volume(f, 0.01, 1.0, lam)
+            assert v == pytest.approx(lam * 0.01 * (U @ S[f]), rel=1e-12, abs=1e-18)
+
+
+def _cube_dilation(oracle_mod, kappa):
+    m = W.hex_mesh(1, 1, 1)
+    o = oracle_mod.Oracle(m)
+    V, xc, S, cf = o.geometry()
+    Up = (m.points - xc[0])     # delta_p = -kappa (x_p - x_c) with dt = kappa
+    return m, o, Up
+
+
+def test_dilation_identity(oracle_mod):
+    """delta_p = -kappa (x_p - x_c) on one cube: sum_f V_f(lam) =
+    V_c (1 - (1 - lam kappa)^3), each face a sixth by symmetry."""
+    kappa = 0.37
+    m, o, Up = _cube_dilation(oracle_mod, kappa)
+    o.set_point_velocity(Up, np.zeros(m.n_faces))
+    for lam in (0.1, 0.5, 1.0, 1.9):
+        vols = [o.flux_volume(f, kappa, 1.0, lam) for f in range(6)]
+        exact = 1.0 - (1.0 - lam * kappa) ** 3
+        assert sum(vols) == pytest.approx(exact, rel=1e-14)
+        assert np.allclose(vols, exact / 6, rtol=1e-13)
+
+
+def test_dilation_correction_closed_form_root(oracle_mod):
+    """Corrected lam for a prescribed face flux: V/6 (1 - (1 - lam k)^3) = F dt,
+    so lam = (1 - (1 - 6 F dt / V)^(1/3)) / k."""
+    kappa = 0.2
+    m, o, Up = _cube_dilation(oracle_mod, kappa)
+    Fdt = np.array([0.01, 0.02, 0.05, 0.08, 0.03, 0.001])
+    dt = kappa
+    o.set_point_velocity(Up, Fdt / dt)
+    lam, it, st, bad = o.flux_correction(dt, 1.0)
+    exact = (1 - (1 - 6 * Fdt) ** (1 / 3)) / kappa
+    assert bad == 0
+    assert np.allclose(lam, exact, rtol=1e-13)
+
+
+def test_discrete_reynolds_identity(oracle_mod):
+    """At lam = 1, sum_f sgn_cf V_f = V_c - |backtracked cell|; the swept
+    sides cancel between neighbouring faces.  The backtracked cell's volume
+    is taken here from its fan-triangulated faces (about the mean of each
+    face's swept points) by the divergence theorem."""
+    t = W.kuhn_tet_mesh(2, 0.2, 5)
+    o = oracle_mod.Oracle(t)
+    V, xc, S, cf = o.geometry()
+    rng = np.random.default_rng(9)
+    Up = rng.normal(scale=0.05, size=(t.n_points, 3))
+    o.set_point_velocity(Up, np.ones(t.n_faces))
+    dt = 1.0
+    q = t.points - dt * Up
+    vf = np.array([o.flux_volume(f, dt, 1.0, 1.0) for f in range(t.n_faces)])
+    net = np.zeros(t.n_cells)
+    np.add.at(net, t.owner, vf)
+    np.add.at(net, t.neighbour, -vf[:t.n_internal])
+    back = np.zeros(t.n_cells)
+    for f in range(t.n_faces):
+        ids = t.face_points[t.face_offsets[f]:t.face_offsets[f + 1]]
+        cq = q[ids].mean(0)
+        contrib = 0.0
+        for i in range(len(ids)):
+            a, b = q[ids[i]], q[ids[(i + 1) % len(ids)]]
+            contrib += np.dot(cq, np.cross(a, b)) / 6
+        back[t.owner[f]] += contrib
+        if f < t.n_internal:
+            back[t.neighbour[f]] -= contrib
+    assert np.abs(net - (V - back)).max() < 1e-15
+
+
+def _perturbed_sweep(oracle_mod, radius, seed):
+    m = W.hex_mesh(5, 5, 5)
+    o = oracle_mod.Oracle(m)
+    V, xc, S, cf = o.geometry()
+    rng = np.random.default_rng(seed)
+    U = np.array([0.5, 0.4, 0.3])
+    h = 1.0 / 5
+    dt = 0.5 * h / np.abs(U).max()
+    d = rng.normal(size=(m.n_points, 3))
+    d *= (rng.random((m.n_points, 1)) ** (1 / 3)) / np.linalg.norm(d, axis=1)[:, None]
+    Up = U + d * radius * h / dt        # swept points moved within a ball
+    F0 = S @ U
+    o.set_point_velocity(Up, F0)
+    lam, it, st, bad = o.flux_correction(dt, 1.0)
+    res = np.array([abs(o.flux_volume(f, dt, 1.0, lam[f]) - F0[f] * dt) / abs(F0[f] * dt)
+                    for f in range(m.n_faces)])
+    return F0, lam, it, st, bad, res
+
+
+def test_correction_robust_to_perturbation(oracle_mod):
+    """Swept points perturbed randomly (Section 2.3 tests up to 20 % of the face
+    length) at Co 0.5.  Up to a ball of radius h/(5 sqrt 3) every face converges
+    to machine tolerance in 3-5 secant iterations on average, as the paper
+    reports; at radius h/5 the few faces whose swept face collapses cannot
+    reach the target on the monotone branch and are flagged (status 1), while
+    all others still converge."""
+    for seed in range(2):
+        F0, lam, it, st, bad, res = _perturbed_sweep(oracle_mod, 0.2 / np.sqrt(3), seed)
+        assert bad == 0
+        assert res[F0 != 0].max() < 1e-13
+        assert 3 <= it[F0 != 0].mean() <= 5
+        F0, lam, it, st, bad, res = _perturbed_sweep(oracle_mod, 0.2, seed)
+        ok = (F0 != 0) & (st == 0)
+        assert bad == (st == 1).sum() and bad < 0.02 * (F0 != 0).sum()
+        assert res[ok].max() < 1e-13
+        assert (res[st == 1] > 1e-3).all()
+
+
+# --------------------------------------------------------------------------
+# reconstruction: positioning (Algorithm 1)
+# --------------------------------------------------------------------------
+
+def test_positioning_reproduces_alpha_box(oracle_mod):
+    """The positioned plane cuts the exact volume fraction: checked with the
+    truncated-box closed form in exact arithmetic."""
+    m = W.hex_mesh(4, 4, 4)
+    o = oracle_mod.Oracle(m)
+    rng = np.random.default_rng(5)
+    alpha = rng.uniform(0.001, 0.999, m.n_cells)
+    rec = o.reconstruct(alpha)
+    h = 0.25
+    for c in range(0, m.n_cells, 5):
+        if rec["cls"][c] != 1:
+            continue
+        n = rec["n"][c]
+        if np.any(n == 0):
+            continue
+        frac = X.truncated_box_volume([Q(x) for x in n], Q(rec["s"][c]),
+                                      [Q(x) for x in m.cell_lo[c]],
+                                      [Q(x) for x in m.cell_hi[c]]) / Q(h) ** 3
+        assert abs(float(frac) - alpha[c]) < 1e-13
+
+
+def test_positioning_tet_closed_form(oracle_mod):
+    t = W.kuhn_tet_mesh(2, 0.2, 3)
+    o = oracle_mod.Oracle(t)
+    V, xc, S, cf = o.geometry()
+    rng = np.random.default_rng(6)
+    alpha = rng.uniform(0.01, 0.99, t.n_cells)
+    rec = o.reconstruct(alpha)
+    for c in range(t.n_cells):
+        if rec["cls"][c] != 1:
+            continue
+        P = t.points[t.cell_verts[c]]
+        hh = P @ rec["n"][c]
+        s = rec["s"][c]
+        frac = 0.0
+        for i in range(4):
+            den = np.prod([hh[j] - hh[i] for j in range(4) if j != i])
+            frac += max(0.0, s - hh[i]) ** 3 / den
+        assert frac == pytest.approx(alpha[c], abs=1e-9)
+
+
+def test_axis_aligned_normal_by_symmetry(oracle_mod):
+    m = W.hex_mesh(8, 8, 8)
+    o = oracle_mod.Oracle(m)
+    lo, hi = m.cell_lo[:, 1], m.cell_hi[:, 1]
+    alpha = np.clip((np.minimum(hi, 0.4) - lo) / (hi - lo), 0, 1)
+    rec = o.reconstruct(alpha)
+    sel = rec["cls"] == 1
+    assert sel.any()
+    assert np.abs(rec["n"][sel] - [0, 1, 0]).max() < 1e-14
+    assert np.abs(rec["s"][sel] - 0.4).max() < 1e-14
+
+
+# --------------------------------------------------------------------------
+# phase flux (eqs. 2.22-2.23) and update (eq. 2.2)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("meshkind", ["hex", "tet"])
+def test_partition_of_unity(oracle_mod, meshkind):
+    """sum_c |T ∩ C_c| = |T| for tets inside the domain."""
+    m = W.hex_mesh(4, 4, 4) if meshkind == "hex" else W.kuhn_tet_mesh(3, 0.2, 8)
+    o = oracle_mod.Oracle(m)
+    rng = np.random.default_rng(7)
+    for _ in range(10):
+        T = 0.2 + 0.6 * rng.random((4, 3))
+        vol = abs(np.linalg.det(T[1:] - T[0])) / 6
+        tot = sum(o.tet_cell_volume(T, c) for c in range(m.n_cells))
+        assert tot == pytest.approx(vol, rel=1e-12, abs=1e-17)
+
+
+def test_slab_translation_whole_step_closed_form(oracle_mod):
+    """An axis-aligned slab moved along its normal stays exact step after step,
+    including the empty-inflow and outflow boundaries."""
+    w = W.translate_slab(16, 1, a=0.3, b=0.55, U=(0.25, 0.0, 0.0), steps=40)
+    o = oracle_mod.Oracle(w.mesh)
+    o.set_velocity(w.U0c, w.F0)
+    a = w.alpha0.copy()
+    for k in range(0, 40, 10):
+        a, st, _, _ = o.advect(a, w.dt[k:k + 10], w.scale[k:k + 10])
+        assert np.abs(a - W.slab_exact(w, k + 10)).max() < 1e-13
+
+
+def test_diagonal_plane_translation_3d(oracle_mod):
+    """Plane x+y+z < c moved along (1,1,1): symmetry makes the NAG normal exact,
+    so one step reproduces the exact fractions away from the boundary."""
+    n = 10
+    m = W.hex_mesh(n, n, n)
+    o = oracle_mod.Oracle(m)
+    V, xc, S, cf = o.geometry()
+    import workloads.fields as Fd
+    U = np.array([1.0, 1.0, 1.0]) * 0.3
+    F0 = Fd.flux_constant(m, U)
+    o.set_velocity(np.tile(U, (m.n_cells, 1)), F0)
+    dt = 0.4 / n / 0.3
+
+    def exact(c0):
+        out = np.empty(m.n_cells)
+        for i in range(m.n_cells):
+            out[i] = float(X.truncated_box_volume([1, 1, 1], Q(c0), m.cell_lo[i], m.cell_hi[i])
+                           ) * n ** 3
+        return out
+    c0 = 1.37
+    a0 = exact(c0)
+    r = o.step(a0, dt, 1.0)
+    ex = exact(c0 + 3 * 0.3 * dt)
+    inner = np.all((m.cell_lo > 2.5 / n) & (m.cell_hi < 1 - 2.5 / n), axis=1)
+    assert np.abs(r["alpha"] - ex)[inner].max() < 1e-13
+
+
+def test_disc2d_conservation_boundedness(oracle_mod):
+    w = W.disc2d()
+    o = oracle_mod.Oracle(w.mesh)
+    V, _, _, _ = o.geometry()
+    o.set_velocity(w.U0c, w.F0)
+    a, st, lam, vp = o.advect(w.alpha0, w.dt, w.scale, check_leak=True)
+    m0 = (w.alpha0 * V).sum()
+    assert abs((a * V).sum() + st["ledger"] - m0) <= 1e-12 * m0
+    assert a.min() > -1e-12 and a.max() < 1 + 1e-12
+    assert st["max_leak"] < 1e-13
+    assert st["max_corr_residual"] < 1e-13
+    assert st["n_clip_errors"] == 0
+
+
+def test_trivial_faces_full_stencil(oracle_mod):
+    """A face whose stencil is all full carries exactly F dt; all empty, 0."""
+    m = W.hex_mesh(6, 6, 6)
+    o = oracle_mod.Oracle(m)
+    import workloads.fields as Fd
+    U = np.array([0.2, 0.1, -0.1])
+    F0 = Fd.flux_constant(m, U)
+    o.set_velocity(np.tile(U, (m.n_cells, 1)), F0)
+    alpha = np.ones(m.n_cells)
+    rec = o.reconstruct(alpha)
+    lam, *_ = o.flux_correction(0.1, 1.0)
+    ph = o.phase_flux(0.1, 1.0, lam, alpha)
+    ni = m.n_internal
+    assert np.array_equal(ph["vphase"][:ni], F0[:ni] * 0.1)
+    assert (ph["kind"][:ni] == 2).all()
+    ph0 = o.phase_flux(0.1, 1.0, lam, np.zeros(m.n_cells))
+    o.reconstruct(np.zeros(m.n_cells))
+    ph0 = o.phase_flux(0.1, 1.0, lam, np.zeros(m.n_cells))
+    assert (ph0["vphase"] == 0).all()
+    del rec

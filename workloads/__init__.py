@@ -1,0 +1,134 @@
+"""Seeded synthetic workloads for the geometric PLIC VoF flux path.
+
+A workload is a mesh plus everything the advection needs as input: the initial
+volume fraction, the cell-centred reference velocity U0_c, the reference face
+flux F0_f (discretely divergence free, eq. 2.4) and a time-step schedule in
+which step n uses velocity scale[n] * U0 and flux scale[n] * F0 with step
+length dt[n].  Both the oracle and the GPU library are fed the same arrays.
+
+Workloads (sizes as in the paper's advection tests, Section 4.2):
+  disc2d      64x64x1 hex layer, disc r=0.15 at (0.5, 0.75), U=(1, 0.5, 0),
+              Co 0.5, 50 steps
+  deform3d    N^3 hex (N=128 for the full case), sphere r=0.15 at
+              (0.35, 0.35, 0.35), deformation field (eq. 4.6) with
+              cos(pi t/T), T=3, Co 0.5 (dt = 1/(4N))
+  rotate_tets jittered Kuhn tets on an N^3 lattice (N=80 full), slotted sphere
+              r=0.15 at (0.5, 0.75, 0.5), slot width 0.05, rigid rotation about
+              z through (0.5, 0.5) at 2 pi per unit time, Co 0.5
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import fields
+from .meshes import Mesh, hex_mesh, kuhn_tet_mesh, single_cell_mesh  # noqa: F401
+
+
+@dataclass
+class Workload:
+    name: str
+    mesh: Mesh
+    alpha0: np.ndarray      # (C,)
+    U0c: np.ndarray         # (C, 3)
+    F0: np.ndarray          # (F,)
+    dt: np.ndarray          # (N,)
+    scale: np.ndarray       # (N,)
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_steps(self) -> int:
+        return int(self.dt.shape[0])
+
+
+def disc2d(n: int = 64, steps: int = 50) -> Workload:
+    """Disc r=0.15 at (0.5, 0.75) on an n x n x 1 layer, U = (1, 0.5, 0), Co 0.5."""
+    h = 1.0 / n
+    m = hex_mesh(n, n, 1, (0.0, 0.0, 0.0), (1.0, 1.0, h))
+    a0 = fields.disc_square_fraction((0.5, 0.75), 0.15, m.cell_lo[:, :2], m.cell_hi[:, :2])
+    U = np.array([1.0, 0.5, 0.0])
+    Uc = np.broadcast_to(U, (m.n_cells, 3)).copy()
+    F0 = fields.flux_constant(m, U)
+    dt = 0.5 * h / np.sqrt(1.25)
+    return Workload("disc2d", m, a0, Uc, F0, np.full(steps, dt), np.ones(steps),
+                    meta={"n": n, "co": 0.5, "U": U.tolist()})
+
+
+def deform3d(n: int = 128, steps: int | None = None, T: float = 3.0,
+             centre=(0.35, 0.35, 0.35), radius: float = 0.15) -> Workload:
+    """Sphere in the periodic deformation field (eq. 4.6), fixed dt = 1/(4n).
+
+    max |U0| over mesh points is 2, so dt = 0.5 h / 2 gives Co 0.5.  Step n uses
+    scale cos(pi (t_n + dt/2) / T).  The default step count reaches T.
+    """
+    m = hex_mesh(n, n, n)
+    a0 = fields.ball_box_fraction(centre, radius, m.cell_lo, m.cell_hi)
+    Uc = fields.deformation_velocity(m.cell_centroids())
+    F0 = fields.flux_deformation(m)
+    dt = 1.0 / (4 * n)
+    N = int(round(T / dt)) if steps is None else steps
+    t = (np.arange(N) + 0.5) * dt
+    return Workload("deform3d", m, a0, Uc, F0, np.full(N, dt), np.cos(np.pi * t / T),
+                    meta={"n": n, "T": T, "co": 0.5, "centre": list(centre), "radius": radius})
+
+
+def slotted_sphere_inside(x, centre=(0.5, 0.75, 0.5), radius=0.15, slot_half=0.025,
+                          slot_top=0.85):
+    """Ball minus the slot {|x - cx| <= w/2, y <= slot_top} (all z)."""
+    c = np.asarray(centre)
+    ball = ((x - c) ** 2).sum(-1) <= radius * radius
+    slot = (np.abs(x[..., 0] - c[0]) <= slot_half) & (x[..., 1] <= slot_top)
+    return ball & ~slot
+
+
+def rotate_tets(n: int = 80, steps: int | None = None, seed: int = 1305,
+                sample: int = 12) -> Workload:
+    """Slotted sphere rotating about z through (0.5, 0.5) on jittered Kuhn tets.
+
+    omega = 2 pi; max |U0| at the domain corners is omega*sqrt(0.5); the shortest
+    lattice spacing after jitter is about 0.6 h, so dt = 1/(9n) keeps Co <= 0.5.
+    The default step count is one revolution.
+    """
+    m = kuhn_tet_mesh(n, 0.2, seed)
+    a0 = fields.tet_fraction_sampled(m, slotted_sphere_inside, sample)
+    omega = 2.0 * np.pi
+    origin = np.array([0.5, 0.5, 0.5])
+    Uc = fields.rotation_velocity(m.cell_centroids(), omega, origin)
+    F0 = fields.flux_rotation(m, omega, origin)
+    N = 9 * n if steps is None else steps
+    dt = 1.0 / (9 * n)
+    return Workload("rotate_tets", m, a0, Uc, F0, np.full(N, dt), np.ones(N),
+                    meta={"n": n, "seed": seed, "omega": omega})
+
+
+def translate_slab(n: int = 16, nz: int = 1, a: float = 0.3, b: float = 0.55,
+                   U=(0.25, 0.0, 0.0), steps: int = 8, dt: float | None = None) -> Workload:
+    """Axis-aligned slab {a < x < b} moved along +x by a uniform velocity.
+
+    The exact solution after k steps is the cell fraction of
+    {a + u t_k < x < b + u t_k}; used as a whole-step closed form.
+    """
+    m = hex_mesh(n, n, nz, (0.0, 0.0, 0.0), (1.0, 1.0, nz / n))
+    lo, hi = m.cell_lo[:, 0], m.cell_hi[:, 0]
+    a0 = np.clip((np.minimum(hi, b) - np.maximum(lo, a)) / (hi - lo), 0.0, 1.0)
+    U = np.asarray(U, dtype=np.float64)
+    Uc = np.broadcast_to(U, (m.n_cells, 3)).copy()
+    F0 = fields.flux_constant(m, U)
+    if dt is None:
+        dt = 0.5 / n / np.linalg.norm(U)
+    return Workload("slab", m, a0, Uc, F0, np.full(steps, dt), np.ones(steps),
+                    meta={"a": a, "b": b, "U": U.tolist(), "n": n})
+
+
+def slab_exact(w: Workload, k: int) -> np.ndarray:
+    """Exact cell fractions of the translated slab after k steps."""
+    t = float(np.sum(w.dt[:k] * w.scale[:k]))
+    u = w.meta["U"][0]
+    a = w.meta["a"] + u * t
+    b = w.meta["b"] + u * t
+    lo, hi = w.mesh.cell_lo[:, 0], w.mesh.cell_hi[:, 0]
+    return np.clip((np.minimum(hi, b) - np.maximum(lo, a)) / (hi - lo), 0.0, 1.0)
+
+
+WORKLOADS = {"disc2d": disc2d, "deform3d": deform3d, "rotate_tets": rotate_tets}
