@@ -1,0 +1,216 @@
+/*
+ * vof.h -- C ABI of the MI355X geometric PLIC VoF flux library.
+ *
+ * The library advances a volume fraction field alpha on an unstructured
+ * finite-volume mesh with the geometric, directionally unsplit PLIC method of
+ * Maric, Marschall & Bothe (arXiv:1305.3417, "voFoam"), Section 2.  One time
+ * step is the five-part path:
+ *
+ *   1. backtrack every mesh point along its discrete Lagrangian trajectory
+ *      x' = x - U_p dt (eq. 2.16), with U_p interpolated from cell velocities
+ *      by inverse distance weighting (eqs. 2.6-2.7);
+ *   2. build one flux polyhedron per face from the face and its swept image,
+ *      its volume taken by tetrahedral decomposition (eqs. 2.18-2.19);
+ *   3. correct each polyhedron iteratively, moving the swept end points along
+ *      their trajectories until its signed volume equals F_f dt (eq. 2.17;
+ *      Section 2.3), without topology changes;
+ *   4. fit a PLIC plane in every interface cell (Algorithm 1: NAG gradient,
+ *      eqs. 2.6-2.12, and iterative positioning, Section 2.2.2);
+ *   5. intersect every flux polyhedron with the cells of its stencil and
+ *      their PLIC half-spaces (eqs. 2.22-2.23) and apply the conservative
+ *      update alpha_c -= (1/V_c) sum_f sgn_cf V_{f,alpha} (eqs. 2.2, 2.5).
+ *
+ * All arithmetic is IEEE double precision on the GPU.
+ *
+ * Conventions for every entry point:
+ *  - Pointers are host or device pointers as stated by a `memory` argument
+ *    (VOF_HOST or VOF_DEVICE).  The caller owns every buffer it passes; the
+ *    library copies inputs before the call returns (host) or before the
+ *    enqueued work that reads them completes (device: keep the buffer alive
+ *    and unmodified until the next synchronising call).
+ *  - Device work is enqueued on the context's HIP stream, in call order.
+ *    vof_read_* and vof_get_stats synchronise that stream.
+ *  - No C++ exception and no abort crosses this interface.  Every function
+ *    returns a vof_status; on failure vof_last_error() describes it (a
+ *    thread-local string valid until the next call on the same thread).
+ *  - Device-side failures (capacity overflow, unreachable flux correction,
+ *    non-finite results) are latched in a flag word on the device and
+ *    reported by the next synchronising call.
+ *  - One context per host thread; calls on the same mesh must not overlap.
+ */
+#ifndef VOF_H
+#define VOF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t vof_status;
+
+#define VOF_OK 0
+#define VOF_EINVAL (-1)    /* bad argument                                      */
+#define VOF_EBADMESH (-2)  /* mesh failed validation                            */
+#define VOF_ENOMEM (-3)    /* device allocation failed                          */
+#define VOF_EDEVICE (-4)   /* HIP runtime error; destroy the context             */
+#define VOF_ENUMERIC (-5)  /* flux correction could not reach F dt on its branch,
+                              or a non-finite value was produced                 */
+#define VOF_ESTENCIL (-6)  /* a flux polyhedron left its stencil (leak check)   */
+#define VOF_ECAPACITY (-8) /* a clipped polytope exceeded its vertex capacity   */
+
+#define VOF_HOST 0
+#define VOF_DEVICE 1
+
+typedef struct vof_context vof_context;
+typedef struct vof_mesh vof_mesh;
+
+/* Create a context on HIP device `device`; all work goes on `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  The stream must outlive the
+ * context. */
+vof_status vof_context_create(int32_t device, void *hip_stream, vof_context **out);
+vof_status vof_context_destroy(vof_context *ctx);
+/* Thread-local description of the last failure on this thread. */
+const char *vof_last_error(void);
+/* Library version string. */
+const char *vof_version(void);
+
+/* Unstructured mesh in owner/neighbour face addressing (Section 2):
+ * points are stored once; a face is an ordered list of point indices; the
+ * owner of a face has the lower cell index; the right-hand rule on the
+ * point order gives an area vector S_f pointing out of the owner into the
+ * neighbour.  Internal faces (with a neighbour) come first: faces
+ * [0, n_internal) are internal, [n_internal, n_faces) are boundary faces
+ * whose S_f points out of the domain.  Cells must be convex with planar
+ * faces; faces have 3..VOF_MAX_FACE_POINTS points. */
+#define VOF_MAX_FACE_POINTS 8
+typedef struct {
+  int64_t n_points, n_cells, n_faces, n_internal;
+  const double *points;        /* 3 * n_points, x y z interleaved          */
+  const int64_t *face_offsets; /* n_faces + 1                              */
+  const int32_t *face_points;  /* face_offsets[n_faces]                    */
+  const int32_t *owner;        /* n_faces                                  */
+  const int32_t *neighbour;    /* n_internal                               */
+  int32_t memory;              /* VOF_HOST or VOF_DEVICE for all arrays    */
+} vof_mesh_desc;
+
+typedef struct {
+  int64_t n_points, n_cells, n_faces, n_internal;
+  int64_t stencil_entries;     /* sum over faces of the flux stencil size   */
+  int32_t max_face_points;
+  int32_t max_cell_faces;
+  int64_t device_bytes;        /* device memory held by the mesh            */
+} vof_mesh_info;
+
+/* Validate the mesh on the host (index ranges, owner < neighbour, face
+ * sizes), copy it to the device, and precompute the derived addressing and
+ * geometry: cell -> faces with owner/neighbour signs (eq. 2.5), point ->
+ * cells, face area vectors and centres, cell volumes and centroids,
+ * inverse-distance weights (eq. 2.7), cell face planes, and the flux stencil
+ * of every face (the cells of its points, Section 2.3).  Orientation of S_f
+ * against the owner -> neighbour direction is checked on the device.
+ * Errors: VOF_EINVAL, VOF_EBADMESH, VOF_ENOMEM, VOF_EDEVICE. */
+vof_status vof_mesh_upload(vof_context *ctx, const vof_mesh_desc *desc, vof_mesh **out);
+vof_status vof_mesh_destroy(vof_mesh *mesh);
+vof_status vof_mesh_get_info(const vof_mesh *mesh, vof_mesh_info *out);
+
+/* Method parameters.  Defaults: eps 1e-12 (interface band: eps < alpha <
+ * 1 - eps; the paper's "reconstruction tolerance", Section 4.2),
+ * correction_rtol 1e-15 (|V_f - F_f dt| <= rtol |F_f dt|), correction_max_iter
+ * 50, position_tol 1e-15 (|fill level - alpha| at the plane),
+ * position_max_iter 100, gradient_zero 1e-8 (|grad alpha| h_c below this makes
+ * an interface cell homogeneous), check_stencil 0 (1: also clip every
+ * flux tet against the empty cells of its stencil and flag any volume that
+ * leaves the stencil). */
+typedef struct {
+  double eps;
+  double correction_rtol;
+  int32_t correction_max_iter;
+  double position_tol;
+  int32_t position_max_iter;
+  double gradient_zero;
+  int32_t check_stencil;
+} vof_params;
+vof_status vof_get_params(const vof_mesh *mesh, vof_params *out);
+vof_status vof_set_params(vof_mesh *mesh, const vof_params *p);
+
+/* Volume fraction state, n_cells doubles. */
+vof_status vof_set_alpha(vof_mesh *mesh, const double *alpha, int32_t memory);
+vof_status vof_read_alpha(vof_mesh *mesh, double *out, int32_t memory);
+
+/* Reference velocity: U0c (3 * n_cells, x y z interleaved, cell-centred) and
+ * the reference face volumetric flux F0 (n_faces; discretely divergence
+ * free, eq. 2.4).  Step n of vof_advect uses scale[n] * U0c and
+ * scale[n] * F0.  The point velocities U0_p are interpolated here by inverse
+ * distance weighting (eqs. 2.6-2.7). */
+vof_status vof_set_velocity(vof_mesh *mesh, const double *U0c, const double *F0,
+                            int32_t memory);
+
+/* Step 4 alone on the current alpha: classify cells and fit the PLIC planes
+ * of the interface cells (Algorithm 1).  Results via vof_read_planes. */
+vof_status vof_reconstruct(vof_mesh *mesh);
+
+/* Advance alpha by n_steps explicit steps (steps 1-5 each); step n has length
+ * dt[n] and velocity / flux scale scale[n].  dt and scale are host arrays of
+ * n_steps doubles, copied before return.  Every step uses alpha^n for all of
+ * its geometry (explicit Euler, eq. 2.2). */
+vof_status vof_advect(vof_mesh *mesh, int32_t n_steps, const double *dt, const double *scale);
+
+/* Per-face results of the last step.  what: VOF_FACE_LAMBDA (double, the
+ * corrected sweep factor), VOF_FACE_VPHASE (double, V_{f,alpha}, signed like
+ * F_f), VOF_FACE_ITERS (uint8, correction iterations), VOF_FACE_KIND (uint8:
+ * 0 no flux, 1 trivially empty stencil, 2 trivially full stencil,
+ * 3 geometric), VOF_FACE_STATUS (uint8: 0 ok, 1 correction target not
+ * reachable on the monotone branch). */
+#define VOF_FACE_LAMBDA 0
+#define VOF_FACE_VPHASE 1
+#define VOF_FACE_ITERS 2
+#define VOF_FACE_KIND 3
+#define VOF_FACE_STATUS 4
+vof_status vof_read_face(vof_mesh *mesh, int32_t what, void *out, int32_t memory);
+
+/* Cell classes and planes of the last reconstruction: cls (int8, n_cells:
+ * 0 empty, 1 interface, 2 full, 3 interface with vanishing gradient, treated
+ * as homogeneous), normal (3 * n_cells doubles) and position s (n_cells) of
+ * the plane n.x = s; the phase occupies n.x <= s.  Any pointer may be NULL. */
+vof_status vof_read_planes(vof_mesh *mesh, int8_t *cls, double *normal, double *s,
+                           int32_t memory);
+
+/* Interpolated point velocities U0_p (3 * n_points doubles). */
+vof_status vof_read_point_velocity(vof_mesh *mesh, double *out, int32_t memory);
+
+typedef struct {
+  int64_t steps;              /* steps advanced since vof_set_alpha         */
+  int64_t face_fluxes;        /* sum over steps of faces with F_f != 0      */
+  int64_t geometric_faces;    /* sum over steps of faces clipped            */
+  int64_t interface_cells;    /* sum over steps of interface cells          */
+  int64_t fallback_cells;     /* sum over steps of vanishing-gradient cells */
+  int64_t unreached_faces;    /* corrections that hit the branch end        */
+  int64_t capacity_overflows; /* clipped polytopes beyond capacity          */
+  int64_t stencil_leaks;      /* flux tets leaving their stencil (if checked) */
+  int64_t correction_iters;   /* sum of correction iterations               */
+  double ledger;              /* sum of V_{f,alpha} over boundary faces      */
+  double mass;                /* sum_c V_c alpha_c (compensated)            */
+  double alpha_min, alpha_max;
+} vof_stats;
+/* Synchronises, computes mass and alpha range, and reports the counters.
+ * Returns VOF_ENUMERIC / VOF_ECAPACITY / VOF_ESTENCIL if the corresponding
+ * counter is non-zero (the stats are still filled in). */
+vof_status vof_get_stats(vof_mesh *mesh, vof_stats *out);
+vof_status vof_reset_stats(vof_mesh *mesh);
+
+/* Block the host until the mesh's enqueued work is done; surfaces latched
+ * device errors. */
+vof_status vof_synchronize(vof_mesh *mesh);
+
+/* Host self-test of the device geometry routines (compiled for the host as
+ * well): volume of the tetrahedron (a, b, c, d) (12 doubles) intersected with
+ * the half-spaces {n_k . x <= s_k} (4 doubles per plane).  Returns the volume
+ * (a flat tetrahedron may give a round-off sized negative value), or NaN on
+ * capacity overflow or a bad argument.  Needs no GPU. */
+double vof_selftest_tet_clip(const double *tet, int32_t n_planes, const double *planes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VOF_H */

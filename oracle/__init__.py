@@ -70,6 +70,9 @@ def lib():
         L.orc_point_values.argtypes = [vp, vp, vp]
         L.orc_nag_gradient.argtypes = [vp, vp, vp]
         L.orc_set_point_velocity.argtypes = [vp, vp, vp]
+        L.orc_reconstruct_subset.argtypes = [vp, vp, i64, vp]
+        L.orc_get_planes.argtypes = [vp, vp, vp, vp]
+        L.orc_faces_subset.argtypes = [vp, d, d, vp, i64, vp, vp, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -208,6 +211,30 @@ class Oracle:
         lib().orc_advect(self.h, _p(a), int(dt.shape[0]), _p(dt), _p(scale), int(check_leak),
                          C.byref(st), _p(lam), _p(vp))
         return a, st.as_dict(), lam, vp
+
+    # subsets (sampled checks of large runs) --------------------------------
+    def reconstruct_subset(self, alpha, cells):
+        alpha = np.ascontiguousarray(alpha, dtype=np.float64)
+        cells = np.ascontiguousarray(cells, dtype=np.int64)
+        lib().orc_reconstruct_subset(self.h, _p(alpha), cells.shape[0], _p(cells))
+        cls = np.empty(self.nc, dtype=np.int8)
+        n = np.empty((self.nc, 3))
+        s = np.empty(self.nc)
+        lib().orc_get_planes(self.h, _p(cls), _p(n), _p(s))
+        return {"cls": cls, "n": n, "s": s}
+
+    def faces_subset(self, dt, s, alpha, faces):
+        alpha = np.ascontiguousarray(alpha, dtype=np.float64)
+        faces = np.ascontiguousarray(faces, dtype=np.int64)
+        k = faces.shape[0]
+        lam = np.empty(k)
+        it = np.empty(k, dtype=np.int32)
+        st = np.empty(k, dtype=np.int8)
+        vp = np.empty(k)
+        kind = np.empty(k, dtype=np.int8)
+        lib().orc_faces_subset(self.h, float(dt), float(s), _p(alpha), k, _p(faces), _p(lam),
+                               _p(it), _p(st), _p(vp), _p(kind))
+        return {"lam": lam, "iters": it, "status": st, "vphase": vp, "kind": kind}
 
     # primitives -----------------------------------------------------------
     def cell_cut_volume(self, c, n, s):

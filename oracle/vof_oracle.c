@@ -988,3 +988,54 @@ void orc_set_point_velocity(omesh *M, const double *Up, const double *F0) {
   memcpy(M->Up, Up, sizeof(double) * 3 * M->np);
   if (F0) memcpy(M->F0, F0, sizeof(double) * M->nf);
 }
+
+/* ------------------------------------------------------------------ */
+/* subsets, for checking full-size runs on sampled outputs              */
+/* ------------------------------------------------------------------ */
+/* classes of every cell; NAG gradient and plane only for the listed cells */
+void orc_reconstruct_subset(omesh *M, const double *alpha, int64_t ncells, const int64_t *cells) {
+  for (int64_t c = 0; c < M->nc; ++c) {
+    double a = alpha[c];
+    M->cls[c] = a <= M->eps ? 0 : (a >= 1.0 - M->eps ? 2 : 1);
+  }
+  double *ap = malloc(sizeof(double) * M->np);
+  orc_point_values(M, alpha, ap);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t i = 0; i < ncells; ++i) {
+    int64_t c = cells[i];
+    if (M->cls[c] != 1) continue;
+    double g[3];
+    nag_gradient(M, c, alpha, ap, g);
+    memcpy(&M->grad[3 * c], g, 24);
+    double gn = v_norm(g);
+    if (gn * cbrt(M->V[c]) < 1e-8) { M->cls[c] = 3; continue; }
+    double n[3] = {-g[0] / gn, -g[1] / gn, -g[2] / gn};
+    memcpy(&M->pn[3 * c], n, 24);
+    int it = 0;
+    M->ps[c] = position_plane(M, c, n, alpha[c], &it);
+  }
+  free(ap);
+}
+
+void orc_get_planes(const omesh *M, int8_t *cls, double *nrm, double *spos) {
+  if (cls) memcpy(cls, M->cls, M->nc);
+  if (nrm) memcpy(nrm, M->pn, sizeof(double) * 3 * M->nc);
+  if (spos) memcpy(spos, M->ps, sizeof(double) * M->nc);
+}
+
+/* flux correction and phase volume for listed faces (planes of the cells in
+ * their stencils must have been reconstructed) */
+void orc_faces_subset(const omesh *M, double dt, double s, const double *alpha, int64_t nfaces,
+                      const int64_t *faces, double *lam, int32_t *iters, int8_t *status,
+                      double *vphase, int8_t *kind) {
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t i = 0; i < nfaces; ++i) {
+    int64_t f = faces[i];
+    int it = 0;
+    status[i] = (int8_t)correct_face(M, f, dt, s, &lam[i], &it);
+    iters[i] = it;
+    int kd = 0, er = 0;
+    phase_flux_face(M, f, dt, s, lam[i], alpha, 0, &vphase[i], &kd, &er);
+    kind[i] = (int8_t)kd;
+  }
+}

@@ -1,0 +1,232 @@
+// geom.hpp -- double-precision geometry for the flux path, usable on the GPU and
+// on the host (for the self-test entry point).
+//
+// Volumes of convex pieces of tetrahedra are what the phase flux needs
+// (eqs. 2.22-2.23): a flux polyhedron is a signed sum of tetrahedra with apex
+// at the face centre, and every tetrahedron is intersected with the planes of
+// a stencil cell and, in interface cells, the PLIC half-space.  Two tools:
+//
+//  * tet_kept_fraction: the fraction of a tetrahedron on the kept side of one
+//    plane as a function of the four signed vertex distances alone (affine
+//    invariance), with no division by near-equal height differences.
+//  * Poly: a convex polytope whose vertices all have exactly three
+//    neighbours (a simple polytope), clipped plane by plane.  Each clip adds
+//    one vertex per cut edge and links the new vertices around the cap by
+//    walking the faces through the removed vertices.  The volume is summed
+//    over the faces, each walked once and fanned from its first vertex.
+//    Closed half-spaces: vertices on the plane are kept, so exactly
+//    coplanar cell faces, face edges and sweep vectors need no tolerance.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#define VHD __host__ __device__ __forceinline__
+
+namespace vof {
+
+struct v3 {
+  double x, y, z;
+};
+VHD v3 mk3(double x, double y, double z) { return v3{x, y, z}; }
+VHD v3 operator+(v3 a, v3 b) { return mk3(a.x + b.x, a.y + b.y, a.z + b.z); }
+VHD v3 operator-(v3 a, v3 b) { return mk3(a.x - b.x, a.y - b.y, a.z - b.z); }
+VHD v3 operator*(double s, v3 a) { return mk3(s * a.x, s * a.y, s * a.z); }
+VHD double dot(v3 a, v3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+VHD v3 cross(v3 a, v3 b) {
+  return mk3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+// six times the signed volume of the tetrahedron (0, a, b, c)
+VHD double det3(v3 a, v3 b, v3 c) { return dot(a, cross(b, c)); }
+VHD double dmin(double a, double b) { return a < b ? a : b; }
+VHD double dmax(double a, double b) { return a > b ? a : b; }
+
+// Fraction of a tetrahedron with signed vertex distances d[0..3] lying in the
+// closed half-space d >= 0.  With t_xy = d_x / (d_x - d_y) the position of the
+// cut on edge x -> y (x kept, y removed):
+//   one kept vertex a:          t_ab t_ac t_ad
+//   three kept (d removed):     1 - prod_j d_d / (d_d - d_j)
+//   two kept (a, b):            t_ac t_ad + t_ad t_bc (1 - t_ac) + t_bc t_bd (1 - t_ad)
+// (the last is the prism a, b | ac, ad, bc, bd cut into three tetrahedra).
+VHD double tet_kept_fraction(const double d[4]) {
+  int kept = 0, mk = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    if (d[i] >= 0.0) { ++kept; mk |= 1 << i; }
+  if (kept == 4) return 1.0;
+  if (kept == 0) return 0.0;
+  if (kept == 1) {
+    int a = __builtin_ctz(mk);
+    double da = d[a], f = 1.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (j != a) f *= da / (da - d[j]);
+    return f;
+  }
+  if (kept == 3) {
+    int r = __builtin_ctz(~mk & 15);
+    double dr = d[r], f = 1.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (j != r) f *= dr / (dr - d[j]);
+    return 1.0 - f;
+  }
+  int a = __builtin_ctz(mk);
+  int b = __builtin_ctz(mk & ~(1 << a));
+  int rm = ~mk & 15;
+  int c = __builtin_ctz(rm);
+  int e = __builtin_ctz(rm & ~(1 << c));
+  double tac = d[a] / (d[a] - d[c]), tad = d[a] / (d[a] - d[e]);
+  double tbc = d[b] / (d[b] - d[c]), tbd = d[b] / (d[b] - d[e]);
+  return tac * tad + tad * tbc * (1.0 - tac) + tbc * tbd * (1.0 - tad);
+}
+
+// ---------------------------------------------------------------------------
+// simple polytope as a vertex graph
+// ---------------------------------------------------------------------------
+// Vertex i has position (X, Y, Z) and neighbours NB(i,0..2) in counter-clockwise
+// order seen from outside.  Face F(i,k) is the wedge between edges i->NB(i,k)
+// and i->NB(i,k+1); walked counter-clockwise it passes NB(i,k+1) -> i -> NB(i,k).
+// Arriving at vertex v from u, the next vertex of the same face is
+// NB(v, (index of u in v) + 2 mod 3).
+//
+// Storage is strided so that a wavefront can keep one polytope per lane in
+// LDS with consecutive lanes in consecutive words.
+struct Poly {
+  double *px, *py, *pz, *ps;  // position and signed distance, element i at [i * st]
+  uint8_t *nb;                // neighbour (i, k) at [(3 i + k) * st]
+  uint8_t *aux;               // scratch byte per vertex at [i * st]
+  int st;                     // element stride
+  int nv;                     // vertex count
+  int cap;                    // vertex capacity
+
+  VHD double &X(int i) { return px[i * st]; }
+  VHD double &Y(int i) { return py[i * st]; }
+  VHD double &Z(int i) { return pz[i * st]; }
+  VHD double &SD(int i) { return ps[i * st]; }
+  VHD uint8_t &NB(int i, int k) { return nb[(3 * i + k) * st]; }
+  VHD uint8_t &AUX(int i) { return aux[i * st]; }
+  VHD v3 P(int i) { return mk3(X(i), Y(i), Z(i)); }
+  VHD void setP(int i, v3 p) { X(i) = p.x; Y(i) = p.y; Z(i) = p.z; }
+  VHD int slot(int v, int u) {  // index of neighbour u in vertex v
+    return NB(v, 0) == u ? 0 : (NB(v, 1) == u ? 1 : 2);
+  }
+
+  // positively oriented tetrahedron (a, b, c, d): det(b - a, c - a, d - a) > 0
+  VHD void init_tet(v3 a, v3 b, v3 c, v3 d) {
+    nv = 4;
+    setP(0, a); setP(1, b); setP(2, c); setP(3, d);
+    NB(0, 0) = 1; NB(0, 1) = 3; NB(0, 2) = 2;
+    NB(1, 0) = 0; NB(1, 1) = 2; NB(1, 2) = 3;
+    NB(2, 0) = 0; NB(2, 1) = 3; NB(2, 2) = 1;
+    NB(3, 0) = 0; NB(3, 1) = 1; NB(3, 2) = 2;
+  }
+
+  // Keep {x : n.x <= s}.  Returns false on capacity overflow or an
+  // inconsistent cap (the polytope must then be discarded by the caller).
+  VHD bool clip(v3 n, double s) {
+    if (nv == 0) return true;
+    bool anyneg = false, anypos = false;
+    for (int i = 0; i < nv; ++i) {
+      double d = s - (n.x * X(i) + n.y * Y(i) + n.z * Z(i));
+      SD(i) = d;
+      anyneg |= d < 0.0;
+      anypos |= d > 0.0;
+    }
+    if (!anyneg) return true;
+    if (!anypos) { nv = 0; return true; }
+    const int onv = nv;
+    int m = nv;
+    // one new vertex on every edge from a kept to a removed vertex
+    for (int u = 0; u < onv; ++u) {
+      double du = SD(u);
+      if (du < 0.0) continue;
+      for (int k = 0; k < 3; ++k) {
+        int v = NB(u, k);
+        if (v >= onv) continue;
+        double dv = SD(v);
+        if (dv >= 0.0) continue;
+        if (m >= cap) return false;
+        double t = du / (du - dv);
+        setP(m, mk3(X(u) + t * (X(v) - X(u)), Y(u) + t * (Y(v) - Y(u)),
+                    Z(u) + t * (Z(v) - Z(u))));
+        NB(m, 0) = (uint8_t)u;
+        NB(m, 1) = 255;
+        NB(m, 2) = 255;
+        AUX(m) = (uint8_t)v;  // removed end of the cut edge
+        NB(u, k) = (uint8_t)m;
+        ++m;
+      }
+    }
+    // link the cap: from the kept end u of a new vertex w, walk the face that
+    // contains u -> (removed end) through removed vertices until a kept
+    // vertex is reached; the new vertex on that exit edge follows w on the cap
+    for (int w = onv; w < m; ++w) {
+      int prev = NB(w, 0), cur = AUX(w);
+      for (int guard = 0; guard < 3 * onv; ++guard) {
+        int nx = NB(cur, (slot(cur, prev) + 2) % 3);
+        prev = cur;
+        cur = nx;
+        if (SD(cur) >= 0.0) break;
+      }
+      int w2 = -1;
+      if (SD(cur) >= 0.0)
+        for (int k = 0; k < 3; ++k) {
+          int c = NB(cur, k);
+          if (c >= onv && c < m && AUX(c) == prev) w2 = c;
+        }
+      if (w2 < 0) { nv = 0; return false; }  // inconsistent cap: report, never index out
+      NB(w, 2) = (uint8_t)w2;
+      NB(w2, 1) = (uint8_t)w;
+    }
+    // compact: kept originals and new vertices, in order
+    int q = 0;
+    for (int i = 0; i < m; ++i) {
+      bool keep = (i >= onv) || (SD(i) >= 0.0);
+      AUX(i) = keep ? (uint8_t)(q++) : (uint8_t)255;
+    }
+    for (int i = 0; i < m; ++i) {
+      int j = AUX(i);
+      if (j == 255 || j == i) continue;
+      X(j) = X(i); Y(j) = Y(i); Z(j) = Z(i);
+      NB(j, 0) = NB(i, 0); NB(j, 1) = NB(i, 1); NB(j, 2) = NB(i, 2);
+    }
+    for (int j = 0; j < q; ++j)
+      for (int k = 0; k < 3; ++k) NB(j, k) = AUX(NB(j, k));
+    nv = q;
+    return true;
+  }
+
+  // six times the volume: every face walked once, fanned from its first vertex
+  VHD double vol6() {
+    if (nv == 0) return 0.0;
+    for (int i = 0; i < nv; ++i) AUX(i) = 0;
+    v3 o = P(0);
+    double v = 0.0;
+    for (int u = 0; u < nv; ++u) {
+      for (int k = 0; k < 3; ++k) {
+        if (AUX(u) & (1 << k)) continue;
+        AUX(u) |= (uint8_t)(1 << k);
+        v3 a = P(u) - o;
+        int prev = u, cur = NB(u, k);
+        v3 b = P(cur) - o;
+        for (int guard = 0; guard < 3 * nv && cur != u; ++guard) {
+          int kn = (slot(cur, prev) + 2) % 3;
+          AUX(cur) |= (uint8_t)(1 << kn);
+          int nx = NB(cur, kn);
+          if (nx != u) {
+            v3 c = P(nx) - o;
+            v += det3(a, b, c);
+            b = c;
+          }
+          prev = cur;
+          cur = nx;
+        }
+      }
+    }
+    return v;
+  }
+};
+
+}  // namespace vof

@@ -1,0 +1,793 @@
+// vof_device.hip -- HIP kernels of the geometric PLIC VoF flux path (gfx950).
+//
+// One step (explicit Euler, eq. 2.2; every geometric quantity uses alpha^n):
+//   k_cell_class   cell classes by the band eps < alpha < 1 - eps, list of
+//                  interface cells                                (step 4a)
+//   k_point_prep   per point: OR of point-cell classes; IDW point values of
+//                  alpha for band points (eq. 2.6)                (step 4b)
+//   k_flux         per face: swept points (eq. 2.16), the flux polyhedron's
+//                  exact volume cubic, Newton correction to F dt (eq. 2.17),
+//                  stencil class -> trivial V_alpha or geometric list (1-3)
+//   k_plane        per interface cell: NAG gradient (eqs. 2.8-2.12) and
+//                  plane positioning (Section 2.2.2)                 (step 4)
+//   k_clip         per (geometric face, flux tet): intersection with the
+//                  stencil cells and their PLIC half-spaces (eqs. 2.22-2.23)
+//   k_face_sum     per geometric face: signed sum of its tet volumes  (5)
+//   k_update       per cell: alpha -= (1/V) sum_f sgn V_alpha (eqs. 2.2, 2.5)
+//   k_ledger       boundary phase volume of the step (one block, fixed order)
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "geom.hpp"
+#include "vof_internal.h"
+
+namespace vof {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kClipBlock = 64;
+constexpr int kClipCap = 20;  // polytope vertices kept per lane in LDS
+
+__device__ __forceinline__ v3 xyz(double4 a) { return mk3(a.x, a.y, a.z); }
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+// Append the lanes with `pred` to a list: one atomic per wavefront.  Must be
+// reached by every lane of the wavefront.
+__device__ __forceinline__ int wave_append(int32_t *counter, bool pred) {
+  unsigned long long mask = __ballot(pred);
+  if (mask == 0ull) return -1;
+  int lane = lane_id();
+  int leader = __ffsll((long long)mask) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(counter, (int)__popcll(mask));
+  base = __shfl(base, leader);
+  int rank = (int)__popcll(mask & ((1ull << lane) - 1ull));
+  return pred ? base + rank : -1;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+__device__ __forceinline__ void wave_count(unsigned long long *dst, unsigned long long v) {
+  v = wave_sum(v);
+  if (lane_id() == 0 && v) atomicAdd(dst, v);
+}
+
+__device__ __forceinline__ void flag(uint32_t *flags, uint32_t bit) { atomicOr(flags, bit); }
+
+// ---------------------------------------------------------------------------
+// mesh preparation
+// ---------------------------------------------------------------------------
+__global__ void k_points(int64_t np, const double *pts, double4 *X) {
+  int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  X[p] = make_double4(pts[3 * p], pts[3 * p + 1], pts[3 * p + 2], 0.0);
+}
+
+// face centre = mean of the points (Section 2.2.1); S = sum 1/2 (p_i - c) x (p_i+1 - c)
+__global__ void k_face_geom(DMesh m, double4 *S, double4 *C) {
+  int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (f >= m.nf) return;
+  int b = m.foff[f], n = m.foff[f + 1] - b;
+  v3 c = mk3(0, 0, 0);
+  for (int i = 0; i < n; ++i) c = c + xyz(m.X[m.fpts[b + i]]);
+  c = (1.0 / n) * c;
+  v3 s = mk3(0, 0, 0);
+  for (int i = 0; i < n; ++i) {
+    v3 a = xyz(m.X[m.fpts[b + i]]) - c;
+    v3 q = xyz(m.X[m.fpts[b + (i + 1 == n ? 0 : i + 1)]]) - c;
+    s = s + cross(a, q);
+  }
+  s = 0.5 * s;
+  C[f] = make_double4(c.x, c.y, c.z, 0.0);
+  S[f] = make_double4(s.x, s.y, s.z, sqrt(dot(s, s)));
+}
+
+// Cell volume and centroid from tetrahedra (apex, c_f, p_i, p_i+1) over the
+// outward face fans; the apex is the mean of the face centres.  Also the cell
+// bounding box.
+__global__ void k_cell_geom(DMesh m, double *V, double4 *XC, double4 *bblo, double4 *bbhi) {
+  int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= m.nc) return;
+  int k0 = m.cf_off[c], k1 = m.cf_off[c + 1];
+  v3 a = mk3(0, 0, 0);
+  for (int k = k0; k < k1; ++k) {
+    int sf = m.cf[k];
+    a = a + xyz(m.C[sf >= 0 ? sf : ~sf]);
+  }
+  a = (1.0 / (k1 - k0)) * a;
+  double v6 = 0.0;
+  v3 mom = mk3(0, 0, 0);
+  v3 lo = mk3(1e300, 1e300, 1e300), hi = mk3(-1e300, -1e300, -1e300);
+  for (int k = k0; k < k1; ++k) {
+    int sf = m.cf[k];
+    int f = sf >= 0 ? sf : ~sf;
+    double sg = sf >= 0 ? 1.0 : -1.0;
+    v3 cf = xyz(m.C[f]) - a;
+    int b = m.foff[f], n = m.foff[f + 1] - b;
+    for (int i = 0; i < n; ++i) {
+      v3 pg = xyz(m.X[m.fpts[b + i]]);
+      lo = mk3(dmin(lo.x, pg.x), dmin(lo.y, pg.y), dmin(lo.z, pg.z));
+      hi = mk3(dmax(hi.x, pg.x), dmax(hi.y, pg.y), dmax(hi.z, pg.z));
+      v3 p = pg - a;
+      v3 q = xyz(m.X[m.fpts[b + (i + 1 == n ? 0 : i + 1)]]) - a;
+      double t = sg * det3(cf, p, q);
+      v6 += t;
+      mom = mom + (0.25 * t) * (cf + p + q);
+    }
+  }
+  V[c] = v6 / 6.0;
+  v3 xc = a + (1.0 / v6) * mom;
+  XC[c] = make_double4(xc.x, xc.y, xc.z, 0.0);
+  bblo[c] = make_double4(lo.x, lo.y, lo.z, 0.0);
+  bbhi[c] = make_double4(hi.x, hi.y, hi.z, 0.0);
+}
+
+// cell face planes: outward unit normal sgn * S/|S| and offset through c_f;
+// the two cells of a face get exactly opposite planes
+__global__ void k_cell_planes(DMesh m, double4 *cpl) {
+  int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= m.nc) return;
+  for (int k = m.cf_off[c]; k < m.cf_off[c + 1]; ++k) {
+    int sf = m.cf[k];
+    int f = sf >= 0 ? sf : ~sf;
+    double4 S = m.S[f];
+    v3 n = (1.0 / S.w) * xyz(S);
+    double d = dot(n, xyz(m.C[f]));
+    double sg = sf >= 0 ? 1.0 : -1.0;
+    cpl[k] = make_double4(sg * n.x, sg * n.y, sg * n.z, sg * d);
+  }
+}
+
+// inverse distance weights of the point-cells (eq. 2.7)
+__global__ void k_idw(DMesh m, double *w) {
+  int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= m.np) return;
+  v3 x = xyz(m.X[p]);
+  double sum = 0.0;
+  int k0 = m.pc_off[p], k1 = m.pc_off[p + 1];
+  for (int k = k0; k < k1; ++k) {
+    v3 r = x - xyz(m.XC[m.pc[k]]);
+    double wk = 1.0 / sqrt(dot(r, r));
+    w[k] = wk;
+    sum += wk;
+  }
+  for (int k = k0; k < k1; ++k) w[k] /= sum;
+}
+
+__global__ void k_check_orientation(DMesh m, uint32_t *flags) {
+  int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (f >= m.ni) return;
+  v3 d = xyz(m.XC[m.nei[f]]) - xyz(m.XC[m.own[f]]);
+  if (!(dot(d, xyz(m.S[f])) > 0.0)) flag(flags, kFlagBadOrientation);
+}
+
+// U_p = sum_c w_pc U_c (eqs. 2.6-2.7 applied to the velocity, Section 2.3)
+__global__ void k_point_velocity(DMesh m, const double *U0c, double4 *U) {
+  int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= m.np) return;
+  v3 u = mk3(0, 0, 0);
+  for (int k = m.pc_off[p]; k < m.pc_off[p + 1]; ++k) {
+    int64_t c = m.pc[k];
+    u = u + m.wpc[k] * mk3(U0c[3 * c], U0c[3 * c + 1], U0c[3 * c + 2]);
+  }
+  U[p] = make_double4(u.x, u.y, u.z, 0.0);
+}
+
+// ---------------------------------------------------------------------------
+// step 4: classes, point values, planes
+// ---------------------------------------------------------------------------
+__global__ void k_reset(DState s) {
+  if (threadIdx.x < kWNum) s.work[threadIdx.x] = 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cell_class(DMesh m, DState s, DParams p) {
+  int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  bool iface = false;
+  if (c < m.nc) {
+    double a = s.alpha[c];
+    int8_t cl = a <= p.eps ? 0 : (a >= 1.0 - p.eps ? 2 : 1);
+    s.cls[c] = cl;
+    iface = cl == 1;
+  }
+  int slot = wave_append(&s.work[kWInterface], iface);
+  if (iface) s.icells[slot] = (int32_t)c;
+}
+
+__global__ __launch_bounds__(kBlock) void k_point_prep(DMesh m, DState s) {
+  int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= m.np) return;
+  int k0 = m.pc_off[p], k1 = m.pc_off[p + 1];
+  uint8_t mask = 0;
+  for (int k = k0; k < k1; ++k) {
+    int8_t cl = s.cls[m.pc[k]];
+    mask |= cl == 0 ? 1 : (cl == 2 ? 2 : 4);
+  }
+  s.pmask[p] = mask;
+  if (mask & 4) {
+    double a = 0.0;
+    for (int k = k0; k < k1; ++k) a += m.wpc[k] * s.alpha[m.pc[k]];
+    s.alpha_p[p] = a;
+  }
+}
+
+// Fill level of cell c below n.x <= s (coordinates relative to o): sum over
+// the tetrahedra (o, c_f, p_i, p_i+1) of the outward face fans of
+// vol6 * kept fraction.  Also returns the height range of the cell points.
+__device__ double cell_fill6(const DMesh &m, int64_t c, v3 o, v3 n, double s) {
+  double acc = 0.0;
+  for (int k = m.cf_off[c]; k < m.cf_off[c + 1]; ++k) {
+    int sf = m.cf[k];
+    int f = sf >= 0 ? sf : ~sf;
+    double sg = sf >= 0 ? 1.0 : -1.0;
+    v3 cf = xyz(m.C[f]) - o;
+    double hc = dot(n, cf);
+    int b = m.foff[f], nn = m.foff[f + 1] - b;
+    v3 p0 = xyz(m.X[m.fpts[b]]) - o;
+    v3 pa = p0;
+    double ha = dot(n, pa);
+    for (int i = 0; i < nn; ++i) {
+      v3 pb = (i + 1 == nn) ? p0 : xyz(m.X[m.fpts[b + i + 1]]) - o;
+      double hb = dot(n, pb);
+      double v6 = sg * det3(cf, pa, pb);
+      double d[4] = {s, s - hc, s - ha, s - hb};
+      acc += v6 * tet_kept_fraction(d);
+      pa = pb;
+      ha = hb;
+    }
+  }
+  return acc;
+}
+
+// NAG gradient (eqs. 2.8-2.12) and plane positioning (Section 2.2.2):
+// the fill level g(s) = |C ∩ {n.x <= s}| / |C| - alpha is monotone between
+// the lowest and highest cell points; it is solved by regula falsi with the
+// Illinois modification, which keeps a bracket and converges superlinearly.
+__global__ __launch_bounds__(kBlock) void k_plane(DMesh m, DState s, DParams p) {
+  const int count = s.work[kWInterface];
+  unsigned long long nfall = 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+    int64_t c = s.icells[i];
+    double a = s.alpha[c];
+    v3 g = mk3(0, 0, 0);
+    for (int k = m.cf_off[c]; k < m.cf_off[c + 1]; ++k) {
+      int sf = m.cf[k];
+      int f = sf >= 0 ? sf : ~sf;
+      double sg = sf >= 0 ? 1.0 : -1.0;
+      int b = m.foff[f], nn = m.foff[f + 1] - b;
+      double fp = 0.0;
+      for (int j = 0; j < nn; ++j) fp += s.alpha_p[m.fpts[b + j]];
+      fp /= nn;
+      v3 cf = xyz(m.C[f]);
+      double num = 0.0, den = 0.0;
+      int q0 = m.fpts[b];
+      int qa = q0;
+      for (int j = 0; j < nn; ++j) {
+        int qb = (j + 1 == nn) ? q0 : m.fpts[b + j + 1];
+        v3 t = cross(xyz(m.X[qa]) - cf, xyz(m.X[qb]) - cf);
+        double A = 0.5 * sqrt(dot(t, t));
+        num += A * (fp + s.alpha_p[qa] + s.alpha_p[qb]) / 3.0;
+        den += A;
+        qa = qb;
+      }
+      double af = num / den;
+      g = g + (sg * af) * xyz(m.S[f]);
+    }
+    double Vc = m.V[c];
+    g = (1.0 / Vc) * g;
+    double gn = sqrt(dot(g, g));
+    if (!(gn * cbrt(Vc) >= p.grad_zero)) {
+      s.cls[c] = 3;
+      s.plane[c] = make_double4(0.0, 0.0, 0.0, 0.0);
+      ++nfall;
+      continue;
+    }
+    v3 n = (-1.0 / gn) * g;
+    v3 o = xyz(m.XC[c]);
+    double hmin = 1e300, hmax = -1e300;
+    for (int k = m.cf_off[c]; k < m.cf_off[c + 1]; ++k) {
+      int sf = m.cf[k];
+      int f = sf >= 0 ? sf : ~sf;
+      for (int j = m.foff[f]; j < m.foff[f + 1]; ++j) {
+        double h = dot(n, xyz(m.X[m.fpts[j]]) - o);
+        hmin = dmin(hmin, h);
+        hmax = dmax(hmax, h);
+      }
+    }
+    double tot6 = cell_fill6(m, c, o, n, hmax);
+    double lo = hmin, glo = -a, hi = hmax, ghi = 1.0 - a;
+    double sx = 0.5 * (lo + hi);
+    int side = 0;
+    for (int it = 0; it < p.pos_max_iter; ++it) {
+      double sn = hi - ghi * (hi - lo) / (ghi - glo);
+      if (!(sn > lo && sn < hi)) sn = 0.5 * (lo + hi);
+      double gs = cell_fill6(m, c, o, n, sn) / tot6 - a;
+      sx = sn;
+      if (fabs(gs) <= p.pos_tol) break;
+      if (gs < 0.0) {
+        lo = sn; glo = gs;
+        if (side == -1) ghi *= 0.5;
+        side = -1;
+      } else {
+        hi = sn; ghi = gs;
+        if (side == 1) glo *= 0.5;
+        side = 1;
+      }
+      if (hi - lo <= 2e-16 * (hmax - hmin)) break;
+    }
+    s.plane[c] = make_double4(n.x, n.y, n.z, sx + dot(n, o));
+  }
+  wave_count(&s.cnt[kCntFallback], nfall);
+}
+
+// ---------------------------------------------------------------------------
+// steps 1-3: flux polyhedra and their correction
+// ---------------------------------------------------------------------------
+// Signed volume of the flux polyhedron of a face with points r_i (relative to
+// the face centre) swept by lam * d_i.  Its surface: the face fan, the swept
+// fan about the mean of the swept points, and each side quad
+// (p_i+1, p_i, q_i, q_i+1) as four triangles about its vertex mean.  Summing
+// the tetrahedra with apex at the face centre in closed form:
+//   side i = (1/6)[lam h_i.(s_i x e_i) + lam^2 h_i.(d_i x d_i+1)]
+//   top    = -(1/6) lam dbar.(A2 + lam B + lam^2 C)
+// with e_i = r_i+1 - r_i, h_i = (r_i + r_i+1)/2, s_i = d_i + d_i+1,
+// A2 = sum r_i x r_i+1, B = sum (r_i x d_i+1 + d_i x r_i+1), C = sum d_i x d_i+1,
+// dbar = mean d_i.  V(lam) = c1 lam + c2 lam^2 + c3 lam^3 exactly.
+//
+// Correction (Section 2.3): V(lam) = F dt on the branch of V through 0 on
+// which V' keeps its sign (bounded by the real roots of V'), by Newton from
+// lam = 1 safeguarded by bisection.  status 1 when the target lies beyond the
+// branch end (lam is then the end, at most 64).
+__device__ __forceinline__ void correct(double c1, double c2, double c3, double T, double rtol,
+                                        int maxit, double &lam, int &iters, int &status) {
+  iters = 0;
+  status = 0;
+  lam = 0.0;
+  if (T == 0.0) return;
+  if (!(c1 != 0.0) || !isfinite(c2) || !isfinite(c3)) { status = 1; return; }
+  const double big = 64.0;
+  double lo = -big, hi = big;
+  if (c3 != 0.0) {
+    double disc = c2 * c2 - 3.0 * c1 * c3;
+    if (disc > 0.0) {
+      double q = -(c2 + copysign(sqrt(disc), c2));
+      double r0 = q / (3.0 * c3), r1 = c1 / q;
+      if (r0 > 0.0) hi = dmin(hi, r0); else if (r0 < 0.0) lo = dmax(lo, r0);
+      if (r1 > 0.0) hi = dmin(hi, r1); else if (r1 < 0.0) lo = dmax(lo, r1);
+    }
+  } else if (c2 != 0.0) {
+    double r = -c1 / (2.0 * c2);
+    if (r > 0.0) hi = dmin(hi, r); else if (r < 0.0) lo = dmax(lo, r);
+  }
+  double end = ((T > 0.0) == (c1 > 0.0)) ? hi : lo;
+  double gend = ((c3 * end + c2) * end + c1) * end - T;
+  if (!(gend * T >= 0.0)) { lam = end; status = 1; return; }
+  double a = dmin(0.0, end), b = dmax(0.0, end);
+  double ga = (a == 0.0) ? -T : gend;
+  double x = 1.0;
+  if (!(x > a && x < b)) x = 0.5 * (a + b);
+  for (;;) {
+    double g = ((c3 * x + c2) * x + c1) * x - T;
+    if (fabs(g) <= rtol * fabs(T) || iters >= maxit) break;
+    if ((g < 0.0) == (ga < 0.0)) { a = x; ga = g; } else { b = x; }
+    double dv = (3.0 * c3 * x + 2.0 * c2) * x + c1;
+    double xn = x - g / dv;
+    if (!(xn > a && xn < b)) xn = 0.5 * (a + b);
+    ++iters;
+    if (xn == x) break;
+    x = xn;
+  }
+  lam = x;
+}
+
+template <int NMAX>
+__global__ __launch_bounds__(kBlock) void k_flux(DMesh m, DState s, DParams p, int step) {
+  const double dt = s.dt[step], sc = s.sc[step];
+  int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  bool geo = false;
+  unsigned long long nflux = 0, nit = 0, nbad = 0;
+  if (f < m.nf) {
+    double F = sc * s.F0[f];
+    double T = F * dt;
+    double lam = 0.0, vph = 0.0;
+    int it = 0, stat = 0;
+    uint8_t kind = 0;
+    if (F != 0.0) {
+      int b = m.foff[f], n = m.foff[f + 1] - b;
+      v3 r[NMAX], d[NMAX];
+      uint8_t mask = 0;
+      v3 c = mk3(0, 0, 0);
+      const double sweep = -sc * dt;
+#pragma unroll
+      for (int i = 0; i < NMAX; ++i) {
+        if (i < n) {
+          int q = m.fpts[b + i];
+          r[i] = xyz(m.X[q]);
+          d[i] = sweep * xyz(s.U[q]);
+          mask |= s.pmask[q];
+          c = c + r[i];
+        } else {
+          r[i] = mk3(0, 0, 0);
+          d[i] = mk3(0, 0, 0);
+        }
+      }
+      c = (1.0 / n) * c;
+#pragma unroll
+      for (int i = 0; i < NMAX; ++i) r[i] = r[i] - c;
+      double t1 = 0.0, t2 = 0.0;
+      v3 A2 = mk3(0, 0, 0), B = mk3(0, 0, 0), Cc = mk3(0, 0, 0), db = mk3(0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < NMAX; ++i) {
+        if (i < n) {
+          v3 rn = (i + 1 < n) ? r[(i + 1) % NMAX] : r[0];
+          v3 dn = (i + 1 < n) ? d[(i + 1) % NMAX] : d[0];
+          v3 e = rn - r[i];
+          v3 h = 0.5 * (r[i] + rn);
+          v3 dd = cross(d[i], dn);
+          t1 += dot(h, cross(d[i] + dn, e));
+          t2 += dot(h, dd);
+          A2 = A2 + cross(r[i], rn);
+          B = B + cross(r[i], dn) + cross(d[i], rn);
+          Cc = Cc + dd;
+          db = db + d[i];
+        }
+      }
+      db = (1.0 / n) * db;
+      double c1 = (t1 - dot(db, A2)) / 6.0;
+      double c2 = (t2 - dot(db, B)) / 6.0;
+      double c3 = -dot(db, Cc) / 6.0;
+      correct(c1, c2, c3, T, p.corr_rtol, p.corr_max_iter, lam, it, stat);
+      nflux = 1;
+      nit = (unsigned long long)it;
+      nbad = (unsigned long long)stat;
+      if ((mask & 6) == 0) {
+        kind = 1;
+        vph = 0.0;
+      } else if (mask == 2 && f < m.ni) {
+        kind = 2;
+        vph = T;
+      } else {
+        kind = 3;
+        geo = true;
+      }
+    }
+    s.lam[f] = lam;
+    if (!geo) s.vphase[f] = vph;
+    s.iters[f] = (uint8_t)(it > 255 ? 255 : it);
+    s.kind[f] = kind;
+    s.fstatus[f] = (uint8_t)stat;
+  }
+  int slot = wave_append(&s.work[kWGeometric], geo);
+  if (geo) s.gfaces[slot] = (int32_t)f;
+  wave_count(&s.cnt[kCntFaceFluxes], nflux);
+  wave_count(&s.cnt[kCntIters], nit);
+  wave_count(&s.cnt[kCntUnreached], nbad);
+  if (__ballot(nbad != 0) && lane_id() == 0) flag(s.flags, kFlagUnreached);
+}
+
+// ---------------------------------------------------------------------------
+// step 5: phase volume of the geometric faces
+// ---------------------------------------------------------------------------
+// Work item (slot, k): tetrahedron k of the flux polyhedron of face
+// gfaces[slot] at its corrected lam, apex at the face centre (local origin):
+//   k = 5 i      top    (c_q, q_i+1, q_i)
+//   k = 5 i + 1  side   (m_i, p_i+1, p_i)
+//   k = 5 i + 2         (m_i, p_i, q_i)
+//   k = 5 i + 3         (m_i, q_i, q_i+1)
+//   k = 5 i + 4         (m_i, q_i+1, p_i+1)
+// The signed tet volume times sum over stencil cells of
+// |T ∩ C_c ∩ H_c| (H = the PLIC half-space in interface cells, all space in
+// full cells, alpha-weighted in vanishing-gradient cells) is stored per item.
+template <int NMAX>
+__global__ __launch_bounds__(kClipBlock) void k_clip(DMesh m, DState s, DParams p, int step) {
+  __shared__ double lx[kClipCap * kClipBlock], ly[kClipCap * kClipBlock],
+      lz[kClipCap * kClipBlock], ld[kClipCap * kClipBlock];
+  __shared__ uint8_t lnb[3 * kClipCap * kClipBlock], laux[kClipCap * kClipBlock];
+  const int tid = threadIdx.x;
+  Poly P;
+  P.px = lx + tid; P.py = ly + tid; P.pz = lz + tid; P.ps = ld + tid;
+  P.nb = lnb + tid; P.aux = laux + tid;
+  P.st = kClipBlock; P.cap = kClipCap; P.nv = 0;
+
+  const double dt = s.dt[step], sc = s.sc[step];
+  const int64_t total = (int64_t)s.work[kWGeometric] * m.tpf;
+  unsigned long long ncap = 0, nleak = 0;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + tid; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    int slot = (int)(idx / m.tpf);
+    int k = (int)(idx - (int64_t)slot * m.tpf);
+    int f = s.gfaces[slot];
+    int b = m.foff[f], n = m.foff[f + 1] - b;
+    if (k >= 5 * n) { s.tetvol[idx] = 0.0; continue; }
+    const double sw = -sc * dt * s.lam[f];
+    // face points and swept points, relative to the face centre
+    int i = k / 5, type = k - 5 * i;
+    int i1 = (i + 1 == n) ? 0 : i + 1;
+    v3 c = mk3(0, 0, 0), cq = mk3(0, 0, 0);
+    v3 pi = mk3(0, 0, 0), pj = mk3(0, 0, 0), qi = mk3(0, 0, 0), qj = mk3(0, 0, 0);
+    for (int j = 0; j < n; ++j) {
+      int q = m.fpts[b + j];
+      v3 x = xyz(m.X[q]);
+      v3 dq = sw * xyz(s.U[q]);
+      c = c + x;
+      cq = cq + dq;
+      if (j == i) { pi = x; qi = dq; }
+      if (j == i1) { pj = x; qj = dq; }
+    }
+    c = (1.0 / n) * c;
+    pi = pi - c; pj = pj - c;
+    qi = pi + qi; qj = pj + qj;
+    cq = (1.0 / n) * cq;  // mean sweep; the mean of the face points is the origin
+    v3 t1, t2, t3;
+    if (type == 0) { t1 = cq; t2 = qj; t3 = qi; }
+    else {
+      v3 mi = 0.25 * (pi + pj + qi + qj);
+      t1 = mi;
+      if (type == 1) { t2 = pj; t3 = pi; }
+      else if (type == 2) { t2 = pi; t3 = qi; }
+      else if (type == 3) { t2 = qi; t3 = qj; }
+      else { t2 = qj; t3 = pj; }
+    }
+    double det = det3(t1, t2, t3);
+    if (det == 0.0) { s.tetvol[idx] = 0.0; continue; }
+    double sgn = det > 0.0 ? 1.0 : -1.0;
+    if (det < 0.0) { v3 tmp = t2; t2 = t3; t3 = tmp; det = -det; }
+    const v3 z = mk3(0, 0, 0);
+    v3 lo = mk3(dmin(dmin(0.0, t1.x), dmin(t2.x, t3.x)), dmin(dmin(0.0, t1.y), dmin(t2.y, t3.y)),
+                dmin(dmin(0.0, t1.z), dmin(t2.z, t3.z)));
+    v3 hi = mk3(dmax(dmax(0.0, t1.x), dmax(t2.x, t3.x)), dmax(dmax(0.0, t1.y), dmax(t2.y, t3.y)),
+                dmax(dmax(0.0, t1.z), dmax(t2.z, t3.z)));
+    lo = lo + c;
+    hi = hi + c;
+    double acc = 0.0, cover = 0.0;
+    for (int e = m.st_off[f]; e < m.st_off[f + 1]; ++e) {
+      int cell = m.st[e];
+      int cl = s.cls[cell];
+      if (cl == 0 && !p.check_stencil) continue;
+      double4 blo = m.bblo[cell], bhi = m.bbhi[cell];
+      if (hi.x <= blo.x || lo.x >= bhi.x || hi.y <= blo.y || lo.y >= bhi.y || hi.z <= blo.z ||
+          lo.z >= bhi.z)
+        continue;
+      // planes of the cell that cut the tet
+      int cuts[kMaxCellPlanes];
+      int ncut = 0;
+      bool outside = false;
+      double dsingle[4];
+      for (int q = m.cf_off[cell]; q < m.cf_off[cell + 1]; ++q) {
+        double4 pl = m.cpl[q];
+        v3 nn = xyz(pl);
+        double off = pl.w - dot(nn, c);
+        double d0 = off, d1 = off - dot(nn, t1), d2 = off - dot(nn, t2), d3 = off - dot(nn, t3);
+        double dmx = dmax(dmax(d0, d1), dmax(d2, d3));
+        double dmn = dmin(dmin(d0, d1), dmin(d2, d3));
+        if (dmx <= 0.0) { outside = true; break; }
+        if (dmn < 0.0) {
+          if (ncut < kMaxCellPlanes) cuts[ncut] = q;
+          ++ncut;
+          dsingle[0] = d0; dsingle[1] = d1; dsingle[2] = d2; dsingle[3] = d3;
+        }
+      }
+      if (outside) continue;
+      double vcell, vph;
+      if (ncut == 0) {
+        vcell = det;
+      } else if (ncut == 1) {
+        vcell = det * tet_kept_fraction(dsingle);
+      } else {
+        vcell = -1.0;
+      }
+      if (cl == 1) {
+        double4 pl = s.plane[cell];
+        v3 nn = xyz(pl);
+        double off = pl.w - dot(nn, c);
+        if (ncut == 0) {
+          double dd[4] = {off, off - dot(nn, t1), off - dot(nn, t2), off - dot(nn, t3)};
+          vph = det * tet_kept_fraction(dd);
+        } else {
+          P.init_tet(z, t1, t2, t3);
+          bool ok = true;
+          for (int q = 0; q < ncut && ok; ++q) {
+            double4 cp = m.cpl[cuts[q < kMaxCellPlanes ? q : 0]];
+            ok = P.clip(xyz(cp), cp.w - dot(xyz(cp), c));
+          }
+          if (ok && p.check_stencil && vcell < 0.0) {
+            // coverage before the plane cut
+            vcell = P.vol6();
+          }
+          ok = ok && P.clip(nn, off);
+          vph = ok ? P.vol6() : 0.0;
+          if (!ok || ncut > kMaxCellPlanes) ++ncap;
+        }
+      } else if (cl == 0) {
+        vph = 0.0;
+      } else {
+        if (vcell < 0.0) {
+          P.init_tet(z, t1, t2, t3);
+          bool ok = true;
+          for (int q = 0; q < ncut && ok; ++q) {
+            double4 cp = m.cpl[cuts[q < kMaxCellPlanes ? q : 0]];
+            ok = P.clip(xyz(cp), cp.w - dot(xyz(cp), c));
+          }
+          vcell = ok ? P.vol6() : 0.0;
+          if (!ok || ncut > kMaxCellPlanes) ++ncap;
+        }
+        vph = (cl == 2) ? vcell : s.alpha[cell] * vcell;
+      }
+      acc += vph;
+      if (p.check_stencil) {
+        if (vcell < 0.0) {
+          P.init_tet(z, t1, t2, t3);
+          bool ok = true;
+          for (int q = 0; q < ncut && ok; ++q) {
+            double4 cp = m.cpl[cuts[q < kMaxCellPlanes ? q : 0]];
+            ok = P.clip(xyz(cp), cp.w - dot(xyz(cp), c));
+          }
+          vcell = ok ? P.vol6() : 0.0;
+        }
+        cover += vcell;
+      }
+      if (ncut == 0) break;  // the tet lies inside this cell
+    }
+    if (p.check_stencil && fabs(cover - det) > 1e-12 * det) ++nleak;
+    s.tetvol[idx] = sgn * acc / 6.0;
+  }
+  wave_count(&s.cnt[kCntCapacity], ncap);
+  wave_count(&s.cnt[kCntLeaks], nleak);
+  if (__ballot(ncap != 0) && lane_id() == 0) flag(s.flags, kFlagCapacity);
+  if (__ballot(nleak != 0) && lane_id() == 0) flag(s.flags, kFlagLeak);
+}
+
+__global__ __launch_bounds__(kBlock) void k_face_sum(DMesh m, DState s) {
+  const int count = s.work[kWGeometric];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+    const double *tv = s.tetvol + (int64_t)i * m.tpf;
+    double acc = 0.0;
+    for (int k = 0; k < m.tpf; ++k) acc += tv[k];
+    s.vphase[s.gfaces[i]] = acc;
+  }
+}
+
+// alpha_c^{n+1} = alpha_c^n - (1/V_c) sum_f sgn_cf V_{f,alpha}, every cell
+__global__ __launch_bounds__(kBlock) void k_update(DMesh m, DState s) {
+  int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= m.nc) return;
+  double acc = 0.0;
+  for (int k = m.cf_off[c]; k < m.cf_off[c + 1]; ++k) {
+    int sf = m.cf[k];
+    acc += sf >= 0 ? s.vphase[sf] : -s.vphase[~sf];
+  }
+  s.alpha[c] = s.alpha[c] - acc / m.V[c];
+}
+
+// boundary ledger: one block, fixed reduction order
+__global__ __launch_bounds__(kBlock) void k_ledger(DMesh m, DState s) {
+  __shared__ double red[kBlock];
+  double acc = 0.0;
+  for (int64_t f = m.ni + threadIdx.x; f < m.nf; f += kBlock) acc += s.vphase[f];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = kBlock / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    s.ledger[0] += red[0];
+    s.cnt[kCntSteps] += 1;
+    s.cnt[kCntGeometric] += (unsigned long long)s.work[kWGeometric];
+    s.cnt[kCntInterface] += (unsigned long long)s.work[kWInterface];
+  }
+}
+
+// mass (Neumaier-compensated), min and max of alpha: one block, fixed order
+__global__ __launch_bounds__(1024) void k_stats(DMesh m, DState s, double *out) {
+  __shared__ double rs[1024], rc[1024], rmn[1024], rmx[1024];
+  double sum = 0.0, comp = 0.0, mn = 1e300, mx = -1e300;
+  for (int64_t c = threadIdx.x; c < m.nc; c += 1024) {
+    double a = s.alpha[c];
+    double v = m.V[c] * a;
+    double t = sum + v;
+    comp += (fabs(sum) >= fabs(v)) ? (sum - t) + v : (v - t) + sum;
+    sum = t;
+    mn = dmin(mn, a);
+    mx = dmax(mx, a);
+  }
+  rs[threadIdx.x] = sum; rc[threadIdx.x] = comp; rmn[threadIdx.x] = mn; rmx[threadIdx.x] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double S = 0.0, Cp = 0.0, lo = 1e300, hi = -1e300;
+    for (int i = 0; i < 1024; ++i) {
+      double v = rs[i];
+      double t = S + v;
+      Cp += (fabs(S) >= fabs(v)) ? (S - t) + v : (v - t) + S;
+      S = t;
+      Cp += rc[i];
+      lo = dmin(lo, rmn[i]);
+      hi = dmax(hi, rmx[i]);
+    }
+    out[0] = S + Cp;
+    out[1] = lo;
+    out[2] = hi;
+    out[3] = 0.0;
+  }
+}
+
+inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+void launch_mesh_geometry(const DMesh &m0, double4 *X, const double *pts, double4 *S, double4 *C,
+                          double *V, double4 *XC, double *wpc, double4 *cpl, double4 *bblo,
+                          double4 *bbhi, uint32_t *flags, hipStream_t st) {
+  DMesh m = m0;
+  k_points<<<grid_for(m.np, kBlock), kBlock, 0, st>>>(m.np, pts, X);
+  k_face_geom<<<grid_for(m.nf, kBlock), kBlock, 0, st>>>(m, S, C);
+  k_cell_geom<<<grid_for(m.nc, kBlock), kBlock, 0, st>>>(m, V, XC, bblo, bbhi);
+  k_cell_planes<<<grid_for(m.nc, kBlock), kBlock, 0, st>>>(m, cpl);
+  k_idw<<<grid_for(m.np, kBlock), kBlock, 0, st>>>(m, wpc);
+  if (m.ni > 0) k_check_orientation<<<grid_for(m.ni, kBlock), kBlock, 0, st>>>(m, flags);
+}
+
+void launch_point_velocity(const DMesh &m, const double *U0c, double4 *U, hipStream_t st) {
+  k_point_velocity<<<grid_for(m.np, kBlock), kBlock, 0, st>>>(m, U0c, U);
+}
+
+static void launch_reconstruct_impl(const DMesh &m, const DState &s, const DParams &p,
+                                    hipStream_t st) {
+  k_cell_class<<<grid_for(m.nc, kBlock), kBlock, 0, st>>>(m, s, p);
+  k_point_prep<<<grid_for(m.np, kBlock), kBlock, 0, st>>>(m, s);
+  unsigned g = grid_for(m.nc, kBlock);
+  k_plane<<<g < 2048 ? (g ? g : 1) : 2048, kBlock, 0, st>>>(m, s, p);
+}
+
+void launch_reconstruct(const DMesh &m, const DState &s, const DParams &p, hipStream_t st) {
+  k_reset<<<1, 64, 0, st>>>(s);
+  launch_reconstruct_impl(m, s, p, st);
+}
+
+void launch_step(const DMesh &m, const DState &s, const DParams &p, int step, hipStream_t st) {
+  k_reset<<<1, 64, 0, st>>>(s);
+  launch_reconstruct_impl(m, s, p, st);
+  unsigned gf = grid_for(m.nf, kBlock);
+  if (m.maxn <= 3)
+    k_flux<3><<<gf, kBlock, 0, st>>>(m, s, p, step);
+  else if (m.maxn == 4)
+    k_flux<4><<<gf, kBlock, 0, st>>>(m, s, p, step);
+  else
+    k_flux<kMaxFacePoints><<<gf, kBlock, 0, st>>>(m, s, p, step);
+  k_clip<kMaxFacePoints><<<4096, kClipBlock, 0, st>>>(m, s, p, step);
+  k_face_sum<<<1024, kBlock, 0, st>>>(m, s);
+  k_update<<<grid_for(m.nc, kBlock), kBlock, 0, st>>>(m, s);
+  k_ledger<<<1, kBlock, 0, st>>>(m, s);
+}
+
+void launch_stats(const DMesh &m, const DState &s, double *out4, hipStream_t st) {
+  k_stats<<<1, 1024, 0, st>>>(m, s, out4);
+}
+
+// Host evaluation of the same clipping code (self-test, no GPU needed).
+double host_tet_clip(const double *tet, int n_planes, const double *planes) {
+  double px[kPolyCap], py[kPolyCap], pz[kPolyCap], ps[kPolyCap];
+  uint8_t nb[3 * kPolyCap], aux[kPolyCap];
+  Poly P;
+  P.px = px; P.py = py; P.pz = pz; P.ps = ps; P.nb = nb; P.aux = aux;
+  P.st = 1; P.cap = kPolyCap; P.nv = 0;
+  v3 a = mk3(tet[0], tet[1], tet[2]), b = mk3(tet[3], tet[4], tet[5]);
+  v3 c = mk3(tet[6], tet[7], tet[8]), d = mk3(tet[9], tet[10], tet[11]);
+  if (det3(b - a, c - a, d - a) < 0.0) { v3 t = c; c = d; d = t; }
+  P.init_tet(a, b, c, d);
+  for (int k = 0; k < n_planes; ++k)
+    if (!P.clip(mk3(planes[4 * k], planes[4 * k + 1], planes[4 * k + 2]), planes[4 * k + 3]))
+      return NAN;
+  return P.vol6() / 6.0;
+}
+
+}  // namespace vof

@@ -1,0 +1,114 @@
+// vof_internal.h -- device-side data layout of the flux library (internal).
+//
+// Layout in HBM.  Gathered per-point data are 32-byte double4 records so one
+// aligned load brings a whole point (coordinates, or velocity); everything
+// streamed per face or per cell is a plain array indexed by face or cell.
+// CSR addressing (int32 offsets) for face -> points, cell -> faces (signed:
+// f for an owned face, ~f for a neighbour face, eq. 2.5), point -> cells and
+// face -> stencil cells.  Cell planes are stored per cell -> face entry.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace vof {
+
+constexpr int kMaxFacePoints = 8;   // points of one face
+constexpr int kPolyCap = 24;        // vertices of one clipped polytope
+constexpr int kMaxCellPlanes = 16;  // planes of one cell tested per tet
+
+// status bits latched on the device
+constexpr uint32_t kFlagCapacity = 1u;
+constexpr uint32_t kFlagUnreached = 2u;
+constexpr uint32_t kFlagNonFinite = 4u;
+constexpr uint32_t kFlagLeak = 8u;
+constexpr uint32_t kFlagBadOrientation = 16u;
+
+// 64-bit counters accumulated across steps
+enum Counter : int {
+  kCntSteps = 0,
+  kCntFaceFluxes,
+  kCntGeometric,
+  kCntInterface,
+  kCntFallback,
+  kCntUnreached,
+  kCntCapacity,
+  kCntLeaks,
+  kCntIters,
+  kCntNum
+};
+
+// per-step work counters (reset every step)
+enum WorkCounter : int { kWInterface = 0, kWGeometric = 1, kWNum = 4 };
+
+struct DMesh {
+  int64_t np, nc, nf, ni;
+  int32_t maxn;    // max points per face
+  int32_t tpf;     // tetrahedra per face slot (5 * maxn)
+  const double4 *X;        // points (x, y, z, 0)
+  const int32_t *foff;     // nf + 1
+  const int32_t *fpts;     // face points
+  const int32_t *own;      // nf
+  const int32_t *nei;      // ni
+  const int32_t *cf_off;   // nc + 1
+  const int32_t *cf;       // signed face index
+  const int32_t *pc_off;   // np + 1
+  const int32_t *pc;       // point -> cells
+  const double *wpc;       // inverse distance weights (eq. 2.7)
+  const int32_t *st_off;   // nf + 1
+  const int32_t *st;       // face -> stencil cells
+  const double4 *S;        // face area vector, w = |S|
+  const double4 *C;        // face centre (mean of points)
+  const double *V;         // cell volume
+  const double4 *XC;       // cell centroid
+  const double4 *cpl;      // per cell -> face entry: outward unit normal, offset
+  const double4 *bblo;     // cell bounding box
+  const double4 *bbhi;
+};
+
+struct DParams {
+  double eps;
+  double corr_rtol;
+  int32_t corr_max_iter;
+  double pos_tol;
+  int32_t pos_max_iter;
+  double grad_zero;
+  int32_t check_stencil;
+};
+
+struct DState {
+  double *alpha;        // nc
+  int8_t *cls;          // nc: 0 empty, 1 interface, 2 full, 3 vanishing gradient
+  double4 *plane;       // nc: unit normal, s  (phase: n.x <= s)
+  uint8_t *pmask;       // np: bit 1 empty, 2 full, 4 interface among point-cells
+  double *alpha_p;      // np: IDW point values (band points only)
+  double4 *U;           // np: reference point velocity
+  double *F0;           // nf
+  double *lam;          // nf
+  double *vphase;       // nf
+  uint8_t *iters;       // nf
+  uint8_t *kind;        // nf
+  uint8_t *fstatus;     // nf
+  int32_t *icells;      // interface cell list
+  int32_t *gfaces;      // geometric face list
+  double *tetvol;       // per geometric face slot x tet
+  int32_t *work;        // per-step counters (kWNum)
+  unsigned long long *cnt;  // kCntNum
+  uint32_t *flags;      // latched status bits
+  double *ledger;       // accumulated boundary phase volume
+  double *dt;           // per-step dt (device copy)
+  double *sc;           // per-step scale
+};
+
+// launchers (vof_device.hip)
+void launch_mesh_geometry(const DMesh &m, double4 *X, const double *pts, double4 *S, double4 *C,
+                          double *V, double4 *XC, double *wpc, double4 *cpl, double4 *bblo,
+                          double4 *bbhi, uint32_t *flags, hipStream_t st);
+void launch_point_velocity(const DMesh &m, const double *U0c, double4 *U, hipStream_t st);
+void launch_step(const DMesh &m, const DState &s, const DParams &p, int step, hipStream_t st);
+void launch_reconstruct(const DMesh &m, const DState &s, const DParams &p, hipStream_t st);
+void launch_stats(const DMesh &m, const DState &s, double *out4, hipStream_t st);
+double host_tet_clip(const double *tet, int n_planes, const double *planes);
+
+}  // namespace vof

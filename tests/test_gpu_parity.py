@@ -1,0 +1,180 @@
+"""GPU parity: the HIP path against the CPU oracle on identical seeded inputs.
+
+Tolerances (FP64 on both sides, different summation orders and different
+geometric routes):
+  lambda_f            relative 1e-12
+  V_{f,alpha}         1e-12 * max(|F_f| dt, 1e-6 V_owner) per face
+  plane normal        1e-12 (components; same classes required)
+  alpha after N steps 1e-10 absolute
+  conservation        sum V alpha + ledger within 1e-12 relative
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.common import gpu_run, oracle_run, vphase_tolerance
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def vof():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1305_3417_amd as vof
+    vof.lib()
+    return vof
+
+
+@pytest.fixture(scope="module")
+def ctx(vof):
+    c = vof.vof_context_create(0)
+    yield c
+    vof.vof_context_destroy(c)
+
+
+def _compare_step(vof, ctx, oracle_mod, w, alpha=None, label=""):
+    """One step from `alpha`: planes, lambda, V_alpha and alpha."""
+    a0 = w.alpha0 if alpha is None else alpha
+    print(f"[{label}] one step, cells {w.mesh.n_cells} faces {w.mesh.n_faces}", flush=True)
+    g = gpu_run(vof, ctx, w, steps=1, alpha=a0)
+    o = oracle_mod.Oracle(w.mesh)
+    V, _, _, _ = o.geometry()
+    o.set_velocity(w.U0c, w.F0)
+    r = o.step(a0, w.dt[0], w.scale[0])
+    rec = r["rec"]
+    assert np.array_equal(g["cls"], rec["cls"]), "cell classes differ"
+    iface = rec["cls"] == 1
+    assert np.abs(g["n"][iface] - rec["n"][iface]).max(initial=0) < 1e-12
+    flux = w.F0 != 0
+    rel = np.abs(g["lam"][flux] - r["lam"][flux]) / np.maximum(np.abs(r["lam"][flux]), 1e-300)
+    assert rel.max(initial=0) < 1e-12, f"lambda rel err {rel.max()}"
+    assert np.array_equal(g["kind"], r["kind"].astype(np.uint8))
+    tol = vphase_tolerance(w, V, w.scale[0] * w.dt[0])
+    err = np.abs(g["vphase"] - r["vphase"])
+    bad = np.flatnonzero(err > tol)
+    assert bad.size == 0, f"{bad.size} faces beyond tolerance, worst {(err / tol).max():.3g}x"
+    assert np.abs(g["alpha"] - r["alpha"]).max() < 1e-13
+    g["mesh"].close()
+    return g, r
+
+
+def test_disc2d_one_step(vof, ctx, oracle_mod):
+    w = W.disc2d()
+    _compare_step(vof, ctx, oracle_mod, w, label="disc2d")
+
+
+def test_disc2d_full_run(vof, ctx, oracle_mod):
+    """All 50 steps: alpha within 1e-10, conservation and boundedness."""
+    w = W.disc2d()
+    g = gpu_run(vof, ctx, w)
+    o, a, st, lam, vp = oracle_run(oracle_mod, w)
+    V, _, _, _ = o.geometry()
+    assert np.abs(g["alpha"] - a).max() < 1e-10
+    m0 = (w.alpha0 * V).sum()
+    gs = g["stats"]
+    assert abs(gs["mass"] + gs["ledger"] - m0) <= 1e-12 * m0
+    assert gs["alpha_min"] > -1e-12 and gs["alpha_max"] < 1 + 1e-12
+    assert gs["capacity_overflows"] == 0 and gs["unreached_faces"] == 0
+    assert gs["face_fluxes"] == 50 * int((w.F0 != 0).sum())
+    g["mesh"].close()
+
+
+def test_slab_translation_exact(vof, ctx):
+    w = W.translate_slab(16, 2, a=0.3, b=0.55, U=(0.25, 0.0, 0.0), steps=24)
+    g = gpu_run(vof, ctx, w)
+    assert np.abs(g["alpha"] - W.slab_exact(w, 24)).max() < 1e-13
+    g["mesh"].close()
+
+
+def test_translation_is_exact_prism(vof, ctx):
+    """Uniform translation: lam = 1 to round-off, no correction iterations."""
+    w = W.disc2d(steps=1)
+    g = gpu_run(vof, ctx, w, steps=1)
+    flux = w.F0 != 0
+    assert np.abs(g["lam"][flux] - 1.0).max() < 1e-13
+    assert g["iters"][flux].max() <= 1
+    g["mesh"].close()
+
+
+def test_deform3d_small_steps(vof, ctx, oracle_mod):
+    w = W.deform3d(24, steps=8)
+    _compare_step(vof, ctx, oracle_mod, w, label="deform3d-24")
+    g = gpu_run(vof, ctx, w)
+    o, a, st, lam, vp = oracle_run(oracle_mod, w)
+    assert np.abs(g["alpha"] - a).max() < 1e-10
+    V, _, _, _ = o.geometry()
+    tol = vphase_tolerance(w, V, w.scale[-1] * w.dt[-1])
+    assert (np.abs(g["vphase"] - vp) <= tol).all()
+    g["mesh"].close()
+
+
+def test_rotate_tets_small(vof, ctx, oracle_mod):
+    w = W.rotate_tets(10, steps=6, sample=8)
+    _compare_step(vof, ctx, oracle_mod, w, label="tets-10")
+    g = gpu_run(vof, ctx, w, params={"check_stencil": 1})
+    o, a, st, lam, vp = oracle_run(oracle_mod, w, check_leak=True)
+    assert st["max_leak"] < 1e-12
+    assert g["stats"]["stencil_leaks"] == 0
+    assert np.abs(g["alpha"] - a).max() < 1e-10
+    g["mesh"].close()
+
+
+def test_empty_and_full_fields(vof, ctx):
+    w = W.deform3d(12, steps=3)
+    for val in (0.0, 1.0):
+        g = gpu_run(vof, ctx, w, alpha=np.full(w.mesh.n_cells, val))
+        assert np.abs(g["alpha"] - val).max() < 1e-13
+        assert g["stats"]["geometric_faces"] == 0
+        g["mesh"].close()
+
+
+def test_deform3d_full_size_sampled(vof, ctx, oracle_mod):
+    """The 128^3 case, one step, in the launch configuration of the benchmark:
+    sampled faces and cells checked one by one against the oracle."""
+    w = W.deform3d(128, steps=1)
+    print("[deform3d-128] gpu step", flush=True)
+    g = gpu_run(vof, ctx, w, steps=1)
+    rng = np.random.default_rng(17)
+    geo = np.flatnonzero(g["kind"] == 3)
+    flux = np.flatnonzero(w.F0 != 0)
+    faces = np.unique(np.concatenate([rng.choice(geo, min(1500, geo.size), replace=False),
+                                      rng.choice(flux, 1500, replace=False)]))
+    # cells whose alpha is checked: interface cells and their faces
+    icells = np.flatnonzero(g["cls"] == 1)
+    cells = rng.choice(icells, min(300, icells.size), replace=False)
+    m = w.mesh
+    own, nei = m.owner, m.neighbour
+    cell_faces = np.flatnonzero(np.isin(own, cells) |
+                                np.isin(np.concatenate([nei, -np.ones(m.n_faces - m.n_internal,
+                                                                      dtype=nei.dtype)]), cells))
+    faces = np.unique(np.concatenate([faces, cell_faces]))
+    print(f"[deform3d-128] oracle on {faces.size} faces", flush=True)
+    o = oracle_mod.Oracle(m)
+    V, _, _, _ = o.geometry()
+    o.set_velocity(w.U0c, w.F0)
+    st_off, st_cells = o.stencil()
+    need = np.unique(np.concatenate([st_cells[st_off[f]:st_off[f + 1]] for f in faces]))
+    rec = o.reconstruct_subset(w.alpha0, need)
+    assert np.array_equal(g["cls"][need], rec["cls"][need])
+    iface = need[rec["cls"][need] == 1]
+    assert np.abs(g["n"][iface] - rec["n"][iface]).max() < 1e-12
+    r = o.faces_subset(w.dt[0], w.scale[0], w.alpha0, faces)
+    fl = w.F0[faces] != 0
+    rel = np.abs(g["lam"][faces][fl] - r["lam"][fl]) / np.abs(r["lam"][fl])
+    assert rel.max() < 1e-12
+    tol = vphase_tolerance(w, V, w.scale[0] * w.dt[0])[faces]
+    assert (np.abs(g["vphase"][faces] - r["vphase"]) <= tol).all()
+    # alpha of the sampled cells from the oracle's face volumes
+    vph = dict(zip(faces.tolist(), r["vphase"].tolist()))
+    for c in cells[:100]:
+        acc = 0.0
+        for f in cell_faces:
+            if own[f] == c:
+                acc += vph[f]
+            elif f < m.n_internal and nei[f] == c:
+                acc -= vph[f]
+        assert abs(g["alpha"][c] - (w.alpha0[c] - acc / V[c])) < 1e-13
+    g["mesh"].close()
