@@ -33,9 +33,9 @@
  *  - No C++ exception and no abort crosses this interface.  Every function
  *    returns a vof_status; on failure vof_last_error() describes it (a
  *    thread-local string valid until the next call on the same thread).
- *  - Device-side failures (capacity overflow, unreachable flux correction,
- *    non-finite results) are latched in a flag word on the device and
- *    reported by the next synchronising call.
+ *  - Device-side failures (polytope capacity overflow, stencil leaks when
+ *    checked) are latched in a flag word on the device and reported by the
+ *    next synchronising call.
  *  - One context per host thread; calls on the same mesh must not overlap.
  */
 #ifndef VOF_H
@@ -54,8 +54,7 @@ typedef int32_t vof_status;
 #define VOF_EBADMESH (-2)  /* mesh failed validation                            */
 #define VOF_ENOMEM (-3)    /* device allocation failed                          */
 #define VOF_EDEVICE (-4)   /* HIP runtime error; destroy the context             */
-#define VOF_ENUMERIC (-5)  /* flux correction could not reach F dt on its branch,
-                              or a non-finite value was produced                 */
+#define VOF_ENUMERIC (-5)  /* a non-finite value was produced                   */
 #define VOF_ESTENCIL (-6)  /* a flux polyhedron left its stencil (leak check)   */
 #define VOF_ECAPACITY (-8) /* a clipped polytope exceeded its vertex capacity   */
 
@@ -160,8 +159,10 @@ vof_status vof_advect(vof_mesh *mesh, int32_t n_steps, const double *dt, const d
  * corrected sweep factor), VOF_FACE_VPHASE (double, V_{f,alpha}, signed like
  * F_f), VOF_FACE_ITERS (uint8, correction iterations), VOF_FACE_KIND (uint8:
  * 0 no flux, 1 trivially empty stencil, 2 trivially full stencil,
- * 3 geometric), VOF_FACE_STATUS (uint8: 0 ok, 1 correction target not
- * reachable on the monotone branch). */
+ * 3 geometric), VOF_FACE_STATUS (uint8: 0 ok, 1 correction target beyond the
+ * extremum of the swept volume on its monotone branch: lambda is set to the
+ * extremum and the face's phase volume is rescaled by F dt / V_f(lambda), so
+ * the face still carries exactly F dt of total volume). */
 #define VOF_FACE_LAMBDA 0
 #define VOF_FACE_VPHASE 1
 #define VOF_FACE_ITERS 2
@@ -185,7 +186,7 @@ typedef struct {
   int64_t geometric_faces;    /* sum over steps of faces clipped            */
   int64_t interface_cells;    /* sum over steps of interface cells          */
   int64_t fallback_cells;     /* sum over steps of vanishing-gradient cells */
-  int64_t unreached_faces;    /* corrections that hit the branch end        */
+  int64_t unreached_faces;    /* corrections clamped at the branch extremum */
   int64_t capacity_overflows; /* clipped polytopes beyond capacity          */
   int64_t stencil_leaks;      /* flux tets leaving their stencil (if checked) */
   int64_t correction_iters;   /* sum of correction iterations               */
@@ -194,8 +195,9 @@ typedef struct {
   double alpha_min, alpha_max;
 } vof_stats;
 /* Synchronises, computes mass and alpha range, and reports the counters.
- * Returns VOF_ENUMERIC / VOF_ECAPACITY / VOF_ESTENCIL if the corresponding
- * counter is non-zero (the stats are still filled in). */
+ * Returns VOF_ECAPACITY / VOF_ESTENCIL if the corresponding counter is
+ * non-zero (the stats are still filled in).  Clamped corrections are counted
+ * in unreached_faces and are not an error. */
 vof_status vof_get_stats(vof_mesh *mesh, vof_stats *out);
 vof_status vof_reset_stats(vof_mesh *mesh);
 

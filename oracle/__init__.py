@@ -55,7 +55,7 @@ def lib():
         L.orc_reconstruct.restype = i64
         L.orc_reconstruct.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.orc_phase_flux.restype = i64
-        L.orc_phase_flux.argtypes = [vp, d, d, vp, vp, C.c_int, vp, vp, vp, vp]
+        L.orc_phase_flux.argtypes = [vp, d, d, vp, vp, vp, C.c_int, vp, vp, vp, vp]
         L.orc_update.restype = d
         L.orc_update.argtypes = [vp, vp, vp, vp]
         L.orc_advect.restype = C.c_int
@@ -172,14 +172,16 @@ class Oracle:
         s = np.ascontiguousarray(s, dtype=np.float64)
         lib().orc_set_planes(self.h, _p(cls), _p(n), _p(s))
 
-    def phase_flux(self, dt, s, lam, alpha, check_leak=False):
+    def phase_flux(self, dt, s, lam, alpha, check_leak=False, status=None):
         lam = np.ascontiguousarray(lam, dtype=np.float64)
+        status = (np.zeros(self.nf, dtype=np.int8) if status is None
+                  else np.ascontiguousarray(status, dtype=np.int8))
         alpha = np.ascontiguousarray(alpha, dtype=np.float64)
         vp = np.empty(self.nf)
         kind = np.empty(self.nf, dtype=np.int8)
         leak = C.c_double(0.0)
         ne = C.c_int64(0)
-        ngeo = lib().orc_phase_flux(self.h, float(dt), float(s), _p(lam), _p(alpha),
+        ngeo = lib().orc_phase_flux(self.h, float(dt), float(s), _p(lam), _p(status), _p(alpha),
                                     int(check_leak), _p(vp), _p(kind), C.byref(leak),
                                     C.byref(ne))
         return {"vphase": vp, "kind": kind, "n_geometric": ngeo, "max_leak": leak.value,
@@ -196,7 +198,7 @@ class Oracle:
         """One full step of the path; returns every intermediate."""
         rec = self.reconstruct(alpha)
         lam, it, st, bad = self.flux_correction(dt, s)
-        ph = self.phase_flux(dt, s, lam, alpha, check_leak)
+        ph = self.phase_flux(dt, s, lam, alpha, check_leak, status=st)
         new, B = self.update(alpha, ph["vphase"])
         return {"alpha": new, "ledger": B, "lam": lam, "iters": it, "status": st,
                 "unreached": bad, **ph, "rec": rec}

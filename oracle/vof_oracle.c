@@ -575,7 +575,36 @@ static int correct_face(const omesh *M, int64_t f, double dt, double s, double *
     if ((v - target) * sg >= 0.0) { lb = l; gb = v - target; found = 1; break; }
     la = l; ga = v - target;
   }
-  if (!found) { *lam_out = la; return 1; }
+  if (!found) {
+    /* READING: the paper does not treat a target beyond the extremum of V on
+     * the branch.  lambda is set to that extremum (the largest swept volume
+     * before the swept face folds) and the face is flagged; its phase volume
+     * is then rescaled to F dt (the scalar coefficient correction the paper
+     * cites as an alternative).  V is exactly a cubic in lambda (every swept
+     * vertex is affine in lambda), so the extremum follows from the cubic
+     * through the four direct samples V(0), V(dir), V(2 dir), V(3 dir). */
+    double V1 = orc_flux_volume(M, f, dt, s, dir * 1.0);
+    double V2 = orc_flux_volume(M, f, dt, s, dir * 2.0);
+    double V3 = orc_flux_volume(M, f, dt, s, dir * 3.0);
+    double a3 = (V3 - 3.0 * V2 + 3.0 * V1) / 6.0;
+    double a2 = (V2 - 2.0 * V1 - 6.0 * a3) / 2.0;
+    double a1 = V1 - a2 - a3;
+    /* first positive root of a1 + 2 a2 t + 3 a3 t^2 (t = lambda / dir) */
+    double te = INFINITY;
+    if (a3 != 0.0) {
+      double disc = a2 * a2 - 3.0 * a1 * a3;
+      if (disc >= 0.0) {
+        double r1 = (-a2 - sqrt(disc)) / (3.0 * a3), r2 = (-a2 + sqrt(disc)) / (3.0 * a3);
+        if (r1 > 0.0) te = fmin(te, r1);
+        if (r2 > 0.0) te = fmin(te, r2);
+      }
+    } else if (a2 != 0.0) {
+      double r = -a1 / (2.0 * a2);
+      if (r > 0.0) te = r;
+    }
+    *lam_out = isfinite(te) ? dir * te : la;
+    return 1;
+  }
   if (gb == 0.0) { *lam_out = lb; return 0; }
   /* secant iterates from (0, -target) and (1, V(1) - target) */
   double x0 = 0.0, g0 = -target, x1 = 1.0, g1 = v1 - target;
@@ -793,7 +822,7 @@ static int tet_cell_volumes(const omesh *M, const double *a, const double *b, co
  * Returns the stencil leak |sum_c sum_k sgn_k |T_k ∩ C_c| - V_f| when
  * check_leak is set (geometric faces only). */
 static double phase_flux_face(const omesh *M, int64_t f, double dt, double s, double lam,
-                              const double *alpha, int check_leak, double *vphase,
+                              int status, const double *alpha, int check_leak, double *vphase,
                               int *kind, int *err) {
   *err = 0;
   double F = s * M->F0[f];
@@ -828,6 +857,8 @@ static double phase_flux_face(const omesh *M, int64_t f, double dt, double s, do
       total += sgn * vp;
     }
   }
+  /* flagged correction: the phase fraction of the swept polyhedron times F dt */
+  if (status == 1 && vf != 0.0) total *= (F * dt) / vf;
   *vphase = total;
   return check_leak ? fabs(covered - vf) : 0.0;
 }
@@ -835,15 +866,16 @@ static double phase_flux_face(const omesh *M, int64_t f, double dt, double s, do
 /* V_{f,alpha} for every face.  Outputs may be NULL.  Returns the number of
  * geometric faces; *max_leak receives the largest relative stencil leak. */
 int64_t orc_phase_flux(const omesh *M, double dt, double s, const double *lam,
-                       const double *alpha, int check_leak, double *vphase, int8_t *kind,
-                       double *max_leak, int64_t *nerr) {
+                       const int8_t *status, const double *alpha, int check_leak,
+                       double *vphase, int8_t *kind, double *max_leak, int64_t *nerr) {
   int64_t ngeo = 0, ne = 0;
   double leak = 0.0;
 #pragma omp parallel for schedule(dynamic, 16) reduction(+ : ngeo, ne) reduction(max : leak)
   for (int64_t f = 0; f < M->nf; ++f) {
     int kd = 0, er = 0;
     double v = 0.0;
-    double l = phase_flux_face(M, f, dt, s, lam[f], alpha, check_leak, &v, &kd, &er);
+    double l = phase_flux_face(M, f, dt, s, lam[f], status ? status[f] : 0, alpha, check_leak,
+                               &v, &kd, &er);
     if (vphase) vphase[f] = v;
     if (kind) kind[f] = (int8_t)kd;
     if (kd == 3) {
@@ -902,7 +934,7 @@ int orc_advect(omesh *M, double *alpha, int64_t nsteps, const double *dt, const 
     double res = 0.0;
     for (int64_t f = 0; f < M->nf; ++f) {
       double T = sc[n] * M->F0[f] * dt[n];
-      if (T != 0.0) {
+      if (T != 0.0 && stt[f] == 0) {
         itsum += it[f]; ++itcnt;
         double r = fabs(orc_flux_volume(M, f, dt[n], sc[n], lam[f]) - T) / fabs(T);
         if (r > res) res = r;
@@ -911,7 +943,7 @@ int orc_advect(omesh *M, double *alpha, int64_t nsteps, const double *dt, const 
     if (res > st->max_corr_residual) st->max_corr_residual = res;
     double leak = 0.0;
     int64_t ne = 0;
-    st->n_geometric += orc_phase_flux(M, dt[n], sc[n], lam, alpha, check_leak, vp, NULL,
+    st->n_geometric += orc_phase_flux(M, dt[n], sc[n], lam, stt, alpha, check_leak, vp, NULL,
                                       &leak, &ne);
     st->n_clip_errors += ne;
     if (leak > st->max_leak) st->max_leak = leak;
@@ -1035,7 +1067,7 @@ void orc_faces_subset(const omesh *M, double dt, double s, const double *alpha, 
     status[i] = (int8_t)correct_face(M, f, dt, s, &lam[i], &it);
     iters[i] = it;
     int kd = 0, er = 0;
-    phase_flux_face(M, f, dt, s, lam[i], alpha, 0, &vphase[i], &kd, &er);
+    phase_flux_face(M, f, dt, s, lam[i], status[i], alpha, 0, &vphase[i], &kd, &er);
     kind[i] = (int8_t)kd;
   }
 }

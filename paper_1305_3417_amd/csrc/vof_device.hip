@@ -343,7 +343,7 @@ __global__ __launch_bounds__(kBlock) void k_plane(DMesh m, DState s, DParams p) 
 // Correction (Section 2.3): V(lam) = F dt on the branch of V through 0 on
 // which V' keeps its sign (bounded by the real roots of V'), by Newton from
 // lam = 1 safeguarded by bisection.  status 1 when the target lies beyond the
-// branch end (lam is then the end, at most 64).
+// extremum of V at the branch end (lam is then that end, at most 64).
 __device__ __forceinline__ void correct(double c1, double c2, double c3, double T, double rtol,
                                         int maxit, double &lam, int &iters, int &status) {
   iters = 0;
@@ -443,6 +443,9 @@ __global__ __launch_bounds__(kBlock) void k_flux(DMesh m, DState s, DParams p, i
       double c2 = (t2 - dot(db, B)) / 6.0;
       double c3 = -dot(db, Cc) / 6.0;
       correct(c1, c2, c3, T, p.corr_rtol, p.corr_max_iter, lam, it, stat);
+      // A target beyond the extremum of V on the branch: lam sits at the
+      // extremum and the phase volume is rescaled to F dt (scalar correction).
+      if (stat) s.vscale[f] = T / (((c3 * lam + c2) * lam + c1) * lam);
       nflux = 1;
       nit = (unsigned long long)it;
       nbad = (unsigned long long)stat;
@@ -649,7 +652,9 @@ __global__ __launch_bounds__(kBlock) void k_face_sum(DMesh m, DState s) {
     const double *tv = s.tetvol + (int64_t)i * m.tpf;
     double acc = 0.0;
     for (int k = 0; k < m.tpf; ++k) acc += tv[k];
-    s.vphase[s.gfaces[i]] = acc;
+    int f = s.gfaces[i];
+    if (s.fstatus[f]) acc *= s.vscale[f];
+    s.vphase[f] = acc;
   }
 }
 

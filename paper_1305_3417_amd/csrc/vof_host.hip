@@ -133,8 +133,6 @@ vof_status device_status(vof_mesh *m) {
   HIP_OR_FAIL(hipMemcpy(&fl, m->ds.flags, sizeof fl, hipMemcpyDeviceToHost));
   if (fl & kFlagCapacity) return fail(VOF_ECAPACITY, "a clipped polytope exceeded its capacity");
   if (fl & kFlagLeak) return fail(VOF_ESTENCIL, "a flux polyhedron left its stencil");
-  if (fl & kFlagUnreached)
-    return fail(VOF_ENUMERIC, "a flux correction could not reach F dt on its branch");
   return VOF_OK;
 }
 
@@ -371,7 +369,7 @@ vof_status vof_mesh_upload(vof_context *ctx, const vof_mesh_desc *d, vof_mesh **
   ALLOC(bblo, nc); ALLOC(bbhi, nc);
   ALLOC(ds.alpha, nc); ALLOC(ds.cls, nc); ALLOC(ds.plane, nc); ALLOC(ds.pmask, np);
   ALLOC(ds.alpha_p, np); ALLOC(ds.U, np); ALLOC(ds.F0, nf); ALLOC(ds.lam, nf);
-  ALLOC(ds.vphase, nf); ALLOC(ds.iters, nf); ALLOC(ds.kind, nf); ALLOC(ds.fstatus, nf);
+  ALLOC(ds.vphase, nf); ALLOC(ds.vscale, nf); ALLOC(ds.iters, nf); ALLOC(ds.kind, nf); ALLOC(ds.fstatus, nf);
   ALLOC(ds.icells, nc); ALLOC(ds.gfaces, nf); ALLOC(ds.tetvol, nf * (int64_t)dm.tpf);
   ALLOC(ds.work, kWNum); ALLOC(ds.cnt, kCntNum); ALLOC(ds.flags, 1); ALLOC(ds.ledger, 1);
   ALLOC(m->stats_buf, 4);

@@ -87,6 +87,7 @@ struct DState {
   double *F0;           // nf
   double *lam;          // nf
   double *vphase;       // nf
+  double *vscale;       // nf: F dt / V(lam) for faces whose correction hit the branch end
   uint8_t *iters;       // nf
   uint8_t *kind;        // nf
   uint8_t *fstatus;     // nf

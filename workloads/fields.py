@@ -164,24 +164,29 @@ def tet_fraction_sampled(mesh: Mesh, inside, m: int = 12):
 # ----------------------------------------------------------------------------
 
 
+def sinpi(x):
+    """sin(pi x), exactly 0 at integer x (so walls and mid-planes get exact zeros)."""
+    x = np.asarray(x, dtype=np.float64)
+    return np.where(x == np.round(x), 0.0, np.sin(np.pi * x))
+
+
 def deformation_velocity(x):
     """Spatial part of the 3-D deformation field (Section 4.2.3, eq. 4.6)."""
     X, Y, Z = x[..., 0], x[..., 1], x[..., 2]
-    s = np.sin
-    pi = np.pi
-    return np.stack([2.0 * s(2 * pi * Y) * s(pi * X) ** 2 * s(2 * pi * Z),
-                     -s(2 * pi * X) * s(pi * Y) ** 2 * s(2 * pi * Z),
-                     -s(2 * pi * X) * s(2 * pi * Y) * s(pi * Z) ** 2], -1)
+    s = sinpi
+    return np.stack([2.0 * s(2 * Y) * s(X) ** 2 * s(2 * Z),
+                     -s(2 * X) * s(Y) ** 2 * s(2 * Z),
+                     -s(2 * X) * s(2 * Y) * s(Z) ** 2], -1)
 
 
 def deformation_potential(x):
     """A with curl A = deformation_velocity: (0, -s²πx s2πy s²πz, s²πx s²πy s2πz)/π."""
     X, Y, Z = x[..., 0], x[..., 1], x[..., 2]
-    s = np.sin
+    s = sinpi
     pi = np.pi
     return np.stack([np.zeros_like(X),
-                     -s(pi * X) ** 2 * s(2 * pi * Y) * s(pi * Z) ** 2 / pi,
-                     s(pi * X) ** 2 * s(pi * Y) ** 2 * s(2 * pi * Z) / pi], -1)
+                     -s(X) ** 2 * s(2 * Y) * s(Z) ** 2 / pi,
+                     s(X) ** 2 * s(Y) ** 2 * s(2 * Z) / pi], -1)
 
 
 def _edge_integral_gauss(potential, p, q, order: int = 8):
@@ -201,18 +206,18 @@ def _deformation_edge_integral(p, q):
     ax = np.abs(d) > 0
     only = ax.sum(1) == 1
     out = _edge_integral_gauss(deformation_potential, p, q)
-    s = np.sin
+    s = sinpi
     pi = np.pi
     cos = np.cos
     ye = only & ax[:, 1]
     if ye.any():
         X, Z = p[ye, 0], p[ye, 2]
-        out[ye] = (s(pi * X) ** 2 * s(pi * Z) ** 2 / (2 * pi * pi)) * (
+        out[ye] = (s(X) ** 2 * s(Z) ** 2 / (2 * pi * pi)) * (
             cos(2 * pi * q[ye, 1]) - cos(2 * pi * p[ye, 1]))
     ze = only & ax[:, 2]
     if ze.any():
         X, Y = p[ze, 0], p[ze, 1]
-        out[ze] = -(s(pi * X) ** 2 * s(pi * Y) ** 2 / (2 * pi * pi)) * (
+        out[ze] = -(s(X) ** 2 * s(Y) ** 2 / (2 * pi * pi)) * (
             cos(2 * pi * q[ze, 2]) - cos(2 * pi * p[ze, 2]))
     xe = only & ax[:, 0]
     out[xe] = 0.0
