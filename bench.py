@@ -1,0 +1,204 @@
+#!/usr/bin/env python3
+"""Throughput of the geometric PLIC VoF flux path on one MI355X.
+
+One step = the whole path on the 128^3 hex mesh of the deformation test
+(eq. 4.6, T = 3, sphere r = 0.15 at (0.35, 0.35, 0.35), Co 0.5, dt = 1/512):
+backtrack, flux polyhedra, flux correction, PLIC planes, clipping and the
+conservative update, for all 6.3M faces and 2.1M cells.  Inputs are resident
+in HBM when the timed region starts.
+
+Prints one JSON line: face-fluxes/s (faces with F != 0 per step, each built,
+corrected and given its phase volume), the dominant kernel's roofline figure
+from HIP-event timing inside the timed region, a sampled parity check of an
+extra step against the oracle, and the oracle's own rate on a bounded sample
+of the same step (CPU baseline).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "face-fluxes/s at 1e-12 rel vol err; batched/served vs plain, p50/p99 lat"
+PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector
+PEAK_HBM_GBS = 8000.0        # MI355X HBM3E
+
+# Algorithmic work per unit ("Measurement"): counted from the
+# arithmetic each kernel must do, not from instructions issued.
+FLUX_FLOPS_PER_QUAD_FACE = 480.0     # sweep, exact volume cubic, branch, ~2 Newton steps
+FLUX_BYTES_PER_FACE = 52.0           # CSR 20, F0 8, lambda 8, V_alpha 8, bytes 3, points ~5
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, alpha, step, n_sample, seed=3):
+    """The oracle on a random sample of the faces of one step (correction and
+    phase volume), with the planes of every cell in their stencils."""
+    import numpy as np
+
+    import oracle
+    o = oracle.Oracle(w.mesh)
+    o.set_velocity(w.U0c, w.F0)
+    rng = np.random.default_rng(seed)
+    flux = np.flatnonzero(w.F0 != 0)
+    faces = np.sort(rng.choice(flux, min(n_sample, flux.size), replace=False))
+    st_off, st_cells = o.stencil()
+    t0 = time.perf_counter()
+    need = np.unique(np.concatenate([st_cells[st_off[f]:st_off[f + 1]] for f in faces]))
+    o.reconstruct_subset(alpha, need)
+    o.faces_subset(w.dt[step], w.scale[step], alpha, faces)
+    t = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": faces.size / t, "unit": "face-fluxes/s", "cores": threads, "kind": "oracle",
+            "sample": f"{faces.size} random flux faces of one 128^3 deformation step "
+                      f"(flux correction + phase volume, planes of their stencil cells), "
+                      f"{t:.1f} s"}
+
+
+def parity_check(vof, mesh, w, step, n_sample=2000, seed=5):
+    """One extra (untimed) step from the current state, checked on sampled
+    faces against the oracle: lambda 1e-12 rel, V_alpha 1e-12 * max(|F| dt,
+    1e-6 V_owner)."""
+    import numpy as np
+
+    import oracle
+    alpha = vof.vof_read_alpha(mesh)
+    vof.vof_advect(mesh, w.dt[step:step + 1], w.scale[step:step + 1])
+    lam = vof.vof_read_face(mesh, vof.VOF_FACE_LAMBDA)
+    vph = vof.vof_read_face(mesh, vof.VOF_FACE_VPHASE)
+    kind = vof.vof_read_face(mesh, vof.VOF_FACE_KIND)
+    status = vof.vof_read_face(mesh, vof.VOF_FACE_STATUS)
+    rng = np.random.default_rng(seed)
+    geo = np.flatnonzero(kind == 3)
+    flux = np.flatnonzero(w.F0 != 0)
+    faces = np.unique(np.concatenate([rng.choice(geo, min(n_sample, geo.size), replace=False),
+                                      rng.choice(flux, n_sample, replace=False)]))
+    o = oracle.Oracle(w.mesh)
+    V, _, _, _ = o.geometry()
+    o.set_velocity(w.U0c, w.F0)
+    st_off, st_cells = o.stencil()
+    need = np.unique(np.concatenate([st_cells[st_off[f]:st_off[f + 1]] for f in faces]))
+    o.reconstruct_subset(alpha, need)
+    r = o.faces_subset(w.dt[step], w.scale[step], alpha, faces)
+    ok = (w.F0[faces] != 0) & (r["status"] == 0)
+    rel_lam = float((np.abs(lam[faces][ok] - r["lam"][ok]) / np.abs(r["lam"][ok])).max())
+    tol = 1e-12 * np.maximum(np.abs(w.F0[faces] * w.scale[step] * w.dt[step]),
+                             1e-6 * V[w.mesh.owner[faces]])
+    ratio = float((np.abs(vph[faces] - r["vphase"]) / tol).max())
+    flags_equal = bool(np.array_equal(status[faces], r["status"].astype(np.uint8)))
+    return {"faces": int(faces.size), "geometric": int(min(n_sample, geo.size)),
+            "max_rel_lambda": rel_lam, "max_vphase_err_over_tol": ratio,
+            "flags_equal": flags_equal,
+            "ok": bool(rel_lam < 1e-12 and ratio <= 1.0 and flags_equal)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=128, help="mesh is n^3 hexahedra")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=32768)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(the flux path is measured on one GPU's share of the mesh)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1305_3417_amd as vof
+    import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    K, Wm = args.steps, args.warmup
+    log(f"[bench] generating deform3d {args.n}^3")
+    w = W.deform3d(args.n, steps=Wm + K + 1)
+    ctx = vof.vof_context_create(0)
+    log("[bench] uploading mesh")
+    mesh = vof.upload_mesh(ctx, w.mesh)
+    vof.vof_set_alpha(mesh, w.alpha0)
+    vof.vof_set_velocity(mesh, w.U0c, w.F0)
+    log(f"[bench] warmup {Wm} steps")
+    vof.vof_advect(mesh, w.dt[:Wm], w.scale[:Wm])
+    st0 = vof.vof_get_stats(mesh)
+    vof.vof_profile_enable(mesh, True)
+    vof.vof_read_profile(mesh)
+    log(f"[bench] timing {K} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    vof.vof_advect(mesh, w.dt[Wm:Wm + K], w.scale[Wm:Wm + K])
+    vof.vof_synchronize(mesh)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = vof.vof_read_profile(mesh)
+    vof.vof_profile_enable(mesh, False)
+    st1 = vof.vof_get_stats(mesh)
+    face_fluxes = st1["face_fluxes"] - st0["face_fluxes"]
+    geo = st1["geometric_faces"] - st0["geometric_faces"]
+    value = face_fluxes / elapsed
+    log(f"[bench] {elapsed * 1e3 / K:.3f} ms/step, {value:.3e} face-fluxes/s")
+    log("[bench] per-kernel: " + ", ".join(f"{k} {v[0] / max(v[1], 1) * 1e3:.1f}us"
+                                           for k, v in prof.items()))
+
+    # dominant kernel and its roofline figure
+    dom = max(prof, key=lambda k: prof[k][0])
+    dom_ms, dom_n = prof[dom]
+    avg_s = dom_ms / dom_n / 1e3
+    per_launch_faces = face_fluxes / K
+    if dom == "flux":
+        achieved = FLUX_FLOPS_PER_QUAD_FACE * per_launch_faces / avg_s / 1e12
+        roof = {"kernel": "flux", "bound": "alu", "achieved": achieved,
+                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                "traffic": None, "avg_launch_us": avg_s * 1e6}
+    else:
+        roof = {"kernel": dom, "bound": "alu", "achieved": None, "peak": PEAK_FP64_TFLOPS,
+                "unit": "TFLOP/s", "frac": None, "traffic": None, "avg_launch_us": avg_s * 1e6}
+
+    parity = None
+    if not args.no_parity:
+        log("[bench] parity check of one extra step against the oracle")
+        parity = parity_check(vof, mesh, w, Wm + K)
+        log(f"[bench] parity {parity}")
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] oracle CPU baseline")
+        a = vof.vof_read_alpha(mesh)
+        cpu = cpu_baseline(w, a, Wm + K, args.cpu_sample)
+        log(f"[bench] cpu {cpu}")
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "face-fluxes/s", "n_gpus": 1, "steps": K,
+        "warmup": Wm, "ms_per_step": elapsed * 1e3 / K, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"deform3d hex {args.n}^3 (eq. 4.6, T=3, sphere r=0.15 at "
+                               f"(0.35,0.35,0.35), Co 0.5, dt=1/{4 * args.n}), steps "
+                               f"{Wm}..{Wm + K - 1}",
+                   "cells": int(w.mesh.n_cells), "faces": int(w.mesh.n_faces),
+                   "parallelism": "single GPU"},
+        "cell_updates_per_s": w.mesh.n_cells * K / elapsed,
+        "geometric_faces_per_step": geo / K,
+        "face_fluxes_per_step": face_fluxes / K,
+        "kernels_us": {k: v[0] / max(v[1], 1) * 1e3 for k, v in prof.items()},
+        "roofline": roof,
+        "parity": parity,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    vof.vof_mesh_destroy(mesh)
+    vof.vof_context_destroy(ctx)
+
+
+if __name__ == "__main__":
+    main()

@@ -205,6 +205,15 @@ vof_status vof_reset_stats(vof_mesh *mesh);
  * device errors. */
 vof_status vof_synchronize(vof_mesh *mesh);
 
+/* Per-kernel timing.  While enabled, vof_advect brackets every kernel it
+ * launches with HIP events on the context's stream.  vof_read_profile
+ * synchronises, writes for kernel ids 0..n-1 the summed duration in ms and
+ * the number of launches since the last read, and clears the totals.
+ * vof_profile_kernel_name gives the name of a kernel id (NULL past the last). */
+vof_status vof_profile_enable(vof_mesh *mesh, int32_t enable);
+const char *vof_profile_kernel_name(int32_t id);
+vof_status vof_read_profile(vof_mesh *mesh, double *ms, int64_t *launches, int32_t n);
+
 /* Host self-test of the device geometry routines (compiled for the host as
  * well): volume of the tetrahedron (a, b, c, d) (12 doubles) intersected with
  * the half-spaces {n_k . x <= s_k} (4 doubles per plane).  Returns the volume

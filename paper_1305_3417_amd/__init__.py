@@ -41,7 +41,7 @@ EXPORTED = [
     "vof_set_params", "vof_set_alpha", "vof_read_alpha", "vof_set_velocity",
     "vof_reconstruct", "vof_advect", "vof_read_face", "vof_read_planes",
     "vof_read_point_velocity", "vof_get_stats", "vof_reset_stats", "vof_synchronize",
-    "vof_selftest_tet_clip",
+    "vof_selftest_tet_clip", "vof_profile_enable", "vof_profile_kernel_name", "vof_read_profile",
 ]
 
 
@@ -118,6 +118,9 @@ def lib():
             "vof_reset_stats": (i32, [vp]),
             "vof_synchronize": (i32, [vp]),
             "vof_selftest_tet_clip": (d, [vp, i32, vp]),
+            "vof_profile_enable": (i32, [vp, i32]),
+            "vof_profile_kernel_name": (C.c_char_p, [i32]),
+            "vof_read_profile": (i32, [vp, vp, vp, i32]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -348,6 +351,27 @@ def vof_selftest_tet_clip(tet, planes) -> float:
         planes = np.zeros((0, 4))
     return lib().vof_selftest_tet_clip(tet.ctypes.data_as(C.c_void_p), int(planes.shape[0]),
                                        planes.ctypes.data_as(C.c_void_p))
+
+
+def vof_profile_enable(mesh: MeshHandle, enable: bool = True):
+    _check(lib().vof_profile_enable(mesh.h, int(bool(enable))), "vof_profile_enable")
+
+
+def vof_profile_kernel_name(i: int):
+    r = lib().vof_profile_kernel_name(int(i))
+    return None if r is None else r.decode()
+
+
+def vof_read_profile(mesh: MeshHandle) -> dict:
+    """{kernel name: (total ms, launches)} since the last read."""
+    names = []
+    while vof_profile_kernel_name(len(names)) is not None:
+        names.append(vof_profile_kernel_name(len(names)))
+    ms = np.zeros(len(names))
+    cnt = np.zeros(len(names), dtype=np.int64)
+    _check(lib().vof_read_profile(mesh.h, ms.ctypes.data_as(C.c_void_p),
+                                  cnt.ctypes.data_as(C.c_void_p), len(names)), "vof_read_profile")
+    return {n: (float(ms[i]), int(cnt[i])) for i, n in enumerate(names)}
 
 
 def upload_mesh(ctx, mesh) -> MeshHandle:

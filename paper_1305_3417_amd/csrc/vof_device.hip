@@ -758,20 +758,45 @@ void launch_reconstruct(const DMesh &m, const DState &s, const DParams &p, hipSt
   launch_reconstruct_impl(m, s, p, st);
 }
 
-void launch_step(const DMesh &m, const DState &s, const DParams &p, int step, hipStream_t st) {
-  k_reset<<<1, 64, 0, st>>>(s);
-  launch_reconstruct_impl(m, s, p, st);
+bool Prof::begin(int kid) {
+  if (n >= cap) return false;
+  (void)hipEventRecord(recs[n].a, st);
+  recs[n].kid = kid;
+  return true;
+}
+void Prof::end(int kid) {
+  (void)kid;
+  (void)hipEventRecord(recs[n].b, st);
+  ++n;
+}
+
+// kernel launch bracketed by timing events when profiling
+#define TIMED(prof, kid, launch)                       \
+  do {                                                 \
+    bool on_ = (prof) && (prof)->begin(kid);           \
+    launch;                                            \
+    if (on_) (prof)->end(kid);                         \
+  } while (0)
+
+void launch_step(const DMesh &m, const DState &s, const DParams &p, int step, hipStream_t st,
+                 Prof *prof) {
+  TIMED(prof, kKReset, (k_reset<<<1, 64, 0, st>>>(s)));
+  TIMED(prof, kKCellClass, (k_cell_class<<<grid_for(m.nc, kBlock), kBlock, 0, st>>>(m, s, p)));
+  TIMED(prof, kKPointPrep, (k_point_prep<<<grid_for(m.np, kBlock), kBlock, 0, st>>>(m, s)));
+  unsigned gp = grid_for(m.nc, kBlock);
+  gp = gp < 2048 ? (gp ? gp : 1) : 2048;
+  TIMED(prof, kKPlane, (k_plane<<<gp, kBlock, 0, st>>>(m, s, p)));
   unsigned gf = grid_for(m.nf, kBlock);
   if (m.maxn <= 3)
-    k_flux<3><<<gf, kBlock, 0, st>>>(m, s, p, step);
+    TIMED(prof, kKFlux, (k_flux<3><<<gf, kBlock, 0, st>>>(m, s, p, step)));
   else if (m.maxn == 4)
-    k_flux<4><<<gf, kBlock, 0, st>>>(m, s, p, step);
+    TIMED(prof, kKFlux, (k_flux<4><<<gf, kBlock, 0, st>>>(m, s, p, step)));
   else
-    k_flux<kMaxFacePoints><<<gf, kBlock, 0, st>>>(m, s, p, step);
-  k_clip<kMaxFacePoints><<<4096, kClipBlock, 0, st>>>(m, s, p, step);
-  k_face_sum<<<1024, kBlock, 0, st>>>(m, s);
-  k_update<<<grid_for(m.nc, kBlock), kBlock, 0, st>>>(m, s);
-  k_ledger<<<1, kBlock, 0, st>>>(m, s);
+    TIMED(prof, kKFlux, (k_flux<kMaxFacePoints><<<gf, kBlock, 0, st>>>(m, s, p, step)));
+  TIMED(prof, kKClip, (k_clip<kMaxFacePoints><<<4096, kClipBlock, 0, st>>>(m, s, p, step)));
+  TIMED(prof, kKFaceSum, (k_face_sum<<<1024, kBlock, 0, st>>>(m, s)));
+  TIMED(prof, kKUpdate, (k_update<<<grid_for(m.nc, kBlock), kBlock, 0, st>>>(m, s)));
+  TIMED(prof, kKLedger, (k_ledger<<<1, kBlock, 0, st>>>(m, s)));
 }
 
 void launch_stats(const DMesh &m, const DState &s, double *out4, hipStream_t st) {

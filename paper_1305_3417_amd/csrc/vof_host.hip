@@ -60,6 +60,10 @@ struct vof_mesh {
   int64_t step_cap = 0;
   bool have_alpha = false, have_velocity = false;
   double *stats_buf = nullptr;  // 4 doubles
+  bool profiling = false;
+  Prof prof;
+  double prof_ms[kKNum] = {0};
+  int64_t prof_count[kKNum] = {0};
 
   template <class T>
   vof_status alloc(T **p, int64_t count) {
@@ -76,6 +80,11 @@ struct vof_mesh {
     return VOF_OK;
   }
   ~vof_mesh() {
+    for (int i = 0; i < prof.cap; ++i) {
+      (void)hipEventDestroy(prof.recs[i].a);
+      (void)hipEventDestroy(prof.recs[i].b);
+    }
+    delete[] prof.recs;
     for (void *q : allocs) (void)hipFree(q);
   }
 };
@@ -526,8 +535,27 @@ vof_status vof_advect(vof_mesh *m, int32_t n_steps, const double *dt, const doub
   }
   HIP_OR_FAIL(hipMemcpy(m->ds.dt, dt, sizeof(double) * n_steps, hipMemcpyHostToDevice));
   HIP_OR_FAIL(hipMemcpy(m->ds.sc, scale, sizeof(double) * n_steps, hipMemcpyHostToDevice));
+  if (m->profiling) {
+    // room for every kernel of every step; pairs are folded into totals by
+    // vof_read_profile
+    int need = m->prof.n + n_steps * kKNum;
+    if (need > m->prof.cap) {
+      HIP_OR_FAIL(hipStreamSynchronize(s));
+      Prof::Rec *nr = new (std::nothrow) Prof::Rec[need];
+      if (!nr) return fail(VOF_ENOMEM, "host allocation failed");
+      for (int i = 0; i < m->prof.cap; ++i) nr[i] = m->prof.recs[i];
+      for (int i = m->prof.cap; i < need; ++i) {
+        HIP_OR_FAIL(hipEventCreate(&nr[i].a));
+        HIP_OR_FAIL(hipEventCreate(&nr[i].b));
+      }
+      delete[] m->prof.recs;
+      m->prof.recs = nr;
+      m->prof.cap = need;
+    }
+    m->prof.st = s;
+  }
   for (int32_t i = 0; i < n_steps; ++i) {
-    launch_step(m->dm, m->ds, m->dp, i, s);
+    launch_step(m->dm, m->ds, m->dp, i, s, m->profiling ? &m->prof : nullptr);
     HIP_OR_FAIL(hipGetLastError());
   }
   return VOF_OK;
@@ -637,6 +665,38 @@ vof_status vof_reset_stats(vof_mesh *m) {
   HIP_OR_FAIL(hipMemsetAsync(m->ds.flags, 0, sizeof(uint32_t), s));
   HIP_OR_FAIL(hipMemsetAsync(m->ds.ledger, 0, sizeof(double), s));
   HIP_OR_FAIL(hipStreamSynchronize(s));
+  return VOF_OK;
+}
+
+vof_status vof_profile_enable(vof_mesh *m, int32_t enable) {
+  if (!m) return fail(VOF_EINVAL, "null argument");
+  m->profiling = enable != 0;
+  return VOF_OK;
+}
+
+const char *vof_profile_kernel_name(int32_t id) {
+  static const char *names[kKNum] = {"reset", "cell_class", "point_prep", "plane", "flux",
+                                     "clip", "face_sum", "update", "ledger"};
+  return (id >= 0 && id < kKNum) ? names[id] : nullptr;
+}
+
+vof_status vof_read_profile(vof_mesh *m, double *ms, int64_t *launches, int32_t n) {
+  if (!m || !ms || !launches || n < 0) return fail(VOF_EINVAL, "null argument");
+  vof_status rc = set_device(m->ctx);
+  if (rc) return rc;
+  HIP_OR_FAIL(hipStreamSynchronize(m->ctx->stream));
+  for (int i = 0; i < m->prof.n; ++i) {
+    float t = 0.0f;
+    HIP_OR_FAIL(hipEventElapsedTime(&t, m->prof.recs[i].a, m->prof.recs[i].b));
+    m->prof_ms[m->prof.recs[i].kid] += t;
+    m->prof_count[m->prof.recs[i].kid] += 1;
+  }
+  m->prof.n = 0;
+  for (int k = 0; k < n && k < kKNum; ++k) {
+    ms[k] = m->prof_ms[k];
+    launches[k] = m->prof_count[k];
+  }
+  for (int k = 0; k < kKNum; ++k) { m->prof_ms[k] = 0.0; m->prof_count[k] = 0; }
   return VOF_OK;
 }
 

@@ -102,12 +102,27 @@ struct DState {
   double *sc;           // per-step scale
 };
 
+// Per-kernel timing with HIP events on the launch stream (optional).
+enum KernelId : int {
+  kKReset = 0, kKCellClass, kKPointPrep, kKPlane, kKFlux, kKClip, kKFaceSum, kKUpdate,
+  kKLedger, kKNum
+};
+struct Prof {
+  struct Rec { int kid; hipEvent_t a, b; };
+  Rec *recs = nullptr;  // pool of recorded pairs
+  int n = 0, cap = 0;
+  hipStream_t st = nullptr;
+  bool begin(int kid);  // records the start event; false if the pool is full
+  void end(int kid);
+};
+
 // launchers (vof_device.hip)
 void launch_mesh_geometry(const DMesh &m, double4 *X, const double *pts, double4 *S, double4 *C,
                           double *V, double4 *XC, double *wpc, double4 *cpl, double4 *bblo,
                           double4 *bbhi, uint32_t *flags, hipStream_t st);
 void launch_point_velocity(const DMesh &m, const double *U0c, double4 *U, hipStream_t st);
-void launch_step(const DMesh &m, const DState &s, const DParams &p, int step, hipStream_t st);
+void launch_step(const DMesh &m, const DState &s, const DParams &p, int step, hipStream_t st,
+                 Prof *prof);
 void launch_reconstruct(const DMesh &m, const DState &s, const DParams &p, hipStream_t st);
 void launch_stats(const DMesh &m, const DState &s, double *out4, hipStream_t st);
 double host_tet_clip(const double *tet, int n_planes, const double *planes);
