@@ -10,8 +10,11 @@ but the first call raises if libvof.so is missing.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import sys
+import weakref
 
 import numpy as np
 
@@ -195,6 +198,9 @@ def vof_context_destroy(ctx):
     _check(lib().vof_context_destroy(ctx), "vof_context_destroy")
 
 
+_live_meshes: "weakref.WeakSet" = weakref.WeakSet()
+
+
 class MeshHandle:
     """Owns a vof_mesh* and the host arrays it was uploaded from."""
 
@@ -202,6 +208,7 @@ class MeshHandle:
         self.h = h
         self.info = info
         self._keep = keep
+        _live_meshes.add(self)
 
     def close(self):
         if self.h:
@@ -209,8 +216,20 @@ class MeshHandle:
             self.h = None
 
     def __del__(self):
+        # never call into the HIP runtime while the interpreter is shutting down
+        if sys.is_finalizing():
+            return
         try:
             self.close()
+        except Exception:
+            pass
+
+
+@atexit.register
+def _close_live_meshes():
+    for m in list(_live_meshes):
+        try:
+            m.close()
         except Exception:
             pass
 

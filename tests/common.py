@@ -40,7 +40,24 @@ def oracle_run(oracle, w, steps=None, alpha=None, check_leak=False):
     return o, a, st, lam, vp
 
 
-def vphase_tolerance(w, V, scale_dt):
-    """Per-face bound 1e-12 * max(|F| dt, 1e-6 V_owner)."""
+def swept_scale(w, S, Up, scale_dt):
+    """Gross swept volume of each face, |S_f| max_i |s dt U_p_i|: the size of the
+    terms whose signed sum is the flux polyhedron volume.  Where the normal
+    flux is small against a tangential sweep the net volume is a difference of
+    much larger terms, so FP64 evaluations agree only to eps times this."""
+    m = w.mesh
+    sp = np.linalg.norm(Up, axis=1)[m.face_points]
+    n = np.diff(m.face_offsets)
+    face_of = np.repeat(np.arange(m.n_faces), n)
+    mx = np.zeros(m.n_faces)
+    np.maximum.at(mx, face_of, sp)
+    return np.linalg.norm(S, axis=1) * mx * abs(scale_dt)
+
+
+def vphase_tolerance(w, V, scale_dt, S=None, Up=None):
+    """Per-face bound 1e-12 * max(|F| dt, gross swept volume, 1e-6 V_owner)."""
     F = np.abs(w.F0) * abs(scale_dt)
-    return 1e-12 * np.maximum(F, 1e-6 * V[w.mesh.owner])
+    ref = np.maximum(F, 1e-6 * V[w.mesh.owner])
+    if S is not None:
+        ref = np.maximum(ref, swept_scale(w, S, Up, scale_dt))
+    return 1e-12 * ref
