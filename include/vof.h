@@ -65,8 +65,9 @@ typedef struct vof_context vof_context;
 typedef struct vof_mesh vof_mesh;
 
 /* Create a context on HIP device `device`; all work goes on `hip_stream`
- * (a hipStream_t; NULL = the default stream).  The stream must outlive the
- * context. */
+ * (a hipStream_t; NULL = the default stream).  A mesh keeps a copy of the
+ * device and stream of the context it was uploaded with, so the context may
+ * be destroyed before its meshes; the stream must outlive every mesh. */
 vof_status vof_context_create(int32_t device, void *hip_stream, vof_context **out);
 vof_status vof_context_destroy(vof_context *ctx);
 /* Thread-local description of the last failure on this thread. */

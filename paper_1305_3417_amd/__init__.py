@@ -224,15 +224,6 @@ class MeshHandle:
         except Exception:
             pass
 
-
-@atexit.register
-def _close_live_meshes():
-    for m in list(_live_meshes):
-        try:
-            m.close()
-        except Exception:
-            pass
-
     @property
     def n_cells(self):
         return self.info.n_cells
@@ -244,6 +235,15 @@ def _close_live_meshes():
     @property
     def n_points(self):
         return self.info.n_points
+
+
+@atexit.register
+def _close_live_meshes():
+    for m in list(_live_meshes):
+        try:
+            m.close()
+        except Exception:
+            pass
 
 
 def vof_mesh_upload(ctx, points, face_offsets, face_points, owner, neighbour, n_cells):

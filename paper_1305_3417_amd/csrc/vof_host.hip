@@ -49,7 +49,7 @@ struct vof_context {
 };
 
 struct vof_mesh {
-  vof_context *ctx = nullptr;
+  vof_context *ctx = nullptr;  // copy of the creating context (device, stream)
   DMesh dm{};
   DState ds{};
   DParams dp{};
@@ -58,6 +58,7 @@ struct vof_mesh {
   int32_t max_cell_faces = 0;
   int64_t st_entries = 0;
   int64_t step_cap = 0;
+  vof_context own_ctx{};
   bool have_alpha = false, have_velocity = false;
   double *stats_buf = nullptr;  // 4 doubles
   bool profiling = false;
@@ -355,7 +356,10 @@ vof_status vof_mesh_upload(vof_context *ctx, const vof_mesh_desc *d, vof_mesh **
 
   vof_mesh *m = new (std::nothrow) vof_mesh;
   if (!m) return fail(VOF_ENOMEM, "host allocation failed");
-  m->ctx = ctx;
+  // the mesh keeps its own copy of the device and stream, so it stays usable
+  // (and destroyable) after the context object is gone
+  m->own_ctx = *ctx;
+  m->ctx = &m->own_ctx;
   m->max_cell_faces = maxcf;
   m->st_entries = (int64_t)st.size();
   DMesh &dm = m->dm;
