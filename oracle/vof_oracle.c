@@ -548,69 +548,74 @@ double orc_flux_volume(const omesh *M, int64_t f, double dt, double s, double la
 
 /* Flux correction (Section 2.3): the swept polyhedron is corrected by the
  * secant method until its volume equals F_f dt (eq. 2.17 with the sign of
- * F_f, eqs. 2.20-2.21).  Start: lambda = 0 (no volume) and lambda = 1 (the
- * plain sweep, whose volume is close to the target).
- * READING: a bracket on the monotone branch of V(lambda) through 0 is found
- * first by stepping lambda by 1/2 away from 0 in the direction in which the
- * volume moves towards the target; a secant iterate leaving the bracket is
- * replaced by bisection.  Converged when |V - F dt| <= 1e-14 |F dt| or the
- * bracket is exhausted.  Status: 0 ok, 1 target not reachable on the branch. */
+ * F_f, eqs. 2.20-2.21), moving the end points along the point trajectories
+ * without topology changes.
+ * READING: one factor lambda per face scales every sweep vector of the face.
+ * Every swept vertex is affine in lambda, so V(lambda) is exactly a cubic;
+ * the monotone branch of V through lambda = 0 is bounded by the real roots
+ * of V' nearest to 0, located from the cubic through the direct samples
+ * V(0) = 0, V(1), V(2), V(3).  The root is sought on the side of 0 where V
+ * takes the sign of F dt.  Secant iterates start from lambda = 0 and the
+ * plain sweep (lambda = +-1), inside that bracket; an iterate leaving the
+ * bracket is replaced by bisection.  Converged when |V - F dt| <= 1e-14 |F dt|
+ * or the bracket is exhausted.
+ * If F dt lies beyond the extremum of V at the branch end, lambda is set to
+ * that extremum and status 1 is returned (the phase volume of such a face is
+ * rescaled to F dt, see phase_flux_face). */
+static void branch_cubic(const omesh *M, int64_t f, double dt, double s, double *a1,
+                         double *a2, double *a3) {
+  double V1 = orc_flux_volume(M, f, dt, s, 1.0);
+  double V2 = orc_flux_volume(M, f, dt, s, 2.0);
+  double V3 = orc_flux_volume(M, f, dt, s, 3.0);
+  *a3 = (V3 - 3.0 * V2 + 3.0 * V1) / 6.0;
+  *a2 = (V2 - 2.0 * V1 - 6.0 * *a3) / 2.0;
+  *a1 = V1 - *a2 - *a3;
+}
+
+/* first root of a1 + 2 a2 t + 3 a3 t^2 with t > 0 (INFINITY if none) */
+static double first_positive_root(double a1, double a2, double a3) {
+  double te = INFINITY;
+  if (a3 != 0.0) {
+    double disc = a2 * a2 - 3.0 * a1 * a3;
+    if (disc >= 0.0) {
+      double r1 = (-a2 - sqrt(disc)) / (3.0 * a3), r2 = (-a2 + sqrt(disc)) / (3.0 * a3);
+      if (r1 > 0.0) te = fmin(te, r1);
+      if (r2 > 0.0) te = fmin(te, r2);
+    }
+  } else if (a2 != 0.0) {
+    double r = -a1 / (2.0 * a2);
+    if (r > 0.0) te = r;
+  }
+  return te;
+}
+
 static int correct_face(const omesh *M, int64_t f, double dt, double s, double *lam_out,
                         int *iters) {
   double target = s * M->F0[f] * dt;
   *iters = 0;
-  if (target == 0.0) { *lam_out = 0.0; return 0; }
-  double sg = target > 0 ? 1.0 : -1.0;
-  double v1 = orc_flux_volume(M, f, dt, s, 1.0);
-  double dir = (v1 * sg > 0.0) ? 1.0 : -1.0;
-  /* bracket search along dir */
-  double la = 0.0, ga = -target, lb = 0.0, gb = -target;
-  double prev = 0.0;
-  int found = 0;
-  for (int k = 1; k <= 64; ++k) {
-    double l = dir * 0.5 * k;
-    double v = orc_flux_volume(M, f, dt, s, l);
-    if (v * sg < prev * sg) break;          /* left the monotone branch */
-    prev = v;
-    if ((v - target) * sg >= 0.0) { lb = l; gb = v - target; found = 1; break; }
-    la = l; ga = v - target;
-  }
-  if (!found) {
-    /* READING: the paper does not treat a target beyond the extremum of V on
-     * the branch.  lambda is set to that extremum (the largest swept volume
-     * before the swept face folds) and the face is flagged; its phase volume
-     * is then rescaled to F dt (the scalar coefficient correction the paper
-     * cites as an alternative).  V is exactly a cubic in lambda (every swept
-     * vertex is affine in lambda), so the extremum follows from the cubic
-     * through the four direct samples V(0), V(dir), V(2 dir), V(3 dir). */
-    double V1 = orc_flux_volume(M, f, dt, s, dir * 1.0);
-    double V2 = orc_flux_volume(M, f, dt, s, dir * 2.0);
-    double V3 = orc_flux_volume(M, f, dt, s, dir * 3.0);
-    double a3 = (V3 - 3.0 * V2 + 3.0 * V1) / 6.0;
-    double a2 = (V2 - 2.0 * V1 - 6.0 * a3) / 2.0;
-    double a1 = V1 - a2 - a3;
-    /* first positive root of a1 + 2 a2 t + 3 a3 t^2 (t = lambda / dir) */
-    double te = INFINITY;
-    if (a3 != 0.0) {
-      double disc = a2 * a2 - 3.0 * a1 * a3;
-      if (disc >= 0.0) {
-        double r1 = (-a2 - sqrt(disc)) / (3.0 * a3), r2 = (-a2 + sqrt(disc)) / (3.0 * a3);
-        if (r1 > 0.0) te = fmin(te, r1);
-        if (r2 > 0.0) te = fmin(te, r2);
-      }
-    } else if (a2 != 0.0) {
-      double r = -a1 / (2.0 * a2);
-      if (r > 0.0) te = r;
-    }
-    *lam_out = isfinite(te) ? dir * te : la;
+  *lam_out = 0.0;
+  if (target == 0.0) return 0;
+  double a1, a2, a3;
+  branch_cubic(M, f, dt, s, &a1, &a2, &a3);
+  if (!(a1 != 0.0)) return 1;
+  /* side of 0 on which V takes the sign of the target; in t = lambda / dir
+   * the cubic is b1 t + b2 t^2 + b3 t^3 with b1 > 0 on the branch */
+  double dir = ((a1 > 0.0) == (target > 0.0)) ? 1.0 : -1.0;
+  double te = first_positive_root(a1 * dir, a2, a3 * dir);
+  double end = isfinite(te) ? fmin(te, 32.0) : 32.0;
+  double vend = orc_flux_volume(M, f, dt, s, dir * end);
+  if ((vend - target) * (target > 0 ? 1.0 : -1.0) < 0.0) {
+    *lam_out = dir * end;
     return 1;
   }
-  if (gb == 0.0) { *lam_out = lb; return 0; }
-  /* secant iterates from (0, -target) and (1, V(1) - target) */
-  double x0 = 0.0, g0 = -target, x1 = 1.0, g1 = v1 - target;
-  double lo = la < lb ? la : lb, hi = la < lb ? lb : la;
-  double glo = la < lb ? ga : gb;
-  double x = x1, gx = g1;
+  /* bracket [lo, hi] around the root, g(lo) and g(hi) of opposite sign */
+  double lo = fmin(0.0, dir * end), hi = fmax(0.0, dir * end);
+  double glo = (lo == 0.0) ? -target : vend - target;
+  /* secant iterates from (0, -target) and (dir, V(dir) - target) */
+  double x0 = 0.0, g0 = -target;
+  double x1 = dir, g1 = orc_flux_volume(M, f, dt, s, dir) - target;
+  double x = x1;
+  if (fabs(g1) <= 1e-14 * fabs(target) && x1 > lo && x1 < hi) { *lam_out = x1; return 0; }
   int bisect = 0;
   for (int it = 0; it < 200; ++it) {
     double xn;
@@ -622,13 +627,12 @@ static int correct_face(const omesh *M, int64_t f, double dt, double s, double *
     }
     double gn = orc_flux_volume(M, f, dt, s, xn) - target;
     ++*iters;
-    x = xn; gx = gn;
+    x = xn;
     if (fabs(gn) <= 1e-14 * fabs(target)) break;
     if ((gn < 0.0) == (glo < 0.0)) { lo = xn; glo = gn; } else { hi = xn; }
     x0 = x1; g0 = g1; x1 = xn; g1 = gn;
     if (hi - lo <= 4e-16 * fmax(fabs(lo), fabs(hi))) break;
   }
-  (void)gx;
   *lam_out = x;
   return 0;
 }
