@@ -572,13 +572,16 @@ static void branch_cubic(const omesh *M, int64_t f, double dt, double s, double 
   *a1 = V1 - *a2 - *a3;
 }
 
-/* first root of a1 + 2 a2 t + 3 a3 t^2 with t > 0 (INFINITY if none) */
+/* first root of a1 + 2 a2 t + 3 a3 t^2 with t > 0 (INFINITY if none); the
+ * two roots are taken as q / (3 a3) and a1 / q with q = -(a2 + sgn(a2) sqrt D),
+ * which avoids cancellation when a3 is small */
 static double first_positive_root(double a1, double a2, double a3) {
   double te = INFINITY;
   if (a3 != 0.0) {
     double disc = a2 * a2 - 3.0 * a1 * a3;
     if (disc >= 0.0) {
-      double r1 = (-a2 - sqrt(disc)) / (3.0 * a3), r2 = (-a2 + sqrt(disc)) / (3.0 * a3);
+      double q = -(a2 + copysign(sqrt(disc), a2));
+      double r1 = q / (3.0 * a3), r2 = (q != 0.0) ? a1 / q : r1;
       if (r1 > 0.0) te = fmin(te, r1);
       if (r2 > 0.0) te = fmin(te, r2);
     }
