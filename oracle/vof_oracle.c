@@ -89,15 +89,27 @@ static double opoly_volume(const opoly *P) {
  * algorithm): every face is clipped against the half-space {x : n.x <= s};
  * points created on cut edges are shared between the two faces of the edge
  * (no repeated points); the cap face is then formed from the cut points and
- * ordered by an insertion sort of their angle about the cap centre.
- * Half-spaces are closed: vertices on the plane are kept.
+ * the kept vertices on the plane, ordered by an insertion sort of their angle
+ * about the cap centre.  Half-spaces are closed: vertices on the plane are
+ * kept.  A clipped face whose vertices are all cap points lies in the plane
+ * (or has no area) and is replaced by the cap, so a face that rounding
+ * leaves a hair outside the plane is not counted twice.
  * Returns 0 on success, -1 on capacity overflow. */
 static int opoly_clip(opoly *P, const double *n, double s) {
   if (P->nv == 0) return 0;
   double d[O_MAXV];
   int any_in = 0, any_out = 0;
+  /* READING: the paper's clip-and-cap treats the void / point / edge / face /
+   * whole special cases internally (Section 2.1).  Here a vertex whose
+   * distance to the plane is below 1e-13 of the polytope's extent counts as
+   * on the plane, so rounding cannot split a face lying in the plane. */
+  double ext = 0.0;
+  for (int i = 1; i < P->nv; ++i)
+    for (int c = 0; c < 3; ++c) ext = fmax(ext, fabs(P->v[i][c] - P->v[0][c]));
+  double tol = 1e-13 * v_norm(n) * ext;
   for (int i = 0; i < P->nv; ++i) {
     d[i] = v_dot(n, P->v[i]) - s;
+    if (fabs(d[i]) <= tol) d[i] = 0.0;
     if (d[i] < 0.0) any_in = 1;
     if (d[i] > 0.0) any_out = 1;
   }
@@ -155,6 +167,24 @@ static int opoly_clip(opoly *P, const double *n, double s) {
     }
   }
 
+  /* faces made only of cap points lie in the plane: the cap replaces them */
+  {
+    int oncap[O_MAXV];
+    for (int i = 0; i < Q.nv; ++i) oncap[i] = 0;
+    for (int i = 0; i < ncap; ++i) oncap[cap[i]] = 1;
+    int kept = 0;
+    for (int f = 0; f < Q.nf; ++f) {
+      int all = 1;
+      for (int k = 0; k < Q.fn[f]; ++k) all &= oncap[Q.fv[f][k]];
+      if (all) continue;
+      if (kept != f) {
+        Q.fn[kept] = Q.fn[f];
+        memcpy(Q.fv[kept], Q.fv[f], sizeof(int) * Q.fn[f]);
+      }
+      ++kept;
+    }
+    Q.nf = kept;
+  }
   if (ncap >= 3) {
     /* cap centre and an in-plane basis (u, w) with u x w along n */
     double c[3] = {0, 0, 0};

@@ -1,0 +1,163 @@
+// clip.hpp -- phase volume of one tetrahedron of a flux polyhedron (step 5),
+// shared by the clip kernel and host builds of it.
+//
+// Tetrahedron k of the flux polyhedron of face f at its corrected lam, apex at
+// the face centre (local origin):
+//   k = 5 i      top    (c_q, q_i+1, q_i)
+//   k = 5 i + 1  side   (m_i, p_i+1, p_i)
+//   k = 5 i + 2         (m_i, p_i, q_i)
+//   k = 5 i + 3         (m_i, q_i, q_i+1)
+//   k = 5 i + 4         (m_i, q_i+1, p_i+1)
+// Returns its signed volume times the fraction lying in the phase region:
+// sum over stencil cells of |T ∩ C_c ∩ H_c| (eqs. 2.22-2.23), H = the PLIC
+// half-space in interface cells, all space in full cells, alpha-weighted in
+// vanishing-gradient cells, nothing in empty cells.
+#pragma once
+
+#include "geom.hpp"
+#include "vof_internal.h"
+
+namespace vof {
+
+VHD v3 xyz4(double4 a) { return mk3(a.x, a.y, a.z); }
+
+VHD double flux_tet_phase(const DMesh &m, const DState &s, const DParams &p, double dt,
+                          double sc, int f, int k, Poly &P, unsigned long long &ncap,
+                          unsigned long long &nleak) {
+    int b = m.foff[f], n = m.foff[f + 1] - b;
+    if (k >= 5 * n) return 0.0;
+    const double sw = -sc * dt * s.lam[f];
+    // face points and swept points, relative to the face centre
+    int i = k / 5, type = k - 5 * i;
+    int i1 = (i + 1 == n) ? 0 : i + 1;
+    v3 c = mk3(0, 0, 0), cq = mk3(0, 0, 0);
+    v3 pi = mk3(0, 0, 0), pj = mk3(0, 0, 0), qi = mk3(0, 0, 0), qj = mk3(0, 0, 0);
+    for (int j = 0; j < n; ++j) {
+      int q = m.fpts[b + j];
+      v3 x = xyz4(m.X[q]);
+      v3 dq = sw * xyz4(s.U[q]);
+      c = c + x;
+      cq = cq + dq;
+      if (j == i) { pi = x; qi = dq; }
+      if (j == i1) { pj = x; qj = dq; }
+    }
+    c = (1.0 / n) * c;
+    pi = pi - c; pj = pj - c;
+    qi = pi + qi; qj = pj + qj;
+    cq = (1.0 / n) * cq;  // mean sweep; the mean of the face points is the origin
+    v3 t1, t2, t3;
+    if (type == 0) { t1 = cq; t2 = qj; t3 = qi; }
+    else {
+      v3 mi = 0.25 * (pi + pj + qi + qj);
+      t1 = mi;
+      if (type == 1) { t2 = pj; t3 = pi; }
+      else if (type == 2) { t2 = pi; t3 = qi; }
+      else if (type == 3) { t2 = qi; t3 = qj; }
+      else { t2 = qj; t3 = pj; }
+    }
+    double det = det3(t1, t2, t3);
+    if (det == 0.0) return 0.0;
+    double sgn = det > 0.0 ? 1.0 : -1.0;
+    if (det < 0.0) { v3 tmp = t2; t2 = t3; t3 = tmp; det = -det; }
+    const v3 z = mk3(0, 0, 0);
+    v3 lo = mk3(dmin(dmin(0.0, t1.x), dmin(t2.x, t3.x)), dmin(dmin(0.0, t1.y), dmin(t2.y, t3.y)),
+                dmin(dmin(0.0, t1.z), dmin(t2.z, t3.z)));
+    v3 hi = mk3(dmax(dmax(0.0, t1.x), dmax(t2.x, t3.x)), dmax(dmax(0.0, t1.y), dmax(t2.y, t3.y)),
+                dmax(dmax(0.0, t1.z), dmax(t2.z, t3.z)));
+    lo = lo + c;
+    hi = hi + c;
+    double acc = 0.0, cover = 0.0;
+    for (int e = m.st_off[f]; e < m.st_off[f + 1]; ++e) {
+      int cell = m.st[e];
+      int cl = s.cls[cell];
+      if (cl == 0 && !p.check_stencil) continue;
+      double4 blo = m.bblo[cell], bhi = m.bbhi[cell];
+      if (hi.x <= blo.x || lo.x >= bhi.x || hi.y <= blo.y || lo.y >= bhi.y || hi.z <= blo.z ||
+          lo.z >= bhi.z)
+        continue;
+      // planes of the cell that cut the tet
+      int cuts[kMaxCellPlanes];
+      int ncut = 0;
+      bool outside = false;
+      double dsingle[4];
+      for (int q = m.cf_off[cell]; q < m.cf_off[cell + 1]; ++q) {
+        double4 pl = m.cpl[q];
+        v3 nn = xyz4(pl);
+        double off = pl.w - dot(nn, c);
+        double d0 = off, d1 = off - dot(nn, t1), d2 = off - dot(nn, t2), d3 = off - dot(nn, t3);
+        double dmx = dmax(dmax(d0, d1), dmax(d2, d3));
+        double dmn = dmin(dmin(d0, d1), dmin(d2, d3));
+        if (dmx <= 0.0) { outside = true; break; }
+        if (dmn < 0.0) {
+          if (ncut < kMaxCellPlanes) cuts[ncut] = q;
+          ++ncut;
+          dsingle[0] = d0; dsingle[1] = d1; dsingle[2] = d2; dsingle[3] = d3;
+        }
+      }
+      if (outside) continue;
+      double vcell, vph;
+      if (ncut == 0) {
+        vcell = det;
+      } else if (ncut == 1) {
+        vcell = det * tet_kept_fraction(dsingle);
+      } else {
+        vcell = -1.0;
+      }
+      if (cl == 1) {
+        double4 pl = s.plane[cell];
+        v3 nn = xyz4(pl);
+        double off = pl.w - dot(nn, c);
+        if (ncut == 0) {
+          double dd[4] = {off, off - dot(nn, t1), off - dot(nn, t2), off - dot(nn, t3)};
+          vph = det * tet_kept_fraction(dd);
+        } else {
+          P.init_tet(z, t1, t2, t3);
+          bool ok = true;
+          for (int q = 0; q < ncut && ok; ++q) {
+            double4 cp = m.cpl[cuts[q < kMaxCellPlanes ? q : 0]];
+            ok = P.clip(xyz4(cp), cp.w - dot(xyz4(cp), c));
+          }
+          if (ok && p.check_stencil && vcell < 0.0) {
+            // coverage before the plane cut
+            vcell = P.vol6();
+          }
+          ok = ok && P.clip(nn, off);
+          vph = ok ? P.vol6() : 0.0;
+          if (!ok || ncut > kMaxCellPlanes) ++ncap;
+        }
+      } else if (cl == 0) {
+        vph = 0.0;
+      } else {
+        if (vcell < 0.0) {
+          P.init_tet(z, t1, t2, t3);
+          bool ok = true;
+          for (int q = 0; q < ncut && ok; ++q) {
+            double4 cp = m.cpl[cuts[q < kMaxCellPlanes ? q : 0]];
+            ok = P.clip(xyz4(cp), cp.w - dot(xyz4(cp), c));
+          }
+          vcell = ok ? P.vol6() : 0.0;
+          if (!ok || ncut > kMaxCellPlanes) ++ncap;
+        }
+        vph = (cl == 2) ? vcell : s.alpha[cell] * vcell;
+      }
+      acc += vph;
+      if (p.check_stencil) {
+        if (vcell < 0.0) {
+          P.init_tet(z, t1, t2, t3);
+          bool ok = true;
+          for (int q = 0; q < ncut && ok; ++q) {
+            double4 cp = m.cpl[cuts[q < kMaxCellPlanes ? q : 0]];
+            ok = P.clip(xyz4(cp), cp.w - dot(xyz4(cp), c));
+          }
+          vcell = ok ? P.vol6() : 0.0;
+        }
+        cover += vcell;
+      }
+      if (ncut == 0) break;  // the tet lies inside this cell
+    }
+    if (p.check_stencil && fabs(cover - det) > 1e-12 * det) ++nleak;
+    if (p.check_stencil && fabs(cover - det) > 1e-12 * det) ++nleak;
+    return sgn * acc / 6.0;
+}
+
+}  // namespace vof

@@ -418,3 +418,31 @@ def test_trivial_faces_full_stencil(oracle_mod):
     ph0 = o.phase_flux(0.1, 1.0, lam, np.zeros(m.n_cells))
     assert (ph0["vphase"] == 0).all()
     del rec
+
+
+def test_clip_face_in_plane_not_doubled(oracle_mod):
+    """A plane containing a face of the polytope (repeated, or with rounding
+    putting a vertex a hair outside) removes nothing: exact rational check."""
+    rng = np.random.default_rng(13)
+    for _ in range(200):
+        T = rng.integers(0, 5, (4, 3)) / 4.0
+        d = np.linalg.det(T[1:] - T[0])
+        if abs(d) < 1e-12:
+            continue
+        if d < 0:
+            T[[2, 3]] = T[[3, 2]]
+        pl = [int(x) for x in rng.integers(-2, 3, 3)] + [float(rng.integers(0, 5) / 4.0)]
+        if not any(pl[:3]):
+            continue
+        exact = float(X.tet_halfspaces_volume(T, [pl]))
+        assert abs(oracle_mod.clip_volume(T, TET_F, [pl, pl]) - exact) <= 1e-15
+    # the plane of face (1, 2, 3) of a tet, with one vertex moved 1e-18 outward
+    T = np.array([[0.1, 0.2, 0.1], [1.0, 0.1, 0.2], [0.2, 1.1, 0.0], [0.3, 0.2, 0.9]])
+    n = np.cross(T[2] - T[1], T[3] - T[1])
+    s = n @ T[1]
+    T2 = T.copy()
+    T2[2] += 1e-18 * n / np.linalg.norm(n)
+    vol = abs(np.linalg.det(T[1:] - T[0])) / 6
+    for P in (T, T2):
+        assert oracle_mod.clip_volume(P, TET_F, [list(n) + [s]]) == pytest.approx(vol, rel=1e-14)
+        assert oracle_mod.clip_volume(P, TET_F, [list(n) + [s]] * 3) == pytest.approx(vol, rel=1e-14)
