@@ -21,9 +21,14 @@ namespace vof {
 
 VHD v3 xyz4(double4 a) { return mk3(a.x, a.y, a.z); }
 
+// With check_stencil set, *deficit receives the signed volume of the tet that
+// no stencil cell covers (summed over a face it must vanish unless the flux
+// polyhedron leaves its stencil) and *gross its unsigned volume.
 VHD double flux_tet_phase(const DMesh &m, const DState &s, const DParams &p, double dt,
                           double sc, int f, int k, Poly &P, unsigned long long &ncap,
-                          unsigned long long &nleak) {
+                          double *deficit, double *gross) {
+    *deficit = 0.0;
+    *gross = 0.0;
     int b = m.foff[f], n = m.foff[f + 1] - b;
     if (k >= 5 * n) return 0.0;
     const double sw = -sc * dt * s.lam[f];
@@ -156,7 +161,10 @@ VHD double flux_tet_phase(const DMesh &m, const DState &s, const DParams &p, dou
       if (ncut == 0) break;  // the tet lies inside this cell
     }
     if (p.check_stencil && fabs(cover - det) > 1e-12 * det) ++nleak;
-    if (p.check_stencil && fabs(cover - det) > 1e-12 * det) ++nleak;
+    if (p.check_stencil) {
+      *deficit = sgn * (det - cover) / 6.0;
+      *gross = det / 6.0;
+    }
     return sgn * acc / 6.0;
 }
 

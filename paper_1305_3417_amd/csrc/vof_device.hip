@@ -501,21 +501,27 @@ __global__ __launch_bounds__(kClipBlock) void k_clip(DMesh m, DState s, DParams 
 
   const double dt = s.dt[step], sc = s.sc[step];
   const int64_t total = (int64_t)s.work[kWGeometric] * m.tpf;
-  unsigned long long ncap = 0, nleak = 0;
+  unsigned long long ncap = 0;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + tid; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
     int slot = (int)(idx / m.tpf);
     int k = (int)(idx - (int64_t)slot * m.tpf);
-    s.tetvol[idx] = flux_tet_phase(m, s, p, dt, sc, s.gfaces[slot], k, P, ncap, nleak);
+    double deficit, gross;
+    s.tetvol[idx] = flux_tet_phase(m, s, p, dt, sc, s.gfaces[slot], k, P, ncap, &deficit, &gross);
+    if (p.check_stencil) {
+      s.tetdef[idx] = deficit;
+      s.tetgross[idx] = gross;
+    }
   }
   wave_count(&s.cnt[kCntCapacity], ncap);
-  wave_count(&s.cnt[kCntLeaks], nleak);
   if (__ballot(ncap != 0) && lane_id() == 0) flag(s.flags, kFlagCapacity);
-  if (__ballot(nleak != 0) && lane_id() == 0) flag(s.flags, kFlagLeak);
 }
 
-__global__ __launch_bounds__(kBlock) void k_face_sum(DMesh m, DState s) {
+// Sum of the tets of each geometric face.  With check_stencil: the uncovered
+// signed volume of the face must vanish to 1e-12 of its gross tet volume.
+__global__ __launch_bounds__(kBlock) void k_face_sum(DMesh m, DState s, DParams p) {
   const int count = s.work[kWGeometric];
+  unsigned long long nleak = 0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
     const double *tv = s.tetvol + (int64_t)i * m.tpf;
     double acc = 0.0;
@@ -523,7 +529,17 @@ __global__ __launch_bounds__(kBlock) void k_face_sum(DMesh m, DState s) {
     int f = s.gfaces[i];
     if (s.fstatus[f]) acc *= s.vscale[f];
     s.vphase[f] = acc;
+    if (p.check_stencil) {
+      double dsum = 0.0, gsum = 0.0;
+      for (int k = 0; k < m.tpf; ++k) {
+        dsum += s.tetdef[(int64_t)i * m.tpf + k];
+        gsum += s.tetgross[(int64_t)i * m.tpf + k];
+      }
+      if (fabs(dsum) > 1e-12 * gsum) ++nleak;
+    }
   }
+  wave_count(&s.cnt[kCntLeaks], nleak);
+  if (__ballot(nleak != 0) && lane_id() == 0) flag(s.flags, kFlagLeak);
 }
 
 // alpha_c^{n+1} = alpha_c^n - (1/V_c) sum_f sgn_cf V_{f,alpha}, every cell
@@ -662,7 +678,7 @@ void launch_step(const DMesh &m, const DState &s, const DParams &p, int step, hi
   else
     TIMED(prof, kKFlux, (k_flux<kMaxFacePoints><<<gf, kBlock, 0, st>>>(m, s, p, step)));
   TIMED(prof, kKClip, (k_clip<kMaxFacePoints><<<4096, kClipBlock, 0, st>>>(m, s, p, step)));
-  TIMED(prof, kKFaceSum, (k_face_sum<<<1024, kBlock, 0, st>>>(m, s)));
+  TIMED(prof, kKFaceSum, (k_face_sum<<<1024, kBlock, 0, st>>>(m, s, p)));
   TIMED(prof, kKUpdate, (k_update<<<grid_for(m.nc, kBlock), kBlock, 0, st>>>(m, s)));
   TIMED(prof, kKLedger, (k_ledger<<<1, kBlock, 0, st>>>(m, s)));
 }

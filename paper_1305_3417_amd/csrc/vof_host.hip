@@ -466,6 +466,14 @@ vof_status vof_set_params(vof_mesh *m, const vof_params *p) {
   if (!(p->position_tol > 0.0) || p->position_max_iter < 1)
     return fail(VOF_EINVAL, "bad positioning tolerance or iteration limit");
   if (!(p->gradient_zero >= 0.0)) return fail(VOF_EINVAL, "gradient_zero must be >= 0");
+  if (p->check_stencil && !m->ds.tetdef) {
+    // the stencil check keeps two more doubles per flux tet
+    vof_status rc = set_device(m->ctx);
+    if (rc) return rc;
+    HIP_OR_FAIL(hipStreamSynchronize(m->ctx->stream));
+    if ((rc = m->alloc(&m->ds.tetdef, m->dm.nf * (int64_t)m->dm.tpf))) return rc;
+    if ((rc = m->alloc(&m->ds.tetgross, m->dm.nf * (int64_t)m->dm.tpf))) return rc;
+  }
   to_dparams(*p, m->dp);
   return VOF_OK;
 }

@@ -94,6 +94,8 @@ struct DState {
   int32_t *icells;      // interface cell list
   int32_t *gfaces;      // geometric face list
   double *tetvol;       // per geometric face slot x tet
+  double *tetdef;       // stencil check only: uncovered signed tet volume
+  double *tetgross;     // stencil check only: unsigned tet volume
   int32_t *work;        // per-step counters (kWNum)
   unsigned long long *cnt;  // kCntNum
   uint32_t *flags;      // latched status bits
