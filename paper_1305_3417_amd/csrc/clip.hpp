@@ -160,7 +160,6 @@ VHD double flux_tet_phase(const DMesh &m, const DState &s, const DParams &p, dou
       }
       if (ncut == 0) break;  // the tet lies inside this cell
     }
-    if (p.check_stencil && fabs(cover - det) > 1e-12 * det) ++nleak;
     if (p.check_stencil) {
       *deficit = sgn * (det - cover) / 6.0;
       *gross = det / 6.0;
