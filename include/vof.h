@@ -161,9 +161,10 @@ vof_status vof_advect(vof_mesh *mesh, int32_t n_steps, const double *dt, const d
  * F_f), VOF_FACE_ITERS (uint8, correction iterations), VOF_FACE_KIND (uint8:
  * 0 no flux, 1 trivially empty stencil, 2 trivially full stencil,
  * 3 geometric), VOF_FACE_STATUS (uint8: 0 ok, 1 correction target beyond the
- * extremum of the swept volume on its monotone branch: lambda is set to the
- * extremum and the face's phase volume is rescaled by F dt / V_f(lambda), so
- * the face still carries exactly F dt of total volume). */
+ * extremum of the swept volume on its monotone branch: lambda is set to that
+ * extremum or to the plain sweep (+-1 on the same side), whichever is nearer
+ * to 0, and the face's phase volume is rescaled by F dt / V_f(lambda), so the
+ * face still carries exactly F dt of total volume). */
 #define VOF_FACE_LAMBDA 0
 #define VOF_FACE_VPHASE 1
 #define VOF_FACE_ITERS 2

@@ -590,8 +590,9 @@ double orc_flux_volume(const omesh *M, int64_t f, double dt, double s, double la
  * bracket is replaced by bisection.  Converged when |V - F dt| <= 1e-14 |F dt|
  * or the bracket is exhausted.
  * If F dt lies beyond the extremum of V at the branch end, lambda is set to
- * that extremum and status 1 is returned (the phase volume of such a face is
- * rescaled to F dt, see phase_flux_face). */
+ * that extremum or to the plain sweep (+-1 on the same side), whichever is
+ * nearer to 0, and status 1 is returned; the phase volume of such a face is
+ * rescaled to F dt (see phase_flux_face). */
 static void branch_cubic(const omesh *M, int64_t f, double dt, double s, double *a1,
                          double *a2, double *a3) {
   double V1 = orc_flux_volume(M, f, dt, s, 1.0);
@@ -638,7 +639,7 @@ static int correct_face(const omesh *M, int64_t f, double dt, double s, double *
   double end = isfinite(te) ? fmin(te, 32.0) : 32.0;
   double vend = orc_flux_volume(M, f, dt, s, dir * end);
   if ((vend - target) * (target > 0 ? 1.0 : -1.0) < 0.0) {
-    *lam_out = dir * end;
+    *lam_out = dir * fmin(end, 1.0);
     return 1;
   }
   /* bracket [lo, hi] around the root, g(lo) and g(hi) of opposite sign */
@@ -856,8 +857,9 @@ static int tet_cell_volumes(const omesh *M, const double *a, const double *b, co
  *       3 geometric.
  * READING: outside the domain counts as empty; for a boundary face the
  * full-stencil shortcut is not taken (its polyhedron may lie outside).
- * Returns the stencil leak |sum_c sum_k sgn_k |T_k ∩ C_c| - V_f| when
- * check_leak is set (geometric faces only). */
+ * Returns the stencil leak |sum_c sum_k sgn_k |T_k ∩ C_c| - V_f| relative to
+ * max(sum_k |T_k|, V_owner) when check_leak is set (geometric faces only).
+ * Volume outside the domain counts as leaked. */
 static double phase_flux_face(const omesh *M, int64_t f, double dt, double s, double lam,
                               int status, const double *alpha, int check_leak, double *vphase,
                               int *kind, int *err) {
@@ -875,11 +877,12 @@ static double phase_flux_face(const omesh *M, int64_t f, double dt, double s, do
   *kind = 3;
   oflux X;
   flux_polyhedron(M, f, dt, s, lam, &X);
-  double total = 0.0, covered = 0.0, vf = 0.0;
+  double total = 0.0, covered = 0.0, vf = 0.0, gross = 0.0;
   for (int t = 0; t < X.nt; ++t) {
     double det = tet6(X.apex, X.t[t][0], X.t[t][1], X.t[t][2]);
     if (det == 0.0) continue;
     vf += det / 6.0;
+    gross += fabs(det) / 6.0;
     double sgn = det > 0 ? 1.0 : -1.0;
     const double *a = X.apex, *b = X.t[t][0], *c = det > 0 ? X.t[t][1] : X.t[t][2],
                  *d = det > 0 ? X.t[t][2] : X.t[t][1];
@@ -897,11 +900,15 @@ static double phase_flux_face(const omesh *M, int64_t f, double dt, double s, do
   /* flagged correction: the phase fraction of the swept polyhedron times F dt */
   if (status == 1 && vf != 0.0) total *= (F * dt) / vf;
   *vphase = total;
-  return check_leak ? fabs(covered - vf) : 0.0;
+  /* uncovered signed volume relative to the gross tet volume of the face or
+   * the owner cell's volume, whichever is larger */
+  double ref = fmax(gross, M->V[M->own[f]]);
+  return check_leak ? fabs(covered - vf) / ref : 0.0;
 }
 
 /* V_{f,alpha} for every face.  Outputs may be NULL.  Returns the number of
- * geometric faces; *max_leak receives the largest relative stencil leak. */
+ * geometric faces; *max_leak receives the largest stencil leak relative to
+ * the gross tet volume of its face. */
 int64_t orc_phase_flux(const omesh *M, double dt, double s, const double *lam,
                        const int8_t *status, const double *alpha, int check_leak,
                        double *vphase, int8_t *kind, double *max_leak, int64_t *nerr) {
@@ -917,8 +924,7 @@ int64_t orc_phase_flux(const omesh *M, double dt, double s, const double *lam,
     if (kind) kind[f] = (int8_t)kd;
     if (kd == 3) {
       ++ngeo;
-      double ref = fabs(s * M->F0[f] * dt);
-      if (ref > 0 && l / ref > leak) leak = l / ref;
+      if (l > leak) leak = l;
     }
     ne += er;
   }

@@ -344,7 +344,8 @@ __global__ __launch_bounds__(kBlock) void k_plane(DMesh m, DState s, DParams p) 
 // Correction (Section 2.3): V(lam) = F dt on the branch of V through 0 on
 // which V' keeps its sign (bounded by the real roots of V'), by Newton from
 // lam = 1 safeguarded by bisection.  status 1 when the target lies beyond the
-// extremum of V at the branch end (lam is then that end, at most 64).
+// extremum of V at the branch end: lam is then that end or the plain sweep
+// (+-1 on the same side), whichever is nearer to 0.
 __device__ __forceinline__ void correct(double c1, double c2, double c3, double T, double rtol,
                                         int maxit, double &lam, int &iters, int &status) {
   iters = 0;
@@ -368,7 +369,7 @@ __device__ __forceinline__ void correct(double c1, double c2, double c3, double 
   }
   double end = ((T > 0.0) == (c1 > 0.0)) ? hi : lo;
   double gend = ((c3 * end + c2) * end + c1) * end - T;
-  if (!(gend * T >= 0.0)) { lam = end; status = 1; return; }
+  if (!(gend * T >= 0.0)) { lam = copysign(dmin(fabs(end), 1.0), end); status = 1; return; }
   double a = dmin(0.0, end), b = dmax(0.0, end);
   double ga = (a == 0.0) ? -T : gend;
   double x = 1.0;
@@ -444,8 +445,8 @@ __global__ __launch_bounds__(kBlock) void k_flux(DMesh m, DState s, DParams p, i
       double c2 = (t2 - dot(db, B)) / 6.0;
       double c3 = -dot(db, Cc) / 6.0;
       correct(c1, c2, c3, T, p.corr_rtol, p.corr_max_iter, lam, it, stat);
-      // A target beyond the extremum of V on the branch: lam sits at the
-      // extremum and the phase volume is rescaled to F dt (scalar correction).
+      // A target beyond the extremum of V on the branch: the phase volume of
+      // the polyhedron at the clamped lam is rescaled to F dt (scalar correction).
       if (stat) s.vscale[f] = T / (((c3 * lam + c2) * lam + c1) * lam);
       nflux = 1;
       nit = (unsigned long long)it;
@@ -518,7 +519,8 @@ __global__ __launch_bounds__(kClipBlock) void k_clip(DMesh m, DState s, DParams 
 }
 
 // Sum of the tets of each geometric face.  With check_stencil: the uncovered
-// signed volume of the face must vanish to 1e-12 of its gross tet volume.
+// signed volume of the face must vanish to 1e-12 of max(gross tet volume,
+// owner cell volume).
 __global__ __launch_bounds__(kBlock) void k_face_sum(DMesh m, DState s, DParams p) {
   const int count = s.work[kWGeometric];
   unsigned long long nleak = 0;
@@ -535,7 +537,7 @@ __global__ __launch_bounds__(kBlock) void k_face_sum(DMesh m, DState s, DParams 
         dsum += s.tetdef[(int64_t)i * m.tpf + k];
         gsum += s.tetgross[(int64_t)i * m.tpf + k];
       }
-      if (fabs(dsum) > 1e-12 * gsum) ++nleak;
+      if (fabs(dsum) > 1e-12 * dmax(gsum, m.V[m.own[f]])) ++nleak;
     }
   }
   wave_count(&s.cnt[kCntLeaks], nleak);

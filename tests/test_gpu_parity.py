@@ -134,6 +134,17 @@ def test_deform3d_small_steps(vof, ctx, oracle_mod):
 def test_rotate_tets_small(vof, ctx, oracle_mod):
     w = W.rotate_tets(10, steps=6, sample=8)
     _compare_step(vof, ctx, oracle_mod, w, label="tets-10")
+    g = gpu_run(vof, ctx, w)
+    o, a, st, lam, vp = oracle_run(oracle_mod, w)
+    assert np.abs(g["alpha"] - a).max() < 1e-10
+    g["mesh"].close()
+
+
+def test_rotate_tets_stencil_complete(vof, ctx, oracle_mod):
+    """A slotted sphere whose orbit stays four cells from the walls: every flux
+    polyhedron of a geometric face lies inside its stencil (the point-cells
+    of its points), on both sides, over several steps."""
+    w = W.rotate_tets(20, steps=4, sample=6, centre=(0.5, 0.65, 0.5))
     g = gpu_run(vof, ctx, w, params={"check_stencil": 1})
     o, a, st, lam, vp = oracle_run(oracle_mod, w, check_leak=True)
     assert st["max_leak"] < 1e-12

@@ -83,7 +83,7 @@ def slotted_sphere_inside(x, centre=(0.5, 0.75, 0.5), radius=0.15, slot_half=0.0
 
 
 def rotate_tets(n: int = 80, steps: int | None = None, seed: int = 1305,
-                sample: int = 12) -> Workload:
+                sample: int = 12, centre=(0.5, 0.75, 0.5), radius: float = 0.15) -> Workload:
     """Slotted sphere rotating about z through (0.5, 0.5) on jittered Kuhn tets.
 
     omega = 2 pi; max |U0| at the domain corners is omega*sqrt(0.5); the shortest
@@ -91,7 +91,9 @@ def rotate_tets(n: int = 80, steps: int | None = None, seed: int = 1305,
     The default step count is one revolution.
     """
     m = kuhn_tet_mesh(n, 0.2, seed)
-    a0 = fields.tet_fraction_sampled(m, slotted_sphere_inside, sample)
+    c = np.asarray(centre, dtype=np.float64)
+    a0 = fields.tet_fraction_sampled(
+        m, lambda x: slotted_sphere_inside(x, c, radius, slot_top=c[1] + 0.1), sample)
     omega = 2.0 * np.pi
     origin = np.array([0.5, 0.5, 0.5])
     Uc = fields.rotation_velocity(m.cell_centroids(), omega, origin)
@@ -99,7 +101,8 @@ def rotate_tets(n: int = 80, steps: int | None = None, seed: int = 1305,
     N = 9 * n if steps is None else steps
     dt = 1.0 / (9 * n)
     return Workload("rotate_tets", m, a0, Uc, F0, np.full(N, dt), np.ones(N),
-                    meta={"n": n, "seed": seed, "omega": omega})
+                    meta={"n": n, "seed": seed, "omega": omega, "centre": list(centre),
+                          "radius": radius})
 
 
 def translate_slab(n: int = 16, nz: int = 1, a: float = 0.3, b: float = 0.55,
