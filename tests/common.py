@@ -55,9 +55,12 @@ def swept_scale(w, S, Up, scale_dt):
 
 
 def vphase_tolerance(w, V, scale_dt, S=None, Up=None):
-    """Per-face bound 1e-12 * max(|F| dt, gross swept volume, 1e-6 V_owner)."""
+    """Per-face bound 1e-12 * max(|F| dt, gross swept volume, 1e-2 V_owner).
+
+    The absolute floor 1e-14 V_owner is the FP64 rounding of the polyhedron's
+    tetrahedra, whose edges are ~h however small the sweep (about 20 eps h^3)."""
     F = np.abs(w.F0) * abs(scale_dt)
-    ref = np.maximum(F, 1e-6 * V[w.mesh.owner])
+    ref = np.maximum(F, 1e-2 * V[w.mesh.owner])
     if S is not None:
         ref = np.maximum(ref, swept_scale(w, S, Up, scale_dt))
     return 1e-12 * ref

@@ -6,9 +6,11 @@ of face f: the flux polyhedron volume is a signed sum of terms of that size,
 so any FP64 evaluation of it is accurate to a few eps * G_f, however small
 the net flux F_f dt.
   lambda_f            the oracle's own volume at lam_gpu within
-                      1e-12 max(|F_f dt|, G_f) of F_f dt (lambda itself is
+                      1e-12 max(|F_f dt|, G_f, 1e-2 V_owner) of F_f dt (lambda itself is
                       ill-conditioned where V' is small; relative 1e-8 sanity)
-  V_{f,alpha}         1e-12 * max(|F_f| dt, G_f, 1e-6 V_owner) per face
+  V_{f,alpha}         1e-12 * max(|F_f| dt, G_f, 1e-2 V_owner) per face; the floor
+                      1e-14 V_owner is the FP64 rounding of tetrahedra whose
+                      edges are ~h (about 20 eps h^3) when the flux is tiny
   plane normal        1e-12 (components; same classes required)
   alpha after N steps 1e-10 absolute
   conservation        sum V alpha + ledger within 1e-12 relative
@@ -67,7 +69,7 @@ def _compare_step(vof, ctx, oracle_mod, w, alpha=None, label=""):
     for f in fl[:: max(1, fl.size // 400)]:
         if g["status"][f] == 0:
             res = abs(o.flux_volume(f, w.dt[0], w.scale[0], g["lam"][f]) - w.F0[f] * sdt)
-            assert res <= 1e-12 * max(abs(w.F0[f] * sdt), G[f])
+            assert res <= 1e-12 * max(abs(w.F0[f] * sdt), G[f], 1e-2 * V[w.mesh.owner[f]])
     assert np.array_equal(g["kind"], r["kind"].astype(np.uint8))
     tol = vphase_tolerance(w, V, sdt, S, Up)
     err = np.abs(g["vphase"] - r["vphase"])
@@ -201,7 +203,7 @@ def test_deform3d_full_size_sampled(vof, ctx, oracle_mod):
     # ill-conditioned where V' is small; the volume is what the update uses)
     for f in faces[fl][::3]:
         res = abs(o.flux_volume(f, w.dt[0], w.scale[0], g["lam"][f]) - w.F0[f] * sdt)
-        assert res <= 1e-12 * max(abs(w.F0[f] * sdt), G[f])
+        assert res <= 1e-12 * max(abs(w.F0[f] * sdt), G[f], 1e-2 * V[m.owner[f]])
     tol = vphase_tolerance(w, V, sdt, S, Up)[faces]
     assert (np.abs(g["vphase"][faces] - r["vphase"]) <= tol).all()
     # alpha of the sampled cells from the oracle's face volumes
