@@ -26,7 +26,7 @@ VHD v3 xyz4(double4 a) { return mk3(a.x, a.y, a.z); }
 // polyhedron leaves its stencil) and *gross its unsigned volume.
 VHD double flux_tet_phase(const DMesh &m, const DState &s, const DParams &p, double dt,
                           double sc, int f, int k, Poly &P, unsigned long long &ncap,
-                          double *deficit, double *gross) {
+                          unsigned long long &npairs, double *deficit, double *gross) {
     *deficit = 0.0;
     *gross = 0.0;
     int b = m.foff[f], n = m.foff[f + 1] - b;
@@ -100,6 +100,7 @@ VHD double flux_tet_phase(const DMesh &m, const DState &s, const DParams &p, dou
         }
       }
       if (outside) continue;
+      ++npairs;  // a (tet, cell) pair with overlapping interiors
       double vcell, vph;
       if (ncut == 0) {
         vcell = det;

@@ -502,19 +502,21 @@ __global__ __launch_bounds__(kClipBlock) void k_clip(DMesh m, DState s, DParams 
 
   const double dt = s.dt[step], sc = s.sc[step];
   const int64_t total = (int64_t)s.work[kWGeometric] * m.tpf;
-  unsigned long long ncap = 0;
+  unsigned long long ncap = 0, npairs = 0;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + tid; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
     int slot = (int)(idx / m.tpf);
     int k = (int)(idx - (int64_t)slot * m.tpf);
     double deficit, gross;
-    s.tetvol[idx] = flux_tet_phase(m, s, p, dt, sc, s.gfaces[slot], k, P, ncap, &deficit, &gross);
+    s.tetvol[idx] = flux_tet_phase(m, s, p, dt, sc, s.gfaces[slot], k, P, ncap, npairs, &deficit,
+                                   &gross);
     if (p.check_stencil) {
       s.tetdef[idx] = deficit;
       s.tetgross[idx] = gross;
     }
   }
   wave_count(&s.cnt[kCntCapacity], ncap);
+  wave_count(&s.cnt[kCntPairs], npairs);
   if (__ballot(ncap != 0) && lane_id() == 0) flag(s.flags, kFlagCapacity);
 }
 

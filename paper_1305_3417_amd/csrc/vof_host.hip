@@ -661,6 +661,7 @@ vof_status vof_get_stats(vof_mesh *m, vof_stats *out) {
   out->capacity_overflows = (int64_t)c[kCntCapacity];
   out->stencil_leaks = (int64_t)c[kCntLeaks];
   out->correction_iters = (int64_t)c[kCntIters];
+  out->clip_pairs = (int64_t)c[kCntPairs];
   out->ledger = led;
   out->mass = st4[0];
   out->alpha_min = st4[1];

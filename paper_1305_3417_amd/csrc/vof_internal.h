@@ -36,6 +36,7 @@ enum Counter : int {
   kCntCapacity,
   kCntLeaks,
   kCntIters,
+  kCntPairs,
   kCntNum
 };
 
