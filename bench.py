@@ -206,6 +206,7 @@ def main():
                    "parallelism": "single GPU"},
         "cell_updates_per_s": w.mesh.n_cells * K / elapsed,
         "geometric_faces_per_step": geo / K,
+        "general_clip_tets_per_step": (st1["general_tets"] - st0["general_tets"]) / K,
         "face_fluxes_per_step": face_fluxes / K,
         "kernels_us": {k: v[0] / max(v[1], 1) * 1e3 for k, v in prof.items()},
         "roofline": roof,

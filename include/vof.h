@@ -193,6 +193,7 @@ typedef struct {
   int64_t stencil_leaks;      /* flux tets leaving their stencil (if checked) */
   int64_t correction_iters;   /* sum of correction iterations               */
   int64_t clip_pairs;         /* (flux tet, stencil cell) pairs that overlap */
+  int64_t general_tets;       /* flux tets clipped by the general polytope path */
   double ledger;              /* sum of V_{f,alpha} over boundary faces      */
   double mass;                /* sum_c V_c alpha_c (compensated)            */
   double alpha_min, alpha_max;

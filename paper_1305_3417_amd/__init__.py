@@ -81,6 +81,7 @@ class vof_stats(C.Structure):
                 ("fallback_cells", C.c_int64), ("unreached_faces", C.c_int64),
                 ("capacity_overflows", C.c_int64), ("stencil_leaks", C.c_int64),
                 ("correction_iters", C.c_int64), ("clip_pairs", C.c_int64),
+                ("general_tets", C.c_int64),
                 ("ledger", C.c_double), ("mass", C.c_double),
                 ("alpha_min", C.c_double), ("alpha_max", C.c_double)]
 

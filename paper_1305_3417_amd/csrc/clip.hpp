@@ -24,46 +24,119 @@ VHD v3 xyz4(double4 a) { return mk3(a.x, a.y, a.z); }
 // With check_stencil set, *deficit receives the signed volume of the tet that
 // no stencil cell covers (summed over a face it must vanish unless the flux
 // polyhedron leaves its stencil) and *gross its unsigned volume.
+// Vertices of tetrahedron k of face f's flux polyhedron at its corrected lam,
+// relative to the face centre c (the apex is the origin), positively ordered;
+// sgn is the orientation of the tet in the signed decomposition.  Returns
+// false for k beyond 5n or a flat tet.
+VHD bool flux_tet(const DMesh &m, const DState &s, double dt, double sc, int f, int k, v3 &c,
+                  v3 &t1, v3 &t2, v3 &t3, double &det, double &sgn) {
+  int b = m.foff[f], n = m.foff[f + 1] - b;
+  if (k >= 5 * n) return false;
+  const double sw = -sc * dt * s.lam[f];
+  int i = k / 5, type = k - 5 * i;
+  int i1 = (i + 1 == n) ? 0 : i + 1;
+  c = mk3(0, 0, 0);
+  v3 cq = mk3(0, 0, 0);
+  v3 pi = mk3(0, 0, 0), pj = mk3(0, 0, 0), qi = mk3(0, 0, 0), qj = mk3(0, 0, 0);
+  for (int j = 0; j < n; ++j) {
+    int q = m.fpts[b + j];
+    v3 x = xyz4(m.X[q]);
+    v3 dq = sw * xyz4(s.U[q]);
+    c = c + x;
+    cq = cq + dq;
+    if (j == i) { pi = x; qi = dq; }
+    if (j == i1) { pj = x; qj = dq; }
+  }
+  c = (1.0 / n) * c;
+  pi = pi - c; pj = pj - c;
+  qi = pi + qi; qj = pj + qj;
+  cq = (1.0 / n) * cq;  // mean sweep; the mean of the face points is the origin
+  if (type == 0) { t1 = cq; t2 = qj; t3 = qi; }
+  else {
+    v3 mi = 0.25 * (pi + pj + qi + qj);
+    t1 = mi;
+    if (type == 1) { t2 = pj; t3 = pi; }
+    else if (type == 2) { t2 = pi; t3 = qi; }
+    else if (type == 3) { t2 = qi; t3 = qj; }
+    else { t2 = qj; t3 = pj; }
+  }
+  det = det3(t1, t2, t3);
+  if (det == 0.0) return false;
+  sgn = det > 0.0 ? 1.0 : -1.0;
+  if (det < 0.0) { v3 tmp = t2; t2 = t3; t3 = tmp; det = -det; }
+  return true;
+}
+
+// Register-only phase volume of flux tet k of face f: every overlapping
+// stencil cell contributes |T ∩ C ∩ H| through at most three planes (the
+// cell planes that cut the tet, and the PLIC plane of an interface cell).
+// Returns false ("deferred") when a pair needs more planes; the tet is then
+// left to flux_tet_phase.
+VHD bool flux_tet_phase_fast(const DMesh &m, const DState &s, double dt, double sc, int f,
+                             int k, double &vol, unsigned long long &npairs) {
+  vol = 0.0;
+  v3 c, t1, t2, t3;
+  double det, sgn;
+  if (!flux_tet(m, s, dt, sc, f, k, c, t1, t2, t3, det, sgn)) return true;
+  const v3 T[4] = {mk3(0, 0, 0), t1, t2, t3};
+  v3 lo = mk3(dmin(dmin(0.0, t1.x), dmin(t2.x, t3.x)), dmin(dmin(0.0, t1.y), dmin(t2.y, t3.y)),
+              dmin(dmin(0.0, t1.z), dmin(t2.z, t3.z))) + c;
+  v3 hi = mk3(dmax(dmax(0.0, t1.x), dmax(t2.x, t3.x)), dmax(dmax(0.0, t1.y), dmax(t2.y, t3.y)),
+              dmax(dmax(0.0, t1.z), dmax(t2.z, t3.z))) + c;
+  double acc = 0.0;
+  unsigned long long np = 0;
+  for (int e = m.st_off[f]; e < m.st_off[f + 1]; ++e) {
+    int cell = m.st[e];
+    int cl = s.cls[cell];
+    if (cl == 0) continue;
+    double4 blo = m.bblo[cell], bhi = m.bbhi[cell];
+    if (hi.x <= blo.x || lo.x >= bhi.x || hi.y <= blo.y || lo.y >= bhi.y || hi.z <= blo.z ||
+        lo.z >= bhi.z)
+      continue;
+    double4 pl[3];
+    const int room = (cl == 1) ? 2 : 3;
+    int ncut = 0;
+    bool outside = false, over = false;
+    for (int q = m.cf_off[cell]; q < m.cf_off[cell + 1]; ++q) {
+      double4 cp = m.cpl[q];
+      v3 nn = xyz4(cp);
+      double off = cp.w - dot(nn, c);
+      double d1 = off - dot(nn, t1), d2 = off - dot(nn, t2), d3 = off - dot(nn, t3);
+      double dmx = dmax(dmax(off, d1), dmax(d2, d3));
+      double dmn = dmin(dmin(off, d1), dmin(d2, d3));
+      if (dmx <= 0.0) { outside = true; break; }
+      if (dmn < 0.0) {
+        if (ncut < room) pl[ncut] = make_double4(nn.x, nn.y, nn.z, off);
+        else over = true;
+        ++ncut;
+      }
+    }
+    if (outside) continue;
+    if (over) return false;
+    ++np;
+    int npl = ncut;
+    if (cl == 1) {
+      double4 pp = s.plane[cell];
+      v3 nn = xyz4(pp);
+      pl[npl++] = make_double4(nn.x, nn.y, nn.z, pp.w - dot(nn, c));
+    }
+    double v = vol6_planes(T, det, pl, npl);
+    acc += (cl == 3) ? s.alpha[cell] * v : v;
+    if (ncut == 0) break;  // the tet lies inside this cell
+  }
+  npairs += np;
+  vol = sgn * acc / 6.0;
+  return true;
+}
+
 VHD double flux_tet_phase(const DMesh &m, const DState &s, const DParams &p, double dt,
                           double sc, int f, int k, Poly &P, unsigned long long &ncap,
                           unsigned long long &npairs, double *deficit, double *gross) {
     *deficit = 0.0;
     *gross = 0.0;
-    int b = m.foff[f], n = m.foff[f + 1] - b;
-    if (k >= 5 * n) return 0.0;
-    const double sw = -sc * dt * s.lam[f];
-    // face points and swept points, relative to the face centre
-    int i = k / 5, type = k - 5 * i;
-    int i1 = (i + 1 == n) ? 0 : i + 1;
-    v3 c = mk3(0, 0, 0), cq = mk3(0, 0, 0);
-    v3 pi = mk3(0, 0, 0), pj = mk3(0, 0, 0), qi = mk3(0, 0, 0), qj = mk3(0, 0, 0);
-    for (int j = 0; j < n; ++j) {
-      int q = m.fpts[b + j];
-      v3 x = xyz4(m.X[q]);
-      v3 dq = sw * xyz4(s.U[q]);
-      c = c + x;
-      cq = cq + dq;
-      if (j == i) { pi = x; qi = dq; }
-      if (j == i1) { pj = x; qj = dq; }
-    }
-    c = (1.0 / n) * c;
-    pi = pi - c; pj = pj - c;
-    qi = pi + qi; qj = pj + qj;
-    cq = (1.0 / n) * cq;  // mean sweep; the mean of the face points is the origin
-    v3 t1, t2, t3;
-    if (type == 0) { t1 = cq; t2 = qj; t3 = qi; }
-    else {
-      v3 mi = 0.25 * (pi + pj + qi + qj);
-      t1 = mi;
-      if (type == 1) { t2 = pj; t3 = pi; }
-      else if (type == 2) { t2 = pi; t3 = qi; }
-      else if (type == 3) { t2 = qi; t3 = qj; }
-      else { t2 = qj; t3 = pj; }
-    }
-    double det = det3(t1, t2, t3);
-    if (det == 0.0) return 0.0;
-    double sgn = det > 0.0 ? 1.0 : -1.0;
-    if (det < 0.0) { v3 tmp = t2; t2 = t3; t3 = tmp; det = -det; }
+    v3 c, t1, t2, t3;
+    double det, sgn;
+    if (!flux_tet(m, s, dt, sc, f, k, c, t1, t2, t3, det, sgn)) return 0.0;
     const v3 z = mk3(0, 0, 0);
     v3 lo = mk3(dmin(dmin(0.0, t1.x), dmin(t2.x, t3.x)), dmin(dmin(0.0, t1.y), dmin(t2.y, t3.y)),
                 dmin(dmin(0.0, t1.z), dmin(t2.z, t3.z)));

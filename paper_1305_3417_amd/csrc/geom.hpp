@@ -83,6 +83,101 @@ VHD double tet_kept_fraction(const double d[4]) {
 }
 
 // ---------------------------------------------------------------------------
+// register-only clipping of a tetrahedron by a few planes
+// ---------------------------------------------------------------------------
+// The part of a tetrahedron on the kept side (d >= 0) of one plane is 0, 1 or
+// 3 tetrahedra: one kept vertex a -> (a, ab, ac, ad); three kept (d removed)
+// -> the prism a b c | ad bd cd as three tets; two kept (a, b) -> the prism
+// a ac ad | b bc bd as three tets.  xy is the cut point on edge x -> y.
+VHD int kept_piece_count(const double d[4]) {
+  int k = (d[0] >= 0.0) + (d[1] >= 0.0) + (d[2] >= 0.0) + (d[3] >= 0.0);
+  return k == 4 ? 1 : (k == 0 ? 0 : (k == 1 ? 1 : 3));
+}
+
+VHD v3 cut_point(v3 x, v3 y, double dx, double dy) {
+  double t = dx / (dx - dy);
+  return x + t * (y - x);
+}
+
+VHD void kept_piece(const v3 v[4], const double d[4], int piece, v3 o[4]) {
+  int mk = (d[0] >= 0.0) | ((d[1] >= 0.0) << 1) | ((d[2] >= 0.0) << 2) | ((d[3] >= 0.0) << 3);
+  int kept = __builtin_popcount(mk);
+  if (kept == 4) { o[0] = v[0]; o[1] = v[1]; o[2] = v[2]; o[3] = v[3]; return; }
+  if (kept == 1) {
+    int a = __builtin_ctz(mk);
+    int r0 = (a + 1) & 3, r1 = (a + 2) & 3, r2 = (a + 3) & 3;
+    o[0] = v[a];
+    o[1] = cut_point(v[a], v[r0], d[a], d[r0]);
+    o[2] = cut_point(v[a], v[r1], d[a], d[r1]);
+    o[3] = cut_point(v[a], v[r2], d[a], d[r2]);
+    return;
+  }
+  if (kept == 3) {
+    int r = __builtin_ctz(~mk & 15);
+    int a = (r + 1) & 3, b = (r + 2) & 3, c = (r + 3) & 3;
+    v3 ad = cut_point(v[a], v[r], d[a], d[r]);
+    v3 bd = cut_point(v[b], v[r], d[b], d[r]);
+    if (piece == 0) { o[0] = v[a]; o[1] = v[b]; o[2] = v[c]; o[3] = ad; return; }
+    if (piece == 1) { o[0] = v[b]; o[1] = v[c]; o[2] = ad; o[3] = bd; return; }
+    o[0] = v[c]; o[1] = ad; o[2] = bd; o[3] = cut_point(v[c], v[r], d[c], d[r]);
+    return;
+  }
+  int a = __builtin_ctz(mk);
+  int b = __builtin_ctz(mk & ~(1 << a));
+  int rm = ~mk & 15;
+  int c = __builtin_ctz(rm);
+  int e = __builtin_ctz(rm & ~(1 << c));
+  v3 ac = cut_point(v[a], v[c], d[a], d[c]);
+  v3 ae = cut_point(v[a], v[e], d[a], d[e]);
+  v3 bc = cut_point(v[b], v[c], d[b], d[c]);
+  if (piece == 0) { o[0] = v[a]; o[1] = ac; o[2] = ae; o[3] = v[b]; return; }
+  if (piece == 1) { o[0] = ac; o[1] = ae; o[2] = v[b]; o[3] = bc; return; }
+  o[0] = ae; o[1] = v[b]; o[2] = bc; o[3] = cut_point(v[b], v[e], d[b], d[e]);
+}
+
+// distances s - n.x of the four vertices to the plane (n, s)
+VHD void plane_dists(const v3 v[4], double4 pl, double d[4]) {
+  v3 n = mk3(pl.x, pl.y, pl.z);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) d[i] = pl.w - dot(n, v[i]);
+}
+
+VHD double abs_vol6(const v3 t[4]) {
+  double v = det3(t[1] - t[0], t[2] - t[0], t[3] - t[0]);
+  return v < 0.0 ? -v : v;
+}
+
+// six times |T ∩ {n_j.x <= s_j, j < k}| for k <= 3 planes: split by all but
+// the last plane into at most nine tetrahedra, closed-form fraction for the last
+VHD double vol6_planes(const v3 T[4], double vol6, const double4 *pl, int k) {
+  if (k == 0) return vol6;
+  double d0[4];
+  plane_dists(T, pl[0], d0);
+  if (k == 1) return vol6 * tet_kept_fraction(d0);
+  double acc = 0.0;
+  const int n1 = kept_piece_count(d0);
+  for (int p1 = 0; p1 < n1; ++p1) {
+    v3 T1[4];
+    kept_piece(T, d0, p1, T1);
+    double d1[4];
+    plane_dists(T1, pl[1], d1);
+    if (k == 2) {
+      acc += abs_vol6(T1) * tet_kept_fraction(d1);
+      continue;
+    }
+    const int n2 = kept_piece_count(d1);
+    for (int p2 = 0; p2 < n2; ++p2) {
+      v3 T2[4];
+      kept_piece(T1, d1, p2, T2);
+      double d2[4];
+      plane_dists(T2, pl[2], d2);
+      acc += abs_vol6(T2) * tet_kept_fraction(d2);
+    }
+  }
+  return acc;
+}
+
+// ---------------------------------------------------------------------------
 // simple polytope as a vertex graph
 // ---------------------------------------------------------------------------
 // Vertex i has position (X, Y, Z) and neighbours NB(i,0..2) in counter-clockwise

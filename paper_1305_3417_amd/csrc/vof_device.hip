@@ -489,8 +489,37 @@ __global__ __launch_bounds__(kBlock) void k_flux(DMesh m, DState s, DParams p, i
 // The signed tet volume times sum over stencil cells of
 // |T ∩ C_c ∩ H_c| (H = the PLIC half-space in interface cells, all space in
 // full cells, alpha-weighted in vanishing-gradient cells) is stored per item.
-template <int NMAX>
-__global__ __launch_bounds__(kClipBlock) void k_clip(DMesh m, DState s, DParams p, int step) {
+// Fast clip: register-only, one lane per (geometric face, flux tet); tets
+// with a pair that needs more than three planes (and every tet when the
+// stencil check is on) are queued for k_clip_general.
+__global__ __launch_bounds__(kBlock) void k_clip_fast(DMesh m, DState s, DParams p, int step) {
+  const double dt = s.dt[step], sc = s.sc[step];
+  const int64_t total = (int64_t)s.work[kWGeometric] * m.tpf;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  unsigned long long npairs = 0;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < total; base += stride) {
+    const int64_t idx = base + threadIdx.x;
+    bool defer = false;
+    if (idx < total) {
+      int slot = (int)(idx / m.tpf);
+      int k = (int)(idx - (int64_t)slot * m.tpf);
+      double v = 0.0;
+      unsigned long long np = 0;
+      defer = p.check_stencil || !flux_tet_phase_fast(m, s, dt, sc, s.gfaces[slot], k, v, np);
+      if (!defer) {
+        s.tetvol[idx] = v;
+        npairs += np;
+      }
+    }
+    int q = wave_append(&s.work[kWDeferred], defer);
+    if (defer) s.defer[q] = (int32_t)idx;
+  }
+  wave_count(&s.cnt[kCntPairs], npairs);
+}
+
+// General clip of the queued tets: vertex-graph polytopes in LDS.
+__global__ __launch_bounds__(kClipBlock) void k_clip_general(DMesh m, DState s, DParams p,
+                                                             int step) {
   __shared__ double lx[kClipCap * kClipBlock], ly[kClipCap * kClipBlock],
       lz[kClipCap * kClipBlock], ld[kClipCap * kClipBlock];
   __shared__ uint8_t lnb[3 * kClipCap * kClipBlock], laux[kClipCap * kClipBlock];
@@ -501,10 +530,10 @@ __global__ __launch_bounds__(kClipBlock) void k_clip(DMesh m, DState s, DParams 
   P.st = kClipBlock; P.cap = kClipCap; P.nv = 0;
 
   const double dt = s.dt[step], sc = s.sc[step];
-  const int64_t total = (int64_t)s.work[kWGeometric] * m.tpf;
+  const int count = s.work[kWDeferred];
   unsigned long long ncap = 0, npairs = 0;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + tid; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
+  for (int i = blockIdx.x * blockDim.x + tid; i < count; i += gridDim.x * blockDim.x) {
+    const int64_t idx = s.defer[i];
     int slot = (int)(idx / m.tpf);
     int k = (int)(idx - (int64_t)slot * m.tpf);
     double deficit, gross;
@@ -574,6 +603,7 @@ __global__ __launch_bounds__(kBlock) void k_ledger(DMesh m, DState s) {
     s.cnt[kCntSteps] += 1;
     s.cnt[kCntGeometric] += (unsigned long long)s.work[kWGeometric];
     s.cnt[kCntInterface] += (unsigned long long)s.work[kWInterface];
+    s.cnt[kCntDeferred] += (unsigned long long)s.work[kWDeferred];
   }
 }
 
@@ -681,7 +711,8 @@ void launch_step(const DMesh &m, const DState &s, const DParams &p, int step, hi
     TIMED(prof, kKFlux, (k_flux<4><<<gf, kBlock, 0, st>>>(m, s, p, step)));
   else
     TIMED(prof, kKFlux, (k_flux<kMaxFacePoints><<<gf, kBlock, 0, st>>>(m, s, p, step)));
-  TIMED(prof, kKClip, (k_clip<kMaxFacePoints><<<4096, kClipBlock, 0, st>>>(m, s, p, step)));
+  TIMED(prof, kKClip, (k_clip_fast<<<4096, kBlock, 0, st>>>(m, s, p, step)));
+  TIMED(prof, kKClipGeneral, (k_clip_general<<<1024, kClipBlock, 0, st>>>(m, s, p, step)));
   TIMED(prof, kKFaceSum, (k_face_sum<<<1024, kBlock, 0, st>>>(m, s, p)));
   TIMED(prof, kKUpdate, (k_update<<<grid_for(m.nc, kBlock), kBlock, 0, st>>>(m, s)));
   TIMED(prof, kKLedger, (k_ledger<<<1, kBlock, 0, st>>>(m, s)));

@@ -384,6 +384,7 @@ vof_status vof_mesh_upload(vof_context *ctx, const vof_mesh_desc *d, vof_mesh **
   ALLOC(ds.alpha_p, np); ALLOC(ds.U, np); ALLOC(ds.F0, nf); ALLOC(ds.lam, nf);
   ALLOC(ds.vphase, nf); ALLOC(ds.vscale, nf); ALLOC(ds.iters, nf); ALLOC(ds.kind, nf); ALLOC(ds.fstatus, nf);
   ALLOC(ds.icells, nc); ALLOC(ds.gfaces, nf); ALLOC(ds.tetvol, nf * (int64_t)dm.tpf);
+  ALLOC(ds.defer, nf * (int64_t)dm.tpf);
   ALLOC(ds.work, kWNum); ALLOC(ds.cnt, kCntNum); ALLOC(ds.flags, 1); ALLOC(ds.ledger, 1);
   ALLOC(m->stats_buf, 4);
 #undef ALLOC
@@ -662,6 +663,7 @@ vof_status vof_get_stats(vof_mesh *m, vof_stats *out) {
   out->stencil_leaks = (int64_t)c[kCntLeaks];
   out->correction_iters = (int64_t)c[kCntIters];
   out->clip_pairs = (int64_t)c[kCntPairs];
+  out->general_tets = (int64_t)c[kCntDeferred];
   out->ledger = led;
   out->mass = st4[0];
   out->alpha_min = st4[1];
@@ -688,8 +690,9 @@ vof_status vof_profile_enable(vof_mesh *m, int32_t enable) {
 }
 
 const char *vof_profile_kernel_name(int32_t id) {
-  static const char *names[kKNum] = {"reset", "cell_class", "point_prep", "plane", "flux",
-                                     "clip", "face_sum", "update", "ledger"};
+  static const char *names[kKNum] = {"reset",   "cell_class",   "point_prep", "plane",
+                                     "flux",    "clip",         "clip_general", "face_sum",
+                                     "update",  "ledger"};
   return (id >= 0 && id < kKNum) ? names[id] : nullptr;
 }
 

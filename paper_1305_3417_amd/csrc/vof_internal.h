@@ -37,11 +37,12 @@ enum Counter : int {
   kCntLeaks,
   kCntIters,
   kCntPairs,
+  kCntDeferred,
   kCntNum
 };
 
 // per-step work counters (reset every step)
-enum WorkCounter : int { kWInterface = 0, kWGeometric = 1, kWNum = 4 };
+enum WorkCounter : int { kWInterface = 0, kWGeometric = 1, kWDeferred = 2, kWNum = 4 };
 
 struct DMesh {
   int64_t np, nc, nf, ni;
@@ -97,6 +98,7 @@ struct DState {
   double *tetvol;       // per geometric face slot x tet
   double *tetdef;       // stencil check only: uncovered signed tet volume
   double *tetgross;     // stencil check only: unsigned tet volume
+  int32_t *defer;       // flux tets left to the general clipper
   int32_t *work;        // per-step counters (kWNum)
   unsigned long long *cnt;  // kCntNum
   uint32_t *flags;      // latched status bits
@@ -107,8 +109,8 @@ struct DState {
 
 // Per-kernel timing with HIP events on the launch stream (optional).
 enum KernelId : int {
-  kKReset = 0, kKCellClass, kKPointPrep, kKPlane, kKFlux, kKClip, kKFaceSum, kKUpdate,
-  kKLedger, kKNum
+  kKReset = 0, kKCellClass, kKPointPrep, kKPlane, kKFlux, kKClip, kKClipGeneral, kKFaceSum,
+  kKUpdate, kKLedger, kKNum
 };
 struct Prof {
   struct Rec { int kid; hipEvent_t a, b; };
