@@ -78,7 +78,7 @@ VHD bool flux_tet_phase_fast(const DMesh &m, const DState &s, double dt, double 
   v3 c, t1, t2, t3;
   double det, sgn;
   if (!flux_tet(m, s, dt, sc, f, k, c, t1, t2, t3, det, sgn)) return true;
-  const v3 T[4] = {mk3(0, 0, 0), t1, t2, t3};
+  const Tet T{mk3(0, 0, 0), t1, t2, t3};
   v3 lo = mk3(dmin(dmin(0.0, t1.x), dmin(t2.x, t3.x)), dmin(dmin(0.0, t1.y), dmin(t2.y, t3.y)),
               dmin(dmin(0.0, t1.z), dmin(t2.z, t3.z))) + c;
   v3 hi = mk3(dmax(dmax(0.0, t1.x), dmax(t2.x, t3.x)), dmax(dmax(0.0, t1.y), dmax(t2.y, t3.y)),
@@ -93,10 +93,12 @@ VHD bool flux_tet_phase_fast(const DMesh &m, const DState &s, double dt, double 
     if (hi.x <= blo.x || lo.x >= bhi.x || hi.y <= blo.y || lo.y >= bhi.y || hi.z <= blo.z ||
         lo.z >= bhi.z)
       continue;
-    double4 pl[3];
+    // cutting planes in registers p0..p2 (the PLIC plane of an interface
+    // cell takes the last slot)
+    Pl p0{0, 0, 0, 0}, p1 = p0, p2 = p0;
     const int room = (cl == 1) ? 2 : 3;
     int ncut = 0;
-    bool outside = false, over = false;
+    bool outside = false;
     for (int q = m.cf_off[cell]; q < m.cf_off[cell + 1]; ++q) {
       double4 cp = m.cpl[q];
       v3 nn = xyz4(cp);
@@ -106,21 +108,27 @@ VHD bool flux_tet_phase_fast(const DMesh &m, const DState &s, double dt, double 
       double dmn = dmin(dmin(off, d1), dmin(d2, d3));
       if (dmx <= 0.0) { outside = true; break; }
       if (dmn < 0.0) {
-        if (ncut < room) pl[ncut] = make_double4(nn.x, nn.y, nn.z, off);
-        else over = true;
+        Pl pn = mkpl(nn, off);
+        p2 = sel(ncut == 2, pn, p2);
+        p1 = sel(ncut == 1, pn, p1);
+        p0 = sel(ncut == 0, pn, p0);
         ++ncut;
       }
     }
     if (outside) continue;
-    if (over) return false;
+    if (ncut > room) return false;
     ++np;
     int npl = ncut;
     if (cl == 1) {
       double4 pp = s.plane[cell];
       v3 nn = xyz4(pp);
-      pl[npl++] = make_double4(nn.x, nn.y, nn.z, pp.w - dot(nn, c));
+      Pl pn = mkpl(nn, pp.w - dot(nn, c));
+      p2 = sel(npl == 2, pn, p2);
+      p1 = sel(npl == 1, pn, p1);
+      p0 = sel(npl == 0, pn, p0);
+      ++npl;
     }
-    double v = vol6_planes(T, det, pl, npl);
+    double v = vol6_planes3(T, det, p0, p1, p2, npl);
     acc += (cl == 3) ? s.alpha[cell] * v : v;
     if (ncut == 0) break;  // the tet lies inside this cell
   }
@@ -186,9 +194,16 @@ VHD double flux_tet_phase(const DMesh &m, const DState &s, const DParams &p, dou
         double4 pl = s.plane[cell];
         v3 nn = xyz4(pl);
         double off = pl.w - dot(nn, c);
-        if (ncut == 0) {
-          double dd[4] = {off, off - dot(nn, t1), off - dot(nn, t2), off - dot(nn, t3)};
-          vph = det * tet_kept_fraction(dd);
+        if (ncut <= 1) {
+          // at most two planes: closed forms, no polytope
+          const Tet T{z, t1, t2, t3};
+          Pl pc{0, 0, 0, 0};
+          if (ncut == 1) {
+            double4 cp = m.cpl[cuts[0]];
+            pc = mkpl(xyz4(cp), cp.w - dot(xyz4(cp), c));
+          }
+          Pl pp = mkpl(nn, off);
+          vph = ncut == 0 ? vol6_planes2(T, det, pp, pp, 1) : vol6_planes2(T, det, pc, pp, 2);
         } else {
           P.init_tet(z, t1, t2, t3);
           bool ok = true;
@@ -207,6 +222,12 @@ VHD double flux_tet_phase(const DMesh &m, const DState &s, const DParams &p, dou
       } else if (cl == 0) {
         vph = 0.0;
       } else {
+        if (vcell < 0.0 && ncut == 2) {
+          const Tet T{z, t1, t2, t3};
+          double4 c0 = m.cpl[cuts[0]], c1 = m.cpl[cuts[1]];
+          vcell = vol6_planes2(T, det, mkpl(xyz4(c0), c0.w - dot(xyz4(c0), c)),
+                               mkpl(xyz4(c1), c1.w - dot(xyz4(c1), c)), 2);
+        }
         if (vcell < 0.0) {
           P.init_tet(z, t1, t2, t3);
           bool ok = true;

@@ -42,44 +42,80 @@ VHD double det3(v3 a, v3 b, v3 c) { return dot(a, cross(b, c)); }
 VHD double dmin(double a, double b) { return a < b ? a : b; }
 VHD double dmax(double a, double b) { return a > b ? a : b; }
 
-// Fraction of a tetrahedron with signed vertex distances d[0..3] lying in the
+// A tetrahedron as four named vertices and four signed distances.  Every
+// case analysis below first orders the vertices so that the kept ones
+// (distance >= 0) come first, with a five-comparator sorting network on
+// values; all later indexing is then by constant position, so nothing is
+// indexed at run time and everything stays in registers.
+struct Tet {
+  v3 a, b, c, d;
+};
+struct D4 {
+  double a, b, c, d;
+};
+
+// Component-wise select.  (A conditional expression on aggregate lvalues is
+// lowered to a select of addresses, which forces them into memory.)
+VHD v3 sel(bool c, v3 a, v3 b) {
+  return v3{c ? a.x : b.x, c ? a.y : b.y, c ? a.z : b.z};
+}
+
+VHD void cswap_kept(v3 &x, v3 &y, double &dx, double &dy) {
+  bool sw = !(dx >= 0.0) && (dy >= 0.0);
+  v3 tx = x;
+  double tdx = dx;
+  x = sel(sw, y, x);
+  dx = sw ? dy : dx;
+  y = sel(sw, tx, y);
+  dy = sw ? tdx : dy;
+}
+VHD void cswap_kept(double &dx, double &dy) {
+  bool sw = !(dx >= 0.0) && (dy >= 0.0);
+  double t = dx;
+  dx = sw ? dy : dx;
+  dy = sw ? t : dy;
+}
+
+// kept vertices first (order among kept / among removed is immaterial)
+VHD void sort_kept(Tet &t, D4 &d) {
+  cswap_kept(t.a, t.b, d.a, d.b);
+  cswap_kept(t.c, t.d, d.c, d.d);
+  cswap_kept(t.a, t.c, d.a, d.c);
+  cswap_kept(t.b, t.d, d.b, d.d);
+  cswap_kept(t.b, t.c, d.b, d.c);
+}
+VHD void sort_kept(D4 &d) {
+  cswap_kept(d.a, d.b);
+  cswap_kept(d.c, d.d);
+  cswap_kept(d.a, d.c);
+  cswap_kept(d.b, d.d);
+  cswap_kept(d.b, d.c);
+}
+
+VHD int kept_count(const D4 &d) {
+  return (d.a >= 0.0) + (d.b >= 0.0) + (d.c >= 0.0) + (d.d >= 0.0);
+}
+
+// Fraction of a tetrahedron with signed vertex distances d lying in the
 // closed half-space d >= 0.  With t_xy = d_x / (d_x - d_y) the position of the
 // cut on edge x -> y (x kept, y removed):
 //   one kept vertex a:          t_ab t_ac t_ad
 //   three kept (d removed):     1 - prod_j d_d / (d_d - d_j)
 //   two kept (a, b):            t_ac t_ad + t_ad t_bc (1 - t_ac) + t_bc t_bd (1 - t_ad)
 // (the last is the prism a, b | ac, ad, bc, bd cut into three tetrahedra).
-VHD double tet_kept_fraction(const double d[4]) {
-  int kept = 0, mk = 0;
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-    if (d[i] >= 0.0) { ++kept; mk |= 1 << i; }
+VHD double tet_kept_fraction(D4 d) {
+  const int kept = kept_count(d);
   if (kept == 4) return 1.0;
   if (kept == 0) return 0.0;
-  if (kept == 1) {
-    int a = __builtin_ctz(mk);
-    double da = d[a], f = 1.0;
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      if (j != a) f *= da / (da - d[j]);
-    return f;
-  }
-  if (kept == 3) {
-    int r = __builtin_ctz(~mk & 15);
-    double dr = d[r], f = 1.0;
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      if (j != r) f *= dr / (dr - d[j]);
-    return 1.0 - f;
-  }
-  int a = __builtin_ctz(mk);
-  int b = __builtin_ctz(mk & ~(1 << a));
-  int rm = ~mk & 15;
-  int c = __builtin_ctz(rm);
-  int e = __builtin_ctz(rm & ~(1 << c));
-  double tac = d[a] / (d[a] - d[c]), tad = d[a] / (d[a] - d[e]);
-  double tbc = d[b] / (d[b] - d[c]), tbd = d[b] / (d[b] - d[e]);
+  sort_kept(d);
+  if (kept == 1) return (d.a / (d.a - d.b)) * (d.a / (d.a - d.c)) * (d.a / (d.a - d.d));
+  if (kept == 3) return 1.0 - (d.d / (d.d - d.a)) * (d.d / (d.d - d.b)) * (d.d / (d.d - d.c));
+  double tac = d.a / (d.a - d.c), tad = d.a / (d.a - d.d);
+  double tbc = d.b / (d.b - d.c), tbd = d.b / (d.b - d.d);
   return tac * tad + tad * tbc * (1.0 - tac) + tbc * tbd * (1.0 - tad);
+}
+VHD double tet_kept_fraction(const double dd[4]) {
+  return tet_kept_fraction(D4{dd[0], dd[1], dd[2], dd[3]});
 }
 
 // ---------------------------------------------------------------------------
@@ -89,8 +125,8 @@ VHD double tet_kept_fraction(const double d[4]) {
 // 3 tetrahedra: one kept vertex a -> (a, ab, ac, ad); three kept (d removed)
 // -> the prism a b c | ad bd cd as three tets; two kept (a, b) -> the prism
 // a ac ad | b bc bd as three tets.  xy is the cut point on edge x -> y.
-VHD int kept_piece_count(const double d[4]) {
-  int k = (d[0] >= 0.0) + (d[1] >= 0.0) + (d[2] >= 0.0) + (d[3] >= 0.0);
+VHD int kept_piece_count(const D4 &d) {
+  int k = kept_count(d);
   return k == 4 ? 1 : (k == 0 ? 0 : (k == 1 ? 1 : 3));
 }
 
@@ -99,80 +135,82 @@ VHD v3 cut_point(v3 x, v3 y, double dx, double dy) {
   return x + t * (y - x);
 }
 
-VHD void kept_piece(const v3 v[4], const double d[4], int piece, v3 o[4]) {
-  int mk = (d[0] >= 0.0) | ((d[1] >= 0.0) << 1) | ((d[2] >= 0.0) << 2) | ((d[3] >= 0.0) << 3);
-  int kept = __builtin_popcount(mk);
-  if (kept == 4) { o[0] = v[0]; o[1] = v[1]; o[2] = v[2]; o[3] = v[3]; return; }
-  if (kept == 1) {
-    int a = __builtin_ctz(mk);
-    int r0 = (a + 1) & 3, r1 = (a + 2) & 3, r2 = (a + 3) & 3;
-    o[0] = v[a];
-    o[1] = cut_point(v[a], v[r0], d[a], d[r0]);
-    o[2] = cut_point(v[a], v[r1], d[a], d[r1]);
-    o[3] = cut_point(v[a], v[r2], d[a], d[r2]);
-    return;
-  }
+// piece-th tetrahedron of the kept part; t and d must be sorted (sort_kept)
+VHD Tet kept_piece_sorted(const Tet &t, const D4 &d, int kept, int piece) {
+  if (kept == 4) return t;
+  if (kept == 1)
+    return Tet{t.a, cut_point(t.a, t.b, d.a, d.b), cut_point(t.a, t.c, d.a, d.c),
+               cut_point(t.a, t.d, d.a, d.d)};
   if (kept == 3) {
-    int r = __builtin_ctz(~mk & 15);
-    int a = (r + 1) & 3, b = (r + 2) & 3, c = (r + 3) & 3;
-    v3 ad = cut_point(v[a], v[r], d[a], d[r]);
-    v3 bd = cut_point(v[b], v[r], d[b], d[r]);
-    if (piece == 0) { o[0] = v[a]; o[1] = v[b]; o[2] = v[c]; o[3] = ad; return; }
-    if (piece == 1) { o[0] = v[b]; o[1] = v[c]; o[2] = ad; o[3] = bd; return; }
-    o[0] = v[c]; o[1] = ad; o[2] = bd; o[3] = cut_point(v[c], v[r], d[c], d[r]);
-    return;
+    v3 ad = cut_point(t.a, t.d, d.a, d.d);
+    v3 bd = cut_point(t.b, t.d, d.b, d.d);
+    if (piece == 0) return Tet{t.a, t.b, t.c, ad};
+    if (piece == 1) return Tet{t.b, t.c, ad, bd};
+    return Tet{t.c, ad, bd, cut_point(t.c, t.d, d.c, d.d)};
   }
-  int a = __builtin_ctz(mk);
-  int b = __builtin_ctz(mk & ~(1 << a));
-  int rm = ~mk & 15;
-  int c = __builtin_ctz(rm);
-  int e = __builtin_ctz(rm & ~(1 << c));
-  v3 ac = cut_point(v[a], v[c], d[a], d[c]);
-  v3 ae = cut_point(v[a], v[e], d[a], d[e]);
-  v3 bc = cut_point(v[b], v[c], d[b], d[c]);
-  if (piece == 0) { o[0] = v[a]; o[1] = ac; o[2] = ae; o[3] = v[b]; return; }
-  if (piece == 1) { o[0] = ac; o[1] = ae; o[2] = v[b]; o[3] = bc; return; }
-  o[0] = ae; o[1] = v[b]; o[2] = bc; o[3] = cut_point(v[b], v[e], d[b], d[e]);
+  v3 ac = cut_point(t.a, t.c, d.a, d.c);
+  v3 ad = cut_point(t.a, t.d, d.a, d.d);
+  v3 bc = cut_point(t.b, t.c, d.b, d.c);
+  if (piece == 0) return Tet{t.a, ac, ad, t.b};
+  if (piece == 1) return Tet{ac, ad, t.b, bc};
+  return Tet{ad, t.b, bc, cut_point(t.b, t.d, d.b, d.d)};
+}
+
+// A plane n.x = s as four plain doubles (plain aggregates stay in registers
+// through selects, unlike the union-based vector types).
+struct Pl {
+  double x, y, z, w;
+};
+VHD Pl mkpl(v3 n, double s) { return Pl{n.x, n.y, n.z, s}; }
+VHD Pl sel(bool c, Pl a, Pl b) {
+  return Pl{c ? a.x : b.x, c ? a.y : b.y, c ? a.z : b.z, c ? a.w : b.w};
 }
 
 // distances s - n.x of the four vertices to the plane (n, s)
-VHD void plane_dists(const v3 v[4], double4 pl, double d[4]) {
+VHD D4 plane_dists(const Tet &t, Pl pl) {
   v3 n = mk3(pl.x, pl.y, pl.z);
-#pragma unroll
-  for (int i = 0; i < 4; ++i) d[i] = pl.w - dot(n, v[i]);
+  return D4{pl.w - dot(n, t.a), pl.w - dot(n, t.b), pl.w - dot(n, t.c), pl.w - dot(n, t.d)};
 }
 
-VHD double abs_vol6(const v3 t[4]) {
-  double v = det3(t[1] - t[0], t[2] - t[0], t[3] - t[0]);
+VHD double abs_vol6(const Tet &t) {
+  double v = det3(t.b - t.a, t.c - t.a, t.d - t.a);
   return v < 0.0 ? -v : v;
 }
 
-// six times |T ∩ {n_j.x <= s_j, j < k}| for k <= 3 planes: split by all but
-// the last plane into at most nine tetrahedra, closed-form fraction for the last
-VHD double vol6_planes(const v3 T[4], double vol6, const double4 *pl, int k) {
+// six times |T ∩ {n_j.x <= s_j, j < k}| for k <= 2 planes: the kept part of
+// the first plane as at most three tetrahedra, each with the closed-form
+// fraction for the second plane
+VHD double vol6_planes2(Tet T, double vol6, Pl p0, Pl p1, int k) {
   if (k == 0) return vol6;
-  double d0[4];
-  plane_dists(T, pl[0], d0);
+  D4 d0 = plane_dists(T, p0);
   if (k == 1) return vol6 * tet_kept_fraction(d0);
+  const int kept = kept_count(d0);
+  const int n1 = kept == 4 ? 1 : (kept == 0 ? 0 : (kept == 1 ? 1 : 3));
+  if (n1 == 0) return 0.0;
+  sort_kept(T, d0);
   double acc = 0.0;
-  const int n1 = kept_piece_count(d0);
-  for (int p1 = 0; p1 < n1; ++p1) {
-    v3 T1[4];
-    kept_piece(T, d0, p1, T1);
-    double d1[4];
-    plane_dists(T1, pl[1], d1);
-    if (k == 2) {
-      acc += abs_vol6(T1) * tet_kept_fraction(d1);
-      continue;
-    }
-    const int n2 = kept_piece_count(d1);
-    for (int p2 = 0; p2 < n2; ++p2) {
-      v3 T2[4];
-      kept_piece(T1, d1, p2, T2);
-      double d2[4];
-      plane_dists(T2, pl[2], d2);
-      acc += abs_vol6(T2) * tet_kept_fraction(d2);
-    }
+  for (int i1 = 0; i1 < n1; ++i1) {
+    Tet T1 = kept_piece_sorted(T, d0, kept, i1);
+    acc += abs_vol6(T1) * tet_kept_fraction(plane_dists(T1, p1));
+  }
+  return acc;
+}
+
+// six times |T ∩ {n_j.x <= s_j, j < k}| for k <= 3 planes: the kept part of
+// the first plane as at most three tetrahedra, each through the two-plane
+// form above
+VHD double vol6_planes3(Tet T, double vol6, Pl p0, Pl p1, Pl p2, int k) {
+  if (k <= 2) return vol6_planes2(T, vol6, p0, p1, k);
+  D4 d0 = plane_dists(T, p0);
+  const int kept = kept_count(d0);
+  if (kept == 0) return 0.0;
+  if (kept == 4) return vol6_planes2(T, vol6, p1, p2, 2);
+  const int n1 = kept == 1 ? 1 : 3;
+  sort_kept(T, d0);
+  double acc = 0.0;
+  for (int i1 = 0; i1 < n1; ++i1) {
+    Tet T1 = kept_piece_sorted(T, d0, kept, i1);
+    acc += vol6_planes2(T1, abs_vol6(T1), p1, p2, 2);
   }
   return acc;
 }

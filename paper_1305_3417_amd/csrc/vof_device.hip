@@ -31,6 +31,7 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kClipBlock = 64;
 constexpr int kClipCap = 20;  // polytope vertices kept per lane in LDS
+constexpr int kLedgerParts = 256;  // partial sums of the boundary ledger
 
 __device__ __forceinline__ v3 xyz(double4 a) { return mk3(a.x, a.y, a.z); }
 
@@ -388,92 +389,112 @@ __device__ __forceinline__ void correct(double c1, double c2, double c3, double 
   lam = x;
 }
 
+// per-block sums of up to three counters, one atomic each per block
+__device__ __forceinline__ void block_count3(unsigned long long *d0, unsigned long long v0,
+                                             unsigned long long *d1, unsigned long long v1,
+                                             unsigned long long *d2, unsigned long long v2) {
+  __shared__ unsigned long long red[3][kBlock / 64];
+  v0 = wave_sum(v0);
+  v1 = wave_sum(v1);
+  v2 = wave_sum(v2);
+  const int w = threadIdx.x / 64;
+  if (lane_id() == 0) { red[0][w] = v0; red[1][w] = v1; red[2][w] = v2; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long a = 0, b = 0, c = 0;
+    for (int i = 0; i < (int)(blockDim.x / 64); ++i) { a += red[0][i]; b += red[1][i]; c += red[2][i]; }
+    if (a) atomicAdd(d0, a);
+    if (b) atomicAdd(d1, b);
+    if (c) atomicAdd(d2, c);
+  }
+}
+
 template <int NMAX>
 __global__ __launch_bounds__(kBlock) void k_flux(DMesh m, DState s, DParams p, int step) {
   const double dt = s.dt[step], sc = s.sc[step];
-  int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  bool geo = false;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   unsigned long long nflux = 0, nit = 0, nbad = 0;
-  if (f < m.nf) {
-    double F = sc * s.F0[f];
-    double T = F * dt;
-    double lam = 0.0, vph = 0.0;
-    int it = 0, stat = 0;
-    uint8_t kind = 0;
-    if (F != 0.0) {
-      int b = m.foff[f], n = m.foff[f + 1] - b;
-      v3 r[NMAX], d[NMAX];
-      uint8_t mask = 0;
-      v3 c = mk3(0, 0, 0);
-      const double sweep = -sc * dt;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < m.nf; base += stride) {
+    const int64_t f = base + threadIdx.x;
+    bool geo = false;
+    if (f < m.nf) {
+      double F = sc * s.F0[f];
+      double T = F * dt;
+      double lam = 0.0, vph = 0.0;
+      int it = 0, stat = 0;
+      uint8_t kind = 0;
+      if (F != 0.0) {
+        int b = m.foff[f], n = m.foff[f + 1] - b;
+        v3 r[NMAX], d[NMAX];
+        uint8_t mask = 0;
+        v3 c = mk3(0, 0, 0);
+        const double sweep = -sc * dt;
 #pragma unroll
-      for (int i = 0; i < NMAX; ++i) {
-        if (i < n) {
-          int q = m.fpts[b + i];
-          r[i] = xyz(m.X[q]);
-          d[i] = sweep * xyz(s.U[q]);
-          mask |= s.pmask[q];
-          c = c + r[i];
+        for (int i = 0; i < NMAX; ++i) {
+          if (i < n) {
+            int q = m.fpts[b + i];
+            r[i] = xyz(m.X[q]);
+            d[i] = sweep * xyz(s.U[q]);
+            mask |= s.pmask[q];
+            c = c + r[i];
+          } else {
+            r[i] = mk3(0, 0, 0);
+            d[i] = mk3(0, 0, 0);
+          }
+        }
+        c = (1.0 / n) * c;
+#pragma unroll
+        for (int i = 0; i < NMAX; ++i) r[i] = r[i] - c;
+        double t1 = 0.0, t2 = 0.0;
+        v3 A2 = mk3(0, 0, 0), B = mk3(0, 0, 0), Cc = mk3(0, 0, 0), db = mk3(0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < NMAX; ++i) {
+          if (i < n) {
+            v3 rn = (i + 1 < n) ? r[(i + 1) % NMAX] : r[0];
+            v3 dn = (i + 1 < n) ? d[(i + 1) % NMAX] : d[0];
+            v3 e = rn - r[i];
+            v3 h = 0.5 * (r[i] + rn);
+            v3 dd = cross(d[i], dn);
+            t1 += dot(h, cross(d[i] + dn, e));
+            t2 += dot(h, dd);
+            A2 = A2 + cross(r[i], rn);
+            B = B + cross(r[i], dn) + cross(d[i], rn);
+            Cc = Cc + dd;
+            db = db + d[i];
+          }
+        }
+        db = (1.0 / n) * db;
+        double c1 = (t1 - dot(db, A2)) / 6.0;
+        double c2 = (t2 - dot(db, B)) / 6.0;
+        double c3 = -dot(db, Cc) / 6.0;
+        correct(c1, c2, c3, T, p.corr_rtol, p.corr_max_iter, lam, it, stat);
+        // A target beyond the extremum of V on the branch: the phase volume of
+        // the polyhedron at the clamped lam is rescaled to F dt (scalar correction).
+        if (stat) s.vscale[f] = T / (((c3 * lam + c2) * lam + c1) * lam);
+        nflux += 1;
+        nit += (unsigned long long)it;
+        nbad += (unsigned long long)stat;
+        if ((mask & 6) == 0) {
+          kind = 1;
+          vph = 0.0;
+        } else if (mask == 2 && f < m.ni) {
+          kind = 2;
+          vph = T;
         } else {
-          r[i] = mk3(0, 0, 0);
-          d[i] = mk3(0, 0, 0);
+          kind = 3;
+          geo = true;
         }
       }
-      c = (1.0 / n) * c;
-#pragma unroll
-      for (int i = 0; i < NMAX; ++i) r[i] = r[i] - c;
-      double t1 = 0.0, t2 = 0.0;
-      v3 A2 = mk3(0, 0, 0), B = mk3(0, 0, 0), Cc = mk3(0, 0, 0), db = mk3(0, 0, 0);
-#pragma unroll
-      for (int i = 0; i < NMAX; ++i) {
-        if (i < n) {
-          v3 rn = (i + 1 < n) ? r[(i + 1) % NMAX] : r[0];
-          v3 dn = (i + 1 < n) ? d[(i + 1) % NMAX] : d[0];
-          v3 e = rn - r[i];
-          v3 h = 0.5 * (r[i] + rn);
-          v3 dd = cross(d[i], dn);
-          t1 += dot(h, cross(d[i] + dn, e));
-          t2 += dot(h, dd);
-          A2 = A2 + cross(r[i], rn);
-          B = B + cross(r[i], dn) + cross(d[i], rn);
-          Cc = Cc + dd;
-          db = db + d[i];
-        }
-      }
-      db = (1.0 / n) * db;
-      double c1 = (t1 - dot(db, A2)) / 6.0;
-      double c2 = (t2 - dot(db, B)) / 6.0;
-      double c3 = -dot(db, Cc) / 6.0;
-      correct(c1, c2, c3, T, p.corr_rtol, p.corr_max_iter, lam, it, stat);
-      // A target beyond the extremum of V on the branch: the phase volume of
-      // the polyhedron at the clamped lam is rescaled to F dt (scalar correction).
-      if (stat) s.vscale[f] = T / (((c3 * lam + c2) * lam + c1) * lam);
-      nflux = 1;
-      nit = (unsigned long long)it;
-      nbad = (unsigned long long)stat;
-      if ((mask & 6) == 0) {
-        kind = 1;
-        vph = 0.0;
-      } else if (mask == 2 && f < m.ni) {
-        kind = 2;
-        vph = T;
-      } else {
-        kind = 3;
-        geo = true;
-      }
+      s.lam[f] = lam;
+      if (!geo) s.vphase[f] = vph;
+      s.iters[f] = (uint8_t)(it > 255 ? 255 : it);
+      s.kind[f] = kind;
+      s.fstatus[f] = (uint8_t)stat;
     }
-    s.lam[f] = lam;
-    if (!geo) s.vphase[f] = vph;
-    s.iters[f] = (uint8_t)(it > 255 ? 255 : it);
-    s.kind[f] = kind;
-    s.fstatus[f] = (uint8_t)stat;
+    int slot = wave_append(&s.work[kWGeometric], geo);
+    if (geo) s.gfaces[slot] = (int32_t)f;
   }
-  int slot = wave_append(&s.work[kWGeometric], geo);
-  if (geo) s.gfaces[slot] = (int32_t)f;
-  wave_count(&s.cnt[kCntFaceFluxes], nflux);
-  wave_count(&s.cnt[kCntIters], nit);
-  wave_count(&s.cnt[kCntUnreached], nbad);
-  if (__ballot(nbad != 0) && lane_id() == 0) flag(s.flags, kFlagUnreached);
+  block_count3(&s.cnt[kCntFaceFluxes], nflux, &s.cnt[kCntIters], nit, &s.cnt[kCntUnreached], nbad);
 }
 
 // ---------------------------------------------------------------------------
@@ -587,11 +608,28 @@ __global__ __launch_bounds__(kBlock) void k_update(DMesh m, DState s) {
   s.alpha[c] = s.alpha[c] - acc / m.V[c];
 }
 
-// boundary ledger: one block, fixed reduction order
-__global__ __launch_bounds__(kBlock) void k_ledger(DMesh m, DState s) {
+// boundary ledger, two stages in fixed order: per-block partial sums of the
+// boundary faces' phase volumes, then one block adds them and the counters
+__global__ __launch_bounds__(kBlock) void k_ledger_part(DMesh m, DState s) {
   __shared__ double red[kBlock];
   double acc = 0.0;
-  for (int64_t f = m.ni + threadIdx.x; f < m.nf; f += kBlock) acc += s.vphase[f];
+  const int64_t nb = m.nf - m.ni;
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < nb;
+       i += (int64_t)gridDim.x * kBlock)
+    acc += s.vphase[m.ni + i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = kBlock / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) s.part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_ledger(DMesh m, DState s, int nparts) {
+  __shared__ double red[kBlock];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += kBlock) acc += s.part[i];
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int o = kBlock / 2; o > 0; o >>= 1) {
@@ -704,7 +742,9 @@ void launch_step(const DMesh &m, const DState &s, const DParams &p, int step, hi
   unsigned gp = grid_for(m.nc, kBlock);
   gp = gp < 2048 ? (gp ? gp : 1) : 2048;
   TIMED(prof, kKPlane, (k_plane<<<gp, kBlock, 0, st>>>(m, s, p)));
+  // persistent-style grid: a few blocks per CU, grid-stride over the faces
   unsigned gf = grid_for(m.nf, kBlock);
+  gf = gf < 8192 ? gf : 8192;
   if (m.maxn <= 3)
     TIMED(prof, kKFlux, (k_flux<3><<<gf, kBlock, 0, st>>>(m, s, p, step)));
   else if (m.maxn == 4)
@@ -715,7 +755,8 @@ void launch_step(const DMesh &m, const DState &s, const DParams &p, int step, hi
   TIMED(prof, kKClipGeneral, (k_clip_general<<<1024, kClipBlock, 0, st>>>(m, s, p, step)));
   TIMED(prof, kKFaceSum, (k_face_sum<<<1024, kBlock, 0, st>>>(m, s, p)));
   TIMED(prof, kKUpdate, (k_update<<<grid_for(m.nc, kBlock), kBlock, 0, st>>>(m, s)));
-  TIMED(prof, kKLedger, (k_ledger<<<1, kBlock, 0, st>>>(m, s)));
+  TIMED(prof, kKLedger, (k_ledger_part<<<kLedgerParts, kBlock, 0, st>>>(m, s),
+                         k_ledger<<<1, kBlock, 0, st>>>(m, s, kLedgerParts)));
 }
 
 void launch_stats(const DMesh &m, const DState &s, double *out4, hipStream_t st) {

@@ -103,6 +103,7 @@ struct DState {
   unsigned long long *cnt;  // kCntNum
   uint32_t *flags;      // latched status bits
   double *ledger;       // accumulated boundary phase volume
+  double *part;         // partial sums of the ledger (256)
   double *dt;           // per-step dt (device copy)
   double *sc;           // per-step scale
 };
