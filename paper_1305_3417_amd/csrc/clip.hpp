@@ -21,6 +21,14 @@ namespace vof {
 
 VHD v3 xyz4(double4 a) { return mk3(a.x, a.y, a.z); }
 
+// Bounding box of tet (0, t1, t2, t3) shifted by c.
+VHD void tet_bbox(v3 c, v3 t1, v3 t2, v3 t3, v3 &lo, v3 &hi) {
+  lo = mk3(dmin(dmin(0.0, t1.x), dmin(t2.x, t3.x)), dmin(dmin(0.0, t1.y), dmin(t2.y, t3.y)),
+           dmin(dmin(0.0, t1.z), dmin(t2.z, t3.z))) + c;
+  hi = mk3(dmax(dmax(0.0, t1.x), dmax(t2.x, t3.x)), dmax(dmax(0.0, t1.y), dmax(t2.y, t3.y)),
+           dmax(dmax(0.0, t1.z), dmax(t2.z, t3.z))) + c;
+}
+
 // With check_stencil set, *deficit receives the signed volume of the tet that
 // no stencil cell covers (summed over a face it must vanish unless the flux
 // polyhedron leaves its stencil) and *gross its unsigned volume.
@@ -79,10 +87,8 @@ VHD bool flux_tet_phase_fast(const DMesh &m, const DState &s, double dt, double 
   double det, sgn;
   if (!flux_tet(m, s, dt, sc, f, k, c, t1, t2, t3, det, sgn)) return true;
   const Tet T{mk3(0, 0, 0), t1, t2, t3};
-  v3 lo = mk3(dmin(dmin(0.0, t1.x), dmin(t2.x, t3.x)), dmin(dmin(0.0, t1.y), dmin(t2.y, t3.y)),
-              dmin(dmin(0.0, t1.z), dmin(t2.z, t3.z))) + c;
-  v3 hi = mk3(dmax(dmax(0.0, t1.x), dmax(t2.x, t3.x)), dmax(dmax(0.0, t1.y), dmax(t2.y, t3.y)),
-              dmax(dmax(0.0, t1.z), dmax(t2.z, t3.z))) + c;
+  v3 lo, hi;
+  tet_bbox(c, t1, t2, t3, lo, hi);
   double acc = 0.0;
   unsigned long long np = 0;
   for (int e = m.st_off[f]; e < m.st_off[f + 1]; ++e) {
@@ -137,129 +143,111 @@ VHD bool flux_tet_phase_fast(const DMesh &m, const DState &s, double dt, double 
   return true;
 }
 
+// Six times the phase volume of the positively ordered flux tet T (apex at
+// the origin = face centre c, vol6 = det) inside stencil cell `cell`, with
+// (lo, hi) the tet's bounding box in mesh coordinates.  At most three planes
+// (cutting cell planes, plus the PLIC plane of an interface cell) take the
+// closed forms; more go through the vertex-graph polytope P.  With
+// check_stencil, *vcell receives six times |T ∩ C| (the coverage), else 0.
+VHD double pair_phase6(const DMesh &m, const DState &s, const DParams &p, v3 c, const Tet &T,
+                       double det, v3 lo, v3 hi, int cell, Poly &P, unsigned long long &ncap,
+                       unsigned long long &npairs, double *vcell) {
+  *vcell = 0.0;
+  const int cl = s.cls[cell];
+  if (cl == 0 && !p.check_stencil) return 0.0;
+  double4 blo = m.bblo[cell], bhi = m.bbhi[cell];
+  if (hi.x <= blo.x || lo.x >= bhi.x || hi.y <= blo.y || lo.y >= bhi.y || hi.z <= blo.z ||
+      lo.z >= bhi.z)
+    return 0.0;
+  int cuts[kMaxCellPlanes];
+  Pl p0{0, 0, 0, 0}, p1 = p0, p2 = p0;
+  int ncut = 0;
+  for (int q = m.cf_off[cell]; q < m.cf_off[cell + 1]; ++q) {
+    double4 cp = m.cpl[q];
+    v3 nn = xyz4(cp);
+    double off = cp.w - dot(nn, c);
+    double d1 = off - dot(nn, T.b), d2 = off - dot(nn, T.c), d3 = off - dot(nn, T.d);
+    double dmx = dmax(dmax(off, d1), dmax(d2, d3));
+    double dmn = dmin(dmin(off, d1), dmin(d2, d3));
+    if (dmx <= 0.0) return 0.0;
+    if (dmn < 0.0) {
+      Pl pn = mkpl(nn, off);
+      p2 = sel(ncut == 2, pn, p2);
+      p1 = sel(ncut == 1, pn, p1);
+      p0 = sel(ncut == 0, pn, p0);
+      if (ncut < kMaxCellPlanes) cuts[ncut] = q;
+      ++ncut;
+    }
+  }
+  ++npairs;  // a (tet, cell) pair with overlapping interiors
+  const bool need_cover = p.check_stencil || cl >= 2;
+  double vc = (need_cover && ncut <= 3) ? vol6_planes3(T, det, p0, p1, p2, ncut) : -1.0;
+  double vph = 0.0;
+  if (cl == 1) {
+    double4 pp = s.plane[cell];
+    v3 nn = xyz4(pp);
+    double off = pp.w - dot(nn, c);
+    if (ncut < 3) {
+      Pl pn = mkpl(nn, off);
+      p2 = sel(ncut == 2, pn, p2);
+      p1 = sel(ncut == 1, pn, p1);
+      p0 = sel(ncut == 0, pn, p0);
+      vph = vol6_planes3(T, det, p0, p1, p2, ncut + 1);
+    } else {
+      P.init_tet(T.a, T.b, T.c, T.d);
+      bool ok = true;
+      for (int q = 0; q < ncut && ok; ++q) {
+        double4 cp = m.cpl[cuts[q < kMaxCellPlanes ? q : 0]];
+        ok = P.clip(xyz4(cp), cp.w - dot(xyz4(cp), c));
+      }
+      if (ok && vc < 0.0 && p.check_stencil) vc = P.vol6();
+      ok = ok && P.clip(nn, off);
+      vph = ok ? P.vol6() : 0.0;
+      if (!ok || ncut > kMaxCellPlanes) ++ncap;
+    }
+  }
+  if (need_cover && vc < 0.0) {
+    P.init_tet(T.a, T.b, T.c, T.d);
+    bool ok = true;
+    for (int q = 0; q < ncut && ok; ++q) {
+      double4 cp = m.cpl[cuts[q < kMaxCellPlanes ? q : 0]];
+      ok = P.clip(xyz4(cp), cp.w - dot(xyz4(cp), c));
+    }
+    vc = ok ? P.vol6() : 0.0;
+    if (!ok || ncut > kMaxCellPlanes) ++ncap;
+  }
+  if (cl == 2) vph = vc;
+  else if (cl == 3) vph = s.alpha[cell] * vc;
+  if (p.check_stencil) *vcell = vc;
+  return vph;
+}
+
+// Serial form over the whole stencil (host builds): the signed phase volume
+// of flux tet k of face f; with check_stencil, *deficit receives the signed
+// volume of the tet that no stencil cell covers and *gross its unsigned
+// volume.
 VHD double flux_tet_phase(const DMesh &m, const DState &s, const DParams &p, double dt,
                           double sc, int f, int k, Poly &P, unsigned long long &ncap,
                           unsigned long long &npairs, double *deficit, double *gross) {
-    *deficit = 0.0;
-    *gross = 0.0;
-    v3 c, t1, t2, t3;
-    double det, sgn;
-    if (!flux_tet(m, s, dt, sc, f, k, c, t1, t2, t3, det, sgn)) return 0.0;
-    const v3 z = mk3(0, 0, 0);
-    v3 lo = mk3(dmin(dmin(0.0, t1.x), dmin(t2.x, t3.x)), dmin(dmin(0.0, t1.y), dmin(t2.y, t3.y)),
-                dmin(dmin(0.0, t1.z), dmin(t2.z, t3.z)));
-    v3 hi = mk3(dmax(dmax(0.0, t1.x), dmax(t2.x, t3.x)), dmax(dmax(0.0, t1.y), dmax(t2.y, t3.y)),
-                dmax(dmax(0.0, t1.z), dmax(t2.z, t3.z)));
-    lo = lo + c;
-    hi = hi + c;
-    double acc = 0.0, cover = 0.0;
-    for (int e = m.st_off[f]; e < m.st_off[f + 1]; ++e) {
-      int cell = m.st[e];
-      int cl = s.cls[cell];
-      if (cl == 0 && !p.check_stencil) continue;
-      double4 blo = m.bblo[cell], bhi = m.bbhi[cell];
-      if (hi.x <= blo.x || lo.x >= bhi.x || hi.y <= blo.y || lo.y >= bhi.y || hi.z <= blo.z ||
-          lo.z >= bhi.z)
-        continue;
-      // planes of the cell that cut the tet
-      int cuts[kMaxCellPlanes];
-      int ncut = 0;
-      bool outside = false;
-      double dsingle[4];
-      for (int q = m.cf_off[cell]; q < m.cf_off[cell + 1]; ++q) {
-        double4 pl = m.cpl[q];
-        v3 nn = xyz4(pl);
-        double off = pl.w - dot(nn, c);
-        double d0 = off, d1 = off - dot(nn, t1), d2 = off - dot(nn, t2), d3 = off - dot(nn, t3);
-        double dmx = dmax(dmax(d0, d1), dmax(d2, d3));
-        double dmn = dmin(dmin(d0, d1), dmin(d2, d3));
-        if (dmx <= 0.0) { outside = true; break; }
-        if (dmn < 0.0) {
-          if (ncut < kMaxCellPlanes) cuts[ncut] = q;
-          ++ncut;
-          dsingle[0] = d0; dsingle[1] = d1; dsingle[2] = d2; dsingle[3] = d3;
-        }
-      }
-      if (outside) continue;
-      ++npairs;  // a (tet, cell) pair with overlapping interiors
-      double vcell, vph;
-      if (ncut == 0) {
-        vcell = det;
-      } else if (ncut == 1) {
-        vcell = det * tet_kept_fraction(dsingle);
-      } else {
-        vcell = -1.0;
-      }
-      if (cl == 1) {
-        double4 pl = s.plane[cell];
-        v3 nn = xyz4(pl);
-        double off = pl.w - dot(nn, c);
-        if (ncut <= 1) {
-          // at most two planes: closed forms, no polytope
-          const Tet T{z, t1, t2, t3};
-          Pl pc{0, 0, 0, 0};
-          if (ncut == 1) {
-            double4 cp = m.cpl[cuts[0]];
-            pc = mkpl(xyz4(cp), cp.w - dot(xyz4(cp), c));
-          }
-          Pl pp = mkpl(nn, off);
-          vph = ncut == 0 ? vol6_planes2(T, det, pp, pp, 1) : vol6_planes2(T, det, pc, pp, 2);
-        } else {
-          P.init_tet(z, t1, t2, t3);
-          bool ok = true;
-          for (int q = 0; q < ncut && ok; ++q) {
-            double4 cp = m.cpl[cuts[q < kMaxCellPlanes ? q : 0]];
-            ok = P.clip(xyz4(cp), cp.w - dot(xyz4(cp), c));
-          }
-          if (ok && p.check_stencil && vcell < 0.0) {
-            // coverage before the plane cut
-            vcell = P.vol6();
-          }
-          ok = ok && P.clip(nn, off);
-          vph = ok ? P.vol6() : 0.0;
-          if (!ok || ncut > kMaxCellPlanes) ++ncap;
-        }
-      } else if (cl == 0) {
-        vph = 0.0;
-      } else {
-        if (vcell < 0.0 && ncut == 2) {
-          const Tet T{z, t1, t2, t3};
-          double4 c0 = m.cpl[cuts[0]], c1 = m.cpl[cuts[1]];
-          vcell = vol6_planes2(T, det, mkpl(xyz4(c0), c0.w - dot(xyz4(c0), c)),
-                               mkpl(xyz4(c1), c1.w - dot(xyz4(c1), c)), 2);
-        }
-        if (vcell < 0.0) {
-          P.init_tet(z, t1, t2, t3);
-          bool ok = true;
-          for (int q = 0; q < ncut && ok; ++q) {
-            double4 cp = m.cpl[cuts[q < kMaxCellPlanes ? q : 0]];
-            ok = P.clip(xyz4(cp), cp.w - dot(xyz4(cp), c));
-          }
-          vcell = ok ? P.vol6() : 0.0;
-          if (!ok || ncut > kMaxCellPlanes) ++ncap;
-        }
-        vph = (cl == 2) ? vcell : s.alpha[cell] * vcell;
-      }
-      acc += vph;
-      if (p.check_stencil) {
-        if (vcell < 0.0) {
-          P.init_tet(z, t1, t2, t3);
-          bool ok = true;
-          for (int q = 0; q < ncut && ok; ++q) {
-            double4 cp = m.cpl[cuts[q < kMaxCellPlanes ? q : 0]];
-            ok = P.clip(xyz4(cp), cp.w - dot(xyz4(cp), c));
-          }
-          vcell = ok ? P.vol6() : 0.0;
-        }
-        cover += vcell;
-      }
-      if (ncut == 0) break;  // the tet lies inside this cell
-    }
-    if (p.check_stencil) {
-      *deficit = sgn * (det - cover) / 6.0;
-      *gross = det / 6.0;
-    }
-    return sgn * acc / 6.0;
+  *deficit = 0.0;
+  *gross = 0.0;
+  v3 c, t1, t2, t3;
+  double det, sgn;
+  if (!flux_tet(m, s, dt, sc, f, k, c, t1, t2, t3, det, sgn)) return 0.0;
+  const Tet T{mk3(0, 0, 0), t1, t2, t3};
+  v3 lo, hi;
+  tet_bbox(c, t1, t2, t3, lo, hi);
+  double acc = 0.0, cover = 0.0;
+  for (int e = m.st_off[f]; e < m.st_off[f + 1]; ++e) {
+    double vc;
+    acc += pair_phase6(m, s, p, c, T, det, lo, hi, m.st[e], P, ncap, npairs, &vc);
+    cover += vc;
+  }
+  if (p.check_stencil) {
+    *deficit = sgn * (det - cover) / 6.0;
+    *gross = det / 6.0;
+  }
+  return sgn * acc / 6.0;
 }
 
 }  // namespace vof

@@ -30,6 +30,8 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kClipBlock = 64;
+constexpr int kPlaneGrid = 2048;  // blocks of four waves, one interface cell per wave
+static_assert(kMaxCellPlanes * kMaxFacePoints <= 128, "two fan tetrahedra per lane");
 constexpr int kClipCap = 20;  // polytope vertices kept per lane in LDS
 constexpr int kLedgerParts = 256;  // partial sums of the boundary ledger
 
@@ -219,47 +221,71 @@ __global__ __launch_bounds__(kBlock) void k_point_prep(DMesh m, DState s) {
   }
 }
 
-// Fill level of cell c below n.x <= s (coordinates relative to o): sum over
-// the tetrahedra (o, c_f, p_i, p_i+1) of the outward face fans of
-// vol6 * kept fraction.  Also returns the height range of the cell points.
-__device__ double cell_fill6(const DMesh &m, int64_t c, v3 o, v3 n, double s) {
-  double acc = 0.0;
+// Wave-wide reductions.  Every lane receives the same value: at each level of
+// the butterfly partner lanes add the same two operands in swapped order,
+// and floating-point addition is commutative.
+__device__ __forceinline__ double wave_sum_d(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ __forceinline__ double wave_min_d(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = dmin(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ double wave_max_d(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = dmax(v, __shfl_xor(v, o));
+  return v;
+}
+
+// One tetrahedron (o, c_f, p_i, p_i+1) of the outward face fans of a cell,
+// relative to the cell centroid o, with its signed volume times six; empty
+// (v6 = 0) for a slot beyond the cell's fan.
+struct FanTet {
+  v3 cf, pa, pb;
+  double v6;
+};
+
+__device__ FanTet fan_tet(const DMesh &m, int64_t c, v3 o, int slot) {
+  FanTet t{mk3(0, 0, 0), mk3(0, 0, 0), mk3(0, 0, 0), 0.0};
+  int acc = 0;
   for (int k = m.cf_off[c]; k < m.cf_off[c + 1]; ++k) {
     int sf = m.cf[k];
     int f = sf >= 0 ? sf : ~sf;
-    double sg = sf >= 0 ? 1.0 : -1.0;
-    v3 cf = xyz(m.C[f]) - o;
-    double hc = dot(n, cf);
     int b = m.foff[f], nn = m.foff[f + 1] - b;
-    v3 p0 = xyz(m.X[m.fpts[b]]) - o;
-    v3 pa = p0;
-    double ha = dot(n, pa);
-    for (int i = 0; i < nn; ++i) {
-      v3 pb = (i + 1 == nn) ? p0 : xyz(m.X[m.fpts[b + i + 1]]) - o;
-      double hb = dot(n, pb);
-      double v6 = sg * det3(cf, pa, pb);
-      double d[4] = {s, s - hc, s - ha, s - hb};
-      acc += v6 * tet_kept_fraction(d);
-      pa = pb;
-      ha = hb;
+    if (slot >= acc && slot < acc + nn) {
+      int i = slot - acc;
+      int i1 = (i + 1 == nn) ? 0 : i + 1;
+      t.cf = xyz(m.C[f]) - o;
+      t.pa = xyz(m.X[m.fpts[b + i]]) - o;
+      t.pb = xyz(m.X[m.fpts[b + i1]]) - o;
+      t.v6 = (sf >= 0 ? 1.0 : -1.0) * det3(t.cf, t.pa, t.pb);
     }
+    acc += nn;
   }
-  return acc;
+  return t;
 }
 
-// NAG gradient (eqs. 2.8-2.12) and plane positioning (Section 2.2.2):
-// the fill level g(s) = |C ∩ {n.x <= s}| / |C| - alpha is monotone between
-// the lowest and highest cell points; it is solved by regula falsi with the
-// Illinois modification, which keeps a bracket and converges superlinearly.
+// NAG gradient (eqs. 2.8-2.12) and plane positioning (Section 2.2.2), one
+// wave per interface cell.  The fill level g(s) = |C ∩ {n.x <= s}| / |C| -
+// alpha is monotone between the lowest and highest cell points; it is solved
+// by regula falsi with the Illinois modification, which keeps a bracket and
+// converges superlinearly.  Each evaluation sums vol6 * kept fraction over
+// the fan tetrahedra of the cell, two per lane (at most 16 faces of at most
+// 8 points), so every decision of the iteration is wave-uniform.
 __global__ __launch_bounds__(kBlock) void k_plane(DMesh m, DState s, DParams p) {
   const int count = s.work[kWInterface];
+  const int lane = lane_id();
+  const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int nwaves = (int)((gridDim.x * blockDim.x) >> 6);
   unsigned long long nfall = 0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
-    int64_t c = s.icells[i];
-    double a = s.alpha[c];
-    v3 g = mk3(0, 0, 0);
-    for (int k = m.cf_off[c]; k < m.cf_off[c + 1]; ++k) {
-      int sf = m.cf[k];
+  for (int i = wave; i < count; i += nwaves) {
+    const int64_t c = s.icells[i];
+    const double a = s.alpha[c];
+    const int k0 = m.cf_off[c], nfc = m.cf_off[c + 1] - k0;
+    // gradient: lanes over the faces of the cell
+    v3 gl = mk3(0, 0, 0);
+    if (lane < nfc) {
+      int sf = m.cf[k0 + lane];
       int f = sf >= 0 ? sf : ~sf;
       double sg = sf >= 0 ? 1.0 : -1.0;
       int b = m.foff[f], nn = m.foff[f + 1] - b;
@@ -268,48 +294,49 @@ __global__ __launch_bounds__(kBlock) void k_plane(DMesh m, DState s, DParams p) 
       fp /= nn;
       v3 cf = xyz(m.C[f]);
       double num = 0.0, den = 0.0;
-      int q0 = m.fpts[b];
-      int qa = q0;
+      int qa = m.fpts[b];
       for (int j = 0; j < nn; ++j) {
-        int qb = (j + 1 == nn) ? q0 : m.fpts[b + j + 1];
+        int qb = m.fpts[b + ((j + 1 == nn) ? 0 : j + 1)];
         v3 t = cross(xyz(m.X[qa]) - cf, xyz(m.X[qb]) - cf);
         double A = 0.5 * sqrt(dot(t, t));
         num += A * (fp + s.alpha_p[qa] + s.alpha_p[qb]) / 3.0;
         den += A;
         qa = qb;
       }
-      double af = num / den;
-      g = g + (sg * af) * xyz(m.S[f]);
+      gl = (sg * (num / den)) * xyz(m.S[f]);
     }
-    double Vc = m.V[c];
-    g = (1.0 / Vc) * g;
+    const double Vc = m.V[c];
+    v3 g = (1.0 / Vc) * mk3(wave_sum_d(gl.x), wave_sum_d(gl.y), wave_sum_d(gl.z));
     double gn = sqrt(dot(g, g));
     if (!(gn * cbrt(Vc) >= p.grad_zero)) {
-      s.cls[c] = 3;
-      s.plane[c] = make_double4(0.0, 0.0, 0.0, 0.0);
-      ++nfall;
+      if (lane == 0) {
+        s.cls[c] = 3;
+        s.plane[c] = make_double4(0.0, 0.0, 0.0, 0.0);
+        ++nfall;
+      }
       continue;
     }
-    v3 n = (-1.0 / gn) * g;
-    v3 o = xyz(m.XC[c]);
-    double hmin = 1e300, hmax = -1e300;
-    for (int k = m.cf_off[c]; k < m.cf_off[c + 1]; ++k) {
-      int sf = m.cf[k];
-      int f = sf >= 0 ? sf : ~sf;
-      for (int j = m.foff[f]; j < m.foff[f + 1]; ++j) {
-        double h = dot(n, xyz(m.X[m.fpts[j]]) - o);
-        hmin = dmin(hmin, h);
-        hmax = dmax(hmax, h);
-      }
-    }
-    double tot6 = cell_fill6(m, c, o, n, hmax);
+    const v3 n = (-1.0 / gn) * g;
+    const v3 o = xyz(m.XC[c]);
+    // fan tetrahedra as heights along n
+    FanTet t0 = fan_tet(m, c, o, lane), t1 = fan_tet(m, c, o, lane + 64);
+    const double hc0 = dot(n, t0.cf), ha0 = dot(n, t0.pa), hb0 = dot(n, t0.pb);
+    const double hc1 = dot(n, t1.cf), ha1 = dot(n, t1.pa), hb1 = dot(n, t1.pb);
+    // the points of the cell are the p_i of its fans
+    double hmin = t0.v6 != 0.0 ? ha0 : 1e300, hmax = t0.v6 != 0.0 ? ha0 : -1e300;
+    if (t1.v6 != 0.0) { hmin = dmin(hmin, ha1); hmax = dmax(hmax, ha1); }
+    hmin = wave_min_d(hmin);
+    hmax = wave_max_d(hmax);
+    const double tot6 = wave_sum_d(t0.v6 + t1.v6);
     double lo = hmin, glo = -a, hi = hmax, ghi = 1.0 - a;
     double sx = 0.5 * (lo + hi);
     int side = 0;
     for (int it = 0; it < p.pos_max_iter; ++it) {
       double sn = hi - ghi * (hi - lo) / (ghi - glo);
       if (!(sn > lo && sn < hi)) sn = 0.5 * (lo + hi);
-      double gs = cell_fill6(m, c, o, n, sn) / tot6 - a;
+      double f0 = t0.v6 * tet_kept_fraction(D4{sn, sn - hc0, sn - ha0, sn - hb0});
+      double f1 = t1.v6 * tet_kept_fraction(D4{sn, sn - hc1, sn - ha1, sn - hb1});
+      double gs = wave_sum_d(f0 + f1) / tot6 - a;
       sx = sn;
       if (fabs(gs) <= p.pos_tol) break;
       if (gs < 0.0) {
@@ -323,7 +350,7 @@ __global__ __launch_bounds__(kBlock) void k_plane(DMesh m, DState s, DParams p) 
       }
       if (hi - lo <= 2e-16 * (hmax - hmin)) break;
     }
-    s.plane[c] = make_double4(n.x, n.y, n.z, sx + dot(n, o));
+    if (lane == 0) s.plane[c] = make_double4(n.x, n.y, n.z, sx + dot(n, o));
   }
   wave_count(&s.cnt[kCntFallback], nfall);
 }
@@ -538,36 +565,58 @@ __global__ __launch_bounds__(kBlock) void k_clip_fast(DMesh m, DState s, DParams
   wave_count(&s.cnt[kCntPairs], npairs);
 }
 
-// General clip of the queued tets: vertex-graph polytopes in LDS.
+// General clip of the queued tets, one wave per tet with the lanes over the
+// face's stencil cells: closed forms up to three planes per pair, beyond
+// that a vertex-graph polytope in LDS per lane.  Pair volumes are summed by
+// the wave butterfly (the same order on every run).
 __global__ __launch_bounds__(kClipBlock) void k_clip_general(DMesh m, DState s, DParams p,
                                                              int step) {
   __shared__ double lx[kClipCap * kClipBlock], ly[kClipCap * kClipBlock],
       lz[kClipCap * kClipBlock], ld[kClipCap * kClipBlock];
   __shared__ uint8_t lnb[3 * kClipCap * kClipBlock], laux[kClipCap * kClipBlock];
-  const int tid = threadIdx.x;
+  static_assert(kClipBlock == 64, "one wave per block");
+  const int lane = threadIdx.x;
   Poly P;
-  P.px = lx + tid; P.py = ly + tid; P.pz = lz + tid; P.ps = ld + tid;
-  P.nb = lnb + tid; P.aux = laux + tid;
+  P.px = lx + lane; P.py = ly + lane; P.pz = lz + lane; P.ps = ld + lane;
+  P.nb = lnb + lane; P.aux = laux + lane;
   P.st = kClipBlock; P.cap = kClipCap; P.nv = 0;
 
   const double dt = s.dt[step], sc = s.sc[step];
   const int count = s.work[kWDeferred];
   unsigned long long ncap = 0, npairs = 0;
-  for (int i = blockIdx.x * blockDim.x + tid; i < count; i += gridDim.x * blockDim.x) {
+  for (int i = blockIdx.x; i < count; i += gridDim.x) {
     const int64_t idx = s.defer[i];
-    int slot = (int)(idx / m.tpf);
-    int k = (int)(idx - (int64_t)slot * m.tpf);
-    double deficit, gross;
-    s.tetvol[idx] = flux_tet_phase(m, s, p, dt, sc, s.gfaces[slot], k, P, ncap, npairs, &deficit,
-                                   &gross);
-    if (p.check_stencil) {
-      s.tetdef[idx] = deficit;
-      s.tetgross[idx] = gross;
+    const int slot = (int)(idx / m.tpf);
+    const int k = (int)(idx - (int64_t)slot * m.tpf);
+    const int f = s.gfaces[slot];
+    v3 c, t1, t2, t3;
+    double det, sgn;
+    double acc = 0.0, cover = 0.0;
+    const bool live = flux_tet(m, s, dt, sc, f, k, c, t1, t2, t3, det, sgn);  // wave-uniform
+    if (live) {
+      const Tet T{mk3(0, 0, 0), t1, t2, t3};
+      v3 lo, hi;
+      tet_bbox(c, t1, t2, t3, lo, hi);
+      double a = 0.0, cv = 0.0;
+      for (int e = m.st_off[f] + lane; e < m.st_off[f + 1]; e += 64) {
+        double vc;
+        a += pair_phase6(m, s, p, c, T, det, lo, hi, m.st[e], P, ncap, npairs, &vc);
+        cv += vc;
+      }
+      acc = wave_sum_d(a);
+      cover = wave_sum_d(cv);
+    }
+    if (lane == 0) {
+      s.tetvol[idx] = live ? sgn * acc / 6.0 : 0.0;
+      if (p.check_stencil) {
+        s.tetdef[idx] = live ? sgn * (det - cover) / 6.0 : 0.0;
+        s.tetgross[idx] = live ? det / 6.0 : 0.0;
+      }
     }
   }
   wave_count(&s.cnt[kCntCapacity], ncap);
   wave_count(&s.cnt[kCntPairs], npairs);
-  if (__ballot(ncap != 0) && lane_id() == 0) flag(s.flags, kFlagCapacity);
+  if (__ballot(ncap != 0) && lane == 0) flag(s.flags, kFlagCapacity);
 }
 
 // Sum of the tets of each geometric face.  With check_stencil: the uncovered
@@ -705,8 +754,7 @@ static void launch_reconstruct_impl(const DMesh &m, const DState &s, const DPara
                                     hipStream_t st) {
   k_cell_class<<<grid_for(m.nc, kBlock), kBlock, 0, st>>>(m, s, p);
   k_point_prep<<<grid_for(m.np, kBlock), kBlock, 0, st>>>(m, s);
-  unsigned g = grid_for(m.nc, kBlock);
-  k_plane<<<g < 2048 ? (g ? g : 1) : 2048, kBlock, 0, st>>>(m, s, p);
+  k_plane<<<kPlaneGrid, kBlock, 0, st>>>(m, s, p);
 }
 
 void launch_reconstruct(const DMesh &m, const DState &s, const DParams &p, hipStream_t st) {
@@ -739,9 +787,7 @@ void launch_step(const DMesh &m, const DState &s, const DParams &p, int step, hi
   TIMED(prof, kKReset, (k_reset<<<1, 64, 0, st>>>(s)));
   TIMED(prof, kKCellClass, (k_cell_class<<<grid_for(m.nc, kBlock), kBlock, 0, st>>>(m, s, p)));
   TIMED(prof, kKPointPrep, (k_point_prep<<<grid_for(m.np, kBlock), kBlock, 0, st>>>(m, s)));
-  unsigned gp = grid_for(m.nc, kBlock);
-  gp = gp < 2048 ? (gp ? gp : 1) : 2048;
-  TIMED(prof, kKPlane, (k_plane<<<gp, kBlock, 0, st>>>(m, s, p)));
+  TIMED(prof, kKPlane, (k_plane<<<kPlaneGrid, kBlock, 0, st>>>(m, s, p)));
   // persistent-style grid: a few blocks per CU, grid-stride over the faces
   unsigned gf = grid_for(m.nf, kBlock);
   gf = gf < 8192 ? gf : 8192;
@@ -752,7 +798,7 @@ void launch_step(const DMesh &m, const DState &s, const DParams &p, int step, hi
   else
     TIMED(prof, kKFlux, (k_flux<kMaxFacePoints><<<gf, kBlock, 0, st>>>(m, s, p, step)));
   TIMED(prof, kKClip, (k_clip_fast<<<4096, kBlock, 0, st>>>(m, s, p, step)));
-  TIMED(prof, kKClipGeneral, (k_clip_general<<<1024, kClipBlock, 0, st>>>(m, s, p, step)));
+  TIMED(prof, kKClipGeneral, (k_clip_general<<<4096, kClipBlock, 0, st>>>(m, s, p, step)));
   TIMED(prof, kKFaceSum, (k_face_sum<<<1024, kBlock, 0, st>>>(m, s, p)));
   TIMED(prof, kKUpdate, (k_update<<<grid_for(m.nc, kBlock), kBlock, 0, st>>>(m, s)));
   TIMED(prof, kKLedger, (k_ledger_part<<<kLedgerParts, kBlock, 0, st>>>(m, s),
