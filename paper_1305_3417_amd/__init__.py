@@ -44,7 +44,7 @@ EXPORTED = [
     "vof_set_params", "vof_set_alpha", "vof_read_alpha", "vof_set_velocity",
     "vof_reconstruct", "vof_advect", "vof_read_face", "vof_read_planes",
     "vof_read_point_velocity", "vof_get_stats", "vof_reset_stats", "vof_synchronize",
-    "vof_selftest_tet_clip", "vof_profile_enable", "vof_profile_kernel_name", "vof_read_profile",
+    "vof_selftest_tet_clip", "vof_selftest_tet_clip_closed", "vof_profile_enable", "vof_profile_kernel_name", "vof_read_profile",
 ]
 
 
@@ -123,6 +123,7 @@ def lib():
             "vof_reset_stats": (i32, [vp]),
             "vof_synchronize": (i32, [vp]),
             "vof_selftest_tet_clip": (d, [vp, i32, vp]),
+            "vof_selftest_tet_clip_closed": (d, [vp, i32, vp]),
             "vof_profile_enable": (i32, [vp, i32]),
             "vof_profile_kernel_name": (C.c_char_p, [i32]),
             "vof_read_profile": (i32, [vp, vp, vp, i32]),
@@ -365,13 +366,21 @@ def vof_synchronize(mesh: MeshHandle, ok=(VOF_OK,)):
     return _check(lib().vof_synchronize(mesh.h), "vof_synchronize", ok)
 
 
-def vof_selftest_tet_clip(tet, planes) -> float:
+def _selftest(fn, tet, planes) -> float:
     tet = np.ascontiguousarray(tet, dtype=np.float64).reshape(12)
     planes = np.ascontiguousarray(np.atleast_2d(planes), dtype=np.float64)
     if planes.size == 0:
         planes = np.zeros((0, 4))
-    return lib().vof_selftest_tet_clip(tet.ctypes.data_as(C.c_void_p), int(planes.shape[0]),
-                                       planes.ctypes.data_as(C.c_void_p))
+    return fn(tet.ctypes.data_as(C.c_void_p), int(planes.shape[0]),
+              planes.ctypes.data_as(C.c_void_p))
+
+
+def vof_selftest_tet_clip(tet, planes) -> float:
+    return _selftest(lib().vof_selftest_tet_clip, tet, planes)
+
+
+def vof_selftest_tet_clip_closed(tet, planes) -> float:
+    return _selftest(lib().vof_selftest_tet_clip_closed, tet, planes)
 
 
 def vof_profile_enable(mesh: MeshHandle, enable: bool = True):

@@ -75,11 +75,62 @@ VHD bool flux_tet(const DMesh &m, const DState &s, double dt, double sc, int f, 
   return true;
 }
 
-// Register-only phase volume of flux tet k of face f: every overlapping
-// stencil cell contributes |T ∩ C ∩ H| through at most three planes (the
-// cell planes that cut the tet, and the PLIC plane of an interface cell).
-// Returns false ("deferred") when a pair needs more planes; the tet is then
-// left to flux_tet_phase.
+// Planes bounding the phase region of a (tet, cell) pair on the register
+// path: the cell planes that cut the tet, then the PLIC plane of an
+// interface cell; the first three go to p0..p2 with offsets relative to the
+// tet's apex c.  Returns their number, or -1 when the pair contributes
+// nothing (an empty cell, bounding boxes apart, or the tet outside one of
+// the cell's planes); ncut receives the number of cutting cell planes.
+VHD int pair_planes(const DMesh &m, const DState &s, v3 c, const Tet &T, v3 lo, v3 hi, int cell,
+                    int cl, Pl &p0, Pl &p1, Pl &p2, int &ncut) {
+  ncut = 0;
+  if (cl == 0) return -1;
+  double4 blo = m.bblo[cell], bhi = m.bbhi[cell];
+  if (hi.x <= blo.x || lo.x >= bhi.x || hi.y <= blo.y || lo.y >= bhi.y || hi.z <= blo.z ||
+      lo.z >= bhi.z)
+    return -1;
+  p0 = Pl{0, 0, 0, 0};
+  p1 = p0;
+  p2 = p0;
+  int n = 0;
+  for (int q = m.cf_off[cell]; q < m.cf_off[cell + 1]; ++q) {
+    double4 cp = m.cpl[q];
+    v3 nn = xyz4(cp);
+    double off = cp.w - dot(nn, c);
+    double d1 = off - dot(nn, T.b), d2 = off - dot(nn, T.c), d3 = off - dot(nn, T.d);
+    double dmx = dmax(dmax(off, d1), dmax(d2, d3));
+    double dmn = dmin(dmin(off, d1), dmin(d2, d3));
+    if (dmx <= 0.0) return -1;
+    if (dmn < 0.0) {
+      Pl pn = mkpl(nn, off);
+      p2 = sel(n == 2, pn, p2);
+      p1 = sel(n == 1, pn, p1);
+      p0 = sel(n == 0, pn, p0);
+      ++n;
+    }
+  }
+  ncut = n;
+  if (cl == 1) {
+    double4 pp = s.plane[cell];
+    v3 nn = xyz4(pp);
+    Pl pn = mkpl(nn, pp.w - dot(nn, c));
+    p2 = sel(n == 2, pn, p2);
+    p1 = sel(n == 1, pn, p1);
+    p0 = sel(n == 0, pn, p0);
+    ++n;
+  }
+  return n;
+}
+
+// weight of a covered volume in the phase region of a full (2) or
+// vanishing-gradient (3) cell; interface cells carry it in their plane
+VHD double class_weight(const DState &s, int cell, int cl) {
+  return cl == 3 ? s.alpha[cell] : 1.0;
+}
+
+// Register-only phase volume of flux tet k of face f (serial over the
+// stencil): every overlapping stencil cell contributes |T ∩ C ∩ H| through
+// at most three planes.  Returns false ("deferred") when a pair needs more.
 VHD bool flux_tet_phase_fast(const DMesh &m, const DState &s, double dt, double sc, int f,
                              int k, double &vol, unsigned long long &npairs) {
   vol = 0.0;
@@ -92,50 +143,15 @@ VHD bool flux_tet_phase_fast(const DMesh &m, const DState &s, double dt, double 
   double acc = 0.0;
   unsigned long long np = 0;
   for (int e = m.st_off[f]; e < m.st_off[f + 1]; ++e) {
-    int cell = m.st[e];
-    int cl = s.cls[cell];
-    if (cl == 0) continue;
-    double4 blo = m.bblo[cell], bhi = m.bbhi[cell];
-    if (hi.x <= blo.x || lo.x >= bhi.x || hi.y <= blo.y || lo.y >= bhi.y || hi.z <= blo.z ||
-        lo.z >= bhi.z)
-      continue;
-    // cutting planes in registers p0..p2 (the PLIC plane of an interface
-    // cell takes the last slot)
-    Pl p0{0, 0, 0, 0}, p1 = p0, p2 = p0;
-    const int room = (cl == 1) ? 2 : 3;
-    int ncut = 0;
-    bool outside = false;
-    for (int q = m.cf_off[cell]; q < m.cf_off[cell + 1]; ++q) {
-      double4 cp = m.cpl[q];
-      v3 nn = xyz4(cp);
-      double off = cp.w - dot(nn, c);
-      double d1 = off - dot(nn, t1), d2 = off - dot(nn, t2), d3 = off - dot(nn, t3);
-      double dmx = dmax(dmax(off, d1), dmax(d2, d3));
-      double dmn = dmin(dmin(off, d1), dmin(d2, d3));
-      if (dmx <= 0.0) { outside = true; break; }
-      if (dmn < 0.0) {
-        Pl pn = mkpl(nn, off);
-        p2 = sel(ncut == 2, pn, p2);
-        p1 = sel(ncut == 1, pn, p1);
-        p0 = sel(ncut == 0, pn, p0);
-        ++ncut;
-      }
-    }
-    if (outside) continue;
-    if (ncut > room) return false;
+    const int cell = m.st[e];
+    const int cl = s.cls[cell];
+    Pl p0, p1, p2;
+    int ncut;
+    const int npl = pair_planes(m, s, c, T, lo, hi, cell, cl, p0, p1, p2, ncut);
+    if (npl < 0) continue;
+    if (npl > 3) return false;
     ++np;
-    int npl = ncut;
-    if (cl == 1) {
-      double4 pp = s.plane[cell];
-      v3 nn = xyz4(pp);
-      Pl pn = mkpl(nn, pp.w - dot(nn, c));
-      p2 = sel(npl == 2, pn, p2);
-      p1 = sel(npl == 1, pn, p1);
-      p0 = sel(npl == 0, pn, p0);
-      ++npl;
-    }
-    double v = vol6_planes3(T, det, p0, p1, p2, npl);
-    acc += (cl == 3) ? s.alpha[cell] * v : v;
+    acc += class_weight(s, cell, cl) * vol6_planes3(T, det, p0, p1, p2, npl);
     if (ncut == 0) break;  // the tet lies inside this cell
   }
   npairs += np;

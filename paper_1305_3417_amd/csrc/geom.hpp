@@ -60,15 +60,6 @@ VHD v3 sel(bool c, v3 a, v3 b) {
   return v3{c ? a.x : b.x, c ? a.y : b.y, c ? a.z : b.z};
 }
 
-VHD void cswap_kept(v3 &x, v3 &y, double &dx, double &dy) {
-  bool sw = !(dx >= 0.0) && (dy >= 0.0);
-  v3 tx = x;
-  double tdx = dx;
-  x = sel(sw, y, x);
-  dx = sw ? dy : dx;
-  y = sel(sw, tx, y);
-  dy = sw ? tdx : dy;
-}
 VHD void cswap_kept(double &dx, double &dy) {
   bool sw = !(dx >= 0.0) && (dy >= 0.0);
   double t = dx;
@@ -77,13 +68,6 @@ VHD void cswap_kept(double &dx, double &dy) {
 }
 
 // kept vertices first (order among kept / among removed is immaterial)
-VHD void sort_kept(Tet &t, D4 &d) {
-  cswap_kept(t.a, t.b, d.a, d.b);
-  cswap_kept(t.c, t.d, d.c, d.d);
-  cswap_kept(t.a, t.c, d.a, d.c);
-  cswap_kept(t.b, t.d, d.b, d.d);
-  cswap_kept(t.b, t.c, d.b, d.c);
-}
 VHD void sort_kept(D4 &d) {
   cswap_kept(d.a, d.b);
   cswap_kept(d.c, d.d);
@@ -121,39 +105,129 @@ VHD double tet_kept_fraction(const double dd[4]) {
 // ---------------------------------------------------------------------------
 // register-only clipping of a tetrahedron by a few planes
 // ---------------------------------------------------------------------------
-// The part of a tetrahedron on the kept side (d >= 0) of one plane is 0, 1 or
-// 3 tetrahedra: one kept vertex a -> (a, ab, ac, ad); three kept (d removed)
-// -> the prism a b c | ad bd cd as three tets; two kept (a, b) -> the prism
-// a ac ad | b bc bd as three tets.  xy is the cut point on edge x -> y.
-VHD int kept_piece_count(const D4 &d) {
-  int k = kept_count(d);
-  return k == 4 ? 1 : (k == 0 ? 0 : (k == 1 ? 1 : 3));
+// The part of a tetrahedron T on the kept side (d >= 0) of one plane is one
+// or three tetrahedra whose vertices are vertices of T or cut points xy on
+// edges x -> y (x kept, y removed) at parameter t_xy = d_x / (d_x - d_y).
+// With the vertices sorted kept-first the pieces are consecutive windows of
+// four in one sequence:
+//   kept 1 (a):     [a, ab, ac, ad]            ratio t_ab t_ac t_ad
+//   kept 2 (a, b):  [a, ac, ad, b, bc, bd]     ratios t_ac t_ad, t_ad t_bc (1 - t_ac),
+//                                                      t_bc t_bd (1 - t_ad)
+//   kept 3 (a,b,c): [a, b, c, ad, bd, cd]      ratios t_ad, (1 - t_ad) t_bd,
+//                                                      (1 - t_ad)(1 - t_bd) t_cd
+//   kept 4:         [a, b, c, d]               ratio 1
+// where the ratio of a piece is its volume over |T| (the determinant of the
+// barycentric coordinates of its vertices).  A cut point's signed distances
+// to the other planes interpolate those of its edge's ends, so clipping by
+// several planes needs only the 4 x K matrix of vertex distances: |T ∩ H_0
+// ∩ ... ∩ H_K-1| = |T| * sum over pieces of ratio * (fraction of the piece
+// kept by the remaining planes).
+
+// signed distances of one vertex to the K planes still to apply
+template <int K>
+struct VD {
+  double d[K];
+};
+template <int K>
+struct TD {
+  VD<K> a, b, c, e;
+};
+
+template <int K>
+VHD VD<K> sel(bool c, const VD<K> &x, const VD<K> &y) {
+  VD<K> r;
+#pragma unroll
+  for (int k = 0; k < K; ++k) r.d[k] = c ? x.d[k] : y.d[k];
+  return r;
 }
 
-VHD v3 cut_point(v3 x, v3 y, double dx, double dy) {
-  double t = dx / (dx - dy);
-  return x + t * (y - x);
+// distances to planes 1..K-1 of the cut point on edge x -> y
+template <int K>
+VHD VD<K - 1> cut_rest(const VD<K> &x, const VD<K> &y, double t) {
+  VD<K - 1> r;
+#pragma unroll
+  for (int k = 1; k < K; ++k) r.d[k - 1] = x.d[k] + t * (y.d[k] - x.d[k]);
+  return r;
+}
+template <int K>
+VHD VD<K - 1> rest(const VD<K> &x) {
+  VD<K - 1> r;
+#pragma unroll
+  for (int k = 1; k < K; ++k) r.d[k - 1] = x.d[k];
+  return r;
 }
 
-// piece-th tetrahedron of the kept part; t and d must be sorted (sort_kept)
-VHD Tet kept_piece_sorted(const Tet &t, const D4 &d, int kept, int piece) {
-  if (kept == 4) return t;
-  if (kept == 1)
-    return Tet{t.a, cut_point(t.a, t.b, d.a, d.b), cut_point(t.a, t.c, d.a, d.c),
-               cut_point(t.a, t.d, d.a, d.d)};
-  if (kept == 3) {
-    v3 ad = cut_point(t.a, t.d, d.a, d.d);
-    v3 bd = cut_point(t.b, t.d, d.b, d.d);
-    if (piece == 0) return Tet{t.a, t.b, t.c, ad};
-    if (piece == 1) return Tet{t.b, t.c, ad, bd};
-    return Tet{t.c, ad, bd, cut_point(t.c, t.d, d.c, d.d)};
+template <int K>
+VHD void cswap_kept(VD<K> &x, VD<K> &y) {
+  bool sw = !(x.d[0] >= 0.0) && (y.d[0] >= 0.0);
+  VD<K> t = x;
+  x = sel(sw, y, x);
+  y = sel(sw, t, y);
+}
+
+// edge parameter of the cut on x -> y for plane 0 (x kept, y removed; 0
+// when unused)
+template <int K>
+VHD double tcut(const VD<K> &x, const VD<K> &y) {
+  double den = x.d[0] - y.d[0];
+  return den > 0.0 ? x.d[0] / den : 0.0;
+}
+
+// fraction of a tetrahedron kept by all K planes, from its vertex distances
+template <int K>
+VHD double kept_fraction(TD<K> T);
+
+template <>
+VHD double kept_fraction<1>(TD<1> T) {
+  return tet_kept_fraction(D4{T.a.d[0], T.b.d[0], T.c.d[0], T.e.d[0]});
+}
+
+template <int K>
+VHD double kept_fraction(TD<K> T) {
+  const int kept = (T.a.d[0] >= 0.0) + (T.b.d[0] >= 0.0) + (T.c.d[0] >= 0.0) +
+                   (T.e.d[0] >= 0.0);
+  if (kept == 0) return 0.0;
+  cswap_kept(T.a, T.b);
+  cswap_kept(T.c, T.e);
+  cswap_kept(T.a, T.c);
+  cswap_kept(T.b, T.e);
+  cswap_kept(T.b, T.c);
+  const bool k1 = kept == 1, k2 = kept == 2, k3 = kept == 3, k4 = kept == 4;
+  // the four cut points any case needs: A = ad, B = ab | ac, C = ac | bc | bd,
+  // D = bd | cd (for kept 1 | 2 | 3)
+  const double tA = tcut(T.a, T.e);
+  const VD<K> Bto = sel(k1, T.b, T.c);
+  const double tB = tcut(T.a, Bto);
+  const VD<K> Cfrom = sel(k1, T.a, T.b);
+  const VD<K> Cto = sel(k3, T.e, T.c);
+  const double tC = tcut(Cfrom, Cto);
+  const VD<K> Dfrom = sel(k3, T.c, T.b);
+  const double tD = tcut(Dfrom, T.e);
+  const VD<K - 1> A = cut_rest(T.a, T.e, tA);
+  const VD<K - 1> B = cut_rest(T.a, Bto, tB);
+  const VD<K - 1> C = cut_rest(Cfrom, Cto, tC);
+  const VD<K - 1> D = cut_rest(Dfrom, T.e, tD);
+  const VD<K - 1> ra = rest(T.a), rb = rest(T.b), rc = rest(T.c), re = rest(T.e);
+  // the sequence of piece vertices
+  const VD<K - 1> S0 = ra;
+  const VD<K - 1> S1 = sel(k3 || k4, rb, B);
+  const VD<K - 1> S2 = sel(k1, C, sel(k2, A, rc));
+  const VD<K - 1> S3 = sel(k2, rb, sel(k4, re, A));
+  const VD<K - 1> S4 = C;
+  const VD<K - 1> S5 = D;
+  const double r0 = k4 ? 1.0 : (k1 ? tB * tC * tA : (k2 ? tB * tA : tA));
+  const double r1 = k2 ? tA * tC * (1.0 - tB) : (1.0 - tA) * tC;
+  const double r2 = k2 ? tC * tD * (1.0 - tA) : (1.0 - tA) * (1.0 - tC) * tD;
+  const int n = (k1 || k4) ? 1 : 3;
+  double acc = 0.0;
+#pragma unroll 1
+  for (int i = 0; i < n; ++i) {
+    TD<K - 1> P{sel(i == 0, S0, sel(i == 1, S1, S2)), sel(i == 0, S1, sel(i == 1, S2, S3)),
+                sel(i == 0, S2, sel(i == 1, S3, S4)), sel(i == 0, S3, sel(i == 1, S4, S5))};
+    const double r = i == 0 ? r0 : (i == 1 ? r1 : r2);
+    acc += r * kept_fraction<K - 1>(P);
   }
-  v3 ac = cut_point(t.a, t.c, d.a, d.c);
-  v3 ad = cut_point(t.a, t.d, d.a, d.d);
-  v3 bc = cut_point(t.b, t.c, d.b, d.c);
-  if (piece == 0) return Tet{t.a, ac, ad, t.b};
-  if (piece == 1) return Tet{ac, ad, t.b, bc};
-  return Tet{ad, t.b, bc, cut_point(t.b, t.d, d.b, d.d)};
+  return acc;
 }
 
 // A plane n.x = s as four plain doubles (plain aggregates stay in registers
@@ -172,47 +246,19 @@ VHD D4 plane_dists(const Tet &t, Pl pl) {
   return D4{pl.w - dot(n, t.a), pl.w - dot(n, t.b), pl.w - dot(n, t.c), pl.w - dot(n, t.d)};
 }
 
-VHD double abs_vol6(const Tet &t) {
-  double v = det3(t.b - t.a, t.c - t.a, t.d - t.a);
-  return v < 0.0 ? -v : v;
-}
-
-// six times |T ∩ {n_j.x <= s_j, j < k}| for k <= 2 planes: the kept part of
-// the first plane as at most three tetrahedra, each with the closed-form
-// fraction for the second plane
-VHD double vol6_planes2(Tet T, double vol6, Pl p0, Pl p1, int k) {
+// six times |T ∩ {n_j.x <= s_j, j < k}| for k <= 3 planes, T positively
+// ordered with six times its volume vol6
+VHD double vol6_planes3(const Tet &T, double vol6, Pl p0, Pl p1, Pl p2, int k) {
   if (k == 0) return vol6;
-  D4 d0 = plane_dists(T, p0);
+  const D4 d0 = plane_dists(T, p0);
   if (k == 1) return vol6 * tet_kept_fraction(d0);
-  const int kept = kept_count(d0);
-  const int n1 = kept == 4 ? 1 : (kept == 0 ? 0 : (kept == 1 ? 1 : 3));
-  if (n1 == 0) return 0.0;
-  sort_kept(T, d0);
-  double acc = 0.0;
-  for (int i1 = 0; i1 < n1; ++i1) {
-    Tet T1 = kept_piece_sorted(T, d0, kept, i1);
-    acc += abs_vol6(T1) * tet_kept_fraction(plane_dists(T1, p1));
-  }
-  return acc;
-}
-
-// six times |T ∩ {n_j.x <= s_j, j < k}| for k <= 3 planes: the kept part of
-// the first plane as at most three tetrahedra, each through the two-plane
-// form above
-VHD double vol6_planes3(Tet T, double vol6, Pl p0, Pl p1, Pl p2, int k) {
-  if (k <= 2) return vol6_planes2(T, vol6, p0, p1, k);
-  D4 d0 = plane_dists(T, p0);
-  const int kept = kept_count(d0);
-  if (kept == 0) return 0.0;
-  if (kept == 4) return vol6_planes2(T, vol6, p1, p2, 2);
-  const int n1 = kept == 1 ? 1 : 3;
-  sort_kept(T, d0);
-  double acc = 0.0;
-  for (int i1 = 0; i1 < n1; ++i1) {
-    Tet T1 = kept_piece_sorted(T, d0, kept, i1);
-    acc += vol6_planes2(T1, abs_vol6(T1), p1, p2, 2);
-  }
-  return acc;
+  const D4 d1 = plane_dists(T, p1);
+  if (k == 2)
+    return vol6 * kept_fraction<2>(TD<2>{{{d0.a, d1.a}}, {{d0.b, d1.b}}, {{d0.c, d1.c}},
+                                         {{d0.d, d1.d}}});
+  const D4 d2 = plane_dists(T, p2);
+  return vol6 * kept_fraction<3>(TD<3>{{{d0.a, d1.a, d2.a}}, {{d0.b, d1.b, d2.b}},
+                                       {{d0.c, d1.c, d2.c}}, {{d0.d, d1.d, d2.d}}});
 }
 
 // ---------------------------------------------------------------------------

@@ -30,6 +30,9 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kClipBlock = 64;
+constexpr int kFastBlock = 64;   // one wave per block in the register clip
+constexpr int kFastSlots = 4;    // queued two- and three-plane pairs per tet
+constexpr int kFastGrid = 16384;
 constexpr int kPlaneGrid = 2048;  // blocks of four waves, one interface cell per wave
 static_assert(kMaxCellPlanes * kMaxFacePoints <= 128, "two fan tetrahedra per lane");
 constexpr int kClipCap = 20;  // polytope vertices kept per lane in LDS
@@ -537,30 +540,111 @@ __global__ __launch_bounds__(kBlock) void k_flux(DMesh m, DState s, DParams p, i
 // The signed tet volume times sum over stencil cells of
 // |T ∩ C_c ∩ H_c| (H = the PLIC half-space in interface cells, all space in
 // full cells, alpha-weighted in vanishing-gradient cells) is stored per item.
-// Fast clip: register-only, one lane per (geometric face, flux tet); tets
-// with a pair that needs more than three planes (and every tet when the
-// stencil check is on) are queued for k_clip_general.
-__global__ __launch_bounds__(kBlock) void k_clip_fast(DMesh m, DState s, DParams p, int step) {
+
+// Step 5 on the register path, one wave per block and one flux tet per lane.
+// Phase A classifies the tet's stencil cells: pairs bounded by at most one
+// plane are summed at once (a single kept fraction); pairs with two or three
+// planes are queued in LDS bins by plane count, and a tet with a pair of
+// more planes (or more than kFastSlots queued pairs) goes to the general
+// kernel's queue.  Phase B evaluates each bin with the plane count uniform
+// across the wave; phase C adds each tet's queued results in stencil order.
+__global__ __launch_bounds__(kFastBlock) void k_clip_fast(DMesh m, DState s, DParams p, int step) {
+  __shared__ double tv[13][kFastBlock];
+  __shared__ int32_t icell[kFastBlock * kFastSlots];
+  __shared__ double res[kFastBlock * kFastSlots];
+  __shared__ uint16_t bins[2][kFastBlock * kFastSlots];
+  __shared__ int nbin[2];
+  const int lane = threadIdx.x;
   const double dt = s.dt[step], sc = s.sc[step];
   const int64_t total = (int64_t)s.work[kWGeometric] * m.tpf;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   unsigned long long npairs = 0;
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < total; base += stride) {
-    const int64_t idx = base + threadIdx.x;
-    bool defer = false;
+  for (int64_t base = (int64_t)blockIdx.x * kFastBlock; base < total;
+       base += (int64_t)gridDim.x * kFastBlock) {
+    const int64_t idx = base + lane;
+    if (lane < 2) nbin[lane] = 0;
+    __syncthreads();
+    bool defer = false, live = false;
+    double acc = 0.0, sgn = 1.0;
+    int nq = 0;
+    unsigned long long np = 0;
     if (idx < total) {
-      int slot = (int)(idx / m.tpf);
-      int k = (int)(idx - (int64_t)slot * m.tpf);
-      double v = 0.0;
-      unsigned long long np = 0;
-      defer = p.check_stencil || !flux_tet_phase_fast(m, s, dt, sc, s.gfaces[slot], k, v, np);
-      if (!defer) {
-        s.tetvol[idx] = v;
-        npairs += np;
+      const int slot = (int)(idx / m.tpf);
+      const int k = (int)(idx - (int64_t)slot * m.tpf);
+      const int f = s.gfaces[slot];
+      v3 c, t1, t2, t3;
+      double det;
+      live = !p.check_stencil && flux_tet(m, s, dt, sc, f, k, c, t1, t2, t3, det, sgn);
+      defer = p.check_stencil;
+      if (live) {
+        tv[0][lane] = c.x; tv[1][lane] = c.y; tv[2][lane] = c.z;
+        tv[3][lane] = t1.x; tv[4][lane] = t1.y; tv[5][lane] = t1.z;
+        tv[6][lane] = t2.x; tv[7][lane] = t2.y; tv[8][lane] = t2.z;
+        tv[9][lane] = t3.x; tv[10][lane] = t3.y; tv[11][lane] = t3.z;
+        tv[12][lane] = det;
+        const Tet T{mk3(0, 0, 0), t1, t2, t3};
+        v3 lo, hi;
+        tet_bbox(c, t1, t2, t3, lo, hi);
+        for (int e = m.st_off[f]; e < m.st_off[f + 1]; ++e) {
+          const int cell = m.st[e];
+          const int cl = s.cls[cell];
+          Pl p0, p1, p2;
+          int ncut;
+          const int npl = pair_planes(m, s, c, T, lo, hi, cell, cl, p0, p1, p2, ncut);
+          if (npl < 0) continue;
+          ++np;
+          if (npl <= 1) {
+            double fr = npl == 0 ? 1.0 : tet_kept_fraction(plane_dists(T, p0));
+            acc += class_weight(s, cell, cl) * det * fr;
+          } else if (npl <= 3 && nq < kFastSlots) {
+            icell[lane * kFastSlots + nq] = cell | ((npl - 2) << 30);
+            ++nq;
+          } else {
+            defer = true;
+            break;
+          }
+          if (ncut == 0) break;  // the tet lies inside this cell
+        }
       }
+    }
+    if (defer) live = false;
+    if (live) {
+      for (int j = 0; j < nq; ++j) {
+        int b = (icell[lane * kFastSlots + j] >> 30) & 1;
+        int pos = atomicAdd(&nbin[b], 1);
+        bins[b][pos] = (uint16_t)(lane * kFastSlots + j);
+      }
+      npairs += np;
+    }
+    __syncthreads();
+    for (int b = 0; b < 2; ++b) {
+      const int cnt = nbin[b];
+      for (int t = lane; t < cnt; t += kFastBlock) {
+        const int item = bins[b][t];
+        const int l = item / kFastSlots;
+        const int cell = icell[item] & 0x3fffffff;
+        const v3 c = mk3(tv[0][l], tv[1][l], tv[2][l]);
+        const Tet T{mk3(0, 0, 0), mk3(tv[3][l], tv[4][l], tv[5][l]),
+                    mk3(tv[6][l], tv[7][l], tv[8][l]), mk3(tv[9][l], tv[10][l], tv[11][l])};
+        const double det = tv[12][l];
+        v3 lo, hi;
+        tet_bbox(c, T.b, T.c, T.d, lo, hi);
+        const int cl = s.cls[cell];
+        Pl p0, p1, p2;
+        int ncut;
+        pair_planes(m, s, c, T, lo, hi, cell, cl, p0, p1, p2, ncut);
+        res[item] = class_weight(s, cell, cl) * vol6_planes3(T, det, p0, p1, p2, b + 2);
+      }
+    }
+    __syncthreads();
+    if (live) {
+      for (int j = 0; j < nq; ++j) acc += res[lane * kFastSlots + j];
+      s.tetvol[idx] = sgn * acc / 6.0;
+    } else if (idx < total && !defer) {
+      s.tetvol[idx] = 0.0;
     }
     int q = wave_append(&s.work[kWDeferred], defer);
     if (defer) s.defer[q] = (int32_t)idx;
+    __syncthreads();
   }
   wave_count(&s.cnt[kCntPairs], npairs);
 }
@@ -797,7 +881,7 @@ void launch_step(const DMesh &m, const DState &s, const DParams &p, int step, hi
     TIMED(prof, kKFlux, (k_flux<4><<<gf, kBlock, 0, st>>>(m, s, p, step)));
   else
     TIMED(prof, kKFlux, (k_flux<kMaxFacePoints><<<gf, kBlock, 0, st>>>(m, s, p, step)));
-  TIMED(prof, kKClip, (k_clip_fast<<<4096, kBlock, 0, st>>>(m, s, p, step)));
+  TIMED(prof, kKClip, (k_clip_fast<<<kFastGrid, kFastBlock, 0, st>>>(m, s, p, step)));
   TIMED(prof, kKClipGeneral, (k_clip_general<<<4096, kClipBlock, 0, st>>>(m, s, p, step)));
   TIMED(prof, kKFaceSum, (k_face_sum<<<1024, kBlock, 0, st>>>(m, s, p)));
   TIMED(prof, kKUpdate, (k_update<<<grid_for(m.nc, kBlock), kBlock, 0, st>>>(m, s)));
@@ -824,6 +908,22 @@ double host_tet_clip(const double *tet, int n_planes, const double *planes) {
     if (!P.clip(mk3(planes[4 * k], planes[4 * k + 1], planes[4 * k + 2]), planes[4 * k + 3]))
       return NAN;
   return P.vol6() / 6.0;
+}
+
+// Host evaluation of the register-only closed forms, with the tetrahedron
+// moved so that its first vertex is the origin as in the clip kernels.
+double host_tet_clip_closed(const double *tet, int n_planes, const double *planes) {
+  if (n_planes > 3) return NAN;
+  v3 a = mk3(tet[0], tet[1], tet[2]), b = mk3(tet[3], tet[4], tet[5]);
+  v3 c = mk3(tet[6], tet[7], tet[8]), d = mk3(tet[9], tet[10], tet[11]);
+  if (det3(b - a, c - a, d - a) < 0.0) { v3 t = c; c = d; d = t; }
+  const Tet T{mk3(0, 0, 0), b - a, c - a, d - a};
+  Pl pl[3] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+  for (int k = 0; k < n_planes; ++k) {
+    v3 n = mk3(planes[4 * k], planes[4 * k + 1], planes[4 * k + 2]);
+    pl[k] = mkpl(n, planes[4 * k + 3] - dot(n, a));
+  }
+  return vol6_planes3(T, det3(T.b, T.c, T.d), pl[0], pl[1], pl[2], n_planes) / 6.0;
 }
 
 }  // namespace vof

@@ -722,4 +722,9 @@ double vof_selftest_tet_clip(const double *tet, int32_t n_planes, const double *
   return host_tet_clip(tet, n_planes, planes);
 }
 
+double vof_selftest_tet_clip_closed(const double *tet, int32_t n_planes, const double *planes) {
+  if (!tet || n_planes < 0 || (n_planes > 0 && !planes)) return NAN;
+  return host_tet_clip_closed(tet, n_planes, planes);
+}
+
 }  // extern "C"

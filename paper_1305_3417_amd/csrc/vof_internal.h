@@ -132,5 +132,6 @@ void launch_step(const DMesh &m, const DState &s, const DParams &p, int step, hi
 void launch_reconstruct(const DMesh &m, const DState &s, const DParams &p, hipStream_t st);
 void launch_stats(const DMesh &m, const DState &s, double *out4, hipStream_t st);
 double host_tet_clip(const double *tet, int n_planes, const double *planes);
+double host_tet_clip_closed(const double *tet, int n_planes, const double *planes);
 
 }  // namespace vof

@@ -62,6 +62,51 @@ def test_selftest_clip_degenerate_dyadic_exact():
         assert abs(a - exact) <= 1e-15
 
 
+def test_selftest_closed_forms_match_oracle(oracle_mod):
+    """The register path (up to three planes, the tet's kept part split into
+    tetrahedra and carried as vertex distances) against the oracle's
+    clip-and-cap, on random tets and planes."""
+    rng = np.random.default_rng(21)
+    for _ in range(3000):
+        T = rng.random((4, 3))
+        k = int(rng.integers(0, 4))
+        planes = np.concatenate([rng.normal(size=(k, 3)), rng.uniform(0, 0.8, (k, 1))], 1)
+        a = vof.vof_selftest_tet_clip_closed(T, planes)
+        Tt = T.copy()
+        if np.linalg.det(Tt[1:] - Tt[0]) < 0:
+            Tt[[2, 3]] = Tt[[3, 2]]
+        b = (oracle_mod.clip_volume(Tt, TET_F, planes) if k
+             else abs(np.linalg.det(T[1:] - T[0])) / 6)
+        assert abs(a - b) <= 1e-15, (k, a, b)
+
+
+def test_selftest_closed_forms_degenerate_dyadic_exact():
+    """Vertices on planes, coplanar faces and parallel planes, against exact
+    rational volumes; every count of kept vertices occurs at every level."""
+    rng = np.random.default_rng(22)
+    seen = 0
+    for _ in range(1500):
+        T = rng.integers(0, 9, (4, 3)) / 8.0
+        if abs(np.linalg.det(T[1:] - T[0])) < 1e-9:
+            continue
+        k = int(rng.integers(1, 4))
+        planes = np.concatenate([rng.integers(-2, 3, (k, 3)), rng.integers(0, 9, (k, 1)) / 8.0], 1)
+        planes = planes[np.abs(planes[:, :3]).sum(1) > 0]
+        a = vof.vof_selftest_tet_clip_closed(T, planes)
+        exact = float(X.tet_halfspaces_volume(T, planes))
+        assert abs(a - exact) <= 1e-15, (T, planes, a, exact)
+        seen += exact > 0
+    assert seen > 300
+
+
+def test_selftest_closed_forms_refuse_four_planes():
+    T = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1.0]])
+    planes = np.array([[1, 0, 0, 0.5], [0, 1, 0, 0.5], [0, 0, 1, 0.5], [1, 1, 1, 0.9]])
+    assert np.isnan(vof.vof_selftest_tet_clip_closed(T, planes))
+    # the cube [0, 1/2]^3 minus its corner beyond x + y + z = 1
+    assert abs(vof.vof_selftest_tet_clip_closed(T, planes[:3]) - 5 / 48) < 1e-17
+
+
 def test_selftest_clip_box_capacity():
     """A tet cut by the six planes of a box and an oblique plane stays within
     the polytope capacity."""
@@ -90,5 +135,6 @@ def test_null_arguments_rejected():
     assert L.vof_set_alpha(None, None, 0) == vof.VOF_EINVAL
     assert L.vof_advect(None, 1, None, None) == vof.VOF_EINVAL
     assert np.isnan(L.vof_selftest_tet_clip(None, 0, None))
+    assert np.isnan(L.vof_selftest_tet_clip_closed(None, 0, None))
     assert vof.vof_profile_kernel_name(0) == "reset"
     assert vof.vof_profile_kernel_name(99) is None
