@@ -118,6 +118,9 @@ def main():
     ap.add_argument("--n", type=int, default=128, help="mesh is n^3 hexahedra")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (read BYTES, write BYTES) "
+                         "three times: the reference kernel for scaling HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
@@ -132,6 +135,16 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        n = args.calibrate_copy // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes_read": n * 8, "bytes_written": n * 8,
+                          "launches": 3}), flush=True)
+        return
     K, Wm = args.steps, args.warmup
     log(f"[bench] generating deform3d {args.n}^3")
     w = W.deform3d(args.n, steps=Wm + K + 1)

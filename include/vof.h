@@ -226,10 +226,10 @@ vof_status vof_read_profile(vof_mesh *mesh, double *ms, int64_t *launches, int32
 double vof_selftest_tet_clip(const double *tet, int32_t n_planes, const double *planes);
 
 /* Host self-test of the register-only closed forms the clip kernels use for a
- * (tetrahedron, cell) pair bounded by at most three planes (Section 2.4: the
+ * (tetrahedron, cell) pair bounded by at most four planes (Section 2.4: the
  * tetrahedron's kept part under each plane as one or three tetrahedra, the
  * last plane by the closed-form kept fraction).  Same arguments and result
- * as vof_selftest_tet_clip; NaN for n_planes > 3 or a bad argument. */
+ * as vof_selftest_tet_clip; NaN for n_planes > 4 or a bad argument. */
 double vof_selftest_tet_clip_closed(const double *tet, int32_t n_planes, const double *planes);
 
 #ifdef __cplusplus

@@ -77,12 +77,12 @@ VHD bool flux_tet(const DMesh &m, const DState &s, double dt, double sc, int f, 
 
 // Planes bounding the phase region of a (tet, cell) pair on the register
 // path: the cell planes that cut the tet, then the PLIC plane of an
-// interface cell; the first three go to p0..p2 with offsets relative to the
-// tet's apex c.  Returns their number, or -1 when the pair contributes
+// interface cell; the first kRegPlanes go to p0..p3 with offsets relative to
+// the tet's apex c.  Returns their number, or -1 when the pair contributes
 // nothing (an empty cell, bounding boxes apart, or the tet outside one of
 // the cell's planes); ncut receives the number of cutting cell planes.
 VHD int pair_planes(const DMesh &m, const DState &s, v3 c, const Tet &T, v3 lo, v3 hi, int cell,
-                    int cl, Pl &p0, Pl &p1, Pl &p2, int &ncut) {
+                    int cl, Pl &p0, Pl &p1, Pl &p2, Pl &p3, int &ncut) {
   ncut = 0;
   if (cl == 0) return -1;
   double4 blo = m.bblo[cell], bhi = m.bbhi[cell];
@@ -92,6 +92,7 @@ VHD int pair_planes(const DMesh &m, const DState &s, v3 c, const Tet &T, v3 lo, 
   p0 = Pl{0, 0, 0, 0};
   p1 = p0;
   p2 = p0;
+  p3 = p0;
   int n = 0;
   for (int q = m.cf_off[cell]; q < m.cf_off[cell + 1]; ++q) {
     double4 cp = m.cpl[q];
@@ -103,6 +104,7 @@ VHD int pair_planes(const DMesh &m, const DState &s, v3 c, const Tet &T, v3 lo, 
     if (dmx <= 0.0) return -1;
     if (dmn < 0.0) {
       Pl pn = mkpl(nn, off);
+      p3 = sel(n == 3, pn, p3);
       p2 = sel(n == 2, pn, p2);
       p1 = sel(n == 1, pn, p1);
       p0 = sel(n == 0, pn, p0);
@@ -114,6 +116,7 @@ VHD int pair_planes(const DMesh &m, const DState &s, v3 c, const Tet &T, v3 lo, 
     double4 pp = s.plane[cell];
     v3 nn = xyz4(pp);
     Pl pn = mkpl(nn, pp.w - dot(nn, c));
+    p3 = sel(n == 3, pn, p3);
     p2 = sel(n == 2, pn, p2);
     p1 = sel(n == 1, pn, p1);
     p0 = sel(n == 0, pn, p0);
@@ -130,7 +133,8 @@ VHD double class_weight(const DState &s, int cell, int cl) {
 
 // Register-only phase volume of flux tet k of face f (serial over the
 // stencil): every overlapping stencil cell contributes |T ∩ C ∩ H| through
-// at most three planes.  Returns false ("deferred") when a pair needs more.
+// at most kRegPlanes planes.  Returns false ("deferred") when a pair needs
+// more.
 VHD bool flux_tet_phase_fast(const DMesh &m, const DState &s, double dt, double sc, int f,
                              int k, double &vol, unsigned long long &npairs) {
   vol = 0.0;
@@ -145,13 +149,13 @@ VHD bool flux_tet_phase_fast(const DMesh &m, const DState &s, double dt, double 
   for (int e = m.st_off[f]; e < m.st_off[f + 1]; ++e) {
     const int cell = m.st[e];
     const int cl = s.cls[cell];
-    Pl p0, p1, p2;
+    Pl p0, p1, p2, p3;
     int ncut;
-    const int npl = pair_planes(m, s, c, T, lo, hi, cell, cl, p0, p1, p2, ncut);
+    const int npl = pair_planes(m, s, c, T, lo, hi, cell, cl, p0, p1, p2, p3, ncut);
     if (npl < 0) continue;
-    if (npl > 3) return false;
+    if (npl > kRegPlanes) return false;
     ++np;
-    acc += class_weight(s, cell, cl) * vol6_planes3(T, det, p0, p1, p2, npl);
+    acc += class_weight(s, cell, cl) * vol6_planes(T, det, p0, p1, p2, p3, npl);
     if (ncut == 0) break;  // the tet lies inside this cell
   }
   npairs += np;
@@ -176,7 +180,7 @@ VHD double pair_phase6(const DMesh &m, const DState &s, const DParams &p, v3 c, 
       lo.z >= bhi.z)
     return 0.0;
   int cuts[kMaxCellPlanes];
-  Pl p0{0, 0, 0, 0}, p1 = p0, p2 = p0;
+  Pl p0{0, 0, 0, 0}, p1 = p0, p2 = p0, p3 = p0;
   int ncut = 0;
   for (int q = m.cf_off[cell]; q < m.cf_off[cell + 1]; ++q) {
     double4 cp = m.cpl[q];
@@ -188,6 +192,7 @@ VHD double pair_phase6(const DMesh &m, const DState &s, const DParams &p, v3 c, 
     if (dmx <= 0.0) return 0.0;
     if (dmn < 0.0) {
       Pl pn = mkpl(nn, off);
+      p3 = sel(ncut == 3, pn, p3);
       p2 = sel(ncut == 2, pn, p2);
       p1 = sel(ncut == 1, pn, p1);
       p0 = sel(ncut == 0, pn, p0);
@@ -197,18 +202,20 @@ VHD double pair_phase6(const DMesh &m, const DState &s, const DParams &p, v3 c, 
   }
   ++npairs;  // a (tet, cell) pair with overlapping interiors
   const bool need_cover = p.check_stencil || cl >= 2;
-  double vc = (need_cover && ncut <= 3) ? vol6_planes3(T, det, p0, p1, p2, ncut) : -1.0;
+  double vc =
+      (need_cover && ncut <= kRegPlanes) ? vol6_planes(T, det, p0, p1, p2, p3, ncut) : -1.0;
   double vph = 0.0;
   if (cl == 1) {
     double4 pp = s.plane[cell];
     v3 nn = xyz4(pp);
     double off = pp.w - dot(nn, c);
-    if (ncut < 3) {
+    if (ncut < kRegPlanes) {
       Pl pn = mkpl(nn, off);
+      p3 = sel(ncut == 3, pn, p3);
       p2 = sel(ncut == 2, pn, p2);
       p1 = sel(ncut == 1, pn, p1);
       p0 = sel(ncut == 0, pn, p0);
-      vph = vol6_planes3(T, det, p0, p1, p2, ncut + 1);
+      vph = vol6_planes(T, det, p0, p1, p2, p3, ncut + 1);
     } else {
       P.init_tet(T.a, T.b, T.c, T.d);
       bool ok = true;

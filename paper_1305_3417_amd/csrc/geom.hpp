@@ -246,9 +246,12 @@ VHD D4 plane_dists(const Tet &t, Pl pl) {
   return D4{pl.w - dot(n, t.a), pl.w - dot(n, t.b), pl.w - dot(n, t.c), pl.w - dot(n, t.d)};
 }
 
-// six times |T ∩ {n_j.x <= s_j, j < k}| for k <= 3 planes, T positively
-// ordered with six times its volume vol6
-VHD double vol6_planes3(const Tet &T, double vol6, Pl p0, Pl p1, Pl p2, int k) {
+// Number of planes a (tetrahedron, cell) pair may have on the register path.
+constexpr int kRegPlanes = 4;
+
+// six times |T ∩ {n_j.x <= s_j, j < k}| for k <= kRegPlanes planes, T
+// positively ordered with six times its volume vol6
+VHD double vol6_planes(const Tet &T, double vol6, Pl p0, Pl p1, Pl p2, Pl p3, int k) {
   if (k == 0) return vol6;
   const D4 d0 = plane_dists(T, p0);
   if (k == 1) return vol6 * tet_kept_fraction(d0);
@@ -257,8 +260,12 @@ VHD double vol6_planes3(const Tet &T, double vol6, Pl p0, Pl p1, Pl p2, int k) {
     return vol6 * kept_fraction<2>(TD<2>{{{d0.a, d1.a}}, {{d0.b, d1.b}}, {{d0.c, d1.c}},
                                          {{d0.d, d1.d}}});
   const D4 d2 = plane_dists(T, p2);
-  return vol6 * kept_fraction<3>(TD<3>{{{d0.a, d1.a, d2.a}}, {{d0.b, d1.b, d2.b}},
-                                       {{d0.c, d1.c, d2.c}}, {{d0.d, d1.d, d2.d}}});
+  if (k == 3)
+    return vol6 * kept_fraction<3>(TD<3>{{{d0.a, d1.a, d2.a}}, {{d0.b, d1.b, d2.b}},
+                                         {{d0.c, d1.c, d2.c}}, {{d0.d, d1.d, d2.d}}});
+  const D4 d3 = plane_dists(T, p3);
+  return vol6 * kept_fraction<4>(TD<4>{{{d0.a, d1.a, d2.a, d3.a}}, {{d0.b, d1.b, d2.b, d3.b}},
+                                       {{d0.c, d1.c, d2.c, d3.c}}, {{d0.d, d1.d, d2.d, d3.d}}});
 }
 
 // ---------------------------------------------------------------------------

@@ -31,7 +31,7 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kClipBlock = 64;
 constexpr int kFastBlock = 64;   // one wave per block in the register clip
-constexpr int kFastSlots = 4;    // queued two- and three-plane pairs per tet
+constexpr int kFastSlots = 4;    // queued pairs of two or more planes per tet
 constexpr int kFastGrid = 16384;
 constexpr int kPlaneGrid = 2048;  // blocks of four waves, one interface cell per wave
 static_assert(kMaxCellPlanes * kMaxFacePoints <= 128, "two fan tetrahedra per lane");
@@ -543,17 +543,17 @@ __global__ __launch_bounds__(kBlock) void k_flux(DMesh m, DState s, DParams p, i
 
 // Step 5 on the register path, one wave per block and one flux tet per lane.
 // Phase A classifies the tet's stencil cells: pairs bounded by at most one
-// plane are summed at once (a single kept fraction); pairs with two or three
-// planes are queued in LDS bins by plane count, and a tet with a pair of
-// more planes (or more than kFastSlots queued pairs) goes to the general
-// kernel's queue.  Phase B evaluates each bin with the plane count uniform
+// plane are summed at once (a single kept fraction); pairs with two to
+// kRegPlanes planes are queued in LDS bins by plane count, and a tet with a
+// pair of more planes (or more than kFastSlots queued pairs) goes to the
+// general kernel's queue.  Phase B evaluates each bin with the plane count uniform
 // across the wave; phase C adds each tet's queued results in stencil order.
 __global__ __launch_bounds__(kFastBlock) void k_clip_fast(DMesh m, DState s, DParams p, int step) {
   __shared__ double tv[13][kFastBlock];
   __shared__ int32_t icell[kFastBlock * kFastSlots];
   __shared__ double res[kFastBlock * kFastSlots];
-  __shared__ uint16_t bins[2][kFastBlock * kFastSlots];
-  __shared__ int nbin[2];
+  __shared__ uint16_t bins[kRegPlanes - 1][kFastBlock * kFastSlots];
+  __shared__ int nbin[kRegPlanes - 1];
   const int lane = threadIdx.x;
   const double dt = s.dt[step], sc = s.sc[step];
   const int64_t total = (int64_t)s.work[kWGeometric] * m.tpf;
@@ -561,7 +561,7 @@ __global__ __launch_bounds__(kFastBlock) void k_clip_fast(DMesh m, DState s, DPa
   for (int64_t base = (int64_t)blockIdx.x * kFastBlock; base < total;
        base += (int64_t)gridDim.x * kFastBlock) {
     const int64_t idx = base + lane;
-    if (lane < 2) nbin[lane] = 0;
+    if (lane < kRegPlanes - 1) nbin[lane] = 0;
     __syncthreads();
     bool defer = false, live = false;
     double acc = 0.0, sgn = 1.0;
@@ -587,16 +587,16 @@ __global__ __launch_bounds__(kFastBlock) void k_clip_fast(DMesh m, DState s, DPa
         for (int e = m.st_off[f]; e < m.st_off[f + 1]; ++e) {
           const int cell = m.st[e];
           const int cl = s.cls[cell];
-          Pl p0, p1, p2;
+          Pl p0, p1, p2, p3;
           int ncut;
-          const int npl = pair_planes(m, s, c, T, lo, hi, cell, cl, p0, p1, p2, ncut);
+          const int npl = pair_planes(m, s, c, T, lo, hi, cell, cl, p0, p1, p2, p3, ncut);
           if (npl < 0) continue;
           ++np;
           if (npl <= 1) {
             double fr = npl == 0 ? 1.0 : tet_kept_fraction(plane_dists(T, p0));
             acc += class_weight(s, cell, cl) * det * fr;
-          } else if (npl <= 3 && nq < kFastSlots) {
-            icell[lane * kFastSlots + nq] = cell | ((npl - 2) << 30);
+          } else if (npl <= kRegPlanes && nq < kFastSlots) {
+            icell[lane * kFastSlots + nq] = (int32_t)((uint32_t)cell | ((uint32_t)(npl - 2) << 30));
             ++nq;
           } else {
             defer = true;
@@ -609,19 +609,19 @@ __global__ __launch_bounds__(kFastBlock) void k_clip_fast(DMesh m, DState s, DPa
     if (defer) live = false;
     if (live) {
       for (int j = 0; j < nq; ++j) {
-        int b = (icell[lane * kFastSlots + j] >> 30) & 1;
+        int b = (int)((uint32_t)icell[lane * kFastSlots + j] >> 30);
         int pos = atomicAdd(&nbin[b], 1);
         bins[b][pos] = (uint16_t)(lane * kFastSlots + j);
       }
       npairs += np;
     }
     __syncthreads();
-    for (int b = 0; b < 2; ++b) {
+    for (int b = 0; b < kRegPlanes - 1; ++b) {
       const int cnt = nbin[b];
       for (int t = lane; t < cnt; t += kFastBlock) {
         const int item = bins[b][t];
         const int l = item / kFastSlots;
-        const int cell = icell[item] & 0x3fffffff;
+        const int cell = (int)((uint32_t)icell[item] & 0x3fffffffu);
         const v3 c = mk3(tv[0][l], tv[1][l], tv[2][l]);
         const Tet T{mk3(0, 0, 0), mk3(tv[3][l], tv[4][l], tv[5][l]),
                     mk3(tv[6][l], tv[7][l], tv[8][l]), mk3(tv[9][l], tv[10][l], tv[11][l])};
@@ -629,10 +629,10 @@ __global__ __launch_bounds__(kFastBlock) void k_clip_fast(DMesh m, DState s, DPa
         v3 lo, hi;
         tet_bbox(c, T.b, T.c, T.d, lo, hi);
         const int cl = s.cls[cell];
-        Pl p0, p1, p2;
+        Pl p0, p1, p2, p3;
         int ncut;
-        pair_planes(m, s, c, T, lo, hi, cell, cl, p0, p1, p2, ncut);
-        res[item] = class_weight(s, cell, cl) * vol6_planes3(T, det, p0, p1, p2, b + 2);
+        pair_planes(m, s, c, T, lo, hi, cell, cl, p0, p1, p2, p3, ncut);
+        res[item] = class_weight(s, cell, cl) * vol6_planes(T, det, p0, p1, p2, p3, b + 2);
       }
     }
     __syncthreads();
@@ -913,17 +913,17 @@ double host_tet_clip(const double *tet, int n_planes, const double *planes) {
 // Host evaluation of the register-only closed forms, with the tetrahedron
 // moved so that its first vertex is the origin as in the clip kernels.
 double host_tet_clip_closed(const double *tet, int n_planes, const double *planes) {
-  if (n_planes > 3) return NAN;
+  if (n_planes > kRegPlanes) return NAN;
   v3 a = mk3(tet[0], tet[1], tet[2]), b = mk3(tet[3], tet[4], tet[5]);
   v3 c = mk3(tet[6], tet[7], tet[8]), d = mk3(tet[9], tet[10], tet[11]);
   if (det3(b - a, c - a, d - a) < 0.0) { v3 t = c; c = d; d = t; }
   const Tet T{mk3(0, 0, 0), b - a, c - a, d - a};
-  Pl pl[3] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+  Pl pl[kRegPlanes] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
   for (int k = 0; k < n_planes; ++k) {
     v3 n = mk3(planes[4 * k], planes[4 * k + 1], planes[4 * k + 2]);
     pl[k] = mkpl(n, planes[4 * k + 3] - dot(n, a));
   }
-  return vol6_planes3(T, det3(T.b, T.c, T.d), pl[0], pl[1], pl[2], n_planes) / 6.0;
+  return vol6_planes(T, det3(T.b, T.c, T.d), pl[0], pl[1], pl[2], pl[3], n_planes) / 6.0;
 }
 
 }  // namespace vof

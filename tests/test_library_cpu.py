@@ -63,13 +63,13 @@ def test_selftest_clip_degenerate_dyadic_exact():
 
 
 def test_selftest_closed_forms_match_oracle(oracle_mod):
-    """The register path (up to three planes, the tet's kept part split into
+    """The register path (up to four planes, the tet's kept part split into
     tetrahedra and carried as vertex distances) against the oracle's
     clip-and-cap, on random tets and planes."""
     rng = np.random.default_rng(21)
-    for _ in range(3000):
+    for _ in range(4000):
         T = rng.random((4, 3))
-        k = int(rng.integers(0, 4))
+        k = int(rng.integers(0, 5))
         planes = np.concatenate([rng.normal(size=(k, 3)), rng.uniform(0, 0.8, (k, 1))], 1)
         a = vof.vof_selftest_tet_clip_closed(T, planes)
         Tt = T.copy()
@@ -89,7 +89,7 @@ def test_selftest_closed_forms_degenerate_dyadic_exact():
         T = rng.integers(0, 9, (4, 3)) / 8.0
         if abs(np.linalg.det(T[1:] - T[0])) < 1e-9:
             continue
-        k = int(rng.integers(1, 4))
+        k = int(rng.integers(1, 5))
         planes = np.concatenate([rng.integers(-2, 3, (k, 3)), rng.integers(0, 9, (k, 1)) / 8.0], 1)
         planes = planes[np.abs(planes[:, :3]).sum(1) > 0]
         a = vof.vof_selftest_tet_clip_closed(T, planes)
@@ -99,10 +99,15 @@ def test_selftest_closed_forms_degenerate_dyadic_exact():
     assert seen > 300
 
 
-def test_selftest_closed_forms_refuse_four_planes():
+def test_selftest_closed_forms_refuse_five_planes():
     T = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1.0]])
-    planes = np.array([[1, 0, 0, 0.5], [0, 1, 0, 0.5], [0, 0, 1, 0.5], [1, 1, 1, 0.9]])
+    planes = np.array([[1, 0, 0, 0.5], [0, 1, 0, 0.5], [0, 0, 1, 0.5], [1, 1, 1, 0.9],
+                       [-1, 0, 0, 0.0]])
     assert np.isnan(vof.vof_selftest_tet_clip_closed(T, planes))
+    # four planes: the cube [0, 1/2]^3 below x + y + z = 0.9 (a corner tet of
+    # legs 0.9 minus three corner tets of legs 0.4 beyond the cube faces)
+    v4 = 0.9 ** 3 / 6 - 3 * 0.4 ** 3 / 6
+    assert abs(vof.vof_selftest_tet_clip_closed(T, planes[:4]) - v4) < 1e-16
     # the cube [0, 1/2]^3 minus its corner beyond x + y + z = 1
     assert abs(vof.vof_selftest_tet_clip_closed(T, planes[:3]) - 5 / 48) < 1e-17
 
