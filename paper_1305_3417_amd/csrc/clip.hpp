@@ -45,16 +45,14 @@ VHD bool flux_tet(const DMesh &m, const DState &s, double dt, double sc, int f, 
   int i1 = (i + 1 == n) ? 0 : i + 1;
   c = mk3(0, 0, 0);
   v3 cq = mk3(0, 0, 0);
-  v3 pi = mk3(0, 0, 0), pj = mk3(0, 0, 0), qi = mk3(0, 0, 0), qj = mk3(0, 0, 0);
   for (int j = 0; j < n; ++j) {
     int q = m.fpts[b + j];
-    v3 x = xyz4(m.X[q]);
-    v3 dq = sw * xyz4(s.U[q]);
-    c = c + x;
-    cq = cq + dq;
-    if (j == i) { pi = x; qi = dq; }
-    if (j == i1) { pj = x; qj = dq; }
+    c = c + xyz4(m.X[q]);
+    cq = cq + sw * xyz4(s.U[q]);
   }
+  const int qa = m.fpts[b + i], qb = m.fpts[b + i1];
+  v3 pi = xyz4(m.X[qa]), pj = xyz4(m.X[qb]);
+  v3 qi = sw * xyz4(s.U[qa]), qj = sw * xyz4(s.U[qb]);
   c = (1.0 / n) * c;
   pi = pi - c; pj = pj - c;
   qi = pi + qi; qj = pj + qj;
@@ -75,26 +73,18 @@ VHD bool flux_tet(const DMesh &m, const DState &s, double dt, double sc, int f, 
   return true;
 }
 
-// Planes bounding the phase region of a (tet, cell) pair on the register
-// path: the cell planes that cut the tet, then the PLIC plane of an
-// interface cell; the first kRegPlanes go to p0..p3 with offsets relative to
-// the tet's apex c.  Returns their number, or -1 when the pair contributes
-// nothing (an empty cell, bounding boxes apart, or the tet outside one of
-// the cell's planes); ncut receives the number of cutting cell planes.
-VHD int pair_planes(const DMesh &m, const DState &s, v3 c, const Tet &T, v3 lo, v3 hi, int cell,
-                    int cl, Pl &p0, Pl &p1, Pl &p2, Pl &p3, int &ncut) {
-  ncut = 0;
-  if (cl == 0) return -1;
+// Classification of a (tet, cell) pair on the register path: -1 when the
+// pair contributes nothing (bounding boxes apart, or the tet outside one of
+// the cell's planes), else the number of cell planes that cut the tet, with
+// bit j of mask set for plane cf_off[cell] + j.
+VHD int pair_cuts(const DMesh &m, v3 c, const Tet &T, v3 lo, v3 hi, int cell, uint32_t &mask) {
+  mask = 0;
   double4 blo = m.bblo[cell], bhi = m.bbhi[cell];
   if (hi.x <= blo.x || lo.x >= bhi.x || hi.y <= blo.y || lo.y >= bhi.y || hi.z <= blo.z ||
       lo.z >= bhi.z)
     return -1;
-  p0 = Pl{0, 0, 0, 0};
-  p1 = p0;
-  p2 = p0;
-  p3 = p0;
-  int n = 0;
-  for (int q = m.cf_off[cell]; q < m.cf_off[cell + 1]; ++q) {
+  const int q0 = m.cf_off[cell], q1 = m.cf_off[cell + 1];
+  for (int q = q0; q < q1; ++q) {
     double4 cp = m.cpl[q];
     v3 nn = xyz4(cp);
     double off = cp.w - dot(nn, c);
@@ -102,27 +92,38 @@ VHD int pair_planes(const DMesh &m, const DState &s, v3 c, const Tet &T, v3 lo, 
     double dmx = dmax(dmax(off, d1), dmax(d2, d3));
     double dmn = dmin(dmin(off, d1), dmin(d2, d3));
     if (dmx <= 0.0) return -1;
-    if (dmn < 0.0) {
-      Pl pn = mkpl(nn, off);
-      p3 = sel(n == 3, pn, p3);
-      p2 = sel(n == 2, pn, p2);
-      p1 = sel(n == 1, pn, p1);
-      p0 = sel(n == 0, pn, p0);
-      ++n;
-    }
+    mask |= (dmn < 0.0 ? 1u : 0u) << (q - q0);
   }
-  ncut = n;
-  if (cl == 1) {
-    double4 pp = s.plane[cell];
-    v3 nn = xyz4(pp);
-    Pl pn = mkpl(nn, pp.w - dot(nn, c));
-    p3 = sel(n == 3, pn, p3);
-    p2 = sel(n == 2, pn, p2);
-    p1 = sel(n == 1, pn, p1);
-    p0 = sel(n == 0, pn, p0);
-    ++n;
-  }
-  return n;
+  return __builtin_popcount(mask);
+}
+
+// cell plane q, or the PLIC plane of cell, with its offset relative to c
+VHD Pl cell_plane_at(const DMesh &m, int q, v3 c) {
+  double4 cp = m.cpl[q];
+  v3 nn = xyz4(cp);
+  return mkpl(nn, cp.w - dot(nn, c));
+}
+VHD Pl plic_plane_at(const DState &s, int cell, v3 c) {
+  double4 pp = s.plane[cell];
+  v3 nn = xyz4(pp);
+  return mkpl(nn, pp.w - dot(nn, c));
+}
+
+// The planes bounding the phase region of a classified pair in slots
+// p0..p3: the cutting cell planes in mask order, then the PLIC plane of an
+// interface cell (slots past the last plane are left unspecified).
+VHD void pair_regs(const DMesh &m, const DState &s, v3 c, int cell, int cl, uint32_t mask, Pl &p0,
+                   Pl &p1, Pl &p2, Pl &p3) {
+  const int q0 = m.cf_off[cell];
+  const Pl pl = cl == 1 ? plic_plane_at(s, cell, c) : Pl{0, 0, 0, 0};
+  uint32_t mm = mask;
+  p0 = mm ? cell_plane_at(m, q0 + __builtin_ctz(mm), c) : pl;
+  mm &= mm - 1;
+  p1 = mm ? cell_plane_at(m, q0 + __builtin_ctz(mm), c) : pl;
+  mm &= mm - 1;
+  p2 = mm ? cell_plane_at(m, q0 + __builtin_ctz(mm), c) : pl;
+  mm &= mm - 1;
+  p3 = mm ? cell_plane_at(m, q0 + __builtin_ctz(mm), c) : pl;
 }
 
 // weight of a covered volume in the phase region of a full (2) or
@@ -149,12 +150,15 @@ VHD bool flux_tet_phase_fast(const DMesh &m, const DState &s, double dt, double 
   for (int e = m.st_off[f]; e < m.st_off[f + 1]; ++e) {
     const int cell = m.st[e];
     const int cl = s.cls[cell];
-    Pl p0, p1, p2, p3;
-    int ncut;
-    const int npl = pair_planes(m, s, c, T, lo, hi, cell, cl, p0, p1, p2, p3, ncut);
-    if (npl < 0) continue;
+    if (cl == 0) continue;
+    uint32_t mask;
+    const int ncut = pair_cuts(m, c, T, lo, hi, cell, mask);
+    if (ncut < 0) continue;
+    const int npl = ncut + (cl == 1);
     if (npl > kRegPlanes) return false;
     ++np;
+    Pl p0, p1, p2, p3;
+    pair_regs(m, s, c, cell, cl, mask, p0, p1, p2, p3);
     acc += class_weight(s, cell, cl) * vol6_planes(T, det, p0, p1, p2, p3, npl);
     if (ncut == 0) break;  // the tet lies inside this cell
   }
@@ -167,11 +171,12 @@ VHD bool flux_tet_phase_fast(const DMesh &m, const DState &s, double dt, double 
 // the origin = face centre c, vol6 = det) inside stencil cell `cell`, with
 // (lo, hi) the tet's bounding box in mesh coordinates.  At most three planes
 // (cutting cell planes, plus the PLIC plane of an interface cell) take the
-// closed forms; more go through the vertex-graph polytope P.  With
+// closed forms; more go through the vertex-graph polytope P (only when
+// poly_ok; otherwise such a pair returns NaN and is left untouched).  With
 // check_stencil, *vcell receives six times |T ∩ C| (the coverage), else 0.
 VHD double pair_phase6(const DMesh &m, const DState &s, const DParams &p, v3 c, const Tet &T,
                        double det, v3 lo, v3 hi, int cell, Poly &P, unsigned long long &ncap,
-                       unsigned long long &npairs, double *vcell) {
+                       unsigned long long &npairs, double *vcell, bool poly_ok = true) {
   *vcell = 0.0;
   const int cl = s.cls[cell];
   if (cl == 0 && !p.check_stencil) return 0.0;
@@ -200,8 +205,10 @@ VHD double pair_phase6(const DMesh &m, const DState &s, const DParams &p, v3 c, 
       ++ncut;
     }
   }
-  ++npairs;  // a (tet, cell) pair with overlapping interiors
   const bool need_cover = p.check_stencil || cl >= 2;
+  if (!poly_ok && ((cl == 1 && ncut >= kRegPlanes) || (need_cover && ncut > kRegPlanes)))
+    return NAN;  // needs the polytope: the caller comes back with poly_ok
+  ++npairs;  // a (tet, cell) pair with overlapping interiors
   double vc =
       (need_cover && ncut <= kRegPlanes) ? vol6_planes(T, det, p0, p1, p2, p3, ncut) : -1.0;
   double vph = 0.0;

@@ -249,23 +249,32 @@ VHD D4 plane_dists(const Tet &t, Pl pl) {
 // Number of planes a (tetrahedron, cell) pair may have on the register path.
 constexpr int kRegPlanes = 4;
 
-// six times |T ∩ {n_j.x <= s_j, j < k}| for k <= kRegPlanes planes, T
-// positively ordered with six times its volume vol6
+// six times |T ∩ {n_j.x <= s_j, j < k}| for k <= KMAX <= kRegPlanes planes,
+// T positively ordered with six times its volume vol6
+template <int KMAX = kRegPlanes>
 VHD double vol6_planes(const Tet &T, double vol6, Pl p0, Pl p1, Pl p2, Pl p3, int k) {
+  static_assert(KMAX >= 1 && KMAX <= kRegPlanes, "plane count");
   if (k == 0) return vol6;
   const D4 d0 = plane_dists(T, p0);
-  if (k == 1) return vol6 * tet_kept_fraction(d0);
+  if (KMAX == 1 || k == 1) return vol6 * tet_kept_fraction(d0);
   const D4 d1 = plane_dists(T, p1);
-  if (k == 2)
+  if (KMAX == 2 || k == 2)
     return vol6 * kept_fraction<2>(TD<2>{{{d0.a, d1.a}}, {{d0.b, d1.b}}, {{d0.c, d1.c}},
                                          {{d0.d, d1.d}}});
   const D4 d2 = plane_dists(T, p2);
-  if (k == 3)
+  if constexpr (KMAX == 3) {
     return vol6 * kept_fraction<3>(TD<3>{{{d0.a, d1.a, d2.a}}, {{d0.b, d1.b, d2.b}},
                                          {{d0.c, d1.c, d2.c}}, {{d0.d, d1.d, d2.d}}});
-  const D4 d3 = plane_dists(T, p3);
-  return vol6 * kept_fraction<4>(TD<4>{{{d0.a, d1.a, d2.a, d3.a}}, {{d0.b, d1.b, d2.b, d3.b}},
-                                       {{d0.c, d1.c, d2.c, d3.c}}, {{d0.d, d1.d, d2.d, d3.d}}});
+  } else {
+    if (k == 3)
+      return vol6 * kept_fraction<3>(TD<3>{{{d0.a, d1.a, d2.a}}, {{d0.b, d1.b, d2.b}},
+                                           {{d0.c, d1.c, d2.c}}, {{d0.d, d1.d, d2.d}}});
+    const D4 d3 = plane_dists(T, p3);
+    return vol6 * kept_fraction<4>(TD<4>{{{d0.a, d1.a, d2.a, d3.a}},
+                                         {{d0.b, d1.b, d2.b, d3.b}},
+                                         {{d0.c, d1.c, d2.c, d3.c}},
+                                         {{d0.d, d1.d, d2.d, d3.d}}});
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -313,9 +322,17 @@ struct Poly {
   // inconsistent cap (the polytope must then be discarded by the caller).
   VHD bool clip(v3 n, double s) {
     if (nv == 0) return true;
+    // A vertex within 1e-13 of the polytope's extent of the plane lies on it
+    // (kept): rounding noise on vertices that are on the plane cannot then
+    // cut a sliver of zero width off the polytope.
+    double ext = 0.0;
+    for (int i = 1; i < nv; ++i)
+      ext = dmax(ext, dmax(fabs(X(i) - X(0)), dmax(fabs(Y(i) - Y(0)), fabs(Z(i) - Z(0)))));
+    const double tol = 1e-13 * sqrt(dot(n, n)) * ext;
     bool anyneg = false, anypos = false;
     for (int i = 0; i < nv; ++i) {
       double d = s - (n.x * X(i) + n.y * Y(i) + n.z * Z(i));
+      if (fabs(d) <= tol) d = 0.0;
       SD(i) = d;
       anyneg |= d < 0.0;
       anypos |= d > 0.0;
@@ -365,6 +382,12 @@ struct Poly {
       if (w2 < 0) { nv = 0; return false; }  // inconsistent cap: report, never index out
       NB(w, 2) = (uint8_t)w2;
       NB(w2, 1) = (uint8_t)w;
+    }
+    // every cap vertex needs two distinct cap neighbours; anything else is a
+    // graph that rounding has made inconsistent: report it, never index out
+    for (int w = onv; w < m; ++w) {
+      const int a = NB(w, 1), b = NB(w, 2);
+      if (a < onv || a >= m || b < onv || b >= m || a == b) { nv = 0; return false; }
     }
     // compact: kept originals and new vertices, in order
     int q = 0;

@@ -32,10 +32,11 @@ constexpr int kBlock = 256;
 constexpr int kClipBlock = 64;
 constexpr int kFastBlock = 64;   // one wave per block in the register clip
 constexpr int kFastSlots = 4;    // queued pairs of two or more planes per tet
+constexpr int kFastPlanes = 3;   // planes per pair in the register clip (more: general)
 constexpr int kFastGrid = 16384;
 constexpr int kPlaneGrid = 2048;  // blocks of four waves, one interface cell per wave
 static_assert(kMaxCellPlanes * kMaxFacePoints <= 128, "two fan tetrahedra per lane");
-constexpr int kClipCap = 20;  // polytope vertices kept per lane in LDS
+static_assert(kMaxCellPlanes <= 16, "cutting-plane masks are 16 bits");
 constexpr int kLedgerParts = 256;  // partial sums of the boundary ledger
 
 __device__ __forceinline__ v3 xyz(double4 a) { return mk3(a.x, a.y, a.z); }
@@ -542,18 +543,19 @@ __global__ __launch_bounds__(kBlock) void k_flux(DMesh m, DState s, DParams p, i
 // full cells, alpha-weighted in vanishing-gradient cells) is stored per item.
 
 // Step 5 on the register path, one wave per block and one flux tet per lane.
-// Phase A classifies the tet's stencil cells: pairs bounded by at most one
+// Phase A classifies the face's stencil cells: pairs bounded by at most one
 // plane are summed at once (a single kept fraction); pairs with two to
-// kRegPlanes planes are queued in LDS bins by plane count, and a tet with a
+// kFastPlanes planes are queued in LDS bins by plane count, and a tet with a
 // pair of more planes (or more than kFastSlots queued pairs) goes to the
 // general kernel's queue.  Phase B evaluates each bin with the plane count uniform
 // across the wave; phase C adds each tet's queued results in stencil order.
 __global__ __launch_bounds__(kFastBlock) void k_clip_fast(DMesh m, DState s, DParams p, int step) {
   __shared__ double tv[13][kFastBlock];
   __shared__ int32_t icell[kFastBlock * kFastSlots];
+  __shared__ uint16_t imask[kFastBlock * kFastSlots];
   __shared__ double res[kFastBlock * kFastSlots];
-  __shared__ uint16_t bins[kRegPlanes - 1][kFastBlock * kFastSlots];
-  __shared__ int nbin[kRegPlanes - 1];
+  __shared__ uint16_t bins[kFastPlanes - 1][kFastBlock * kFastSlots];
+  __shared__ int nbin[kFastPlanes - 1];
   const int lane = threadIdx.x;
   const double dt = s.dt[step], sc = s.sc[step];
   const int64_t total = (int64_t)s.work[kWGeometric] * m.tpf;
@@ -561,7 +563,7 @@ __global__ __launch_bounds__(kFastBlock) void k_clip_fast(DMesh m, DState s, DPa
   for (int64_t base = (int64_t)blockIdx.x * kFastBlock; base < total;
        base += (int64_t)gridDim.x * kFastBlock) {
     const int64_t idx = base + lane;
-    if (lane < kRegPlanes - 1) nbin[lane] = 0;
+    if (lane < kFastPlanes - 1) nbin[lane] = 0;
     __syncthreads();
     bool defer = false, live = false;
     double acc = 0.0, sgn = 1.0;
@@ -584,19 +586,27 @@ __global__ __launch_bounds__(kFastBlock) void k_clip_fast(DMesh m, DState s, DPa
         const Tet T{mk3(0, 0, 0), t1, t2, t3};
         v3 lo, hi;
         tet_bbox(c, t1, t2, t3, lo, hi);
-        for (int e = m.st_off[f]; e < m.st_off[f + 1]; ++e) {
+        const int e0 = m.st_off[f], e1 = m.st_off[f + 1];
+        for (int e = e0; e < e1; ++e) {
           const int cell = m.st[e];
           const int cl = s.cls[cell];
-          Pl p0, p1, p2, p3;
-          int ncut;
-          const int npl = pair_planes(m, s, c, T, lo, hi, cell, cl, p0, p1, p2, p3, ncut);
-          if (npl < 0) continue;
+          if (cl == 0) continue;
+          uint32_t mask;
+          const int ncut = pair_cuts(m, c, T, lo, hi, cell, mask);
+          if (ncut < 0) continue;
+          const int npl = ncut + (cl == 1);
           ++np;
           if (npl <= 1) {
-            double fr = npl == 0 ? 1.0 : tet_kept_fraction(plane_dists(T, p0));
+            double fr = 1.0;
+            if (npl == 1) {
+              const Pl pl = ncut ? cell_plane_at(m, m.cf_off[cell] + __builtin_ctz(mask), c)
+                                 : plic_plane_at(s, cell, c);
+              fr = tet_kept_fraction(plane_dists(T, pl));
+            }
             acc += class_weight(s, cell, cl) * det * fr;
-          } else if (npl <= kRegPlanes && nq < kFastSlots) {
+          } else if (npl <= kFastPlanes && nq < kFastSlots) {
             icell[lane * kFastSlots + nq] = (int32_t)((uint32_t)cell | ((uint32_t)(npl - 2) << 30));
+            imask[lane * kFastSlots + nq] = (uint16_t)mask;
             ++nq;
           } else {
             defer = true;
@@ -616,7 +626,7 @@ __global__ __launch_bounds__(kFastBlock) void k_clip_fast(DMesh m, DState s, DPa
       npairs += np;
     }
     __syncthreads();
-    for (int b = 0; b < kRegPlanes - 1; ++b) {
+    for (int b = 0; b < kFastPlanes - 1; ++b) {
       const int cnt = nbin[b];
       for (int t = lane; t < cnt; t += kFastBlock) {
         const int item = bins[b][t];
@@ -626,13 +636,11 @@ __global__ __launch_bounds__(kFastBlock) void k_clip_fast(DMesh m, DState s, DPa
         const Tet T{mk3(0, 0, 0), mk3(tv[3][l], tv[4][l], tv[5][l]),
                     mk3(tv[6][l], tv[7][l], tv[8][l]), mk3(tv[9][l], tv[10][l], tv[11][l])};
         const double det = tv[12][l];
-        v3 lo, hi;
-        tet_bbox(c, T.b, T.c, T.d, lo, hi);
         const int cl = s.cls[cell];
         Pl p0, p1, p2, p3;
-        int ncut;
-        pair_planes(m, s, c, T, lo, hi, cell, cl, p0, p1, p2, p3, ncut);
-        res[item] = class_weight(s, cell, cl) * vol6_planes(T, det, p0, p1, p2, p3, b + 2);
+        pair_regs(m, s, c, cell, cl, imask[item], p0, p1, p2, p3);
+        res[item] =
+            class_weight(s, cell, cl) * vol6_planes<kFastPlanes>(T, det, p0, p1, p2, p3, b + 2);
       }
     }
     __syncthreads();
@@ -650,20 +658,20 @@ __global__ __launch_bounds__(kFastBlock) void k_clip_fast(DMesh m, DState s, DPa
 }
 
 // General clip of the queued tets, one wave per tet with the lanes over the
-// face's stencil cells: closed forms up to three planes per pair, beyond
-// that a vertex-graph polytope in LDS per lane.  Pair volumes are summed by
-// the wave butterfly (the same order on every run).
+// face's stencil cells: closed forms up to kRegPlanes planes per pair in
+// every lane at once; the rare pairs with more planes then take turns on
+// one vertex-graph polytope in LDS shared by the wave.  Pair volumes are
+// summed by the wave butterfly (the same order on every run).
 __global__ __launch_bounds__(kClipBlock) void k_clip_general(DMesh m, DState s, DParams p,
                                                              int step) {
-  __shared__ double lx[kClipCap * kClipBlock], ly[kClipCap * kClipBlock],
-      lz[kClipCap * kClipBlock], ld[kClipCap * kClipBlock];
-  __shared__ uint8_t lnb[3 * kClipCap * kClipBlock], laux[kClipCap * kClipBlock];
+  __shared__ double lx[kPolyCap], ly[kPolyCap], lz[kPolyCap], ld[kPolyCap];
+  __shared__ uint8_t lnb[3 * kPolyCap], laux[kPolyCap];
   static_assert(kClipBlock == 64, "one wave per block");
   const int lane = threadIdx.x;
   Poly P;
-  P.px = lx + lane; P.py = ly + lane; P.pz = lz + lane; P.ps = ld + lane;
-  P.nb = lnb + lane; P.aux = laux + lane;
-  P.st = kClipBlock; P.cap = kClipCap; P.nv = 0;
+  P.px = lx; P.py = ly; P.pz = lz; P.ps = ld;
+  P.nb = lnb; P.aux = laux;
+  P.st = 1; P.cap = kPolyCap; P.nv = 0;
 
   const double dt = s.dt[step], sc = s.sc[step];
   const int count = s.work[kWDeferred];
@@ -682,9 +690,25 @@ __global__ __launch_bounds__(kClipBlock) void k_clip_general(DMesh m, DState s, 
       v3 lo, hi;
       tet_bbox(c, t1, t2, t3, lo, hi);
       double a = 0.0, cv = 0.0;
-      for (int e = m.st_off[f] + lane; e < m.st_off[f + 1]; e += 64) {
-        double vc;
-        a += pair_phase6(m, s, p, c, T, det, lo, hi, m.st[e], P, ncap, npairs, &vc);
+      const int e1 = m.st_off[f + 1];
+      for (int e0 = m.st_off[f]; e0 < e1; e0 += 64) {
+        const int e = e0 + lane;
+        double v = 0.0, vc = 0.0;
+        if (e < e1) v = pair_phase6(m, s, p, c, T, det, lo, hi, m.st[e], P, ncap, npairs, &vc,
+                                    false);
+        const bool pend = v != v;
+        unsigned long long pm = __ballot(pend);
+        while (pm) {
+          const int L = __ffsll((long long)pm) - 1;
+          pm &= pm - 1ull;
+          // the polytope changes hands: order one lane's LDS traffic before
+          // the next lane's (without this the compiler may interleave them)
+          __syncthreads();
+          if (lane == L)
+            v = pair_phase6(m, s, p, c, T, det, lo, hi, m.st[e], P, ncap, npairs, &vc, true);
+        }
+        __syncthreads();
+        a += v;
         cv += vc;
       }
       acc = wave_sum_d(a);

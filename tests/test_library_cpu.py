@@ -112,6 +112,37 @@ def test_selftest_closed_forms_refuse_five_planes():
     assert abs(vof.vof_selftest_tet_clip_closed(T, planes[:3]) - 5 / 48) < 1e-17
 
 
+def test_selftest_clip_near_degenerate_sequences():
+    """Planes through vertices, edges and earlier cut points of the tet, each
+    offset moved by rounding-sized amounts (1e-17 relative) and applied in
+    sequences of six: coincident vertices and sign noise on them must give a
+    consistent polytope (no NaN) whose volume is the exact one to 1e-14."""
+    rng = np.random.default_rng(23)
+    for _ in range(400):
+        T = rng.integers(0, 9, (4, 3)) / 8.0
+        if abs(np.linalg.det(T[1:] - T[0])) < 1e-9:
+            continue
+        planes, exact_planes = [], []
+        for _ in range(6):
+            nrm = rng.integers(-3, 4, 3).astype(float)
+            if not nrm.any():
+                nrm[0] = 1.0
+            # through a vertex, or through the midpoint of an edge
+            if rng.random() < 0.5:
+                x = T[rng.integers(4)]
+            else:
+                i, j = rng.choice(4, 2, replace=False)
+                x = 0.5 * (T[i] + T[j])
+            s0 = float(nrm @ x)
+            exact_planes.append(list(nrm) + [s0])
+            noise = rng.choice([-1.0, 0.0, 1.0]) * 1e-17 * (abs(s0) + 1.0)
+            planes.append(list(nrm) + [s0 + noise])
+        a = vof.vof_selftest_tet_clip(T, np.array(planes))
+        exact = float(X.tet_halfspaces_volume(T, exact_planes))
+        assert np.isfinite(a), (T, planes)
+        assert abs(a - exact) <= 1e-14, (T, planes, a, exact)
+
+
 def test_selftest_clip_box_capacity():
     """A tet cut by the six planes of a box and an oblique plane stays within
     the polytope capacity."""
