@@ -38,7 +38,9 @@ VHD void tet_bbox(v3 c, v3 t1, v3 t2, v3 t3, v3 &lo, v3 &hi) {
 // false for k beyond 5n or a flat tet.
 VHD bool flux_tet(const DMesh &m, const DState &s, double dt, double sc, int f, int k, v3 &c,
                   v3 &t1, v3 &t2, v3 &t3, double &det, double &sgn) {
-  int b = m.foff[f], n = m.foff[f + 1] - b;
+  const int32_t *fp = m.fpad + (int64_t)f * m.padw;
+  int n = 0;
+  for (int j = 0; j < m.padw; ++j) n += fp[j] >= 0;
   if (k >= 5 * n) return false;
   const double sw = -sc * dt * s.lam[f];
   int i = k / 5, type = k - 5 * i;
@@ -46,13 +48,13 @@ VHD bool flux_tet(const DMesh &m, const DState &s, double dt, double sc, int f, 
   c = mk3(0, 0, 0);
   v3 cq = mk3(0, 0, 0);
   for (int j = 0; j < n; ++j) {
-    int q = m.fpts[b + j];
-    c = c + xyz4(m.X[q]);
-    cq = cq + sw * xyz4(s.U[q]);
+    const double4 *xu = s.XU + 2 * (int64_t)fp[j];
+    c = c + xyz4(xu[0]);
+    cq = cq + sw * xyz4(xu[1]);
   }
-  const int qa = m.fpts[b + i], qb = m.fpts[b + i1];
-  v3 pi = xyz4(m.X[qa]), pj = xyz4(m.X[qb]);
-  v3 qi = sw * xyz4(s.U[qa]), qj = sw * xyz4(s.U[qb]);
+  const double4 *xa = s.XU + 2 * (int64_t)fp[i], *xb = s.XU + 2 * (int64_t)fp[i1];
+  v3 pi = xyz4(xa[0]), pj = xyz4(xb[0]);
+  v3 qi = sw * xyz4(xa[1]), qj = sw * xyz4(xb[1]);
   c = (1.0 / n) * c;
   pi = pi - c; pj = pj - c;
   qi = pi + qi; qj = pj + qj;

@@ -43,6 +43,16 @@ __device__ __forceinline__ v3 xyz(double4 a) { return mk3(a.x, a.y, a.z); }
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
+// Workgroups are dispatched round-robin over the eight XCDs (block b on XCD
+// b % 8), each with its own L2.  Renumbered this way every XCD works through
+// a contiguous range of the logical block indices, so neighbouring faces
+// (which share points) meet in the same L2.  The grid must be a multiple of 8.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_block() {
+  const int b = (int)blockIdx.x;
+  return (b % kXcds) * (int)(gridDim.x / kXcds) + b / kXcds;
+}
+
 // Append the lanes with `pred` to a list: one atomic per wavefront.  Must be
 // reached by every lane of the wavefront.
 __device__ __forceinline__ int wave_append(int32_t *counter, bool pred) {
@@ -177,7 +187,9 @@ __global__ void k_check_orientation(DMesh m, uint32_t *flags) {
 }
 
 // U_p = sum_c w_pc U_c (eqs. 2.6-2.7 applied to the velocity, Section 2.3)
-__global__ void k_point_velocity(DMesh m, const double *U0c, double4 *U) {
+// IDW point velocity (eq. 2.6); also the per-point record (position,
+// velocity) that the flux kernels gather with one cache line per point.
+__global__ void k_point_velocity(DMesh m, const double *U0c, double4 *U, double4 *XU) {
   int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (p >= m.np) return;
   v3 u = mk3(0, 0, 0);
@@ -186,6 +198,8 @@ __global__ void k_point_velocity(DMesh m, const double *U0c, double4 *U) {
     u = u + m.wpc[k] * mk3(U0c[3 * c], U0c[3 * c + 1], U0c[3 * c + 2]);
   }
   U[p] = make_double4(u.x, u.y, u.z, 0.0);
+  XU[2 * p] = m.X[p];
+  XU[2 * p + 1] = make_double4(u.x, u.y, u.z, 0.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -420,6 +434,24 @@ __device__ __forceinline__ void correct(double c1, double c2, double c3, double 
   lam = x;
 }
 
+// Point indices of face f from the padded list (-1 past the last point): one
+// 16-byte load per four points.
+template <int NMAX>
+__device__ __forceinline__ void load_face_points(const DMesh &m, int64_t f, int (&q)[NMAX]) {
+  if constexpr (NMAX <= 4) {
+    const int4 v = *reinterpret_cast<const int4 *>(m.fpad + 4 * f);
+    const int w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int i = 0; i < NMAX; ++i) q[i] = w[i];
+  } else {
+    const int4 a = *reinterpret_cast<const int4 *>(m.fpad + 8 * f);
+    const int4 b = *reinterpret_cast<const int4 *>(m.fpad + 8 * f + 4);
+    const int w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+    for (int i = 0; i < NMAX; ++i) q[i] = w[i];
+  }
+}
+
 // per-block sums of up to three counters, one atomic each per block
 __device__ __forceinline__ void block_count3(unsigned long long *d0, unsigned long long v0,
                                              unsigned long long *d1, unsigned long long v1,
@@ -445,17 +477,22 @@ __global__ __launch_bounds__(kBlock) void k_flux(DMesh m, DState s, DParams p, i
   const double dt = s.dt[step], sc = s.sc[step];
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   unsigned long long nflux = 0, nit = 0, nbad = 0;
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < m.nf; base += stride) {
+  for (int64_t base = (int64_t)xcd_block() * blockDim.x; base < m.nf; base += stride) {
     const int64_t f = base + threadIdx.x;
     bool geo = false;
     if (f < m.nf) {
+      // the point list and the flux are independent loads, issued together
+      int q[NMAX];
+      load_face_points<NMAX>(m, f, q);
       double F = sc * s.F0[f];
       double T = F * dt;
       double lam = 0.0, vph = 0.0;
       int it = 0, stat = 0;
       uint8_t kind = 0;
       if (F != 0.0) {
-        int b = m.foff[f], n = m.foff[f + 1] - b;
+        int n = 0;
+#pragma unroll
+        for (int i = 0; i < NMAX; ++i) n += q[i] >= 0;
         v3 r[NMAX], d[NMAX];
         uint8_t mask = 0;
         v3 c = mk3(0, 0, 0);
@@ -463,10 +500,10 @@ __global__ __launch_bounds__(kBlock) void k_flux(DMesh m, DState s, DParams p, i
 #pragma unroll
         for (int i = 0; i < NMAX; ++i) {
           if (i < n) {
-            int q = m.fpts[b + i];
-            r[i] = xyz(m.X[q]);
-            d[i] = sweep * xyz(s.U[q]);
-            mask |= s.pmask[q];
+            const double4 *xu = s.XU + 2 * (int64_t)q[i];
+            r[i] = xyz(xu[0]);
+            d[i] = sweep * xyz(xu[1]);
+            mask |= s.pmask[q[i]];
             c = c + r[i];
           } else {
             r[i] = mk3(0, 0, 0);
@@ -476,6 +513,9 @@ __global__ __launch_bounds__(kBlock) void k_flux(DMesh m, DState s, DParams p, i
         c = (1.0 / n) * c;
 #pragma unroll
         for (int i = 0; i < NMAX; ++i) r[i] = r[i] - c;
+        // h_i.((d_i + d_i+1) x e_i) = -(d_i + d_i+1).(r_i x r_i+1) (triple product
+        // with e_i = r_i+1 - r_i, h_i = (r_i + r_i+1) / 2), so every edge needs the
+        // three products r_i x r_i+1, d_i x d_i+1 and r_i x d_i+1 + d_i x r_i+1.
         double t1 = 0.0, t2 = 0.0;
         v3 A2 = mk3(0, 0, 0), B = mk3(0, 0, 0), Cc = mk3(0, 0, 0), db = mk3(0, 0, 0);
 #pragma unroll
@@ -483,21 +523,21 @@ __global__ __launch_bounds__(kBlock) void k_flux(DMesh m, DState s, DParams p, i
           if (i < n) {
             v3 rn = (i + 1 < n) ? r[(i + 1) % NMAX] : r[0];
             v3 dn = (i + 1 < n) ? d[(i + 1) % NMAX] : d[0];
-            v3 e = rn - r[i];
-            v3 h = 0.5 * (r[i] + rn);
+            v3 a = cross(r[i], rn);
             v3 dd = cross(d[i], dn);
-            t1 += dot(h, cross(d[i] + dn, e));
-            t2 += dot(h, dd);
-            A2 = A2 + cross(r[i], rn);
+            t1 -= dot(d[i] + dn, a);
+            t2 += 0.5 * dot(r[i] + rn, dd);
+            A2 = A2 + a;
             B = B + cross(r[i], dn) + cross(d[i], rn);
             Cc = Cc + dd;
             db = db + d[i];
           }
         }
         db = (1.0 / n) * db;
-        double c1 = (t1 - dot(db, A2)) / 6.0;
-        double c2 = (t2 - dot(db, B)) / 6.0;
-        double c3 = -dot(db, Cc) / 6.0;
+        const double sixth = 1.0 / 6.0;
+        double c1 = (t1 - dot(db, A2)) * sixth;
+        double c2 = (t2 - dot(db, B)) * sixth;
+        double c3 = -dot(db, Cc) * sixth;
         correct(c1, c2, c3, T, p.corr_rtol, p.corr_max_iter, lam, it, stat);
         // A target beyond the extremum of V on the branch: the phase volume of
         // the polyhedron at the clamped lam is rescaled to F dt (scalar correction).
@@ -854,8 +894,9 @@ void launch_mesh_geometry(const DMesh &m0, double4 *X, const double *pts, double
   if (m.ni > 0) k_check_orientation<<<grid_for(m.ni, kBlock), kBlock, 0, st>>>(m, flags);
 }
 
-void launch_point_velocity(const DMesh &m, const double *U0c, double4 *U, hipStream_t st) {
-  k_point_velocity<<<grid_for(m.np, kBlock), kBlock, 0, st>>>(m, U0c, U);
+void launch_point_velocity(const DMesh &m, const double *U0c, double4 *U, double4 *XU,
+                           hipStream_t st) {
+  k_point_velocity<<<grid_for(m.np, kBlock), kBlock, 0, st>>>(m, U0c, U, XU);
 }
 
 static void launch_reconstruct_impl(const DMesh &m, const DState &s, const DParams &p,
@@ -899,6 +940,7 @@ void launch_step(const DMesh &m, const DState &s, const DParams &p, int step, hi
   // persistent-style grid: a few blocks per CU, grid-stride over the faces
   unsigned gf = grid_for(m.nf, kBlock);
   gf = gf < 8192 ? gf : 8192;
+  gf = (gf + kXcds - 1) / kXcds * kXcds;
   if (m.maxn <= 3)
     TIMED(prof, kKFlux, (k_flux<3><<<gf, kBlock, 0, st>>>(m, s, p, step)));
   else if (m.maxn == 4)

@@ -371,10 +371,17 @@ vof_status vof_mesh_upload(vof_context *ctx, const vof_mesh_desc *d, vof_mesh **
 
   double4 *X, *S, *C, *XC, *cpl, *bblo, *bbhi;
   int32_t *d_foff, *d_fpts, *d_own, *d_nei, *d_cf_off, *d_cf, *d_pc_off, *d_pc, *d_st_off, *d_st;
+  int32_t *d_fpad;
+  // face points padded to a fixed width: one vector load per face
+  const int32_t padw = maxn <= 4 ? 4 : 8;
+  std::vector<int32_t> fpad((size_t)nf * padw, -1);
+  for (int64_t f = 0; f < nf; ++f)
+    for (int64_t k = foff[f]; k < foff[f + 1]; ++k) fpad[(size_t)f * padw + (k - foff[f])] = fpts[k];
   double *wpc, *V, *d_pts;
 #define ALLOC(p, n) \
   do { if ((rc = m->alloc(&(p), (n)))) { delete m; return rc; } } while (0)
   ALLOC(X, np); ALLOC(d_pts, 3 * np); ALLOC(d_foff, nf + 1); ALLOC(d_fpts, nfp);
+  ALLOC(d_fpad, nf * (int64_t)padw); ALLOC(ds.XU, 2 * np);
   ALLOC(d_own, nf); ALLOC(d_nei, ni); ALLOC(d_cf_off, nc + 1); ALLOC(d_cf, (int64_t)cf.size());
   ALLOC(d_pc_off, np + 1); ALLOC(d_pc, (int64_t)pc.size()); ALLOC(wpc, (int64_t)pc.size());
   ALLOC(d_st_off, nf + 1); ALLOC(d_st, (int64_t)st.size());
@@ -392,6 +399,7 @@ vof_status vof_mesh_upload(vof_context *ctx, const vof_mesh_desc *d, vof_mesh **
 #define UP(dst, src, n)                                                                    \
   do { if ((rc = to_device(dst, src, n, VOF_HOST, s))) { delete m; return rc; } } while (0)
   UP(d_pts, pts.data(), 3 * np); UP(d_foff, foff.data(), nf + 1); UP(d_fpts, fpts.data(), nfp);
+  UP(d_fpad, fpad.data(), nf * (int64_t)padw);
   UP(d_own, own.data(), nf); UP(d_nei, nei.data(), ni); UP(d_cf_off, cf_off.data(), nc + 1);
   UP(d_cf, cf.data(), (int64_t)cf.size()); UP(d_pc_off, pc_off.data(), np + 1);
   UP(d_pc, pc.data(), (int64_t)pc.size()); UP(d_st_off, st_off.data(), nf + 1);
@@ -404,6 +412,7 @@ vof_status vof_mesh_upload(vof_context *ctx, const vof_mesh_desc *d, vof_mesh **
   if (e == hipSuccess) e = hipMemsetAsync(ds.plane, 0, sizeof(double4) * nc, s);
   if (e == hipSuccess) e = hipMemsetAsync(ds.alpha, 0, sizeof(double) * nc, s);
   if (e == hipSuccess) e = hipMemsetAsync(ds.U, 0, sizeof(double4) * np, s);
+  if (e == hipSuccess) e = hipMemsetAsync(ds.XU, 0, sizeof(double4) * 2 * np, s);
   if (e == hipSuccess) e = hipMemsetAsync(ds.F0, 0, sizeof(double) * nf, s);
   if (e == hipSuccess) e = hipMemsetAsync(ds.lam, 0, sizeof(double) * nf, s);
   if (e == hipSuccess) e = hipMemsetAsync(ds.vphase, 0, sizeof(double) * nf, s);
@@ -412,6 +421,7 @@ vof_status vof_mesh_upload(vof_context *ctx, const vof_mesh_desc *d, vof_mesh **
   if (e == hipSuccess) e = hipMemsetAsync(ds.fstatus, 0, nf, s);
   if (e != hipSuccess) { delete m; return fail(VOF_EDEVICE, "memset: %s", hipGetErrorString(e)); }
   dm.X = X; dm.foff = d_foff; dm.fpts = d_fpts; dm.own = d_own; dm.nei = d_nei;
+  dm.fpad = d_fpad; dm.padw = padw;
   dm.cf_off = d_cf_off; dm.cf = d_cf; dm.pc_off = d_pc_off; dm.pc = d_pc; dm.wpc = wpc;
   dm.st_off = d_st_off; dm.st = d_st; dm.S = S; dm.C = C; dm.V = V; dm.XC = XC; dm.cpl = cpl;
   dm.bblo = bblo; dm.bbhi = bbhi;
@@ -507,7 +517,7 @@ vof_status vof_set_velocity(vof_mesh *m, const double *U0c, const double *F0, in
   rc = to_device(tmp, U0c, 3 * m->dm.nc, memory, s);
   if (!rc) rc = to_device(m->ds.F0, F0, m->dm.nf, memory, s);
   if (!rc) {
-    launch_point_velocity(m->dm, tmp, m->ds.U, s);
+    launch_point_velocity(m->dm, tmp, m->ds.U, m->ds.XU, s);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) rc = fail(VOF_EDEVICE, "point velocity: %s", hipGetErrorString(e));

@@ -51,6 +51,8 @@ struct DMesh {
   const double4 *X;        // points (x, y, z, 0)
   const int32_t *foff;     // nf + 1
   const int32_t *fpts;     // face points
+  const int32_t *fpad;     // face points padded to padw per face (-1 past the last)
+  int32_t padw;            // 4 when every face has at most 4 points, else 8
   const int32_t *own;      // nf
   const int32_t *nei;      // ni
   const int32_t *cf_off;   // nc + 1
@@ -86,6 +88,7 @@ struct DState {
   uint8_t *pmask;       // np: bit 1 empty, 2 full, 4 interface among point-cells
   double *alpha_p;      // np: IDW point values (band points only)
   double4 *U;           // np: reference point velocity
+  double4 *XU;          // 2 np: (position, reference velocity) of each point, adjacent
   double *F0;           // nf
   double *lam;          // nf
   double *vphase;       // nf
@@ -126,7 +129,8 @@ struct Prof {
 void launch_mesh_geometry(const DMesh &m, double4 *X, const double *pts, double4 *S, double4 *C,
                           double *V, double4 *XC, double *wpc, double4 *cpl, double4 *bblo,
                           double4 *bbhi, uint32_t *flags, hipStream_t st);
-void launch_point_velocity(const DMesh &m, const double *U0c, double4 *U, hipStream_t st);
+void launch_point_velocity(const DMesh &m, const double *U0c, double4 *U, double4 *XU,
+                           hipStream_t st);
 void launch_step(const DMesh &m, const DState &s, const DParams &p, int step, hipStream_t st,
                  Prof *prof);
 void launch_reconstruct(const DMesh &m, const DState &s, const DParams &p, hipStream_t st);
