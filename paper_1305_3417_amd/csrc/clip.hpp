@@ -79,9 +79,9 @@ VHD bool flux_tet(const DMesh &m, const DState &s, double dt, double sc, int f, 
 // pair contributes nothing (bounding boxes apart, or the tet outside one of
 // the cell's planes), else the number of cell planes that cut the tet, with
 // bit j of mask set for plane cf_off[cell] + j.
-VHD int pair_cuts(const DMesh &m, v3 c, const Tet &T, v3 lo, v3 hi, int cell, uint32_t &mask) {
+VHD int pair_cuts_box(const DMesh &m, v3 c, const Tet &T, v3 lo, v3 hi, v3 blo, v3 bhi, int cell,
+                      uint32_t &mask) {
   mask = 0;
-  double4 blo = m.bblo[cell], bhi = m.bbhi[cell];
   if (hi.x <= blo.x || lo.x >= bhi.x || hi.y <= blo.y || lo.y >= bhi.y || hi.z <= blo.z ||
       lo.z >= bhi.z)
     return -1;
@@ -97,6 +97,10 @@ VHD int pair_cuts(const DMesh &m, v3 c, const Tet &T, v3 lo, v3 hi, int cell, ui
     mask |= (dmn < 0.0 ? 1u : 0u) << (q - q0);
   }
   return __builtin_popcount(mask);
+}
+VHD int pair_cuts(const DMesh &m, v3 c, const Tet &T, v3 lo, v3 hi, int cell, uint32_t &mask) {
+  const double4 blo = m.bblo[cell], bhi = m.bbhi[cell];
+  return pair_cuts_box(m, c, T, lo, hi, xyz4(blo), xyz4(bhi), cell, mask);
 }
 
 // cell plane q, or the PLIC plane of cell, with its offset relative to c

@@ -87,16 +87,27 @@ VHD int kept_count(const D4 &d) {
 //   three kept (d removed):     1 - prod_j d_d / (d_d - d_j)
 //   two kept (a, b):            t_ac t_ad + t_ad t_bc (1 - t_ac) + t_bc t_bd (1 - t_ad)
 // (the last is the prism a, b | ac, ad, bc, bd cut into three tetrahedra).
+// Each case is one quotient over a common denominator of positive factors
+// (d_x >= 0 > d_y); with A = a - c, B = a - d, C = b - c, D = b - d the two-kept
+// case is (a^2 C D - a b c D - b^2 d A) / (A B C D), every term positive.  The
+// case is chosen by selects, so every lane performs a single division.
 VHD double tet_kept_fraction(D4 d) {
   const int kept = kept_count(d);
   if (kept == 4) return 1.0;
   if (kept == 0) return 0.0;
   sort_kept(d);
-  if (kept == 1) return (d.a / (d.a - d.b)) * (d.a / (d.a - d.c)) * (d.a / (d.a - d.d));
-  if (kept == 3) return 1.0 - (d.d / (d.d - d.a)) * (d.d / (d.d - d.b)) * (d.d / (d.d - d.c));
-  double tac = d.a / (d.a - d.c), tad = d.a / (d.a - d.d);
-  double tbc = d.b / (d.b - d.c), tbd = d.b / (d.b - d.d);
-  return tac * tad + tad * tbc * (1.0 - tac) + tbc * tbd * (1.0 - tad);
+  const double a = d.a, b = d.b, c = d.c, e = d.d;
+  // one kept vertex
+  const double n1 = a * a * a, q1 = (a - b) * (a - c) * (a - e);
+  // three kept: the removed corner at e
+  const double n3 = -(e * e * e), q3 = (a - e) * (b - e) * (c - e);
+  // two kept
+  const double A = a - c, B = a - e, C = b - c, D = b - e;
+  const double n2 = a * a * C * D - a * b * c * D - b * b * e * A, q2 = A * B * C * D;
+  const double num = kept == 1 ? n1 : (kept == 2 ? n2 : n3);
+  const double den = kept == 1 ? q1 : (kept == 2 ? q2 : q3);
+  const double r = num / den;
+  return kept == 3 ? 1.0 - r : r;
 }
 VHD double tet_kept_fraction(const double dd[4]) {
   return tet_kept_fraction(D4{dd[0], dd[1], dd[2], dd[3]});

@@ -33,7 +33,9 @@ constexpr int kClipBlock = 64;
 constexpr int kFastBlock = 64;   // one wave per block in the register clip
 constexpr int kFastSlots = 4;    // queued pairs of two or more planes per tet
 constexpr int kFastPlanes = 3;   // planes per pair in the register clip (more: general)
-constexpr int kFastGrid = 16384;
+constexpr int kFastGrid = 4096;   // blocks claim face groups from a counter
+constexpr int kGroupFaces = 4;    // faces per wavefront group (64 / at least 15 tets)
+constexpr int kCand = 16;         // candidate cells per face kept in LDS
 constexpr int kPlaneGrid = 2048;  // blocks of four waves, one interface cell per wave
 static_assert(kMaxCellPlanes * kMaxFacePoints <= 128, "two fan tetrahedra per lane");
 static_assert(kMaxCellPlanes <= 16, "cutting-plane masks are 16 bits");
@@ -582,57 +584,145 @@ __global__ __launch_bounds__(kBlock) void k_flux(DMesh m, DState s, DParams p, i
 // |T ∩ C_c ∩ H_c| (H = the PLIC half-space in interface cells, all space in
 // full cells, alpha-weighted in vanishing-gradient cells) is stored per item.
 
-// Step 5 on the register path, one wave per block and one flux tet per lane.
-// Phase A classifies the face's stencil cells: pairs bounded by at most one
+// Step 5 on the register path.  A wavefront takes a group of whole geometric
+// faces (64 / tets-per-face of them; groups claimed from a counter), one flux
+// tet per lane.  First the faces' candidate cells: each face's stencil is
+// scanned by all lanes at once and the non-empty cells whose box overlaps
+// the flux polyhedron's box are compacted (in stencil order) into LDS with
+// their class and box.  Phase A: every tet classifies its face's candidates
+// by a mask of the cell planes that cut it; pairs bounded by at most one
 // plane are summed at once (a single kept fraction); pairs with two to
 // kFastPlanes planes are queued in LDS bins by plane count, and a tet with a
-// pair of more planes (or more than kFastSlots queued pairs) goes to the
-// general kernel's queue.  Phase B evaluates each bin with the plane count uniform
-// across the wave; phase C adds each tet's queued results in stencil order.
-__global__ __launch_bounds__(kFastBlock) void k_clip_fast(DMesh m, DState s, DParams p, int step) {
-  __shared__ double tv[13][kFastBlock];
+// pair of more planes, more than kFastSlots queued pairs, or a face with more
+// than kCand candidates goes to the general kernel's queue.  Phase B
+// evaluates each bin with the plane count uniform across the wave; phase C
+// adds each tet's queued results in stencil order.
+__global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_clip_fast(DMesh m, DState s, DParams p, int step) {
+  __shared__ double tv[10][kFastBlock];
+  __shared__ double fc[kGroupFaces][3];  // face centre (the apex of the face's tets)
   __shared__ int32_t icell[kFastBlock * kFastSlots];
   __shared__ uint16_t imask[kFastBlock * kFastSlots];
   __shared__ double res[kFastBlock * kFastSlots];
   __shared__ uint16_t bins[kFastPlanes - 1][kFastBlock * kFastSlots];
   __shared__ int nbin[kFastPlanes - 1];
+  __shared__ int32_t ccell[kGroupFaces][kCand];
+  __shared__ int8_t ccls[kGroupFaces][kCand];
+  // candidate boxes rounded outwards to float: the test stays conservative
+  __shared__ float cbox[kGroupFaces][kCand][6];
+  __shared__ double fbox[kGroupFaces][6];
+  __shared__ int cnum[kGroupFaces];
+  __shared__ int group;
   const int lane = threadIdx.x;
   const double dt = s.dt[step], sc = s.sc[step];
-  const int64_t total = (int64_t)s.work[kWGeometric] * m.tpf;
+  const double sweep = -sc * dt;
+  const int count = s.work[kWGeometric];
+  const int tpf = m.tpf;
+  const int F = kFastBlock / tpf;  // faces per group, 1..kGroupFaces
+  const int ngroups = (count + F - 1) / F;
   unsigned long long npairs = 0;
-  for (int64_t base = (int64_t)blockIdx.x * kFastBlock; base < total;
-       base += (int64_t)gridDim.x * kFastBlock) {
-    const int64_t idx = base + lane;
+  for (;;) {
+    if (lane == 0) group = atomicAdd(&s.work[kWClipNext], 1);
     if (lane < kFastPlanes - 1) nbin[lane] = 0;
+    // flux polyhedron boxes, one lane per face (points and their swept
+    // images).  Unpadded: a cell that only touches the box meets the
+    // polyhedron in a sliver of zero width (or of the width of the rounding
+    // of the tets' vertices), whose volume is below the rounding of the sum.
     __syncthreads();
+    const int g = group;
+    if (g >= ngroups) break;
+    if (lane < F) {
+      const int slot = g * F + lane;
+      if (slot < count) {
+        const int f = s.gfaces[slot];
+        const double sw = sweep * s.lam[f];
+        const int32_t *fp = m.fpad + (int64_t)f * m.padw;
+        v3 lo = mk3(1e300, 1e300, 1e300), hi = mk3(-1e300, -1e300, -1e300);
+        for (int j = 0; j < m.padw; ++j) {
+          if (fp[j] < 0) break;
+          const double4 *xu = s.XU + 2 * (int64_t)fp[j];
+          const v3 x = xyz(xu[0]);
+          const v3 y = x + sw * xyz(xu[1]);
+          lo = mk3(dmin(lo.x, dmin(x.x, y.x)), dmin(lo.y, dmin(x.y, y.y)),
+                   dmin(lo.z, dmin(x.z, y.z)));
+          hi = mk3(dmax(hi.x, dmax(x.x, y.x)), dmax(hi.y, dmax(x.y, y.y)),
+                   dmax(hi.z, dmax(x.z, y.z)));
+        }
+        fbox[lane][0] = lo.x; fbox[lane][1] = lo.y; fbox[lane][2] = lo.z;
+        fbox[lane][3] = hi.x; fbox[lane][4] = hi.y; fbox[lane][5] = hi.z;
+      }
+    }
+    __syncthreads();
+    // candidate cells of each face of the group
+    for (int fi = 0; fi < F; ++fi) {
+      const int slot = g * F + fi;
+      if (slot >= count) break;
+      const int f = s.gfaces[slot];
+      const int w = m.st_off[f], nst = m.st_off[f + 1] - w;
+      int cnt = 0;
+      for (int e0 = 0; e0 < nst; e0 += kFastBlock) {
+        const int e = e0 + lane;
+        bool keep = false;
+        int cell = 0, cl = 0;
+        double4 blo = make_double4(0, 0, 0, 0), bhi = blo;
+        if (e < nst) {
+          cell = m.st[w + e];
+          cl = s.cls[cell];
+          if (cl != 0) {
+            blo = m.bblo[cell];
+            bhi = m.bbhi[cell];
+            keep = !(fbox[fi][3] <= blo.x || fbox[fi][0] >= bhi.x || fbox[fi][4] <= blo.y ||
+                     fbox[fi][1] >= bhi.y || fbox[fi][5] <= blo.z || fbox[fi][2] >= bhi.z);
+          }
+        }
+        const unsigned long long bal = __ballot(keep);
+        const int pos = cnt + (int)__popcll(bal & ((1ull << lane) - 1ull));
+        if (keep && pos < kCand) {
+          ccell[fi][pos] = cell;
+          ccls[fi][pos] = (int8_t)cl;
+          cbox[fi][pos][0] = __double2float_rd(blo.x);
+          cbox[fi][pos][1] = __double2float_rd(blo.y);
+          cbox[fi][pos][2] = __double2float_rd(blo.z);
+          cbox[fi][pos][3] = __double2float_ru(bhi.x);
+          cbox[fi][pos][4] = __double2float_ru(bhi.y);
+          cbox[fi][pos][5] = __double2float_ru(bhi.z);
+        }
+        cnt += (int)__popcll(bal);
+      }
+      if (lane == 0) cnum[fi] = cnt;
+    }
+    __syncthreads();
+    // phase A
+    const int fi = lane / tpf, k = lane - fi * tpf;
+    const int slot = g * F + fi;
+    const bool active = fi < F && slot < count;
+    const int64_t idx = (int64_t)slot * tpf + k;
     bool defer = false, live = false;
     double acc = 0.0, sgn = 1.0;
     int nq = 0;
     unsigned long long np = 0;
-    if (idx < total) {
-      const int slot = (int)(idx / m.tpf);
-      const int k = (int)(idx - (int64_t)slot * m.tpf);
+    if (active) {
       const int f = s.gfaces[slot];
       v3 c, t1, t2, t3;
       double det;
       live = !p.check_stencil && flux_tet(m, s, dt, sc, f, k, c, t1, t2, t3, det, sgn);
-      defer = p.check_stencil;
-      if (live) {
-        tv[0][lane] = c.x; tv[1][lane] = c.y; tv[2][lane] = c.z;
-        tv[3][lane] = t1.x; tv[4][lane] = t1.y; tv[5][lane] = t1.z;
-        tv[6][lane] = t2.x; tv[7][lane] = t2.y; tv[8][lane] = t2.z;
-        tv[9][lane] = t3.x; tv[10][lane] = t3.y; tv[11][lane] = t3.z;
-        tv[12][lane] = det;
+      defer = p.check_stencil || cnum[fi] > kCand;
+      if (live && !defer) {
+        if (k == 0) { fc[fi][0] = c.x; fc[fi][1] = c.y; fc[fi][2] = c.z; }
+        tv[0][lane] = t1.x; tv[1][lane] = t1.y; tv[2][lane] = t1.z;
+        tv[3][lane] = t2.x; tv[4][lane] = t2.y; tv[5][lane] = t2.z;
+        tv[6][lane] = t3.x; tv[7][lane] = t3.y; tv[8][lane] = t3.z;
+        tv[9][lane] = det;
         const Tet T{mk3(0, 0, 0), t1, t2, t3};
         v3 lo, hi;
         tet_bbox(c, t1, t2, t3, lo, hi);
-        const int e0 = m.st_off[f], e1 = m.st_off[f + 1];
-        for (int e = e0; e < e1; ++e) {
-          const int cell = m.st[e];
-          const int cl = s.cls[cell];
-          if (cl == 0) continue;
+        const int nc = cnum[fi];
+        for (int ci = 0; ci < nc; ++ci) {
+          const int cell = ccell[fi][ci];
+          const int cl = ccls[fi][ci];
+          const float *bb = cbox[fi][ci];
           uint32_t mask;
-          const int ncut = pair_cuts(m, c, T, lo, hi, cell, mask);
+          const int ncut = pair_cuts_box(m, c, T, lo, hi, mk3(bb[0], bb[1], bb[2]),
+                                         mk3(bb[3], bb[4], bb[5]), cell, mask);
           if (ncut < 0) continue;
           const int npl = ncut + (cl == 1);
           ++np;
@@ -666,16 +756,18 @@ __global__ __launch_bounds__(kFastBlock) void k_clip_fast(DMesh m, DState s, DPa
       npairs += np;
     }
     __syncthreads();
+    // phase B
     for (int b = 0; b < kFastPlanes - 1; ++b) {
       const int cnt = nbin[b];
       for (int t = lane; t < cnt; t += kFastBlock) {
         const int item = bins[b][t];
         const int l = item / kFastSlots;
         const int cell = (int)((uint32_t)icell[item] & 0x3fffffffu);
-        const v3 c = mk3(tv[0][l], tv[1][l], tv[2][l]);
-        const Tet T{mk3(0, 0, 0), mk3(tv[3][l], tv[4][l], tv[5][l]),
-                    mk3(tv[6][l], tv[7][l], tv[8][l]), mk3(tv[9][l], tv[10][l], tv[11][l])};
-        const double det = tv[12][l];
+        const int lf = l / tpf;
+        const v3 c = mk3(fc[lf][0], fc[lf][1], fc[lf][2]);
+        const Tet T{mk3(0, 0, 0), mk3(tv[0][l], tv[1][l], tv[2][l]),
+                    mk3(tv[3][l], tv[4][l], tv[5][l]), mk3(tv[6][l], tv[7][l], tv[8][l])};
+        const double det = tv[9][l];
         const int cl = s.cls[cell];
         Pl p0, p1, p2, p3;
         pair_regs(m, s, c, cell, cl, imask[item], p0, p1, p2, p3);
@@ -684,10 +776,11 @@ __global__ __launch_bounds__(kFastBlock) void k_clip_fast(DMesh m, DState s, DPa
       }
     }
     __syncthreads();
+    // phase C
     if (live) {
       for (int j = 0; j < nq; ++j) acc += res[lane * kFastSlots + j];
       s.tetvol[idx] = sgn * acc / 6.0;
-    } else if (idx < total && !defer) {
+    } else if (active && !defer) {
       s.tetvol[idx] = 0.0;
     }
     int q = wave_append(&s.work[kWDeferred], defer);

@@ -42,7 +42,7 @@ enum Counter : int {
 };
 
 // per-step work counters (reset every step)
-enum WorkCounter : int { kWInterface = 0, kWGeometric = 1, kWDeferred = 2, kWNum = 4 };
+enum WorkCounter : int { kWInterface = 0, kWGeometric = 1, kWDeferred = 2, kWClipNext = 3, kWNum = 4 };
 
 struct DMesh {
   int64_t np, nc, nf, ni;
