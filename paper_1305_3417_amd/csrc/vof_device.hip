@@ -69,6 +69,27 @@ __device__ __forceinline__ int wave_append(int32_t *counter, bool pred) {
   return pred ? base + rank : -1;
 }
 
+// Append the threads with `pred` to a list with one atomic per block (the
+// waves' counts are combined in LDS).  Every thread of the block must reach
+// it; the block size must be kBlock.
+__device__ __forceinline__ int block_append(int32_t *counter, bool pred) {
+  __shared__ int wbase[kBlock / 64];
+  __shared__ int bbase;
+  const unsigned long long mask = __ballot(pred);
+  const int lane = lane_id(), w = (int)(threadIdx.x >> 6);
+  if (lane == 0) wbase[w] = (int)__popcll(mask);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int i = 0; i < kBlock / 64; ++i) { int c = wbase[i]; wbase[i] = tot; tot += c; }
+    bbase = tot ? atomicAdd(counter, tot) : 0;
+  }
+  __syncthreads();
+  const int pos = bbase + wbase[w] + (int)__popcll(mask & ((1ull << lane) - 1ull));
+  __syncthreads();  // wbase / bbase are reused by the next call
+  return pred ? pos : -1;
+}
+
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   return v;
@@ -220,7 +241,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_class(DMesh m, DState s, DParam
     s.cls[c] = cl;
     iface = cl == 1;
   }
-  int slot = wave_append(&s.work[kWInterface], iface);
+  int slot = block_append(&s.work[kWInterface], iface);
   if (iface) s.icells[slot] = (int32_t)c;
 }
 
@@ -229,6 +250,8 @@ __global__ __launch_bounds__(kBlock) void k_point_prep(DMesh m, DState s) {
   if (p >= m.np) return;
   int k0 = m.pc_off[p], k1 = m.pc_off[p + 1];
   uint8_t mask = 0;
+  // unrolled so that the cell ids, then the class bytes, load together
+#pragma unroll 8
   for (int k = k0; k < k1; ++k) {
     int8_t cl = s.cls[m.pc[k]];
     mask |= cl == 0 ? 1 : (cl == 2 ? 2 : 4);
@@ -735,8 +758,8 @@ __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3)))
             }
             acc += class_weight(s, cell, cl) * det * fr;
           } else if (npl <= kFastPlanes && nq < kFastSlots) {
-            icell[lane * kFastSlots + nq] = (int32_t)((uint32_t)cell | ((uint32_t)(npl - 2) << 30));
-            imask[lane * kFastSlots + nq] = (uint16_t)mask;
+            icell[nq * kFastBlock + lane] = (int32_t)((uint32_t)cell | ((uint32_t)(npl - 2) << 30));
+            imask[nq * kFastBlock + lane] = (uint16_t)mask;
             ++nq;
           } else {
             defer = true;
@@ -749,9 +772,9 @@ __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3)))
     if (defer) live = false;
     if (live) {
       for (int j = 0; j < nq; ++j) {
-        int b = (int)((uint32_t)icell[lane * kFastSlots + j] >> 30);
+        int b = (int)((uint32_t)icell[j * kFastBlock + lane] >> 30);
         int pos = atomicAdd(&nbin[b], 1);
-        bins[b][pos] = (uint16_t)(lane * kFastSlots + j);
+        bins[b][pos] = (uint16_t)(j * kFastBlock + lane);
       }
       npairs += np;
     }
@@ -761,7 +784,7 @@ __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3)))
       const int cnt = nbin[b];
       for (int t = lane; t < cnt; t += kFastBlock) {
         const int item = bins[b][t];
-        const int l = item / kFastSlots;
+        const int l = item % kFastBlock;
         const int cell = (int)((uint32_t)icell[item] & 0x3fffffffu);
         const int lf = l / tpf;
         const v3 c = mk3(fc[lf][0], fc[lf][1], fc[lf][2]);
@@ -778,7 +801,7 @@ __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3)))
     __syncthreads();
     // phase C
     if (live) {
-      for (int j = 0; j < nq; ++j) acc += res[lane * kFastSlots + j];
+      for (int j = 0; j < nq; ++j) acc += res[j * kFastBlock + lane];
       s.tetvol[idx] = sgn * acc / 6.0;
     } else if (active && !defer) {
       s.tetvol[idx] = 0.0;
@@ -891,6 +914,8 @@ __global__ __launch_bounds__(kBlock) void k_update(DMesh m, DState s) {
   int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (c >= m.nc) return;
   double acc = 0.0;
+  // unrolled so that the face ids, then the phase volumes, load together
+#pragma unroll 6
   for (int k = m.cf_off[c]; k < m.cf_off[c + 1]; ++k) {
     int sf = m.cf[k];
     acc += sf >= 0 ? s.vphase[sf] : -s.vphase[~sf];
