@@ -8,10 +8,12 @@ conservative update, for all 6.3M faces and 2.1M cells.  Inputs are resident
 in HBM when the timed region starts.
 
 Prints one JSON line: face-fluxes/s (faces with F != 0 per step, each built,
-corrected and given its phase volume), the dominant kernel's roofline figure
-from HIP-event timing inside the timed region, a sampled parity check of an
-extra step against the oracle, and the oracle's own rate on a bounded sample
-of the same step (CPU baseline).
+corrected and given its phase volume) over the timed steps, run as the
+library runs them (each step one captured HIP graph); per-kernel durations
+and the dominant kernel's roofline figure from HIP events around every
+kernel over the next min(K, 20) steps, launched kernel by kernel; a sampled
+parity check of an extra step against the oracle; and the oracle's own rate
+on a bounded sample of the same step (CPU baseline).
 """
 from __future__ import annotations
 
@@ -182,8 +184,9 @@ def main():
                           "launches": 3}), flush=True)
         return
     K, Wm = args.steps, args.warmup
+    P = min(K, 20)  # profiled steps after the timed region
     log(f"[bench] generating deform3d {args.n}^3")
-    w = W.deform3d(args.n, steps=Wm + K + 1)
+    w = W.deform3d(args.n, steps=Wm + K + P + 1)
     ctx = vof.vof_context_create(0)
     log("[bench] uploading mesh")
     mesh = vof.upload_mesh(ctx, w.mesh)
@@ -191,9 +194,10 @@ def main():
     vof.vof_set_velocity(mesh, w.U0c, w.F0)
     log(f"[bench] warmup {Wm} steps")
     vof.vof_advect(mesh, w.dt[:Wm], w.scale[:Wm])
+    vof.vof_synchronize(mesh)
     st0 = vof.vof_get_stats(mesh)
-    vof.vof_profile_enable(mesh, True)
-    vof.vof_read_profile(mesh)
+    # timed region: the step as the library runs it (one captured graph per
+    # step, replayed on the library's stream)
     log(f"[bench] timing {K} steps")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -201,25 +205,38 @@ def main():
     vof.vof_synchronize(mesh)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    prof = vof.vof_read_profile(mesh)
-    vof.vof_profile_enable(mesh, False)
     st1 = vof.vof_get_stats(mesh)
     face_fluxes = st1["face_fluxes"] - st0["face_fluxes"]
     geo = st1["geometric_faces"] - st0["geometric_faces"]
     value = face_fluxes / elapsed
     log(f"[bench] {elapsed * 1e3 / K:.3f} ms/step, {value:.3e} face-fluxes/s")
+
+    # per-kernel durations: the next P steps launched kernel by kernel, each
+    # bracketed by HIP events on the library's stream
+    vof.vof_profile_enable(mesh, True)
+    vof.vof_read_profile(mesh)
+    sp0 = vof.vof_get_stats(mesh)
+    tp0 = time.perf_counter()
+    vof.vof_advect(mesh, w.dt[Wm + K:Wm + K + P], w.scale[Wm + K:Wm + K + P])
+    vof.vof_synchronize(mesh)
+    prof_elapsed = time.perf_counter() - tp0
+    prof = vof.vof_read_profile(mesh)
+    vof.vof_profile_enable(mesh, False)
+    sp1 = vof.vof_get_stats(mesh)
     log("[bench] per-kernel: " + ", ".join(f"{k} {v[0] / max(v[1], 1) * 1e3:.1f}us"
                                            for k, v in prof.items()))
 
     # dominant kernel and its roofline figure: algorithmic flops per launch
-    # (per-unit figure x units per launch) over its average duration
+    # (per-unit figure x units per launch, counted over the profiled steps)
+    # over its average duration
     dom = max(prof, key=lambda k: prof[k][0])
     dom_ms, dom_n = prof[dom]
     avg_s = dom_ms / dom_n / 1e3
-    units = {"flux": (face_fluxes / K, FLUX_FLOPS_PER_QUAD_FACE, "face-fluxes"),
-             "clip": ((st1["clip_pairs"] - st0["clip_pairs"]) / K, CLIP_FLOPS_PER_PAIR,
+    units = {"flux": ((sp1["face_fluxes"] - sp0["face_fluxes"]) / P, FLUX_FLOPS_PER_QUAD_FACE,
+                      "face-fluxes"),
+             "clip": ((sp1["clip_pairs"] - sp0["clip_pairs"]) / P, CLIP_FLOPS_PER_PAIR,
                       "overlapping (tet, cell) pairs"),
-             "plane": ((st1["interface_cells"] - st0["interface_cells"]) / K,
+             "plane": ((sp1["interface_cells"] - sp0["interface_cells"]) / P,
                        PLANE_FLOPS_PER_CELL, "interface cells")}
     if dom in units:
         n_units, per_unit, what = units[dom]
@@ -228,22 +245,23 @@ def main():
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
                 "traffic": recorded_traffic(dom, args.n),
                 "avg_launch_us": avg_s * 1e6, "units_per_launch": n_units,
-                "flop_per_unit": per_unit, "unit_kind": what}
+                "flop_per_unit": per_unit, "unit_kind": what, "profiled_steps": P}
     else:
         roof = {"kernel": dom, "bound": "alu", "achieved": None, "peak": PEAK_FP64_TFLOPS,
                 "unit": "TFLOP/s", "frac": None, "traffic": recorded_traffic(dom, args.n),
-                "avg_launch_us": avg_s * 1e6}
+                "avg_launch_us": avg_s * 1e6, "profiled_steps": P}
+    step_after = Wm + K + P
 
     parity = None
     if not args.no_parity:
         log("[bench] parity check of one extra step against the oracle")
-        parity = parity_check(vof, mesh, w, Wm + K)
+        parity = parity_check(vof, mesh, w, step_after)
         log(f"[bench] parity {parity}")
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] oracle CPU baseline")
         a = vof.vof_read_alpha(mesh)
-        cpu = cpu_baseline(w, a, Wm + K)
+        cpu = cpu_baseline(w, a, step_after)
         log(f"[bench] cpu {cpu}")
 
     out = {
@@ -260,6 +278,7 @@ def main():
         "general_clip_tets_per_step": (st1["general_tets"] - st0["general_tets"]) / K,
         "face_fluxes_per_step": face_fluxes / K,
         "kernels_us": {k: v[0] / max(v[1], 1) * 1e3 for k, v in prof.items()},
+        "profiled_ms_per_step": prof_elapsed * 1e3 / P,
         "roofline": roof,
         "parity": parity,
         "cpu_baseline": cpu,

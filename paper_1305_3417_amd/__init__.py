@@ -218,9 +218,10 @@ class MeshHandle:
             lib().vof_mesh_destroy(self.h)
             self.h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # never call into the HIP runtime while the interpreter is shutting down
-        if sys.is_finalizing():
+        # (module globals may already be gone then, hence the bound default)
+        if _finalizing():
             return
         try:
             self.close()

@@ -498,7 +498,8 @@ __device__ __forceinline__ void block_count3(unsigned long long *d0, unsigned lo
 }
 
 template <int NMAX>
-__global__ __launch_bounds__(kBlock) void k_flux(DMesh m, DState s, DParams p, int step) {
+__global__ __launch_bounds__(kBlock) void k_flux(DMesh m, DState s, DParams p) {
+  const int step = *s.stepno;
   const double dt = s.dt[step], sc = s.sc[step];
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   unsigned long long nflux = 0, nit = 0, nbad = 0;
@@ -620,7 +621,8 @@ __global__ __launch_bounds__(kBlock) void k_flux(DMesh m, DState s, DParams p, i
 // than kCand candidates goes to the general kernel's queue.  Phase B
 // evaluates each bin with the plane count uniform across the wave; phase C
 // adds each tet's queued results in stencil order.
-__global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_clip_fast(DMesh m, DState s, DParams p, int step) {
+__global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_clip_fast(DMesh m, DState s, DParams p) {
+  const int step = *s.stepno;
   __shared__ double tv[10][kFastBlock];
   __shared__ double fc[kGroupFaces][3];  // face centre (the apex of the face's tets)
   __shared__ int32_t icell[kFastBlock * kFastSlots];
@@ -818,8 +820,8 @@ __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3)))
 // every lane at once; the rare pairs with more planes then take turns on
 // one vertex-graph polytope in LDS shared by the wave.  Pair volumes are
 // summed by the wave butterfly (the same order on every run).
-__global__ __launch_bounds__(kClipBlock) void k_clip_general(DMesh m, DState s, DParams p,
-                                                             int step) {
+__global__ __launch_bounds__(kClipBlock) void k_clip_general(DMesh m, DState s, DParams p) {
+  const int step = *s.stepno;
   __shared__ double lx[kPolyCap], ly[kPolyCap], lz[kPolyCap], ld[kPolyCap];
   __shared__ uint8_t lnb[3 * kPolyCap], laux[kPolyCap];
   static_assert(kClipBlock == 64, "one wave per block");
@@ -957,6 +959,7 @@ __global__ __launch_bounds__(kBlock) void k_ledger(DMesh m, DState s, int nparts
     s.cnt[kCntGeometric] += (unsigned long long)s.work[kWGeometric];
     s.cnt[kCntInterface] += (unsigned long long)s.work[kWInterface];
     s.cnt[kCntDeferred] += (unsigned long long)s.work[kWDeferred];
+    s.stepno[0] += 1;  // the next step reads dt, scale at the next index
   }
 }
 
@@ -1049,8 +1052,10 @@ void Prof::end(int kid) {
     if (on_) (prof)->end(kid);                         \
   } while (0)
 
-void launch_step(const DMesh &m, const DState &s, const DParams &p, int step, hipStream_t st,
-                 Prof *prof) {
+// One step of the path; the step index (for dt and scale) is read by the
+// kernels from s.stepno, which the last kernel advances, so the same launch
+// sequence serves every step (and is captured once as a graph).
+void launch_step(const DMesh &m, const DState &s, const DParams &p, hipStream_t st, Prof *prof) {
   TIMED(prof, kKReset, (k_reset<<<1, 64, 0, st>>>(s)));
   TIMED(prof, kKCellClass, (k_cell_class<<<grid_for(m.nc, kBlock), kBlock, 0, st>>>(m, s, p)));
   TIMED(prof, kKPointPrep, (k_point_prep<<<grid_for(m.np, kBlock), kBlock, 0, st>>>(m, s)));
@@ -1060,13 +1065,13 @@ void launch_step(const DMesh &m, const DState &s, const DParams &p, int step, hi
   gf = gf < 8192 ? gf : 8192;
   gf = (gf + kXcds - 1) / kXcds * kXcds;
   if (m.maxn <= 3)
-    TIMED(prof, kKFlux, (k_flux<3><<<gf, kBlock, 0, st>>>(m, s, p, step)));
+    TIMED(prof, kKFlux, (k_flux<3><<<gf, kBlock, 0, st>>>(m, s, p)));
   else if (m.maxn == 4)
-    TIMED(prof, kKFlux, (k_flux<4><<<gf, kBlock, 0, st>>>(m, s, p, step)));
+    TIMED(prof, kKFlux, (k_flux<4><<<gf, kBlock, 0, st>>>(m, s, p)));
   else
-    TIMED(prof, kKFlux, (k_flux<kMaxFacePoints><<<gf, kBlock, 0, st>>>(m, s, p, step)));
-  TIMED(prof, kKClip, (k_clip_fast<<<kFastGrid, kFastBlock, 0, st>>>(m, s, p, step)));
-  TIMED(prof, kKClipGeneral, (k_clip_general<<<4096, kClipBlock, 0, st>>>(m, s, p, step)));
+    TIMED(prof, kKFlux, (k_flux<kMaxFacePoints><<<gf, kBlock, 0, st>>>(m, s, p)));
+  TIMED(prof, kKClip, (k_clip_fast<<<kFastGrid, kFastBlock, 0, st>>>(m, s, p)));
+  TIMED(prof, kKClipGeneral, (k_clip_general<<<4096, kClipBlock, 0, st>>>(m, s, p)));
   TIMED(prof, kKFaceSum, (k_face_sum<<<1024, kBlock, 0, st>>>(m, s, p)));
   TIMED(prof, kKUpdate, (k_update<<<grid_for(m.nc, kBlock), kBlock, 0, st>>>(m, s)));
   TIMED(prof, kKLedger, (k_ledger_part<<<kLedgerParts, kBlock, 0, st>>>(m, s),

@@ -63,6 +63,11 @@ struct vof_mesh {
   double *stats_buf = nullptr;  // 4 doubles
   bool profiling = false;
   Prof prof;
+  // the launch sequence of one step captured once (valid while the kernel
+  // arguments -- buffers and parameters -- stay as captured)
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t step_graph = nullptr;
+  bool graph_ok = false;
   double prof_ms[kKNum] = {0};
   int64_t prof_count[kKNum] = {0};
 
@@ -81,6 +86,8 @@ struct vof_mesh {
     return VOF_OK;
   }
   ~vof_mesh() {
+    if (step_graph) (void)hipGraphExecDestroy(step_graph);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (int i = 0; i < prof.cap; ++i) {
       (void)hipEventDestroy(prof.recs[i].a);
       (void)hipEventDestroy(prof.recs[i].b);
@@ -178,6 +185,30 @@ vof_params from_dparams(const DParams &d) {
   p.gradient_zero = d.grad_zero;
   p.check_stencil = d.check_stencil;
   return p;
+}
+
+// Capture the launch sequence of one step on a private stream (the caller's
+// stream may be the null stream, which cannot be captured).  The step
+// contains kernels only: no memset or copy nodes.
+vof_status build_step_graph(vof_mesh *m) {
+  if (!m->cap_stream) HIP_OR_FAIL(hipStreamCreateWithFlags(&m->cap_stream, hipStreamNonBlocking));
+  if (m->step_graph) {
+    HIP_OR_FAIL(hipGraphExecDestroy(m->step_graph));
+    m->step_graph = nullptr;
+  }
+  hipGraph_t g = nullptr;
+  HIP_OR_FAIL(hipStreamBeginCapture(m->cap_stream, hipStreamCaptureModeThreadLocal));
+  launch_step(m->dm, m->ds, m->dp, m->cap_stream, nullptr);
+  hipError_t e = hipStreamEndCapture(m->cap_stream, &g);
+  if (e != hipSuccess) return fail(VOF_EDEVICE, "step capture: %s", hipGetErrorString(e));
+  e = hipGraphInstantiate(&m->step_graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    m->step_graph = nullptr;
+    return fail(VOF_EDEVICE, "step graph: %s", hipGetErrorString(e));
+  }
+  m->graph_ok = true;
+  return VOF_OK;
 }
 
 }  // namespace
@@ -392,7 +423,7 @@ vof_status vof_mesh_upload(vof_context *ctx, const vof_mesh_desc *d, vof_mesh **
   ALLOC(ds.vphase, nf); ALLOC(ds.vscale, nf); ALLOC(ds.iters, nf); ALLOC(ds.kind, nf); ALLOC(ds.fstatus, nf);
   ALLOC(ds.icells, nc); ALLOC(ds.gfaces, nf); ALLOC(ds.tetvol, nf * (int64_t)dm.tpf);
   ALLOC(ds.defer, nf * (int64_t)dm.tpf);
-  ALLOC(ds.work, kWNum); ALLOC(ds.cnt, kCntNum); ALLOC(ds.flags, 1); ALLOC(ds.ledger, 1);
+  ALLOC(ds.stepno, 1); ALLOC(ds.work, kWNum); ALLOC(ds.cnt, kCntNum); ALLOC(ds.flags, 1); ALLOC(ds.ledger, 1);
   ALLOC(ds.part, 256);
   ALLOC(m->stats_buf, 4);
 #undef ALLOC
@@ -487,6 +518,7 @@ vof_status vof_set_params(vof_mesh *m, const vof_params *p) {
     if ((rc = m->alloc(&m->ds.tetgross, m->dm.nf * (int64_t)m->dm.tpf))) return rc;
   }
   to_dparams(*p, m->dp);
+  m->graph_ok = false;
   return VOF_OK;
 }
 
@@ -554,11 +586,14 @@ vof_status vof_advect(vof_mesh *m, int32_t n_steps, const double *dt, const doub
     if ((rc = m->alloc(&m->ds.dt, n_steps))) return rc;
     if ((rc = m->alloc(&m->ds.sc, n_steps))) return rc;
     m->step_cap = n_steps;
+    m->graph_ok = false;
   } else {
     HIP_OR_FAIL(hipStreamSynchronize(s));
   }
   HIP_OR_FAIL(hipMemcpy(m->ds.dt, dt, sizeof(double) * n_steps, hipMemcpyHostToDevice));
   HIP_OR_FAIL(hipMemcpy(m->ds.sc, scale, sizeof(double) * n_steps, hipMemcpyHostToDevice));
+  const int32_t first = 0;
+  HIP_OR_FAIL(hipMemcpy(m->ds.stepno, &first, sizeof first, hipMemcpyHostToDevice));
   if (m->profiling) {
     // room for every kernel of every step; pairs are folded into totals by
     // vof_read_profile
@@ -578,10 +613,16 @@ vof_status vof_advect(vof_mesh *m, int32_t n_steps, const double *dt, const doub
     }
     m->prof.st = s;
   }
-  for (int32_t i = 0; i < n_steps; ++i) {
-    launch_step(m->dm, m->ds, m->dp, i, s, m->profiling ? &m->prof : nullptr);
-    HIP_OR_FAIL(hipGetLastError());
+  if (m->profiling) {
+    // kernel by kernel, each bracketed by timing events
+    for (int32_t i = 0; i < n_steps; ++i) {
+      launch_step(m->dm, m->ds, m->dp, s, &m->prof);
+      HIP_OR_FAIL(hipGetLastError());
+    }
+    return VOF_OK;
   }
+  if (!m->graph_ok && (rc = build_step_graph(m))) return rc;
+  for (int32_t i = 0; i < n_steps; ++i) HIP_OR_FAIL(hipGraphLaunch(m->step_graph, s));
   return VOF_OK;
 }
 

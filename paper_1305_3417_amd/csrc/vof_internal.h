@@ -107,6 +107,7 @@ struct DState {
   uint32_t *flags;      // latched status bits
   double *ledger;       // accumulated boundary phase volume
   double *part;         // partial sums of the ledger (256)
+  int32_t *stepno;      // index into dt / sc of the step being run
   double *dt;           // per-step dt (device copy)
   double *sc;           // per-step scale
 };
@@ -131,8 +132,7 @@ void launch_mesh_geometry(const DMesh &m, double4 *X, const double *pts, double4
                           double4 *bbhi, uint32_t *flags, hipStream_t st);
 void launch_point_velocity(const DMesh &m, const double *U0c, double4 *U, double4 *XU,
                            hipStream_t st);
-void launch_step(const DMesh &m, const DState &s, const DParams &p, int step, hipStream_t st,
-                 Prof *prof);
+void launch_step(const DMesh &m, const DState &s, const DParams &p, hipStream_t st, Prof *prof);
 void launch_reconstruct(const DMesh &m, const DState &s, const DParams &p, hipStream_t st);
 void launch_stats(const DMesh &m, const DState &s, double *out4, hipStream_t st);
 double host_tet_clip(const double *tet, int n_planes, const double *planes);
