@@ -47,6 +47,7 @@ KERNEL_FUNCS = {"flux": "k_flux", "clip": "k_clip_fast", "clip_general": "k_clip
                 "plane": "k_plane", "update": "k_update", "point_prep": "k_point_prep",
                 "cell_class": "k_cell_class", "face_sum": "k_face_sum"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_deform3d_128.md")
+WORKLOAD = ["deform3d"]  # set from the command line
 
 
 def kernel_source_hash():
@@ -66,7 +67,8 @@ def recorded_traffic(kernel, n):
     """HBM bytes per launch of `kernel` from the committed FETCH_SIZE / WRITE_SIZE
     summary (copy-calibrated), or None when that summary was taken on other
     kernel sources or another mesh size."""
-    if n != 128 or kernel not in KERNEL_FUNCS or not os.path.exists(TRAFFIC_FILE):
+    if n != 128 or kernel not in KERNEL_FUNCS or not os.path.exists(TRAFFIC_FILE) or \
+            WORKLOAD[0] != "deform3d":
         return None
     with open(TRAFFIC_FILE) as fh:
         line = next((ln for ln in fh if ln.startswith("traffic-json:")), None)
@@ -92,7 +94,7 @@ def cpu_baseline(w, alpha, step):
     t = time.perf_counter() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": n_flux / t, "unit": "face-fluxes/s", "cores": threads, "kind": "oracle",
-            "sample": f"one whole step ({n_flux} flux faces) of the 128^3 deformation case "
+            "sample": f"one whole step ({n_flux} flux faces) of the same {w.name} case "
                       f"from the benchmark's final state, {t:.1f} s"}
 
 
@@ -154,6 +156,9 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--n", type=int, default=128, help="mesh is n^3 hexahedra")
+    ap.add_argument("--workload", choices=["deform3d", "shear3d"], default="deform3d",
+                    help="deform3d (eq. 4.6, fixed dt; the headline case) or shear3d "
+                         "(eq. 4.5, adaptive Courant dt)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -183,10 +188,12 @@ def main():
         print(json.dumps({"calibrate_copy_bytes_read": n * 8, "bytes_written": n * 8,
                           "launches": 3}), flush=True)
         return
+    WORKLOAD[0] = args.workload
     K, Wm = args.steps, args.warmup
     P = min(K, 20)  # profiled steps after the timed region
-    log(f"[bench] generating deform3d {args.n}^3")
-    w = W.deform3d(args.n, steps=Wm + K + P + 1)
+    log(f"[bench] generating {args.workload} {args.n}^3")
+    make = W.deform3d if args.workload == "deform3d" else W.shear3d
+    w = make(args.n, steps=Wm + K + P + 1)
     ctx = vof.vof_context_create(0)
     log("[bench] uploading mesh")
     mesh = vof.upload_mesh(ctx, w.mesh)
@@ -268,9 +275,12 @@ def main():
         "metric": METRIC, "value": value, "unit": "face-fluxes/s", "n_gpus": 1, "steps": K,
         "warmup": Wm, "ms_per_step": elapsed * 1e3 / K, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"deform3d hex {args.n}^3 (eq. 4.6, T=3, sphere r=0.15 at "
-                               f"(0.35,0.35,0.35), Co 0.5, dt=1/{4 * args.n}), steps "
-                               f"{Wm}..{Wm + K - 1}",
+        "config": {"workload": (f"deform3d hex {args.n}^3 (eq. 4.6, T=3, sphere r=0.15 at "
+                                f"(0.35,0.35,0.35), Co 0.5, dt=1/{4 * args.n}), steps "
+                                f"{Wm}..{Wm + K - 1}" if args.workload == "deform3d" else
+                                f"shear3d hex {args.n}^3 (eq. 4.5, T=3, u_max=1, R=0.5, sphere "
+                                f"r=0.15 at (0.5,0.75,0.25), adaptive Courant dt at Co 0.5), "
+                                f"steps {Wm}..{Wm + K - 1}"),
                    "cells": int(w.mesh.n_cells), "faces": int(w.mesh.n_faces),
                    "parallelism": "single GPU"},
         "cell_updates_per_s": w.mesh.n_cells * K / elapsed,

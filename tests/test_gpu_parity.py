@@ -217,6 +217,29 @@ def test_step_graph_replays_match_eager(vof, ctx):
         m.close()
 
 
+def test_shear_adaptive_courant(vof, ctx, oracle_mod):
+    """The shear field (eq. 4.5) with the adaptive Courant time step through
+    the same kernels, 16^3 to T = 3 (71 steps, through the reversal): one step
+    at t = 0 and one from the oracle's state at mid-run (the longest steps),
+    then alpha and the advection error E_g after the whole run."""
+    import dataclasses
+    w = W.shear3d(16)
+    _compare_step(vof, ctx, oracle_mod, w, label="shear-16")
+    mid = w.n_steps // 2
+    o, a_mid, st, lam, vp = oracle_run(oracle_mod, w, steps=mid)
+    wm = dataclasses.replace(w, dt=w.dt[mid:], scale=w.scale[mid:])
+    _compare_step(vof, ctx, oracle_mod, wm, alpha=a_mid, label="shear-16-mid")
+    g = gpu_run(vof, ctx, w)
+    o, a, st, lam, vp = oracle_run(oracle_mod, w)
+    assert np.abs(g["alpha"] - a).max() < 1e-10
+    V = o.geometry()[0]
+    eg_gpu = float((V * np.abs(g["alpha"] - w.alpha0)).sum())
+    eg_orc = float((V * np.abs(a - w.alpha0)).sum())
+    print(f"[shear-16] E_g gpu {eg_gpu:.6e} oracle {eg_orc:.6e}", flush=True)
+    assert abs(eg_gpu - eg_orc) <= 1e-10 * eg_orc
+    g["mesh"].close()
+
+
 def test_empty_and_full_fields(vof, ctx):
     w = W.deform3d(12, steps=3)
     for val in (0.0, 1.0):

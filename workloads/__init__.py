@@ -15,6 +15,8 @@ Workloads (sizes as in the paper's advection tests, Section 4.2):
   rotate_tets jittered Kuhn tets on an N^3 lattice (N=80 full), slotted sphere
               r=0.15 at (0.5, 0.75, 0.5), slot width 0.05, rigid rotation about
               z through (0.5, 0.5) at 2 pi per unit time, Co 0.5
+  shear3d     N^3 hex, sphere r=0.15 at (0.5, 0.75, 0.25), shear field (eq. 4.5)
+              with cos(pi t/T), T=3, u_max=1, R=0.5, adaptive Courant time step
 """
 from __future__ import annotations
 
@@ -134,4 +136,46 @@ def slab_exact(w: Workload, k: int) -> np.ndarray:
     return np.clip((np.minimum(hi, b) - np.maximum(lo, a)) / (hi - lo), 0.0, 1.0)
 
 
-WORKLOADS = {"disc2d": disc2d, "deform3d": deform3d, "rotate_tets": rotate_tets}
+def courant_schedule(Umax: float, h: float, T: float, co: float = 0.5, growth: float = 2.0,
+                     steps: int | None = None):
+    """Adaptive time steps for a field U0(x) cos(pi t / T) (Section 4.2.2): the
+    Courant number of the current step, from the largest velocity of that step
+    (at t_n + dt_n / 2), sets the next step to meet `co` again:
+    dt_{n+1} = co h / (Umax |cos(pi (t_n + dt_n/2) / T)|).  The step never
+    exceeds `growth` times the first one (the field vanishes at t = T/2, where
+    the rule alone is unbounded), and the last step ends at T exactly.
+    Returns (dt, scale) with scale_n = cos(pi (t_n + dt_n/2) / T)."""
+    dt0 = co * h / Umax
+    dts, scs = [], []
+    t, dt = 0.0, dt0
+    while True:
+        if steps is None and t + dt >= T * (1.0 - 1e-12):
+            dt = T - t
+        s = np.cos(np.pi * (t + 0.5 * dt) / T)
+        dts.append(dt)
+        scs.append(s)
+        t += dt
+        if (steps is not None and len(dts) == steps) or (steps is None and t >= T * (1.0 - 1e-12)):
+            break
+        dt = min(co * h / (Umax * max(abs(s), 1e-300)), growth * dt0)
+    return np.array(dts), np.array(scs)
+
+
+def shear3d(n: int = 64, steps: int | None = None, T: float = 3.0, co: float = 0.5,
+            centre=(0.5, 0.75, 0.25), radius: float = 0.15, growth: float = 2.0) -> Workload:
+    """Sphere in the shear field (eq. 4.5) with the adaptive Courant time step.
+
+    Umax is the largest |U0| at the cell centroids.  The default runs to T."""
+    m = hex_mesh(n, n, n)
+    a0 = fields.ball_box_fraction(centre, radius, m.cell_lo, m.cell_hi)
+    Uc = fields.shear_velocity(m.cell_centroids())
+    F0 = fields.flux_shear(m)
+    Umax = float(np.linalg.norm(Uc, axis=1).max())
+    dt, sc = courant_schedule(Umax, 1.0 / n, T, co, growth, steps)
+    return Workload("shear3d", m, a0, Uc, F0, dt, sc,
+                    meta={"n": n, "T": T, "co": co, "centre": list(centre), "radius": radius,
+                          "Umax": Umax, "growth": growth})
+
+
+WORKLOADS = {"disc2d": disc2d, "deform3d": deform3d, "rotate_tets": rotate_tets,
+             "shear3d": shear3d}

@@ -244,6 +244,58 @@ def _constant_edge_integral(p, q, U):
     return 0.25 * (np.cross(np.broadcast_to(U, p.shape), p + q) * (q - p)).sum(1)
 
 
+def shear_velocity(x, u_max: float = 1.0, R: float = 0.5):
+    """Spatial part of the shear field (Section 4.2.2, eq. 4.5), read as
+    (sin 2πy sin²πx, -sin 2πx sin²πy, u_max (1 - r/R)²), r the distance to the
+    axis x = y = 1/2."""
+    X, Y = x[..., 0], x[..., 1]
+    s = sinpi
+    r = np.hypot(X - 0.5, Y - 0.5)
+    return np.stack([s(2 * Y) * s(X) ** 2, -s(2 * X) * s(Y) ** 2,
+                     u_max * (1.0 - r / R) ** 2], -1)
+
+
+def _shear_Ay(x, y, u_max: float, R: float):
+    """A_y(x, y) = ∫_0^x w(s, y) ds for w = u_max (1 - r/R)², in closed form:
+    with t = s - 1/2 and a = y - 1/2, ∫ r dt = (t r + a² asinh(t/|a|)) / 2 and
+    ∫ r² dt = t³/3 + a² t."""
+    a = y - 0.5
+    aa = np.abs(a)
+
+    def F1(t):
+        r = np.hypot(t, a)
+        safe = np.where(aa > 0, aa, 1.0)
+        return 0.5 * (t * r + np.where(aa > 0, a * a * np.arcsinh(t / safe), 0.0))
+
+    def F2(t):
+        return t ** 3 / 3.0 + a * a * t
+
+    t1, t0 = x - 0.5, -0.5
+    return u_max * (x - 2.0 / R * (F1(t1) - F1(t0)) + (F2(t1) - F2(t0)) / (R * R))
+
+
+def _shear_edge_integral(p, q, u_max: float = 1.0, R: float = 0.5, order: int = 24):
+    """Line integral of A = (0, A_y(x, y), ψ(x, y)), ψ = sin²πx sin²πy / π, along
+    axis-aligned edges: z-edges ψ Δz exactly, y-edges ∫ A_y dy by Gauss-Legendre,
+    x-edges 0 (curl A = shear_velocity)."""
+    d = q - p
+    out = np.zeros(p.shape[0])
+    ze = np.abs(d[:, 2]) > 0
+    s = sinpi
+    out[ze] = s(p[ze, 0]) ** 2 * s(p[ze, 1]) ** 2 / np.pi * d[ze, 2]
+    ye = np.abs(d[:, 1]) > 0
+    if ye.any():
+        xg, wg = np.polynomial.legendre.leggauss(order)
+        x, y0, y1 = p[ye, 0], p[ye, 1], q[ye, 1]
+        acc = np.zeros(x.shape[0])
+        for tk, wk in zip(0.5 * (xg + 1.0), 0.5 * wg):
+            acc += wk * _shear_Ay(x, y0 + tk * (y1 - y0), u_max, R)
+        out[ye] = acc * (y1 - y0)
+    if (np.abs(d) > 0).sum(1).max(initial=0) > 1:
+        raise ValueError("shear fluxes are defined for axis-aligned (hex) edges")
+    return out
+
+
 def face_flux_from_edges(mesh: Mesh, edge_integral):
     """F_f = Σ over the face's directed edges of ∫ A·dl (edge values shared)."""
     offs = mesh.face_offsets
@@ -280,3 +332,7 @@ def flux_deformation(mesh: Mesh):
 def flux_rotation(mesh: Mesh, omega, origin, axis=(0.0, 0.0, 1.0)):
     o = np.asarray(origin, dtype=np.float64)
     return face_flux_from_edges(mesh, lambda p, q: _rotation_edge_integral(p, q, omega, o, axis))
+
+
+def flux_shear(mesh: Mesh, u_max: float = 1.0, R: float = 0.5):
+    return face_flux_from_edges(mesh, lambda p, q: _shear_edge_integral(p, q, u_max, R))
