@@ -69,6 +69,8 @@ def lib():
         L.orc_set_planes.argtypes = [vp, vp, vp, vp]
         L.orc_point_values.argtypes = [vp, vp, vp]
         L.orc_nag_gradient.argtypes = [vp, vp, vp]
+        L.orc_lsq_gradient.argtypes = [vp, vp, vp]
+        L.orc_set_gradient.argtypes = [vp, C.c_int]
         L.orc_set_point_velocity.argtypes = [vp, vp, vp]
         L.orc_reconstruct_subset.argtypes = [vp, vp, i64, vp]
         L.orc_get_planes.argtypes = [vp, vp, vp, vp]
@@ -95,7 +97,7 @@ class OStats(C.Structure):
 class Oracle:
     """The oracle on one mesh (points, face CSR, owner, neighbour)."""
 
-    def __init__(self, mesh, eps: float = 1e-12):
+    def __init__(self, mesh, eps: float = 1e-12, gradient: str = "nag"):
         L = lib()
         self.mesh = mesh
         self._keep = [np.ascontiguousarray(mesh.points, dtype=np.float64),
@@ -111,6 +113,14 @@ class Oracle:
         self.h = L.orc_create(self.np_, self.nc, self.nf, self.ni, _p(pts), _p(offs), _p(fp),
                               _p(own), _p(nei))
         L.orc_set_eps(self.h, eps)
+        self.set_gradient(gradient)
+
+    def set_gradient(self, kind: str):
+        """Gradient of the reconstruction: "nag" (Section 2.2.1) or "lsq" (the
+        generalized least-squares gradient of the same section)."""
+        if kind not in ("nag", "lsq"):
+            raise ValueError(kind)
+        lib().orc_set_gradient(self.h, 1 if kind == "lsq" else 0)
 
     def __del__(self):
         if getattr(self, "h", None):
@@ -257,6 +267,12 @@ class Oracle:
         phi = np.ascontiguousarray(phi, dtype=np.float64)
         g = np.empty((self.nc, 3))
         lib().orc_nag_gradient(self.h, _p(phi), _p(g))
+        return g
+
+    def lsq_gradient(self, phi):
+        phi = np.ascontiguousarray(phi, dtype=np.float64)
+        g = np.empty((self.nc, 3))
+        lib().orc_lsq_gradient(self.h, _p(phi), _p(g))
         return g
 
 

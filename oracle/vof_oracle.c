@@ -271,6 +271,7 @@ typedef struct {
   double *ps;                /* plane position                         */
   double *grad;              /* NAG gradient (3 nc)                    */
   double eps;                /* reconstruction tolerance               */
+  int grad_kind;             /* 0 NAG (Section 2.2.1), 1 generalized LSQ */
 } omesh;
 
 static int cmp_i32(const void *a, const void *b) {
@@ -485,6 +486,8 @@ void orc_destroy(omesh *M) {
 }
 
 void orc_set_eps(omesh *M, double eps) { M->eps = eps; }
+/* gradient of the reconstruction: 0 NAG, 1 generalized LSQ */
+void orc_set_gradient(omesh *M, int kind) { M->grad_kind = kind; }
 
 /* geometry getters for the tests */
 void orc_geometry(const omesh *M, double *V, double *xc, double *S, double *cf) {
@@ -728,6 +731,64 @@ static void nag_gradient(const omesh *M, int64_t c, const double *alpha, const d
   for (int j = 0; j < 3; ++j) g[j] /= M->V[c];            /* eq. 2.12 */
 }
 
+/* Generalized least-squares gradient (Section 2.2.1, after the NAG
+ * gradient): over the point neighbours k of cell c (the cells sharing a point
+ * with it), minimise sum_k w_ck^2 E_ck^2 with E_ck = -(phi_c - phi_k) +
+ * g . (x_c - x_k) and w_ck the inverse distance of the centroids.  The normal
+ * equations (sum w^2 d d^T) g = sum w^2 d (phi_k - phi_c), d = x_k - x_c, are
+ * a 3x3 system, solved here by Cramer's rule. */
+static void lsq_gradient(const omesh *M, int64_t c, const double *phi, double *g) {
+  int32_t *nb = NULL;
+  int64_t nn = 0, cap = 0;
+  for (int64_t k = M->cf_off[c]; k < M->cf_off[c + 1]; ++k) {
+    int64_t f = M->cf_face[k];
+    for (int64_t i = M->foff[f]; i < M->foff[f + 1]; ++i) {
+      int64_t p = M->fpts[i];
+      for (int64_t j = M->pc_off[p]; j < M->pc_off[p + 1]; ++j) {
+        if (M->pc_cell[j] == c) continue;
+        if (nn == cap) {
+          cap = cap ? 2 * cap : 64;
+          nb = realloc(nb, sizeof(int32_t) * cap);
+        }
+        nb[nn++] = M->pc_cell[j];
+      }
+    }
+  }
+  qsort(nb, nn, sizeof(int32_t), cmp_i32);
+  double A[3][3] = {{0}}, b[3] = {0};
+  for (int64_t i = 0; i < nn; ++i) {
+    if (i > 0 && nb[i] == nb[i - 1]) continue;     /* each neighbour once */
+    int64_t k = nb[i];
+    double d[3];
+    v_sub(&M->xc[3 * k], &M->xc[3 * c], d);
+    double w2 = 1.0 / v_dot(d, d);                 /* w_ck^2, w = 1/|d| */
+    double dphi = phi[k] - phi[c];
+    for (int r = 0; r < 3; ++r) {
+      b[r] += w2 * d[r] * dphi;
+      for (int q = 0; q < 3; ++q) A[r][q] += w2 * d[r] * d[q];
+    }
+  }
+  free(nb);
+  double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
+               A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+               A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+  for (int r = 0; r < 3; ++r) {
+    double Ar[3][3];
+    memcpy(Ar, A, sizeof A);
+    for (int q = 0; q < 3; ++q) Ar[q][r] = b[q];     /* column r replaced by b */
+    double dr = Ar[0][0] * (Ar[1][1] * Ar[2][2] - Ar[1][2] * Ar[2][1]) -
+                Ar[0][1] * (Ar[1][0] * Ar[2][2] - Ar[1][2] * Ar[2][0]) +
+                Ar[0][2] * (Ar[1][0] * Ar[2][1] - Ar[1][1] * Ar[2][0]);
+    g[r] = det != 0.0 ? dr / det : 0.0;
+  }
+}
+
+static void cell_gradient(const omesh *M, int64_t c, const double *alpha, const double *ap,
+                          double *g) {
+  if (M->grad_kind == 1) lsq_gradient(M, c, alpha, g);
+  else nag_gradient(M, c, alpha, ap, g);
+}
+
 /* Interface positioning (Section 2.2.2, Algorithm 1): the fill level
  * g(s) = |C ∩ {n.x <= s}| / V_c - alpha rises monotonically from -alpha to
  * 1 - alpha over [min n.x_v, max n.x_v]; secant iterations, and once the
@@ -798,7 +859,7 @@ int64_t orc_reconstruct(omesh *M, const double *alpha, int8_t *cls, double *grad
     else if (a >= 1.0 - M->eps) M->cls[c] = 2;
     else {
       double g[3];
-      nag_gradient(M, c, alpha, ap, g);
+      cell_gradient(M, c, alpha, ap, g);
       memcpy(&M->grad[3 * c], g, 24);
       double gn = v_norm(g);
       double hc = cbrt(M->V[c]);
@@ -1050,6 +1111,12 @@ void orc_point_values(const omesh *M, const double *phi, double *out) {
   }
 }
 
+/* generalized LSQ gradient of an arbitrary cell field on every cell (tests) */
+void orc_lsq_gradient(const omesh *M, const double *phi, double *grad) {
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t c = 0; c < M->nc; ++c) lsq_gradient(M, c, phi, &grad[3 * c]);
+}
+
 /* NAG gradient of an arbitrary cell field on every cell (tests) */
 void orc_nag_gradient(const omesh *M, const double *phi, double *grad) {
   double *ap = malloc(sizeof(double) * M->np);
@@ -1080,7 +1147,7 @@ void orc_reconstruct_subset(omesh *M, const double *alpha, int64_t ncells, const
     int64_t c = cells[i];
     if (M->cls[c] != 1) continue;
     double g[3];
-    nag_gradient(M, c, alpha, ap, g);
+    cell_gradient(M, c, alpha, ap, g);
     memcpy(&M->grad[3 * c], g, 24);
     double gn = v_norm(g);
     if (gn * cbrt(M->V[c]) < 1e-8) { M->cls[c] = 3; continue; }

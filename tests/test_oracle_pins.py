@@ -147,6 +147,39 @@ def test_nag_exact_for_linear_fields(oracle_mod):
     assert np.abs(G[inner] - g).max() < 1e-12
 
 
+@pytest.mark.parametrize("meshkind", ["hex", "tets"])
+def test_lsq_gradient_exact_for_linear_fields(oracle_mod, meshkind):
+    """The generalized LSQ gradient has zero residual for a linear field on
+    any mesh, boundary cells and jittered tets included."""
+    m = W.hex_mesh(5, 4, 6) if meshkind == "hex" else W.kuhn_tet_mesh(4, 0.2, 7)
+    o = oracle_mod.Oracle(m)
+    V, xc, S, cf = o.geometry()
+    g = np.array([0.3, -1.7, 2.2])
+    G = o.lsq_gradient(0.1 + xc @ g)
+    assert np.abs(G - g).max() < 1e-12
+
+
+def test_lsq_gradient_is_the_weighted_least_squares_solution(oracle_mod):
+    """Against numpy's SVD least squares on the weighted system, with the
+    point-neighbour stencil built here from the cells' vertex lists."""
+    m = W.kuhn_tet_mesh(3, 0.2, 11)
+    o = oracle_mod.Oracle(m)
+    V, xc, S, cf = o.geometry()
+    rng = np.random.default_rng(4)
+    phi = rng.random(m.n_cells)
+    G = o.lsq_gradient(phi)
+    cells_of_point = [[] for _ in range(m.n_points)]
+    for c, verts in enumerate(m.cell_verts):
+        for p in verts:
+            cells_of_point[p].append(c)
+    for c in range(m.n_cells):
+        nb = sorted({k for p in m.cell_verts[c] for k in cells_of_point[p]} - {c})
+        D = xc[nb] - xc[c]
+        w = 1.0 / np.linalg.norm(D, axis=1)
+        sol = np.linalg.lstsq(w[:, None] * D, w * (phi[nb] - phi[c]), rcond=None)[0]
+        assert np.abs(G[c] - sol).max() <= 1e-11 * max(1.0, np.abs(sol).max())
+
+
 # --------------------------------------------------------------------------
 # flux polyhedra (eqs. 2.16-2.19) and flux correction (Section 2.3)
 # --------------------------------------------------------------------------
