@@ -121,7 +121,13 @@ vof_status vof_mesh_get_info(const vof_mesh *mesh, vof_mesh_info *out);
  * position_max_iter 100, gradient_zero 1e-8 (|grad alpha| h_c below this makes
  * an interface cell homogeneous), check_stencil 0 (1: also clip every
  * flux tet against the empty cells of its stencil and flag any volume that
- * leaves the stencil). */
+ * leaves the stencil), gradient VOF_GRADIENT_NAG (the interface normal from
+ * the node-averaged Gauss gradient, eqs. 2.6-2.12; VOF_GRADIENT_LSQ: from the
+ * generalized least-squares gradient over the cells sharing a point with the
+ * cell, inverse-distance weighted, Section 2.2.1 -- the first reconstruction
+ * with it builds that cell stencil on the host). */
+#define VOF_GRADIENT_NAG 0
+#define VOF_GRADIENT_LSQ 1
 typedef struct {
   double eps;
   double correction_rtol;
@@ -130,6 +136,7 @@ typedef struct {
   int32_t position_max_iter;
   double gradient_zero;
   int32_t check_stencil;
+  int32_t gradient;
 } vof_params;
 vof_status vof_get_params(const vof_mesh *mesh, vof_params *out);
 vof_status vof_set_params(vof_mesh *mesh, const vof_params *p);

@@ -37,6 +37,8 @@ VOF_FACE_ITERS = 2
 VOF_FACE_KIND = 3
 VOF_FACE_STATUS = 4
 VOF_MAX_FACE_POINTS = 8
+VOF_GRADIENT_NAG = 0
+VOF_GRADIENT_LSQ = 1
 
 EXPORTED = [
     "vof_context_create", "vof_context_destroy", "vof_last_error", "vof_version",
@@ -72,7 +74,7 @@ class vof_params(C.Structure):
     _fields_ = [("eps", C.c_double), ("correction_rtol", C.c_double),
                 ("correction_max_iter", C.c_int32), ("position_tol", C.c_double),
                 ("position_max_iter", C.c_int32), ("gradient_zero", C.c_double),
-                ("check_stencil", C.c_int32)]
+                ("check_stencil", C.c_int32), ("gradient", C.c_int32)]
 
 
 class vof_stats(C.Structure):

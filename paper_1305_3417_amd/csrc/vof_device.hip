@@ -325,31 +325,57 @@ __global__ __launch_bounds__(kBlock) void k_plane(DMesh m, DState s, DParams p) 
     const int64_t c = s.icells[i];
     const double a = s.alpha[c];
     const int k0 = m.cf_off[c], nfc = m.cf_off[c + 1] - k0;
-    // gradient: lanes over the faces of the cell
-    v3 gl = mk3(0, 0, 0);
-    if (lane < nfc) {
-      int sf = m.cf[k0 + lane];
-      int f = sf >= 0 ? sf : ~sf;
-      double sg = sf >= 0 ? 1.0 : -1.0;
-      int b = m.foff[f], nn = m.foff[f + 1] - b;
-      double fp = 0.0;
-      for (int j = 0; j < nn; ++j) fp += s.alpha_p[m.fpts[b + j]];
-      fp /= nn;
-      v3 cf = xyz(m.C[f]);
-      double num = 0.0, den = 0.0;
-      int qa = m.fpts[b];
-      for (int j = 0; j < nn; ++j) {
-        int qb = m.fpts[b + ((j + 1 == nn) ? 0 : j + 1)];
-        v3 t = cross(xyz(m.X[qa]) - cf, xyz(m.X[qb]) - cf);
-        double A = 0.5 * sqrt(dot(t, t));
-        num += A * (fp + s.alpha_p[qa] + s.alpha_p[qb]) / 3.0;
-        den += A;
-        qa = qb;
-      }
-      gl = (sg * (num / den)) * xyz(m.S[f]);
-    }
     const double Vc = m.V[c];
-    v3 g = (1.0 / Vc) * mk3(wave_sum_d(gl.x), wave_sum_d(gl.y), wave_sum_d(gl.z));
+    v3 g;
+    if (p.gradient == 1) {
+      // generalized least squares (Section 2.2.1): lanes over the cells that
+      // share a point with c; (sum w^2 d d^T) g = sum w^2 d (alpha_k - alpha_c)
+      // with d = x_k - x_c, w = 1/|d|, solved by Cramer's rule
+      const v3 xc = xyz(m.XC[c]);
+      double a00 = 0, a01 = 0, a02 = 0, a11 = 0, a12 = 0, a22 = 0, b0 = 0, b1 = 0, b2 = 0;
+      for (int e = m.cpn_off[c] + lane; e < m.cpn_off[c + 1]; e += 64) {
+        const int k = m.cpn[e];
+        const v3 d = xyz(m.XC[k]) - xc;
+        const double w2 = 1.0 / dot(d, d);
+        const double da = s.alpha[k] - a;
+        a00 += w2 * d.x * d.x; a01 += w2 * d.x * d.y; a02 += w2 * d.x * d.z;
+        a11 += w2 * d.y * d.y; a12 += w2 * d.y * d.z; a22 += w2 * d.z * d.z;
+        b0 += w2 * d.x * da; b1 += w2 * d.y * da; b2 += w2 * d.z * da;
+      }
+      a00 = wave_sum_d(a00); a01 = wave_sum_d(a01); a02 = wave_sum_d(a02);
+      a11 = wave_sum_d(a11); a12 = wave_sum_d(a12); a22 = wave_sum_d(a22);
+      b0 = wave_sum_d(b0); b1 = wave_sum_d(b1); b2 = wave_sum_d(b2);
+      const double det = det3(mk3(a00, a01, a02), mk3(a01, a11, a12), mk3(a02, a12, a22));
+      const double d0 = det3(mk3(b0, b1, b2), mk3(a01, a11, a12), mk3(a02, a12, a22));
+      const double d1 = det3(mk3(a00, a01, a02), mk3(b0, b1, b2), mk3(a02, a12, a22));
+      const double d2 = det3(mk3(a00, a01, a02), mk3(a01, a11, a12), mk3(b0, b1, b2));
+      g = det != 0.0 ? mk3(d0 / det, d1 / det, d2 / det) : mk3(0, 0, 0);
+    } else {
+      // NAG: lanes over the faces of the cell
+      v3 gl = mk3(0, 0, 0);
+      if (lane < nfc) {
+        int sf = m.cf[k0 + lane];
+        int f = sf >= 0 ? sf : ~sf;
+        double sg = sf >= 0 ? 1.0 : -1.0;
+        int b = m.foff[f], nn = m.foff[f + 1] - b;
+        double fp = 0.0;
+        for (int j = 0; j < nn; ++j) fp += s.alpha_p[m.fpts[b + j]];
+        fp /= nn;
+        v3 cf = xyz(m.C[f]);
+        double num = 0.0, den = 0.0;
+        int qa = m.fpts[b];
+        for (int j = 0; j < nn; ++j) {
+          int qb = m.fpts[b + ((j + 1 == nn) ? 0 : j + 1)];
+          v3 t = cross(xyz(m.X[qa]) - cf, xyz(m.X[qb]) - cf);
+          double A = 0.5 * sqrt(dot(t, t));
+          num += A * (fp + s.alpha_p[qa] + s.alpha_p[qb]) / 3.0;
+          den += A;
+          qa = qb;
+        }
+        gl = (sg * (num / den)) * xyz(m.S[f]);
+      }
+      g = (1.0 / Vc) * mk3(wave_sum_d(gl.x), wave_sum_d(gl.y), wave_sum_d(gl.z));
+    }
     double gn = sqrt(dot(g, g));
     if (!(gn * cbrt(Vc) >= p.grad_zero)) {
       if (lane == 0) {

@@ -162,6 +162,7 @@ vof_params default_params() {
   p.position_max_iter = 100;
   p.gradient_zero = 1e-8;
   p.check_stencil = 0;
+  p.gradient = VOF_GRADIENT_NAG;
   return p;
 }
 
@@ -173,6 +174,7 @@ void to_dparams(const vof_params &p, DParams &d) {
   d.pos_max_iter = p.position_max_iter;
   d.grad_zero = p.gradient_zero;
   d.check_stencil = p.check_stencil;
+  d.gradient = p.gradient;
 }
 
 vof_params from_dparams(const DParams &d) {
@@ -184,7 +186,73 @@ vof_params from_dparams(const DParams &d) {
   p.position_max_iter = d.pos_max_iter;
   p.gradient_zero = d.grad_zero;
   p.check_stencil = d.check_stencil;
+  p.gradient = d.gradient;
   return p;
+}
+
+// The cells sharing a point with each cell (sorted, the cell itself left
+// out): the stencil of the least-squares gradient, built once on the host
+// from the addressing already on the device.
+vof_status build_point_neighbours(vof_mesh *m) {
+  const DMesh &dm = m->dm;
+  const int64_t nc = dm.nc, nf = dm.nf, np = dm.np;
+  std::vector<int32_t> cf_off(nc + 1), foff(nf + 1), pc_off(np + 1);
+  std::vector<int32_t> cf, fpts, pc;
+  HIP_OR_FAIL(hipStreamSynchronize(m->ctx->stream));
+  HIP_OR_FAIL(hipMemcpy(cf_off.data(), dm.cf_off, sizeof(int32_t) * (nc + 1), hipMemcpyDeviceToHost));
+  HIP_OR_FAIL(hipMemcpy(foff.data(), dm.foff, sizeof(int32_t) * (nf + 1), hipMemcpyDeviceToHost));
+  HIP_OR_FAIL(hipMemcpy(pc_off.data(), dm.pc_off, sizeof(int32_t) * (np + 1), hipMemcpyDeviceToHost));
+  cf.resize(cf_off[nc]);
+  fpts.resize(foff[nf]);
+  pc.resize(pc_off[np]);
+  HIP_OR_FAIL(hipMemcpy(cf.data(), dm.cf, sizeof(int32_t) * cf.size(), hipMemcpyDeviceToHost));
+  HIP_OR_FAIL(hipMemcpy(fpts.data(), dm.fpts, sizeof(int32_t) * fpts.size(), hipMemcpyDeviceToHost));
+  HIP_OR_FAIL(hipMemcpy(pc.data(), dm.pc, sizeof(int32_t) * pc.size(), hipMemcpyDeviceToHost));
+  auto gather = [&](int64_t c, std::vector<int32_t> &buf) {
+    buf.clear();
+    for (int32_t k = cf_off[c]; k < cf_off[c + 1]; ++k) {
+      int32_t f = cf[k] >= 0 ? cf[k] : ~cf[k];
+      for (int32_t i = foff[f]; i < foff[f + 1]; ++i)
+        for (int32_t j = pc_off[fpts[i]]; j < pc_off[fpts[i] + 1]; ++j)
+          if (pc[j] != c) buf.push_back(pc[j]);
+    }
+    std::sort(buf.begin(), buf.end());
+    buf.erase(std::unique(buf.begin(), buf.end()), buf.end());
+  };
+  std::vector<int32_t> cnt(nc);
+#pragma omp parallel
+  {
+    std::vector<int32_t> buf;
+#pragma omp for schedule(static)
+    for (int64_t c = 0; c < nc; ++c) {
+      gather(c, buf);
+      cnt[c] = (int32_t)buf.size();
+    }
+  }
+  std::vector<int32_t> off(nc + 1, 0);
+  for (int64_t c = 0; c < nc; ++c) {
+    if (off[c] > INT32_MAX - cnt[c]) return fail(VOF_ENOMEM, "point-neighbour stencil too large");
+    off[c + 1] = off[c] + cnt[c];
+  }
+  std::vector<int32_t> nb(off[nc]);
+#pragma omp parallel
+  {
+    std::vector<int32_t> buf;
+#pragma omp for schedule(static)
+    for (int64_t c = 0; c < nc; ++c) {
+      gather(c, buf);
+      std::copy(buf.begin(), buf.end(), nb.begin() + off[c]);
+    }
+  }
+  int32_t *d_off = nullptr, *d_nb = nullptr;
+  vof_status rc;
+  if ((rc = m->alloc(&d_off, nc + 1)) || (rc = m->alloc(&d_nb, (int64_t)nb.size()))) return rc;
+  HIP_OR_FAIL(hipMemcpy(d_off, off.data(), sizeof(int32_t) * (nc + 1), hipMemcpyHostToDevice));
+  if (!nb.empty())
+    HIP_OR_FAIL(hipMemcpy(d_nb, nb.data(), sizeof(int32_t) * nb.size(), hipMemcpyHostToDevice));
+  m->dm.cpn_off = d_off;
+  m->dm.cpn = d_nb;
+  return VOF_OK;
 }
 
 // Capture the launch sequence of one step on a private stream (the caller's
@@ -509,6 +577,12 @@ vof_status vof_set_params(vof_mesh *m, const vof_params *p) {
   if (!(p->position_tol > 0.0) || p->position_max_iter < 1)
     return fail(VOF_EINVAL, "bad positioning tolerance or iteration limit");
   if (!(p->gradient_zero >= 0.0)) return fail(VOF_EINVAL, "gradient_zero must be >= 0");
+  if (p->gradient != VOF_GRADIENT_NAG && p->gradient != VOF_GRADIENT_LSQ)
+    return fail(VOF_EINVAL, "gradient must be VOF_GRADIENT_NAG or VOF_GRADIENT_LSQ");
+  if (p->gradient == VOF_GRADIENT_LSQ && !m->dm.cpn) {
+    vof_status rc = set_device(m->ctx);
+    if (rc || (rc = build_point_neighbours(m))) return rc;
+  }
   if (p->check_stencil && !m->ds.tetdef) {
     // the stencil check keeps two more doubles per flux tet
     vof_status rc = set_device(m->ctx);

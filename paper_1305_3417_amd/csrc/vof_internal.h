@@ -60,6 +60,8 @@ struct DMesh {
   const int32_t *pc_off;   // np + 1
   const int32_t *pc;       // point -> cells
   const double *wpc;       // inverse distance weights (eq. 2.7)
+  const int32_t *cpn_off;  // nc + 1: cells sharing a point with the cell (built on
+  const int32_t *cpn;      // first use of the least-squares gradient), sorted
   const int32_t *st_off;   // nf + 1
   const int32_t *st;       // face -> stencil cells
   const double4 *S;        // face area vector, w = |S|
@@ -79,6 +81,7 @@ struct DParams {
   int32_t pos_max_iter;
   double grad_zero;
   int32_t check_stencil;
+  int32_t gradient;        // 0 NAG, 1 generalized least squares
 };
 
 struct DState {

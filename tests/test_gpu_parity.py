@@ -42,12 +42,13 @@ def ctx(vof):
     vof.vof_context_destroy(c)
 
 
-def _compare_step(vof, ctx, oracle_mod, w, alpha=None, label=""):
+def _compare_step(vof, ctx, oracle_mod, w, alpha=None, label="", gradient="nag"):
     """One step from `alpha`: planes, lambda, V_alpha and alpha."""
     a0 = w.alpha0 if alpha is None else alpha
     print(f"[{label}] one step, cells {w.mesh.n_cells} faces {w.mesh.n_faces}", flush=True)
-    g = gpu_run(vof, ctx, w, steps=1, alpha=a0)
-    o = oracle_mod.Oracle(w.mesh)
+    params = {"gradient": vof.VOF_GRADIENT_LSQ} if gradient == "lsq" else None
+    g = gpu_run(vof, ctx, w, steps=1, alpha=a0, params=params)
+    o = oracle_mod.Oracle(w.mesh, gradient=gradient)
     V, _, S, _ = o.geometry()
     Up = o.set_velocity(w.U0c, w.F0)
     r = o.step(a0, w.dt[0], w.scale[0])
@@ -237,6 +238,19 @@ def test_shear_adaptive_courant(vof, ctx, oracle_mod):
     eg_orc = float((V * np.abs(a - w.alpha0)).sum())
     print(f"[shear-16] E_g gpu {eg_gpu:.6e} oracle {eg_orc:.6e}", flush=True)
     assert abs(eg_gpu - eg_orc) <= 1e-10 * eg_orc
+    g["mesh"].close()
+
+
+@pytest.mark.parametrize("case", ["deform3d", "tets"])
+def test_lsq_gradient_reconstruction(vof, ctx, oracle_mod, case):
+    """The generalized least-squares gradient (Section 2.2.1) in place of NAG:
+    one step at step level (classes, normals to 1e-12, lambda, V_alpha), then
+    alpha after several steps."""
+    w = W.deform3d(16, steps=6) if case == "deform3d" else W.rotate_tets(10, steps=6, sample=8)
+    _compare_step(vof, ctx, oracle_mod, w, label=f"lsq-{case}", gradient="lsq")
+    g = gpu_run(vof, ctx, w, params={"gradient": vof.VOF_GRADIENT_LSQ})
+    o, a, st, lam, vp = oracle_run(oracle_mod, w, gradient="lsq")
+    assert np.abs(g["alpha"] - a).max() < 1e-10
     g["mesh"].close()
 
 
