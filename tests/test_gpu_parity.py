@@ -254,6 +254,32 @@ def test_lsq_gradient_reconstruction(vof, ctx, oracle_mod, case):
     g["mesh"].close()
 
 
+@pytest.mark.parametrize("gradient", ["nag", "lsq"])
+def test_sphere_reconstruction_error(vof, ctx, oracle_mod, gradient):
+    """Reconstruction alone (vof_reconstruct) of an exact sphere on 32^3
+    hexahedra: classes equal, and the volume of symmetric difference E_vsd
+    (Section 4.1) of the GPU's planes equals that of the oracle's planes."""
+    from tests.reconstruction_error import vsd
+    from workloads import fields
+    c, r = np.array([0.5123, 0.4871, 0.5036]), 0.15
+    m = W.hex_mesh(32, 32, 32)
+    a0 = fields.ball_box_fraction(c, r, m.cell_lo, m.cell_hi)
+    h = vof.upload_mesh(ctx, m)
+    p = vof.vof_get_params(h)
+    p.gradient = vof.VOF_GRADIENT_LSQ if gradient == "lsq" else vof.VOF_GRADIENT_NAG
+    vof.vof_set_params(h, p)
+    vof.vof_set_alpha(h, a0)
+    vof.vof_reconstruct(h)
+    cls, nrm, s = vof.vof_read_planes(h)
+    h.close()
+    rec = oracle_mod.Oracle(m, gradient=gradient).reconstruct(a0)
+    assert np.array_equal(cls, rec["cls"])
+    e_gpu = vsd(m, cls, nrm, s, (c, r))
+    e_orc = vsd(m, rec["cls"], rec["n"], rec["s"], (c, r))
+    print(f"[vsd-{gradient}] E_vsd gpu {e_gpu:.6e} oracle {e_orc:.6e}", flush=True)
+    assert abs(e_gpu - e_orc) <= 1e-9 * e_orc
+
+
 def test_empty_and_full_fields(vof, ctx):
     w = W.deform3d(12, steps=3)
     for val in (0.0, 1.0):

@@ -481,3 +481,52 @@ def test_clip_face_in_plane_not_doubled(oracle_mod):
     for P in (T, T2):
         assert oracle_mod.clip_volume(P, TET_F, [list(n) + [s]]) == pytest.approx(vol, rel=1e-14)
         assert oracle_mod.clip_volume(P, TET_F, [list(n) + [s]] * 3) == pytest.approx(vol, rel=1e-14)
+
+
+# --------------------------------------------------------------------------
+# reconstruction error E_vsd against an analytic sphere (Section 4.1)
+# --------------------------------------------------------------------------
+
+def test_vsd_quadrature_components(oracle_mod):
+    """The E_vsd integrator's volumes: |C ∩ ball| against the exact sphere-box
+    fractions, and |PLIC polyhedron| against alpha V (the positioning)."""
+    from tests.reconstruction_error import _z_lengths, cell_vsd  # noqa: F401
+    from workloads import fields
+    c, r = np.array([0.5123, 0.4871, 0.5036]), 0.15
+    m = W.hex_mesh(12, 12, 12)
+    a0 = fields.ball_box_fraction(c, r, m.cell_lo, m.cell_hi)
+    o = oracle_mod.Oracle(m)
+    rec = o.reconstruct(a0)
+    xg, wg = np.polynomial.legendre.leggauss(4)
+    for cell in np.flatnonzero(rec["cls"] == 1)[::5]:
+        lo, hi = m.cell_lo[cell], m.cell_hi[cell]
+        e = np.linspace(0, 1, 17)
+        t = (0.5 * (e[:-1, None] + e[1:, None]) + 0.5 * (e[1:, None] - e[:-1, None]) * xg).ravel()
+        w = (0.5 * (e[1:, None] - e[:-1, None]) * wg).ravel()
+        X, Y = np.meshgrid(lo[0] + t * (hi[0] - lo[0]), lo[1] + t * (hi[1] - lo[1]), indexing="ij")
+        Wt = np.outer(w, w) * (hi[0] - lo[0]) * (hi[1] - lo[1])
+        V = np.prod(hi - lo)
+        I = (Wt * _z_lengths(X, Y, lo[2], hi[2], None, (c, r))).sum()
+        R = (Wt * _z_lengths(X, Y, lo[2], hi[2], (rec["n"][cell], rec["s"][cell]), None)).sum()
+        assert abs(I - a0[cell] * V) <= 1e-3 * V       # the silhouette slows the rule
+        assert abs(R - a0[cell] * V) <= 1e-5 * V
+
+
+@pytest.mark.slow
+def test_vsd_converges_nag_and_lsq(oracle_mod):
+    """E_vsd of the sphere reconstruction falls at least threefold from 16^3 to
+    32^3 hexahedra with either gradient (second order on coarse meshes,
+    Section 4.1.1)."""
+    from tests.reconstruction_error import vsd
+    from workloads import fields
+    c, r = np.array([0.5123, 0.4871, 0.5036]), 0.15
+    out = {}
+    for n in (16, 32):
+        m = W.hex_mesh(n, n, n)
+        a0 = fields.ball_box_fraction(c, r, m.cell_lo, m.cell_hi)
+        for g in ("nag", "lsq"):
+            rec = oracle_mod.Oracle(m, gradient=g).reconstruct(a0)
+            out[(n, g)] = vsd(m, rec["cls"], rec["n"], rec["s"], (c, r))
+    print("E_vsd", out)
+    for g in ("nag", "lsq"):
+        assert 0 < out[(32, g)] < out[(16, g)] / 3
