@@ -75,6 +75,10 @@ def lib():
         L.orc_reconstruct_subset.argtypes = [vp, vp, i64, vp]
         L.orc_get_planes.argtypes = [vp, vp, vp, vp]
         L.orc_faces_subset.argtypes = [vp, d, d, vp, i64, vp, vp, vp, vp, vp, vp]
+        L.orc_set_band.argtypes = [vp, C.c_int]
+        L.orc_set_wisps.argtypes = [vp, C.c_int]
+        L.orc_bulk_cells.argtypes = [vp, vp, vp]
+        L.orc_redistribute.argtypes = [vp, vp, vp]
         _lib = L
     return _lib
 
@@ -88,7 +92,8 @@ class OStats(C.Structure):
                 ("n_fallback", C.c_int64), ("n_unreached", C.c_int64),
                 ("n_clip_errors", C.c_int64), ("ledger", C.c_double),
                 ("max_leak", C.c_double), ("max_corr_residual", C.c_double),
-                ("mean_secant_iters", C.c_double)]
+                ("mean_secant_iters", C.c_double), ("n_wisps", C.c_int64),
+                ("n_wisps_left", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -97,7 +102,8 @@ class OStats(C.Structure):
 class Oracle:
     """The oracle on one mesh (points, face CSR, owner, neighbour)."""
 
-    def __init__(self, mesh, eps: float = 1e-12, gradient: str = "nag"):
+    def __init__(self, mesh, eps: float = 1e-12, gradient: str = "nag", band: bool = False,
+                 wisps: bool = False):
         L = lib()
         self.mesh = mesh
         self._keep = [np.ascontiguousarray(mesh.points, dtype=np.float64),
@@ -114,6 +120,8 @@ class Oracle:
                               _p(own), _p(nei))
         L.orc_set_eps(self.h, eps)
         self.set_gradient(gradient)
+        self.set_band(band)
+        self.set_wisps(wisps)
 
     def set_gradient(self, kind: str):
         """Gradient of the reconstruction: "nag" (Section 2.2.1) or "lsq" (the
@@ -121,6 +129,16 @@ class Oracle:
         if kind not in ("nag", "lsq"):
             raise ValueError(kind)
         lib().orc_set_gradient(self.h, 1 if kind == "lsq" else 0)
+
+    def set_band(self, on: bool):
+        """Narrow band (Section 2.4): bulk cells are not updated."""
+        self.band = bool(on)
+        lib().orc_set_band(self.h, int(self.band))
+
+    def set_wisps(self, on: bool):
+        """Wisp redistribution after every update (Section 2.4)."""
+        self.wisps = bool(on)
+        lib().orc_set_wisps(self.h, int(self.wisps))
 
     def __del__(self):
         if getattr(self, "h", None):
@@ -210,8 +228,26 @@ class Oracle:
         lam, it, st, bad = self.flux_correction(dt, s)
         ph = self.phase_flux(dt, s, lam, alpha, check_leak, status=st)
         new, B = self.update(alpha, ph["vphase"])
-        return {"alpha": new, "ledger": B, "lam": lam, "iters": it, "status": st,
-                "unreached": bad, **ph, "rec": rec}
+        out = {"lam": lam, "iters": it, "status": st, "unreached": bad, **ph, "rec": rec}
+        if self.wisps:
+            out["updated"] = new.copy()
+            new, out["wisp_counts"] = self.redistribute(new)
+        return {"alpha": new, "ledger": B, **out}
+
+    def bulk_cells(self, alpha):
+        """Cells left alone by the narrow band for this alpha (bool per cell)."""
+        alpha = np.ascontiguousarray(alpha, dtype=np.float64)
+        out = np.empty(self.nc, dtype=np.int8)
+        lib().orc_bulk_cells(self.h, _p(alpha), _p(out))
+        return out.astype(bool)
+
+    def redistribute(self, alpha):
+        """One wisp redistribution pass; returns the new alpha and the counts
+        (wisps, wisps left with a remainder, receivers)."""
+        a = np.array(alpha, dtype=np.float64, copy=True)
+        cnt = np.zeros(3, dtype=np.int64)
+        lib().orc_redistribute(self.h, _p(a), _p(cnt))
+        return a, {"wisps": int(cnt[0]), "left": int(cnt[1]), "receivers": int(cnt[2])}
 
     def advect(self, alpha, dt, scale, check_leak=False):
         a = np.array(alpha, dtype=np.float64, copy=True)

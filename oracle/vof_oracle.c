@@ -24,7 +24,10 @@
  *   phase flux        S_f clipped by each stencil cell (eq. 2.22), then by
  *                     the PLIC half-space in interface cells (eq. 2.23), by
  *                     plane clipping and capping (Section 2.1)
- *   update            eq. 2.2 with owner/neighbour signs (eq. 2.5)
+ *   update            eq. 2.2 with owner/neighbour signs (eq. 2.5); optionally
+ *                     only outside the bulk (the narrow band, Section 2.4)
+ *   wisps             optional conservative redistribution of wisps to the
+ *                     interface cells around them (Section 2.4)
  *
  * Build: gcc -O2 -fopenmp -shared -fPIC -o liboracle.so vof_oracle.c -lm
  */
@@ -272,6 +275,8 @@ typedef struct {
   double *grad;              /* NAG gradient (3 nc)                    */
   double eps;                /* reconstruction tolerance               */
   int grad_kind;             /* 0 NAG (Section 2.2.1), 1 generalized LSQ */
+  int band;                  /* 1: bulk cells are not updated (Section 2.4) */
+  int wisps;                 /* 1: wisps redistributed after the update */
 } omesh;
 
 static int cmp_i32(const void *a, const void *b) {
@@ -731,13 +736,10 @@ static void nag_gradient(const omesh *M, int64_t c, const double *alpha, const d
   for (int j = 0; j < 3; ++j) g[j] /= M->V[c];            /* eq. 2.12 */
 }
 
-/* Generalized least-squares gradient (Section 2.2.1, after the NAG
- * gradient): over the point neighbours k of cell c (the cells sharing a point
- * with it), minimise sum_k w_ck^2 E_ck^2 with E_ck = -(phi_c - phi_k) +
- * g . (x_c - x_k) and w_ck the inverse distance of the centroids.  The normal
- * equations (sum w^2 d d^T) g = sum w^2 d (phi_k - phi_c), d = x_k - x_c, are
- * a 3x3 system, solved here by Cramer's rule. */
-static void lsq_gradient(const omesh *M, int64_t c, const double *phi, double *g) {
+/* The cells other than c that share a point with c, each once, in
+ * ascending order (the point neighbours of Sections 2.2.1 and 2.4).  The
+ * caller frees the list. */
+static int32_t *point_neighbours(const omesh *M, int64_t c, int64_t *count) {
   int32_t *nb = NULL;
   int64_t nn = 0, cap = 0;
   for (int64_t k = M->cf_off[c]; k < M->cf_off[c + 1]; ++k) {
@@ -754,10 +756,25 @@ static void lsq_gradient(const omesh *M, int64_t c, const double *phi, double *g
       }
     }
   }
-  qsort(nb, nn, sizeof(int32_t), cmp_i32);
+  if (nn > 1) qsort(nb, nn, sizeof(int32_t), cmp_i32);
+  int64_t u = 0;
+  for (int64_t i = 0; i < nn; ++i)
+    if (u == 0 || nb[i] != nb[u - 1]) nb[u++] = nb[i];
+  *count = u;
+  return nb;
+}
+
+/* Generalized least-squares gradient (Section 2.2.1, after the NAG
+ * gradient): over the point neighbours k of cell c (the cells sharing a point
+ * with it), minimise sum_k w_ck^2 E_ck^2 with E_ck = -(phi_c - phi_k) +
+ * g . (x_c - x_k) and w_ck the inverse distance of the centroids.  The normal
+ * equations (sum w^2 d d^T) g = sum w^2 d (phi_k - phi_c), d = x_k - x_c, are
+ * a 3x3 system, solved here by Cramer's rule. */
+static void lsq_gradient(const omesh *M, int64_t c, const double *phi, double *g) {
+  int64_t nn = 0;
+  int32_t *nb = point_neighbours(M, c, &nn);
   double A[3][3] = {{0}}, b[3] = {0};
   for (int64_t i = 0; i < nn; ++i) {
-    if (i > 0 && nb[i] == nb[i - 1]) continue;     /* each neighbour once */
     int64_t k = nb[i];
     double d[3];
     v_sub(&M->xc[3 * k], &M->xc[3 * c], d);
@@ -997,12 +1014,39 @@ int64_t orc_phase_flux(const omesh *M, double dt, double s, const double *lam,
 /* ------------------------------------------------------------------ */
 /* conservative update (eq. 2.2 with eq. 2.5; outflow-only phase volume) */
 /* ------------------------------------------------------------------ */
-/* alpha_c^{n+1} = alpha_c^n - (1/V_c) sum_f sgn_cf V_{f,alpha}, every cell,
+/* READING (Section 2.4, narrow band): a bulk cell is one whose volume
+ * fraction gradient vanishes; taken here as a cell such that it and every
+ * cell sharing a point with it hold alpha exactly 0, or all exactly 1.  Then
+ * every inverse-distance point value of the cell equals its alpha and the NAG
+ * gradient is zero in exact arithmetic. */
+static int bulk_cell(const omesh *M, int64_t c, const double *alpha) {
+  const double a = alpha[c];
+  if (a != 0.0 && a != 1.0) return 0;
+  int64_t nn = 0;
+  int32_t *nb = point_neighbours(M, c, &nn);
+  int bulk = 1;
+  for (int64_t i = 0; i < nn && bulk; ++i) bulk = alpha[nb[i]] == a;
+  free(nb);
+  return bulk;
+}
+
+void orc_bulk_cells(const omesh *M, const double *alpha, int8_t *out) {
+#pragma omp parallel for schedule(static)
+  for (int64_t c = 0; c < M->nc; ++c) out[c] = (int8_t)bulk_cell(M, c, alpha);
+}
+
+/* alpha_c^{n+1} = alpha_c^n - (1/V_c) sum_f sgn_cf V_{f,alpha}, every cell
+ * (with the narrow band: every cell but the bulk cells, whose alpha is left
+ * as it is; the paper computes the phase volumes of their faces all the same),
  * no clamping.  Returns the boundary ledger sum of V_{f,alpha} over boundary
  * faces (volume that left the domain, negative for inflow). */
 double orc_update(const omesh *M, const double *alpha, const double *vphase, double *out) {
 #pragma omp parallel for schedule(static)
   for (int64_t c = 0; c < M->nc; ++c) {
+    if (M->band && bulk_cell(M, c, alpha)) {
+      out[c] = alpha[c];
+      continue;
+    }
     double acc = 0.0;
     for (int64_t k = M->cf_off[c]; k < M->cf_off[c + 1]; ++k)
       acc += M->cf_sign[k] * vphase[M->cf_face[k]];
@@ -1014,11 +1058,123 @@ double orc_update(const omesh *M, const double *alpha, const double *vphase, dou
 }
 
 /* ------------------------------------------------------------------ */
+/* wisp redistribution (Section 2.4)                                    */
+/* ------------------------------------------------------------------ */
+/* Wisps, small volume fractions left outside the interface band by the
+ * update, are moved conservatively to the interface cells around them, and
+ * no receiving cell may be pushed out of the interface band (no new over- or
+ * undershoot and no new wisp).  The paper cites Harvie and Fletcher and
+ * gives no formulas; READING, step by step:
+ *   - wisp: a cell whose alpha lies outside the band (eps, 1 - eps) but is
+ *     not exactly 0 or 1 (phase wisps 0 < alpha <= eps, void wisps
+ *     1 - eps <= alpha < 1, undershoots alpha < 0, overshoots alpha > 1);
+ *     its signed excess is m_w = (alpha_w - t) V_w with the target t = 0 if
+ *     alpha_w <= eps, else 1;
+ *   - receivers: interface cells (eps < alpha < 1 - eps) sharing a point with
+ *     the wisp;
+ *   - a receiver r can take (1 - eps - alpha_r) V_r of phase and give
+ *     (alpha_r - eps) V_r; it offers each wisp around it the share of that
+ *     room (for m > 0) or store (for m < 0) proportional to |m_w| among the
+ *     wisps of the same sign around it;
+ *   - a wisp moves min(|m_w|, total offered) and splits it over its receivers
+ *     in proportion to their offers; a wisp moved whole is set to its
+ *     target exactly, one with too little room around it keeps the rest.
+ * All quantities come from the alpha after the update (one pass per step),
+ * so every receiver stays within [eps, 1 - eps]: its gain is at most its
+ * room and its loss at most its store.  counts: wisps, wisps left with a
+ * remainder, receivers. */
+void orc_redistribute(const omesh *M, double *alpha, int64_t *counts) {
+  const int64_t nc = M->nc;
+  const double eps = M->eps;
+  double *m = calloc(nc, sizeof(double));      /* signed excess of each wisp */
+  double *dpos = calloc(nc, sizeof(double));   /* per receiver: sum of m > 0 around it */
+  double *dneg = calloc(nc, sizeof(double));   /*               sum of -m, m < 0 */
+  double *moved = calloc(nc, sizeof(double));  /* per wisp: volume moved */
+  double *offered = calloc(nc, sizeof(double));
+  double *gain = calloc(nc, sizeof(double));
+  int8_t *band = malloc(nc);
+  int64_t nw = 0, nleft = 0, nrecv = 0;
+  for (int64_t c = 0; c < nc; ++c) {
+    const double a = alpha[c];
+    band[c] = a > eps && a < 1.0 - eps;
+    if (!band[c] && a != 0.0 && a != 1.0) {
+      m[c] = (a - (a <= eps ? 0.0 : 1.0)) * M->V[c];
+      ++nw;
+    }
+  }
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : nrecv)
+  for (int64_t r = 0; r < nc; ++r) {
+    if (!band[r]) continue;
+    int64_t nn = 0;
+    int32_t *nb = point_neighbours(M, r, &nn);
+    int any = 0;
+    for (int64_t i = 0; i < nn; ++i) {
+      const double mw = m[nb[i]];
+      if (mw > 0.0) dpos[r] += mw;
+      if (mw < 0.0) dneg[r] -= mw;
+      any |= mw != 0.0;
+    }
+    nrecv += any;
+    free(nb);
+  }
+  /* the offer of receiver r to wisp w */
+#define OFFER(r, w)                                                                    \
+  (m[w] > 0.0 ? (1.0 - eps - alpha[r]) * M->V[r] * (m[w] / dpos[r])                   \
+              : (alpha[r] - eps) * M->V[r] * (-m[w] / dneg[r]))
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t w = 0; w < nc; ++w) {
+    if (m[w] == 0.0) continue;
+    int64_t nn = 0;
+    int32_t *nb = point_neighbours(M, w, &nn);
+    double O = 0.0;
+    for (int64_t i = 0; i < nn; ++i)
+      if (band[nb[i]]) O += OFFER(nb[i], w);
+    offered[w] = O;
+    moved[w] = fmin(fabs(m[w]), O);
+    free(nb);
+  }
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t r = 0; r < nc; ++r) {
+    if (!band[r]) continue;
+    int64_t nn = 0;
+    int32_t *nb = point_neighbours(M, r, &nn);
+    for (int64_t i = 0; i < nn; ++i) {
+      const int64_t w = nb[i];
+      if (m[w] == 0.0 || offered[w] == 0.0) continue;
+      const double x = moved[w] * (OFFER(r, w) / offered[w]);   /* w -> r */
+      gain[r] += m[w] > 0.0 ? x : -x;
+    }
+    free(nb);
+  }
+#undef OFFER
+  for (int64_t c = 0; c < nc; ++c) {
+    if (band[c]) {
+      alpha[c] += gain[c] / M->V[c];
+    } else if (m[c] != 0.0) {
+      if (offered[c] >= fabs(m[c])) {
+        alpha[c] = alpha[c] <= eps ? 0.0 : 1.0;
+      } else {
+        alpha[c] -= (m[c] > 0.0 ? moved[c] : -moved[c]) / M->V[c];
+        ++nleft;
+      }
+    }
+  }
+  counts[0] = nw;
+  counts[1] = nleft;
+  counts[2] = nrecv;
+  free(m); free(dpos); free(dneg); free(moved); free(offered); free(gain); free(band);
+}
+
+void orc_set_band(omesh *M, int band) { M->band = band; }
+void orc_set_wisps(omesh *M, int wisps) { M->wisps = wisps; }
+
+/* ------------------------------------------------------------------ */
 /* time loop: all geometry of step n uses alpha^n (explicit Euler, eq. 2.2) */
 /* ------------------------------------------------------------------ */
 typedef struct {
   int64_t n_interface, n_geometric, n_fallback, n_unreached, n_clip_errors;
   double ledger, max_leak, max_corr_residual, mean_secant_iters;
+  int64_t n_wisps, n_wisps_left;
 } ostats;
 
 int orc_advect(omesh *M, double *alpha, int64_t nsteps, const double *dt, const double *sc,
@@ -1052,6 +1208,12 @@ int orc_advect(omesh *M, double *alpha, int64_t nsteps, const double *dt, const 
     st->n_clip_errors += ne;
     if (leak > st->max_leak) st->max_leak = leak;
     st->ledger += orc_update(M, alpha, vp, nxt);
+    if (M->wisps) {
+      int64_t wc[3];
+      orc_redistribute(M, nxt, wc);
+      st->n_wisps += wc[0];
+      st->n_wisps_left += wc[1];
+    }
     memcpy(alpha, nxt, sizeof(double) * M->nc);
   }
   st->mean_secant_iters = itcnt ? itsum / itcnt : 0.0;

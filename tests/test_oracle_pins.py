@@ -530,3 +530,162 @@ def test_vsd_converges_nag_and_lsq(oracle_mod):
     print("E_vsd", out)
     for g in ("nag", "lsq"):
         assert 0 < out[(32, g)] < out[(16, g)] / 3
+
+
+# --------------------------------------------------------------------------
+# narrow band and wisp redistribution (Section 2.4)
+# --------------------------------------------------------------------------
+
+def _cell_points(mesh):
+    """Point set of every cell, from the faces (owner and neighbour side)."""
+    pts = [set() for _ in range(mesh.n_cells)]
+    off = mesh.face_offsets
+    for f in range(mesh.n_faces):
+        ps = mesh.face_points[off[f]:off[f + 1]]
+        pts[mesh.owner[f]].update(ps.tolist())
+        if f < mesh.n_internal:
+            pts[mesh.neighbour[f]].update(ps.tolist())
+    return pts
+
+
+def _point_neighbours(mesh):
+    """Cells other than c sharing a point with c, by brute force over sets."""
+    cp = _cell_points(mesh)
+    owner_of = {}
+    for c, ps in enumerate(cp):
+        for p in ps:
+            owner_of.setdefault(p, set()).add(c)
+    return [sorted(set().union(*(owner_of[p] for p in cp[c])) - {c}) for c in range(mesh.n_cells)]
+
+
+def test_bulk_cells_are_cells_with_uniform_exact_neighbourhood(oracle_mod):
+    """A bulk cell (vanishing gradient): it and every cell sharing a point with
+    it hold exactly 0, or all exactly 1.  Brute force over point sets, on a
+    field with exact bulk regions, interface cells and wisps (1e-14 and
+    1 - 1e-14, which are not exact)."""
+    m = W.hex_mesh(12, 6, 6)
+    xc = m.cell_centroids()
+    a = (xc[:, 0] > 0.5).astype(np.float64)
+    a[(np.abs(xc[:, 0] - 0.5) < 0.1) & (xc[:, 1] < 0.4)] = 0.4
+    rng = np.random.default_rng(7)
+    zero, one = np.flatnonzero(a == 0.0), np.flatnonzero(a == 1.0)
+    a[rng.choice(zero, 2, replace=False)] = 1e-14
+    a[rng.choice(one, 2, replace=False)] = 1.0 - 1e-14
+    nb = _point_neighbours(m)
+    expect = np.array([(a[c] in (0.0, 1.0)) and all(a[k] == a[c] for k in nb[c])
+                       for c in range(m.n_cells)])
+    o = oracle_mod.Oracle(m)
+    got = o.bulk_cells(a)
+    assert expect.sum() > 10 and (~expect).sum() > 10
+    assert np.array_equal(got, expect)
+
+
+def test_narrow_band_update_is_exact(oracle_mod):
+    """Skipping the bulk cells changes nothing in exact arithmetic: their faces
+    are all trivial and their net flux is sum_f sgn F_f dt = 0 (eq. 2.4).  One
+    step of the deformation field: bulk cells keep their alpha bit for bit,
+    every other cell gets the full update, and the full update of a bulk cell
+    differs from its alpha only by rounding."""
+    w = W.deform3d(16, steps=4)
+    full = oracle_mod.Oracle(w.mesh)
+    band = oracle_mod.Oracle(w.mesh, band=True)
+    for o in (full, band):
+        o.set_velocity(w.U0c, w.F0)
+    a0 = w.alpha0
+    bulk = band.bulk_cells(a0)
+    assert bulk.sum() > 0.8 * w.mesh.n_cells
+    sf = full.step(a0, w.dt[1], w.scale[1])
+    sb = band.step(a0, w.dt[1], w.scale[1])
+    assert np.array_equal(sb["alpha"][bulk], a0[bulk])
+    assert np.array_equal(sb["alpha"][~bulk], sf["alpha"][~bulk])
+    assert np.max(np.abs(sf["alpha"][bulk] - a0[bulk])) < 1e-14
+    assert sb["ledger"] == sf["ledger"]
+
+
+def _chain(alpha):
+    """len(alpha) x 1 x 1 hexahedra: cell i shares points with i - 1 and i + 1 only."""
+    m = W.hex_mesh(len(alpha), 1, 1)
+    return m, np.array(alpha, dtype=np.float64)
+
+
+def test_wisp_moves_to_receivers_in_proportion_to_room(oracle_mod):
+    """A phase wisp between two interface cells moves whole, split in
+    proportion to the receivers' room (1 - eps - alpha) V; it ends exactly at 0."""
+    eps = Q(1, 10**12)
+    m, a = _chain([0.5, 1e-13, 0.3])
+    o = oracle_mod.Oracle(m)
+    new, cnt = o.redistribute(a)
+    mw = Q(a[1])
+    r0, r2 = 1 - eps - Q(a[0]), 1 - eps - Q(a[2])
+    e0 = Q(a[0]) + mw * r0 / (r0 + r2)
+    e2 = Q(a[2]) + mw * r2 / (r0 + r2)
+    assert new[1] == 0.0
+    assert abs(new[0] - float(e0)) <= 2e-16 * float(e0)
+    assert abs(new[2] - float(e2)) <= 2e-16 * float(e2)
+    assert cnt == {"wisps": 1, "left": 0, "receivers": 2}
+
+
+def test_wisp_limited_by_room_keeps_the_rest(oracle_mod):
+    """An overshoot larger than the room around it: both receivers are filled
+    to 1 - eps and the wisp keeps the remainder."""
+    eps = Q(1, 10**12)
+    m, a = _chain([0.875, 1.5, 0.9375])
+    o = oracle_mod.Oracle(m)
+    new, cnt = o.redistribute(a)
+    room = (1 - eps - Q(a[0])) + (1 - eps - Q(a[2]))
+    assert abs(new[0] - float(1 - eps)) <= 2e-16
+    assert abs(new[2] - float(1 - eps)) <= 2e-16
+    assert abs(new[1] - float(Q(a[1]) - room)) <= 4e-16
+    assert cnt == {"wisps": 1, "left": 1, "receivers": 2}
+
+
+def test_wisps_share_a_receiver_by_excess(oracle_mod):
+    """Two overshoots around one receiver with little room share that room in
+    proportion to their excess; a receiver between an overshoot and an
+    undershoot takes from one and gives to the other."""
+    eps = Q(1, 10**12)
+    m, a = _chain([1.0 + 3e-9, 1.0 - 1e-9, 1.0 + 1e-9])
+    new, cnt = oracle_mod.Oracle(m).redistribute(a)
+    m0, m2 = Q(a[0]) - 1, Q(a[2]) - 1
+    room = 1 - eps - Q(a[1])
+    assert abs(new[1] - float(1 - eps)) <= 2e-16
+    assert abs(new[0] - float(Q(a[0]) - room * m0 / (m0 + m2))) <= 2e-16
+    assert abs(new[2] - float(Q(a[2]) - room * m2 / (m0 + m2))) <= 2e-16
+    assert cnt["left"] == 2
+
+    m, a = _chain([1.25, 0.5, -0.125])
+    new, cnt = oracle_mod.Oracle(m).redistribute(a)
+    assert new[0] == 1.0 and new[2] == 0.0
+    assert abs(new[1] - 0.625) <= 2e-16
+    assert cnt == {"wisps": 2, "left": 0, "receivers": 1}
+
+
+def test_redistribution_conserves_and_keeps_receivers_in_band(oracle_mod):
+    """Along a deformation run with the narrow band and wisps: each pass keeps
+    sum V alpha (to rounding), leaves every receiver within [eps, 1 - eps],
+    and sets every wisp it moves whole to exactly 0 or 1; over the run the
+    total with the boundary ledger is conserved."""
+    w = W.deform3d(16, steps=24)
+    o = oracle_mod.Oracle(w.mesh, band=True, wisps=True)
+    o.set_velocity(w.U0c, w.F0)
+    V = o.geometry()[0]
+    a = w.alpha0.copy()
+    m0 = np.sum(V * a)
+    ledger = 0.0
+    eps = 1e-12
+    total = 0
+    for k in range(w.n_steps):
+        st = o.step(a, w.dt[k], w.scale[k])
+        up, new = st["updated"], st["alpha"]
+        ledger += st["ledger"]
+        band = (up > eps) & (up < 1 - eps)
+        wisp = ~band & (up != 0.0) & (up != 1.0)
+        total += wisp.sum()
+        assert st["wisp_counts"]["wisps"] == wisp.sum()
+        assert abs(np.sum(V * new) - np.sum(V * up)) <= 1e-15 * np.sum(V * up)
+        assert np.all(new[band] >= eps * (1 - 1e-12)) and np.all(new[band] <= 1 - eps + 1e-16)
+        whole = wisp & ((new == 0.0) | (new == 1.0))
+        assert whole.sum() == wisp.sum() - st["wisp_counts"]["left"]
+        a = new
+    assert total > 100
+    assert abs(np.sum(V * a) + ledger - m0) <= 1e-12 * m0
