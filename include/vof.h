@@ -125,7 +125,19 @@ vof_status vof_mesh_get_info(const vof_mesh *mesh, vof_mesh_info *out);
  * the node-averaged Gauss gradient, eqs. 2.6-2.12; VOF_GRADIENT_LSQ: from the
  * generalized least-squares gradient over the cells sharing a point with the
  * cell, inverse-distance weighted, Section 2.2.1 -- the first reconstruction
- * with it builds that cell stencil on the host). */
+ * with it builds that cell stencil on the host), narrow_band 0 (1: the narrow
+ * band of Section 2.4 -- bulk cells, those whose cells sharing a point, the
+ * cell included, all hold alpha exactly 0 or all exactly 1, are not updated;
+ * their update is zero in exact arithmetic), wisps 0 (1: after every update,
+ * wisps -- cells outside the interface band eps < alpha < 1 - eps whose
+ * alpha is not exactly 0 or 1, over- and undershoots included -- move their
+ * excess over 0 or 1 to the interface cells sharing a point with them
+ * (Section 2.4): each receiver offers the room (1 - eps - alpha) V, or for a
+ * deficit the store (alpha - eps) V, it has, shared among the wisps around
+ * it in proportion to their excess; a wisp moves at most what it is offered,
+ * split in proportion to the offers, and is set to exactly 0 or 1 when it
+ * moves all of it.  No receiver leaves [eps, 1 - eps].  Needs the same cell
+ * stencil as the least-squares gradient). */
 #define VOF_GRADIENT_NAG 0
 #define VOF_GRADIENT_LSQ 1
 typedef struct {
@@ -137,6 +149,8 @@ typedef struct {
   double gradient_zero;
   int32_t check_stencil;
   int32_t gradient;
+  int32_t narrow_band;
+  int32_t wisps;
 } vof_params;
 vof_status vof_get_params(const vof_mesh *mesh, vof_params *out);
 vof_status vof_set_params(vof_mesh *mesh, const vof_params *p);
@@ -204,6 +218,8 @@ typedef struct {
   double ledger;              /* sum of V_{f,alpha} over boundary faces      */
   double mass;                /* sum_c V_c alpha_c (compensated)            */
   double alpha_min, alpha_max;
+  int64_t wisps;              /* sum over steps of wisps found (wisps = 1)   */
+  int64_t wisps_left;         /* of those, wisps with too little room around */
 } vof_stats;
 /* Synchronises, computes mass and alpha range, and reports the counters.
  * Returns VOF_ECAPACITY / VOF_ESTENCIL if the corresponding counter is

@@ -74,7 +74,8 @@ class vof_params(C.Structure):
     _fields_ = [("eps", C.c_double), ("correction_rtol", C.c_double),
                 ("correction_max_iter", C.c_int32), ("position_tol", C.c_double),
                 ("position_max_iter", C.c_int32), ("gradient_zero", C.c_double),
-                ("check_stencil", C.c_int32), ("gradient", C.c_int32)]
+                ("check_stencil", C.c_int32), ("gradient", C.c_int32),
+                ("narrow_band", C.c_int32), ("wisps", C.c_int32)]
 
 
 class vof_stats(C.Structure):
@@ -85,7 +86,8 @@ class vof_stats(C.Structure):
                 ("correction_iters", C.c_int64), ("clip_pairs", C.c_int64),
                 ("general_tets", C.c_int64),
                 ("ledger", C.c_double), ("mass", C.c_double),
-                ("alpha_min", C.c_double), ("alpha_max", C.c_double)]
+                ("alpha_min", C.c_double), ("alpha_max", C.c_double),
+                ("wisps", C.c_int64), ("wisps_left", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

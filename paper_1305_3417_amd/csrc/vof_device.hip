@@ -40,6 +40,7 @@ constexpr int kPlaneGrid = 2048;  // blocks of four waves, one interface cell pe
 static_assert(kMaxCellPlanes * kMaxFacePoints <= 128, "two fan tetrahedra per lane");
 static_assert(kMaxCellPlanes <= 16, "cutting-plane masks are 16 bits");
 constexpr int kLedgerParts = 256;  // partial sums of the boundary ledger
+constexpr int kWispGrid = 512;     // blocks of the wisp passes (grid-stride over the lists)
 
 __device__ __forceinline__ v3 xyz(double4 a) { return mk3(a.x, a.y, a.z); }
 
@@ -240,21 +241,34 @@ __global__ __launch_bounds__(kBlock) void k_cell_class(DMesh m, DState s, DParam
     int8_t cl = a <= p.eps ? 0 : (a >= 1.0 - p.eps ? 2 : 1);
     s.cls[c] = cl;
     iface = cl == 1;
+    if (p.band) s.inexact[c] = cl != 1 && a != 0.0 && a != 1.0;
   }
   int slot = block_append(&s.work[kWInterface], iface);
   if (iface) s.icells[slot] = (int32_t)c;
 }
 
-__global__ __launch_bounds__(kBlock) void k_point_prep(DMesh m, DState s) {
+// Point mask: bit 1 empty, 2 full, 4 interface among the point-cells; with
+// the narrow band also bit 8, an empty or full point-cell whose alpha is not
+// exactly 0 or 1, so that mask 1 (2) means every point-cell is exactly 0 (1).
+__global__ __launch_bounds__(kBlock) void k_point_prep(DMesh m, DState s, DParams pr) {
   int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (p >= m.np) return;
   int k0 = m.pc_off[p], k1 = m.pc_off[p + 1];
   uint8_t mask = 0;
   // unrolled so that the cell ids, then the class bytes, load together
+  if (pr.band) {
 #pragma unroll 8
-  for (int k = k0; k < k1; ++k) {
-    int8_t cl = s.cls[m.pc[k]];
-    mask |= cl == 0 ? 1 : (cl == 2 ? 2 : 4);
+    for (int k = k0; k < k1; ++k) {
+      const int c = m.pc[k];
+      int8_t cl = s.cls[c];
+      mask |= (cl == 0 ? 1 : (cl == 2 ? 2 : 4)) | (s.inexact[c] ? 8 : 0);
+    }
+  } else {
+#pragma unroll 8
+    for (int k = k0; k < k1; ++k) {
+      int8_t cl = s.cls[m.pc[k]];
+      mask |= cl == 0 ? 1 : (cl == 2 ? 2 : 4);
+    }
   }
   s.pmask[p] = mask;
   if (mask & 4) {
@@ -540,13 +554,12 @@ __global__ __launch_bounds__(kBlock) void k_flux(DMesh m, DState s, DParams p) {
       double T = F * dt;
       double lam = 0.0, vph = 0.0;
       int it = 0, stat = 0;
-      uint8_t kind = 0;
+      uint8_t kind = 0, mask = 0;
       if (F != 0.0) {
         int n = 0;
 #pragma unroll
         for (int i = 0; i < NMAX; ++i) n += q[i] >= 0;
         v3 r[NMAX], d[NMAX];
-        uint8_t mask = 0;
         v3 c = mk3(0, 0, 0);
         const double sweep = -sc * dt;
 #pragma unroll
@@ -600,13 +613,23 @@ __global__ __launch_bounds__(kBlock) void k_flux(DMesh m, DState s, DParams p) {
         if ((mask & 6) == 0) {
           kind = 1;
           vph = 0.0;
-        } else if (mask == 2 && f < m.ni) {
+        } else if ((mask & 7) == 2 && f < m.ni) {
           kind = 2;
           vph = T;
         } else {
           kind = 3;
           geo = true;
         }
+      }
+      if (p.band) {
+        // narrow band: whether every point-cell of every face point is exactly
+        // 0 (1), also for faces without flux
+        if (F == 0.0) {
+#pragma unroll
+          for (int i = 0; i < NMAX; ++i)
+            if (q[i] >= 0) mask |= s.pmask[q[i]];
+        }
+        s.fbulk[f] = mask == 1 ? 1 : (mask == 2 ? 2 : 0);
       }
       s.lam[f] = lam;
       if (!geo) s.vphase[f] = vph;
@@ -937,18 +960,145 @@ __global__ __launch_bounds__(kBlock) void k_face_sum(DMesh m, DState s, DParams 
   if (__ballot(nleak != 0) && lane_id() == 0) flag(s.flags, kFlagLeak);
 }
 
-// alpha_c^{n+1} = alpha_c^n - (1/V_c) sum_f sgn_cf V_{f,alpha}, every cell
-__global__ __launch_bounds__(kBlock) void k_update(DMesh m, DState s) {
+// alpha_c^{n+1} = alpha_c^n - (1/V_c) sum_f sgn_cf V_{f,alpha}, every cell;
+// with the narrow band (Section 2.4) every cell but the bulk cells, those
+// whose faces' points touch only cells that are exactly 0 (or only exactly 1),
+// so that every cell sharing a point with them is.  With wisps on, the
+// updated cells outside the interface band whose alpha is not exactly 0 or
+// 1 are listed with their excess over the nearer of the two.
+__global__ __launch_bounds__(kBlock) void k_update(DMesh m, DState s, DParams p) {
   int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (c >= m.nc) return;
-  double acc = 0.0;
-  // unrolled so that the face ids, then the phase volumes, load together
+  const uint32_t stamp = p.wisps ? s.wctr[0] + 1u : 0u;
+  bool wisp = false;
+  double ex = 0.0;
+  if (c < m.nc) {
+    const int k0 = m.cf_off[c], k1 = m.cf_off[c + 1];
+    bool skip = false;
+    if (p.band) {
+      uint8_t b = 3;
 #pragma unroll 6
-  for (int k = m.cf_off[c]; k < m.cf_off[c + 1]; ++k) {
-    int sf = m.cf[k];
-    acc += sf >= 0 ? s.vphase[sf] : -s.vphase[~sf];
+      for (int k = k0; k < k1; ++k) {
+        int sf = m.cf[k];
+        b &= s.fbulk[sf >= 0 ? sf : ~sf];
+      }
+      skip = b != 0;
+    }
+    if (!skip) {
+      double acc = 0.0;
+      // unrolled so that the face ids, then the phase volumes, load together
+#pragma unroll 6
+      for (int k = k0; k < k1; ++k) {
+        int sf = m.cf[k];
+        acc += sf >= 0 ? s.vphase[sf] : -s.vphase[~sf];
+      }
+      const double V = m.V[c];
+      const double a = s.alpha[c] - acc / V;
+      s.alpha[c] = a;
+      if (p.wisps && !(a > p.eps && a < 1.0 - p.eps) && a != 0.0 && a != 1.0) {
+        wisp = true;
+        ex = (a - (a <= p.eps ? 0.0 : 1.0)) * V;
+      }
+    }
   }
-  s.alpha[c] = s.alpha[c] - acc / m.V[c];
+  if (p.wisps) {
+    int slot = block_append(&s.work[kWWisps], wisp);
+    if (wisp) {
+      s.wlist[slot] = (int32_t)c;
+      s.wex[c] = ex;
+      s.wstamp[c] = stamp;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// wisp redistribution (Section 2.4), four passes over this step's wisps and
+// their receivers (interface cells sharing a point with a wisp):
+//   receivers   each wisp lists the interface cells around it, once each
+//   offers      per receiver r: rho+ = (1 - eps - alpha_r) V_r / sum of the
+//               positive excesses around it, rho- = (alpha_r - eps) V_r / sum
+//               of the negative ones (the offer to wisp w is rho |m_w|)
+//   sums        per wisp: the sum of its receivers' rho of its sign; it moves
+//               |m_w| min(1, sum), a share rho / sum to each receiver
+//   moves       per receiver: alpha += sum_w m_w rho min(1, 1 / sum_w) / V;
+//               per wisp: alpha = target if sum >= 1, else alpha - m sum / V
+// Every sum runs over the sorted point-neighbour list, in order.  Receivers
+// and wisps are disjoint (inside and outside the interface band), so the last
+// pass reads and writes each cell's alpha from one thread only.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool in_band(double a, double eps) { return a > eps && a < 1.0 - eps; }
+
+__global__ __launch_bounds__(kBlock) void k_wisp_receivers(DMesh m, DState s, DParams p) {
+  const int count = s.work[kWWisps];
+  const uint32_t stamp = s.wctr[0] + 1u;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+    const int w = s.wlist[i];
+    for (int k = m.cpn_off[w]; k < m.cpn_off[w + 1]; ++k) {
+      const int r = m.cpn[k];
+      if (in_band(s.alpha[r], p.eps) && atomicExch(&s.rstamp[r], stamp) != stamp)
+        s.rlist[atomicAdd(&s.work[kWRecv], 1)] = r;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_wisp_offers(DMesh m, DState s, DParams p) {
+  const int count = s.work[kWRecv];
+  const uint32_t stamp = s.wctr[0] + 1u;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+    const int r = s.rlist[i];
+    double pos = 0.0, neg = 0.0;
+    for (int k = m.cpn_off[r]; k < m.cpn_off[r + 1]; ++k) {
+      const int w = m.cpn[k];
+      if (s.wstamp[w] != stamp) continue;
+      const double e = s.wex[w];
+      if (e > 0.0) pos += e;
+      else neg -= e;
+    }
+    const double a = s.alpha[r], V = m.V[r];
+    s.rho[r] = make_double2(pos > 0.0 ? (1.0 - p.eps - a) * V / pos : 0.0,
+                            neg > 0.0 ? (a - p.eps) * V / neg : 0.0);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_wisp_sums(DMesh m, DState s, DParams p) {
+  const int count = s.work[kWWisps];
+  unsigned long long nleft = 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+    const int w = s.wlist[i];
+    const bool give = s.wex[w] > 0.0;
+    double sum = 0.0;
+    for (int k = m.cpn_off[w]; k < m.cpn_off[w + 1]; ++k) {
+      const int r = m.cpn[k];
+      if (!in_band(s.alpha[r], p.eps)) continue;
+      const double2 rr = s.rho[r];
+      sum += give ? rr.x : rr.y;
+    }
+    s.wsum[w] = sum;
+    nleft += sum < 1.0;
+  }
+  wave_count(&s.cnt[kCntWispsLeft], nleft);
+}
+
+__global__ __launch_bounds__(kBlock) void k_wisp_moves(DMesh m, DState s, DParams p) {
+  const int nr = s.work[kWRecv], nw = s.work[kWWisps];
+  const uint32_t stamp = s.wctr[0] + 1u;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nr + nw; i += gridDim.x * blockDim.x) {
+    if (i < nr) {
+      const int r = s.rlist[i];
+      const double2 rr = s.rho[r];
+      double gain = 0.0;
+      for (int k = m.cpn_off[r]; k < m.cpn_off[r + 1]; ++k) {
+        const int w = m.cpn[k];
+        if (s.wstamp[w] != stamp) continue;
+        const double e = s.wex[w], sum = s.wsum[w];
+        gain += e * (e > 0.0 ? rr.x : rr.y) * (sum > 1.0 ? 1.0 / sum : 1.0);
+      }
+      s.alpha[r] += gain / m.V[r];
+    } else {
+      const int w = s.wlist[i - nr];
+      const double a = s.alpha[w], sum = s.wsum[w];
+      s.alpha[w] = sum >= 1.0 ? (a <= p.eps ? 0.0 : 1.0) : a - s.wex[w] * sum / m.V[w];
+    }
+  }
 }
 
 // boundary ledger, two stages in fixed order: per-block partial sums of the
@@ -969,7 +1119,7 @@ __global__ __launch_bounds__(kBlock) void k_ledger_part(DMesh m, DState s) {
   if (threadIdx.x == 0) s.part[blockIdx.x] = red[0];
 }
 
-__global__ __launch_bounds__(kBlock) void k_ledger(DMesh m, DState s, int nparts) {
+__global__ __launch_bounds__(kBlock) void k_ledger(DMesh m, DState s, DParams p, int nparts) {
   __shared__ double red[kBlock];
   double acc = 0.0;
   for (int i = threadIdx.x; i < nparts; i += kBlock) acc += s.part[i];
@@ -985,6 +1135,10 @@ __global__ __launch_bounds__(kBlock) void k_ledger(DMesh m, DState s, int nparts
     s.cnt[kCntGeometric] += (unsigned long long)s.work[kWGeometric];
     s.cnt[kCntInterface] += (unsigned long long)s.work[kWInterface];
     s.cnt[kCntDeferred] += (unsigned long long)s.work[kWDeferred];
+    if (p.wisps) {
+      s.cnt[kCntWisps] += (unsigned long long)s.work[kWWisps];
+      s.wctr[0] += 1u;  // the next step's wisps and receivers get a new stamp
+    }
     s.stepno[0] += 1;  // the next step reads dt, scale at the next index
   }
 }
@@ -1049,7 +1203,7 @@ void launch_point_velocity(const DMesh &m, const double *U0c, double4 *U, double
 static void launch_reconstruct_impl(const DMesh &m, const DState &s, const DParams &p,
                                     hipStream_t st) {
   k_cell_class<<<grid_for(m.nc, kBlock), kBlock, 0, st>>>(m, s, p);
-  k_point_prep<<<grid_for(m.np, kBlock), kBlock, 0, st>>>(m, s);
+  k_point_prep<<<grid_for(m.np, kBlock), kBlock, 0, st>>>(m, s, p);
   k_plane<<<kPlaneGrid, kBlock, 0, st>>>(m, s, p);
 }
 
@@ -1084,7 +1238,7 @@ void Prof::end(int kid) {
 void launch_step(const DMesh &m, const DState &s, const DParams &p, hipStream_t st, Prof *prof) {
   TIMED(prof, kKReset, (k_reset<<<1, 64, 0, st>>>(s)));
   TIMED(prof, kKCellClass, (k_cell_class<<<grid_for(m.nc, kBlock), kBlock, 0, st>>>(m, s, p)));
-  TIMED(prof, kKPointPrep, (k_point_prep<<<grid_for(m.np, kBlock), kBlock, 0, st>>>(m, s)));
+  TIMED(prof, kKPointPrep, (k_point_prep<<<grid_for(m.np, kBlock), kBlock, 0, st>>>(m, s, p)));
   TIMED(prof, kKPlane, (k_plane<<<kPlaneGrid, kBlock, 0, st>>>(m, s, p)));
   // persistent-style grid: a few blocks per CU, grid-stride over the faces
   unsigned gf = grid_for(m.nf, kBlock);
@@ -1099,9 +1253,14 @@ void launch_step(const DMesh &m, const DState &s, const DParams &p, hipStream_t 
   TIMED(prof, kKClip, (k_clip_fast<<<kFastGrid, kFastBlock, 0, st>>>(m, s, p)));
   TIMED(prof, kKClipGeneral, (k_clip_general<<<4096, kClipBlock, 0, st>>>(m, s, p)));
   TIMED(prof, kKFaceSum, (k_face_sum<<<1024, kBlock, 0, st>>>(m, s, p)));
-  TIMED(prof, kKUpdate, (k_update<<<grid_for(m.nc, kBlock), kBlock, 0, st>>>(m, s)));
+  TIMED(prof, kKUpdate, (k_update<<<grid_for(m.nc, kBlock), kBlock, 0, st>>>(m, s, p)));
+  if (p.wisps)
+    TIMED(prof, kKWisps, (k_wisp_receivers<<<kWispGrid, kBlock, 0, st>>>(m, s, p),
+                          k_wisp_offers<<<kWispGrid, kBlock, 0, st>>>(m, s, p),
+                          k_wisp_sums<<<kWispGrid, kBlock, 0, st>>>(m, s, p),
+                          k_wisp_moves<<<kWispGrid, kBlock, 0, st>>>(m, s, p)));
   TIMED(prof, kKLedger, (k_ledger_part<<<kLedgerParts, kBlock, 0, st>>>(m, s),
-                         k_ledger<<<1, kBlock, 0, st>>>(m, s, kLedgerParts)));
+                         k_ledger<<<1, kBlock, 0, st>>>(m, s, p, kLedgerParts)));
 }
 
 void launch_stats(const DMesh &m, const DState &s, double *out4, hipStream_t st) {

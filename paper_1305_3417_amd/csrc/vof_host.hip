@@ -163,6 +163,8 @@ vof_params default_params() {
   p.gradient_zero = 1e-8;
   p.check_stencil = 0;
   p.gradient = VOF_GRADIENT_NAG;
+  p.narrow_band = 0;
+  p.wisps = 0;
   return p;
 }
 
@@ -175,6 +177,8 @@ void to_dparams(const vof_params &p, DParams &d) {
   d.grad_zero = p.gradient_zero;
   d.check_stencil = p.check_stencil;
   d.gradient = p.gradient;
+  d.band = p.narrow_band;
+  d.wisps = p.wisps;
 }
 
 vof_params from_dparams(const DParams &d) {
@@ -187,6 +191,8 @@ vof_params from_dparams(const DParams &d) {
   p.gradient_zero = d.grad_zero;
   p.check_stencil = d.check_stencil;
   p.gradient = d.gradient;
+  p.narrow_band = d.band;
+  p.wisps = d.wisps;
   return p;
 }
 
@@ -579,7 +585,9 @@ vof_status vof_set_params(vof_mesh *m, const vof_params *p) {
   if (!(p->gradient_zero >= 0.0)) return fail(VOF_EINVAL, "gradient_zero must be >= 0");
   if (p->gradient != VOF_GRADIENT_NAG && p->gradient != VOF_GRADIENT_LSQ)
     return fail(VOF_EINVAL, "gradient must be VOF_GRADIENT_NAG or VOF_GRADIENT_LSQ");
-  if (p->gradient == VOF_GRADIENT_LSQ && !m->dm.cpn) {
+  if ((p->narrow_band != 0 && p->narrow_band != 1) || (p->wisps != 0 && p->wisps != 1))
+    return fail(VOF_EINVAL, "narrow_band and wisps must be 0 or 1");
+  if ((p->gradient == VOF_GRADIENT_LSQ || p->wisps) && !m->dm.cpn) {
     vof_status rc = set_device(m->ctx);
     if (rc || (rc = build_point_neighbours(m))) return rc;
   }
@@ -590,6 +598,29 @@ vof_status vof_set_params(vof_mesh *m, const vof_params *p) {
     HIP_OR_FAIL(hipStreamSynchronize(m->ctx->stream));
     if ((rc = m->alloc(&m->ds.tetdef, m->dm.nf * (int64_t)m->dm.tpf))) return rc;
     if ((rc = m->alloc(&m->ds.tetgross, m->dm.nf * (int64_t)m->dm.tpf))) return rc;
+  }
+  if (p->narrow_band && !m->ds.inexact) {
+    vof_status rc = set_device(m->ctx);
+    if (rc) return rc;
+    HIP_OR_FAIL(hipStreamSynchronize(m->ctx->stream));
+    if ((rc = m->alloc(&m->ds.inexact, m->dm.nc)) || (rc = m->alloc(&m->ds.fbulk, m->dm.nf)))
+      return rc;
+  }
+  if (p->wisps && !m->ds.wctr) {
+    vof_status rc = set_device(m->ctx);
+    if (rc) return rc;
+    DState &d = m->ds;
+    const int64_t nc = m->dm.nc;
+    HIP_OR_FAIL(hipStreamSynchronize(m->ctx->stream));
+    if ((rc = m->alloc(&d.wctr, 1)) || (rc = m->alloc(&d.wstamp, nc)) ||
+        (rc = m->alloc(&d.rstamp, nc)) || (rc = m->alloc(&d.wlist, nc)) ||
+        (rc = m->alloc(&d.rlist, nc)) || (rc = m->alloc(&d.wex, nc)) ||
+        (rc = m->alloc(&d.wsum, nc)) || (rc = m->alloc(&d.rho, nc)))
+      return rc;
+    HIP_OR_FAIL(hipMemset(d.wctr, 0, sizeof(uint32_t)));
+    HIP_OR_FAIL(hipMemset(d.wstamp, 0, sizeof(uint32_t) * nc));
+    HIP_OR_FAIL(hipMemset(d.rstamp, 0, sizeof(uint32_t) * nc));
+    HIP_OR_FAIL(hipDeviceSynchronize());
   }
   to_dparams(*p, m->dp);
   m->graph_ok = false;
@@ -794,6 +825,8 @@ vof_status vof_get_stats(vof_mesh *m, vof_stats *out) {
   out->mass = st4[0];
   out->alpha_min = st4[1];
   out->alpha_max = st4[2];
+  out->wisps = (int64_t)c[kCntWisps];
+  out->wisps_left = (int64_t)c[kCntWispsLeft];
   return device_status(m);
 }
 
@@ -818,7 +851,7 @@ vof_status vof_profile_enable(vof_mesh *m, int32_t enable) {
 const char *vof_profile_kernel_name(int32_t id) {
   static const char *names[kKNum] = {"reset",   "cell_class",   "point_prep", "plane",
                                      "flux",    "clip",         "clip_general", "face_sum",
-                                     "update",  "ledger"};
+                                     "update",  "ledger",       "wisps"};
   return (id >= 0 && id < kKNum) ? names[id] : nullptr;
 }
 

@@ -38,11 +38,16 @@ enum Counter : int {
   kCntIters,
   kCntPairs,
   kCntDeferred,
+  kCntWisps,
+  kCntWispsLeft,
   kCntNum
 };
 
 // per-step work counters (reset every step)
-enum WorkCounter : int { kWInterface = 0, kWGeometric = 1, kWDeferred = 2, kWClipNext = 3, kWNum = 4 };
+enum WorkCounter : int {
+  kWInterface = 0, kWGeometric = 1, kWDeferred = 2, kWClipNext = 3, kWWisps = 4, kWRecv = 5,
+  kWNum = 6
+};
 
 struct DMesh {
   int64_t np, nc, nf, ni;
@@ -82,6 +87,8 @@ struct DParams {
   double grad_zero;
   int32_t check_stencil;
   int32_t gradient;        // 0 NAG, 1 generalized least squares
+  int32_t band;            // bulk cells are not updated
+  int32_t wisps;           // wisp redistribution after the update
 };
 
 struct DState {
@@ -113,12 +120,25 @@ struct DState {
   int32_t *stepno;      // index into dt / sc of the step being run
   double *dt;           // per-step dt (device copy)
   double *sc;           // per-step scale
+  // narrow band
+  uint8_t *inexact;     // nc: class empty or full but alpha not exactly 0 or 1
+  uint8_t *fbulk;       // nf: 1 (2) when every point-cell of every face point is exactly 0 (1)
+  // wisp redistribution (cells stamped with the running step's stamp are
+  // this step's wisps or receivers; stamps start at 1, arrays at 0)
+  uint32_t *wctr;       // stamp of the last finished step
+  uint32_t *wstamp;     // nc
+  uint32_t *rstamp;     // nc
+  int32_t *wlist;       // wisps of this step
+  int32_t *rlist;       // receivers of this step
+  double *wex;          // nc: signed excess volume (alpha - target) V of a wisp
+  double *wsum;         // nc: per wisp, sum of its receivers' offer ratios
+  double2 *rho;         // nc: per receiver, room / sum of m > 0, store / sum of -m, m < 0
 };
 
 // Per-kernel timing with HIP events on the launch stream (optional).
 enum KernelId : int {
   kKReset = 0, kKCellClass, kKPointPrep, kKPlane, kKFlux, kKClip, kKClipGeneral, kKFaceSum,
-  kKUpdate, kKLedger, kKNum
+  kKUpdate, kKLedger, kKWisps, kKNum
 };
 struct Prof {
   struct Rec { int kid; hipEvent_t a, b; };

@@ -31,8 +31,9 @@ def gpu_run(vof, ctx, w, steps=None, alpha=None, params=None):
     return out
 
 
-def oracle_run(oracle, w, steps=None, alpha=None, check_leak=False, gradient="nag"):
-    o = oracle.Oracle(w.mesh, gradient=gradient)
+def oracle_run(oracle, w, steps=None, alpha=None, check_leak=False, gradient="nag", band=False,
+               wisps=False):
+    o = oracle.Oracle(w.mesh, gradient=gradient, band=band, wisps=wisps)
     o.set_velocity(w.U0c, w.F0)
     n = w.n_steps if steps is None else steps
     a0 = w.alpha0 if alpha is None else alpha

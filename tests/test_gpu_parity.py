@@ -254,6 +254,56 @@ def test_lsq_gradient_reconstruction(vof, ctx, oracle_mod, case):
     g["mesh"].close()
 
 
+def test_narrow_band_leaves_bulk_cells(vof, ctx, oracle_mod):
+    """Narrow band (Section 2.4), one step of the deformation field: the bulk
+    cells (every cell sharing a point exactly 0, or all exactly 1) keep their
+    alpha bit for bit; the others match the oracle's band step."""
+    w = W.deform3d(24, steps=2)
+    o = oracle_mod.Oracle(w.mesh, band=True)
+    o.set_velocity(w.U0c, w.F0)
+    bulk = o.bulk_cells(w.alpha0)
+    r = o.step(w.alpha0, w.dt[0], w.scale[0])
+    g = gpu_run(vof, ctx, w, steps=1, params={"narrow_band": 1})
+    assert np.array_equal(g["alpha"][bulk], w.alpha0[bulk])
+    assert np.abs(g["alpha"] - r["alpha"]).max() < 1e-13
+    g["mesh"].close()
+
+
+WISP_CASES = {
+    "deform3d": lambda: W.deform3d(24, steps=40),
+    "tets": lambda: W.rotate_tets(10, steps=12, sample=8),
+    "shear": lambda: W.shear3d(16, steps=30),
+    "disc2d": lambda: W.disc2d(),
+}
+
+
+@pytest.mark.parametrize("case", sorted(WISP_CASES))
+def test_narrow_band_and_wisps(vof, ctx, oracle_mod, case):
+    """Narrow band and wisp redistribution (Section 2.4) over a run: alpha
+    within 1e-10 of the oracle's, volume conserved with the ledger, and a
+    second run bitwise identical (the wisp and receiver lists are filled by
+    atomics in any order, every sum runs in stencil order)."""
+    w = WISP_CASES[case]()
+    params = {"narrow_band": 1, "wisps": 1}
+    print(f"[wisps-{case}] cells {w.mesh.n_cells} steps {w.n_steps}", flush=True)
+    g = gpu_run(vof, ctx, w, params=params)
+    o, a, st, lam, vp = oracle_run(oracle_mod, w, band=True, wisps=True)
+    V = o.geometry()[0]
+    gs = g["stats"]
+    print(f"[wisps-{case}] wisps gpu {gs['wisps']} ({gs['wisps_left']} left) oracle "
+          f"{st['n_wisps']} ({st['n_wisps_left']} left); alpha range gpu "
+          f"[{gs['alpha_min']:.3e}, {gs['alpha_max']:.3e}] oracle [{a.min():.3e}, {a.max():.3e}]",
+          flush=True)
+    assert np.abs(g["alpha"] - a).max() < 1e-10
+    m0 = (w.alpha0 * V).sum()
+    assert abs(gs["mass"] + gs["ledger"] - m0) <= 1e-12 * m0
+    assert gs["wisps"] > 0 and st["n_wisps"] > 0
+    g2 = gpu_run(vof, ctx, w, params=params)
+    assert np.array_equal(g2["alpha"], g["alpha"])
+    g["mesh"].close()
+    g2["mesh"].close()
+
+
 @pytest.mark.parametrize("gradient", ["nag", "lsq"])
 def test_sphere_reconstruction_error(vof, ctx, oracle_mod, gradient):
     """Reconstruction alone (vof_reconstruct) of an exact sphere on 32^3
