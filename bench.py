@@ -159,6 +159,9 @@ def main():
     ap.add_argument("--workload", choices=["deform3d", "shear3d"], default="deform3d",
                     help="deform3d (eq. 4.6, fixed dt; the headline case) or shear3d "
                          "(eq. 4.5, adaptive Courant dt)")
+    ap.add_argument("--band-wisps", action="store_true",
+                    help="run the step with the narrow band and wisp redistribution "
+                         "(Section 2.4) after the update")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
@@ -197,6 +200,10 @@ def main():
     ctx = vof.vof_context_create(0)
     log("[bench] uploading mesh")
     mesh = vof.upload_mesh(ctx, w.mesh)
+    if args.band_wisps:
+        p = vof.vof_get_params(mesh)
+        p.narrow_band, p.wisps = 1, 1
+        vof.vof_set_params(mesh, p)
     vof.vof_set_alpha(mesh, w.alpha0)
     vof.vof_set_velocity(mesh, w.U0c, w.F0)
     log(f"[bench] warmup {Wm} steps")
@@ -227,7 +234,7 @@ def main():
     vof.vof_advect(mesh, w.dt[Wm + K:Wm + K + P], w.scale[Wm + K:Wm + K + P])
     vof.vof_synchronize(mesh)
     prof_elapsed = time.perf_counter() - tp0
-    prof = vof.vof_read_profile(mesh)
+    prof = {k: v for k, v in vof.vof_read_profile(mesh).items() if v[1] > 0}
     vof.vof_profile_enable(mesh, False)
     sp1 = vof.vof_get_stats(mesh)
     log("[bench] per-kernel: " + ", ".join(f"{k} {v[0] / max(v[1], 1) * 1e3:.1f}us"
@@ -282,10 +289,12 @@ def main():
                                 f"r=0.15 at (0.5,0.75,0.25), adaptive Courant dt at Co 0.5), "
                                 f"steps {Wm}..{Wm + K - 1}"),
                    "cells": int(w.mesh.n_cells), "faces": int(w.mesh.n_faces),
+                   "band_wisps": bool(args.band_wisps),
                    "parallelism": "single GPU"},
         "cell_updates_per_s": w.mesh.n_cells * K / elapsed,
         "geometric_faces_per_step": geo / K,
         "general_clip_tets_per_step": (st1["general_tets"] - st0["general_tets"]) / K,
+        "wisps_per_step": (st1["wisps"] - st0["wisps"]) / K,
         "face_fluxes_per_step": face_fluxes / K,
         "kernels_us": {k: v[0] / max(v[1], 1) * 1e3 for k, v in prof.items()},
         "profiled_ms_per_step": prof_elapsed * 1e3 / P,

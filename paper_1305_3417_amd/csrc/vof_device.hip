@@ -28,6 +28,7 @@ namespace vof {
 
 namespace {
 
+constexpr int kWave = 64;     // wavefront width
 constexpr int kBlock = 256;
 constexpr int kClipBlock = 64;
 constexpr int kFastBlock = 64;   // one wave per block in the register clip
@@ -40,7 +41,7 @@ constexpr int kPlaneGrid = 2048;  // blocks of four waves, one interface cell pe
 static_assert(kMaxCellPlanes * kMaxFacePoints <= 128, "two fan tetrahedra per lane");
 static_assert(kMaxCellPlanes <= 16, "cutting-plane masks are 16 bits");
 constexpr int kLedgerParts = 256;  // partial sums of the boundary ledger
-constexpr int kWispGrid = 512;     // blocks of the wisp passes (grid-stride over the lists)
+constexpr int kWispGrid = 2048;    // blocks of the wisp passes (wave-stride over the lists)
 
 __device__ __forceinline__ v3 xyz(double4 a) { return mk3(a.x, a.y, a.z); }
 
@@ -102,6 +103,11 @@ __device__ __forceinline__ void wave_count(unsigned long long *dst, unsigned lon
 }
 
 __device__ __forceinline__ void flag(uint32_t *flags, uint32_t bit) { atomicOr(flags, bit); }
+
+// this block's slot of counter id
+__device__ __forceinline__ unsigned long long *cnt_at(unsigned long long *cnt, int id) {
+  return cnt + ((int64_t)id * kCntLanes + (int64_t)(blockIdx.x % kCntLanes)) * kCntStride;
+}
 
 // ---------------------------------------------------------------------------
 // mesh preparation
@@ -435,7 +441,7 @@ __global__ __launch_bounds__(kBlock) void k_plane(DMesh m, DState s, DParams p) 
     }
     if (lane == 0) s.plane[c] = make_double4(n.x, n.y, n.z, sx + dot(n, o));
   }
-  wave_count(&s.cnt[kCntFallback], nfall);
+  wave_count(cnt_at(s.cnt, kCntFallback), nfall);
 }
 
 // ---------------------------------------------------------------------------
@@ -640,7 +646,7 @@ __global__ __launch_bounds__(kBlock) void k_flux(DMesh m, DState s, DParams p) {
     int slot = wave_append(&s.work[kWGeometric], geo);
     if (geo) s.gfaces[slot] = (int32_t)f;
   }
-  block_count3(&s.cnt[kCntFaceFluxes], nflux, &s.cnt[kCntIters], nit, &s.cnt[kCntUnreached], nbad);
+  block_count3(cnt_at(s.cnt, kCntFaceFluxes), nflux, cnt_at(s.cnt, kCntIters), nit, cnt_at(s.cnt, kCntUnreached), nbad);
 }
 
 // ---------------------------------------------------------------------------
@@ -861,7 +867,7 @@ __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3)))
     if (defer) s.defer[q] = (int32_t)idx;
     __syncthreads();
   }
-  wave_count(&s.cnt[kCntPairs], npairs);
+  wave_count(cnt_at(s.cnt, kCntPairs), npairs);
 }
 
 // General clip of the queued tets, one wave per tet with the lanes over the
@@ -929,8 +935,8 @@ __global__ __launch_bounds__(kClipBlock) void k_clip_general(DMesh m, DState s, 
       }
     }
   }
-  wave_count(&s.cnt[kCntCapacity], ncap);
-  wave_count(&s.cnt[kCntPairs], npairs);
+  wave_count(cnt_at(s.cnt, kCntCapacity), ncap);
+  wave_count(cnt_at(s.cnt, kCntPairs), npairs);
   if (__ballot(ncap != 0) && lane == 0) flag(s.flags, kFlagCapacity);
 }
 
@@ -956,7 +962,7 @@ __global__ __launch_bounds__(kBlock) void k_face_sum(DMesh m, DState s, DParams 
       if (fabs(dsum) > 1e-12 * dmax(gsum, m.V[m.own[f]])) ++nleak;
     }
   }
-  wave_count(&s.cnt[kCntLeaks], nleak);
+  wave_count(cnt_at(s.cnt, kCntLeaks), nleak);
   if (__ballot(nleak != 0) && lane_id() == 0) flag(s.flags, kFlagLeak);
 }
 
@@ -1021,21 +1027,36 @@ __global__ __launch_bounds__(kBlock) void k_update(DMesh m, DState s, DParams p)
 //               |m_w| min(1, sum), a share rho / sum to each receiver
 //   moves       per receiver: alpha += sum_w m_w rho min(1, 1 / sum_w) / V;
 //               per wisp: alpha = target if sum >= 1, else alpha - m sum / V
-// Every sum runs over the sorted point-neighbour list, in order.  Receivers
-// and wisps are disjoint (inside and outside the interface band), so the last
-// pass reads and writes each cell's alpha from one thread only.
+// One wavefront per wisp or receiver, lanes over its point neighbours, sums by
+// butterfly (a fixed order).  Receivers and wisps are disjoint (inside and
+// outside the interface band), so the last pass reads and writes each cell's
+// alpha from one wavefront only.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ bool in_band(double a, double eps) { return a > eps && a < 1.0 - eps; }
+
+__device__ __forceinline__ int wave_index() {
+  return (int)(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave);
+}
+__device__ __forceinline__ int wave_stride() { return (int)(gridDim.x * (blockDim.x / kWave)); }
 
 __global__ __launch_bounds__(kBlock) void k_wisp_receivers(DMesh m, DState s, DParams p) {
   const int count = s.work[kWWisps];
   const uint32_t stamp = s.wctr[0] + 1u;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+  const int lane = lane_id();
+  for (int i = wave_index(); i < count; i += wave_stride()) {
     const int w = s.wlist[i];
-    for (int k = m.cpn_off[w]; k < m.cpn_off[w + 1]; ++k) {
-      const int r = m.cpn[k];
-      if (in_band(s.alpha[r], p.eps) && atomicExch(&s.rstamp[r], stamp) != stamp)
-        s.rlist[atomicAdd(&s.work[kWRecv], 1)] = r;
+    const int k1 = m.cpn_off[w + 1];
+    for (int k = m.cpn_off[w] + lane; k - lane < k1; k += kWave) {
+      bool fresh = false;
+      int r = 0;
+      if (k < k1) {
+        r = m.cpn[k];
+        // the plain read skips the atomic for receivers stamped already
+        fresh = in_band(s.alpha[r], p.eps) && s.rstamp[r] != stamp &&
+                atomicExch(&s.rstamp[r], stamp) != stamp;
+      }
+      const int slot = wave_append(&s.work[kWRecv], fresh);
+      if (fresh) s.rlist[slot] = r;
     }
   }
 }
@@ -1043,57 +1064,71 @@ __global__ __launch_bounds__(kBlock) void k_wisp_receivers(DMesh m, DState s, DP
 __global__ __launch_bounds__(kBlock) void k_wisp_offers(DMesh m, DState s, DParams p) {
   const int count = s.work[kWRecv];
   const uint32_t stamp = s.wctr[0] + 1u;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+  const int lane = lane_id();
+  for (int i = wave_index(); i < count; i += wave_stride()) {
     const int r = s.rlist[i];
+    const int k1 = m.cpn_off[r + 1];
     double pos = 0.0, neg = 0.0;
-    for (int k = m.cpn_off[r]; k < m.cpn_off[r + 1]; ++k) {
+    for (int k = m.cpn_off[r] + lane; k < k1; k += kWave) {
       const int w = m.cpn[k];
       if (s.wstamp[w] != stamp) continue;
       const double e = s.wex[w];
       if (e > 0.0) pos += e;
       else neg -= e;
     }
-    const double a = s.alpha[r], V = m.V[r];
-    s.rho[r] = make_double2(pos > 0.0 ? (1.0 - p.eps - a) * V / pos : 0.0,
-                            neg > 0.0 ? (a - p.eps) * V / neg : 0.0);
+    pos = wave_sum_d(pos);
+    neg = wave_sum_d(neg);
+    if (lane == 0) {
+      const double a = s.alpha[r], V = m.V[r];
+      s.rho[r] = make_double2(pos > 0.0 ? (1.0 - p.eps - a) * V / pos : 0.0,
+                              neg > 0.0 ? (a - p.eps) * V / neg : 0.0);
+    }
   }
 }
 
 __global__ __launch_bounds__(kBlock) void k_wisp_sums(DMesh m, DState s, DParams p) {
   const int count = s.work[kWWisps];
+  const int lane = lane_id();
   unsigned long long nleft = 0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+  for (int i = wave_index(); i < count; i += wave_stride()) {
     const int w = s.wlist[i];
     const bool give = s.wex[w] > 0.0;
+    const int k1 = m.cpn_off[w + 1];
     double sum = 0.0;
-    for (int k = m.cpn_off[w]; k < m.cpn_off[w + 1]; ++k) {
+    for (int k = m.cpn_off[w] + lane; k < k1; k += kWave) {
       const int r = m.cpn[k];
       if (!in_band(s.alpha[r], p.eps)) continue;
       const double2 rr = s.rho[r];
       sum += give ? rr.x : rr.y;
     }
-    s.wsum[w] = sum;
-    nleft += sum < 1.0;
+    sum = wave_sum_d(sum);
+    if (lane == 0) {
+      s.wsum[w] = sum;
+      nleft += sum < 1.0;
+    }
   }
-  wave_count(&s.cnt[kCntWispsLeft], nleft);
+  wave_count(cnt_at(s.cnt, kCntWispsLeft), nleft);
 }
 
 __global__ __launch_bounds__(kBlock) void k_wisp_moves(DMesh m, DState s, DParams p) {
   const int nr = s.work[kWRecv], nw = s.work[kWWisps];
   const uint32_t stamp = s.wctr[0] + 1u;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nr + nw; i += gridDim.x * blockDim.x) {
+  const int lane = lane_id();
+  for (int i = wave_index(); i < nr + nw; i += wave_stride()) {
     if (i < nr) {
       const int r = s.rlist[i];
       const double2 rr = s.rho[r];
+      const int k1 = m.cpn_off[r + 1];
       double gain = 0.0;
-      for (int k = m.cpn_off[r]; k < m.cpn_off[r + 1]; ++k) {
+      for (int k = m.cpn_off[r] + lane; k < k1; k += kWave) {
         const int w = m.cpn[k];
         if (s.wstamp[w] != stamp) continue;
         const double e = s.wex[w], sum = s.wsum[w];
         gain += e * (e > 0.0 ? rr.x : rr.y) * (sum > 1.0 ? 1.0 / sum : 1.0);
       }
-      s.alpha[r] += gain / m.V[r];
-    } else {
+      gain = wave_sum_d(gain);
+      if (lane == 0) s.alpha[r] += gain / m.V[r];
+    } else if (lane == 0) {
       const int w = s.wlist[i - nr];
       const double a = s.alpha[w], sum = s.wsum[w];
       s.alpha[w] = sum >= 1.0 ? (a <= p.eps ? 0.0 : 1.0) : a - s.wex[w] * sum / m.V[w];
@@ -1131,12 +1166,12 @@ __global__ __launch_bounds__(kBlock) void k_ledger(DMesh m, DState s, DParams p,
   }
   if (threadIdx.x == 0) {
     s.ledger[0] += red[0];
-    s.cnt[kCntSteps] += 1;
-    s.cnt[kCntGeometric] += (unsigned long long)s.work[kWGeometric];
-    s.cnt[kCntInterface] += (unsigned long long)s.work[kWInterface];
-    s.cnt[kCntDeferred] += (unsigned long long)s.work[kWDeferred];
+    *cnt_at(s.cnt, kCntSteps) += 1;
+    *cnt_at(s.cnt, kCntGeometric) += (unsigned long long)s.work[kWGeometric];
+    *cnt_at(s.cnt, kCntInterface) += (unsigned long long)s.work[kWInterface];
+    *cnt_at(s.cnt, kCntDeferred) += (unsigned long long)s.work[kWDeferred];
     if (p.wisps) {
-      s.cnt[kCntWisps] += (unsigned long long)s.work[kWWisps];
+      *cnt_at(s.cnt, kCntWisps) += (unsigned long long)s.work[kWWisps];
       s.wctr[0] += 1u;  // the next step's wisps and receivers get a new stamp
     }
     s.stepno[0] += 1;  // the next step reads dt, scale at the next index

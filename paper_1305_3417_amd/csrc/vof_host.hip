@@ -497,7 +497,7 @@ vof_status vof_mesh_upload(vof_context *ctx, const vof_mesh_desc *d, vof_mesh **
   ALLOC(ds.vphase, nf); ALLOC(ds.vscale, nf); ALLOC(ds.iters, nf); ALLOC(ds.kind, nf); ALLOC(ds.fstatus, nf);
   ALLOC(ds.icells, nc); ALLOC(ds.gfaces, nf); ALLOC(ds.tetvol, nf * (int64_t)dm.tpf);
   ALLOC(ds.defer, nf * (int64_t)dm.tpf);
-  ALLOC(ds.stepno, 1); ALLOC(ds.work, kWNum); ALLOC(ds.cnt, kCntNum); ALLOC(ds.flags, 1); ALLOC(ds.ledger, 1);
+  ALLOC(ds.stepno, 1); ALLOC(ds.work, kWNum); ALLOC(ds.cnt, kCntWords); ALLOC(ds.flags, 1); ALLOC(ds.ledger, 1);
   ALLOC(ds.part, 256);
   ALLOC(m->stats_buf, 4);
 #undef ALLOC
@@ -510,7 +510,7 @@ vof_status vof_mesh_upload(vof_context *ctx, const vof_mesh_desc *d, vof_mesh **
   UP(d_pc, pc.data(), (int64_t)pc.size()); UP(d_st_off, st_off.data(), nf + 1);
   UP(d_st, st.data(), (int64_t)st.size());
 #undef UP
-  hipError_t e = hipMemsetAsync(ds.cnt, 0, sizeof(unsigned long long) * kCntNum, s);
+  hipError_t e = hipMemsetAsync(ds.cnt, 0, sizeof(unsigned long long) * kCntWords, s);
   if (e == hipSuccess) e = hipMemsetAsync(ds.flags, 0, sizeof(uint32_t), s);
   if (e == hipSuccess) e = hipMemsetAsync(ds.ledger, 0, sizeof(double), s);
   if (e == hipSuccess) e = hipMemsetAsync(ds.cls, 0, nc, s);
@@ -805,9 +805,12 @@ vof_status vof_get_stats(vof_mesh *m, vof_stats *out) {
   hipStream_t s = m->ctx->stream;
   launch_stats(m->dm, m->ds, m->stats_buf, s);
   HIP_OR_FAIL(hipGetLastError());
-  unsigned long long c[kCntNum];
+  std::vector<unsigned long long> slots(kCntWords);
+  unsigned long long c[kCntNum] = {0};
   double st4[4], led = 0.0;
-  if ((rc = from_device(c, m->ds.cnt, kCntNum, VOF_HOST, s))) return rc;
+  if ((rc = from_device(slots.data(), m->ds.cnt, kCntWords, VOF_HOST, s))) return rc;
+  for (int id = 0; id < kCntNum; ++id)
+    for (int l = 0; l < kCntLanes; ++l) c[id] += slots[((int64_t)id * kCntLanes + l) * kCntStride];
   if ((rc = from_device(st4, m->stats_buf, 4, VOF_HOST, s))) return rc;
   if ((rc = from_device(&led, m->ds.ledger, 1, VOF_HOST, s))) return rc;
   out->steps = (int64_t)c[kCntSteps];
@@ -835,7 +838,7 @@ vof_status vof_reset_stats(vof_mesh *m) {
   vof_status rc = set_device(m->ctx);
   if (rc) return rc;
   hipStream_t s = m->ctx->stream;
-  HIP_OR_FAIL(hipMemsetAsync(m->ds.cnt, 0, sizeof(unsigned long long) * kCntNum, s));
+  HIP_OR_FAIL(hipMemsetAsync(m->ds.cnt, 0, sizeof(unsigned long long) * kCntWords, s));
   HIP_OR_FAIL(hipMemsetAsync(m->ds.flags, 0, sizeof(uint32_t), s));
   HIP_OR_FAIL(hipMemsetAsync(m->ds.ledger, 0, sizeof(double), s));
   HIP_OR_FAIL(hipStreamSynchronize(s));

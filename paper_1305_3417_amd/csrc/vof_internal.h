@@ -44,6 +44,13 @@ enum Counter : int {
 };
 
 // per-step work counters (reset every step)
+// Each counter is spread over kCntLanes slots, one 128-byte line apart,
+// picked by block index: atomics of many blocks on one address serialise in
+// L2.  The host adds the slots when it reads the counters.
+constexpr int kCntLanes = 64;
+constexpr int kCntStride = 16;
+constexpr int64_t kCntWords = (int64_t)kCntNum * kCntLanes * kCntStride;
+
 enum WorkCounter : int {
   kWInterface = 0, kWGeometric = 1, kWDeferred = 2, kWClipNext = 3, kWWisps = 4, kWRecv = 5,
   kWNum = 6
@@ -113,7 +120,7 @@ struct DState {
   double *tetgross;     // stencil check only: unsigned tet volume
   int32_t *defer;       // flux tets left to the general clipper
   int32_t *work;        // per-step counters (kWNum)
-  unsigned long long *cnt;  // kCntNum
+  unsigned long long *cnt;  // kCntWords (kCntNum counters x kCntLanes slots)
   uint32_t *flags;      // latched status bits
   double *ledger;       // accumulated boundary phase volume
   double *part;         // partial sums of the ledger (256)
