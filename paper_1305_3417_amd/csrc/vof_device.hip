@@ -35,6 +35,7 @@ constexpr int kFastBlock = 64;   // one wave per block in the register clip
 constexpr int kFastSlots = 4;    // queued pairs of two or more planes per tet
 constexpr int kFastPlanes = 3;   // planes per pair in the register clip (more: general)
 constexpr int kFastGrid = 4096;   // blocks claim face groups from a counter
+constexpr int kClaim = 2;         // face groups per claim
 constexpr int kGroupFaces = 4;    // faces per wavefront group (64 / at least 15 tets)
 constexpr int kCand = 16;         // candidate cells per face kept in LDS
 constexpr int kPlaneGrid = 2048;  // blocks of four waves, one interface cell per wave
@@ -700,8 +701,23 @@ __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3)))
   const int F = kFastBlock / tpf;  // faces per group, 1..kGroupFaces
   const int ngroups = (count + F - 1) / F;
   unsigned long long npairs = 0;
+  // Groups are taken kClaim at a time: the first kClaim by block index, the
+  // rest claimed from a counter.  Thousands of waves claiming one group each
+  // serialise on the counter's atomic, above all at the start of the kernel.
+  int left = -1;
   for (;;) {
-    if (lane == 0) group = atomicAdd(&s.work[kWClipNext], 1);
+    if (lane == 0) {
+      if (left < 0) {
+        group = kClaim * (int)blockIdx.x;
+        left = kClaim;
+      } else if (left == 0) {
+        group = kClaim * ((int)gridDim.x + atomicAdd(&s.work[kWClipNext], 1));
+        left = kClaim;
+      } else {
+        group = group + 1;
+      }
+      --left;
+    }
     if (lane < kFastPlanes - 1) nbin[lane] = 0;
     // flux polyhedron boxes, one lane per face (points and their swept
     // images).  Unpadded: a cell that only touches the box meets the
