@@ -161,7 +161,7 @@ def main():
                          "(eq. 4.5, adaptive Courant dt)")
     ap.add_argument("--band-wisps", action="store_true",
                     help="run the step with the narrow band and wisp redistribution "
-                         "(Section 2.4) after the update")
+                         "(Section 2.3) after the update")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",

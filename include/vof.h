@@ -126,13 +126,13 @@ vof_status vof_mesh_get_info(const vof_mesh *mesh, vof_mesh_info *out);
  * generalized least-squares gradient over the cells sharing a point with the
  * cell, inverse-distance weighted, Section 2.2.1 -- the first reconstruction
  * with it builds that cell stencil on the host), narrow_band 0 (1: the narrow
- * band of Section 2.4 -- bulk cells, those whose cells sharing a point, the
+ * band of Section 2.3 -- bulk cells, those whose cells sharing a point, the
  * cell included, all hold alpha exactly 0 or all exactly 1, are not updated;
  * their update is zero in exact arithmetic), wisps 0 (1: after every update,
  * wisps -- cells outside the interface band eps < alpha < 1 - eps whose
  * alpha is not exactly 0 or 1, over- and undershoots included -- move their
  * excess over 0 or 1 to the interface cells sharing a point with them
- * (Section 2.4): each receiver offers the room (1 - eps - alpha) V, or for a
+ * (Section 2.3): each receiver offers the room (1 - eps - alpha) V, or for a
  * deficit the store (alpha - eps) V, it has, shared among the wisps around
  * it in proportion to their excess; a wisp moves at most what it is offered,
  * split in proportion to the offers, and is set to exactly 0 or 1 when it
@@ -249,7 +249,7 @@ vof_status vof_read_profile(vof_mesh *mesh, double *ms, int64_t *launches, int32
 double vof_selftest_tet_clip(const double *tet, int32_t n_planes, const double *planes);
 
 /* Host self-test of the register-only closed forms the clip kernels use for a
- * (tetrahedron, cell) pair bounded by at most four planes (Section 2.4: the
+ * (tetrahedron, cell) pair bounded by at most four planes (Section 2.1: the
  * tetrahedron's kept part under each plane as one or three tetrahedra, the
  * last plane by the closed-form kept fraction).  Same arguments and result
  * as vof_selftest_tet_clip; NaN for n_planes > 4 or a bad argument. */

@@ -131,12 +131,12 @@ class Oracle:
         lib().orc_set_gradient(self.h, 1 if kind == "lsq" else 0)
 
     def set_band(self, on: bool):
-        """Narrow band (Section 2.4): bulk cells are not updated."""
+        """Narrow band (Section 2.3): bulk cells are not updated."""
         self.band = bool(on)
         lib().orc_set_band(self.h, int(self.band))
 
     def set_wisps(self, on: bool):
-        """Wisp redistribution after every update (Section 2.4)."""
+        """Wisp redistribution after every update (Section 2.3)."""
         self.wisps = bool(on)
         lib().orc_set_wisps(self.h, int(self.wisps))
 

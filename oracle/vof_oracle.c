@@ -25,9 +25,9 @@
  *                     the PLIC half-space in interface cells (eq. 2.23), by
  *                     plane clipping and capping (Section 2.1)
  *   update            eq. 2.2 with owner/neighbour signs (eq. 2.5); optionally
- *                     only outside the bulk (the narrow band, Section 2.4)
+ *                     only outside the bulk (the narrow band, Section 2.3)
  *   wisps             optional conservative redistribution of wisps to the
- *                     interface cells around them (Section 2.4)
+ *                     interface cells around them (Section 2.3)
  *
  * Build: gcc -O2 -fopenmp -shared -fPIC -o liboracle.so vof_oracle.c -lm
  */
@@ -275,7 +275,7 @@ typedef struct {
   double *grad;              /* NAG gradient (3 nc)                    */
   double eps;                /* reconstruction tolerance               */
   int grad_kind;             /* 0 NAG (Section 2.2.1), 1 generalized LSQ */
-  int band;                  /* 1: bulk cells are not updated (Section 2.4) */
+  int band;                  /* 1: bulk cells are not updated (Section 2.3) */
   int wisps;                 /* 1: wisps redistributed after the update */
 } omesh;
 
@@ -737,7 +737,7 @@ static void nag_gradient(const omesh *M, int64_t c, const double *alpha, const d
 }
 
 /* The cells other than c that share a point with c, each once, in
- * ascending order (the point neighbours of Sections 2.2.1 and 2.4).  The
+ * ascending order (the point neighbours of Sections 2.2.1 and 2.3).  The
  * caller frees the list. */
 static int32_t *point_neighbours(const omesh *M, int64_t c, int64_t *count) {
   int32_t *nb = NULL;
@@ -1014,7 +1014,7 @@ int64_t orc_phase_flux(const omesh *M, double dt, double s, const double *lam,
 /* ------------------------------------------------------------------ */
 /* conservative update (eq. 2.2 with eq. 2.5; outflow-only phase volume) */
 /* ------------------------------------------------------------------ */
-/* READING (Section 2.4, narrow band): a bulk cell is one whose volume
+/* READING (Section 2.3, narrow band): a bulk cell is one whose volume
  * fraction gradient vanishes; taken here as a cell such that it and every
  * cell sharing a point with it hold alpha exactly 0, or all exactly 1.  Then
  * every inverse-distance point value of the cell equals its alpha and the NAG
@@ -1058,7 +1058,7 @@ double orc_update(const omesh *M, const double *alpha, const double *vphase, dou
 }
 
 /* ------------------------------------------------------------------ */
-/* wisp redistribution (Section 2.4)                                    */
+/* wisp redistribution (Section 2.3)                                    */
 /* ------------------------------------------------------------------ */
 /* Wisps, small volume fractions left outside the interface band by the
  * update, are moved conservatively to the interface cells around them, and

@@ -983,7 +983,7 @@ __global__ __launch_bounds__(kBlock) void k_face_sum(DMesh m, DState s, DParams 
 }
 
 // alpha_c^{n+1} = alpha_c^n - (1/V_c) sum_f sgn_cf V_{f,alpha}, every cell;
-// with the narrow band (Section 2.4) every cell but the bulk cells, those
+// with the narrow band (Section 2.3) every cell but the bulk cells, those
 // whose faces' points touch only cells that are exactly 0 (or only exactly 1),
 // so that every cell sharing a point with them is.  With wisps on, the
 // updated cells outside the interface band whose alpha is not exactly 0 or
@@ -1033,7 +1033,7 @@ __global__ __launch_bounds__(kBlock) void k_update(DMesh m, DState s, DParams p)
 }
 
 // ---------------------------------------------------------------------------
-// wisp redistribution (Section 2.4), four passes over this step's wisps and
+// wisp redistribution (Section 2.3), four passes over this step's wisps and
 // their receivers (interface cells sharing a point with a wisp):
 //   receivers   each wisp lists the interface cells around it, once each
 //   offers      per receiver r: rho+ = (1 - eps - alpha_r) V_r / sum of the

@@ -255,7 +255,7 @@ def test_lsq_gradient_reconstruction(vof, ctx, oracle_mod, case):
 
 
 def test_narrow_band_leaves_bulk_cells(vof, ctx, oracle_mod):
-    """Narrow band (Section 2.4), one step of the deformation field: the bulk
+    """Narrow band (Section 2.3), one step of the deformation field: the bulk
     cells (every cell sharing a point exactly 0, or all exactly 1) keep their
     alpha bit for bit; the others match the oracle's band step."""
     w = W.deform3d(24, steps=2)
@@ -279,7 +279,7 @@ WISP_CASES = {
 
 @pytest.mark.parametrize("case", sorted(WISP_CASES))
 def test_narrow_band_and_wisps(vof, ctx, oracle_mod, case):
-    """Narrow band and wisp redistribution (Section 2.4) over a run: alpha
+    """Narrow band and wisp redistribution (Section 2.3) over a run: alpha
     within 1e-10 of the oracle's, volume conserved with the ledger, and a
     second run bitwise identical (the wisp and receiver lists are filled by
     atomics in any order, every sum runs in stencil order)."""

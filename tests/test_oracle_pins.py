@@ -533,7 +533,7 @@ def test_vsd_converges_nag_and_lsq(oracle_mod):
 
 
 # --------------------------------------------------------------------------
-# narrow band and wisp redistribution (Section 2.4)
+# narrow band and wisp redistribution (Section 2.3)
 # --------------------------------------------------------------------------
 
 def _cell_points(mesh):
