@@ -79,6 +79,7 @@ def lib():
         L.orc_set_wisps.argtypes = [vp, C.c_int]
         L.orc_bulk_cells.argtypes = [vp, vp, vp]
         L.orc_redistribute.argtypes = [vp, vp, vp]
+        L.orc_map_alpha.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -259,6 +260,25 @@ class Oracle:
         lib().orc_advect(self.h, _p(a), int(dt.shape[0]), _p(dt), _p(scale), int(check_leak),
                          C.byref(st), _p(lam), _p(vp))
         return a, st.as_dict(), lam, vp
+
+    def map_alpha(self, src, alpha_src, map_offsets, map_cells):
+        """Volume fraction on this mesh from alpha_src on the mesh of the
+        oracle `src` (Section 3, Algorithm 2): src reconstructs alpha_src, and
+        new cell c takes the old cells map_cells[map_offsets[c]:map_offsets[c+1]]
+        (one old cell containing c, or several whose union is c)."""
+        alpha_src = np.ascontiguousarray(alpha_src, dtype=np.float64)
+        rec = src.reconstruct(alpha_src)
+        V_src = src.geometry()[0]
+        off = np.ascontiguousarray(map_offsets, dtype=np.int64)
+        cells = np.ascontiguousarray(map_cells, dtype=np.int32)
+        assert off.shape[0] == self.nc + 1 and off[-1] == cells.shape[0]
+        cls = np.ascontiguousarray(rec["cls"], dtype=np.int8)
+        n = np.ascontiguousarray(rec["n"], dtype=np.float64)
+        s = np.ascontiguousarray(rec["s"], dtype=np.float64)
+        out = np.empty(self.nc)
+        lib().orc_map_alpha(self.h, _p(off), _p(cells), _p(alpha_src), _p(V_src), _p(cls),
+                            _p(n), _p(s), _p(out))
+        return out
 
     # subsets (sampled checks of large runs) --------------------------------
     def reconstruct_subset(self, alpha, cells):

@@ -28,6 +28,8 @@
  *                     only outside the bulk (the narrow band, Section 2.3)
  *   wisps             optional conservative redistribution of wisps to the
  *                     interface cells around them (Section 2.3)
+ *   mapping           volume fraction on a changed mesh from the old
+ *                     reconstruction (Section 3, Algorithm 2)
  *
  * Build: gcc -O2 -fopenmp -shared -fPIC -o liboracle.so vof_oracle.c -lm
  */
@@ -1167,6 +1169,43 @@ void orc_redistribute(const omesh *M, double *alpha, int64_t *counts) {
 
 void orc_set_band(omesh *M, int band) { M->band = band; }
 void orc_set_wisps(omesh *M, int wisps) { M->wisps = wisps; }
+
+/* ------------------------------------------------------------------ */
+/* geometric mapping after a mesh change (Section 3, Algorithm 2)       */
+/* ------------------------------------------------------------------ */
+/* The volume fraction of each cell of the new mesh M is the part of it that
+ * the old mesh's reconstruction fills.  For new cell c, map_cell lists the
+ * old cells it came from (map_off is CSR over the new cells):
+ *   - one old cell o that contains c (c refined from o, or c = o): the
+ *     paper intersects o's interface plane with c, so alpha_c =
+ *     |C_c ∩ {n_o . x <= s_o}| / V_c for an interface cell o; READING: for
+ *     an empty, full or vanishing-gradient cell o, alpha_c = alpha_o (the
+ *     old cell's content spread evenly, which keeps the volume exactly);
+ *   - several old cells whose union is c (c coarsened from them): READING,
+ *     the union of their reconstructed phase volumes, alpha_c =
+ *     sum_o alpha_o V_o / V_c (|C_o ∩ I_o| = alpha_o V_o by the
+ *     positioning).
+ * cls_old, n_old (3 per cell), s_old: the reconstruction of alpha_old on the
+ * old mesh (classes 0 empty, 1 interface, 2 full, 3 vanishing gradient). */
+void orc_map_alpha(const omesh *M, const int64_t *map_off, const int32_t *map_cell,
+                   const double *alpha_old, const double *V_old, const int8_t *cls_old,
+                   const double *n_old, const double *s_old, double *alpha_new) {
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t c = 0; c < M->nc; ++c) {
+    const int64_t k0 = map_off[c], k1 = map_off[c + 1];
+    if (k1 - k0 == 1) {
+      const int32_t o = map_cell[k0];
+      if (cls_old[o] == 1)
+        alpha_new[c] = cell_cut_volume(M, c, &n_old[3 * o], s_old[o]) / M->V[c];
+      else
+        alpha_new[c] = alpha_old[o];
+    } else {
+      double v = 0.0;
+      for (int64_t k = k0; k < k1; ++k) v += alpha_old[map_cell[k]] * V_old[map_cell[k]];
+      alpha_new[c] = v / M->V[c];
+    }
+  }
+}
 
 /* ------------------------------------------------------------------ */
 /* time loop: all geometry of step n uses alpha^n (explicit Euler, eq. 2.2) */

@@ -689,3 +689,72 @@ def test_redistribution_conserves_and_keeps_receivers_in_band(oracle_mod):
         a = new
     assert total > 100
     assert abs(np.sum(V * a) + ledger - m0) <= 1e-12 * m0
+
+
+# --------------------------------------------------------------------------
+# geometric mapping after refinement (Section 3, Algorithm 2)
+# --------------------------------------------------------------------------
+
+def _refined_pair(n, alpha_fn):
+    """Uniform n^3 mesh with alpha, and its refinement of the interface cells."""
+    from workloads.refine import refine_hex
+    m0 = W.hex_mesh(n, n, n)
+    a0 = alpha_fn(m0.cell_lo, m0.cell_hi)
+    m1, parent, children = refine_hex(n, (a0 > 0) & (a0 < 1))
+    return m0, a0, m1, parent, children
+
+
+def test_mapping_of_a_diagonal_plane_is_exact(oracle_mod):
+    """alpha = exact fractions of {x + y + z <= c}: the NAG normal of interior
+    cells is (1,1,1)/sqrt 3 by symmetry and the plane is positioned exactly, so
+    every child of an interior interface cell gets the exact fraction of the
+    half-space in its own box (truncated box in exact rationals).  The parent's
+    plane is placed to a fill-level tolerance of 1e-15, which a child of an
+    eighth of the volume sees up to eight times over: 1e-14."""
+    c = Q(45, 32)
+    n = 8
+
+    def frac(lo, hi):
+        return np.array([float(X.truncated_box_volume((1, 1, 1), c, tuple(map(Q, l)), tuple(map(Q, h)))
+                               / np.prod([Q(b) - Q(a) for a, b in zip(l, h)]))
+                         for l, h in zip(lo, hi)])
+    m0, a0, m1, parent, _ = _refined_pair(n, frac)
+    o0, o1 = oracle_mod.Oracle(m0), oracle_mod.Oracle(m1)
+    a1 = o1.map_alpha(o0, a0, np.arange(m1.n_cells + 1), parent)
+    exact = frac(m1.cell_lo, m1.cell_hi)
+    ijk = np.stack([parent % n, (parent // n) % n, parent // (n * n)], 1)
+    interior = np.all((ijk >= 2) & (ijk <= n - 3), axis=1)
+    iface = (a0[parent] > 0) & (a0[parent] < 1)
+    sel = interior & iface
+    assert sel.sum() > 50
+    assert np.abs(a1[sel] - exact[sel]).max() < 1e-14
+    assert np.array_equal(a1[~iface], a0[parent][~iface])
+
+
+def test_mapping_conserves_volume_per_parent(oracle_mod):
+    """The children of a refined interface cell share exactly the volume its
+    PLIC polyhedron held, alpha V (to the positioning tolerance)."""
+    from workloads import fields
+    n = 10
+    m0, a0, m1, parent, (coff, cells) = _refined_pair(
+        n, lambda lo, hi: fields.ball_box_fraction((0.52, 0.47, 0.5), 0.27, lo, hi))
+    o0, o1 = oracle_mod.Oracle(m0), oracle_mod.Oracle(m1)
+    a1 = o1.map_alpha(o0, a0, np.arange(m1.n_cells + 1), parent)
+    V0, V1 = o0.geometry()[0], o1.geometry()[0]
+    per_parent = np.zeros(m0.n_cells)
+    np.add.at(per_parent, parent, a1 * V1)
+    assert np.abs(per_parent - a0 * V0).max() <= 2e-15 * V0.max()
+    assert np.all((a1 >= -1e-14) & (a1 <= 1 + 1e-14))  # cut volumes round
+
+
+def test_mapping_back_by_union_restores_alpha(oracle_mod):
+    """Refine, then undo it: each uniform cell is the union of its children and
+    gets sum alpha V / V back, the original alpha to rounding."""
+    from workloads import fields
+    n = 8
+    m0, a0, m1, parent, (coff, cells) = _refined_pair(
+        n, lambda lo, hi: fields.ball_box_fraction((0.5, 0.5, 0.5), 0.3, lo, hi))
+    o0, o1 = oracle_mod.Oracle(m0), oracle_mod.Oracle(m1)
+    a1 = o1.map_alpha(o0, a0, np.arange(m1.n_cells + 1), parent)
+    back = o0.map_alpha(o1, a1, coff, cells)
+    assert np.abs(back - a0).max() <= 2e-15

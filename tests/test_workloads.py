@@ -79,3 +79,77 @@ def test_courant_schedule_rule():
     assert courant.max() <= co * 1.05
     # the slowed-down middle of the run uses the longer steps
     assert dt.max() == 2.0 * dt[0] and len(dt) < T / dt[0]
+
+
+# --------------------------------------------------------------------------
+# 2:1 refined hexahedral meshes
+# --------------------------------------------------------------------------
+
+def _sphere_band_mask(n, centre=(0.45, 0.5, 0.55), r=0.3, width=0.6):
+    k, j, i = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    xc = (np.stack([i.ravel(), j.ravel(), k.ravel()], 1) + 0.5) / n
+    d = np.abs(np.linalg.norm(xc - np.asarray(centre), axis=1) - r)
+    return d < width / n
+
+
+def test_refined_mesh_is_conforming():
+    """Every cell's outward faces close up: each directed edge of its surface
+    has its reverse in the same cell (so faces list the points neighbours add
+    on shared edges), the area vectors sum to zero, volumes and centroids are
+    those of the generating boxes, and no cell has more than 15 faces or a
+    face more than 8 points."""
+    from workloads.refine import refine_hex
+    n = 6
+    m, parent, (coff, cells) = refine_hex(n, _sphere_band_mask(n))
+    assert m.meta["refined"] > 0
+    off = m.face_offsets
+    faces_of = [[] for _ in range(m.n_cells)]
+    for f in range(m.n_faces):
+        ps = m.face_points[off[f]:off[f + 1]].tolist()
+        faces_of[m.owner[f]].append(ps)
+        if f < m.n_internal:
+            faces_of[m.neighbour[f]].append(ps[::-1])
+    for c, fs in enumerate(faces_of):
+        assert len(fs) <= 15
+        edges = {}
+        for ps in fs:
+            assert 4 <= len(ps) <= 8
+            for a, b in zip(ps, ps[1:] + ps[:1]):
+                edges[(a, b)] = edges.get((a, b), 0) + 1
+        assert all(v == 1 and edges.get((b, a)) == 1 for (a, b), v in edges.items()), c
+        # area vectors of the outward faces sum to zero; volume by divergence
+        X = m.points
+        Ssum = np.zeros(3)
+        vol = 0.0
+        for ps in fs:
+            P = X[ps]
+            cf = P.mean(axis=0)
+            for a, b in zip(P, np.roll(P, -1, axis=0)):
+                Ssum += 0.5 * np.cross(a - cf, b - cf)
+                vol += np.dot(cf, np.cross(a - cf, b - cf)) / 6.0
+        assert np.abs(Ssum).max() < 1e-15
+        assert abs(vol - np.prod(m.cell_hi[c] - m.cell_lo[c])) < 1e-15
+    # parent and children maps agree
+    assert coff[-1] == m.n_cells and np.array_equal(np.repeat(np.arange(n ** 3), np.diff(coff)), parent)
+    for o in range(n ** 3):
+        kids = cells[coff[o]:coff[o + 1]]
+        lo = m.cell_lo[kids].min(axis=0)
+        hi = m.cell_hi[kids].max(axis=0)
+        i, j, k = o % n, (o // n) % n, o // (n * n)
+        assert np.allclose(lo, np.array([i, j, k]) / n) and np.allclose(hi, np.array([i + 1, j + 1, k + 1]) / n)
+
+
+def test_refinement_closure():
+    """No coarse cell is left with more than three refined face neighbours."""
+    from workloads.refine import close_refinement
+    n = 7
+    rng = np.random.default_rng(3)
+    m = close_refinement(n, rng.random(n ** 3) < 0.3).reshape(n, n, n)
+    cnt = np.zeros(m.shape, dtype=int)
+    for ax in range(3):
+        lo = [slice(None)] * 3
+        hi = [slice(None)] * 3
+        lo[ax], hi[ax] = slice(0, n - 1), slice(1, n)
+        cnt[tuple(lo)] += m[tuple(hi)]
+        cnt[tuple(hi)] += m[tuple(lo)]
+    assert cnt[~m].max(initial=0) <= 3
