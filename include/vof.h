@@ -159,6 +159,27 @@ vof_status vof_set_params(vof_mesh *mesh, const vof_params *p);
 vof_status vof_set_alpha(vof_mesh *mesh, const double *alpha, int32_t memory);
 vof_status vof_read_alpha(vof_mesh *mesh, double *out, int32_t memory);
 
+/* Geometric mapping of the volume fraction after a mesh change (Section 3,
+ * Algorithm 2), e.g. after 2:1 refinement or its undoing.  src holds the old
+ * mesh and its alpha; it is reconstructed (Algorithm 1, with src's
+ * parameters), and every cell c of dst takes its alpha from the old cells
+ * map_cells[map_offsets[c] .. map_offsets[c + 1] - 1]:
+ *   - one old cell o that contains c (c refined from o, or the same cell):
+ *     alpha_c = |C_c ∩ {n_o . x <= s_o}| / V_c for an interface cell o (the
+ *     old plane intersected with the new cell), alpha_o for an empty, full or
+ *     vanishing-gradient cell o;
+ *   - several old cells whose union is c (c coarsened from them):
+ *     alpha_c = sum_o alpha_o V_o / V_c.
+ * Both meshes live on the same device.  map_offsets: n_cells(dst) + 1
+ * int32 starting at 0, every cell with at least one entry; map_cells: int32
+ * cells of src; both in `memory` (host arrays are checked before any work,
+ * device arrays by the kernel).  Synchronises.  Resets dst's statistics like
+ * vof_set_alpha.  Errors: VOF_EINVAL (null or equal meshes, different
+ * devices, src alpha not set, a bad map -- then dst's alpha is not set),
+ * VOF_ENOMEM, VOF_EDEVICE. */
+vof_status vof_map_alpha(vof_mesh *dst, vof_mesh *src, const int32_t *map_offsets,
+                         const int32_t *map_cells, int32_t memory);
+
 /* Reference velocity: U0c (3 * n_cells, x y z interleaved, cell-centred) and
  * the reference face volumetric flux F0 (n_faces; discretely divergence
  * free, eq. 2.4).  Step n of vof_advect uses scale[n] * U0c and

@@ -43,7 +43,7 @@ VOF_GRADIENT_LSQ = 1
 EXPORTED = [
     "vof_context_create", "vof_context_destroy", "vof_last_error", "vof_version",
     "vof_mesh_upload", "vof_mesh_destroy", "vof_mesh_get_info", "vof_get_params",
-    "vof_set_params", "vof_set_alpha", "vof_read_alpha", "vof_set_velocity",
+    "vof_set_params", "vof_set_alpha", "vof_read_alpha", "vof_map_alpha", "vof_set_velocity",
     "vof_reconstruct", "vof_advect", "vof_read_face", "vof_read_planes",
     "vof_read_point_velocity", "vof_get_stats", "vof_reset_stats", "vof_synchronize",
     "vof_selftest_tet_clip", "vof_selftest_tet_clip_closed", "vof_profile_enable", "vof_profile_kernel_name", "vof_read_profile",
@@ -117,6 +117,7 @@ def lib():
             "vof_set_params": (i32, [vp, C.POINTER(vof_params)]),
             "vof_set_alpha": (i32, [vp, vp, i32]),
             "vof_read_alpha": (i32, [vp, vp, i32]),
+            "vof_map_alpha": (i32, [vp, vp, vp, vp, i32]),
             "vof_set_velocity": (i32, [vp, vp, vp, i32]),
             "vof_reconstruct": (i32, [vp]),
             "vof_advect": (i32, [vp, i32, vp, vp]),
@@ -300,6 +301,18 @@ def vof_set_alpha(mesh: MeshHandle, alpha):
     if keep.shape[0] != mesh.n_cells:
         raise ValueError("alpha must have n_cells entries")
     _check(lib().vof_set_alpha(mesh.h, p, mem), "vof_set_alpha")
+
+
+def vof_map_alpha(dst: MeshHandle, src: MeshHandle, map_offsets, map_cells):
+    """alpha of dst from src's alpha by the geometric mapping (int32 CSR over
+    dst's cells of src cells: one containing cell, or the cells of a union)."""
+    po, mo, ko = _arg(map_offsets, np.int32)
+    pc, mc, kc = _arg(map_cells, np.int32)
+    if mo != mc:
+        raise TypeError("map_offsets and map_cells must both be host or both device arrays")
+    if ko.shape[0] != dst.n_cells + 1:
+        raise ValueError("map_offsets must have n_cells(dst) + 1 entries")
+    _check(lib().vof_map_alpha(dst.h, src.h, po, pc, mo), "vof_map_alpha")
 
 
 def vof_read_alpha(mesh: MeshHandle, out=None, ok=(VOF_OK,)):

@@ -78,14 +78,14 @@ VHD bool flux_tet(const DMesh &m, const DState &s, double dt, double sc, int f, 
 // Classification of a (tet, cell) pair on the register path: -1 when the
 // pair contributes nothing (bounding boxes apart, or the tet outside one of
 // the cell's planes), else the number of cell planes that cut the tet, with
-// bit j of mask set for plane cf_off[cell] + j.
+// bit j of mask set for plane cf_off[cell] + j (the cell's distinct planes).
 VHD int pair_cuts_box(const DMesh &m, v3 c, const Tet &T, v3 lo, v3 hi, v3 blo, v3 bhi, int cell,
                       uint32_t &mask) {
   mask = 0;
   if (hi.x <= blo.x || lo.x >= bhi.x || hi.y <= blo.y || lo.y >= bhi.y || hi.z <= blo.z ||
       lo.z >= bhi.z)
     return -1;
-  const int q0 = m.cf_off[cell], q1 = m.cf_off[cell + 1];
+  const int q0 = m.cf_off[cell], q1 = q0 + m.npl[cell];
   for (int q = q0; q < q1; ++q) {
     double4 cp = m.cpl[q];
     v3 nn = xyz4(cp);
@@ -193,7 +193,7 @@ VHD double pair_phase6(const DMesh &m, const DState &s, const DParams &p, v3 c, 
   int cuts[kMaxCellPlanes];
   Pl p0{0, 0, 0, 0}, p1 = p0, p2 = p0, p3 = p0;
   int ncut = 0;
-  for (int q = m.cf_off[cell]; q < m.cf_off[cell + 1]; ++q) {
+  for (int q = m.cf_off[cell], q1 = m.cf_off[cell] + m.npl[cell]; q < q1; ++q) {
     double4 cp = m.cpl[q];
     v3 nn = xyz4(cp);
     double off = cp.w - dot(nn, c);

@@ -179,19 +179,30 @@ __global__ void k_cell_geom(DMesh m, double *V, double4 *XC, double4 *bblo, doub
 }
 
 // cell face planes: outward unit normal sgn * S/|S| and offset through c_f;
-// the two cells of a face get exactly opposite planes
-__global__ void k_cell_planes(DMesh m, double4 *cpl) {
+// the two cells of a face get exactly opposite planes.  A plane equal (bit
+// for bit) to one the cell has already is not repeated: the coplanar faces a
+// coarse cell shares with refined neighbours are one plane of the cell.
+__global__ void k_cell_planes(DMesh m, double4 *cpl, uint8_t *npl) {
   int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (c >= m.nc) return;
-  for (int k = m.cf_off[c]; k < m.cf_off[c + 1]; ++k) {
+  const int k0 = m.cf_off[c];
+  int cnt = 0;
+  for (int k = k0; k < m.cf_off[c + 1]; ++k) {
     int sf = m.cf[k];
     int f = sf >= 0 ? sf : ~sf;
     double4 S = m.S[f];
     v3 n = (1.0 / S.w) * xyz(S);
     double d = dot(n, xyz(m.C[f]));
     double sg = sf >= 0 ? 1.0 : -1.0;
-    cpl[k] = make_double4(sg * n.x, sg * n.y, sg * n.z, sg * d);
+    const double4 pl = make_double4(sg * n.x, sg * n.y, sg * n.z, sg * d);
+    bool dup = false;
+    for (int q = 0; q < cnt; ++q) {
+      const double4 o = cpl[k0 + q];
+      dup |= o.x == pl.x && o.y == pl.y && o.z == pl.z && o.w == pl.w;
+    }
+    if (!dup) cpl[k0 + cnt++] = pl;
   }
+  npl[c] = (uint8_t)cnt;
 }
 
 // inverse distance weights of the point-cells (eq. 2.7)
@@ -1227,6 +1238,67 @@ __global__ __launch_bounds__(1024) void k_stats(DMesh m, DState s, double *out) 
   }
 }
 
+// Geometric mapping after a mesh change (Section 3, Algorithm 2): alpha of
+// each cell c of the new mesh d from the reconstruction of the old mesh o.
+// One old cell containing c: for an interface cell, the fill level of c under
+// the old cell's plane, summed over the fan tetrahedra (c's centroid, face
+// centre, consecutive face points) with the closed-form kept fraction; for
+// any other class the old alpha.  Several old cells: c is their union, and
+// gets the sum of alpha V over them.  A map entry out of range, or a cell
+// with no entry or offsets outside [0, off[nc]], raises kFlagBadMap and
+// writes NaN.
+__global__ __launch_bounds__(kBlock) void k_map_alpha(DMesh d, double *alpha, const int32_t *off,
+                                                      const int32_t *cells, DMesh o, DState os,
+                                                      uint32_t *flags) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= d.nc) return;
+  const int k0 = off[c], k1 = off[c + 1];
+  bool bad = k0 < 0 || k1 <= k0 || k1 > off[d.nc];
+  double a = NAN;
+  if (!bad && k1 - k0 == 1) {
+    const int oc = cells[k0];
+    bad = oc < 0 || oc >= o.nc;
+    if (!bad && os.cls[oc] != 1) {
+      a = os.alpha[oc];
+    } else if (!bad) {
+      const double4 pl = os.plane[oc];
+      const v3 n = xyz(pl), org = xyz(d.XC[c]);
+      const double sn = pl.w - dot(n, org);
+      double acc = 0.0, tot = 0.0;
+      for (int k = d.cf_off[c]; k < d.cf_off[c + 1]; ++k) {
+        const int sf = d.cf[k];
+        const int f = sf >= 0 ? sf : ~sf;
+        const double sg = sf >= 0 ? 1.0 : -1.0;
+        const int b = d.foff[f], nn = d.foff[f + 1] - b;
+        const v3 cf = xyz(d.C[f]) - org;
+        const double hc = dot(n, cf);
+        v3 pa = xyz(d.X[d.fpts[b + nn - 1]]) - org;
+        for (int i = 0; i < nn; ++i) {
+          const v3 pb = xyz(d.X[d.fpts[b + i]]) - org;
+          const double v6 = sg * det3(cf, pa, pb);
+          acc += v6 * tet_kept_fraction(D4{sn, sn - hc, sn - dot(n, pa), sn - dot(n, pb)});
+          tot += v6;
+          pa = pb;
+        }
+      }
+      a = acc / tot;
+    }
+  } else if (!bad) {
+    double v = 0.0;
+    for (int k = k0; k < k1 && !bad; ++k) {
+      const int oc = cells[k];
+      bad = oc < 0 || oc >= o.nc;
+      if (!bad) v += os.alpha[oc] * o.V[oc];
+    }
+    a = bad ? NAN : v / d.V[c];
+  }
+  if (bad) {
+    a = NAN;
+    flag(flags, kFlagBadMap);
+  }
+  alpha[c] = a;
+}
+
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
 }  // namespace
@@ -1235,13 +1307,14 @@ inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 
 // launchers
 // ---------------------------------------------------------------------------
 void launch_mesh_geometry(const DMesh &m0, double4 *X, const double *pts, double4 *S, double4 *C,
-                          double *V, double4 *XC, double *wpc, double4 *cpl, double4 *bblo,
+                          double *V, double4 *XC, double *wpc, double4 *cpl, uint8_t *npl,
+                          double4 *bblo,
                           double4 *bbhi, uint32_t *flags, hipStream_t st) {
   DMesh m = m0;
   k_points<<<grid_for(m.np, kBlock), kBlock, 0, st>>>(m.np, pts, X);
   k_face_geom<<<grid_for(m.nf, kBlock), kBlock, 0, st>>>(m, S, C);
   k_cell_geom<<<grid_for(m.nc, kBlock), kBlock, 0, st>>>(m, V, XC, bblo, bbhi);
-  k_cell_planes<<<grid_for(m.nc, kBlock), kBlock, 0, st>>>(m, cpl);
+  k_cell_planes<<<grid_for(m.nc, kBlock), kBlock, 0, st>>>(m, cpl, npl);
   k_idw<<<grid_for(m.np, kBlock), kBlock, 0, st>>>(m, wpc);
   if (m.ni > 0) k_check_orientation<<<grid_for(m.ni, kBlock), kBlock, 0, st>>>(m, flags);
 }
@@ -1312,6 +1385,12 @@ void launch_step(const DMesh &m, const DState &s, const DParams &p, hipStream_t 
                           k_wisp_moves<<<kWispGrid, kBlock, 0, st>>>(m, s, p)));
   TIMED(prof, kKLedger, (k_ledger_part<<<kLedgerParts, kBlock, 0, st>>>(m, s),
                          k_ledger<<<1, kBlock, 0, st>>>(m, s, p, kLedgerParts)));
+}
+
+void launch_map_alpha(const DMesh &d, double *alpha, const int32_t *off, const int32_t *cells,
+                      const DMesh &o, const DState &os, uint32_t *flags, hipStream_t st) {
+  if (d.nc > 0)
+    k_map_alpha<<<grid_for(d.nc, kBlock), kBlock, 0, st>>>(d, alpha, off, cells, o, os, flags);
 }
 
 void launch_stats(const DMesh &m, const DState &s, double *out4, hipStream_t st) {

@@ -491,6 +491,8 @@ vof_status vof_mesh_upload(vof_context *ctx, const vof_mesh_desc *d, vof_mesh **
   ALLOC(d_pc_off, np + 1); ALLOC(d_pc, (int64_t)pc.size()); ALLOC(wpc, (int64_t)pc.size());
   ALLOC(d_st_off, nf + 1); ALLOC(d_st, (int64_t)st.size());
   ALLOC(S, nf); ALLOC(C, nf); ALLOC(V, nc); ALLOC(XC, nc); ALLOC(cpl, (int64_t)cf.size());
+  uint8_t *npl;
+  ALLOC(npl, nc);
   ALLOC(bblo, nc); ALLOC(bbhi, nc);
   ALLOC(ds.alpha, nc); ALLOC(ds.cls, nc); ALLOC(ds.plane, nc); ALLOC(ds.pmask, np);
   ALLOC(ds.alpha_p, np); ALLOC(ds.U, np); ALLOC(ds.F0, nf); ALLOC(ds.lam, nf);
@@ -528,9 +530,9 @@ vof_status vof_mesh_upload(vof_context *ctx, const vof_mesh_desc *d, vof_mesh **
   dm.X = X; dm.foff = d_foff; dm.fpts = d_fpts; dm.own = d_own; dm.nei = d_nei;
   dm.fpad = d_fpad; dm.padw = padw;
   dm.cf_off = d_cf_off; dm.cf = d_cf; dm.pc_off = d_pc_off; dm.pc = d_pc; dm.wpc = wpc;
-  dm.st_off = d_st_off; dm.st = d_st; dm.S = S; dm.C = C; dm.V = V; dm.XC = XC; dm.cpl = cpl;
+  dm.st_off = d_st_off; dm.st = d_st; dm.S = S; dm.C = C; dm.V = V; dm.XC = XC; dm.cpl = cpl; dm.npl = npl;
   dm.bblo = bblo; dm.bbhi = bbhi;
-  launch_mesh_geometry(dm, X, d_pts, S, C, V, XC, wpc, cpl, bblo, bbhi, ds.flags, s);
+  launch_mesh_geometry(dm, X, d_pts, S, C, V, XC, wpc, cpl, npl, bblo, bbhi, ds.flags, s);
   e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) { delete m; return fail(VOF_EDEVICE, "mesh geometry: %s", hipGetErrorString(e)); }
@@ -634,6 +636,71 @@ vof_status vof_set_alpha(vof_mesh *m, const double *alpha, int32_t memory) {
   if ((rc = to_device(m->ds.alpha, alpha, m->dm.nc, memory, m->ctx->stream))) return rc;
   m->have_alpha = true;
   return vof_reset_stats(m);
+}
+
+vof_status vof_map_alpha(vof_mesh *dst, vof_mesh *src, const int32_t *map_offsets,
+                         const int32_t *map_cells, int32_t memory) {
+  if (!dst || !src || !map_offsets || !map_cells) return fail(VOF_EINVAL, "null argument");
+  if (dst == src) return fail(VOF_EINVAL, "source and destination meshes must differ");
+  vof_status rc = check_memory(memory);
+  if (rc) return rc;
+  if (dst->ctx->device != src->ctx->device)
+    return fail(VOF_EINVAL, "source and destination meshes are on different devices");
+  if (!src->have_alpha) return fail(VOF_EINVAL, "source alpha not set");
+  if ((rc = set_device(dst->ctx))) return rc;
+  const int64_t nc = dst->dm.nc, onc = src->dm.nc;
+  // temporary device buffers: the map (for host arrays) and a flag word
+  struct Tmp {
+    std::vector<void *> p;
+    ~Tmp() { for (void *q : p) (void)hipFree(q); }
+  } tmp;
+  auto tmp_alloc = [&](size_t bytes, void **q) -> vof_status {
+    hipError_t e = hipMalloc(q, bytes > 0 ? bytes : 1);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(VOF_ENOMEM, "hipMalloc of %zu bytes failed", bytes);
+    }
+    tmp.p.push_back(*q);
+    return VOF_OK;
+  };
+  const int32_t *off = map_offsets, *cells = map_cells;
+  if (memory == VOF_HOST) {
+    if (map_offsets[0] != 0) return fail(VOF_EINVAL, "map_offsets[0] must be 0");
+    for (int64_t c = 0; c < nc; ++c)
+      if (map_offsets[c + 1] <= map_offsets[c])
+        return fail(VOF_EINVAL, "destination cell %lld has no source cell", (long long)c);
+    const int64_t ne = map_offsets[nc];
+    for (int64_t k = 0; k < ne; ++k)
+      if (map_cells[k] < 0 || map_cells[k] >= onc)
+        return fail(VOF_EINVAL, "map_cells[%lld] = %d out of range", (long long)k, map_cells[k]);
+    void *a = nullptr, *b = nullptr;
+    if ((rc = tmp_alloc(sizeof(int32_t) * (nc + 1), &a)) ||
+        (rc = tmp_alloc(sizeof(int32_t) * ne, &b)))
+      return rc;
+    HIP_OR_FAIL(hipMemcpy(a, map_offsets, sizeof(int32_t) * (nc + 1), hipMemcpyHostToDevice));
+    if (ne > 0) HIP_OR_FAIL(hipMemcpy(b, map_cells, sizeof(int32_t) * ne, hipMemcpyHostToDevice));
+    off = (const int32_t *)a;
+    cells = (const int32_t *)b;
+  }
+  void *fl = nullptr;
+  if ((rc = tmp_alloc(sizeof(uint32_t), &fl))) return rc;
+  HIP_OR_FAIL(hipMemset(fl, 0, sizeof(uint32_t)));
+  // the old mesh's reconstruction of its current alpha, then the new alpha
+  launch_reconstruct(src->dm, src->ds, src->dp, src->ctx->stream);
+  HIP_OR_FAIL(hipGetLastError());
+  HIP_OR_FAIL(hipStreamSynchronize(src->ctx->stream));
+  hipStream_t st = dst->ctx->stream;
+  launch_map_alpha(dst->dm, dst->ds.alpha, off, cells, src->dm, src->ds, (uint32_t *)fl, st);
+  HIP_OR_FAIL(hipGetLastError());
+  HIP_OR_FAIL(hipStreamSynchronize(st));
+  uint32_t bad = 0;
+  HIP_OR_FAIL(hipMemcpy(&bad, fl, sizeof bad, hipMemcpyDeviceToHost));
+  if (bad) {
+    dst->have_alpha = false;
+    return fail(VOF_EINVAL, "a map entry is out of range or a destination cell has no entry");
+  }
+  dst->have_alpha = true;
+  return vof_reset_stats(dst);
 }
 
 vof_status vof_read_alpha(vof_mesh *m, double *out, int32_t memory) {

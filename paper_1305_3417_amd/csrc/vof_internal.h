@@ -24,6 +24,7 @@ constexpr uint32_t kFlagUnreached = 2u;
 constexpr uint32_t kFlagNonFinite = 4u;
 constexpr uint32_t kFlagLeak = 8u;
 constexpr uint32_t kFlagBadOrientation = 16u;
+constexpr uint32_t kFlagBadMap = 32u;
 
 // 64-bit counters accumulated across steps
 enum Counter : int {
@@ -80,7 +81,9 @@ struct DMesh {
   const double4 *C;        // face centre (mean of points)
   const double *V;         // cell volume
   const double4 *XC;       // cell centroid
-  const double4 *cpl;      // per cell -> face entry: outward unit normal, offset
+  const double4 *cpl;      // per cell, from cf_off[c]: its distinct face planes
+                           // (outward unit normal, offset), npl[c] of them
+  const uint8_t *npl;
   const double4 *bblo;     // cell bounding box
   const double4 *bbhi;
 };
@@ -158,13 +161,16 @@ struct Prof {
 
 // launchers (vof_device.hip)
 void launch_mesh_geometry(const DMesh &m, double4 *X, const double *pts, double4 *S, double4 *C,
-                          double *V, double4 *XC, double *wpc, double4 *cpl, double4 *bblo,
+                          double *V, double4 *XC, double *wpc, double4 *cpl, uint8_t *npl,
+                          double4 *bblo,
                           double4 *bbhi, uint32_t *flags, hipStream_t st);
 void launch_point_velocity(const DMesh &m, const double *U0c, double4 *U, double4 *XU,
                            hipStream_t st);
 void launch_step(const DMesh &m, const DState &s, const DParams &p, hipStream_t st, Prof *prof);
 void launch_reconstruct(const DMesh &m, const DState &s, const DParams &p, hipStream_t st);
 void launch_stats(const DMesh &m, const DState &s, double *out4, hipStream_t st);
+void launch_map_alpha(const DMesh &d, double *alpha, const int32_t *off, const int32_t *cells,
+                      const DMesh &o, const DState &os, uint32_t *flags, hipStream_t st);
 double host_tet_clip(const double *tet, int n_planes, const double *planes);
 double host_tet_clip_closed(const double *tet, int n_planes, const double *planes);
 

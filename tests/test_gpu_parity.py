@@ -304,6 +304,64 @@ def test_narrow_band_and_wisps(vof, ctx, oracle_mod, case):
     g2["mesh"].close()
 
 
+def test_refined_mesh_advection(vof, ctx, oracle_mod):
+    """A hex mesh refined once around the sphere (2:1, faces of 4-6 points,
+    cells of up to 15 faces, coplanar faces of a coarse cell one clipping
+    plane): one step compared quantity by quantity, then alpha after 8 steps
+    with every flux polyhedron checked to stay inside its stencil."""
+    w = W.deform3d_refined(12, steps=8)
+    _compare_step(vof, ctx, oracle_mod, w, label="refined-12")
+    g = gpu_run(vof, ctx, w, params={"check_stencil": 1})
+    o, a, st, lam, vp = oracle_run(oracle_mod, w, check_leak=True)
+    assert st["max_leak"] < 1e-12 and g["stats"]["stencil_leaks"] == 0
+    assert np.abs(g["alpha"] - a).max() < 1e-10
+    V = o.geometry()[0]
+    m0 = (w.alpha0 * V).sum()
+    assert abs(g["stats"]["mass"] + g["stats"]["ledger"] - m0) <= 1e-12 * m0
+    g["mesh"].close()
+
+
+def test_geometric_mapping(vof, ctx, oracle_mod):
+    """Algorithm 2 (Section 3): the oracle's alpha after six deformation steps
+    on 16^3 is mapped onto the mesh refined in its interface cells, on the GPU
+    and by the oracle (each reconstructing the same alpha), then mapped back
+    by union; host and device map arrays; a bad map is refused."""
+    import torch
+    from workloads.refine import refine_hex
+    n = 16
+    w0 = W.deform3d(n, steps=6)
+    _, a_old, _, _, _ = oracle_run(oracle_mod, w0)
+    m1, parent, (coff, cells) = refine_hex(n, (a_old > 1e-12) & (a_old < 1 - 1e-12))
+    print(f"[mapping] {w0.mesh.n_cells} -> {m1.n_cells} cells", flush=True)
+    o0, o1 = oracle_mod.Oracle(w0.mesh), oracle_mod.Oracle(m1)
+    ident = np.arange(m1.n_cells + 1, dtype=np.int32)
+    e1 = o1.map_alpha(o0, a_old, ident, parent)
+    e0 = o0.map_alpha(o1, e1, coff, cells)
+    src = vof.upload_mesh(ctx, w0.mesh)
+    dst = vof.upload_mesh(ctx, m1)
+    vof.vof_set_alpha(src, a_old)
+    vof.vof_map_alpha(dst, src, ident, parent)
+    g1 = vof.vof_read_alpha(dst)
+    assert np.abs(g1 - e1).max() < 1e-11
+    V0, V1 = o0.geometry()[0], o1.geometry()[0]
+    assert abs((g1 * V1).sum() - (a_old * V0).sum()) <= 1e-13 * (a_old * V0).sum()
+    # back to the uniform mesh, map arrays on the device
+    back = vof.upload_mesh(ctx, w0.mesh)
+    vof.vof_map_alpha(back, dst, torch.as_tensor(coff.astype(np.int32), device="cuda"),
+                      torch.as_tensor(cells.astype(np.int32), device="cuda"))
+    g0 = vof.vof_read_alpha(back)
+    assert np.abs(g0 - e0).max() < 1e-11 and np.abs(g0 - a_old).max() < 1e-11
+    bad = parent.copy()
+    bad[3] = w0.mesh.n_cells
+    with pytest.raises(vof.VofError):
+        vof.vof_map_alpha(dst, src, ident, bad)
+    with pytest.raises(vof.VofError):
+        vof.vof_map_alpha(back, dst, torch.as_tensor(coff.astype(np.int32), device="cuda"),
+                          torch.as_tensor(np.full(cells.size, -1, np.int32), device="cuda"))
+    for h in (src, dst, back):
+        h.close()
+
+
 @pytest.mark.parametrize("gradient", ["nag", "lsq"])
 def test_sphere_reconstruction_error(vof, ctx, oracle_mod, gradient):
     """Reconstruction alone (vof_reconstruct) of an exact sphere on 32^3

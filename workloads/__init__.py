@@ -177,5 +177,26 @@ def shear3d(n: int = 64, steps: int | None = None, T: float = 3.0, co: float = 0
                           "Umax": Umax, "growth": growth})
 
 
+def deform3d_refined(n: int = 32, steps: int | None = None, T: float = 3.0,
+                     centre=(0.35, 0.35, 0.35), radius: float = 0.15) -> Workload:
+    """The deformation case on an n^3 hex mesh refined once (2:1, hanging
+    points) in the cells the sphere's surface cuts; alpha^0 the exact sphere
+    fractions of the refined cells, dt = 1/(8n) (Co 0.5 on the fine cells).
+    meta["parent"] maps each cell to its cell of the uniform mesh."""
+    from .refine import refine_hex
+    m0 = hex_mesh(n, n, n)
+    f0 = fields.ball_box_fraction(centre, radius, m0.cell_lo, m0.cell_hi)
+    m, parent, children = refine_hex(n, (f0 > 0) & (f0 < 1))
+    a0 = fields.ball_box_fraction(centre, radius, m.cell_lo, m.cell_hi)
+    Uc = fields.deformation_velocity(m.cell_centroids())
+    F0 = fields.flux_deformation(m)
+    dt = 1.0 / (8 * n)
+    N = int(round(T / dt)) if steps is None else steps
+    t = (np.arange(N) + 0.5) * dt
+    return Workload("deform3d_refined", m, a0, Uc, F0, np.full(N, dt), np.cos(np.pi * t / T),
+                    meta={"n": n, "T": T, "co": 0.5, "centre": list(centre), "radius": radius,
+                          "parent": parent, "children": children})
+
+
 WORKLOADS = {"disc2d": disc2d, "deform3d": deform3d, "rotate_tets": rotate_tets,
-             "shear3d": shear3d}
+             "shear3d": shear3d, "deform3d_refined": deform3d_refined}
