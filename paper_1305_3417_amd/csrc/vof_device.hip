@@ -555,8 +555,12 @@ __device__ __forceinline__ void block_count3(unsigned long long *d0, unsigned lo
   }
 }
 
+// Faces of up to four points run at four waves per SIMD (at most 128 VGPRs:
+// the loads of a face are a chain of two dependent gathers, hidden by the
+// other waves); faces of up to eight points need more registers.
 template <int NMAX>
-__global__ __launch_bounds__(kBlock) void k_flux(DMesh m, DState s, DParams p) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NMAX <= 4 ? 4 : 1)))
+void k_flux(DMesh m, DState s, DParams p) {
   const int step = *s.stepno;
   const double dt = s.dt[step], sc = s.sc[step];
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -578,7 +582,7 @@ __global__ __launch_bounds__(kBlock) void k_flux(DMesh m, DState s, DParams p) {
 #pragma unroll
         for (int i = 0; i < NMAX; ++i) n += q[i] >= 0;
         v3 r[NMAX], d[NMAX];
-        v3 c = mk3(0, 0, 0);
+        v3 c = mk3(0, 0, 0), db = mk3(0, 0, 0);
         const double sweep = -sc * dt;
 #pragma unroll
         for (int i = 0; i < NMAX; ++i) {
@@ -588,39 +592,39 @@ __global__ __launch_bounds__(kBlock) void k_flux(DMesh m, DState s, DParams p) {
             d[i] = sweep * xyz(xu[1]);
             mask |= s.pmask[q[i]];
             c = c + r[i];
+            db = db + d[i];
           } else {
             r[i] = mk3(0, 0, 0);
             d[i] = mk3(0, 0, 0);
           }
         }
         c = (1.0 / n) * c;
+        db = (1.0 / n) * db;
 #pragma unroll
         for (int i = 0; i < NMAX; ++i) r[i] = r[i] - c;
         // h_i.((d_i + d_i+1) x e_i) = -(d_i + d_i+1).(r_i x r_i+1) (triple product
         // with e_i = r_i+1 - r_i, h_i = (r_i + r_i+1) / 2), so every edge needs the
-        // three products r_i x r_i+1, d_i x d_i+1 and r_i x d_i+1 + d_i x r_i+1.
-        double t1 = 0.0, t2 = 0.0;
-        v3 A2 = mk3(0, 0, 0), B = mk3(0, 0, 0), Cc = mk3(0, 0, 0), db = mk3(0, 0, 0);
+        // three products r_i x r_i+1, d_i x d_i+1 and r_i x d_i+1 + d_i x r_i+1,
+        // taken against the mean sweep d-bar edge by edge:
+        //   6 c1 = -sum (d_i + d_i+1 + d-bar).(r_i x r_i+1)
+        //   6 c2 = sum [(r_i + r_i+1)/2 . (d_i x d_i+1) - d-bar.(r_i x d_i+1 + d_i x r_i+1)]
+        //   6 c3 = -sum d-bar.(d_i x d_i+1)
+        double t1 = 0.0, t2 = 0.0, t3 = 0.0;
 #pragma unroll
         for (int i = 0; i < NMAX; ++i) {
           if (i < n) {
             v3 rn = (i + 1 < n) ? r[(i + 1) % NMAX] : r[0];
             v3 dn = (i + 1 < n) ? d[(i + 1) % NMAX] : d[0];
-            v3 a = cross(r[i], rn);
             v3 dd = cross(d[i], dn);
-            t1 -= dot(d[i] + dn, a);
-            t2 += 0.5 * dot(r[i] + rn, dd);
-            A2 = A2 + a;
-            B = B + cross(r[i], dn) + cross(d[i], rn);
-            Cc = Cc + dd;
-            db = db + d[i];
+            t1 -= dot(d[i] + dn + db, cross(r[i], rn));
+            t2 += 0.5 * dot(r[i] + rn, dd) - dot(db, cross(r[i], dn) + cross(d[i], rn));
+            t3 -= dot(db, dd);
           }
         }
-        db = (1.0 / n) * db;
         const double sixth = 1.0 / 6.0;
-        double c1 = (t1 - dot(db, A2)) * sixth;
-        double c2 = (t2 - dot(db, B)) * sixth;
-        double c3 = -dot(db, Cc) * sixth;
+        double c1 = t1 * sixth;
+        double c2 = t2 * sixth;
+        double c3 = t3 * sixth;
         correct(c1, c2, c3, T, p.corr_rtol, p.corr_max_iter, lam, it, stat);
         // A target beyond the extremum of V on the branch: the phase volume of
         // the polyhedron at the clamped lam is rescaled to F dt (scalar correction).
