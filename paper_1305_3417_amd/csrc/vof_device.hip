@@ -679,6 +679,32 @@ void k_flux(DMesh m, DState s, DParams p) {
 // |T ∩ C_c ∩ H_c| (H = the PLIC half-space in interface cells, all space in
 // full cells, alpha-weighted in vanishing-gradient cells) is stored per item.
 
+// Tetrahedron k of a face staged in LDS (P[j]: point j minus the face centre,
+// then its sweep at the corrected lam; cq: the mean sweep; n points), built
+// exactly as flux_tet builds it from global memory.
+__device__ __forceinline__ bool staged_tet(const double (*P)[6], int n, const double *cq, int k,
+                                           v3 &t1, v3 &t2, v3 &t3, double &det, double &sgn) {
+  if (k >= 5 * n) return false;
+  const int i = k / 5, type = k - 5 * i;
+  const int i1 = (i + 1 == n) ? 0 : i + 1;
+  const v3 pi = mk3(P[i][0], P[i][1], P[i][2]), pj = mk3(P[i1][0], P[i1][1], P[i1][2]);
+  const v3 qi = pi + mk3(P[i][3], P[i][4], P[i][5]);
+  const v3 qj = pj + mk3(P[i1][3], P[i1][4], P[i1][5]);
+  if (type == 0) { t1 = mk3(cq[0], cq[1], cq[2]); t2 = qj; t3 = qi; }
+  else {
+    t1 = 0.25 * (pi + pj + qi + qj);
+    if (type == 1) { t2 = pj; t3 = pi; }
+    else if (type == 2) { t2 = pi; t3 = qi; }
+    else if (type == 3) { t2 = qi; t3 = qj; }
+    else { t2 = qj; t3 = pj; }
+  }
+  det = det3(t1, t2, t3);
+  if (det == 0.0) return false;
+  sgn = det > 0.0 ? 1.0 : -1.0;
+  if (det < 0.0) { v3 tmp = t2; t2 = t3; t3 = tmp; det = -det; }
+  return true;
+}
+
 // Step 5 on the register path.  A wavefront takes a group of whole geometric
 // faces (64 / tets-per-face of them; groups claimed from a counter), one flux
 // tet per lane.  First the faces' candidate cells: each face's stencil is
@@ -694,8 +720,14 @@ void k_flux(DMesh m, DState s, DParams p) {
 // adds each tet's queued results in stencil order.
 __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_clip_fast(DMesh m, DState s, DParams p) {
   const int step = *s.stepno;
+  // the group's faces: points minus the face centre and their sweeps at the
+  // corrected lam, the mean sweep, the point count and the face centre (the
+  // apex of the face's tets); every tet is built from these
+  __shared__ double fpt[kGroupFaces][kMaxFacePoints][6];
+  __shared__ double fcq[kGroupFaces][3];
+  __shared__ int fn[kGroupFaces];
+  __shared__ double fc[kGroupFaces][3];
   __shared__ double tv[10][kFastBlock];
-  __shared__ double fc[kGroupFaces][3];  // face centre (the apex of the face's tets)
   __shared__ int32_t icell[kFastBlock * kFastSlots];
   __shared__ uint16_t imask[kFastBlock * kFastSlots];
   __shared__ double res[kFastBlock * kFastSlots];
@@ -735,9 +767,10 @@ __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3)))
     }
     if (lane < kFastPlanes - 1) nbin[lane] = 0;
     // flux polyhedron boxes, one lane per face (points and their swept
-    // images).  Unpadded: a cell that only touches the box meets the
-    // polyhedron in a sliver of zero width (or of the width of the rounding
-    // of the tets' vertices), whose volume is below the rounding of the sum.
+    // images), and the face staged in LDS.  Unpadded: a cell that only
+    // touches the box meets the polyhedron in a sliver of zero width (or of
+    // the width of the rounding of the tets' vertices), whose volume is below
+    // the rounding of the sum.
     __syncthreads();
     const int g = group;
     if (g >= ngroups) break;
@@ -747,59 +780,92 @@ __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3)))
         const int f = s.gfaces[slot];
         const double sw = sweep * s.lam[f];
         const int32_t *fp = m.fpad + (int64_t)f * m.padw;
+        const int4 r0 = *reinterpret_cast<const int4 *>(fp);
+        const int4 r1 = m.padw > 4 ? *reinterpret_cast<const int4 *>(fp + 4)
+                                   : make_int4(-1, -1, -1, -1);
+        int n = 0;
+        v3 c = mk3(0, 0, 0), cs = mk3(0, 0, 0);
         v3 lo = mk3(1e300, 1e300, 1e300), hi = mk3(-1e300, -1e300, -1e300);
-        for (int j = 0; j < m.padw; ++j) {
-          if (fp[j] < 0) break;
-          const double4 *xu = s.XU + 2 * (int64_t)fp[j];
-          const v3 x = xyz(xu[0]);
-          const v3 y = x + sw * xyz(xu[1]);
-          lo = mk3(dmin(lo.x, dmin(x.x, y.x)), dmin(lo.y, dmin(x.y, y.y)),
-                   dmin(lo.z, dmin(x.z, y.z)));
-          hi = mk3(dmax(hi.x, dmax(x.x, y.x)), dmax(hi.y, dmax(x.y, y.y)),
-                   dmax(hi.z, dmax(x.z, y.z)));
+        const int q[kMaxFacePoints] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+#pragma unroll
+        for (int j = 0; j < kMaxFacePoints; ++j) {
+          if (q[j] >= 0) {
+            const double4 *xu = s.XU + 2 * (int64_t)q[j];
+            const v3 x = xyz(xu[0]);
+            const v3 u = sw * xyz(xu[1]);
+            const v3 y = x + u;
+            fpt[lane][j][0] = x.x; fpt[lane][j][1] = x.y; fpt[lane][j][2] = x.z;
+            fpt[lane][j][3] = u.x; fpt[lane][j][4] = u.y; fpt[lane][j][5] = u.z;
+            c = c + x;
+            cs = cs + u;
+            ++n;
+            lo = mk3(dmin(lo.x, dmin(x.x, y.x)), dmin(lo.y, dmin(x.y, y.y)),
+                     dmin(lo.z, dmin(x.z, y.z)));
+            hi = mk3(dmax(hi.x, dmax(x.x, y.x)), dmax(hi.y, dmax(x.y, y.y)),
+                     dmax(hi.z, dmax(x.z, y.z)));
+          }
         }
+        c = (1.0 / n) * c;
+        cs = (1.0 / n) * cs;  // mean sweep
+        for (int j = 0; j < n; ++j) {
+          fpt[lane][j][0] -= c.x; fpt[lane][j][1] -= c.y; fpt[lane][j][2] -= c.z;
+        }
+        fn[lane] = n;
+        fc[lane][0] = c.x; fc[lane][1] = c.y; fc[lane][2] = c.z;
+        fcq[lane][0] = cs.x; fcq[lane][1] = cs.y; fcq[lane][2] = cs.z;
         fbox[lane][0] = lo.x; fbox[lane][1] = lo.y; fbox[lane][2] = lo.z;
         fbox[lane][3] = hi.x; fbox[lane][4] = hi.y; fbox[lane][5] = hi.z;
       }
     }
     __syncthreads();
-    // candidate cells of each face of the group
-    for (int fi = 0; fi < F; ++fi) {
-      const int slot = g * F + fi;
-      if (slot >= count) break;
-      const int f = s.gfaces[slot];
-      const int w = m.st_off[f], nst = m.st_off[f + 1] - w;
+    // candidate cells of the group's faces, kFastBlock / F lanes per face, in
+    // stencil order
+    {
+      const int L = kFastBlock / F;
+      const int cf = lane / L, e_in = lane - cf * L;
+      const int slot = g * F + cf;
+      const bool mine = cf < F && slot < count;
+      int w = 0, nst = 0;
+      if (mine) {
+        const int f = s.gfaces[slot];
+        w = m.st_off[f];
+        nst = m.st_off[f + 1] - w;
+      }
+      int most = nst;  // the largest stencil of the group sets the trip count
+      for (int o = 32; o > 0; o >>= 1) most = max(most, __shfl_xor(most, o));
+      const unsigned long long seg =
+          !mine ? 0ull : (L == kFastBlock ? ~0ull : (((1ull << L) - 1ull) << (cf * L)));
       int cnt = 0;
-      for (int e0 = 0; e0 < nst; e0 += kFastBlock) {
-        const int e = e0 + lane;
+      for (int e0 = 0; e0 < most; e0 += L) {
+        const int e = e0 + e_in;
         bool keep = false;
         int cell = 0, cl = 0;
         double4 blo = make_double4(0, 0, 0, 0), bhi = blo;
-        if (e < nst) {
+        if (mine && e < nst) {
           cell = m.st[w + e];
           cl = s.cls[cell];
           if (cl != 0) {
             blo = m.bblo[cell];
             bhi = m.bbhi[cell];
-            keep = !(fbox[fi][3] <= blo.x || fbox[fi][0] >= bhi.x || fbox[fi][4] <= blo.y ||
-                     fbox[fi][1] >= bhi.y || fbox[fi][5] <= blo.z || fbox[fi][2] >= bhi.z);
+            keep = !(fbox[cf][3] <= blo.x || fbox[cf][0] >= bhi.x || fbox[cf][4] <= blo.y ||
+                     fbox[cf][1] >= bhi.y || fbox[cf][5] <= blo.z || fbox[cf][2] >= bhi.z);
           }
         }
-        const unsigned long long bal = __ballot(keep);
+        const unsigned long long bal = __ballot(keep) & seg;
         const int pos = cnt + (int)__popcll(bal & ((1ull << lane) - 1ull));
         if (keep && pos < kCand) {
-          ccell[fi][pos] = cell;
-          ccls[fi][pos] = (int8_t)cl;
-          cbox[fi][pos][0] = __double2float_rd(blo.x);
-          cbox[fi][pos][1] = __double2float_rd(blo.y);
-          cbox[fi][pos][2] = __double2float_rd(blo.z);
-          cbox[fi][pos][3] = __double2float_ru(bhi.x);
-          cbox[fi][pos][4] = __double2float_ru(bhi.y);
-          cbox[fi][pos][5] = __double2float_ru(bhi.z);
+          ccell[cf][pos] = cell;
+          ccls[cf][pos] = (int8_t)cl;
+          cbox[cf][pos][0] = __double2float_rd(blo.x);
+          cbox[cf][pos][1] = __double2float_rd(blo.y);
+          cbox[cf][pos][2] = __double2float_rd(blo.z);
+          cbox[cf][pos][3] = __double2float_ru(bhi.x);
+          cbox[cf][pos][4] = __double2float_ru(bhi.y);
+          cbox[cf][pos][5] = __double2float_ru(bhi.z);
         }
         cnt += (int)__popcll(bal);
       }
-      if (lane == 0) cnum[fi] = cnt;
+      if (mine && e_in == 0) cnum[cf] = cnt;
     }
     __syncthreads();
     // phase A
@@ -812,13 +878,12 @@ __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3)))
     int nq = 0;
     unsigned long long np = 0;
     if (active) {
-      const int f = s.gfaces[slot];
-      v3 c, t1, t2, t3;
+      const v3 c = mk3(fc[fi][0], fc[fi][1], fc[fi][2]);
+      v3 t1, t2, t3;
       double det;
-      live = !p.check_stencil && flux_tet(m, s, dt, sc, f, k, c, t1, t2, t3, det, sgn);
+      live = !p.check_stencil && staged_tet(fpt[fi], fn[fi], fcq[fi], k, t1, t2, t3, det, sgn);
       defer = p.check_stencil || cnum[fi] > kCand;
       if (live && !defer) {
-        if (k == 0) { fc[fi][0] = c.x; fc[fi][1] = c.y; fc[fi][2] = c.z; }
         tv[0][lane] = t1.x; tv[1][lane] = t1.y; tv[2][lane] = t1.z;
         tv[3][lane] = t2.x; tv[4][lane] = t2.y; tv[5][lane] = t2.z;
         tv[6][lane] = t3.x; tv[7][lane] = t3.y; tv[8][lane] = t3.z;
