@@ -555,6 +555,60 @@ __device__ __forceinline__ void block_count3(unsigned long long *d0, unsigned lo
   }
 }
 
+// Coefficients of the volume cubic V(lam) = c1 lam + c2 lam^2 + c3 lam^3 of
+// the flux polyhedron of a face with points q[0..n-1] and sweep factor
+// `sweep` (-s dt), and the OR of its points' class masks.  N > 0 fixes n = N
+// at compile time; N = 0 takes n at run time (at most NMAX).
+template <int NMAX, int N>
+__device__ __forceinline__ void face_cubic(const DState &s, const int (&q)[NMAX], int n,
+                                           double sweep, uint8_t &mask, double &c1, double &c2,
+                                           double &c3) {
+  v3 r[NMAX], d[NMAX];
+  v3 c = mk3(0, 0, 0), db = mk3(0, 0, 0);
+#pragma unroll
+  for (int i = 0; i < NMAX; ++i) {
+    if (N > 0 || i < n) {
+      const double4 *xu = s.XU + 2 * (int64_t)q[i];
+      r[i] = xyz(xu[0]);
+      d[i] = sweep * xyz(xu[1]);
+      mask |= s.pmask[q[i]];
+      c = c + r[i];
+      db = db + d[i];
+    } else {
+      r[i] = mk3(0, 0, 0);
+      d[i] = mk3(0, 0, 0);
+    }
+  }
+  const double inv = N > 0 ? 1.0 / N : 1.0 / n;
+  c = inv * c;
+  db = inv * db;
+#pragma unroll
+  for (int i = 0; i < NMAX; ++i) r[i] = r[i] - c;
+  // h_i.((d_i + d_i+1) x e_i) = -(d_i + d_i+1).(r_i x r_i+1) (triple product
+  // with e_i = r_i+1 - r_i, h_i = (r_i + r_i+1) / 2), so every edge needs the
+  // three products r_i x r_i+1, d_i x d_i+1 and r_i x d_i+1 + d_i x r_i+1,
+  // taken against the mean sweep d-bar edge by edge:
+  //   6 c1 = -sum (d_i + d_i+1 + d-bar).(r_i x r_i+1)
+  //   6 c2 = sum [(r_i + r_i+1)/2 . (d_i x d_i+1) - d-bar.(r_i x d_i+1 + d_i x r_i+1)]
+  //   6 c3 = -sum d-bar.(d_i x d_i+1)
+  double t1 = 0.0, t2 = 0.0, t3 = 0.0;
+#pragma unroll
+  for (int i = 0; i < NMAX; ++i) {
+    if (N > 0 || i < n) {
+      const v3 rn = N > 0 ? r[(i + 1) % NMAX] : ((i + 1 < n) ? r[(i + 1) % NMAX] : r[0]);
+      const v3 dn = N > 0 ? d[(i + 1) % NMAX] : ((i + 1 < n) ? d[(i + 1) % NMAX] : d[0]);
+      const v3 dd = cross(d[i], dn);
+      t1 -= dot(d[i] + dn + db, cross(r[i], rn));
+      t2 += 0.5 * dot(r[i] + rn, dd) - dot(db, cross(r[i], dn) + cross(d[i], rn));
+      t3 -= dot(db, dd);
+    }
+  }
+  const double sixth = 1.0 / 6.0;
+  c1 = t1 * sixth;
+  c2 = t2 * sixth;
+  c3 = t3 * sixth;
+}
+
 // Faces of up to four points run at four waves per SIMD (at most 128 VGPRs:
 // the loads of a face are a chain of two dependent gathers, hidden by the
 // other waves); faces of up to eight points need more registers.
@@ -581,50 +635,12 @@ void k_flux(DMesh m, DState s, DParams p) {
         int n = 0;
 #pragma unroll
         for (int i = 0; i < NMAX; ++i) n += q[i] >= 0;
-        v3 r[NMAX], d[NMAX];
-        v3 c = mk3(0, 0, 0), db = mk3(0, 0, 0);
         const double sweep = -sc * dt;
-#pragma unroll
-        for (int i = 0; i < NMAX; ++i) {
-          if (i < n) {
-            const double4 *xu = s.XU + 2 * (int64_t)q[i];
-            r[i] = xyz(xu[0]);
-            d[i] = sweep * xyz(xu[1]);
-            mask |= s.pmask[q[i]];
-            c = c + r[i];
-            db = db + d[i];
-          } else {
-            r[i] = mk3(0, 0, 0);
-            d[i] = mk3(0, 0, 0);
-          }
-        }
-        c = (1.0 / n) * c;
-        db = (1.0 / n) * db;
-#pragma unroll
-        for (int i = 0; i < NMAX; ++i) r[i] = r[i] - c;
-        // h_i.((d_i + d_i+1) x e_i) = -(d_i + d_i+1).(r_i x r_i+1) (triple product
-        // with e_i = r_i+1 - r_i, h_i = (r_i + r_i+1) / 2), so every edge needs the
-        // three products r_i x r_i+1, d_i x d_i+1 and r_i x d_i+1 + d_i x r_i+1,
-        // taken against the mean sweep d-bar edge by edge:
-        //   6 c1 = -sum (d_i + d_i+1 + d-bar).(r_i x r_i+1)
-        //   6 c2 = sum [(r_i + r_i+1)/2 . (d_i x d_i+1) - d-bar.(r_i x d_i+1 + d_i x r_i+1)]
-        //   6 c3 = -sum d-bar.(d_i x d_i+1)
-        double t1 = 0.0, t2 = 0.0, t3 = 0.0;
-#pragma unroll
-        for (int i = 0; i < NMAX; ++i) {
-          if (i < n) {
-            v3 rn = (i + 1 < n) ? r[(i + 1) % NMAX] : r[0];
-            v3 dn = (i + 1 < n) ? d[(i + 1) % NMAX] : d[0];
-            v3 dd = cross(d[i], dn);
-            t1 -= dot(d[i] + dn + db, cross(r[i], rn));
-            t2 += 0.5 * dot(r[i] + rn, dd) - dot(db, cross(r[i], dn) + cross(d[i], rn));
-            t3 -= dot(db, dd);
-          }
-        }
-        const double sixth = 1.0 / 6.0;
-        double c1 = t1 * sixth;
-        double c2 = t2 * sixth;
-        double c3 = t3 * sixth;
+        double c1, c2, c3;
+        // a face with every slot used (all faces of a hex or tet mesh) takes
+        // the path with no per-point selects
+        if (n == NMAX) face_cubic<NMAX, NMAX>(s, q, n, sweep, mask, c1, c2, c3);
+        else face_cubic<NMAX, 0>(s, q, n, sweep, mask, c1, c2, c3);
         correct(c1, c2, c3, T, p.corr_rtol, p.corr_max_iter, lam, it, stat);
         // A target beyond the extremum of V on the branch: the phase volume of
         // the polyhedron at the clamped lam is rescaled to F dt (scalar correction).
