@@ -320,22 +320,25 @@ struct FanTet {
   double v6;
 };
 
-__device__ FanTet fan_tet(const DMesh &m, int64_t c, v3 o, int slot) {
+// The cell's faces are spread over the lanes (lane j < nfc holds face j: its
+// index f, sign, first point b and point count nn); the fan slots are numbered
+// face by face, so slot s belongs to the last face whose first slot (an
+// exclusive prefix sum of nn over the lanes) is at most s.
+__device__ FanTet fan_tet(const DMesh &m, v3 o, int slot, int nfc, int f, double sg, int b,
+                          int nn, int first, int total) {
+  int j = 0;
+  for (int q = 1; q < nfc; ++q)
+    if (__shfl(first, q) <= slot) j = q;
+  const int fj = __shfl(f, j), bj = __shfl(b, j), nj = __shfl(nn, j);
+  const double sj = __shfl(sg, j);
+  const int i = slot - __shfl(first, j);
   FanTet t{mk3(0, 0, 0), mk3(0, 0, 0), mk3(0, 0, 0), 0.0};
-  int acc = 0;
-  for (int k = m.cf_off[c]; k < m.cf_off[c + 1]; ++k) {
-    int sf = m.cf[k];
-    int f = sf >= 0 ? sf : ~sf;
-    int b = m.foff[f], nn = m.foff[f + 1] - b;
-    if (slot >= acc && slot < acc + nn) {
-      int i = slot - acc;
-      int i1 = (i + 1 == nn) ? 0 : i + 1;
-      t.cf = xyz(m.C[f]) - o;
-      t.pa = xyz(m.X[m.fpts[b + i]]) - o;
-      t.pb = xyz(m.X[m.fpts[b + i1]]) - o;
-      t.v6 = (sf >= 0 ? 1.0 : -1.0) * det3(t.cf, t.pa, t.pb);
-    }
-    acc += nn;
+  if (slot < total) {
+    const int i1 = (i + 1 == nj) ? 0 : i + 1;
+    t.cf = xyz(m.C[fj]) - o;
+    t.pa = xyz(m.X[m.fpts[bj + i]]) - o;
+    t.pb = xyz(m.X[m.fpts[bj + i1]]) - o;
+    t.v6 = sj * det3(t.cf, t.pa, t.pb);
   }
   return t;
 }
@@ -358,6 +361,16 @@ __global__ __launch_bounds__(kBlock) void k_plane(DMesh m, DState s, DParams p) 
     const double a = s.alpha[c];
     const int k0 = m.cf_off[c], nfc = m.cf_off[c + 1] - k0;
     const double Vc = m.V[c];
+    // face lane of the cell: lanes j < nfc hold face j
+    int lf = 0, lb = 0, lnn = 0;
+    double lsg = 0.0;
+    if (lane < nfc) {
+      const int sf = m.cf[k0 + lane];
+      lf = sf >= 0 ? sf : ~sf;
+      lsg = sf >= 0 ? 1.0 : -1.0;
+      lb = m.foff[lf];
+      lnn = m.foff[lf + 1] - lb;
+    }
     v3 g;
     if (p.gradient == 1) {
       // generalized least squares (Section 2.2.1): lanes over the cells that
@@ -386,10 +399,8 @@ __global__ __launch_bounds__(kBlock) void k_plane(DMesh m, DState s, DParams p) 
       // NAG: lanes over the faces of the cell
       v3 gl = mk3(0, 0, 0);
       if (lane < nfc) {
-        int sf = m.cf[k0 + lane];
-        int f = sf >= 0 ? sf : ~sf;
-        double sg = sf >= 0 ? 1.0 : -1.0;
-        int b = m.foff[f], nn = m.foff[f + 1] - b;
+        const int f = lf, b = lb, nn = lnn;
+        const double sg = lsg;
         double fp = 0.0;
         for (int j = 0; j < nn; ++j) fp += s.alpha_p[m.fpts[b + j]];
         fp /= nn;
@@ -420,7 +431,15 @@ __global__ __launch_bounds__(kBlock) void k_plane(DMesh m, DState s, DParams p) 
     const v3 n = (-1.0 / gn) * g;
     const v3 o = xyz(m.XC[c]);
     // fan tetrahedra as heights along n
-    FanTet t0 = fan_tet(m, c, o, lane), t1 = fan_tet(m, c, o, lane + 64);
+    int first = lnn;  // inclusive prefix sum of the point counts, then exclusive
+    for (int q = 1; q < 64; q <<= 1) {
+      const int t = __shfl_up(first, q);
+      if (lane >= q) first += t;
+    }
+    const int total = __shfl(first, 63);
+    first -= lnn;
+    FanTet t0 = fan_tet(m, o, lane, nfc, lf, lsg, lb, lnn, first, total);
+    FanTet t1 = fan_tet(m, o, lane + 64, nfc, lf, lsg, lb, lnn, first, total);
     const double hc0 = dot(n, t0.cf), ha0 = dot(n, t0.pa), hb0 = dot(n, t0.pb);
     const double hc1 = dot(n, t1.cf), ha1 = dot(n, t1.pa), hb1 = dot(n, t1.pb);
     // the points of the cell are the p_i of its fans
