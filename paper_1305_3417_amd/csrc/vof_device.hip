@@ -1462,12 +1462,23 @@ void Prof::end(int kid) {
 
 // One step of the path; the step index (for dt and scale) is read by the
 // kernels from s.stepno, which the last kernel advances, so the same launch
-// sequence serves every step (and is captured once as a graph).
-void launch_step(const DMesh &m, const DState &s, const DParams &p, hipStream_t st, Prof *prof) {
+// sequence serves every step (and is captured once as a graph).  The flux
+// kernel needs the point masks but not the planes, so with a Fork the plane
+// kernel runs beside it.
+void launch_step(const DMesh &m, const DState &s, const DParams &p, hipStream_t st, Prof *prof,
+                 const Fork *fork) {
+  const bool split = fork && !prof;
   TIMED(prof, kKReset, (k_reset<<<1, 64, 0, st>>>(s)));
   TIMED(prof, kKCellClass, (k_cell_class<<<grid_for(m.nc, kBlock), kBlock, 0, st>>>(m, s, p)));
   TIMED(prof, kKPointPrep, (k_point_prep<<<grid_for(m.np, kBlock), kBlock, 0, st>>>(m, s, p)));
-  TIMED(prof, kKPlane, (k_plane<<<kPlaneGrid, kBlock, 0, st>>>(m, s, p)));
+  if (split) {
+    (void)hipEventRecord(fork->fork, st);
+    (void)hipStreamWaitEvent(fork->side, fork->fork, 0);
+    k_plane<<<kPlaneGrid, kBlock, 0, fork->side>>>(m, s, p);
+    (void)hipEventRecord(fork->join, fork->side);
+  } else {
+    TIMED(prof, kKPlane, (k_plane<<<kPlaneGrid, kBlock, 0, st>>>(m, s, p)));
+  }
   // persistent-style grid: a few blocks per CU, grid-stride over the faces
   unsigned gf = grid_for(m.nf, kBlock);
   gf = gf < 8192 ? gf : 8192;
@@ -1478,6 +1489,7 @@ void launch_step(const DMesh &m, const DState &s, const DParams &p, hipStream_t 
     TIMED(prof, kKFlux, (k_flux<4><<<gf, kBlock, 0, st>>>(m, s, p)));
   else
     TIMED(prof, kKFlux, (k_flux<kMaxFacePoints><<<gf, kBlock, 0, st>>>(m, s, p)));
+  if (split) (void)hipStreamWaitEvent(st, fork->join, 0);
   TIMED(prof, kKClip, (k_clip_fast<<<kFastGrid, kFastBlock, 0, st>>>(m, s, p)));
   TIMED(prof, kKClipGeneral, (k_clip_general<<<4096, kClipBlock, 0, st>>>(m, s, p)));
   TIMED(prof, kKFaceSum, (k_face_sum<<<1024, kBlock, 0, st>>>(m, s, p)));

@@ -66,6 +66,7 @@ struct vof_mesh {
   // the launch sequence of one step captured once (valid while the kernel
   // arguments -- buffers and parameters -- stay as captured)
   hipStream_t cap_stream = nullptr;
+  Fork fork;  // side stream and events of the captured step
   hipGraphExec_t step_graph = nullptr;
   bool graph_ok = false;
   double prof_ms[kKNum] = {0};
@@ -88,6 +89,9 @@ struct vof_mesh {
   ~vof_mesh() {
     if (step_graph) (void)hipGraphExecDestroy(step_graph);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (fork.side) (void)hipStreamDestroy(fork.side);
+    if (fork.fork) (void)hipEventDestroy(fork.fork);
+    if (fork.join) (void)hipEventDestroy(fork.join);
     for (int i = 0; i < prof.cap; ++i) {
       (void)hipEventDestroy(prof.recs[i].a);
       (void)hipEventDestroy(prof.recs[i].b);
@@ -262,17 +266,21 @@ vof_status build_point_neighbours(vof_mesh *m) {
 }
 
 // Capture the launch sequence of one step on a private stream (the caller's
-// stream may be the null stream, which cannot be captured).  The step
-// contains kernels only: no memset or copy nodes.
+// stream may be the null stream, which cannot be captured), with the plane
+// kernel on a side stream forked from and joined back into the capture.  The
+// step contains kernels only: no memset or copy nodes.
 vof_status build_step_graph(vof_mesh *m) {
   if (!m->cap_stream) HIP_OR_FAIL(hipStreamCreateWithFlags(&m->cap_stream, hipStreamNonBlocking));
+  if (!m->fork.side) HIP_OR_FAIL(hipStreamCreateWithFlags(&m->fork.side, hipStreamNonBlocking));
+  if (!m->fork.fork) HIP_OR_FAIL(hipEventCreateWithFlags(&m->fork.fork, hipEventDisableTiming));
+  if (!m->fork.join) HIP_OR_FAIL(hipEventCreateWithFlags(&m->fork.join, hipEventDisableTiming));
   if (m->step_graph) {
     HIP_OR_FAIL(hipGraphExecDestroy(m->step_graph));
     m->step_graph = nullptr;
   }
   hipGraph_t g = nullptr;
   HIP_OR_FAIL(hipStreamBeginCapture(m->cap_stream, hipStreamCaptureModeThreadLocal));
-  launch_step(m->dm, m->ds, m->dp, m->cap_stream, nullptr);
+  launch_step(m->dm, m->ds, m->dp, m->cap_stream, nullptr, &m->fork);
   hipError_t e = hipStreamEndCapture(m->cap_stream, &g);
   if (e != hipSuccess) return fail(VOF_EDEVICE, "step capture: %s", hipGetErrorString(e));
   e = hipGraphInstantiate(&m->step_graph, g, nullptr, nullptr, 0);
@@ -788,7 +796,7 @@ vof_status vof_advect(vof_mesh *m, int32_t n_steps, const double *dt, const doub
   if (m->profiling) {
     // kernel by kernel, each bracketed by timing events
     for (int32_t i = 0; i < n_steps; ++i) {
-      launch_step(m->dm, m->ds, m->dp, s, &m->prof);
+      launch_step(m->dm, m->ds, m->dp, s, &m->prof, nullptr);
       HIP_OR_FAIL(hipGetLastError());
     }
     return VOF_OK;

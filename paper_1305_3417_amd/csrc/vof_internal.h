@@ -166,7 +166,15 @@ void launch_mesh_geometry(const DMesh &m, double4 *X, const double *pts, double4
                           double4 *bbhi, uint32_t *flags, hipStream_t st);
 void launch_point_velocity(const DMesh &m, const double *U0c, double4 *U, double4 *XU,
                            hipStream_t st);
-void launch_step(const DMesh &m, const DState &s, const DParams &p, hipStream_t st, Prof *prof);
+// A second stream and two events: when given (and not profiling), the PLIC
+// planes are computed on `side` while the flux kernel runs on the main stream
+// (neither reads what the other writes); the clip waits for both.
+struct Fork {
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+void launch_step(const DMesh &m, const DState &s, const DParams &p, hipStream_t st, Prof *prof,
+                 const Fork *fork);
 void launch_reconstruct(const DMesh &m, const DState &s, const DParams &p, hipStream_t st);
 void launch_stats(const DMesh &m, const DState &s, double *out4, hipStream_t st);
 void launch_map_alpha(const DMesh &d, double *alpha, const int32_t *off, const int32_t *cells,
