@@ -182,7 +182,8 @@ __global__ void k_cell_geom(DMesh m, double *V, double4 *XC, double4 *bblo, doub
 // the two cells of a face get exactly opposite planes.  A plane equal (bit
 // for bit) to one the cell has already is not repeated: the coplanar faces a
 // coarse cell shares with refined neighbours are one plane of the cell.
-__global__ void k_cell_planes(DMesh m, double4 *cpl, uint8_t *npl) {
+__global__ void k_cell_planes(DMesh m, double4 *cpl, uint8_t *npl, uint8_t *isbox,
+                              const double4 *bblo, const double4 *bbhi) {
   int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (c >= m.nc) return;
   const int k0 = m.cf_off[c];
@@ -203,6 +204,20 @@ __global__ void k_cell_planes(DMesh m, double4 *cpl, uint8_t *npl) {
     if (!dup) cpl[k0 + cnt++] = pl;
   }
   npl[c] = (uint8_t)cnt;
+  // a box cell: its six planes are +-e_x, +-e_y, +-e_z through its bounds
+  const double4 lo = bblo[c], hi = bbhi[c];
+  const double blo[3] = {lo.x, lo.y, lo.z}, bhi[3] = {hi.x, hi.y, hi.z};
+  int sides = 0;
+  for (int q = 0; q < cnt; ++q) {
+    const double4 pl = cpl[k0 + q];
+    const double n[3] = {pl.x, pl.y, pl.z};
+    for (int a = 0; a < 3; ++a) {
+      const bool axis = n[a] != 0.0 && n[(a + 1) % 3] == 0.0 && n[(a + 2) % 3] == 0.0;
+      if (axis && n[a] == 1.0 && pl.w == bhi[a]) sides |= 1 << (2 * a);
+      if (axis && n[a] == -1.0 && pl.w == -blo[a]) sides |= 2 << (2 * a);
+    }
+  }
+  isbox[c] = cnt == 6 && sides == 63;
 }
 
 // inverse distance weights of the point-cells (eq. 2.7)
@@ -714,6 +729,57 @@ void k_flux(DMesh m, DState s, DParams p) {
 // |T ∩ C_c ∩ H_c| (H = the PLIC half-space in interface cells, all space in
 // full cells, alpha-weighted in vanishing-gradient cells) is stored per item.
 
+// Plane j of a box cell with bounds bb (lo x y z, hi x y z), relative to c:
+// j = 0 +x, 1 -x, 2 +y, 3 -y, 4 +z, 5 -z.
+__device__ __forceinline__ Pl box_plane(const double *bb, int j, v3 c) {
+  const int a = j >> 1;
+  const double ca = a == 0 ? c.x : (a == 1 ? c.y : c.z);
+  const double sg = (j & 1) ? -1.0 : 1.0;
+  const double w = (j & 1) ? ca - bb[a] : bb[3 + a] - ca;
+  return Pl{a == 0 ? sg : 0.0, a == 1 ? sg : 0.0, a == 2 ? sg : 0.0, w};
+}
+
+// The cutting-plane mask of a box cell for the tet (c, c + T.b, c + T.c,
+// c + T.d), in box_plane order, or -1 when one plane has the whole tet outside
+// (touching included), as pair_cuts_box tests every plane.  Rounding is
+// monotone, so the extreme vertex distance to an axis plane is the distance
+// of the extreme coordinate.
+__device__ __forceinline__ int box_cuts(const double *bb, v3 c, const Tet &T, uint32_t &mask) {
+  mask = 0;
+  bool out = false;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double ca = a == 0 ? c.x : (a == 1 ? c.y : c.z);
+    const double t1 = a == 0 ? T.b.x : (a == 1 ? T.b.y : T.b.z);
+    const double t2 = a == 0 ? T.c.x : (a == 1 ? T.c.y : T.c.z);
+    const double t3 = a == 0 ? T.d.x : (a == 1 ? T.d.y : T.d.z);
+    const double tmx = dmax(dmax(0.0, t1), dmax(t2, t3));
+    const double tmn = dmin(dmin(0.0, t1), dmin(t2, t3));
+    const double up = bb[3 + a] - ca;  // +axis: distance up - t
+    const double dn = ca - bb[a];      // -axis: distance dn + t
+    out |= up - tmn <= 0.0 || dn + tmx <= 0.0;
+    mask |= (up - tmx < 0.0 ? 1u : 0u) << (2 * a);
+    mask |= (dn + tmn < 0.0 ? 1u : 0u) << (2 * a + 1);
+  }
+  return out ? -1 : __builtin_popcount(mask);
+}
+
+// pair_regs for a box cell: its cutting planes in mask order, then the PLIC
+// plane of an interface cell.
+__device__ __forceinline__ void pair_regs_box(const double *bb, const DState &s, v3 c, int cell,
+                                              int cl, uint32_t mask, Pl &p0, Pl &p1, Pl &p2,
+                                              Pl &p3) {
+  const Pl pl = cl == 1 ? plic_plane_at(s, cell, c) : Pl{0, 0, 0, 0};
+  uint32_t mm = mask;
+  p0 = mm ? box_plane(bb, __builtin_ctz(mm), c) : pl;
+  mm &= mm - 1;
+  p1 = mm ? box_plane(bb, __builtin_ctz(mm), c) : pl;
+  mm &= mm - 1;
+  p2 = mm ? box_plane(bb, __builtin_ctz(mm), c) : pl;
+  mm &= mm - 1;
+  p3 = mm ? box_plane(bb, __builtin_ctz(mm), c) : pl;
+}
+
 // Tetrahedron k of a face staged in LDS (P[j]: point j minus the face centre,
 // then its sweep at the corrected lam; cq: the mean sweep; n points), built
 // exactly as flux_tet builds it from global memory.
@@ -764,14 +830,15 @@ __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3)))
   __shared__ double fc[kGroupFaces][3];
   __shared__ double tv[10][kFastBlock];
   __shared__ int32_t icell[kFastBlock * kFastSlots];
-  __shared__ uint16_t imask[kFastBlock * kFastSlots];
+  __shared__ uint32_t imask[kFastBlock * kFastSlots];  // plane mask, candidate << 16, box << 20
   __shared__ double res[kFastBlock * kFastSlots];
   __shared__ uint16_t bins[kFastPlanes - 1][kFastBlock * kFastSlots];
   __shared__ int nbin[kFastPlanes - 1];
   __shared__ int32_t ccell[kGroupFaces][kCand];
-  __shared__ int8_t ccls[kGroupFaces][kCand];
-  // candidate boxes rounded outwards to float: the test stays conservative
-  __shared__ float cbox[kGroupFaces][kCand][6];
+  __shared__ int8_t ccls[kGroupFaces][kCand];  // class | 8 for a box cell
+  // candidate bounds (lo x y z, hi x y z): the box test, and the planes of a
+  // box cell
+  __shared__ double cbox[kGroupFaces][kCand][6];
   __shared__ double fbox[kGroupFaces][6];
   __shared__ int cnum[kGroupFaces];
   __shared__ int group;
@@ -890,13 +957,13 @@ __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3)))
         const int pos = cnt + (int)__popcll(bal & ((1ull << lane) - 1ull));
         if (keep && pos < kCand) {
           ccell[cf][pos] = cell;
-          ccls[cf][pos] = (int8_t)cl;
-          cbox[cf][pos][0] = __double2float_rd(blo.x);
-          cbox[cf][pos][1] = __double2float_rd(blo.y);
-          cbox[cf][pos][2] = __double2float_rd(blo.z);
-          cbox[cf][pos][3] = __double2float_ru(bhi.x);
-          cbox[cf][pos][4] = __double2float_ru(bhi.y);
-          cbox[cf][pos][5] = __double2float_ru(bhi.z);
+          ccls[cf][pos] = (int8_t)(cl | (m.isbox[cell] ? 8 : 0));
+          cbox[cf][pos][0] = blo.x;
+          cbox[cf][pos][1] = blo.y;
+          cbox[cf][pos][2] = blo.z;
+          cbox[cf][pos][3] = bhi.x;
+          cbox[cf][pos][4] = bhi.y;
+          cbox[cf][pos][5] = bhi.z;
         }
         cnt += (int)__popcll(bal);
       }
@@ -929,25 +996,30 @@ __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3)))
         const int nc = cnum[fi];
         for (int ci = 0; ci < nc; ++ci) {
           const int cell = ccell[fi][ci];
-          const int cl = ccls[fi][ci];
-          const float *bb = cbox[fi][ci];
+          const int cb = ccls[fi][ci];
+          const int cl = cb & 7;
+          const bool box = cb & 8;
+          const double *bb = cbox[fi][ci];
           uint32_t mask;
-          const int ncut = pair_cuts_box(m, c, T, lo, hi, mk3(bb[0], bb[1], bb[2]),
-                                         mk3(bb[3], bb[4], bb[5]), cell, mask);
+          const int ncut = box ? box_cuts(bb, c, T, mask)
+                               : pair_cuts_box(m, c, T, lo, hi, mk3(bb[0], bb[1], bb[2]),
+                                               mk3(bb[3], bb[4], bb[5]), cell, mask);
           if (ncut < 0) continue;
           const int npl = ncut + (cl == 1);
           ++np;
           if (npl <= 1) {
             double fr = 1.0;
             if (npl == 1) {
-              const Pl pl = ncut ? cell_plane_at(m, m.cf_off[cell] + __builtin_ctz(mask), c)
-                                 : plic_plane_at(s, cell, c);
+              const int q = __builtin_ctz(mask);
+              const Pl pl = !ncut ? plic_plane_at(s, cell, c)
+                                  : (box ? box_plane(bb, q, c)
+                                         : cell_plane_at(m, m.cf_off[cell] + q, c));
               fr = tet_kept_fraction(plane_dists(T, pl));
             }
             acc += class_weight(s, cell, cl) * det * fr;
           } else if (npl <= kFastPlanes && nq < kFastSlots) {
             icell[nq * kFastBlock + lane] = (int32_t)((uint32_t)cell | ((uint32_t)(npl - 2) << 30));
-            imask[nq * kFastBlock + lane] = (uint16_t)mask;
+            imask[nq * kFastBlock + lane] = mask | ((uint32_t)ci << 16) | (box ? 1u << 20 : 0u);
             ++nq;
           } else {
             defer = true;
@@ -980,8 +1052,12 @@ __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3)))
                     mk3(tv[3][l], tv[4][l], tv[5][l]), mk3(tv[6][l], tv[7][l], tv[8][l])};
         const double det = tv[9][l];
         const int cl = s.cls[cell];
+        const uint32_t im = imask[item];
         Pl p0, p1, p2, p3;
-        pair_regs(m, s, c, cell, cl, imask[item], p0, p1, p2, p3);
+        if (im & (1u << 20))
+          pair_regs_box(cbox[lf][(im >> 16) & 15u], s, c, cell, cl, im & 0xffffu, p0, p1, p2, p3);
+        else
+          pair_regs(m, s, c, cell, cl, im & 0xffffu, p0, p1, p2, p3);
         res[item] =
             class_weight(s, cell, cl) * vol6_planes<kFastPlanes>(T, det, p0, p1, p2, p3, b + 2);
       }
@@ -1412,13 +1488,13 @@ inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 
 // ---------------------------------------------------------------------------
 void launch_mesh_geometry(const DMesh &m0, double4 *X, const double *pts, double4 *S, double4 *C,
                           double *V, double4 *XC, double *wpc, double4 *cpl, uint8_t *npl,
-                          double4 *bblo,
+                          uint8_t *isbox, double4 *bblo,
                           double4 *bbhi, uint32_t *flags, hipStream_t st) {
   DMesh m = m0;
   k_points<<<grid_for(m.np, kBlock), kBlock, 0, st>>>(m.np, pts, X);
   k_face_geom<<<grid_for(m.nf, kBlock), kBlock, 0, st>>>(m, S, C);
   k_cell_geom<<<grid_for(m.nc, kBlock), kBlock, 0, st>>>(m, V, XC, bblo, bbhi);
-  k_cell_planes<<<grid_for(m.nc, kBlock), kBlock, 0, st>>>(m, cpl, npl);
+  k_cell_planes<<<grid_for(m.nc, kBlock), kBlock, 0, st>>>(m, cpl, npl, isbox, bblo, bbhi);
   k_idw<<<grid_for(m.np, kBlock), kBlock, 0, st>>>(m, wpc);
   if (m.ni > 0) k_check_orientation<<<grid_for(m.ni, kBlock), kBlock, 0, st>>>(m, flags);
 }

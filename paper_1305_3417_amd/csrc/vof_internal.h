@@ -84,6 +84,7 @@ struct DMesh {
   const double4 *cpl;      // per cell, from cf_off[c]: its distinct face planes
                            // (outward unit normal, offset), npl[c] of them
   const uint8_t *npl;
+  const uint8_t *isbox;    // 1: the cell is its bounding box (six axis planes at its bounds)
   const double4 *bblo;     // cell bounding box
   const double4 *bbhi;
 };
@@ -162,7 +163,7 @@ struct Prof {
 // launchers (vof_device.hip)
 void launch_mesh_geometry(const DMesh &m, double4 *X, const double *pts, double4 *S, double4 *C,
                           double *V, double4 *XC, double *wpc, double4 *cpl, uint8_t *npl,
-                          double4 *bblo,
+                          uint8_t *isbox, double4 *bblo,
                           double4 *bbhi, uint32_t *flags, hipStream_t st);
 void launch_point_velocity(const DMesh &m, const double *U0c, double4 *U, double4 *XU,
                            hipStream_t st);
