@@ -38,19 +38,28 @@ VHD void tet_bbox(v3 c, v3 t1, v3 t2, v3 t3, v3 &lo, v3 &hi) {
 // false for k beyond 5n or a flat tet.
 VHD bool flux_tet(const DMesh &m, const DState &s, double dt, double sc, int f, int k, v3 &c,
                   v3 &t1, v3 &t2, v3 &t3, double &det, double &sgn) {
+  // the padded point list in one or two 16-byte rows, the records loaded
+  // together (unrolled, in point order)
   const int32_t *fp = m.fpad + (int64_t)f * m.padw;
+  const int4 r0 = *reinterpret_cast<const int4 *>(fp);
+  const int4 r1 = m.padw > 4 ? *reinterpret_cast<const int4 *>(fp + 4) : make_int4(-1, -1, -1, -1);
+  const int q[kMaxFacePoints] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
   int n = 0;
-  for (int j = 0; j < m.padw; ++j) n += fp[j] >= 0;
+#pragma unroll
+  for (int j = 0; j < kMaxFacePoints; ++j) n += q[j] >= 0;
   if (k >= 5 * n) return false;
   const double sw = -sc * dt * s.lam[f];
   int i = k / 5, type = k - 5 * i;
   int i1 = (i + 1 == n) ? 0 : i + 1;
   c = mk3(0, 0, 0);
   v3 cq = mk3(0, 0, 0);
-  for (int j = 0; j < n; ++j) {
-    const double4 *xu = s.XU + 2 * (int64_t)fp[j];
-    c = c + xyz4(xu[0]);
-    cq = cq + sw * xyz4(xu[1]);
+#pragma unroll
+  for (int j = 0; j < kMaxFacePoints; ++j) {
+    if (q[j] >= 0) {
+      const double4 *xu = s.XU + 2 * (int64_t)q[j];
+      c = c + xyz4(xu[0]);
+      cq = cq + sw * xyz4(xu[1]);
+    }
   }
   const double4 *xa = s.XU + 2 * (int64_t)fp[i], *xb = s.XU + 2 * (int64_t)fp[i1];
   v3 pi = xyz4(xa[0]), pj = xyz4(xb[0]);
@@ -103,11 +112,50 @@ VHD int pair_cuts(const DMesh &m, v3 c, const Tet &T, v3 lo, v3 hi, int cell, ui
   return pair_cuts_box(m, c, T, lo, hi, xyz4(blo), xyz4(bhi), cell, mask);
 }
 
+// Plane j of a box cell with bounds bb (lo x y z, hi x y z), relative to c:
+// j = 0 +x, 1 -x, 2 +y, 3 -y, 4 +z, 5 -z.
+VHD Pl box_plane(const double *bb, int j, v3 c) {
+  const int a = j >> 1;
+  const double ca = a == 0 ? c.x : (a == 1 ? c.y : c.z);
+  const double sg = (j & 1) ? -1.0 : 1.0;
+  const double w = (j & 1) ? ca - bb[a] : bb[3 + a] - ca;
+  return Pl{a == 0 ? sg : 0.0, a == 1 ? sg : 0.0, a == 2 ? sg : 0.0, w};
+}
+
+// The cutting-plane mask of a box cell for the tet (c, c + T.b, c + T.c,
+// c + T.d), in box_plane order, or -1 when one plane has the whole tet outside
+// (touching included), as pair_cuts_box tests every plane.  Rounding is
+// monotone, so the extreme vertex distance to an axis plane is the distance
+// of the extreme coordinate.
+VHD int box_cuts(const double *bb, v3 c, const Tet &T, uint32_t &mask) {
+  mask = 0;
+  bool out = false;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double ca = a == 0 ? c.x : (a == 1 ? c.y : c.z);
+    const double t1 = a == 0 ? T.b.x : (a == 1 ? T.b.y : T.b.z);
+    const double t2 = a == 0 ? T.c.x : (a == 1 ? T.c.y : T.c.z);
+    const double t3 = a == 0 ? T.d.x : (a == 1 ? T.d.y : T.d.z);
+    const double tmx = dmax(dmax(0.0, t1), dmax(t2, t3));
+    const double tmn = dmin(dmin(0.0, t1), dmin(t2, t3));
+    const double up = bb[3 + a] - ca;  // +axis: distance up - t
+    const double dn = ca - bb[a];      // -axis: distance dn + t
+    out |= up - tmn <= 0.0 || dn + tmx <= 0.0;
+    mask |= (up - tmx < 0.0 ? 1u : 0u) << (2 * a);
+    mask |= (dn + tmn < 0.0 ? 1u : 0u) << (2 * a + 1);
+  }
+  return out ? -1 : __builtin_popcount(mask);
+}
+
 // cell plane q, or the PLIC plane of cell, with its offset relative to c
 VHD Pl cell_plane_at(const DMesh &m, int q, v3 c) {
   double4 cp = m.cpl[q];
   v3 nn = xyz4(cp);
   return mkpl(nn, cp.w - dot(nn, c));
+}
+// cutting plane u of a pair: cell plane u, or plane ~u of a box cell
+VHD Pl cut_plane(const DMesh &m, int u, const double *bb, v3 c) {
+  return u >= 0 ? cell_plane_at(m, u, c) : box_plane(bb, ~u, c);
 }
 VHD Pl plic_plane_at(const DState &s, int cell, v3 c) {
   double4 pp = s.plane[cell];
@@ -190,25 +238,43 @@ VHD double pair_phase6(const DMesh &m, const DState &s, const DParams &p, v3 c, 
   if (hi.x <= blo.x || lo.x >= bhi.x || hi.y <= blo.y || lo.y >= bhi.y || hi.z <= blo.z ||
       lo.z >= bhi.z)
     return 0.0;
+  // cutting planes: cuts[] holds cell-plane indices, or ~j for plane j of a
+  // box cell (taken from its bounds)
   int cuts[kMaxCellPlanes];
   Pl p0{0, 0, 0, 0}, p1 = p0, p2 = p0, p3 = p0;
   int ncut = 0;
-  for (int q = m.cf_off[cell], q1 = m.cf_off[cell] + m.npl[cell]; q < q1; ++q) {
-    double4 cp = m.cpl[q];
-    v3 nn = xyz4(cp);
-    double off = cp.w - dot(nn, c);
-    double d1 = off - dot(nn, T.b), d2 = off - dot(nn, T.c), d3 = off - dot(nn, T.d);
-    double dmx = dmax(dmax(off, d1), dmax(d2, d3));
-    double dmn = dmin(dmin(off, d1), dmin(d2, d3));
-    if (dmx <= 0.0) return 0.0;
-    if (dmn < 0.0) {
-      Pl pn = mkpl(nn, off);
+  const double bb[6] = {blo.x, blo.y, blo.z, bhi.x, bhi.y, bhi.z};
+  if (m.isbox[cell]) {
+    uint32_t mask;
+    if (box_cuts(bb, c, T, mask) < 0) return 0.0;
+    for (uint32_t mm = mask; mm; mm &= mm - 1) {
+      const int j = __builtin_ctz(mm);
+      const Pl pn = box_plane(bb, j, c);
       p3 = sel(ncut == 3, pn, p3);
       p2 = sel(ncut == 2, pn, p2);
       p1 = sel(ncut == 1, pn, p1);
       p0 = sel(ncut == 0, pn, p0);
-      if (ncut < kMaxCellPlanes) cuts[ncut] = q;
+      cuts[ncut] = ~j;
       ++ncut;
+    }
+  } else {
+    for (int q = m.cf_off[cell], q1 = m.cf_off[cell] + m.npl[cell]; q < q1; ++q) {
+      double4 cp = m.cpl[q];
+      v3 nn = xyz4(cp);
+      double off = cp.w - dot(nn, c);
+      double d1 = off - dot(nn, T.b), d2 = off - dot(nn, T.c), d3 = off - dot(nn, T.d);
+      double dmx = dmax(dmax(off, d1), dmax(d2, d3));
+      double dmn = dmin(dmin(off, d1), dmin(d2, d3));
+      if (dmx <= 0.0) return 0.0;
+      if (dmn < 0.0) {
+        Pl pn = mkpl(nn, off);
+        p3 = sel(ncut == 3, pn, p3);
+        p2 = sel(ncut == 2, pn, p2);
+        p1 = sel(ncut == 1, pn, p1);
+        p0 = sel(ncut == 0, pn, p0);
+        if (ncut < kMaxCellPlanes) cuts[ncut] = q;
+        ++ncut;
+      }
     }
   }
   const bool need_cover = p.check_stencil || cl >= 2;
@@ -233,8 +299,8 @@ VHD double pair_phase6(const DMesh &m, const DState &s, const DParams &p, v3 c, 
       P.init_tet(T.a, T.b, T.c, T.d);
       bool ok = true;
       for (int q = 0; q < ncut && ok; ++q) {
-        double4 cp = m.cpl[cuts[q < kMaxCellPlanes ? q : 0]];
-        ok = P.clip(xyz4(cp), cp.w - dot(xyz4(cp), c));
+        const Pl pc = cut_plane(m, cuts[q < kMaxCellPlanes ? q : 0], bb, c);
+        ok = P.clip(mk3(pc.x, pc.y, pc.z), pc.w);
       }
       if (ok && vc < 0.0 && p.check_stencil) vc = P.vol6();
       ok = ok && P.clip(nn, off);
@@ -246,8 +312,8 @@ VHD double pair_phase6(const DMesh &m, const DState &s, const DParams &p, v3 c, 
     P.init_tet(T.a, T.b, T.c, T.d);
     bool ok = true;
     for (int q = 0; q < ncut && ok; ++q) {
-      double4 cp = m.cpl[cuts[q < kMaxCellPlanes ? q : 0]];
-      ok = P.clip(xyz4(cp), cp.w - dot(xyz4(cp), c));
+      const Pl pc = cut_plane(m, cuts[q < kMaxCellPlanes ? q : 0], bb, c);
+      ok = P.clip(mk3(pc.x, pc.y, pc.z), pc.w);
     }
     vc = ok ? P.vol6() : 0.0;
     if (!ok || ncut > kMaxCellPlanes) ++ncap;

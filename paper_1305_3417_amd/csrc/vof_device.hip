@@ -729,41 +729,6 @@ void k_flux(DMesh m, DState s, DParams p) {
 // |T ∩ C_c ∩ H_c| (H = the PLIC half-space in interface cells, all space in
 // full cells, alpha-weighted in vanishing-gradient cells) is stored per item.
 
-// Plane j of a box cell with bounds bb (lo x y z, hi x y z), relative to c:
-// j = 0 +x, 1 -x, 2 +y, 3 -y, 4 +z, 5 -z.
-__device__ __forceinline__ Pl box_plane(const double *bb, int j, v3 c) {
-  const int a = j >> 1;
-  const double ca = a == 0 ? c.x : (a == 1 ? c.y : c.z);
-  const double sg = (j & 1) ? -1.0 : 1.0;
-  const double w = (j & 1) ? ca - bb[a] : bb[3 + a] - ca;
-  return Pl{a == 0 ? sg : 0.0, a == 1 ? sg : 0.0, a == 2 ? sg : 0.0, w};
-}
-
-// The cutting-plane mask of a box cell for the tet (c, c + T.b, c + T.c,
-// c + T.d), in box_plane order, or -1 when one plane has the whole tet outside
-// (touching included), as pair_cuts_box tests every plane.  Rounding is
-// monotone, so the extreme vertex distance to an axis plane is the distance
-// of the extreme coordinate.
-__device__ __forceinline__ int box_cuts(const double *bb, v3 c, const Tet &T, uint32_t &mask) {
-  mask = 0;
-  bool out = false;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    const double ca = a == 0 ? c.x : (a == 1 ? c.y : c.z);
-    const double t1 = a == 0 ? T.b.x : (a == 1 ? T.b.y : T.b.z);
-    const double t2 = a == 0 ? T.c.x : (a == 1 ? T.c.y : T.c.z);
-    const double t3 = a == 0 ? T.d.x : (a == 1 ? T.d.y : T.d.z);
-    const double tmx = dmax(dmax(0.0, t1), dmax(t2, t3));
-    const double tmn = dmin(dmin(0.0, t1), dmin(t2, t3));
-    const double up = bb[3 + a] - ca;  // +axis: distance up - t
-    const double dn = ca - bb[a];      // -axis: distance dn + t
-    out |= up - tmn <= 0.0 || dn + tmx <= 0.0;
-    mask |= (up - tmx < 0.0 ? 1u : 0u) << (2 * a);
-    mask |= (dn + tmn < 0.0 ? 1u : 0u) << (2 * a + 1);
-  }
-  return out ? -1 : __builtin_popcount(mask);
-}
-
 // pair_regs for a box cell: its cutting planes in mask order, then the PLIC
 // plane of an interface cell.
 __device__ __forceinline__ void pair_regs_box(const double *bb, const DState &s, v3 c, int cell,
@@ -1082,7 +1047,7 @@ __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3)))
 // every lane at once; the rare pairs with more planes then take turns on
 // one vertex-graph polytope in LDS shared by the wave.  Pair volumes are
 // summed by the wave butterfly (the same order on every run).
-__global__ __launch_bounds__(kClipBlock) void k_clip_general(DMesh m, DState s, DParams p) {
+__global__ __launch_bounds__(kClipBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_clip_general(DMesh m, DState s, DParams p) {
   const int step = *s.stepno;
   __shared__ double lx[kPolyCap], ly[kPolyCap], lz[kPolyCap], ld[kPolyCap];
   __shared__ uint8_t lnb[3 * kPolyCap], laux[kPolyCap];
