@@ -37,7 +37,8 @@ constexpr int kFastPlanes = 3;   // planes per pair in the register clip (more: 
 constexpr int kFastGrid = 4096;   // blocks claim face groups from a counter
 constexpr int kClaim = 2;         // face groups per claim
 constexpr int kGroupFaces = 4;    // faces per wavefront group (64 / at least 15 tets)
-constexpr int kCand = 16;         // candidate cells per face kept in LDS
+constexpr int kCandPool = 48;     // candidate cells of a face group kept in LDS (48 / F per face)
+constexpr int kFacePool = 12;     // staged points of a face group: F * max points <= 64 / 5
 constexpr int kPlaneGrid = 2048;  // blocks of four waves, one interface cell per wave
 static_assert(kMaxCellPlanes * kMaxFacePoints <= 128, "two fan tetrahedra per lane");
 static_assert(kMaxCellPlanes <= 16, "cutting-plane masks are 16 bits");
@@ -781,7 +782,7 @@ __device__ __forceinline__ bool staged_tet(const double (*P)[6], int n, const do
 // plane are summed at once (a single kept fraction); pairs with two to
 // kFastPlanes planes are queued in LDS bins by plane count, and a tet with a
 // pair of more planes, more than kFastSlots queued pairs, or a face with more
-// than kCand candidates goes to the general kernel's queue.  Phase B
+// than kCandPool / F candidates goes to the general kernel's queue.  Phase B
 // evaluates each bin with the plane count uniform across the wave; phase C
 // adds each tet's queued results in stencil order.
 __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_clip_fast(DMesh m, DState s, DParams p) {
@@ -789,21 +790,23 @@ __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3)))
   // the group's faces: points minus the face centre and their sweeps at the
   // corrected lam, the mean sweep, the point count and the face centre (the
   // apex of the face's tets); every tet is built from these
-  __shared__ double fpt[kGroupFaces][kMaxFacePoints][6];
+  __shared__ double fpt[kFacePool][6];  // face fi's point j at fi * maxn + j
   __shared__ double fcq[kGroupFaces][3];
   __shared__ int fn[kGroupFaces];
   __shared__ double fc[kGroupFaces][3];
   __shared__ double tv[10][kFastBlock];
-  __shared__ int32_t icell[kFastBlock * kFastSlots];
-  __shared__ uint32_t imask[kFastBlock * kFastSlots];  // plane mask, candidate << 16, box << 20
+  // queued pair: plane mask (bits 0-15), candidate (16-21), box cell (22),
+  // plane count - 2 (30-31)
+  __shared__ uint32_t qpair[kFastBlock * kFastSlots];
   __shared__ double res[kFastBlock * kFastSlots];
   __shared__ uint16_t bins[kFastPlanes - 1][kFastBlock * kFastSlots];
   __shared__ int nbin[kFastPlanes - 1];
-  __shared__ int32_t ccell[kGroupFaces][kCand];
-  __shared__ int8_t ccls[kGroupFaces][kCand];  // class | 8 for a box cell
+  // candidates of face fi at fi * (kCandPool / F) + position
+  __shared__ int32_t ccell[kCandPool];
+  __shared__ int8_t ccls[kCandPool];  // class | 8 for a box cell
   // candidate bounds (lo x y z, hi x y z): the box test, and the planes of a
   // box cell
-  __shared__ double cbox[kGroupFaces][kCand][6];
+  __shared__ double cbox[kCandPool][6];
   __shared__ double fbox[kGroupFaces][6];
   __shared__ int cnum[kGroupFaces];
   __shared__ int group;
@@ -813,6 +816,7 @@ __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3)))
   const int count = s.work[kWGeometric];
   const int tpf = m.tpf;
   const int F = kFastBlock / tpf;  // faces per group, 1..kGroupFaces
+  const int kc = kCandPool / F;    // candidates kept per face
   const int ngroups = (count + F - 1) / F;
   unsigned long long npairs = 0;
   // Groups are taken kClaim at a time: the first kClaim by block index, the
@@ -861,8 +865,9 @@ __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3)))
             const v3 x = xyz(xu[0]);
             const v3 u = sw * xyz(xu[1]);
             const v3 y = x + u;
-            fpt[lane][j][0] = x.x; fpt[lane][j][1] = x.y; fpt[lane][j][2] = x.z;
-            fpt[lane][j][3] = u.x; fpt[lane][j][4] = u.y; fpt[lane][j][5] = u.z;
+            double *row = fpt[lane * m.maxn + j];
+            row[0] = x.x; row[1] = x.y; row[2] = x.z;
+            row[3] = u.x; row[4] = u.y; row[5] = u.z;
             c = c + x;
             cs = cs + u;
             ++n;
@@ -875,7 +880,8 @@ __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3)))
         c = (1.0 / n) * c;
         cs = (1.0 / n) * cs;  // mean sweep
         for (int j = 0; j < n; ++j) {
-          fpt[lane][j][0] -= c.x; fpt[lane][j][1] -= c.y; fpt[lane][j][2] -= c.z;
+          double *row = fpt[lane * m.maxn + j];
+          row[0] -= c.x; row[1] -= c.y; row[2] -= c.z;
         }
         fn[lane] = n;
         fc[lane][0] = c.x; fc[lane][1] = c.y; fc[lane][2] = c.z;
@@ -920,15 +926,16 @@ __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3)))
         }
         const unsigned long long bal = __ballot(keep) & seg;
         const int pos = cnt + (int)__popcll(bal & ((1ull << lane) - 1ull));
-        if (keep && pos < kCand) {
-          ccell[cf][pos] = cell;
-          ccls[cf][pos] = (int8_t)(cl | (m.isbox[cell] ? 8 : 0));
-          cbox[cf][pos][0] = blo.x;
-          cbox[cf][pos][1] = blo.y;
-          cbox[cf][pos][2] = blo.z;
-          cbox[cf][pos][3] = bhi.x;
-          cbox[cf][pos][4] = bhi.y;
-          cbox[cf][pos][5] = bhi.z;
+        if (keep && pos < kc) {
+          const int u = cf * kc + pos;
+          ccell[u] = cell;
+          ccls[u] = (int8_t)(cl | (m.isbox[cell] ? 8 : 0));
+          cbox[u][0] = blo.x;
+          cbox[u][1] = blo.y;
+          cbox[u][2] = blo.z;
+          cbox[u][3] = bhi.x;
+          cbox[u][4] = bhi.y;
+          cbox[u][5] = bhi.z;
         }
         cnt += (int)__popcll(bal);
       }
@@ -948,8 +955,9 @@ __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3)))
       const v3 c = mk3(fc[fi][0], fc[fi][1], fc[fi][2]);
       v3 t1, t2, t3;
       double det;
-      live = !p.check_stencil && staged_tet(fpt[fi], fn[fi], fcq[fi], k, t1, t2, t3, det, sgn);
-      defer = p.check_stencil || cnum[fi] > kCand;
+      live = !p.check_stencil &&
+             staged_tet(&fpt[fi * m.maxn], fn[fi], fcq[fi], k, t1, t2, t3, det, sgn);
+      defer = p.check_stencil || cnum[fi] > kc;
       if (live && !defer) {
         tv[0][lane] = t1.x; tv[1][lane] = t1.y; tv[2][lane] = t1.z;
         tv[3][lane] = t2.x; tv[4][lane] = t2.y; tv[5][lane] = t2.z;
@@ -960,11 +968,12 @@ __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3)))
         tet_bbox(c, t1, t2, t3, lo, hi);
         const int nc = cnum[fi];
         for (int ci = 0; ci < nc; ++ci) {
-          const int cell = ccell[fi][ci];
-          const int cb = ccls[fi][ci];
+          const int u = fi * kc + ci;
+          const int cell = ccell[u];
+          const int cb = ccls[u];
           const int cl = cb & 7;
           const bool box = cb & 8;
-          const double *bb = cbox[fi][ci];
+          const double *bb = cbox[u];
           uint32_t mask;
           const int ncut = box ? box_cuts(bb, c, T, mask)
                                : pair_cuts_box(m, c, T, lo, hi, mk3(bb[0], bb[1], bb[2]),
@@ -983,8 +992,8 @@ __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3)))
             }
             acc += class_weight(s, cell, cl) * det * fr;
           } else if (npl <= kFastPlanes && nq < kFastSlots) {
-            icell[nq * kFastBlock + lane] = (int32_t)((uint32_t)cell | ((uint32_t)(npl - 2) << 30));
-            imask[nq * kFastBlock + lane] = mask | ((uint32_t)ci << 16) | (box ? 1u << 20 : 0u);
+            qpair[nq * kFastBlock + lane] = mask | ((uint32_t)ci << 16) | (box ? 1u << 22 : 0u) |
+                                            ((uint32_t)(npl - 2) << 30);
             ++nq;
           } else {
             defer = true;
@@ -997,7 +1006,7 @@ __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3)))
     if (defer) live = false;
     if (live) {
       for (int j = 0; j < nq; ++j) {
-        int b = (int)((uint32_t)icell[j * kFastBlock + lane] >> 30);
+        int b = (int)(qpair[j * kFastBlock + lane] >> 30);
         int pos = atomicAdd(&nbin[b], 1);
         bins[b][pos] = (uint16_t)(j * kFastBlock + lane);
       }
@@ -1010,19 +1019,20 @@ __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3)))
       for (int t = lane; t < cnt; t += kFastBlock) {
         const int item = bins[b][t];
         const int l = item % kFastBlock;
-        const int cell = (int)((uint32_t)icell[item] & 0x3fffffffu);
+        const uint32_t qp = qpair[item];
         const int lf = l / tpf;
+        const int u = lf * kc + (int)((qp >> 16) & 63u);
+        const int cell = ccell[u];
         const v3 c = mk3(fc[lf][0], fc[lf][1], fc[lf][2]);
         const Tet T{mk3(0, 0, 0), mk3(tv[0][l], tv[1][l], tv[2][l]),
                     mk3(tv[3][l], tv[4][l], tv[5][l]), mk3(tv[6][l], tv[7][l], tv[8][l])};
         const double det = tv[9][l];
         const int cl = s.cls[cell];
-        const uint32_t im = imask[item];
         Pl p0, p1, p2, p3;
-        if (im & (1u << 20))
-          pair_regs_box(cbox[lf][(im >> 16) & 15u], s, c, cell, cl, im & 0xffffu, p0, p1, p2, p3);
+        if (qp & (1u << 22))
+          pair_regs_box(cbox[u], s, c, cell, cl, qp & 0xffffu, p0, p1, p2, p3);
         else
-          pair_regs(m, s, c, cell, cl, im & 0xffffu, p0, p1, p2, p3);
+          pair_regs(m, s, c, cell, cl, qp & 0xffffu, p0, p1, p2, p3);
         res[item] =
             class_weight(s, cell, cl) * vol6_planes<kFastPlanes>(T, det, p0, p1, p2, p3, b + 2);
       }
