@@ -177,11 +177,13 @@ def test_rerun_is_bitwise_identical(vof, ctx):
 
 
 def test_step_graph_replays_match_eager(vof, ctx):
-    """Steps replayed from the captured graph (profiling off) against the same
-    steps launched kernel by kernel (profiling on): bitwise equal after every
-    call, with eager work (reads, a reconstruction, a parameter change that
-    forces a new capture) between the replays."""
-    w = W.deform3d(16, steps=12)
+    """Steps replayed from the captured graph (profiling off; the plane kernel
+    on a side stream) against the same steps launched kernel by kernel on one
+    stream (profiling on): bitwise equal after every call, with eager work
+    (reads, a reconstruction, parameter changes that force new captures: the
+    stencil check, the narrow band with wisps, the LSQ gradient) between the
+    replays."""
+    w = W.deform3d(16, steps=16)
     meshes = []
     for prof in (False, True):
         m = vof.upload_mesh(ctx, w.mesh)
@@ -200,7 +202,8 @@ def test_step_graph_replays_match_eager(vof, ctx):
 
     k = 0
     for n, params in [(3, None), (1, None), (2, {"check_stencil": 1}), (2, {"check_stencil": 0}),
-                      (4, None)]:
+                      (2, {"narrow_band": 1, "wisps": 1}), (2, {"gradient": vof.VOF_GRADIENT_LSQ}),
+                      (4, {"narrow_band": 0, "wisps": 0, "gradient": vof.VOF_GRADIENT_NAG})]:
         for m in meshes:
             if params:
                 p = vof.vof_get_params(m)
