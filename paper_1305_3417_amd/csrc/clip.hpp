@@ -21,6 +21,16 @@ namespace vof {
 
 VHD v3 xyz4(double4 a) { return mk3(a.x, a.y, a.z); }
 
+// Position x and reference velocity u of point q from its 48-byte record.
+struct PointRec {
+  v3 x, u;
+};
+VHD PointRec point_rec(const double *XU, int q) {
+  const double2 *r = reinterpret_cast<const double2 *>(XU + 6 * (int64_t)q);
+  const double2 a = r[0], b = r[1], c = r[2];
+  return PointRec{mk3(a.x, a.y, b.x), mk3(b.y, c.x, c.y)};
+}
+
 // Bounding box of tet (0, t1, t2, t3) shifted by c.
 VHD void tet_bbox(v3 c, v3 t1, v3 t2, v3 t3, v3 &lo, v3 &hi) {
   lo = mk3(dmin(dmin(0.0, t1.x), dmin(t2.x, t3.x)), dmin(dmin(0.0, t1.y), dmin(t2.y, t3.y)),
@@ -56,14 +66,14 @@ VHD bool flux_tet(const DMesh &m, const DState &s, double dt, double sc, int f, 
 #pragma unroll
   for (int j = 0; j < kMaxFacePoints; ++j) {
     if (q[j] >= 0) {
-      const double4 *xu = s.XU + 2 * (int64_t)q[j];
-      c = c + xyz4(xu[0]);
-      cq = cq + sw * xyz4(xu[1]);
+      const PointRec pr = point_rec(s.XU, q[j]);
+      c = c + pr.x;
+      cq = cq + sw * pr.u;
     }
   }
-  const double4 *xa = s.XU + 2 * (int64_t)fp[i], *xb = s.XU + 2 * (int64_t)fp[i1];
-  v3 pi = xyz4(xa[0]), pj = xyz4(xb[0]);
-  v3 qi = sw * xyz4(xa[1]), qj = sw * xyz4(xb[1]);
+  const PointRec ra = point_rec(s.XU, fp[i]), rb = point_rec(s.XU, fp[i1]);
+  v3 pi = ra.x, pj = rb.x;
+  v3 qi = sw * ra.u, qj = sw * rb.u;
   c = (1.0 / n) * c;
   pi = pi - c; pj = pj - c;
   qi = pi + qi; qj = pj + qj;

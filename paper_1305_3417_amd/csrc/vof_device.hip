@@ -247,7 +247,7 @@ __global__ void k_check_orientation(DMesh m, uint32_t *flags) {
 // U_p = sum_c w_pc U_c (eqs. 2.6-2.7 applied to the velocity, Section 2.3)
 // IDW point velocity (eq. 2.6); also the per-point record (position,
 // velocity) that the flux kernels gather with one cache line per point.
-__global__ void k_point_velocity(DMesh m, const double *U0c, double4 *U, double4 *XU) {
+__global__ void k_point_velocity(DMesh m, const double *U0c, double4 *U, double *XU) {
   int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (p >= m.np) return;
   v3 u = mk3(0, 0, 0);
@@ -256,8 +256,11 @@ __global__ void k_point_velocity(DMesh m, const double *U0c, double4 *U, double4
     u = u + m.wpc[k] * mk3(U0c[3 * c], U0c[3 * c + 1], U0c[3 * c + 2]);
   }
   U[p] = make_double4(u.x, u.y, u.z, 0.0);
-  XU[2 * p] = m.X[p];
-  XU[2 * p + 1] = make_double4(u.x, u.y, u.z, 0.0);
+  const double4 x = m.X[p];
+  double2 *r = reinterpret_cast<double2 *>(XU + 6 * p);
+  r[0] = make_double2(x.x, x.y);
+  r[1] = make_double2(x.z, u.x);
+  r[2] = make_double2(u.y, u.z);
 }
 
 // ---------------------------------------------------------------------------
@@ -603,9 +606,9 @@ __device__ __forceinline__ void face_cubic(const DState &s, const int (&q)[NMAX]
 #pragma unroll
   for (int i = 0; i < NMAX; ++i) {
     if (N > 0 || i < n) {
-      const double4 *xu = s.XU + 2 * (int64_t)q[i];
-      r[i] = xyz(xu[0]);
-      d[i] = sweep * xyz(xu[1]);
+      const PointRec pr = point_rec(s.XU, q[i]);
+      r[i] = pr.x;
+      d[i] = sweep * pr.u;
       mask |= s.pmask[q[i]];
       c = c + r[i];
       db = db + d[i];
@@ -861,9 +864,9 @@ __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3)))
 #pragma unroll
         for (int j = 0; j < kMaxFacePoints; ++j) {
           if (q[j] >= 0) {
-            const double4 *xu = s.XU + 2 * (int64_t)q[j];
-            const v3 x = xyz(xu[0]);
-            const v3 u = sw * xyz(xu[1]);
+            const PointRec pr = point_rec(s.XU, q[j]);
+            const v3 x = pr.x;
+            const v3 u = sw * pr.u;
             const v3 y = x + u;
             double *row = fpt[lane * m.maxn + j];
             row[0] = x.x; row[1] = x.y; row[2] = x.z;
@@ -1474,7 +1477,7 @@ void launch_mesh_geometry(const DMesh &m0, double4 *X, const double *pts, double
   if (m.ni > 0) k_check_orientation<<<grid_for(m.ni, kBlock), kBlock, 0, st>>>(m, flags);
 }
 
-void launch_point_velocity(const DMesh &m, const double *U0c, double4 *U, double4 *XU,
+void launch_point_velocity(const DMesh &m, const double *U0c, double4 *U, double *XU,
                            hipStream_t st) {
   k_point_velocity<<<grid_for(m.np, kBlock), kBlock, 0, st>>>(m, U0c, U, XU);
 }

@@ -494,7 +494,7 @@ vof_status vof_mesh_upload(vof_context *ctx, const vof_mesh_desc *d, vof_mesh **
 #define ALLOC(p, n) \
   do { if ((rc = m->alloc(&(p), (n)))) { delete m; return rc; } } while (0)
   ALLOC(X, np); ALLOC(d_pts, 3 * np); ALLOC(d_foff, nf + 1); ALLOC(d_fpts, nfp);
-  ALLOC(d_fpad, nf * (int64_t)padw); ALLOC(ds.XU, 2 * np);
+  ALLOC(d_fpad, nf * (int64_t)padw); ALLOC(ds.XU, 6 * np);
   ALLOC(d_own, nf); ALLOC(d_nei, ni); ALLOC(d_cf_off, nc + 1); ALLOC(d_cf, (int64_t)cf.size());
   ALLOC(d_pc_off, np + 1); ALLOC(d_pc, (int64_t)pc.size()); ALLOC(wpc, (int64_t)pc.size());
   ALLOC(d_st_off, nf + 1); ALLOC(d_st, (int64_t)st.size());
@@ -528,7 +528,7 @@ vof_status vof_mesh_upload(vof_context *ctx, const vof_mesh_desc *d, vof_mesh **
   if (e == hipSuccess) e = hipMemsetAsync(ds.plane, 0, sizeof(double4) * nc, s);
   if (e == hipSuccess) e = hipMemsetAsync(ds.alpha, 0, sizeof(double) * nc, s);
   if (e == hipSuccess) e = hipMemsetAsync(ds.U, 0, sizeof(double4) * np, s);
-  if (e == hipSuccess) e = hipMemsetAsync(ds.XU, 0, sizeof(double4) * 2 * np, s);
+  if (e == hipSuccess) e = hipMemsetAsync(ds.XU, 0, sizeof(double) * 6 * np, s);
   if (e == hipSuccess) e = hipMemsetAsync(ds.F0, 0, sizeof(double) * nf, s);
   if (e == hipSuccess) e = hipMemsetAsync(ds.lam, 0, sizeof(double) * nf, s);
   if (e == hipSuccess) e = hipMemsetAsync(ds.vphase, 0, sizeof(double) * nf, s);

@@ -109,7 +109,8 @@ struct DState {
   uint8_t *pmask;       // np: bit 1 empty, 2 full, 4 interface among point-cells
   double *alpha_p;      // np: IDW point values (band points only)
   double4 *U;           // np: reference point velocity
-  double4 *XU;          // 2 np: (position, reference velocity) of each point, adjacent
+  double *XU;           // 6 np: position and reference velocity of each point, adjacent
+                        // (48 bytes, three 16-byte loads)
   double *F0;           // nf
   double *lam;          // nf
   double *vphase;       // nf
@@ -165,7 +166,7 @@ void launch_mesh_geometry(const DMesh &m, double4 *X, const double *pts, double4
                           double *V, double4 *XC, double *wpc, double4 *cpl, uint8_t *npl,
                           uint8_t *isbox, double4 *bblo,
                           double4 *bbhi, uint32_t *flags, hipStream_t st);
-void launch_point_velocity(const DMesh &m, const double *U0c, double4 *U, double4 *XU,
+void launch_point_velocity(const DMesh &m, const double *U0c, double4 *U, double *XU,
                            hipStream_t st);
 // A second stream and two events: when given (and not profiling), the PLIC
 // planes are computed on `side` while the flux kernel runs on the main stream
