@@ -43,6 +43,9 @@ constexpr int kPlaneGrid = 2048;  // blocks of four waves, one interface cell pe
 static_assert(kMaxCellPlanes * kMaxFacePoints <= 128, "two fan tetrahedra per lane");
 static_assert(kMaxCellPlanes <= 16, "cutting-plane masks are 16 bits");
 constexpr int kLedgerParts = 256;  // partial sums of the boundary ledger
+constexpr int kGenTets = 3;        // deferred tets per wavefront in the general clip
+constexpr int kGenLanes = 21;      // lanes per tet (a hex face's stencil is 18 cells)
+static_assert(kGenTets * kGenLanes <= 64, "tets of a wavefront");
 constexpr int kWispGrid = 2048;    // blocks of the wisp passes (wave-stride over the lists)
 
 __device__ __forceinline__ v3 xyz(double4 a) { return mk3(a.x, a.y, a.z); }
@@ -1055,11 +1058,12 @@ __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3)))
   wave_count(cnt_at(s.cnt, kCntPairs), npairs);
 }
 
-// General clip of the queued tets, one wave per tet with the lanes over the
-// face's stencil cells: closed forms up to kRegPlanes planes per pair in
-// every lane at once; the rare pairs with more planes then take turns on
-// one vertex-graph polytope in LDS shared by the wave.  Pair volumes are
-// summed by the wave butterfly (the same order on every run).
+// General clip of the queued tets, kGenTets tets per wave with kGenLanes lanes
+// each over the face's stencil cells: closed forms up to kRegPlanes planes per
+// pair in every lane at once; the rare pairs with more planes then take turns
+// on one vertex-graph polytope in LDS shared by the wave.  A tet's pair
+// volumes are added lane by lane in stencil order (the same order on every
+// run).
 __global__ __launch_bounds__(kClipBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_clip_general(DMesh m, DState s, DParams p) {
   const int step = *s.stepno;
   __shared__ double lx[kPolyCap], ly[kPolyCap], lz[kPolyCap], ld[kPolyCap];
@@ -1071,54 +1075,76 @@ __global__ __launch_bounds__(kClipBlock) __attribute__((amdgpu_waves_per_eu(2)))
   P.nb = lnb; P.aux = laux;
   P.st = 1; P.cap = kPolyCap; P.nv = 0;
 
+  __shared__ double red[2][kClipBlock];
   const double dt = s.dt[step], sc = s.sc[step];
   const int count = s.work[kWDeferred];
+  // kGenTets tets per wavefront, kGenLanes lanes each over the tet's stencil
+  const int seg = lane / kGenLanes, sl = lane - seg * kGenLanes;
   unsigned long long ncap = 0, npairs = 0;
-  for (int i = blockIdx.x; i < count; i += gridDim.x) {
-    const int64_t idx = s.defer[i];
-    const int slot = (int)(idx / m.tpf);
-    const int k = (int)(idx - (int64_t)slot * m.tpf);
-    const int f = s.gfaces[slot];
-    v3 c, t1, t2, t3;
-    double det, sgn;
-    double acc = 0.0, cover = 0.0;
-    const bool live = flux_tet(m, s, dt, sc, f, k, c, t1, t2, t3, det, sgn);  // wave-uniform
-    if (live) {
-      const Tet T{mk3(0, 0, 0), t1, t2, t3};
-      v3 lo, hi;
-      tet_bbox(c, t1, t2, t3, lo, hi);
-      double a = 0.0, cv = 0.0;
-      const int e1 = m.st_off[f + 1];
-      for (int e0 = m.st_off[f]; e0 < e1; e0 += 64) {
-        const int e = e0 + lane;
-        double v = 0.0, vc = 0.0;
-        if (e < e1) v = pair_phase6(m, s, p, c, T, det, lo, hi, m.st[e], P, ncap, npairs, &vc,
-                                    false);
-        const bool pend = v != v;
-        unsigned long long pm = __ballot(pend);
-        while (pm) {
-          const int L = __ffsll((long long)pm) - 1;
-          pm &= pm - 1ull;
-          // the polytope changes hands: order one lane's LDS traffic before
-          // the next lane's (without this the compiler may interleave them)
-          __syncthreads();
-          if (lane == L)
-            v = pair_phase6(m, s, p, c, T, det, lo, hi, m.st[e], P, ncap, npairs, &vc, true);
-        }
-        __syncthreads();
-        a += v;
-        cv += vc;
+  for (int i0 = blockIdx.x * kGenTets; i0 < count; i0 += gridDim.x * kGenTets) {
+    const int i = i0 + seg;
+    const bool mine = seg < kGenTets && i < count;
+    int64_t idx = 0;
+    int f = 0;
+    v3 c = mk3(0, 0, 0), t1 = c, t2 = c, t3 = c;
+    double det = 0.0, sgn = 1.0;
+    bool live = false;
+    int e0 = 0, e1 = 0;
+    if (mine) {
+      idx = s.defer[i];
+      const int slot = (int)(idx / m.tpf);
+      const int k = (int)(idx - (int64_t)slot * m.tpf);
+      f = s.gfaces[slot];
+      live = flux_tet(m, s, dt, sc, f, k, c, t1, t2, t3, det, sgn);
+      if (live) {
+        e0 = m.st_off[f];
+        e1 = m.st_off[f + 1];
       }
-      acc = wave_sum_d(a);
-      cover = wave_sum_d(cv);
     }
-    if (lane == 0) {
+    // the largest stencil among the wave's tets sets the trip count
+    int most = e1 - e0;
+    for (int o = 32; o > 0; o >>= 1) most = max(most, __shfl_xor(most, o));
+    const Tet T{mk3(0, 0, 0), t1, t2, t3};
+    v3 lo, hi;
+    tet_bbox(c, t1, t2, t3, lo, hi);
+    double a = 0.0, cv = 0.0;
+    for (int b = 0; b < most; b += kGenLanes) {
+      const int e = e0 + b + sl;
+      const bool act = live && e < e1;
+      double v = 0.0, vc = 0.0;
+      if (act) v = pair_phase6(m, s, p, c, T, det, lo, hi, m.st[e], P, ncap, npairs, &vc, false);
+      const bool pend = act && v != v;
+      unsigned long long pm = __ballot(pend);
+      while (pm) {
+        const int L = __ffsll((long long)pm) - 1;
+        pm &= pm - 1ull;
+        // the polytope changes hands: order one lane's LDS traffic before
+        // the next lane's (without this the compiler may interleave them)
+        __syncthreads();
+        if (lane == L)
+          v = pair_phase6(m, s, p, c, T, det, lo, hi, m.st[e], P, ncap, npairs, &vc, true);
+      }
+      __syncthreads();
+      a += v;
+      cv += vc;
+    }
+    // per tet, its lanes' sums added in lane order
+    red[0][lane] = a;
+    red[1][lane] = cv;
+    __syncthreads();
+    if (mine && sl == 0) {
+      double acc = 0.0, cover = 0.0;
+      for (int j = 0; j < kGenLanes; ++j) {
+        acc += red[0][lane + j];
+        cover += red[1][lane + j];
+      }
       s.tetvol[idx] = live ? sgn * acc / 6.0 : 0.0;
       if (p.check_stencil) {
         s.tetdef[idx] = live ? sgn * (det - cover) / 6.0 : 0.0;
         s.tetgross[idx] = live ? det / 6.0 : 0.0;
       }
     }
+    __syncthreads();
   }
   wave_count(cnt_at(s.cnt, kCntCapacity), ncap);
   wave_count(cnt_at(s.cnt, kCntPairs), npairs);
