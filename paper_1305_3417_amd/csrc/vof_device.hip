@@ -1386,6 +1386,7 @@ __global__ __launch_bounds__(kBlock) void k_ledger(DMesh m, DState s, DParams p,
       s.wctr[0] += 1u;  // the next step's wisps and receivers get a new stamp
     }
     s.stepno[0] += 1;  // the next step reads dt, scale at the next index
+    for (int w = 0; w < kWNum; ++w) s.work[w] = 0;  // the next step's lists start empty
   }
 }
 
@@ -1515,9 +1516,12 @@ static void launch_reconstruct_impl(const DMesh &m, const DState &s, const DPara
   k_plane<<<kPlaneGrid, kBlock, 0, st>>>(m, s, p);
 }
 
+// A step starts from zero work counters (the previous step's last kernel
+// clears them), so a reconstruction clears them again when it is done.
 void launch_reconstruct(const DMesh &m, const DState &s, const DParams &p, hipStream_t st) {
   k_reset<<<1, 64, 0, st>>>(s);
   launch_reconstruct_impl(m, s, p, st);
+  k_reset<<<1, 64, 0, st>>>(s);
 }
 
 bool Prof::begin(int kid) {
@@ -1548,7 +1552,6 @@ void Prof::end(int kid) {
 void launch_step(const DMesh &m, const DState &s, const DParams &p, hipStream_t st, Prof *prof,
                  const Fork *fork) {
   const bool split = fork && !prof;
-  TIMED(prof, kKReset, (k_reset<<<1, 64, 0, st>>>(s)));
   TIMED(prof, kKCellClass, (k_cell_class<<<grid_for(m.nc, kBlock), kBlock, 0, st>>>(m, s, p)));
   TIMED(prof, kKPointPrep, (k_point_prep<<<grid_for(m.np, kBlock), kBlock, 0, st>>>(m, s, p)));
   if (split) {

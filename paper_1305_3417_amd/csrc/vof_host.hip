@@ -523,6 +523,7 @@ vof_status vof_mesh_upload(vof_context *ctx, const vof_mesh_desc *d, vof_mesh **
 #undef UP
   hipError_t e = hipMemsetAsync(ds.cnt, 0, sizeof(unsigned long long) * kCntWords, s);
   if (e == hipSuccess) e = hipMemsetAsync(ds.flags, 0, sizeof(uint32_t), s);
+  if (e == hipSuccess) e = hipMemsetAsync(ds.work, 0, sizeof(int32_t) * kWNum, s);
   if (e == hipSuccess) e = hipMemsetAsync(ds.ledger, 0, sizeof(double), s);
   if (e == hipSuccess) e = hipMemsetAsync(ds.cls, 0, nc, s);
   if (e == hipSuccess) e = hipMemsetAsync(ds.plane, 0, sizeof(double4) * nc, s);
