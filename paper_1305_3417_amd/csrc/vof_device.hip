@@ -187,7 +187,7 @@ __global__ void k_cell_geom(DMesh m, double *V, double4 *XC, double4 *bblo, doub
 // for bit) to one the cell has already is not repeated: the coplanar faces a
 // coarse cell shares with refined neighbours are one plane of the cell.
 __global__ void k_cell_planes(DMesh m, double4 *cpl, uint8_t *npl, uint8_t *isbox,
-                              const double4 *bblo, const double4 *bbhi) {
+                              uint8_t *fan_small, const double4 *bblo, const double4 *bbhi) {
   int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (c >= m.nc) return;
   const int k0 = m.cf_off[c];
@@ -222,6 +222,13 @@ __global__ void k_cell_planes(DMesh m, double4 *cpl, uint8_t *npl, uint8_t *isbo
     }
   }
   isbox[c] = cnt == 6 && sides == 63;
+  int slots = 0;  // face-fan tetrahedra of the cell: one per face point
+  for (int k = k0; k < m.cf_off[c + 1]; ++k) {
+    const int sf = m.cf[k];
+    const int f = sf >= 0 ? sf : ~sf;
+    slots += m.foff[f + 1] - m.foff[f];
+  }
+  fan_small[c] = m.cf_off[c + 1] - k0 <= 32 && slots <= 64;
 }
 
 // inverse distance weights of the point-cells (eq. 2.7)
@@ -342,18 +349,19 @@ struct FanTet {
   double v6;
 };
 
-// The cell's faces are spread over the lanes (lane j < nfc holds face j: its
-// index f, sign, first point b and point count nn); the fan slots are numbered
-// face by face, so slot s belongs to the last face whose first slot (an
-// exclusive prefix sum of nn over the lanes) is at most s.
+// The cell's faces are spread over the W lanes of its group (lane j < nfc
+// holds face j: its index f, sign, first point b and point count nn); the fan
+// slots are numbered face by face, so slot s belongs to the last face whose
+// first slot (an exclusive prefix sum of nn over the lanes) is at most s.
+template <int W>
 __device__ FanTet fan_tet(const DMesh &m, v3 o, int slot, int nfc, int f, double sg, int b,
                           int nn, int first, int total) {
   int j = 0;
   for (int q = 1; q < nfc; ++q)
-    if (__shfl(first, q) <= slot) j = q;
-  const int fj = __shfl(f, j), bj = __shfl(b, j), nj = __shfl(nn, j);
-  const double sj = __shfl(sg, j);
-  const int i = slot - __shfl(first, j);
+    if (__shfl(first, q, W) <= slot) j = q;
+  const int fj = __shfl(f, j, W), bj = __shfl(b, j, W), nj = __shfl(nn, j, W);
+  const double sj = __shfl(sg, j, W);
+  const int i = slot - __shfl(first, j, W);
   FanTet t{mk3(0, 0, 0), mk3(0, 0, 0), mk3(0, 0, 0), 0.0};
   if (slot < total) {
     const int i1 = (i + 1 == nj) ? 0 : i + 1;
@@ -365,6 +373,24 @@ __device__ FanTet fan_tet(const DMesh &m, v3 o, int slot, int nfc, int f, double
   return t;
 }
 
+// Sums, minima and maxima over a group of W lanes (W = 32 or 64), the same
+// value in every lane of the group (butterfly within the group).
+template <int W>
+__device__ __forceinline__ double group_sum(double v) {
+  for (int o = W / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, W);
+  return v;
+}
+template <int W>
+__device__ __forceinline__ double group_min(double v) {
+  for (int o = W / 2; o > 0; o >>= 1) v = dmin(v, __shfl_xor(v, o, W));
+  return v;
+}
+template <int W>
+__device__ __forceinline__ double group_max(double v) {
+  for (int o = W / 2; o > 0; o >>= 1) v = dmax(v, __shfl_xor(v, o, W));
+  return v;
+}
+
 // NAG gradient (eqs. 2.8-2.12) and plane positioning (Section 2.2.2), one
 // wave per interface cell.  The fill level g(s) = |C ∩ {n.x <= s}| / |C| -
 // alpha is monotone between the lowest and highest cell points; it is solved
@@ -372,14 +398,11 @@ __device__ FanTet fan_tet(const DMesh &m, v3 o, int slot, int nfc, int f, double
 // converges superlinearly.  Each evaluation sums vol6 * kept fraction over
 // the fan tetrahedra of the cell, two per lane (at most 16 faces of at most
 // 8 points), so every decision of the iteration is wave-uniform.
-__global__ __launch_bounds__(kBlock) void k_plane(DMesh m, DState s, DParams p) {
-  const int count = s.work[kWInterface];
-  const int lane = lane_id();
-  const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-  const int nwaves = (int)((gridDim.x * blockDim.x) >> 6);
-  unsigned long long nfall = 0;
-  for (int i = wave; i < count; i += nwaves) {
-    const int64_t c = s.icells[i];
+// Plane of interface cell c by a group of W lanes (lane: the index in the
+// group): NAG (or least-squares) gradient, normal, and positioning.
+template <int W>
+__device__ __forceinline__ void plane_cell(const DMesh &m, const DState &s, const DParams &p,
+                                           int64_t c, int lane, unsigned long long &nfall) {
     const double a = s.alpha[c];
     const int k0 = m.cf_off[c], nfc = m.cf_off[c + 1] - k0;
     const double Vc = m.V[c];
@@ -400,7 +423,7 @@ __global__ __launch_bounds__(kBlock) void k_plane(DMesh m, DState s, DParams p) 
       // with d = x_k - x_c, w = 1/|d|, solved by Cramer's rule
       const v3 xc = xyz(m.XC[c]);
       double a00 = 0, a01 = 0, a02 = 0, a11 = 0, a12 = 0, a22 = 0, b0 = 0, b1 = 0, b2 = 0;
-      for (int e = m.cpn_off[c] + lane; e < m.cpn_off[c + 1]; e += 64) {
+      for (int e = m.cpn_off[c] + lane; e < m.cpn_off[c + 1]; e += W) {
         const int k = m.cpn[e];
         const v3 d = xyz(m.XC[k]) - xc;
         const double w2 = 1.0 / dot(d, d);
@@ -409,9 +432,9 @@ __global__ __launch_bounds__(kBlock) void k_plane(DMesh m, DState s, DParams p) 
         a11 += w2 * d.y * d.y; a12 += w2 * d.y * d.z; a22 += w2 * d.z * d.z;
         b0 += w2 * d.x * da; b1 += w2 * d.y * da; b2 += w2 * d.z * da;
       }
-      a00 = wave_sum_d(a00); a01 = wave_sum_d(a01); a02 = wave_sum_d(a02);
-      a11 = wave_sum_d(a11); a12 = wave_sum_d(a12); a22 = wave_sum_d(a22);
-      b0 = wave_sum_d(b0); b1 = wave_sum_d(b1); b2 = wave_sum_d(b2);
+      a00 = group_sum<W>(a00); a01 = group_sum<W>(a01); a02 = group_sum<W>(a02);
+      a11 = group_sum<W>(a11); a12 = group_sum<W>(a12); a22 = group_sum<W>(a22);
+      b0 = group_sum<W>(b0); b1 = group_sum<W>(b1); b2 = group_sum<W>(b2);
       const double det = det3(mk3(a00, a01, a02), mk3(a01, a11, a12), mk3(a02, a12, a22));
       const double d0 = det3(mk3(b0, b1, b2), mk3(a01, a11, a12), mk3(a02, a12, a22));
       const double d1 = det3(mk3(a00, a01, a02), mk3(b0, b1, b2), mk3(a02, a12, a22));
@@ -439,7 +462,7 @@ __global__ __launch_bounds__(kBlock) void k_plane(DMesh m, DState s, DParams p) 
         }
         gl = (sg * (num / den)) * xyz(m.S[f]);
       }
-      g = (1.0 / Vc) * mk3(wave_sum_d(gl.x), wave_sum_d(gl.y), wave_sum_d(gl.z));
+      g = (1.0 / Vc) * mk3(group_sum<W>(gl.x), group_sum<W>(gl.y), group_sum<W>(gl.z));
     }
     double gn = sqrt(dot(g, g));
     if (!(gn * cbrt(Vc) >= p.grad_zero)) {
@@ -448,28 +471,28 @@ __global__ __launch_bounds__(kBlock) void k_plane(DMesh m, DState s, DParams p) 
         s.plane[c] = make_double4(0.0, 0.0, 0.0, 0.0);
         ++nfall;
       }
-      continue;
+      return;
     }
     const v3 n = (-1.0 / gn) * g;
     const v3 o = xyz(m.XC[c]);
     // fan tetrahedra as heights along n
     int first = lnn;  // inclusive prefix sum of the point counts, then exclusive
-    for (int q = 1; q < 64; q <<= 1) {
-      const int t = __shfl_up(first, q);
+    for (int q = 1; q < W; q <<= 1) {
+      const int t = __shfl_up(first, q, W);
       if (lane >= q) first += t;
     }
-    const int total = __shfl(first, 63);
+    const int total = __shfl(first, W - 1, W);
     first -= lnn;
-    FanTet t0 = fan_tet(m, o, lane, nfc, lf, lsg, lb, lnn, first, total);
-    FanTet t1 = fan_tet(m, o, lane + 64, nfc, lf, lsg, lb, lnn, first, total);
+    FanTet t0 = fan_tet<W>(m, o, lane, nfc, lf, lsg, lb, lnn, first, total);
+    FanTet t1 = fan_tet<W>(m, o, lane + W, nfc, lf, lsg, lb, lnn, first, total);
     const double hc0 = dot(n, t0.cf), ha0 = dot(n, t0.pa), hb0 = dot(n, t0.pb);
     const double hc1 = dot(n, t1.cf), ha1 = dot(n, t1.pa), hb1 = dot(n, t1.pb);
     // the points of the cell are the p_i of its fans
     double hmin = t0.v6 != 0.0 ? ha0 : 1e300, hmax = t0.v6 != 0.0 ? ha0 : -1e300;
     if (t1.v6 != 0.0) { hmin = dmin(hmin, ha1); hmax = dmax(hmax, ha1); }
-    hmin = wave_min_d(hmin);
-    hmax = wave_max_d(hmax);
-    const double tot6 = wave_sum_d(t0.v6 + t1.v6);
+    hmin = group_min<W>(hmin);
+    hmax = group_max<W>(hmax);
+    const double tot6 = group_sum<W>(t0.v6 + t1.v6);
     double lo = hmin, glo = -a, hi = hmax, ghi = 1.0 - a;
     double sx = 0.5 * (lo + hi);
     int side = 0;
@@ -478,7 +501,7 @@ __global__ __launch_bounds__(kBlock) void k_plane(DMesh m, DState s, DParams p) 
       if (!(sn > lo && sn < hi)) sn = 0.5 * (lo + hi);
       double f0 = t0.v6 * tet_kept_fraction(D4{sn, sn - hc0, sn - ha0, sn - hb0});
       double f1 = t1.v6 * tet_kept_fraction(D4{sn, sn - hc1, sn - ha1, sn - hb1});
-      double gs = wave_sum_d(f0 + f1) / tot6 - a;
+      double gs = group_sum<W>(f0 + f1) / tot6 - a;
       sx = sn;
       if (fabs(gs) <= p.pos_tol) break;
       if (gs < 0.0) {
@@ -493,6 +516,28 @@ __global__ __launch_bounds__(kBlock) void k_plane(DMesh m, DState s, DParams p) 
       if (hi - lo <= 2e-16 * (hmax - hmin)) break;
     }
     if (lane == 0) s.plane[c] = make_double4(n.x, n.y, n.z, sx + dot(n, o));
+}
+
+// NAG gradient and plane positioning of the interface cells.  A wave takes
+// two cells; when both have at most 32 faces and 64 fan tetrahedra (so
+// that two per lane cover them) each gets half of the wave, else the whole
+// wave does one after the other.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_plane(DMesh m, DState s, DParams p) {
+  const int count = s.work[kWInterface];
+  const int lane = lane_id();
+  const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int nwaves = (int)((gridDim.x * blockDim.x) >> 6);
+  unsigned long long nfall = 0;
+  for (int i = 2 * wave; i < count; i += 2 * nwaves) {
+    const int64_t ca = s.icells[i];
+    const int64_t cb = i + 1 < count ? s.icells[i + 1] : -1;
+    if (m.fan_small[ca] && (cb < 0 || m.fan_small[cb])) {
+      const int64_t c = lane < 32 ? ca : cb;
+      if (c >= 0) plane_cell<32>(m, s, p, c, lane & 31, nfall);
+    } else {
+      plane_cell<64>(m, s, p, ca, lane, nfall);
+      if (cb >= 0) plane_cell<64>(m, s, p, cb, lane, nfall);
+    }
   }
   wave_count(cnt_at(s.cnt, kCntFallback), nfall);
 }
@@ -1493,13 +1538,14 @@ inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 
 // ---------------------------------------------------------------------------
 void launch_mesh_geometry(const DMesh &m0, double4 *X, const double *pts, double4 *S, double4 *C,
                           double *V, double4 *XC, double *wpc, double4 *cpl, uint8_t *npl,
-                          uint8_t *isbox, double4 *bblo,
+                          uint8_t *isbox, uint8_t *fan_small, double4 *bblo,
                           double4 *bbhi, uint32_t *flags, hipStream_t st) {
   DMesh m = m0;
   k_points<<<grid_for(m.np, kBlock), kBlock, 0, st>>>(m.np, pts, X);
   k_face_geom<<<grid_for(m.nf, kBlock), kBlock, 0, st>>>(m, S, C);
   k_cell_geom<<<grid_for(m.nc, kBlock), kBlock, 0, st>>>(m, V, XC, bblo, bbhi);
-  k_cell_planes<<<grid_for(m.nc, kBlock), kBlock, 0, st>>>(m, cpl, npl, isbox, bblo, bbhi);
+  k_cell_planes<<<grid_for(m.nc, kBlock), kBlock, 0, st>>>(m, cpl, npl, isbox, fan_small, bblo,
+                                                            bbhi);
   k_idw<<<grid_for(m.np, kBlock), kBlock, 0, st>>>(m, wpc);
   if (m.ni > 0) k_check_orientation<<<grid_for(m.ni, kBlock), kBlock, 0, st>>>(m, flags);
 }
