@@ -42,7 +42,7 @@ constexpr int kFacePool = 12;     // staged points of a face group: F * max poin
 constexpr int kPlaneGrid = 2048;  // blocks of four waves, one interface cell per wave
 static_assert(kMaxCellPlanes * kMaxFacePoints <= 128, "two fan tetrahedra per lane");
 static_assert(kMaxCellPlanes <= 16, "cutting-plane masks are 16 bits");
-constexpr int kLedgerParts = 256;  // partial sums of the boundary ledger
+constexpr int kLedgerBlock = 1024;  // the one block of the ledger's second stage
 constexpr int kGenTets = 3;        // deferred tets per wavefront in the general clip
 constexpr int kGenLanes = 21;      // lanes per tet (a hex face's stencil is 18 cells)
 static_assert(kGenTets * kGenLanes <= 64, "tets of a wavefront");
@@ -1222,17 +1222,21 @@ __global__ __launch_bounds__(kBlock) void k_face_sum(DMesh m, DState s, DParams 
   if (__ballot(nleak != 0) && lane_id() == 0) flag(s.flags, kFlagLeak);
 }
 
-// alpha_c^{n+1} = alpha_c^n - (1/V_c) sum_f sgn_cf V_{f,alpha}, every cell;
+// alpha_c^{n+1} = alpha_c^n - (1/V_c) sum_f sgn_cf V_{f,alpha}, every cell
+// (and each block's sum of the phase volumes through its cells' boundary
+// faces, the first stage of the ledger);
 // with the narrow band (Section 2.3) every cell but the bulk cells, those
 // whose faces' points touch only cells that are exactly 0 (or only exactly 1),
 // so that every cell sharing a point with them is.  With wisps on, the
 // updated cells outside the interface band whose alpha is not exactly 0 or
 // 1 are listed with their excess over the nearer of the two.
 __global__ __launch_bounds__(kBlock) void k_update(DMesh m, DState s, DParams p) {
+  __shared__ double red[kBlock];
   int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const uint32_t stamp = p.wisps ? s.wctr[0] + 1u : 0u;
   bool wisp = false;
   double ex = 0.0;
+  double led = 0.0;  // phase volume through the cell's boundary faces
   if (c < m.nc) {
     const int k0 = m.cf_off[c], k1 = m.cf_off[c + 1];
     bool skip = false;
@@ -1244,14 +1248,22 @@ __global__ __launch_bounds__(kBlock) void k_update(DMesh m, DState s, DParams p)
         b &= s.fbulk[sf >= 0 ? sf : ~sf];
       }
       skip = b != 0;
+      if (skip) {
+        for (int k = k0; k < k1; ++k) {
+          const int sf = m.cf[k];
+          if (sf >= m.ni) led += s.vphase[sf];
+        }
+      }
     }
     if (!skip) {
       double acc = 0.0;
       // unrolled so that the face ids, then the phase volumes, load together
 #pragma unroll 6
       for (int k = k0; k < k1; ++k) {
-        int sf = m.cf[k];
-        acc += sf >= 0 ? s.vphase[sf] : -s.vphase[~sf];
+        const int sf = m.cf[k];
+        const double v = s.vphase[sf >= 0 ? sf : ~sf];
+        acc += sf >= 0 ? v : -v;
+        led += sf >= m.ni ? v : 0.0;
       }
       const double V = m.V[c];
       const double a = s.alpha[c] - acc / V;
@@ -1270,6 +1282,14 @@ __global__ __launch_bounds__(kBlock) void k_update(DMesh m, DState s, DParams p)
       s.wstamp[c] = stamp;
     }
   }
+  // the block's part of the boundary ledger, summed in a fixed order
+  red[threadIdx.x] = led;
+  __syncthreads();
+  for (int o = kBlock / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) s.part[blockIdx.x] = red[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -1392,31 +1412,17 @@ __global__ __launch_bounds__(kBlock) void k_wisp_moves(DMesh m, DState s, DParam
   }
 }
 
-// boundary ledger, two stages in fixed order: per-block partial sums of the
-// boundary faces' phase volumes, then one block adds them and the counters
-__global__ __launch_bounds__(kBlock) void k_ledger_part(DMesh m, DState s) {
-  __shared__ double red[kBlock];
+// boundary ledger, second stage: one block adds the update kernel's
+// per-block sums in a fixed order, and the step's counts
+__global__ __launch_bounds__(kLedgerBlock) void k_ledger(DMesh m, DState s, DParams p, int nparts) {
+  __shared__ double red[kLedgerBlock];
   double acc = 0.0;
-  const int64_t nb = m.nf - m.ni;
-  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < nb;
-       i += (int64_t)gridDim.x * kBlock)
-    acc += s.vphase[m.ni + i];
+  // unrolled so that a thread's partial sums load together
+#pragma unroll 8
+  for (int i = threadIdx.x; i < nparts; i += kLedgerBlock) acc += s.part[i];
   red[threadIdx.x] = acc;
   __syncthreads();
-  for (int o = kBlock / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) s.part[blockIdx.x] = red[0];
-}
-
-__global__ __launch_bounds__(kBlock) void k_ledger(DMesh m, DState s, DParams p, int nparts) {
-  __shared__ double red[kBlock];
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += kBlock) acc += s.part[i];
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int o = kBlock / 2; o > 0; o >>= 1) {
+  for (int o = kLedgerBlock / 2; o > 0; o >>= 1) {
     if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
     __syncthreads();
   }
@@ -1628,8 +1634,8 @@ void launch_step(const DMesh &m, const DState &s, const DParams &p, hipStream_t 
                           k_wisp_offers<<<kWispGrid, kBlock, 0, st>>>(m, s, p),
                           k_wisp_sums<<<kWispGrid, kBlock, 0, st>>>(m, s, p),
                           k_wisp_moves<<<kWispGrid, kBlock, 0, st>>>(m, s, p)));
-  TIMED(prof, kKLedger, (k_ledger_part<<<kLedgerParts, kBlock, 0, st>>>(m, s),
-                         k_ledger<<<1, kBlock, 0, st>>>(m, s, p, kLedgerParts)));
+  TIMED(prof, kKLedger,
+        (k_ledger<<<1, kLedgerBlock, 0, st>>>(m, s, p, (int)grid_for(m.nc, kBlock))));
 }
 
 void launch_map_alpha(const DMesh &d, double *alpha, const int32_t *off, const int32_t *cells,

@@ -510,7 +510,7 @@ vof_status vof_mesh_upload(vof_context *ctx, const vof_mesh_desc *d, vof_mesh **
   ALLOC(ds.icells, nc); ALLOC(ds.gfaces, nf); ALLOC(ds.tetvol, nf * (int64_t)dm.tpf);
   ALLOC(ds.defer, nf * (int64_t)dm.tpf);
   ALLOC(ds.stepno, 1); ALLOC(ds.work, kWNum); ALLOC(ds.cnt, kCntWords); ALLOC(ds.flags, 1); ALLOC(ds.ledger, 1);
-  ALLOC(ds.part, 256);
+  ALLOC(ds.part, (nc + 255) / 256 > 256 ? (nc + 255) / 256 : 256);
   ALLOC(m->stats_buf, 4);
 #undef ALLOC
 #define UP(dst, src, n)                                                                    \

@@ -129,7 +129,7 @@ struct DState {
   unsigned long long *cnt;  // kCntWords (kCntNum counters x kCntLanes slots)
   uint32_t *flags;      // latched status bits
   double *ledger;       // accumulated boundary phase volume
-  double *part;         // partial sums of the ledger (256)
+  double *part;         // per update block: its cells' boundary phase volume
   int32_t *stepno;      // index into dt / sc of the step being run
   double *dt;           // per-step dt (device copy)
   double *sc;           // per-step scale
