@@ -1204,9 +1204,17 @@ __global__ __launch_bounds__(kBlock) void k_face_sum(DMesh m, DState s, DParams 
   unsigned long long nleak = 0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
     const double *tv = s.tetvol + (int64_t)i * m.tpf;
+    const int f = s.gfaces[i];
     double acc = 0.0;
-    for (int k = 0; k < m.tpf; ++k) acc += tv[k];
-    int f = s.gfaces[i];
+    // five tets per point of the face: the loads of a point's five go together
+    for (int k = 0; k < m.tpf; k += 5) {
+      const double w0 = tv[k], w1 = tv[k + 1], w2 = tv[k + 2], w3 = tv[k + 3], w4 = tv[k + 4];
+      acc += w0;
+      acc += w1;
+      acc += w2;
+      acc += w3;
+      acc += w4;
+    }
     if (s.fstatus[f]) acc *= s.vscale[f];
     s.vphase[f] = acc;
     if (p.check_stencil) {
