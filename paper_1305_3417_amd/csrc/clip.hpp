@@ -238,10 +238,32 @@ VHD bool flux_tet_phase_fast(const DMesh &m, const DState &s, double dt, double 
 // closed forms; more go through the vertex-graph polytope P (only when
 // poly_ok; otherwise such a pair returns NaN and is left untouched).  With
 // check_stencil, *vcell receives six times |T ∩ C| (the coverage), else 0.
+// A pair of four planes handed back: its six-fold phase volume is
+// w * det * f4(D), D the 4 x 4 vertex distances written to row[16] (vertex by
+// vertex, plane by plane) and f4 the kept fraction of four planes.
+struct Four {
+  double *row;  // where the distances go
+  double w;
+  bool on;
+};
+VHD void dists4(const Tet &T, Pl p0, Pl p1, Pl p2, Pl p3, double *row) {
+  const Pl pl[4] = {p0, p1, p2, p3};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const D4 d = plane_dists(T, pl[j]);
+    row[j] = d.a;
+    row[4 + j] = d.b;
+    row[8 + j] = d.c;
+    row[12 + j] = d.d;
+  }
+}
+
 VHD double pair_phase6(const DMesh &m, const DState &s, const DParams &p, v3 c, const Tet &T,
                        double det, v3 lo, v3 hi, int cell, Poly &P, unsigned long long &ncap,
-                       unsigned long long &npairs, double *vcell, bool poly_ok = true) {
+                       unsigned long long &npairs, double *vcell, bool poly_ok = true,
+                       Four *four = nullptr) {
   *vcell = 0.0;
+  if (four) four->on = false;
   const int cl = s.cls[cell];
   if (cl == 0 && !p.check_stencil) return 0.0;
   double4 blo = m.bblo[cell], bhi = m.bbhi[cell];
@@ -291,6 +313,14 @@ VHD double pair_phase6(const DMesh &m, const DState &s, const DParams &p, v3 c, 
   if (!poly_ok && ((cl == 1 && ncut >= kRegPlanes) || (need_cover && ncut > kRegPlanes)))
     return NAN;  // needs the polytope: the caller comes back with poly_ok
   ++npairs;  // a (tet, cell) pair with overlapping interiors
+  // with `four` given (and no stencil check), a pair of exactly four planes
+  // is handed back for the caller to evaluate
+  if (four && !p.check_stencil && cl >= 2 && ncut == kRegPlanes) {
+    dists4(T, p0, p1, p2, p3, four->row);
+    four->w = cl == 3 ? s.alpha[cell] : 1.0;
+    four->on = true;
+    return 0.0;
+  }
   double vc =
       (need_cover && ncut <= kRegPlanes) ? vol6_planes(T, det, p0, p1, p2, p3, ncut) : -1.0;
   double vph = 0.0;
@@ -298,6 +328,12 @@ VHD double pair_phase6(const DMesh &m, const DState &s, const DParams &p, v3 c, 
     double4 pp = s.plane[cell];
     v3 nn = xyz4(pp);
     double off = pp.w - dot(nn, c);
+    if (four && !p.check_stencil && ncut == kRegPlanes - 1) {
+      dists4(T, p0, p1, p2, mkpl(nn, off), four->row);
+      four->w = 1.0;
+      four->on = true;
+      return 0.0;
+    }
     if (ncut < kRegPlanes) {
       Pl pn = mkpl(nn, off);
       p3 = sel(ncut == 3, pn, p3);

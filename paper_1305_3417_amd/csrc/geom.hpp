@@ -193,11 +193,21 @@ VHD double kept_fraction<1>(TD<1> T) {
   return tet_kept_fraction(D4{T.a.d[0], T.b.d[0], T.c.d[0], T.e.d[0]});
 }
 
+// The kept part of a tetrahedron under its first plane as at most three
+// tetrahedra: piece i is the window S_i..S_i+3 of a six-point sequence of
+// vertices and cut points, carrying the distances to the other planes, with
+// volume ratio r_i to the whole; n pieces (0 when nothing is kept).
 template <int K>
-VHD double kept_fraction(TD<K> T) {
+struct Split {
+  VD<K - 1> S0, S1, S2, S3, S4, S5;
+  double r0, r1, r2;
+  int n;
+};
+
+template <int K>
+VHD Split<K> split_first(TD<K> T) {
   const int kept = (T.a.d[0] >= 0.0) + (T.b.d[0] >= 0.0) + (T.c.d[0] >= 0.0) +
                    (T.e.d[0] >= 0.0);
-  if (kept == 0) return 0.0;
   cswap_kept(T.a, T.b);
   cswap_kept(T.c, T.e);
   cswap_kept(T.a, T.c);
@@ -219,23 +229,39 @@ VHD double kept_fraction(TD<K> T) {
   const VD<K - 1> C = cut_rest(Cfrom, Cto, tC);
   const VD<K - 1> D = cut_rest(Dfrom, T.e, tD);
   const VD<K - 1> ra = rest(T.a), rb = rest(T.b), rc = rest(T.c), re = rest(T.e);
+  Split<K> sp;
   // the sequence of piece vertices
-  const VD<K - 1> S0 = ra;
-  const VD<K - 1> S1 = sel(k3 || k4, rb, B);
-  const VD<K - 1> S2 = sel(k1, C, sel(k2, A, rc));
-  const VD<K - 1> S3 = sel(k2, rb, sel(k4, re, A));
-  const VD<K - 1> S4 = C;
-  const VD<K - 1> S5 = D;
-  const double r0 = k4 ? 1.0 : (k1 ? tB * tC * tA : (k2 ? tB * tA : tA));
-  const double r1 = k2 ? tA * tC * (1.0 - tB) : (1.0 - tA) * tC;
-  const double r2 = k2 ? tC * tD * (1.0 - tA) : (1.0 - tA) * (1.0 - tC) * tD;
-  const int n = (k1 || k4) ? 1 : 3;
+  sp.S0 = ra;
+  sp.S1 = sel(k3 || k4, rb, B);
+  sp.S2 = sel(k1, C, sel(k2, A, rc));
+  sp.S3 = sel(k2, rb, sel(k4, re, A));
+  sp.S4 = C;
+  sp.S5 = D;
+  sp.r0 = k4 ? 1.0 : (k1 ? tB * tC * tA : (k2 ? tB * tA : tA));
+  sp.r1 = k2 ? tA * tC * (1.0 - tB) : (1.0 - tA) * tC;
+  sp.r2 = k2 ? tC * tD * (1.0 - tA) : (1.0 - tA) * (1.0 - tC) * tD;
+  sp.n = kept == 0 ? 0 : ((k1 || k4) ? 1 : 3);
+  return sp;
+}
+
+// piece i of a split and its volume ratio
+template <int K>
+VHD TD<K - 1> split_piece(const Split<K> sp, int i, double &r) {
+  r = i == 0 ? sp.r0 : (i == 1 ? sp.r1 : sp.r2);
+  return TD<K - 1>{sel(i == 0, sp.S0, sel(i == 1, sp.S1, sp.S2)),
+                   sel(i == 0, sp.S1, sel(i == 1, sp.S2, sp.S3)),
+                   sel(i == 0, sp.S2, sel(i == 1, sp.S3, sp.S4)),
+                   sel(i == 0, sp.S3, sel(i == 1, sp.S4, sp.S5))};
+}
+
+template <int K>
+VHD double kept_fraction(TD<K> T) {
+  const Split<K> sp = split_first<K>(T);
   double acc = 0.0;
 #pragma unroll 1
-  for (int i = 0; i < n; ++i) {
-    TD<K - 1> P{sel(i == 0, S0, sel(i == 1, S1, S2)), sel(i == 0, S1, sel(i == 1, S2, S3)),
-                sel(i == 0, S2, sel(i == 1, S3, S4)), sel(i == 0, S3, sel(i == 1, S4, S5))};
-    const double r = i == 0 ? r0 : (i == 1 ? r1 : r2);
+  for (int i = 0; i < sp.n; ++i) {
+    double r;
+    const TD<K - 1> P = split_piece<K>(sp, i, r);
     acc += r * kept_fraction<K - 1>(P);
   }
   return acc;

@@ -1121,6 +1121,12 @@ __global__ __launch_bounds__(kClipBlock) __attribute__((amdgpu_waves_per_eu(2)))
   P.st = 1; P.cap = kPolyCap; P.nv = 0;
 
   __shared__ double red[2][kClipBlock];
+  // pairs of four planes handed back by the lanes: distances, weight, det,
+  // and the kept fraction, evaluated by three lanes each (one per piece of
+  // the first plane's split)
+  __shared__ double fd[kClipBlock][16];
+  __shared__ double fw[kClipBlock], fres[kClipBlock];
+  __shared__ int8_t fidx[kClipBlock];
   const double dt = s.dt[step], sc = s.sc[step];
   const int count = s.work[kWDeferred];
   // kGenTets tets per wavefront, kGenLanes lanes each over the tet's stencil
@@ -1157,7 +1163,43 @@ __global__ __launch_bounds__(kClipBlock) __attribute__((amdgpu_waves_per_eu(2)))
       const int e = e0 + b + sl;
       const bool act = live && e < e1;
       double v = 0.0, vc = 0.0;
-      if (act) v = pair_phase6(m, s, p, c, T, det, lo, hi, m.st[e], P, ncap, npairs, &vc, false);
+      Four four;
+      four.row = fd[lane];
+      four.on = false;
+      if (act)
+        v = pair_phase6(m, s, p, c, T, det, lo, hi, m.st[e], P, ncap, npairs, &vc, false, &four);
+      // four-plane pairs: listed in LDS, three lanes per pair
+      const unsigned long long fm = __ballot(four.on);
+      if (fm) {
+        const int slot = (int)__popcll(fm & ((1ull << lane) - 1ull));
+        if (four.on) {
+          fidx[slot] = (int8_t)lane;
+          fw[lane] = four.w;
+        }
+        __syncthreads();
+        const int nf4 = (int)__popcll(fm);
+        for (int b4 = 0; b4 < nf4; b4 += kClipBlock / 3) {
+          const int pr = b4 + lane / 3, piece = lane % 3;
+          double val = 0.0;
+          if (lane < (kClipBlock / 3) * 3 && pr < nf4) {
+            const double *q = fd[fidx[pr]];
+            const TD<4> D{{{q[0], q[1], q[2], q[3]}}, {{q[4], q[5], q[6], q[7]}},
+                          {{q[8], q[9], q[10], q[11]}}, {{q[12], q[13], q[14], q[15]}}};
+            const Split<4> sp = split_first<4>(D);
+            if (piece < sp.n) {
+              double r;
+              const TD<3> Pc = split_piece<4>(sp, piece, r);
+              val = r * kept_fraction<3>(Pc);
+            }
+          }
+          const double v1 = __shfl_down(val, 1), v2 = __shfl_down(val, 2);
+          if (piece == 0 && lane < (kClipBlock / 3) * 3 && pr < nf4)
+            fres[fidx[pr]] = (val + v1) + v2;
+        }
+        __syncthreads();
+        if (four.on) v = fw[lane] * (det * fres[lane]);
+        __syncthreads();
+      }
       const bool pend = act && v != v;
       unsigned long long pm = __ballot(pend);
       while (pm) {
