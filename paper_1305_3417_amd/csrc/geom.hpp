@@ -314,6 +314,14 @@ VHD double vol6_planes(const Tet &T, double vol6, Pl p0, Pl p1, Pl p2, Pl p3, in
   }
 }
 
+// distances of the tet's vertices to four planes (vertex by vertex)
+VHD TD<4> dist_table4(const Tet &T, Pl p0, Pl p1, Pl p2, Pl p3) {
+  const D4 d0 = plane_dists(T, p0), d1 = plane_dists(T, p1), d2 = plane_dists(T, p2),
+           d3 = plane_dists(T, p3);
+  return TD<4>{{{d0.a, d1.a, d2.a, d3.a}}, {{d0.b, d1.b, d2.b, d3.b}},
+               {{d0.c, d1.c, d2.c, d3.c}}, {{d0.d, d1.d, d2.d, d3.d}}};
+}
+
 // ---------------------------------------------------------------------------
 // simple polytope as a vertex graph
 // ---------------------------------------------------------------------------

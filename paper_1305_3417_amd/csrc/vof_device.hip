@@ -33,7 +33,7 @@ constexpr int kBlock = 256;
 constexpr int kClipBlock = 64;
 constexpr int kFastBlock = 64;   // one wave per block in the register clip
 constexpr int kFastSlots = 4;    // queued pairs of two or more planes per tet
-constexpr int kFastPlanes = 3;   // planes per pair in the register clip (more: general)
+constexpr int kFastPlanes = 4;   // planes per pair in the register clip (more: general)
 constexpr int kFastGrid = 4096;   // blocks claim face groups from a counter
 constexpr int kClaim = 2;         // face groups per claim
 constexpr int kGroupFaces = 4;    // faces per wavefront group (64 / at least 15 tets)
@@ -823,6 +823,31 @@ __device__ __forceinline__ bool staged_tet(const double (*P)[6], int n, const do
   return true;
 }
 
+// A queued pair of the register clip: the tet (from its lane's LDS row), its
+// six-fold volume, the cell, its class and its planes in mask order (then
+// the PLIC plane of an interface cell).
+__device__ __forceinline__ void queued_pair(const DMesh &m, const DState &s, const uint32_t *qpair,
+                                            const double (*tv)[kFastBlock],
+                                            const double (*fc)[3], const int32_t *ccell,
+                                            const double (*cbox)[6], int tpf, int kc, int item,
+                                            Tet &T, double &det, int &cell, int &cl, Pl &p0,
+                                            Pl &p1, Pl &p2, Pl &p3) {
+  const int l = item % kFastBlock;
+  const uint32_t qp = qpair[item];
+  const int lf = l / tpf;
+  const int u = lf * kc + (int)((qp >> 16) & 63u);
+  cell = ccell[u];
+  const v3 c = mk3(fc[lf][0], fc[lf][1], fc[lf][2]);
+  T = Tet{mk3(0, 0, 0), mk3(tv[0][l], tv[1][l], tv[2][l]), mk3(tv[3][l], tv[4][l], tv[5][l]),
+          mk3(tv[6][l], tv[7][l], tv[8][l])};
+  det = tv[9][l];
+  cl = s.cls[cell];
+  if (qp & (1u << 22))
+    pair_regs_box(cbox[u], s, c, cell, cl, qp & 0xffffu, p0, p1, p2, p3);
+  else
+    pair_regs(m, s, c, cell, cl, qp & 0xffffu, p0, p1, p2, p3);
+}
+
 // Step 5 on the register path.  A wavefront takes a group of whole geometric
 // faces (64 / tets-per-face of them; groups claimed from a counter), one flux
 // tet per lane.  First the faces' candidate cells: each face's stencil is
@@ -834,8 +859,9 @@ __device__ __forceinline__ bool staged_tet(const double (*P)[6], int n, const do
 // kFastPlanes planes are queued in LDS bins by plane count, and a tet with a
 // pair of more planes, more than kFastSlots queued pairs, or a face with more
 // than kCandPool / F candidates goes to the general kernel's queue.  Phase B
-// evaluates each bin with the plane count uniform across the wave; phase C
-// adds each tet's queued results in stencil order.
+// evaluates each bin with the plane count uniform across the wave (a pair of
+// four planes by three lanes, one per piece of its first plane's split);
+// phase C adds each tet's queued results in stencil order.
 __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_clip_fast(DMesh m, DState s, DParams p) {
   const int step = *s.stepno;
   // the group's faces: points minus the face centre and their sweeps at the
@@ -850,7 +876,9 @@ __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3)))
   // plane count - 2 (30-31)
   __shared__ uint32_t qpair[kFastBlock * kFastSlots];
   __shared__ double res[kFastBlock * kFastSlots];
-  __shared__ uint16_t bins[kFastPlanes - 1][kFastBlock * kFastSlots];
+  // queued pairs by plane count: two planes in bins[0], three from the start
+  // of bins[1] and four from its end (kFastBlock * kFastSlots pairs at most)
+  __shared__ uint16_t bins[2][kFastBlock * kFastSlots];
   __shared__ int nbin[kFastPlanes - 1];
   // candidates of face fi at fi * (kCandPool / F) + position
   __shared__ int32_t ccell[kCandPool];
@@ -1059,34 +1087,50 @@ __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3)))
       for (int j = 0; j < nq; ++j) {
         int b = (int)(qpair[j * kFastBlock + lane] >> 30);
         int pos = atomicAdd(&nbin[b], 1);
-        bins[b][pos] = (uint16_t)(j * kFastBlock + lane);
+        if (b == 2) pos = kFastBlock * kFastSlots - 1 - pos;
+        bins[b < 2 ? b : 1][pos] = (uint16_t)(j * kFastBlock + lane);
       }
       npairs += np;
     }
     __syncthreads();
-    // phase B
-    for (int b = 0; b < kFastPlanes - 1; ++b) {
+    // phase B: pairs of two and three planes one per lane
+    for (int b = 0; b < 2; ++b) {
       const int cnt = nbin[b];
       for (int t = lane; t < cnt; t += kFastBlock) {
         const int item = bins[b][t];
-        const int l = item % kFastBlock;
-        const uint32_t qp = qpair[item];
-        const int lf = l / tpf;
-        const int u = lf * kc + (int)((qp >> 16) & 63u);
-        const int cell = ccell[u];
-        const v3 c = mk3(fc[lf][0], fc[lf][1], fc[lf][2]);
-        const Tet T{mk3(0, 0, 0), mk3(tv[0][l], tv[1][l], tv[2][l]),
-                    mk3(tv[3][l], tv[4][l], tv[5][l]), mk3(tv[6][l], tv[7][l], tv[8][l])};
-        const double det = tv[9][l];
-        const int cl = s.cls[cell];
+        Tet T;
+        double det;
+        int cell, cl;
         Pl p0, p1, p2, p3;
-        if (qp & (1u << 22))
-          pair_regs_box(cbox[u], s, c, cell, cl, qp & 0xffffu, p0, p1, p2, p3);
-        else
-          pair_regs(m, s, c, cell, cl, qp & 0xffffu, p0, p1, p2, p3);
-        res[item] =
-            class_weight(s, cell, cl) * vol6_planes<kFastPlanes>(T, det, p0, p1, p2, p3, b + 2);
+        queued_pair(m, s, qpair, tv, fc, ccell, cbox, tpf, kc, item, T, det, cell, cl, p0, p1,
+                    p2, p3);
+        res[item] = class_weight(s, cell, cl) * vol6_planes<3>(T, det, p0, p1, p2, p3, b + 2);
       }
+    }
+    // pairs of four planes: three lanes each, one per piece of the first
+    // plane's split, the pieces added in the closed form's order
+    for (int t0 = 0; t0 < nbin[2]; t0 += kFastBlock / 3) {
+      const int t = t0 + lane / 3, piece = lane - 3 * (lane / 3);
+      const bool on = lane < (kFastBlock / 3) * 3 && t < nbin[2];
+      int item = 0;
+      double val = 0.0, w = 0.0, det = 0.0;
+      if (on) {
+        item = bins[1][kFastBlock * kFastSlots - 1 - t];
+        Tet T;
+        int cell, cl;
+        Pl p0, p1, p2, p3;
+        queued_pair(m, s, qpair, tv, fc, ccell, cbox, tpf, kc, item, T, det, cell, cl, p0, p1,
+                    p2, p3);
+        const Split<4> sp = split_first<4>(dist_table4(T, p0, p1, p2, p3));
+        if (piece < sp.n) {
+          double r;
+          const TD<3> pc = split_piece<4>(sp, piece, r);
+          val = r * kept_fraction<3>(pc);
+        }
+        w = class_weight(s, cell, cl);
+      }
+      const double v1 = __shfl_down(val, 1), v2 = __shfl_down(val, 2);
+      if (on && piece == 0) res[item] = w * (det * ((val + v1) + v2));
     }
     __syncthreads();
     // phase C
