@@ -1058,8 +1058,17 @@ __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3)))
                                : pair_cuts_box(m, c, T, lo, hi, mk3(bb[0], bb[1], bb[2]),
                                                mk3(bb[3], bb[4], bb[5]), cell, mask);
           if (ncut < 0) continue;
-          const int npl = ncut + (cl == 1);
           ++np;
+          // next to cell planes, the PLIC plane of an interface cell counts
+          // only where it crosses the tet: with the tet wholly on its kept
+          // side it drops out, wholly beyond it the pair holds no phase
+          bool plic = cl == 1;
+          if (plic && ncut > 0) {
+            const D4 dp = plane_dists(T, plic_plane_at(s, cell, c));
+            if (dmax(dmax(dp.a, dp.b), dmax(dp.c, dp.d)) <= 0.0) continue;
+            if (dmin(dmin(dp.a, dp.b), dmin(dp.c, dp.d)) >= 0.0) plic = false;
+          }
+          const int npl = ncut + (plic ? 1 : 0);
           if (npl <= 1) {
             double fr = 1.0;
             if (npl == 1) {
