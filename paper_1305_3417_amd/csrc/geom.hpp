@@ -314,12 +314,33 @@ VHD double vol6_planes(const Tet &T, double vol6, Pl p0, Pl p1, Pl p2, Pl p3, in
   }
 }
 
-// distances of the tet's vertices to four planes (vertex by vertex)
-VHD TD<4> dist_table4(const Tet &T, Pl p0, Pl p1, Pl p2, Pl p3) {
-  const D4 d0 = plane_dists(T, p0), d1 = plane_dists(T, p1), d2 = plane_dists(T, p2),
-           d3 = plane_dists(T, p3);
-  return TD<4>{{{d0.a, d1.a, d2.a, d3.a}}, {{d0.b, d1.b, d2.b, d3.b}},
-               {{d0.c, d1.c, d2.c, d3.c}}, {{d0.d, d1.d, d2.d, d3.d}}};
+// distances of the tet's vertices to the first K of four planes (vertex by
+// vertex)
+template <int K>
+VHD TD<K> dist_table(const Tet &T, Pl p0, Pl p1, Pl p2, Pl p3) {
+  const Pl pl[4] = {p0, p1, p2, p3};
+  TD<K> D;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const D4 d = plane_dists(T, pl[k]);
+    D.a.d[k] = d.a;
+    D.b.d[k] = d.b;
+    D.c.d[k] = d.c;
+    D.e.d[k] = d.d;
+  }
+  return D;
+}
+
+// Term i of kept_fraction<K>(D): piece i of the first plane's split, its
+// volume ratio times the fraction of it the other planes keep (0 past the
+// split's pieces).  kept_fraction<K> adds the terms for i = 0, 1, 2 in order.
+template <int K>
+VHD double split_term(const TD<K> &D, int i) {
+  const Split<K> sp = split_first<K>(D);
+  if (i >= sp.n) return 0.0;
+  double r;
+  const TD<K - 1> pc = split_piece<K>(sp, i, r);
+  return r * kept_fraction<K - 1>(pc);
 }
 
 // ---------------------------------------------------------------------------

@@ -848,6 +848,38 @@ __device__ __forceinline__ void queued_pair(const DMesh &m, const DState &s, con
     pair_regs(m, s, c, cell, cl, qp & 0xffffu, p0, p1, p2, p3);
 }
 
+// A phase-B bin of pairs of K planes, three lanes per pair (one per term of
+// the first plane's split; 21 pairs per pass).  The bin's items are bin[t],
+// or bin[kFastBlock * kFastSlots - 1 - t] for a bin filled from the end.
+template <int K>
+__device__ __forceinline__ void three_lane_bin(const DMesh &m, const DState &s,
+                                               const uint32_t *qpair,
+                                               const double (*tv)[kFastBlock],
+                                               const double (*fc)[3], const int32_t *ccell,
+                                               const double (*cbox)[6], int tpf, int kc,
+                                               const uint16_t *bin, int cnt, bool from_end,
+                                               double *res) {
+  const int lane = threadIdx.x;
+  for (int t0 = 0; t0 < cnt; t0 += kFastBlock / 3) {
+    const int t = t0 + lane / 3, term = lane - 3 * (lane / 3);
+    const bool on = lane < (kFastBlock / 3) * 3 && t < cnt;
+    int item = 0;
+    double val = 0.0, w = 0.0, det = 0.0;
+    if (on) {
+      item = bin[from_end ? kFastBlock * kFastSlots - 1 - t : t];
+      Tet T;
+      int cell, cl;
+      Pl p0, p1, p2, p3;
+      queued_pair(m, s, qpair, tv, fc, ccell, cbox, tpf, kc, item, T, det, cell, cl, p0, p1, p2,
+                  p3);
+      val = split_term<K>(dist_table<K>(T, p0, p1, p2, p3), term);
+      w = class_weight(s, cell, cl);
+    }
+    const double v1 = __shfl_down(val, 1), v2 = __shfl_down(val, 2);
+    if (on && term == 0) res[item] = w * (det * ((val + v1) + v2));
+  }
+}
+
 // Step 5 on the register path.  A wavefront takes a group of whole geometric
 // faces (64 / tets-per-face of them; groups claimed from a counter), one flux
 // tet per lane.  First the faces' candidate cells: each face's stencil is
@@ -859,9 +891,9 @@ __device__ __forceinline__ void queued_pair(const DMesh &m, const DState &s, con
 // kFastPlanes planes are queued in LDS bins by plane count, and a tet with a
 // pair of more planes, more than kFastSlots queued pairs, or a face with more
 // than kCandPool / F candidates goes to the general kernel's queue.  Phase B
-// evaluates each bin with the plane count uniform across the wave (a pair of
-// four planes by three lanes, one per piece of its first plane's split);
-// phase C adds each tet's queued results in stencil order.
+// evaluates each bin with the plane count uniform across the wave, three
+// lanes per pair (one per piece of its first plane's split); phase C adds
+// each tet's queued results in stencil order.
 __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_clip_fast(DMesh m, DState s, DParams p) {
   const int step = *s.stepno;
   // the group's faces: points minus the face centre and their sweeps at the
@@ -1102,45 +1134,13 @@ __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3)))
       npairs += np;
     }
     __syncthreads();
-    // phase B: pairs of two and three planes one per lane
-    for (int b = 0; b < 2; ++b) {
-      const int cnt = nbin[b];
-      for (int t = lane; t < cnt; t += kFastBlock) {
-        const int item = bins[b][t];
-        Tet T;
-        double det;
-        int cell, cl;
-        Pl p0, p1, p2, p3;
-        queued_pair(m, s, qpair, tv, fc, ccell, cbox, tpf, kc, item, T, det, cell, cl, p0, p1,
-                    p2, p3);
-        res[item] = class_weight(s, cell, cl) * vol6_planes<3>(T, det, p0, p1, p2, p3, b + 2);
-      }
-    }
-    // pairs of four planes: three lanes each, one per piece of the first
-    // plane's split, the pieces added in the closed form's order
-    for (int t0 = 0; t0 < nbin[2]; t0 += kFastBlock / 3) {
-      const int t = t0 + lane / 3, piece = lane - 3 * (lane / 3);
-      const bool on = lane < (kFastBlock / 3) * 3 && t < nbin[2];
-      int item = 0;
-      double val = 0.0, w = 0.0, det = 0.0;
-      if (on) {
-        item = bins[1][kFastBlock * kFastSlots - 1 - t];
-        Tet T;
-        int cell, cl;
-        Pl p0, p1, p2, p3;
-        queued_pair(m, s, qpair, tv, fc, ccell, cbox, tpf, kc, item, T, det, cell, cl, p0, p1,
-                    p2, p3);
-        const Split<4> sp = split_first<4>(dist_table4(T, p0, p1, p2, p3));
-        if (piece < sp.n) {
-          double r;
-          const TD<3> pc = split_piece<4>(sp, piece, r);
-          val = r * kept_fraction<3>(pc);
-        }
-        w = class_weight(s, cell, cl);
-      }
-      const double v1 = __shfl_down(val, 1), v2 = __shfl_down(val, 2);
-      if (on && piece == 0) res[item] = w * (det * ((val + v1) + v2));
-    }
+    // phase B, one bin at a time (the plane count uniform across the wave),
+    // three lanes per pair.  Every bin takes the same way whatever its size:
+    // which faces share a group follows the order of the geometric-face list,
+    // which is not fixed from run to run.
+    three_lane_bin<2>(m, s, qpair, tv, fc, ccell, cbox, tpf, kc, bins[0], nbin[0], false, res);
+    three_lane_bin<3>(m, s, qpair, tv, fc, ccell, cbox, tpf, kc, bins[1], nbin[1], false, res);
+    three_lane_bin<4>(m, s, qpair, tv, fc, ccell, cbox, tpf, kc, bins[1], nbin[2], true, res);
     __syncthreads();
     // phase C
     if (live) {
