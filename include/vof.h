@@ -273,7 +273,11 @@ double vof_selftest_tet_clip(const double *tet, int32_t n_planes, const double *
  * (tetrahedron, cell) pair bounded by at most four planes (Section 2.1: the
  * tetrahedron's kept part under each plane as one or three tetrahedra, the
  * last plane by the closed-form kept fraction).  Same arguments and result
- * as vof_selftest_tet_clip; NaN for n_planes > 4 or a bad argument. */
+ * as vof_selftest_tet_clip; NaN for n_planes > 4 or a bad argument.  For two
+ * to four planes the result is the sum of the first plane's split terms as
+ * the clip kernels add them (three lanes per pair), and NaN when it differs
+ * from the one-lane recursion by more than 1e-14 of the tetrahedron's
+ * volume. */
 double vof_selftest_tet_clip_closed(const double *tet, int32_t n_planes, const double *planes);
 
 #ifdef __cplusplus

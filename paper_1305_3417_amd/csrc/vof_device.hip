@@ -1781,7 +1781,18 @@ double host_tet_clip_closed(const double *tet, int n_planes, const double *plane
     v3 n = mk3(planes[4 * k], planes[4 * k + 1], planes[4 * k + 2]);
     pl[k] = mkpl(n, planes[4 * k + 3] - dot(n, a));
   }
-  return vol6_planes(T, det3(T.b, T.c, T.d), pl[0], pl[1], pl[2], pl[3], n_planes) / 6.0;
+  const double det = det3(T.b, T.c, T.d);
+  const double one = vol6_planes(T, det, pl[0], pl[1], pl[2], pl[3], n_planes);
+  if (n_planes < 2) return one / 6.0;
+  // the split terms as the three lanes of a queued pair add them
+  double t[3];
+  for (int i = 0; i < 3; ++i)
+    t[i] = n_planes == 2   ? split_term<2>(dist_table<2>(T, pl[0], pl[1], pl[2], pl[3]), i)
+           : n_planes == 3 ? split_term<3>(dist_table<3>(T, pl[0], pl[1], pl[2], pl[3]), i)
+                           : split_term<4>(dist_table<4>(T, pl[0], pl[1], pl[2], pl[3]), i);
+  const double three = det * ((t[0] + t[1]) + t[2]);
+  if (!(fabs(three - one) <= 1e-14 * det)) return NAN;
+  return three / 6.0;
 }
 
 }  // namespace vof
