@@ -1718,8 +1718,9 @@ void launch_step(const DMesh &m, const DState &s, const DParams &p, hipStream_t 
     TIMED(prof, kKPlane, (k_plane<<<kPlaneGrid, kBlock, 0, st>>>(m, s, p)));
   }
   // persistent-style grid: a few blocks per CU, grid-stride over the faces
+  // (4096 blocks leave room for the plane kernel beside it)
   unsigned gf = grid_for(m.nf, kBlock);
-  gf = gf < 8192 ? gf : 8192;
+  gf = gf < 4096 ? gf : 4096;
   gf = (gf + kXcds - 1) / kXcds * kXcds;
   if (m.maxn <= 3)
     TIMED(prof, kKFlux, (k_flux<3><<<gf, kBlock, 0, st>>>(m, s, p)));
