@@ -30,8 +30,8 @@ METRIC = "face-fluxes/s at 1e-12 rel vol err; batched/served vs plain, p50/p99 l
 PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector
 PEAK_HBM_GBS = 8000.0        # MI355X HBM3E
 
-# Algorithmic work per unit (kernels and measurement): counted
-# from the arithmetic each kernel must do, not from instructions issued.
+# Algorithmic work per unit, counted from the arithmetic each kernel must do,
+# not from the instructions it issues.
 FLUX_FLOPS_PER_QUAD_FACE = 400.0     # sweep, exact volume cubic, branch, ~2 Newton steps
 FLUX_BYTES_PER_FACE = 52.0           # CSR 20, F0 8, lambda 8, V_alpha 8, bytes 3, points ~5
 CLIP_FLOPS_PER_PAIR = 1000.0         # plane tests, clips and volume of one (tet, cell) pair
