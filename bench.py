@@ -166,10 +166,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--n", type=int, default=128, help="mesh is n^3 hexahedra")
-    ap.add_argument("--workload", choices=["deform3d", "shear3d"], default="deform3d",
-                    help="deform3d (eq. 4.6, fixed dt; the headline case) or shear3d "
-                         "(eq. 4.5, adaptive Courant dt)")
+    ap.add_argument("--n", type=int, default=None,
+                    help="mesh is n^3 hexahedra (default 128), or n^3 cubes of six jittered "
+                         "tetrahedra for tets (default 80)")
+    ap.add_argument("--workload", choices=["deform3d", "shear3d", "tets"], default="deform3d",
+                    help="deform3d (eq. 4.6, fixed dt; the headline case), shear3d "
+                         "(eq. 4.5, adaptive Courant dt) or tets (slotted sphere rotating "
+                         "on jittered tetrahedra)")
     ap.add_argument("--band-wisps", action="store_true",
                     help="run the step with the narrow band and wisp redistribution "
                          "(Section 2.3) after the update")
@@ -203,10 +206,12 @@ def main():
                           "launches": 3}), flush=True)
         return
     WORKLOAD[0] = args.workload
+    if args.n is None:
+        args.n = 80 if args.workload == "tets" else 128
     K, Wm = args.steps, args.warmup
     P = min(K, 20)  # profiled steps after the timed region
     log(f"[bench] generating {args.workload} {args.n}^3")
-    make = W.deform3d if args.workload == "deform3d" else W.shear3d
+    make = {"deform3d": W.deform3d, "shear3d": W.shear3d, "tets": W.rotate_tets}[args.workload]
     w = make(args.n, steps=Wm + K + P + 1 + CPU_SAMPLE_MAX_STEPS)
     ctx = vof.vof_context_create(0)
     log("[bench] uploading mesh")
@@ -293,12 +298,16 @@ def main():
         "metric": METRIC, "value": value, "unit": "face-fluxes/s", "n_gpus": 1, "steps": K,
         "warmup": Wm, "ms_per_step": elapsed * 1e3 / K, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": (f"deform3d hex {args.n}^3 (eq. 4.6, T=3, sphere r=0.15 at "
-                                f"(0.35,0.35,0.35), Co 0.5, dt=1/{4 * args.n}), steps "
-                                f"{Wm}..{Wm + K - 1}" if args.workload == "deform3d" else
-                                f"shear3d hex {args.n}^3 (eq. 4.5, T=3, u_max=1, R=0.5, sphere "
-                                f"r=0.15 at (0.5,0.75,0.25), adaptive Courant dt at Co 0.5), "
-                                f"steps {Wm}..{Wm + K - 1}"),
+        "config": {"workload": {
+                       "deform3d": f"deform3d hex {args.n}^3 (eq. 4.6, T=3, sphere r=0.15 at "
+                                   f"(0.35,0.35,0.35), Co 0.5, dt=1/{4 * args.n})",
+                       "shear3d": f"shear3d hex {args.n}^3 (eq. 4.5, T=3, u_max=1, R=0.5, "
+                                  f"sphere r=0.15 at (0.5,0.75,0.25), adaptive Courant dt at "
+                                  f"Co 0.5)",
+                       "tets": f"tets {args.n}^3 cubes x 6 jittered Kuhn tetrahedra (slotted "
+                               f"sphere r=0.15 at (0.5,0.75,0.5), rotation about z, "
+                               f"omega=2 pi, dt=1/{9 * args.n})"}[args.workload]
+                               + f", steps {Wm}..{Wm + K - 1}",
                    "cells": int(w.mesh.n_cells), "faces": int(w.mesh.n_faces),
                    "band_wisps": bool(args.band_wisps),
                    "parallelism": "single GPU"},

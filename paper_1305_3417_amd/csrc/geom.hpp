@@ -314,11 +314,11 @@ VHD double vol6_planes(const Tet &T, double vol6, Pl p0, Pl p1, Pl p2, Pl p3, in
   }
 }
 
-// distances of the tet's vertices to the first K of four planes (vertex by
+// distances of the tet's vertices to the first K of five planes (vertex by
 // vertex)
 template <int K>
-VHD TD<K> dist_table(const Tet &T, Pl p0, Pl p1, Pl p2, Pl p3) {
-  const Pl pl[4] = {p0, p1, p2, p3};
+VHD TD<K> dist_table(const Tet &T, Pl p0, Pl p1, Pl p2, Pl p3, Pl p4 = Pl{0, 0, 0, 0}) {
+  const Pl pl[5] = {p0, p1, p2, p3, p4};
   TD<K> D;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
@@ -341,6 +341,18 @@ VHD double split_term(const TD<K> &D, int i) {
   double r;
   const TD<K - 1> pc = split_piece<K>(sp, i, r);
   return r * kept_fraction<K - 1>(pc);
+}
+
+// Term (i, j) two levels down: piece i of the first plane's split (its ratio
+// in *ri, 0 past the split's pieces) and term j of that piece's own split.
+// kept_fraction<K>(D) is the sum over i of r_i times the sum over j.
+template <int K>
+VHD double split_term2(const TD<K> &D, int i, int j, double &ri) {
+  const Split<K> sp = split_first<K>(D);
+  ri = 0.0;
+  if (i >= sp.n) return 0.0;
+  const TD<K - 1> pc = split_piece<K>(sp, i, ri);
+  return split_term<K - 1>(pc, j);
 }
 
 // ---------------------------------------------------------------------------

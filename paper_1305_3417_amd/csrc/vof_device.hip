@@ -32,12 +32,20 @@ constexpr int kWave = 64;     // wavefront width
 constexpr int kBlock = 256;
 constexpr int kClipBlock = 64;
 constexpr int kFastBlock = 64;   // one wave per block in the register clip
-constexpr int kFastSlots = 4;    // queued pairs of two or more planes per tet
+// register clip configurations: queued pairs of two or more planes per tet,
+// candidate cells of a face group kept in LDS (CAND / F per face), and
+// whether the candidates' bounds are kept in LDS (box cells need them).
+// Quad faces (a hex face's stencil: 18 cells) take the first; triangle faces
+// of tetrahedral meshes (58 stencil cells, about 7 overlapping cells per
+// flux tet) the second, at two waves per SIMD.
+constexpr int kFastSlots = 4;
+constexpr int kTriSlots = 12, kTriCand = 192;
 constexpr int kFastPlanes = 4;   // planes per pair in the register clip (more: general)
+constexpr int kTriPlanes = 5;    // the same for triangle faces
 constexpr int kFastGrid = 4096;   // blocks claim face groups from a counter
 constexpr int kClaim = 2;         // face groups per claim
 constexpr int kGroupFaces = 4;    // faces per wavefront group (64 / at least 15 tets)
-constexpr int kCandPool = 48;     // candidate cells of a face group kept in LDS (48 / F per face)
+constexpr int kCandPool = 48;
 constexpr int kFacePool = 12;     // staged points of a face group: F * max points <= 64 / 5
 constexpr int kPlaneGrid = 2048;  // blocks of four waves, one interface cell per wave
 static_assert(kMaxCellPlanes * kMaxFacePoints <= 128, "two fan tetrahedra per lane");
@@ -850,7 +858,7 @@ __device__ __forceinline__ void queued_pair(const DMesh &m, const DState &s, con
 
 // A phase-B bin of pairs of K planes, three lanes per pair (one per term of
 // the first plane's split; 21 pairs per pass).  The bin's items are bin[t],
-// or bin[kFastBlock * kFastSlots - 1 - t] for a bin filled from the end.
+// or bin[cap - 1 - t] for a bin filled from the end.
 template <int K>
 __device__ __forceinline__ void three_lane_bin(const DMesh &m, const DState &s,
                                                const uint32_t *qpair,
@@ -858,7 +866,7 @@ __device__ __forceinline__ void three_lane_bin(const DMesh &m, const DState &s,
                                                const double (*fc)[3], const int32_t *ccell,
                                                const double (*cbox)[6], int tpf, int kc,
                                                const uint16_t *bin, int cnt, bool from_end,
-                                               double *res) {
+                                               int cap, double *res) {
   const int lane = threadIdx.x;
   for (int t0 = 0; t0 < cnt; t0 += kFastBlock / 3) {
     const int t = t0 + lane / 3, term = lane - 3 * (lane / 3);
@@ -866,7 +874,7 @@ __device__ __forceinline__ void three_lane_bin(const DMesh &m, const DState &s,
     int item = 0;
     double val = 0.0, w = 0.0, det = 0.0;
     if (on) {
-      item = bin[from_end ? kFastBlock * kFastSlots - 1 - t : t];
+      item = bin[from_end ? cap - 1 - t : t];
       Tet T;
       int cell, cl;
       Pl p0, p1, p2, p3;
@@ -880,6 +888,56 @@ __device__ __forceinline__ void three_lane_bin(const DMesh &m, const DState &s,
   }
 }
 
+// A phase-B bin of pairs of five planes of cells that are not boxes, nine
+// lanes per pair (term j of piece i of the first two planes' splits; seven
+// pairs per pass), filled from the end of bin (capacity cap).  The terms are
+// combined as the recursion adds them: the three of a piece, then the pieces
+// weighted by their ratios.
+__device__ __forceinline__ void nine_lane_bin(const DMesh &m, const DState &s,
+                                              const uint32_t *qpair,
+                                              const double (*tv)[kFastBlock],
+                                              const double (*fc)[3], const int32_t *ccell,
+                                              int tpf, int kc, const uint16_t *bin, int cnt,
+                                              int cap, double *res) {
+  const int lane = threadIdx.x;
+  for (int t0 = 0; t0 < cnt; t0 += kFastBlock / 9) {
+    const int t = t0 + lane / 9, sub = lane - 9 * (lane / 9);
+    const int i = sub / 3, j = sub - 3 * i;
+    const bool on = lane < (kFastBlock / 9) * 9 && t < cnt;
+    int item = 0;
+    double val = 0.0, ri = 0.0, w = 0.0, det = 0.0;
+    if (on) {
+      item = bin[cap - 1 - t];
+      const int l = item % kFastBlock;
+      const uint32_t qp = qpair[item];
+      const int lf = l / tpf;
+      const int cell = ccell[lf * kc + (int)((qp >> 16) & 63u)];
+      const v3 c = mk3(fc[lf][0], fc[lf][1], fc[lf][2]);
+      const Tet T{mk3(0, 0, 0), mk3(tv[0][l], tv[1][l], tv[2][l]),
+                  mk3(tv[3][l], tv[4][l], tv[5][l]), mk3(tv[6][l], tv[7][l], tv[8][l])};
+      det = tv[9][l];
+      const int cl = s.cls[cell];
+      // the four cutting planes in mask order, then the PLIC plane
+      const Pl pl = plic_plane_at(s, cell, c);
+      const int q0 = m.cf_off[cell];
+      uint32_t mm = qp & 0xffffu;
+      const Pl a = cell_plane_at(m, q0 + __builtin_ctz(mm), c);
+      mm &= mm - 1;
+      const Pl b = cell_plane_at(m, q0 + __builtin_ctz(mm), c);
+      mm &= mm - 1;
+      const Pl d = cell_plane_at(m, q0 + __builtin_ctz(mm), c);
+      mm &= mm - 1;
+      const Pl e = cell_plane_at(m, q0 + __builtin_ctz(mm), c);
+      val = split_term2<5>(dist_table<5>(T, a, b, d, e, pl), i, j, ri);
+      w = class_weight(s, cell, cl);
+    }
+    const double f = (val + __shfl_down(val, 1)) + __shfl_down(val, 2);
+    const double ti = ri * f;
+    const double tot = (ti + __shfl_down(ti, 3)) + __shfl_down(ti, 6);
+    if (on && sub == 0) res[item] = w * (det * tot);
+  }
+}
+
 // Step 5 on the register path.  A wavefront takes a group of whole geometric
 // faces (64 / tets-per-face of them; groups claimed from a counter), one flux
 // tet per lane.  First the faces' candidate cells: each face's stencil is
@@ -888,13 +946,17 @@ __device__ __forceinline__ void three_lane_bin(const DMesh &m, const DState &s,
 // their class and box.  Phase A: every tet classifies its face's candidates
 // by a mask of the cell planes that cut it; pairs bounded by at most one
 // plane are summed at once (a single kept fraction); pairs with two to
-// kFastPlanes planes are queued in LDS bins by plane count, and a tet with a
-// pair of more planes, more than kFastSlots queued pairs, or a face with more
-// than kCandPool / F candidates goes to the general kernel's queue.  Phase B
+// MAXPL planes are queued in LDS bins by plane count, and a tet with a
+// pair of more planes, more than SLOTS queued pairs, or a face with more
+// than CAND / F candidates goes to the general kernel's queue.  Phase B
 // evaluates each bin with the plane count uniform across the wave, three
-// lanes per pair (one per piece of its first plane's split); phase C adds
-// each tet's queued results in stencil order.
-__global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_clip_fast(DMesh m, DState s, DParams p) {
+// lanes per pair (one per piece of its first plane's split; nine for five
+// planes, one per piece of the first two splits); phase C adds each tet's
+// queued results in stencil order.
+template <int SLOTS, int CAND, bool BOXES, int MAXPL>
+__global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(BOXES ? 3 : 2)))
+void k_clip_fast(DMesh m, DState s, DParams p) {
+  static_assert(MAXPL <= 4 || !BOXES, "five-plane pairs only for cells that are not boxes");
   const int step = *s.stepno;
   // the group's faces: points minus the face centre and their sweeps at the
   // corrected lam, the mean sweep, the point count and the face centre (the
@@ -906,18 +968,20 @@ __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3)))
   __shared__ double tv[10][kFastBlock];
   // queued pair: plane mask (bits 0-15), candidate (16-21), box cell (22),
   // plane count - 2 (30-31)
-  __shared__ uint32_t qpair[kFastBlock * kFastSlots];
-  __shared__ double res[kFastBlock * kFastSlots];
-  // queued pairs by plane count: two planes in bins[0], three from the start
-  // of bins[1] and four from its end (kFastBlock * kFastSlots pairs at most)
-  __shared__ uint16_t bins[2][kFastBlock * kFastSlots];
-  __shared__ int nbin[kFastPlanes - 1];
-  // candidates of face fi at fi * (kCandPool / F) + position
-  __shared__ int32_t ccell[kCandPool];
-  __shared__ int8_t ccls[kCandPool];  // class | 8 for a box cell
+  constexpr int kCap = kFastBlock * SLOTS;
+  __shared__ uint32_t qpair[kCap];
+  __shared__ double res[kCap];
+  // queued pairs by plane count: two planes from the start of bins[0], five
+  // from its end, three from the start of bins[1] and four from its end (kCap
+  // pairs at most)
+  __shared__ uint16_t bins[2][kCap];
+  __shared__ int nbin[4];
+  // candidates of face fi at fi * (CAND / F) + position
+  __shared__ int32_t ccell[CAND];
+  __shared__ int8_t ccls[CAND];  // class | 8 for a box cell
   // candidate bounds (lo x y z, hi x y z): the box test, and the planes of a
   // box cell
-  __shared__ double cbox[kCandPool][6];
+  __shared__ double cbox[BOXES ? CAND : 1][6];
   __shared__ double fbox[kGroupFaces][6];
   __shared__ int cnum[kGroupFaces];
   __shared__ int group;
@@ -927,7 +991,8 @@ __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3)))
   const int count = s.work[kWGeometric];
   const int tpf = m.tpf;
   const int F = kFastBlock / tpf;  // faces per group, 1..kGroupFaces
-  const int kc = kCandPool / F;    // candidates kept per face
+  // candidates kept per face (the candidate field of a queued pair has 6 bits)
+  const int kc = CAND / F < 63 ? CAND / F : 63;
   const int ngroups = (count + F - 1) / F;
   unsigned long long npairs = 0;
   // Groups are taken kClaim at a time: the first kClaim by block index, the
@@ -947,7 +1012,7 @@ __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3)))
       }
       --left;
     }
-    if (lane < kFastPlanes - 1) nbin[lane] = 0;
+    if (lane < 4) nbin[lane] = 0;
     // flux polyhedron boxes, one lane per face (points and their swept
     // images), and the face staged in LDS.  Unpadded: a cell that only
     // touches the box meets the polyhedron in a sliver of zero width (or of
@@ -1040,13 +1105,15 @@ __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3)))
         if (keep && pos < kc) {
           const int u = cf * kc + pos;
           ccell[u] = cell;
-          ccls[u] = (int8_t)(cl | (m.isbox[cell] ? 8 : 0));
-          cbox[u][0] = blo.x;
-          cbox[u][1] = blo.y;
-          cbox[u][2] = blo.z;
-          cbox[u][3] = bhi.x;
-          cbox[u][4] = bhi.y;
-          cbox[u][5] = bhi.z;
+          ccls[u] = (int8_t)(cl | (BOXES && m.isbox[cell] ? 8 : 0));
+          if (BOXES) {
+            cbox[u][0] = blo.x;
+            cbox[u][1] = blo.y;
+            cbox[u][2] = blo.z;
+            cbox[u][3] = bhi.x;
+            cbox[u][4] = bhi.y;
+            cbox[u][5] = bhi.z;
+          }
         }
         cnt += (int)__popcll(bal);
       }
@@ -1083,12 +1150,15 @@ __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3)))
           const int cell = ccell[u];
           const int cb = ccls[u];
           const int cl = cb & 7;
-          const bool box = cb & 8;
-          const double *bb = cbox[u];
+          const bool box = BOXES && (cb & 8);
+          const double *bb = cbox[BOXES ? u : 0];
           uint32_t mask;
-          const int ncut = box ? box_cuts(bb, c, T, mask)
-                               : pair_cuts_box(m, c, T, lo, hi, mk3(bb[0], bb[1], bb[2]),
-                                               mk3(bb[3], bb[4], bb[5]), cell, mask);
+          int ncut;
+          if (!BOXES) ncut = pair_cuts(m, c, T, lo, hi, cell, mask);
+          else if (box) ncut = box_cuts(bb, c, T, mask);
+          else
+            ncut = pair_cuts_box(m, c, T, lo, hi, mk3(bb[0], bb[1], bb[2]),
+                                 mk3(bb[3], bb[4], bb[5]), cell, mask);
           if (ncut < 0) continue;
           ++np;
           // next to cell planes, the PLIC plane of an interface cell counts
@@ -1111,7 +1181,7 @@ __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3)))
               fr = tet_kept_fraction(plane_dists(T, pl));
             }
             acc += class_weight(s, cell, cl) * det * fr;
-          } else if (npl <= kFastPlanes && nq < kFastSlots) {
+          } else if (npl <= MAXPL && nq < SLOTS) {
             qpair[nq * kFastBlock + lane] = mask | ((uint32_t)ci << 16) | (box ? 1u << 22 : 0u) |
                                             ((uint32_t)(npl - 2) << 30);
             ++nq;
@@ -1128,8 +1198,8 @@ __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3)))
       for (int j = 0; j < nq; ++j) {
         int b = (int)(qpair[j * kFastBlock + lane] >> 30);
         int pos = atomicAdd(&nbin[b], 1);
-        if (b == 2) pos = kFastBlock * kFastSlots - 1 - pos;
-        bins[b < 2 ? b : 1][pos] = (uint16_t)(j * kFastBlock + lane);
+        if (b >= 2) pos = kCap - 1 - pos;
+        bins[b == 0 || b == 3 ? 0 : 1][pos] = (uint16_t)(j * kFastBlock + lane);
       }
       npairs += np;
     }
@@ -1138,9 +1208,14 @@ __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(3)))
     // three lanes per pair.  Every bin takes the same way whatever its size:
     // which faces share a group follows the order of the geometric-face list,
     // which is not fixed from run to run.
-    three_lane_bin<2>(m, s, qpair, tv, fc, ccell, cbox, tpf, kc, bins[0], nbin[0], false, res);
-    three_lane_bin<3>(m, s, qpair, tv, fc, ccell, cbox, tpf, kc, bins[1], nbin[1], false, res);
-    three_lane_bin<4>(m, s, qpair, tv, fc, ccell, cbox, tpf, kc, bins[1], nbin[2], true, res);
+    three_lane_bin<2>(m, s, qpair, tv, fc, ccell, cbox, tpf, kc, bins[0], nbin[0], false, kCap,
+                      res);
+    three_lane_bin<3>(m, s, qpair, tv, fc, ccell, cbox, tpf, kc, bins[1], nbin[1], false, kCap,
+                      res);
+    three_lane_bin<4>(m, s, qpair, tv, fc, ccell, cbox, tpf, kc, bins[1], nbin[2], true, kCap,
+                      res);
+    if constexpr (MAXPL >= 5)
+      nine_lane_bin(m, s, qpair, tv, fc, ccell, tpf, kc, bins[0], nbin[3], kCap, res);
     __syncthreads();
     // phase C
     if (live) {
@@ -1729,7 +1804,14 @@ void launch_step(const DMesh &m, const DState &s, const DParams &p, hipStream_t 
   else
     TIMED(prof, kKFlux, (k_flux<kMaxFacePoints><<<gf, kBlock, 0, st>>>(m, s, p)));
   if (split) (void)hipStreamWaitEvent(st, fork->join, 0);
-  TIMED(prof, kKClip, (k_clip_fast<<<kFastGrid, kFastBlock, 0, st>>>(m, s, p)));
+  if (m.maxn <= 3)
+    TIMED(prof, kKClip,
+          (k_clip_fast<kTriSlots, kTriCand, false, kTriPlanes>
+           <<<kFastGrid, kFastBlock, 0, st>>>(m, s, p)));
+  else
+    TIMED(prof, kKClip,
+          (k_clip_fast<kFastSlots, kCandPool, true, kFastPlanes>
+           <<<kFastGrid, kFastBlock, 0, st>>>(m, s, p)));
   TIMED(prof, kKClipGeneral, (k_clip_general<<<4096, kClipBlock, 0, st>>>(m, s, p)));
   TIMED(prof, kKFaceSum, (k_face_sum<<<1024, kBlock, 0, st>>>(m, s, p)));
   TIMED(prof, kKUpdate, (k_update<<<grid_for(m.nc, kBlock), kBlock, 0, st>>>(m, s, p)));
