@@ -240,11 +240,13 @@ VHD bool flux_tet_phase_fast(const DMesh &m, const DState &s, double dt, double 
 // check_stencil, *vcell receives six times |T ∩ C| (the coverage), else 0.
 // A pair of four planes handed back: its six-fold phase volume is
 // w * det * f4(D), D the 4 x 4 vertex distances written to row[16] (vertex by
-// vertex, plane by plane) and f4 the kept fraction of four planes.
+// vertex, plane by plane) and f4 the kept fraction of four planes.  With
+// `five`, an interface cell's four cutting planes and its PLIC plane: D is
+// 4 x 5, in row[20], and f5 the kept fraction of five planes.
 struct Four {
   double *row;  // where the distances go
   double w;
-  bool on;
+  bool on, five;
 };
 VHD void dists4(const Tet &T, Pl p0, Pl p1, Pl p2, Pl p3, double *row) {
   const Pl pl[4] = {p0, p1, p2, p3};
@@ -258,12 +260,24 @@ VHD void dists4(const Tet &T, Pl p0, Pl p1, Pl p2, Pl p3, double *row) {
   }
 }
 
+VHD void dists5(const Tet &T, Pl p0, Pl p1, Pl p2, Pl p3, Pl p4, double *row) {
+  const Pl pl[5] = {p0, p1, p2, p3, p4};
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+    const D4 d = plane_dists(T, pl[j]);
+    row[j] = d.a;
+    row[5 + j] = d.b;
+    row[10 + j] = d.c;
+    row[15 + j] = d.d;
+  }
+}
+
 VHD double pair_phase6(const DMesh &m, const DState &s, const DParams &p, v3 c, const Tet &T,
                        double det, v3 lo, v3 hi, int cell, Poly &P, unsigned long long &ncap,
                        unsigned long long &npairs, double *vcell, bool poly_ok = true,
                        Four *four = nullptr) {
   *vcell = 0.0;
-  if (four) four->on = false;
+  if (four) four->on = four->five = false;
   const int cl = s.cls[cell];
   if (cl == 0 && !p.check_stencil) return 0.0;
   double4 blo = m.bblo[cell], bhi = m.bbhi[cell];
@@ -310,6 +324,23 @@ VHD double pair_phase6(const DMesh &m, const DState &s, const DParams &p, v3 c, 
     }
   }
   const bool need_cover = p.check_stencil || cl >= 2;
+  if (four && !p.check_stencil && cl == 1 && ncut == kRegPlanes) {
+    // four cutting planes and the PLIC plane: that plane counts only where it
+    // crosses the tet (wholly kept: four planes; wholly removed: no phase)
+    ++npairs;
+    const Pl pl = plic_plane_at(s, cell, c);
+    const D4 dp = plane_dists(T, pl);
+    if (dmax(dmax(dp.a, dp.b), dmax(dp.c, dp.d)) <= 0.0) return 0.0;
+    if (dmin(dmin(dp.a, dp.b), dmin(dp.c, dp.d)) >= 0.0) {
+      dists4(T, p0, p1, p2, p3, four->row);
+    } else {
+      dists5(T, p0, p1, p2, p3, pl, four->row);
+      four->five = true;
+    }
+    four->w = 1.0;
+    four->on = true;
+    return 0.0;
+  }
   if (!poly_ok && ((cl == 1 && ncut >= kRegPlanes) || (need_cover && ncut > kRegPlanes)))
     return NAN;  // needs the polytope: the caller comes back with poly_ok
   ++npairs;  // a (tet, cell) pair with overlapping interiors

@@ -1252,9 +1252,9 @@ __global__ __launch_bounds__(kClipBlock) __attribute__((amdgpu_waves_per_eu(2)))
   // pairs of four planes handed back by the lanes: distances, weight, det,
   // and the kept fraction, evaluated by three lanes each (one per piece of
   // the first plane's split)
-  __shared__ double fd[kClipBlock][16];
+  __shared__ double fd[kClipBlock][20];
   __shared__ double fw[kClipBlock], fres[kClipBlock];
-  __shared__ int8_t fidx[kClipBlock];
+  __shared__ int8_t fidx[kClipBlock], fidx5[kClipBlock];
   const double dt = s.dt[step], sc = s.sc[step];
   const int count = s.work[kWDeferred];
   // kGenTets tets per wavefront, kGenLanes lanes each over the tet's stencil
@@ -1296,16 +1296,20 @@ __global__ __launch_bounds__(kClipBlock) __attribute__((amdgpu_waves_per_eu(2)))
       four.on = false;
       if (act)
         v = pair_phase6(m, s, p, c, T, det, lo, hi, m.st[e], P, ncap, npairs, &vc, false, &four);
-      // four-plane pairs: listed in LDS, three lanes per pair
+      // pairs of four planes listed in LDS, three lanes per pair; pairs of
+      // five, nine lanes per pair (one per piece of the first two splits)
       const unsigned long long fm = __ballot(four.on);
       if (fm) {
-        const int slot = (int)__popcll(fm & ((1ull << lane) - 1ull));
+        const unsigned long long m4 = __ballot(four.on && !four.five);
+        const unsigned long long m5 = fm & ~m4;
+        const unsigned long long below = (1ull << lane) - 1ull;
         if (four.on) {
-          fidx[slot] = (int8_t)lane;
+          if (four.five) fidx5[__popcll(m5 & below)] = (int8_t)lane;
+          else fidx[__popcll(m4 & below)] = (int8_t)lane;
           fw[lane] = four.w;
         }
         __syncthreads();
-        const int nf4 = (int)__popcll(fm);
+        const int nf4 = (int)__popcll(m4);
         for (int b4 = 0; b4 < nf4; b4 += kClipBlock / 3) {
           const int pr = b4 + lane / 3, piece = lane % 3;
           double val = 0.0;
@@ -1323,6 +1327,23 @@ __global__ __launch_bounds__(kClipBlock) __attribute__((amdgpu_waves_per_eu(2)))
           const double v1 = __shfl_down(val, 1), v2 = __shfl_down(val, 2);
           if (piece == 0 && lane < (kClipBlock / 3) * 3 && pr < nf4)
             fres[fidx[pr]] = (val + v1) + v2;
+        }
+        const int nf5 = (int)__popcll(m5);
+        for (int b5 = 0; b5 < nf5; b5 += kClipBlock / 9) {
+          const int pr = b5 + lane / 9, sub = lane % 9;
+          const bool on5 = lane < (kClipBlock / 9) * 9 && pr < nf5;
+          double val = 0.0, ri = 0.0;
+          if (on5) {
+            const double *q = fd[fidx5[pr]];
+            const TD<5> D{{{q[0], q[1], q[2], q[3], q[4]}}, {{q[5], q[6], q[7], q[8], q[9]}},
+                          {{q[10], q[11], q[12], q[13], q[14]}},
+                          {{q[15], q[16], q[17], q[18], q[19]}}};
+            val = split_term2<5>(D, sub / 3, sub % 3, ri);
+          }
+          const double f = (val + __shfl_down(val, 1)) + __shfl_down(val, 2);
+          const double ti = ri * f;
+          const double tot = (ti + __shfl_down(ti, 3)) + __shfl_down(ti, 6);
+          if (on5 && sub == 0) fres[fidx5[pr]] = tot;
         }
         __syncthreads();
         if (four.on) v = fw[lane] * (det * fres[lane]);
