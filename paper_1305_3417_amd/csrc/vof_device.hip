@@ -947,8 +947,10 @@ __device__ __forceinline__ void nine_lane_bin(const DMesh &m, const DState &s,
 // by a mask of the cell planes that cut it; pairs bounded by at most one
 // plane are summed at once (a single kept fraction); pairs with two to
 // MAXPL planes are queued in LDS bins by plane count, and a tet with a
-// pair of more planes, more than SLOTS queued pairs, or a face with more
-// than CAND / F candidates goes to the general kernel's queue.  Phase B
+// pair of more planes or a face with more than CAND / F candidates goes to
+// the general kernel's queue; a tet with more than SLOTS queued pairs stops
+// at the first that finds its queue full and resumes there in another round
+// of the three phases.  Phase B
 // evaluates each bin with the plane count uniform across the wave, three
 // lanes per pair (one per piece of its first plane's split; nine for five
 // planes, one per piece of the first two splits); phase C adds each tet's
@@ -1127,10 +1129,7 @@ void k_clip_fast(DMesh m, DState s, DParams p) {
     const int64_t idx = (int64_t)slot * tpf + k;
     bool defer = false, live = false;
     double acc = 0.0, sgn = 1.0;
-    int nq = 0;
-    unsigned long long np = 0;
     if (active) {
-      const v3 c = mk3(fc[fi][0], fc[fi][1], fc[fi][2]);
       v3 t1, t2, t3;
       double det;
       live = !p.check_stencil &&
@@ -1141,11 +1140,30 @@ void k_clip_fast(DMesh m, DState s, DParams p) {
         tv[3][lane] = t2.x; tv[4][lane] = t2.y; tv[5][lane] = t2.z;
         tv[6][lane] = t3.x; tv[7][lane] = t3.y; tv[8][lane] = t3.z;
         tv[9][lane] = det;
+      }
+    }
+    if (defer) live = false;
+    // Phases A to C in rounds: a tet whose queue is full stops at that pair
+    // and resumes there in the next round, once its queued pairs are added.
+    bool todo = live;  // candidates left to visit
+    int ci0 = 0;
+    unsigned long long np = 0;
+    for (;;) {
+      int nq = 0;
+      if (todo) {
+        // the tet from its LDS row (kept there for phase B anyway)
+        const v3 c = mk3(fc[fi][0], fc[fi][1], fc[fi][2]);
+        const v3 t1 = mk3(tv[0][lane], tv[1][lane], tv[2][lane]);
+        const v3 t2 = mk3(tv[3][lane], tv[4][lane], tv[5][lane]);
+        const v3 t3 = mk3(tv[6][lane], tv[7][lane], tv[8][lane]);
+        const double det = tv[9][lane];
         const Tet T{mk3(0, 0, 0), t1, t2, t3};
         v3 lo, hi;
         tet_bbox(c, t1, t2, t3, lo, hi);
         const int nc = cnum[fi];
-        for (int ci = 0; ci < nc; ++ci) {
+        bool paused = false;
+        int ci = ci0;
+        for (; ci < nc; ++ci) {
           const int u = fi * kc + ci;
           const int cell = ccell[u];
           const int cb = ccls[u];
@@ -1181,45 +1199,55 @@ void k_clip_fast(DMesh m, DState s, DParams p) {
               fr = tet_kept_fraction(plane_dists(T, pl));
             }
             acc += class_weight(s, cell, cl) * det * fr;
-          } else if (npl <= MAXPL && nq < SLOTS) {
+          } else if (npl > MAXPL) {
+            defer = true;
+            break;
+          } else if (nq == SLOTS) {
+            --np;  // counted again when the next round takes it
+            paused = true;
+            break;
+          } else {
             qpair[nq * kFastBlock + lane] = mask | ((uint32_t)ci << 16) | (box ? 1u << 22 : 0u) |
                                             ((uint32_t)(npl - 2) << 30);
             ++nq;
-          } else {
-            defer = true;
-            break;
           }
           if (ncut == 0) break;  // the tet lies inside this cell
         }
+        if (defer) live = false;
+        todo = live && paused;
+        ci0 = ci;
+        if (live) {
+          for (int j = 0; j < nq; ++j) {
+            int b = (int)(qpair[j * kFastBlock + lane] >> 30);
+            int pos = atomicAdd(&nbin[b], 1);
+            if (b >= 2) pos = kCap - 1 - pos;
+            bins[b == 0 || b == 3 ? 0 : 1][pos] = (uint16_t)(j * kFastBlock + lane);
+          }
+        }
       }
+      __syncthreads();
+      // phase B, one bin at a time (the plane count uniform across the wave),
+      // three lanes per pair.  Every bin takes the same way whatever its size:
+      // which faces share a group follows the order of the geometric-face
+      // list, which is not fixed from run to run.
+      three_lane_bin<2>(m, s, qpair, tv, fc, ccell, cbox, tpf, kc, bins[0], nbin[0], false,
+                        kCap, res);
+      three_lane_bin<3>(m, s, qpair, tv, fc, ccell, cbox, tpf, kc, bins[1], nbin[1], false,
+                        kCap, res);
+      three_lane_bin<4>(m, s, qpair, tv, fc, ccell, cbox, tpf, kc, bins[1], nbin[2], true,
+                        kCap, res);
+      if constexpr (MAXPL >= 5)
+        nine_lane_bin(m, s, qpair, tv, fc, ccell, tpf, kc, bins[0], nbin[3], kCap, res);
+      __syncthreads();
+      // phase C
+      if (live)
+        for (int j = 0; j < nq; ++j) acc += res[j * kFastBlock + lane];
+      if (!__ballot(todo)) break;
+      if (lane < 4) nbin[lane] = 0;
+      __syncthreads();
     }
-    if (defer) live = false;
     if (live) {
-      for (int j = 0; j < nq; ++j) {
-        int b = (int)(qpair[j * kFastBlock + lane] >> 30);
-        int pos = atomicAdd(&nbin[b], 1);
-        if (b >= 2) pos = kCap - 1 - pos;
-        bins[b == 0 || b == 3 ? 0 : 1][pos] = (uint16_t)(j * kFastBlock + lane);
-      }
       npairs += np;
-    }
-    __syncthreads();
-    // phase B, one bin at a time (the plane count uniform across the wave),
-    // three lanes per pair.  Every bin takes the same way whatever its size:
-    // which faces share a group follows the order of the geometric-face list,
-    // which is not fixed from run to run.
-    three_lane_bin<2>(m, s, qpair, tv, fc, ccell, cbox, tpf, kc, bins[0], nbin[0], false, kCap,
-                      res);
-    three_lane_bin<3>(m, s, qpair, tv, fc, ccell, cbox, tpf, kc, bins[1], nbin[1], false, kCap,
-                      res);
-    three_lane_bin<4>(m, s, qpair, tv, fc, ccell, cbox, tpf, kc, bins[1], nbin[2], true, kCap,
-                      res);
-    if constexpr (MAXPL >= 5)
-      nine_lane_bin(m, s, qpair, tv, fc, ccell, tpf, kc, bins[0], nbin[3], kCap, res);
-    __syncthreads();
-    // phase C
-    if (live) {
-      for (int j = 0; j < nq; ++j) acc += res[j * kFastBlock + lane];
       s.tetvol[idx] = sgn * acc / 6.0;
     } else if (active && !defer) {
       s.tetvol[idx] = 0.0;
