@@ -105,6 +105,30 @@ __device__ __forceinline__ int block_append(int32_t *counter, bool pred) {
   return pred ? pos : -1;
 }
 
+// Append n items per thread to a list (one atomic per block); returns the
+// thread's first position.  Must be reached by every thread of the block.
+__device__ __forceinline__ int block_append_n(int32_t *counter, int n) {
+  __shared__ int wsum[kBlock / 64];
+  __shared__ int bbase;
+  const int lane = lane_id(), w = (int)(threadIdx.x >> 6);
+  int v = n;  // inclusive scan over the wavefront
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(v, o);
+    if (lane >= o) v += t;
+  }
+  if (lane == 63) wsum[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int i = 0; i < kBlock / 64; ++i) { int c = wsum[i]; wsum[i] = tot; tot += c; }
+    bbase = tot ? atomicAdd(counter, tot) : 0;
+  }
+  __syncthreads();
+  const int pos = bbase + wsum[w] + v - n;
+  __syncthreads();  // wsum / bbase are reused by the next call
+  return pos;
+}
+
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   return v;
@@ -288,18 +312,30 @@ __global__ void k_reset(DState s) {
   if (threadIdx.x < kWNum) s.work[threadIdx.x] = 0;
 }
 
+// kClassCells cells per thread, strided by the grid (coalesced), and the
+// thread's interface cells appended together: one atomic per block of
+// kBlock * kClassCells cells on the list's counter.
+constexpr int kClassCells = 8;
 __global__ __launch_bounds__(kBlock) void k_cell_class(DMesh m, DState s, DParams p) {
-  int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  bool iface = false;
-  if (c < m.nc) {
-    double a = s.alpha[c];
-    int8_t cl = a <= p.eps ? 0 : (a >= 1.0 - p.eps ? 2 : 1);
-    s.cls[c] = cl;
-    iface = cl == 1;
-    if (p.band) s.inexact[c] = cl != 1 && a != 0.0 && a != 1.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t c0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  unsigned im = 0;  // bit i: cell c0 + i stride is an interface cell
+#pragma unroll
+  for (int i = 0; i < kClassCells; ++i) {
+    const int64_t c = c0 + i * stride;
+    if (c < m.nc) {
+      const double a = s.alpha[c];
+      const int8_t cl = a <= p.eps ? 0 : (a >= 1.0 - p.eps ? 2 : 1);
+      s.cls[c] = cl;
+      if (p.band) s.inexact[c] = cl != 1 && a != 0.0 && a != 1.0;
+      im |= (cl == 1 ? 1u : 0u) << i;
+    }
   }
-  int slot = block_append(&s.work[kWInterface], iface);
-  if (iface) s.icells[slot] = (int32_t)c;
+  const int pos = block_append_n(&s.work[kWInterface], __builtin_popcount(im));
+#pragma unroll
+  for (int i = 0; i < kClassCells; ++i)
+    if ((im >> i) & 1u)
+      s.icells[pos + __builtin_popcount(im & ((1u << i) - 1u))] = (int32_t)(c0 + i * stride);
 }
 
 // Point mask: bit 1 empty, 2 full, 4 interface among the point-cells; with
@@ -1790,7 +1826,7 @@ void launch_point_velocity(const DMesh &m, const double *U0c, double4 *U, double
 
 static void launch_reconstruct_impl(const DMesh &m, const DState &s, const DParams &p,
                                     hipStream_t st) {
-  k_cell_class<<<grid_for(m.nc, kBlock), kBlock, 0, st>>>(m, s, p);
+  k_cell_class<<<grid_for(m.nc, kBlock * kClassCells), kBlock, 0, st>>>(m, s, p);
   k_point_prep<<<grid_for(m.np, kBlock), kBlock, 0, st>>>(m, s, p);
   k_plane<<<kPlaneGrid, kBlock, 0, st>>>(m, s, p);
 }
@@ -1831,7 +1867,8 @@ void Prof::end(int kid) {
 void launch_step(const DMesh &m, const DState &s, const DParams &p, hipStream_t st, Prof *prof,
                  const Fork *fork) {
   const bool split = fork && !prof;
-  TIMED(prof, kKCellClass, (k_cell_class<<<grid_for(m.nc, kBlock), kBlock, 0, st>>>(m, s, p)));
+  TIMED(prof, kKCellClass,
+        (k_cell_class<<<grid_for(m.nc, kBlock * kClassCells), kBlock, 0, st>>>(m, s, p)));
   TIMED(prof, kKPointPrep, (k_point_prep<<<grid_for(m.np, kBlock), kBlock, 0, st>>>(m, s, p)));
   if (split) {
     (void)hipEventRecord(fork->fork, st);
