@@ -983,15 +983,17 @@ __device__ __forceinline__ void nine_lane_bin(const DMesh &m, const DState &s,
 // by a mask of the cell planes that cut it; pairs bounded by at most one
 // plane are summed at once (a single kept fraction); pairs with two to
 // MAXPL planes are queued in LDS bins by plane count, and a tet with a
-// pair of more planes or a face with more than CAND / F candidates goes to
-// the general kernel's queue; a tet with more than SLOTS queued pairs stops
+// pair of more planes (or, without CHUNKED, of a face with more than CAND / F
+// candidates; with it the candidates come in chunks of that many, the next
+// once the group's tets are through the current one) goes to the general
+// kernel's queue; a tet with more than SLOTS queued pairs stops
 // at the first that finds its queue full and resumes there in another round
 // of the three phases.  Phase B
 // evaluates each bin with the plane count uniform across the wave, three
 // lanes per pair (one per piece of its first plane's split; nine for five
 // planes, one per piece of the first two splits); phase C adds each tet's
 // queued results in stencil order.
-template <int SLOTS, int CAND, bool BOXES, int MAXPL>
+template <int SLOTS, int CAND, bool BOXES, int MAXPL, bool CHUNKED>
 __global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(BOXES ? 3 : 2)))
 void k_clip_fast(DMesh m, DState s, DParams p) {
   static_assert(MAXPL <= 4 || !BOXES, "five-plane pairs only for cells that are not boxes");
@@ -1105,59 +1107,6 @@ void k_clip_fast(DMesh m, DState s, DParams p) {
       }
     }
     __syncthreads();
-    // candidate cells of the group's faces, kFastBlock / F lanes per face, in
-    // stencil order
-    {
-      const int L = kFastBlock / F;
-      const int cf = lane / L, e_in = lane - cf * L;
-      const int slot = g * F + cf;
-      const bool mine = cf < F && slot < count;
-      int w = 0, nst = 0;
-      if (mine) {
-        const int f = s.gfaces[slot];
-        w = m.st_off[f];
-        nst = m.st_off[f + 1] - w;
-      }
-      int most = nst;  // the largest stencil of the group sets the trip count
-      for (int o = 32; o > 0; o >>= 1) most = max(most, __shfl_xor(most, o));
-      const unsigned long long seg =
-          !mine ? 0ull : (L == kFastBlock ? ~0ull : (((1ull << L) - 1ull) << (cf * L)));
-      int cnt = 0;
-      for (int e0 = 0; e0 < most; e0 += L) {
-        const int e = e0 + e_in;
-        bool keep = false;
-        int cell = 0, cl = 0;
-        double4 blo = make_double4(0, 0, 0, 0), bhi = blo;
-        if (mine && e < nst) {
-          cell = m.st[w + e];
-          cl = s.cls[cell];
-          if (cl != 0) {
-            blo = m.bblo[cell];
-            bhi = m.bbhi[cell];
-            keep = !(fbox[cf][3] <= blo.x || fbox[cf][0] >= bhi.x || fbox[cf][4] <= blo.y ||
-                     fbox[cf][1] >= bhi.y || fbox[cf][5] <= blo.z || fbox[cf][2] >= bhi.z);
-          }
-        }
-        const unsigned long long bal = __ballot(keep) & seg;
-        const int pos = cnt + (int)__popcll(bal & ((1ull << lane) - 1ull));
-        if (keep && pos < kc) {
-          const int u = cf * kc + pos;
-          ccell[u] = cell;
-          ccls[u] = (int8_t)(cl | (BOXES && m.isbox[cell] ? 8 : 0));
-          if (BOXES) {
-            cbox[u][0] = blo.x;
-            cbox[u][1] = blo.y;
-            cbox[u][2] = blo.z;
-            cbox[u][3] = bhi.x;
-            cbox[u][4] = bhi.y;
-            cbox[u][5] = bhi.z;
-          }
-        }
-        cnt += (int)__popcll(bal);
-      }
-      if (mine && e_in == 0) cnum[cf] = cnt;
-    }
-    __syncthreads();
     // phase A
     const int fi = lane / tpf, k = lane - fi * tpf;
     const int slot = g * F + fi;
@@ -1170,7 +1119,7 @@ void k_clip_fast(DMesh m, DState s, DParams p) {
       double det;
       live = !p.check_stencil &&
              staged_tet(&fpt[fi * m.maxn], fn[fi], fcq[fi], k, t1, t2, t3, det, sgn);
-      defer = p.check_stencil || cnum[fi] > kc;
+      defer = p.check_stencil;
       if (live && !defer) {
         tv[0][lane] = t1.x; tv[1][lane] = t1.y; tv[2][lane] = t1.z;
         tv[3][lane] = t2.x; tv[4][lane] = t2.y; tv[5][lane] = t2.z;
@@ -1179,106 +1128,181 @@ void k_clip_fast(DMesh m, DState s, DParams p) {
       }
     }
     if (defer) live = false;
-    // Phases A to C in rounds: a tet whose queue is full stops at that pair
-    // and resumes there in the next round, once its queued pairs are added.
-    bool todo = live;  // candidates left to visit
+    bool todo = live;   // candidates of the current chunk left to visit
+    bool more = false;  // candidates past the current chunk left to visit
     int ci0 = 0;
     unsigned long long np = 0;
-    for (;;) {
-      int nq = 0;
-      if (todo) {
-        // the tet from its LDS row (kept there for phase B anyway)
-        const v3 c = mk3(fc[fi][0], fc[fi][1], fc[fi][2]);
-        const v3 t1 = mk3(tv[0][lane], tv[1][lane], tv[2][lane]);
-        const v3 t2 = mk3(tv[3][lane], tv[4][lane], tv[5][lane]);
-        const v3 t3 = mk3(tv[6][lane], tv[7][lane], tv[8][lane]);
-        const double det = tv[9][lane];
-        const Tet T{mk3(0, 0, 0), t1, t2, t3};
-        v3 lo, hi;
-        tet_bbox(c, t1, t2, t3, lo, hi);
-        const int nc = cnum[fi];
-        bool paused = false;
-        int ci = ci0;
-        for (; ci < nc; ++ci) {
-          const int u = fi * kc + ci;
-          const int cell = ccell[u];
-          const int cb = ccls[u];
-          const int cl = cb & 7;
-          const bool box = BOXES && (cb & 8);
-          const double *bb = cbox[BOXES ? u : 0];
-          uint32_t mask;
-          int ncut;
-          if (!BOXES) ncut = pair_cuts(m, c, T, lo, hi, cell, mask);
-          else if (box) ncut = box_cuts(bb, c, T, mask);
-          else
-            ncut = pair_cuts_box(m, c, T, lo, hi, mk3(bb[0], bb[1], bb[2]),
-                                 mk3(bb[3], bb[4], bb[5]), cell, mask);
-          if (ncut < 0) continue;
-          ++np;
-          // next to cell planes, the PLIC plane of an interface cell counts
-          // only where it crosses the tet: with the tet wholly on its kept
-          // side it drops out, wholly beyond it the pair holds no phase
-          bool plic = cl == 1;
-          if (plic && ncut > 0) {
-            const D4 dp = plane_dists(T, plic_plane_at(s, cell, c));
-            if (dmax(dmax(dp.a, dp.b), dmax(dp.c, dp.d)) <= 0.0) continue;
-            if (dmin(dmin(dp.a, dp.b), dmin(dp.c, dp.d)) >= 0.0) plic = false;
-          }
-          const int npl = ncut + (plic ? 1 : 0);
-          if (npl <= 1) {
-            double fr = 1.0;
-            if (npl == 1) {
-              const int q = __builtin_ctz(mask);
-              const Pl pl = !ncut ? plic_plane_at(s, cell, c)
-                                  : (box ? box_plane(bb, q, c)
-                                         : cell_plane_at(m, m.cf_off[cell] + q, c));
-              fr = tet_kept_fraction(plane_dists(T, pl));
+    // candidate cells of the group's faces in chunks of kc per face (in
+    // stencil order, kFastBlock / F lanes per face): a face with more takes
+    // the next chunk once its tets are through the current one
+    for (int skip = 0;; skip += kc) {
+      {
+        const int L = kFastBlock / F;
+        const int cf = lane / L, e_in = lane - cf * L;
+        const int slot = g * F + cf;
+        const bool mine = cf < F && slot < count;
+        int w = 0, nst = 0;
+        if (mine) {
+          const int f = s.gfaces[slot];
+          w = m.st_off[f];
+          nst = m.st_off[f + 1] - w;
+        }
+        int most = nst;  // the largest stencil of the group sets the trip count
+        for (int o = 32; o > 0; o >>= 1) most = max(most, __shfl_xor(most, o));
+        const unsigned long long seg =
+            !mine ? 0ull : (L == kFastBlock ? ~0ull : (((1ull << L) - 1ull) << (cf * L)));
+        int cnt = 0;
+        for (int e0 = 0; e0 < most; e0 += L) {
+          const int e = e0 + e_in;
+          bool keep = false;
+          int cell = 0, cl = 0;
+          double4 blo = make_double4(0, 0, 0, 0), bhi = blo;
+          if (mine && e < nst) {
+            cell = m.st[w + e];
+            cl = s.cls[cell];
+            if (cl != 0) {
+              blo = m.bblo[cell];
+              bhi = m.bbhi[cell];
+              keep = !(fbox[cf][3] <= blo.x || fbox[cf][0] >= bhi.x || fbox[cf][4] <= blo.y ||
+                       fbox[cf][1] >= bhi.y || fbox[cf][5] <= blo.z || fbox[cf][2] >= bhi.z);
             }
-            acc += class_weight(s, cell, cl) * det * fr;
-          } else if (npl > MAXPL) {
-            defer = true;
-            break;
-          } else if (nq == SLOTS) {
-            --np;  // counted again when the next round takes it
-            paused = true;
-            break;
-          } else {
-            qpair[nq * kFastBlock + lane] = mask | ((uint32_t)ci << 16) | (box ? 1u << 22 : 0u) |
-                                            ((uint32_t)(npl - 2) << 30);
-            ++nq;
           }
-          if (ncut == 0) break;  // the tet lies inside this cell
-        }
-        if (defer) live = false;
-        todo = live && paused;
-        ci0 = ci;
-        if (live) {
-          for (int j = 0; j < nq; ++j) {
-            int b = (int)(qpair[j * kFastBlock + lane] >> 30);
-            int pos = atomicAdd(&nbin[b], 1);
-            if (b >= 2) pos = kCap - 1 - pos;
-            bins[b == 0 || b == 3 ? 0 : 1][pos] = (uint16_t)(j * kFastBlock + lane);
+          const unsigned long long bal = __ballot(keep) & seg;
+          const int pos = cnt + (int)__popcll(bal & ((1ull << lane) - 1ull));
+          if (keep && pos >= skip && pos < skip + kc) {
+            const int u = cf * kc + (pos - skip);
+            ccell[u] = cell;
+            ccls[u] = (int8_t)(cl | (BOXES && m.isbox[cell] ? 8 : 0));
+            if (BOXES) {
+              cbox[u][0] = blo.x;
+              cbox[u][1] = blo.y;
+              cbox[u][2] = blo.z;
+              cbox[u][3] = bhi.x;
+              cbox[u][4] = bhi.y;
+              cbox[u][5] = bhi.z;
+            }
           }
+          cnt += (int)__popcll(bal);
         }
+        if (mine && e_in == 0) cnum[cf] = cnt;
       }
       __syncthreads();
-      // phase B, one bin at a time (the plane count uniform across the wave),
-      // three lanes per pair.  Every bin takes the same way whatever its size:
-      // which faces share a group follows the order of the geometric-face
-      // list, which is not fixed from run to run.
-      three_lane_bin<2>(m, s, qpair, tv, fc, ccell, cbox, tpf, kc, bins[0], nbin[0], false,
-                        kCap, res);
-      three_lane_bin<3>(m, s, qpair, tv, fc, ccell, cbox, tpf, kc, bins[1], nbin[1], false,
-                        kCap, res);
-      three_lane_bin<4>(m, s, qpair, tv, fc, ccell, cbox, tpf, kc, bins[1], nbin[2], true,
-                        kCap, res);
-      if constexpr (MAXPL >= 5)
-        nine_lane_bin(m, s, qpair, tv, fc, ccell, tpf, kc, bins[0], nbin[3], kCap, res);
-      __syncthreads();
-      // phase C
-      if (live)
-        for (int j = 0; j < nq; ++j) acc += res[j * kFastBlock + lane];
-      if (!__ballot(todo)) break;
+      // without chunks, a face with more candidates than its share goes to
+      // the general kernel
+      if constexpr (!CHUNKED) {
+        if (todo && cnum[fi] > kc) {
+          defer = true;
+          live = todo = false;
+        }
+      }
+      // Phases A to C in rounds: a tet whose queue is full stops at that pair
+      // and resumes there in the next round, once its queued pairs are added.
+      for (;;) {
+        int nq = 0;
+        if (todo) {
+          // the tet from its LDS row (kept there for phase B anyway)
+          const v3 c = mk3(fc[fi][0], fc[fi][1], fc[fi][2]);
+          const v3 t1 = mk3(tv[0][lane], tv[1][lane], tv[2][lane]);
+          const v3 t2 = mk3(tv[3][lane], tv[4][lane], tv[5][lane]);
+          const v3 t3 = mk3(tv[6][lane], tv[7][lane], tv[8][lane]);
+          const double det = tv[9][lane];
+          const Tet T{mk3(0, 0, 0), t1, t2, t3};
+          v3 lo, hi;
+          tet_bbox(c, t1, t2, t3, lo, hi);
+          const int nc = min(cnum[fi] - skip, kc);
+          bool paused = false, inside = false;
+          int ci = ci0;
+          for (; ci < nc; ++ci) {
+            const int u = fi * kc + ci;
+            const int cell = ccell[u];
+            const int cb = ccls[u];
+            const int cl = cb & 7;
+            const bool box = BOXES && (cb & 8);
+            const double *bb = cbox[BOXES ? u : 0];
+            uint32_t mask;
+            int ncut;
+            if (!BOXES) ncut = pair_cuts(m, c, T, lo, hi, cell, mask);
+            else if (box) ncut = box_cuts(bb, c, T, mask);
+            else
+              ncut = pair_cuts_box(m, c, T, lo, hi, mk3(bb[0], bb[1], bb[2]),
+                                   mk3(bb[3], bb[4], bb[5]), cell, mask);
+            if (ncut < 0) continue;
+            ++np;
+            // next to cell planes, the PLIC plane of an interface cell counts
+            // only where it crosses the tet: with the tet wholly on its kept
+            // side it drops out, wholly beyond it the pair holds no phase
+            bool plic = cl == 1;
+            if (plic && ncut > 0) {
+              const D4 dp = plane_dists(T, plic_plane_at(s, cell, c));
+              if (dmax(dmax(dp.a, dp.b), dmax(dp.c, dp.d)) <= 0.0) continue;
+              if (dmin(dmin(dp.a, dp.b), dmin(dp.c, dp.d)) >= 0.0) plic = false;
+            }
+            const int npl = ncut + (plic ? 1 : 0);
+            if (npl <= 1) {
+              double fr = 1.0;
+              if (npl == 1) {
+                const int q = __builtin_ctz(mask);
+                const Pl pl = !ncut ? plic_plane_at(s, cell, c)
+                                    : (box ? box_plane(bb, q, c)
+                                           : cell_plane_at(m, m.cf_off[cell] + q, c));
+                fr = tet_kept_fraction(plane_dists(T, pl));
+              }
+              acc += class_weight(s, cell, cl) * det * fr;
+            } else if (npl > MAXPL) {
+              defer = true;
+              break;
+            } else if (nq == SLOTS) {
+              --np;  // counted again when the next round takes it
+              paused = true;
+              break;
+            } else {
+              qpair[nq * kFastBlock + lane] = mask | ((uint32_t)ci << 16) | (box ? 1u << 22 : 0u) |
+                                              ((uint32_t)(npl - 2) << 30);
+              ++nq;
+            }
+            if (ncut == 0) {  // the tet lies inside this cell
+              inside = true;
+              break;
+            }
+          }
+          if (defer) live = false;
+          todo = live && paused;
+          more = CHUNKED && live && !paused && !inside && cnum[fi] > skip + kc;
+          ci0 = todo ? ci : 0;
+          if (live) {
+            for (int j = 0; j < nq; ++j) {
+              int b = (int)(qpair[j * kFastBlock + lane] >> 30);
+              int pos = atomicAdd(&nbin[b], 1);
+              if (b >= 2) pos = kCap - 1 - pos;
+              bins[b == 0 || b == 3 ? 0 : 1][pos] = (uint16_t)(j * kFastBlock + lane);
+            }
+          }
+        }
+        __syncthreads();
+        // phase B, one bin at a time (the plane count uniform across the wave),
+        // three lanes per pair.  Every bin takes the same way whatever its size:
+        // which faces share a group follows the order of the geometric-face
+        // list, which is not fixed from run to run.
+        three_lane_bin<2>(m, s, qpair, tv, fc, ccell, cbox, tpf, kc, bins[0], nbin[0], false,
+                          kCap, res);
+        three_lane_bin<3>(m, s, qpair, tv, fc, ccell, cbox, tpf, kc, bins[1], nbin[1], false,
+                          kCap, res);
+        three_lane_bin<4>(m, s, qpair, tv, fc, ccell, cbox, tpf, kc, bins[1], nbin[2], true,
+                          kCap, res);
+        if constexpr (MAXPL >= 5)
+          nine_lane_bin(m, s, qpair, tv, fc, ccell, tpf, kc, bins[0], nbin[3], kCap, res);
+        __syncthreads();
+        // phase C
+        if (live)
+          for (int j = 0; j < nq; ++j) acc += res[j * kFastBlock + lane];
+        if (!__ballot(todo)) break;
+        if (lane < 4) nbin[lane] = 0;
+        __syncthreads();
+      }
+      if (!__ballot(more)) break;
+      todo = more;
+      more = false;
+      ci0 = 0;
       if (lane < 4) nbin[lane] = 0;
       __syncthreads();
     }
@@ -1892,11 +1916,11 @@ void launch_step(const DMesh &m, const DState &s, const DParams &p, hipStream_t 
   if (split) (void)hipStreamWaitEvent(st, fork->join, 0);
   if (m.maxn <= 3)
     TIMED(prof, kKClip,
-          (k_clip_fast<kTriSlots, kTriCand, false, kTriPlanes>
+          (k_clip_fast<kTriSlots, kTriCand, false, kTriPlanes, true>
            <<<kFastGrid, kFastBlock, 0, st>>>(m, s, p)));
   else
     TIMED(prof, kKClip,
-          (k_clip_fast<kFastSlots, kCandPool, true, kFastPlanes>
+          (k_clip_fast<kFastSlots, kCandPool, true, kFastPlanes, false>
            <<<kFastGrid, kFastBlock, 0, st>>>(m, s, p)));
   TIMED(prof, kKClipGeneral, (k_clip_general<<<4096, kClipBlock, 0, st>>>(m, s, p)));
   TIMED(prof, kKFaceSum, (k_face_sum<<<1024, kBlock, 0, st>>>(m, s, p)));
