@@ -402,15 +402,17 @@ def test_empty_and_full_fields(vof, ctx):
 
 FULL_SIZE = {
     "deform3d-128": lambda: W.deform3d(128, steps=1),
+    "shear3d-128": lambda: W.shear3d(128, steps=1),
     "tets-80": lambda: W.rotate_tets(80, steps=1),
 }
 
 
 @pytest.mark.parametrize("case", sorted(FULL_SIZE))
 def test_full_size_sampled(vof, ctx, oracle_mod, case):
-    """The 128^3 hex case (the benchmark's, in its launch configuration) and
-    the 80^3 x 6 jittered-tet case, one step each: sampled faces and cells
-    checked one by one against the oracle."""
+    """The 128^3 deformation case (the benchmark's, in its launch
+    configuration), the 128^3 shear case and the 80^3 x 6 jittered-tet case,
+    one step each: sampled faces and cells checked one by one against the
+    oracle."""
     w = FULL_SIZE[case]()
     print(f"[{case}] gpu step", flush=True)
     g = gpu_run(vof, ctx, w, steps=1)
