@@ -274,6 +274,7 @@ def test_narrow_band_leaves_bulk_cells(vof, ctx, oracle_mod):
 
 WISP_CASES = {
     "deform3d": lambda: W.deform3d(24, steps=40),
+    "deform3d-128": lambda: W.deform3d(128, steps=6),
     "tets": lambda: W.rotate_tets(10, steps=12, sample=8),
     "shear": lambda: W.shear3d(16, steps=30),
     "disc2d": lambda: W.disc2d(),
