@@ -241,6 +241,10 @@ typedef struct {
   double alpha_min, alpha_max;
   int64_t wisps;              /* sum over steps of wisps found (wisps = 1)   */
   int64_t wisps_left;         /* of those, wisps with too little room around */
+  int64_t chunk_rescans;      /* tetrahedral meshes: face groups whose stencils
+                                 were scanned again for a further chunk of
+                                 candidate cells (a face with more candidates
+                                 than a group's share)                       */
 } vof_stats;
 /* Synchronises, computes mass and alpha range, and reports the counters.
  * Returns VOF_ECAPACITY / VOF_ESTENCIL if the corresponding counter is

@@ -87,7 +87,8 @@ class vof_stats(C.Structure):
                 ("general_tets", C.c_int64),
                 ("ledger", C.c_double), ("mass", C.c_double),
                 ("alpha_min", C.c_double), ("alpha_max", C.c_double),
-                ("wisps", C.c_int64), ("wisps_left", C.c_int64)]
+                ("wisps", C.c_int64), ("wisps_left", C.c_int64),
+                ("chunk_rescans", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -612,7 +612,9 @@ __device__ __forceinline__ void correct(double c1, double c2, double c3, double 
   lam = 0.0;
   if (T == 0.0) return;
   if (!(c1 != 0.0) || !isfinite(c2) || !isfinite(c3)) { status = 1; return; }
-  const double big = 64.0;
+  // the branch ends at +-32 when V' has no root nearer to 0 (a corrected sweep
+  // 32 times the plain one is far outside any Courant limit)
+  const double big = 32.0;
   double lo = -big, hi = big;
   if (c3 != 0.0) {
     double disc = c2 * c2 - 3.0 * c1 * c3;
@@ -774,7 +776,13 @@ void k_flux(DMesh m, DState s, DParams p) {
         correct(c1, c2, c3, T, p.corr_rtol, p.corr_max_iter, lam, it, stat);
         // A target beyond the extremum of V on the branch: the phase volume of
         // the polyhedron at the clamped lam is rescaled to F dt (scalar correction).
-        if (stat) s.vscale[f] = T / (((c3 * lam + c2) * lam + c1) * lam);
+        // A volume of zero at the clamped lam (no sweep: c1 = 0, lam = 0) has
+        // nothing to rescale; the face then carries its clipped phase as is.
+        if (stat) {
+          const double vl = ((c3 * lam + c2) * lam + c1) * lam;
+          const double r = T / vl;
+          s.vscale[f] = (vl != 0.0 && isfinite(r)) ? r : 1.0;
+        }
         nflux += 1;
         nit += (unsigned long long)it;
         nbad += (unsigned long long)stat;
@@ -1034,7 +1042,7 @@ void k_clip_fast(DMesh m, DState s, DParams p) {
   // candidates kept per face (the candidate field of a queued pair has 6 bits)
   const int kc = CAND / F < 63 ? CAND / F : 63;
   const int ngroups = (count + F - 1) / F;
-  unsigned long long npairs = 0;
+  unsigned long long npairs = 0, nresc = 0;
   // Groups are taken kClaim at a time: the first kClaim by block index, the
   // rest claimed from a counter.  Thousands of waves claiming one group each
   // serialise on the counter's atomic, above all at the start of the kernel.
@@ -1300,6 +1308,7 @@ void k_clip_fast(DMesh m, DState s, DParams p) {
         __syncthreads();
       }
       if (!__ballot(more)) break;
+      if (lane == 0) ++nresc;  // the group's stencils scanned again for the next chunk
       todo = more;
       more = false;
       ci0 = 0;
@@ -1317,6 +1326,7 @@ void k_clip_fast(DMesh m, DState s, DParams p) {
     __syncthreads();
   }
   wave_count(cnt_at(s.cnt, kCntPairs), npairs);
+  wave_count(cnt_at(s.cnt, kCntRescans), nresc);
 }
 
 // General clip of the queued tets, kGenTets tets per wave with kGenLanes lanes

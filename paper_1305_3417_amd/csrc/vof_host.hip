@@ -909,6 +909,7 @@ vof_status vof_get_stats(vof_mesh *m, vof_stats *out) {
   out->alpha_max = st4[2];
   out->wisps = (int64_t)c[kCntWisps];
   out->wisps_left = (int64_t)c[kCntWispsLeft];
+  out->chunk_rescans = (int64_t)c[kCntRescans];
   return device_status(m);
 }
 

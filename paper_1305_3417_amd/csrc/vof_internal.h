@@ -41,6 +41,7 @@ enum Counter : int {
   kCntDeferred,
   kCntWisps,
   kCntWispsLeft,
+  kCntRescans,
   kCntNum
 };
 

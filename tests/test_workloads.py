@@ -81,6 +81,25 @@ def test_courant_schedule_rule():
     assert dt.max() == 2.0 * dt[0] and len(dt) < T / dt[0]
 
 
+def test_tet_step_keeps_cell_courant_at_half(oracle_mod):
+    """The jittered-tet rotation's step: every cell's Courant number
+    (1/2) sum_f |F_f| dt / V_c, with V_c from the oracle's own geometry, is at
+    most 0.5, and the largest is within one step of it (dt = 1 / N)."""
+    w = W.rotate_tets(12, steps=2, sample=2)
+    V = oracle_mod.Oracle(w.mesh).geometry()[0]
+    m = w.mesh
+    S = np.zeros(m.n_cells)
+    np.add.at(S, m.owner, np.abs(w.F0))
+    np.add.at(S, m.neighbour, np.abs(w.F0[:m.n_internal]))
+    co = 0.5 * S * w.dt[0] / V
+    N = w.meta["steps_per_rev"]
+    assert w.dt[0] == 1.0 / N
+    assert co.max() <= 0.5 * (1 + 1e-12)
+    assert co.max() >= 0.5 * (N - 1) / N
+    # the velocity-over-spacing step this replaces would give cells above 1
+    assert (0.5 * S / V).max() / (9 * 12) > 1.0
+
+
 # --------------------------------------------------------------------------
 # 2:1 refined hexahedral meshes
 # --------------------------------------------------------------------------

@@ -14,7 +14,8 @@ Workloads (sizes as in the paper's advection tests, Section 4.2):
               cos(pi t/T), T=3, Co 0.5 (dt = 1/(4N))
   rotate_tets jittered Kuhn tets on an N^3 lattice (N=80 full), slotted sphere
               r=0.15 at (0.5, 0.75, 0.5), slot width 0.05, rigid rotation about
-              z through (0.5, 0.5) at 2 pi per unit time, Co 0.5
+              z through (0.5, 0.5) at 2 pi per unit time, cell Courant number
+              at most 0.5
   shear3d     N^3 hex, sphere r=0.15 at (0.5, 0.75, 0.25), shear field (eq. 4.5)
               with cos(pi t/T), T=3, u_max=1, R=0.5, adaptive Courant time step
 """
@@ -84,13 +85,37 @@ def slotted_sphere_inside(x, centre=(0.5, 0.75, 0.5), radius=0.15, slot_half=0.0
     return ball & ~slot
 
 
+def generated_volumes(mesh) -> np.ndarray:
+    """Cell volumes from the generator's description (boxes, tet vertices)."""
+    if mesh.kind == "hex":
+        return np.prod(mesh.cell_hi - mesh.cell_lo, axis=1)
+    p = mesh.points[mesh.cell_verts]
+    return np.abs(np.einsum("ij,ij->i", np.cross(p[:, 1] - p[:, 0], p[:, 2] - p[:, 0]),
+                            p[:, 3] - p[:, 0])) / 6.0
+
+
+def max_cell_courant_rate(mesh, F0) -> float:
+    """max over cells of (1/2) sum_f |F_f| / V_c: the cell Courant number of a
+    unit time step (the outflow volume of a divergence-free cell over its
+    volume)."""
+    S = np.zeros(mesh.n_cells)
+    a = np.abs(F0)
+    np.add.at(S, mesh.owner, a)
+    np.add.at(S, mesh.neighbour, a[:mesh.n_internal])
+    return float((0.5 * S / generated_volumes(mesh)).max())
+
+
 def rotate_tets(n: int = 80, steps: int | None = None, seed: int = 1305,
-                sample: int = 12, centre=(0.5, 0.75, 0.5), radius: float = 0.15) -> Workload:
+                sample: int = 12, centre=(0.5, 0.75, 0.5), radius: float = 0.15,
+                co: float = 0.5) -> Workload:
     """Slotted sphere rotating about z through (0.5, 0.5) on jittered Kuhn tets.
 
-    omega = 2 pi; max |U0| at the domain corners is omega*sqrt(0.5); the shortest
-    lattice spacing after jitter is about 0.6 h, so dt = 1/(9n) keeps Co <= 0.5.
-    The default step count is one revolution.
+    omega = 2 pi, one revolution per unit time.  The step is the largest
+    1/N with every cell's Courant number (1/2) sum_f |F_f| dt / V_c at most
+    `co`: the jittered tets hold slivers down to about h^3 / 70, so this is
+    far below the step a velocity-over-spacing Courant number would give
+    (about 1/(300 n) at n = 80, against 1/(9 n)).  The default step count is
+    one revolution.
     """
     m = kuhn_tet_mesh(n, 0.2, seed)
     c = np.asarray(centre, dtype=np.float64)
@@ -100,11 +125,12 @@ def rotate_tets(n: int = 80, steps: int | None = None, seed: int = 1305,
     origin = np.array([0.5, 0.5, 0.5])
     Uc = fields.rotation_velocity(m.cell_centroids(), omega, origin)
     F0 = fields.flux_rotation(m, omega, origin)
-    N = 9 * n if steps is None else steps
-    dt = 1.0 / (9 * n)
+    per_rev = int(np.ceil(max_cell_courant_rate(m, F0) / co))
+    N = per_rev if steps is None else steps
+    dt = 1.0 / per_rev
     return Workload("rotate_tets", m, a0, Uc, F0, np.full(N, dt), np.ones(N),
                     meta={"n": n, "seed": seed, "omega": omega, "centre": list(centre),
-                          "radius": radius})
+                          "radius": radius, "co": co, "steps_per_rev": per_rev})
 
 
 def translate_slab(n: int = 16, nz: int = 1, a: float = 0.3, b: float = 0.55,
@@ -196,6 +222,51 @@ def deform3d_refined(n: int = 32, steps: int | None = None, T: float = 3.0,
     return Workload("deform3d_refined", m, a0, Uc, F0, np.full(N, dt), np.cos(np.pi * t / T),
                     meta={"n": n, "T": T, "co": 0.5, "centre": list(centre), "radius": radius,
                           "parent": parent, "children": children})
+
+
+def uniform_alpha(w: Workload, value: float = 0.37) -> Workload:
+    """`w` with alpha = value in every cell: every cell is then an interface
+    cell whose gradient vanishes (the reconstruction's homogeneous case), so
+    every face with flux is clipped and carries value times its swept volume."""
+    import dataclasses
+    return dataclasses.replace(w, name=w.name + "-uniform", alpha0=np.full(w.mesh.n_cells, value),
+                               meta={**w.meta, "uniform": value})
+
+
+def isolated_cell(n: int = 8, u: float = 0.25, alpha: float = 0.5, steps: int = 1) -> Workload:
+    """One cell of value `alpha` at the centre of an empty n^3 box, translated
+    along +x at u (Co 0.5): its gradient vanishes by symmetry."""
+    m = hex_mesh(n, n, n)
+    a0 = np.zeros(m.n_cells)
+    c = n // 2
+    centre = (c * n + c) * n + c  # cell (c, c, c), x fastest
+    a0[centre] = alpha
+    U = np.array([u, 0.0, 0.0])
+    Uc = np.broadcast_to(U, (m.n_cells, 3)).copy()
+    F0 = fields.flux_constant(m, U)
+    dt = 0.5 / n / u
+    return Workload("isolated_cell", m, a0, Uc, F0, np.full(steps, dt), np.ones(steps),
+                    meta={"n": n, "u": u, "alpha": alpha, "cell": centre})
+
+
+def scaled_translation(n: int = 8, k: float = 20.0, u: float = 0.02, alpha: float = 0.37,
+                       steps: int = 1) -> Workload:
+    """Uniform translation along +x at u with every face flux k times U.S_f:
+    the swept volume is linear in the sweep factor, so the flux correction
+    must move the swept points k times the plain sweep (dt = h / 2)."""
+    m = hex_mesh(n, n, n)
+    U = np.array([u, 0.0, 0.0])
+    Uc = np.broadcast_to(U, (m.n_cells, 3)).copy()
+    F0 = k * fields.flux_constant(m, U)
+    dt = 0.5 / n
+    return Workload("scaled_translation", m, np.full(m.n_cells, alpha), Uc, F0,
+                    np.full(steps, dt), np.ones(steps), meta={"n": n, "k": k, "u": u})
+
+
+def boundary_points(mesh) -> np.ndarray:
+    """Points on the faces of the unit box (bool per point)."""
+    p = mesh.points
+    return ((p == 0.0) | (p == 1.0)).any(axis=1)
 
 
 WORKLOADS = {"disc2d": disc2d, "deform3d": deform3d, "rotate_tets": rotate_tets,
