@@ -55,13 +55,33 @@ def swept_scale(w, S, Up, scale_dt):
     return np.linalg.norm(S, axis=1) * mx * abs(scale_dt)
 
 
-def vphase_tolerance(w, V, scale_dt, S=None, Up=None):
-    """Per-face bound 1e-12 * max(|F| dt, gross swept volume, 1e-2 V_owner).
+def face_size_floor(w, V):
+    """max(V_owner, d_f^3) per face, d_f = twice the largest distance of a face
+    point from the face centre.  Each of the flux polyhedron's tetrahedra is
+    rounded to a few eps times the product of its edges, which are as long as
+    the face however short the sweep: the sum is good to about 1e-14 d_f^3
+    (20 eps h^3 on hex faces) even where F dt and the sweep are tiny.  On
+    jittered tets d_f^3 exceeds a sliver owner's volume many times over."""
+    m = w.mesh
+    n = np.diff(m.face_offsets)
+    face_of = np.repeat(np.arange(m.n_faces), n)
+    P = m.points[m.face_points]
+    c = np.zeros((m.n_faces, 3))
+    np.add.at(c, face_of, P)
+    c /= n[:, None]
+    r = np.zeros(m.n_faces)
+    np.maximum.at(r, face_of, np.linalg.norm(P - c[face_of], axis=1))
+    return np.maximum(V[m.owner], (2.0 * r) ** 3)
 
-    The absolute floor 1e-14 V_owner is the FP64 rounding of the polyhedron's
-    tetrahedra, whose edges are ~h however small the sweep (about 20 eps h^3)."""
+
+def vphase_tolerance(w, V, scale_dt, S=None, Up=None):
+    """Per-face bound 1e-12 * max(|F| dt, gross swept volume, 1e-2 max(V_owner, d_f^3)).
+
+    The absolute floor 1e-14 max(V_owner, d_f^3) is the FP64 rounding of the
+    polyhedron's tetrahedra, whose edges are as long as the face however small
+    the sweep (see face_size_floor)."""
     F = np.abs(w.F0) * abs(scale_dt)
-    ref = np.maximum(F, 1e-2 * V[w.mesh.owner])
+    ref = np.maximum(F, 1e-2 * face_size_floor(w, V))
     if S is not None:
         ref = np.maximum(ref, swept_scale(w, S, Up, scale_dt))
     return 1e-12 * ref

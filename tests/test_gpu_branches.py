@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from tests.common import gpu_run, swept_scale
+from tests.common import gpu_run, vphase_tolerance
 
 pytestmark = pytest.mark.gpu
 
@@ -49,8 +49,7 @@ def test_uniform_alpha_clamped_and_homogeneous(vof, ctx, oracle_mod):
     assert np.array_equal(g["status"], r["status"].astype(np.uint8))
     assert np.array_equal(g["kind"], r["kind"].astype(np.uint8))
     sdt = w.dt[0] * w.scale[0]
-    G = swept_scale(w, S, Up, sdt)
-    tol = 1e-12 * np.maximum(np.maximum(np.abs(w.F0) * abs(sdt), G), 1e-2 * V[w.mesh.owner])
+    tol = vphase_tolerance(w, V, sdt, S, Up)
     err = np.abs(g["vphase"] - r["vphase"])
     assert np.isfinite(g["vphase"]).all()
     assert (err <= tol).all(), (err / tol).max()

@@ -26,7 +26,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from tests.common import swept_scale
+from tests.common import vphase_tolerance
 
 
 def _interior_faces(w):
@@ -53,8 +53,7 @@ def test_uniform_alpha_faces_carry_alpha_times_flux(oracle_mod):
     assert (r["rec"]["cls"] == 3).all()
     sdt = w.dt[0] * w.scale[0]
     T = w.F0 * sdt
-    G = swept_scale(w, S, Up, sdt)
-    tol = 1e-12 * np.maximum(np.maximum(np.abs(T), G), 1e-2 * V[w.mesh.owner])
+    tol = vphase_tolerance(w, V, sdt, S, Up)
     faces = _interior_faces(w)
     clamped = faces[r["status"][faces] == 1]
     print(f"[uniform] {faces.size} interior faces, {clamped.size} clamped", flush=True)
