@@ -198,6 +198,25 @@ vof_status vof_reconstruct(vof_mesh *mesh);
  * its geometry (explicit Euler, eq. 2.2). */
 vof_status vof_advect(vof_mesh *mesh, int32_t n_steps, const double *dt, const double *scale);
 
+/* vof_advect for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same steps, bitwise the same results, with no allocation of any kind.  The
+ * schedule (dt, scale: host arrays of n_steps doubles, copied before return)
+ * is staged in a fixed buffer of the library on the mesh's device (room for
+ * VOF_NOALLOC_MAX_STEPS steps, 1 MiB, held until the process ends) instead of
+ * memory the mesh allocates, and the steps are launched kernel by kernel on
+ * the mesh's stream (no graph is built, the per-kernel profile is not
+ * recorded).  Every scratch array the kernels use otherwise was allocated
+ * with the mesh.  The staging buffer is shared by every call on one device:
+ * calls that overlap on one GPU (from several host threads, or on meshes with
+ * different streams before the earlier call's steps have run) race on it.
+ * Blocks until earlier work on the mesh's stream is done and the schedule is
+ * staged.  Errors: VOF_EINVAL (n_steps < 0 or above VOF_NOALLOC_MAX_STEPS,
+ * null or non-finite schedule, alpha or velocity not set), VOF_EDEVICE. */
+#define VOF_NOALLOC_MAX_STEPS 65536
+vof_status vof_advect_noalloc(vof_mesh *mesh, int32_t n_steps, const double *dt,
+                              const double *scale);
+
 /* Per-face results of the last step.  what: VOF_FACE_LAMBDA (double, the
  * corrected sweep factor), VOF_FACE_VPHASE (double, V_{f,alpha}, signed like
  * F_f), VOF_FACE_ITERS (uint8, correction iterations), VOF_FACE_KIND (uint8:

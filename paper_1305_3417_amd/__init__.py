@@ -44,7 +44,7 @@ EXPORTED = [
     "vof_context_create", "vof_context_destroy", "vof_last_error", "vof_version",
     "vof_mesh_upload", "vof_mesh_destroy", "vof_mesh_get_info", "vof_get_params",
     "vof_set_params", "vof_set_alpha", "vof_read_alpha", "vof_map_alpha", "vof_set_velocity",
-    "vof_reconstruct", "vof_advect", "vof_read_face", "vof_read_planes",
+    "vof_reconstruct", "vof_advect", "vof_advect_noalloc", "vof_read_face", "vof_read_planes",
     "vof_read_point_velocity", "vof_get_stats", "vof_reset_stats", "vof_synchronize",
     "vof_selftest_tet_clip", "vof_selftest_tet_clip_closed", "vof_profile_enable", "vof_profile_kernel_name", "vof_read_profile",
 ]
@@ -122,6 +122,7 @@ def lib():
             "vof_set_velocity": (i32, [vp, vp, vp, i32]),
             "vof_reconstruct": (i32, [vp]),
             "vof_advect": (i32, [vp, i32, vp, vp]),
+            "vof_advect_noalloc": (i32, [vp, i32, vp, vp]),
             "vof_read_face": (i32, [vp, i32, vp, i32]),
             "vof_read_planes": (i32, [vp, vp, vp, vp, i32]),
             "vof_read_point_velocity": (i32, [vp, vp, i32]),
@@ -343,6 +344,20 @@ def vof_advect(mesh: MeshHandle, dt, scale):
         raise ValueError("dt and scale must be 1-D arrays of equal length")
     _check(lib().vof_advect(mesh.h, int(dt.shape[0]), dt.ctypes.data_as(C.c_void_p),
                             scale.ctypes.data_as(C.c_void_p)), "vof_advect")
+
+
+VOF_NOALLOC_MAX_STEPS = 65536
+
+
+def vof_advect_noalloc(mesh: MeshHandle, dt, scale):
+    """vof_advect with no device allocation (schedule staged in the library's
+    fixed per-device buffer; at most VOF_NOALLOC_MAX_STEPS steps)."""
+    dt = np.ascontiguousarray(dt, dtype=np.float64)
+    scale = np.ascontiguousarray(scale, dtype=np.float64)
+    if dt.shape != scale.shape or dt.ndim != 1:
+        raise ValueError("dt and scale must be 1-D arrays of equal length")
+    _check(lib().vof_advect_noalloc(mesh.h, int(dt.shape[0]), dt.ctypes.data_as(C.c_void_p),
+                                    scale.ctypes.data_as(C.c_void_p)), "vof_advect_noalloc")
 
 
 def vof_read_face(mesh: MeshHandle, what: int, out=None, ok=(VOF_OK,)):

@@ -12,6 +12,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -40,6 +41,42 @@ vof_status fail(vof_status code, const char *fmt, ...) {
     hipError_t e_ = (expr);                                                           \
     if (e_ != hipSuccess) return fail(VOF_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
+
+}  // namespace
+
+// Staging of the step schedule (dt, then scale) for vof_advect_noalloc, in a
+// fixed array of the library rather than memory the mesh allocates.  In host
+// code `scratch` names a host-side stand-in: its device address on each GPU
+// is taken once with hipGetSymbolAddress (at context creation, with that
+// device current) and only that address is handed to kernels and copies.
+static __device__ __align__(256) double scratch[2 * VOF_NOALLOC_MAX_STEPS];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch[kMaxDevices] = {nullptr};
+
+// the device address of `scratch` on the current device (once per device)
+vof_status scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return fail(VOF_EINVAL, "device %d out of range", device);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[device]) return VOF_OK;
+  void *ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    (void)hipGetLastError();
+    return fail(VOF_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+  }
+  g_scratch[device] = (double *)ptr;
+  return VOF_OK;
+}
+
+double *scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch[device];
+}
 
 }  // namespace
 
@@ -312,6 +349,8 @@ vof_status vof_context_create(int32_t device, void *hip_stream, vof_context **ou
   }
   if (device < 0 || device >= n) return fail(VOF_EINVAL, "device %d out of range", device);
   HIP_OR_FAIL(hipSetDevice(device));
+  vof_status rc = scratch_init(device);
+  if (rc) return rc;
   vof_context *c = new (std::nothrow) vof_context;
   if (!c) return fail(VOF_ENOMEM, "host allocation failed");
   c->device = device;
@@ -807,6 +846,43 @@ vof_status vof_advect(vof_mesh *m, int32_t n_steps, const double *dt, const doub
   }
   if (!m->graph_ok && (rc = build_step_graph(m))) return rc;
   for (int32_t i = 0; i < n_steps; ++i) HIP_OR_FAIL(hipGraphLaunch(m->step_graph, s));
+  return VOF_OK;
+}
+
+vof_status vof_advect_noalloc(vof_mesh *m, int32_t n_steps, const double *dt,
+                              const double *scale) {
+  if (!m) return fail(VOF_EINVAL, "null argument");
+  if (n_steps < 0) return fail(VOF_EINVAL, "n_steps < 0");
+  if (n_steps > VOF_NOALLOC_MAX_STEPS)
+    return fail(VOF_EINVAL, "n_steps %d beyond the staging maximum of %d steps", n_steps,
+                VOF_NOALLOC_MAX_STEPS);
+  if (n_steps == 0) return VOF_OK;
+  if (!dt || !scale) return fail(VOF_EINVAL, "null dt or scale");
+  if (!m->have_alpha || !m->have_velocity) return fail(VOF_EINVAL, "alpha or velocity not set");
+  for (int32_t i = 0; i < n_steps; ++i)
+    if (!(dt[i] > 0.0) || !std::isfinite(dt[i]) || !std::isfinite(scale[i]))
+      return fail(VOF_EINVAL, "dt must be positive and finite, scale finite (step %d)", i);
+  vof_status rc = set_device(m->ctx);
+  if (rc) return rc;
+  double *ptr = scratch_ptr(m->ctx->device);
+  if (!ptr) return fail(VOF_EDEVICE, "staging buffer of device %d not set up", m->ctx->device);
+  hipStream_t s = m->ctx->stream;
+  // schedule and step counter staged in stream order behind earlier work of
+  // this mesh; the host arrays may be reused once the call returns
+  const int32_t first = 0;
+  HIP_OR_FAIL(hipMemcpyAsync(ptr, dt, sizeof(double) * n_steps, hipMemcpyHostToDevice, s));
+  HIP_OR_FAIL(hipMemcpyAsync(ptr + VOF_NOALLOC_MAX_STEPS, scale, sizeof(double) * n_steps,
+                             hipMemcpyHostToDevice, s));
+  HIP_OR_FAIL(hipMemcpyAsync(m->ds.stepno, &first, sizeof first, hipMemcpyHostToDevice, s));
+  HIP_OR_FAIL(hipStreamSynchronize(s));
+  DState ds = m->ds;
+  ds.dt = ptr;
+  ds.sc = ptr + VOF_NOALLOC_MAX_STEPS;
+  // kernel by kernel on the mesh's stream (building a graph may allocate)
+  for (int32_t i = 0; i < n_steps; ++i) {
+    launch_step(m->dm, ds, m->dp, s, nullptr, nullptr);
+    HIP_OR_FAIL(hipGetLastError());
+  }
   return VOF_OK;
 }
 
