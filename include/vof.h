@@ -285,6 +285,54 @@ vof_status vof_profile_enable(vof_mesh *mesh, int32_t enable);
 const char *vof_profile_kernel_name(int32_t id);
 vof_status vof_read_profile(vof_mesh *mesh, double *ms, int64_t *launches, int32_t n);
 
+/* ---- Batched form --------------------------------------------------------
+ * Many independent meshes advanced by the same launches (the paper's
+ * parallel runs split one mesh across processes, Section 4.2.2; here whole
+ * meshes share each kernel launch).  A batch refers to meshes uploaded with
+ * vof_mesh_upload, each with its alpha and velocity set; they stay owned by
+ * the caller, keep their own state (alpha, statistics, face results: read
+ * with the single-mesh calls) and must outlive the batch.  Every step of
+ * vof_batch_advect is one replay of a captured graph whose kernels walk the
+ * work of all meshes at once -- cell and face blocks, interface cells and
+ * geometric face groups taken from one queue spanning every mesh -- and run
+ * on each mesh's work the same code, in the same order, as vof_advect does:
+ * every mesh's results are bitwise those of its own vof_advect with the same
+ * schedule (the paper's serial-equals-parallel property, Section 4.2.2).  */
+typedef struct vof_batch vof_batch;
+
+/* Launch configuration of a batch step; it changes the speed of a step, never
+ * its results.  Defaults: grid_flux 4096, grid_clip 4096, clip_claim 2,
+ * grid_plane 2048, grid_cells 4096. */
+typedef struct {
+  int32_t grid_flux;   /* persistent blocks of the flux kernel (rounded up to 8) */
+  int32_t grid_clip;   /* waves of the register clip                          */
+  int32_t clip_claim;  /* face groups per claim of the register clip's queue  */
+  int32_t grid_plane;  /* blocks (four waves) of the plane kernel             */
+  int32_t grid_cells;  /* blocks of the cell, point and update kernels        */
+} vof_batch_config;
+
+/* meshes: n (1..VOF_MAX_BATCH) distinct meshes on the context's device.  The
+ * batch runs on the context's stream.  Errors: VOF_EINVAL, VOF_ENOMEM,
+ * VOF_EDEVICE. */
+#define VOF_MAX_BATCH 256
+vof_status vof_batch_create(vof_context *ctx, vof_mesh *const *meshes, int32_t n,
+                            vof_batch **out);
+vof_status vof_batch_destroy(vof_batch *batch);
+/* Advance every mesh of the batch by n_steps steps; mesh i's step k has length
+ * dt[i * n_steps + k] and velocity / flux scale scale[i * n_steps + k] (host
+ * arrays, copied before return).  Each mesh must have alpha and velocity set
+ * and wisp redistribution off.  Waits for earlier work on the meshes' own
+ * streams, then returns with the steps enqueued on the batch's stream: call
+ * vof_batch_synchronize before using a mesh through the single-mesh calls.
+ * Errors: VOF_EINVAL, VOF_ENOMEM, VOF_EDEVICE. */
+vof_status vof_batch_advect(vof_batch *batch, int32_t n_steps, const double *dt,
+                            const double *scale);
+/* Wait for the batch's steps; returns the first latched device error of any
+ * mesh (VOF_ECAPACITY, VOF_ESTENCIL). */
+vof_status vof_batch_synchronize(vof_batch *batch);
+vof_status vof_batch_get_config(const vof_batch *batch, vof_batch_config *out);
+vof_status vof_batch_set_config(vof_batch *batch, const vof_batch_config *config);
+
 /* Host self-test of the device geometry routines (compiled for the host as
  * well): volume of the tetrahedron (a, b, c, d) (12 doubles) intersected with
  * the half-spaces {n_k . x <= s_k} (4 doubles per plane).  Returns the volume

@@ -47,7 +47,10 @@ EXPORTED = [
     "vof_reconstruct", "vof_advect", "vof_advect_noalloc", "vof_read_face", "vof_read_planes",
     "vof_read_point_velocity", "vof_get_stats", "vof_reset_stats", "vof_synchronize",
     "vof_selftest_tet_clip", "vof_selftest_tet_clip_closed", "vof_profile_enable", "vof_profile_kernel_name", "vof_read_profile",
+    "vof_batch_create", "vof_batch_destroy", "vof_batch_advect", "vof_batch_synchronize",
+    "vof_batch_get_config", "vof_batch_set_config",
 ]
+VOF_MAX_BATCH = 256
 
 
 class VofError(RuntimeError):
@@ -94,6 +97,14 @@ class vof_stats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class vof_batch_config(C.Structure):
+    _fields_ = [("grid_flux", C.c_int32), ("grid_clip", C.c_int32), ("clip_claim", C.c_int32),
+                ("grid_plane", C.c_int32), ("grid_cells", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -134,6 +145,12 @@ def lib():
             "vof_profile_enable": (i32, [vp, i32]),
             "vof_profile_kernel_name": (C.c_char_p, [i32]),
             "vof_read_profile": (i32, [vp, vp, vp, i32]),
+            "vof_batch_create": (i32, [vp, vp, i32, C.POINTER(vp)]),
+            "vof_batch_destroy": (i32, [vp]),
+            "vof_batch_advect": (i32, [vp, i32, vp, vp]),
+            "vof_batch_synchronize": (i32, [vp]),
+            "vof_batch_get_config": (i32, [vp, C.POINTER(vof_batch_config)]),
+            "vof_batch_set_config": (i32, [vp, C.POINTER(vof_batch_config)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -442,3 +459,63 @@ def upload_mesh(ctx, mesh) -> MeshHandle:
     """vof_mesh_upload of a workloads.Mesh-like object (host arrays)."""
     return vof_mesh_upload(ctx, mesh.points, mesh.face_offsets, mesh.face_points, mesh.owner,
                            mesh.neighbour, mesh.n_cells)
+
+
+# ---------------------------------------------------------------------------
+# batched form
+# ---------------------------------------------------------------------------
+
+class BatchHandle:
+    """Owns a vof_batch* (the meshes stay owned by their handles)."""
+
+    def __init__(self, h, meshes):
+        self.h = h
+        self.meshes = list(meshes)
+
+    def close(self):
+        if self.h:
+            lib().vof_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def vof_batch_create(ctx, meshes) -> BatchHandle:
+    arr = (C.c_void_p * len(meshes))(*[m.h for m in meshes])
+    h = C.c_void_p()
+    _check(lib().vof_batch_create(ctx, arr, len(meshes), C.byref(h)), "vof_batch_create")
+    return BatchHandle(h, meshes)
+
+
+def vof_batch_destroy(batch: BatchHandle):
+    batch.close()
+
+
+def vof_batch_advect(batch: BatchHandle, dt, scale):
+    """dt, scale: (n_meshes, n_steps) arrays (row i: mesh i's schedule)."""
+    dt = np.ascontiguousarray(dt, dtype=np.float64)
+    scale = np.ascontiguousarray(scale, dtype=np.float64)
+    if dt.shape != scale.shape or dt.ndim != 2 or dt.shape[0] != len(batch.meshes):
+        raise ValueError("dt and scale must be (n_meshes, n_steps) arrays")
+    _check(lib().vof_batch_advect(batch.h, int(dt.shape[1]), dt.ctypes.data_as(C.c_void_p),
+                                  scale.ctypes.data_as(C.c_void_p)), "vof_batch_advect")
+
+
+def vof_batch_synchronize(batch: BatchHandle, ok=(VOF_OK,)):
+    return _check(lib().vof_batch_synchronize(batch.h), "vof_batch_synchronize", ok)
+
+
+def vof_batch_get_config(batch: BatchHandle) -> vof_batch_config:
+    c = vof_batch_config()
+    _check(lib().vof_batch_get_config(batch.h, C.byref(c)), "vof_batch_get_config")
+    return c
+
+
+def vof_batch_set_config(batch: BatchHandle, config: vof_batch_config):
+    _check(lib().vof_batch_set_config(batch.h, C.byref(config)), "vof_batch_set_config")

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvof.so")
-SOURCES = ["vof_device.hip", "vof_host.hip"]
+SOURCES = ["vof_device.hip", "vof_host.hip", "vof_systems.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -60,6 +60,10 @@ __device__ __forceinline__ v3 xyz(double4 a) { return mk3(a.x, a.y, a.z); }
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
+__host__ __device__ __forceinline__ int64_t grid_for_dev(int64_t n, int block) {
+  return (n + block - 1) / block;
+}
+
 // Workgroups are dispatched round-robin over the eight XCDs (block b on XCD
 // b % 8), each with its own L2.  Renumbered this way every XCD works through
 // a contiguous range of the logical block indices, so neighbouring faces
@@ -316,9 +320,11 @@ __global__ void k_reset(DState s) {
 // thread's interface cells appended together: one atomic per block of
 // kBlock * kClassCells cells on the list's counter.
 constexpr int kClassCells = 8;
-__global__ __launch_bounds__(kBlock) void k_cell_class(DMesh m, DState s, DParams p) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const int64_t c0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+// Block vb of a grid of vg blocks over the cells of one mesh.
+__device__ __forceinline__ void cell_class_blk(const DMesh &m, const DState &s, const DParams &p,
+                                               int64_t vb, int64_t vg) {
+  const int64_t stride = vg * blockDim.x;
+  const int64_t c0 = vb * (int64_t)blockDim.x + threadIdx.x;
   unsigned im = 0;  // bit i: cell c0 + i stride is an interface cell
 #pragma unroll
   for (int i = 0; i < kClassCells; ++i) {
@@ -337,12 +343,15 @@ __global__ __launch_bounds__(kBlock) void k_cell_class(DMesh m, DState s, DParam
     if ((im >> i) & 1u)
       s.icells[pos + __builtin_popcount(im & ((1u << i) - 1u))] = (int32_t)(c0 + i * stride);
 }
+__global__ __launch_bounds__(kBlock) void k_cell_class(DMesh m, DState s, DParams p) {
+  cell_class_blk(m, s, p, blockIdx.x, gridDim.x);
+}
 
 // Point mask: bit 1 empty, 2 full, 4 interface among the point-cells; with
 // the narrow band also bit 8, an empty or full point-cell whose alpha is not
 // exactly 0 or 1, so that mask 1 (2) means every point-cell is exactly 0 (1).
-__global__ __launch_bounds__(kBlock) void k_point_prep(DMesh m, DState s, DParams pr) {
-  int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+__device__ __forceinline__ void point_prep_one(const DMesh &m, const DState &s, const DParams &pr,
+                                               int64_t p) {
   if (p >= m.np) return;
   int k0 = m.pc_off[p], k1 = m.pc_off[p + 1];
   uint8_t mask = 0;
@@ -367,6 +376,9 @@ __global__ __launch_bounds__(kBlock) void k_point_prep(DMesh m, DState s, DParam
     for (int k = k0; k < k1; ++k) a += m.wpc[k] * s.alpha[m.pc[k]];
     s.alpha_p[p] = a;
   }
+}
+__global__ __launch_bounds__(kBlock) void k_point_prep(DMesh m, DState s, DParams pr) {
+  point_prep_one(m, s, pr, blockIdx.x * (int64_t)blockDim.x + threadIdx.x);
 }
 
 // Wave-wide reductions.  Every lane receives the same value: at each level of
@@ -566,23 +578,28 @@ __device__ __forceinline__ void plane_cell(const DMesh &m, const DState &s, cons
 // two cells; when both have at most 32 faces and 64 fan tetrahedra (so
 // that two per lane cover them) each gets half of the wave, else the whole
 // wave does one after the other.
+// The pair of interface cells i = 2q, 2q + 1 of the list (of `count`).
+__device__ __forceinline__ void plane_pair(const DMesh &m, const DState &s, const DParams &p,
+                                           int q, int count, int lane,
+                                           unsigned long long &nfall) {
+  const int i = 2 * q;
+  const int64_t ca = s.icells[i];
+  const int64_t cb = i + 1 < count ? s.icells[i + 1] : -1;
+  if (m.fan_small[ca] && (cb < 0 || m.fan_small[cb])) {
+    const int64_t c = lane < 32 ? ca : cb;
+    if (c >= 0) plane_cell<32>(m, s, p, c, lane & 31, nfall);
+  } else {
+    plane_cell<64>(m, s, p, ca, lane, nfall);
+    if (cb >= 0) plane_cell<64>(m, s, p, cb, lane, nfall);
+  }
+}
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_plane(DMesh m, DState s, DParams p) {
   const int count = s.work[kWInterface];
   const int lane = lane_id();
   const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   const int nwaves = (int)((gridDim.x * blockDim.x) >> 6);
   unsigned long long nfall = 0;
-  for (int i = 2 * wave; i < count; i += 2 * nwaves) {
-    const int64_t ca = s.icells[i];
-    const int64_t cb = i + 1 < count ? s.icells[i + 1] : -1;
-    if (m.fan_small[ca] && (cb < 0 || m.fan_small[cb])) {
-      const int64_t c = lane < 32 ? ca : cb;
-      if (c >= 0) plane_cell<32>(m, s, p, c, lane & 31, nfall);
-    } else {
-      plane_cell<64>(m, s, p, ca, lane, nfall);
-      if (cb >= 0) plane_cell<64>(m, s, p, cb, lane, nfall);
-    }
-  }
+  for (int q = wave; 2 * q < count; q += nwaves) plane_pair(m, s, p, q, count, lane, nfall);
   wave_count(cnt_at(s.cnt, kCntFallback), nfall);
 }
 
@@ -744,14 +761,12 @@ __device__ __forceinline__ void face_cubic(const DState &s, const int (&q)[NMAX]
 // Faces of up to four points run at four waves per SIMD (at most 128 VGPRs:
 // the loads of a face are a chain of two dependent gathers, hidden by the
 // other waves); faces of up to eight points need more registers.
+// The faces base .. base + blockDim.x - 1 of one mesh, one per thread.
 template <int NMAX>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NMAX <= 4 ? 4 : 1)))
-void k_flux(DMesh m, DState s, DParams p) {
-  const int step = *s.stepno;
-  const double dt = s.dt[step], sc = s.sc[step];
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  unsigned long long nflux = 0, nit = 0, nbad = 0;
-  for (int64_t base = (int64_t)xcd_block() * blockDim.x; base < m.nf; base += stride) {
+__device__ __forceinline__ void flux_chunk(const DMesh &m, const DState &s, const DParams &p,
+                                           int64_t base, double dt, double sc,
+                                           unsigned long long &nflux, unsigned long long &nit,
+                                           unsigned long long &nbad) {
     const int64_t f = base + threadIdx.x;
     bool geo = false;
     if (f < m.nf) {
@@ -815,7 +830,17 @@ void k_flux(DMesh m, DState s, DParams p) {
     }
     int slot = wave_append(&s.work[kWGeometric], geo);
     if (geo) s.gfaces[slot] = (int32_t)f;
-  }
+}
+
+template <int NMAX>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NMAX <= 4 ? 4 : 1)))
+void k_flux(DMesh m, DState s, DParams p) {
+  const int step = *s.stepno;
+  const double dt = s.dt[step], sc = s.sc[step];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  unsigned long long nflux = 0, nit = 0, nbad = 0;
+  for (int64_t base = (int64_t)xcd_block() * blockDim.x; base < m.nf; base += stride)
+    flux_chunk<NMAX>(m, s, p, base, dt, sc, nflux, nit, nbad);
   block_count3(cnt_at(s.cnt, kCntFaceFluxes), nflux, cnt_at(s.cnt, kCntIters), nit, cnt_at(s.cnt, kCntUnreached), nbad);
 }
 
@@ -1001,11 +1026,14 @@ __device__ __forceinline__ void nine_lane_bin(const DMesh &m, const DState &s,
 // lanes per pair (one per piece of its first plane's split; nine for five
 // planes, one per piece of the first two splits); phase C adds each tet's
 // queued results in stencil order.
+// Group g of the geometric faces of one mesh (`count` of them, F = 64 / tpf
+// per group), swept by `sweep` (-s dt).  Must be reached by the whole wave.
 template <int SLOTS, int CAND, bool BOXES, int MAXPL, bool CHUNKED>
-__global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(BOXES ? 3 : 2)))
-void k_clip_fast(DMesh m, DState s, DParams p) {
+__device__ __forceinline__ void clip_fast_group(const DMesh &m, const DState &s, const DParams &p,
+                                                int g, int count, double sweep,
+                                                unsigned long long &npairs,
+                                                unsigned long long &nresc) {
   static_assert(MAXPL <= 4 || !BOXES, "five-plane pairs only for cells that are not boxes");
-  const int step = *s.stepno;
   // the group's faces: points minus the face centre and their sweeps at the
   // corrected lam, the mean sweep, the point count and the face centre (the
   // apex of the face's tets); every tet is built from these
@@ -1032,43 +1060,18 @@ void k_clip_fast(DMesh m, DState s, DParams p) {
   __shared__ double cbox[BOXES ? CAND : 1][6];
   __shared__ double fbox[kGroupFaces][6];
   __shared__ int cnum[kGroupFaces];
-  __shared__ int group;
   const int lane = threadIdx.x;
-  const double dt = s.dt[step], sc = s.sc[step];
-  const double sweep = -sc * dt;
-  const int count = s.work[kWGeometric];
   const int tpf = m.tpf;
   const int F = kFastBlock / tpf;  // faces per group, 1..kGroupFaces
   // candidates kept per face (the candidate field of a queued pair has 6 bits)
   const int kc = CAND / F < 63 ? CAND / F : 63;
-  const int ngroups = (count + F - 1) / F;
-  unsigned long long npairs = 0, nresc = 0;
-  // Groups are taken kClaim at a time: the first kClaim by block index, the
-  // rest claimed from a counter.  Thousands of waves claiming one group each
-  // serialise on the counter's atomic, above all at the start of the kernel.
-  int left = -1;
-  for (;;) {
-    if (lane == 0) {
-      if (left < 0) {
-        group = kClaim * (int)blockIdx.x;
-        left = kClaim;
-      } else if (left == 0) {
-        group = kClaim * ((int)gridDim.x + atomicAdd(&s.work[kWClipNext], 1));
-        left = kClaim;
-      } else {
-        group = group + 1;
-      }
-      --left;
-    }
+  {
     if (lane < 4) nbin[lane] = 0;
     // flux polyhedron boxes, one lane per face (points and their swept
     // images), and the face staged in LDS.  Unpadded: a cell that only
     // touches the box meets the polyhedron in a sliver of zero width (or of
     // the width of the rounding of the tets' vertices), whose volume is below
     // the rounding of the sum.
-    __syncthreads();
-    const int g = group;
-    if (g >= ngroups) break;
     if (lane < F) {
       const int slot = g * F + lane;
       if (slot < count) {
@@ -1325,6 +1328,42 @@ void k_clip_fast(DMesh m, DState s, DParams p) {
     if (defer) s.defer[q] = (int32_t)idx;
     __syncthreads();
   }
+}
+
+// Step 5 on the register path over one mesh: groups are taken kClaim at a
+// time, the first kClaim by block index, the rest claimed from a counter
+// (thousands of waves claiming one group each serialise on the counter's
+// atomic, above all at the start of the kernel).
+template <int SLOTS, int CAND, bool BOXES, int MAXPL, bool CHUNKED>
+__global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(BOXES ? 3 : 2)))
+void k_clip_fast(DMesh m, DState s, DParams p) {
+  __shared__ int group;
+  const int lane = threadIdx.x;
+  const int step = *s.stepno;
+  const double sweep = -s.sc[step] * s.dt[step];
+  const int count = s.work[kWGeometric];
+  const int F = kFastBlock / m.tpf;
+  const int ngroups = (count + F - 1) / F;
+  unsigned long long npairs = 0, nresc = 0;
+  int left = -1;
+  for (;;) {
+    if (lane == 0) {
+      if (left < 0) {
+        group = kClaim * (int)blockIdx.x;
+        left = kClaim;
+      } else if (left == 0) {
+        group = kClaim * ((int)gridDim.x + atomicAdd(&s.work[kWClipNext], 1));
+        left = kClaim;
+      } else {
+        group = group + 1;
+      }
+      --left;
+    }
+    __syncthreads();
+    const int g = group;
+    if (g >= ngroups) break;
+    clip_fast_group<SLOTS, CAND, BOXES, MAXPL, CHUNKED>(m, s, p, g, count, sweep, npairs, nresc);
+  }
   wave_count(cnt_at(s.cnt, kCntPairs), npairs);
   wave_count(cnt_at(s.cnt, kCntRescans), nresc);
 }
@@ -1335,8 +1374,11 @@ void k_clip_fast(DMesh m, DState s, DParams p) {
 // on one vertex-graph polytope in LDS shared by the wave.  A tet's pair
 // volumes are added lane by lane in stencil order (the same order on every
 // run).
-__global__ __launch_bounds__(kClipBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_clip_general(DMesh m, DState s, DParams p) {
-  const int step = *s.stepno;
+// The deferred tets i0 .. i0 + kGenTets - 1 (of `count`) of one mesh.
+__device__ __forceinline__ void clip_general_tets(const DMesh &m, const DState &s,
+                                                  const DParams &p, int i0, int count, double dt,
+                                                  double sc, unsigned long long &ncap,
+                                                  unsigned long long &npairs) {
   __shared__ double lx[kPolyCap], ly[kPolyCap], lz[kPolyCap], ld[kPolyCap];
   __shared__ uint8_t lnb[3 * kPolyCap], laux[kPolyCap];
   static_assert(kClipBlock == 64, "one wave per block");
@@ -1353,12 +1395,9 @@ __global__ __launch_bounds__(kClipBlock) __attribute__((amdgpu_waves_per_eu(2)))
   __shared__ double fd[kClipBlock][20];
   __shared__ double fw[kClipBlock], fres[kClipBlock];
   __shared__ int8_t fidx[kClipBlock], fidx5[kClipBlock];
-  const double dt = s.dt[step], sc = s.sc[step];
-  const int count = s.work[kWDeferred];
   // kGenTets tets per wavefront, kGenLanes lanes each over the tet's stencil
   const int seg = lane / kGenLanes, sl = lane - seg * kGenLanes;
-  unsigned long long ncap = 0, npairs = 0;
-  for (int i0 = blockIdx.x * kGenTets; i0 < count; i0 += gridDim.x * kGenTets) {
+  {
     const int i = i0 + seg;
     const bool mine = seg < kGenTets && i < count;
     int64_t idx = 0;
@@ -1480,18 +1519,32 @@ __global__ __launch_bounds__(kClipBlock) __attribute__((amdgpu_waves_per_eu(2)))
     }
     __syncthreads();
   }
+}
+
+// the counters of the general clip, and the capacity flag
+__device__ __forceinline__ void clip_general_counts(const DState &s, unsigned long long ncap,
+                                                    unsigned long long npairs) {
   wave_count(cnt_at(s.cnt, kCntCapacity), ncap);
   wave_count(cnt_at(s.cnt, kCntPairs), npairs);
-  if (__ballot(ncap != 0) && lane == 0) flag(s.flags, kFlagCapacity);
+  if (__ballot(ncap != 0) && lane_id() == 0) flag(s.flags, kFlagCapacity);
+}
+
+__global__ __launch_bounds__(kClipBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_clip_general(DMesh m, DState s, DParams p) {
+  const int step = *s.stepno;
+  const double dt = s.dt[step], sc = s.sc[step];
+  const int count = s.work[kWDeferred];
+  unsigned long long ncap = 0, npairs = 0;
+  for (int i0 = blockIdx.x * kGenTets; i0 < count; i0 += gridDim.x * kGenTets)
+    clip_general_tets(m, s, p, i0, count, dt, sc, ncap, npairs);
+  clip_general_counts(s, ncap, npairs);
 }
 
 // Sum of the tets of each geometric face.  With check_stencil: the uncovered
 // signed volume of the face must vanish to 1e-12 of max(gross tet volume,
 // owner cell volume).
-__global__ __launch_bounds__(kBlock) void k_face_sum(DMesh m, DState s, DParams p) {
-  const int count = s.work[kWGeometric];
-  unsigned long long nleak = 0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
+__device__ __forceinline__ void face_sum_one(const DMesh &m, const DState &s, const DParams &p,
+                                             int i, unsigned long long &nleak) {
+  {
     const double *tv = s.tetvol + (int64_t)i * m.tpf;
     const int f = s.gfaces[i];
     double acc = 0.0;
@@ -1515,8 +1568,17 @@ __global__ __launch_bounds__(kBlock) void k_face_sum(DMesh m, DState s, DParams 
       if (fabs(dsum) > 1e-12 * dmax(gsum, m.V[m.own[f]])) ++nleak;
     }
   }
+}
+__device__ __forceinline__ void face_sum_counts(const DState &s, unsigned long long nleak) {
   wave_count(cnt_at(s.cnt, kCntLeaks), nleak);
   if (__ballot(nleak != 0) && lane_id() == 0) flag(s.flags, kFlagLeak);
+}
+__global__ __launch_bounds__(kBlock) void k_face_sum(DMesh m, DState s, DParams p) {
+  const int count = s.work[kWGeometric];
+  unsigned long long nleak = 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
+    face_sum_one(m, s, p, i, nleak);
+  face_sum_counts(s, nleak);
 }
 
 // alpha_c^{n+1} = alpha_c^n - (1/V_c) sum_f sgn_cf V_{f,alpha}, every cell
@@ -1527,9 +1589,12 @@ __global__ __launch_bounds__(kBlock) void k_face_sum(DMesh m, DState s, DParams 
 // so that every cell sharing a point with them is.  With wisps on, the
 // updated cells outside the interface band whose alpha is not exactly 0 or
 // 1 are listed with their excess over the nearer of the two.
-__global__ __launch_bounds__(kBlock) void k_update(DMesh m, DState s, DParams p) {
+// Block vb of the update of one mesh: cells vb * kBlock ... (and the block's
+// part of the ledger in part[vb]).
+__device__ __forceinline__ void update_blk(const DMesh &m, const DState &s, const DParams &p,
+                                           int64_t vb) {
   __shared__ double red[kBlock];
-  int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int64_t c = vb * (int64_t)blockDim.x + threadIdx.x;
   const uint32_t stamp = p.wisps ? s.wctr[0] + 1u : 0u;
   bool wisp = false;
   double ex = 0.0;
@@ -1586,7 +1651,11 @@ __global__ __launch_bounds__(kBlock) void k_update(DMesh m, DState s, DParams p)
     if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) s.part[blockIdx.x] = red[0];
+  if (threadIdx.x == 0) s.part[vb] = red[0];
+  __syncthreads();  // red is reused by the next block of a persistent caller
+}
+__global__ __launch_bounds__(kBlock) void k_update(DMesh m, DState s, DParams p) {
+  update_blk(m, s, p, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1711,7 +1780,8 @@ __global__ __launch_bounds__(kBlock) void k_wisp_moves(DMesh m, DState s, DParam
 
 // boundary ledger, second stage: one block adds the update kernel's
 // per-block sums in a fixed order, and the step's counts
-__global__ __launch_bounds__(kLedgerBlock) void k_ledger(DMesh m, DState s, DParams p, int nparts) {
+__device__ __forceinline__ void ledger_blk(const DMesh &m, const DState &s, const DParams &p,
+                                           int nparts) {
   __shared__ double red[kLedgerBlock];
   double acc = 0.0;
   // unrolled so that a thread's partial sums load together
@@ -1736,6 +1806,9 @@ __global__ __launch_bounds__(kLedgerBlock) void k_ledger(DMesh m, DState s, DPar
     s.stepno[0] += 1;  // the next step reads dt, scale at the next index
     for (int w = 0; w < kWNum; ++w) s.work[w] = 0;  // the next step's lists start empty
   }
+}
+__global__ __launch_bounds__(kLedgerBlock) void k_ledger(DMesh m, DState s, DParams p, int nparts) {
+  ledger_blk(m, s, p, nparts);
 }
 
 // mass (Neumaier-compensated), min and max of alpha: one block, fixed order
@@ -1830,6 +1903,278 @@ __global__ __launch_bounds__(kBlock) void k_map_alpha(DMesh d, double *alpha, co
     flag(flags, kFlagBadMap);
   }
   alpha[c] = a;
+}
+
+// ---------------------------------------------------------------------------
+// batches: one launch per kernel over the work of many meshes
+// ---------------------------------------------------------------------------
+// The mesh of global item g in an exclusive prefix `off` of n meshes (off[0]
+// = 0, off[n] = the total, empty meshes repeat an offset): the i with
+// off[i] <= g < off[i + 1].  Works on global or LDS arrays.
+__device__ __forceinline__ int find_inst(const int32_t *off, int n, int g) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= g) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Exclusive prefix over the batch's meshes of units(i) into pre[0..n] (LDS,
+// kMaxBatch + 1 entries), and the mesh's count(i) into cnt[i]: every thread of
+// the block takes a run of consecutive meshes, the runs' sums are scanned
+// across the wave and then across the block's waves.  Whole block.
+template <class Units>
+__device__ void batch_prefix(int n, int32_t *pre, Units units) {
+  __shared__ int32_t wtot[kBlock / kWave];
+  const int T = (int)blockDim.x, W = T / kWave;
+  const int per = (n + T - 1) / T;
+  const int a = (int)threadIdx.x * per;
+  int loc = 0;
+  for (int k = 0; k < per; ++k)
+    if (a + k < n) loc += units(a + k);
+  const int lane = lane_id(), w = (int)threadIdx.x / kWave;
+  int v = loc;
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int t = __shfl_up(v, o);
+    if (lane >= o) v += t;
+  }
+  if (lane == kWave - 1) wtot[w] = v;
+  __syncthreads();
+  int base = 0;
+  for (int i = 0; i < w; ++i) base += wtot[i];
+  int run = base + v - loc;
+  for (int k = 0; k < per; ++k)
+    if (a + k < n) {
+      pre[a + k] = run;
+      run += units(a + k);
+    }
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int i = 0; i < W; ++i) tot += wtot[i];
+    pre[n] = tot;
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kBlock) void kb_begin(BTab t) {
+  const int n = t.hdr[0];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    t.inst[i].s.stepno[0] = 0;
+}
+
+__global__ __launch_bounds__(kBlock) void kb_cell_class(BTab t) {
+  const int n = t.hdr[0], tot = t.cls_off[n];
+  for (int g = blockIdx.x; g < tot; g += gridDim.x) {
+    const int i = find_inst(t.cls_off, n, g);
+    const BInst &I = t.inst[i];
+    cell_class_blk(I.m, I.s, I.p, g - t.cls_off[i], t.cls_off[i + 1] - t.cls_off[i]);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void kb_point_prep(BTab t) {
+  const int n = t.hdr[0], tot = t.pt_off[n];
+  for (int g = blockIdx.x; g < tot; g += gridDim.x) {
+    const int i = find_inst(t.pt_off, n, g);
+    const BInst &I = t.inst[i];
+    point_prep_one(I.m, I.s, I.p, (int64_t)(g - t.pt_off[i]) * blockDim.x + threadIdx.x);
+  }
+}
+
+// Pairs of interface cells of all meshes, one pair per wave at a time.
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void kb_plane(BTab t) {
+  __shared__ int32_t pre[kMaxBatch + 1];
+  const int n = t.hdr[0];
+  batch_prefix(n, pre, [&](int i) { return (t.inst[i].s.work[kWInterface] + 1) / 2; });
+  const int lane = lane_id();
+  const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int nwaves = (int)((gridDim.x * blockDim.x) >> 6);
+  unsigned long long nfall = 0;
+  int cur = -1;
+  for (int q = wave; q < pre[n]; q += nwaves) {
+    const int i = find_inst(pre, n, q);
+    if (i != cur) {
+      if (cur >= 0) wave_count(cnt_at(t.inst[cur].s.cnt, kCntFallback), nfall);
+      nfall = 0;
+      cur = i;
+    }
+    const BInst &I = t.inst[i];
+    plane_pair(I.m, I.s, I.p, q - pre[i], I.s.work[kWInterface], lane, nfall);
+  }
+  if (cur >= 0) wave_count(cnt_at(t.inst[cur].s.cnt, kCntFallback), nfall);
+}
+
+// Flux blocks of the meshes of one face kind; every XCD walks a contiguous
+// range of the blocks (neighbouring faces share points, and so L2 lines).
+template <int NMAX>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NMAX <= 4 ? 4 : 1)))
+void kb_flux(BTab t, int kind) {
+  const int kn = t.hdr[1 + kind];
+  const int32_t *list = t.klist + kind * kMaxBatch;
+  const int32_t *off = t.kflux_off + kind * (kMaxBatch + 1);
+  const int tot = off[kn];
+  const int per = (int)gridDim.x / kXcds;  // blocks per XCD
+  const int x = (int)blockIdx.x % kXcds, j = (int)blockIdx.x / kXcds;
+  const int g0 = (int)((int64_t)tot * x / kXcds), g1 = (int)((int64_t)tot * (x + 1) / kXcds);
+  unsigned long long nflux = 0, nit = 0, nbad = 0;
+  int cur = -1;
+  for (int g = g0 + j; g < g1; g += per) {
+    const int k = find_inst(off, kn, g);
+    if (k != cur) {
+      if (cur >= 0) {
+        const DState &S = t.inst[list[cur]].s;
+        block_count3(cnt_at(S.cnt, kCntFaceFluxes), nflux, cnt_at(S.cnt, kCntIters), nit,
+                     cnt_at(S.cnt, kCntUnreached), nbad);
+        __syncthreads();
+      }
+      nflux = nit = nbad = 0;
+      cur = k;
+    }
+    const BInst &I = t.inst[list[k]];
+    const int step = *I.s.stepno;
+    flux_chunk<NMAX>(I.m, I.s, I.p, (int64_t)(g - off[k]) * blockDim.x, I.s.dt[step],
+                     I.s.sc[step], nflux, nit, nbad);
+  }
+  if (cur >= 0) {
+    const DState &S = t.inst[list[cur]].s;
+    block_count3(cnt_at(S.cnt, kCntFaceFluxes), nflux, cnt_at(S.cnt, kCntIters), nit,
+                 cnt_at(S.cnt, kCntUnreached), nbad);
+  }
+}
+
+// Face groups of the geometric faces of the meshes of one face kind, claimed
+// `claim` at a time (the first by block index, the rest from a counter).
+// Prefix of the face groups of the register clip over the meshes of each
+// face kind (one block; after the flux kernels): kept in global memory, as
+// the clip kernel's LDS is what bounds its occupancy.
+__global__ __launch_bounds__(kBlock) void kb_group_prefix(BTab t) {
+  __shared__ int32_t pre[kMaxBatch + 1];
+  for (int kind = 0; kind < kFaceKinds; ++kind) {
+    const int kn = t.hdr[1 + kind];
+    const int32_t *list = t.klist + kind * kMaxBatch;
+    batch_prefix(kn, pre, [&](int k) {
+      const BInst &I = t.inst[list[k]];
+      const int F = kFastBlock / I.m.tpf;
+      return (I.s.work[kWGeometric] + F - 1) / F;
+    });
+    for (int k = threadIdx.x; k <= kn; k += blockDim.x)
+      t.gpre[kind * (kMaxBatch + 1) + k] = pre[k];
+    __syncthreads();
+  }
+}
+
+template <int SLOTS, int CAND, bool BOXES, int MAXPL, bool CHUNKED>
+__global__ __launch_bounds__(kFastBlock) __attribute__((amdgpu_waves_per_eu(BOXES ? 3 : 2)))
+void kb_clip_fast(BTab t, int kind, int claim) {
+  __shared__ int group;
+  const int kn = t.hdr[1 + kind];
+  const int32_t *list = t.klist + kind * kMaxBatch;
+  const int32_t *pre = t.gpre + kind * (kMaxBatch + 1);
+  const int lane = threadIdx.x;
+  const int ngroups = pre[kn];
+  unsigned long long npairs = 0, nresc = 0;
+  int cur = -1, left = -1;
+  for (;;) {
+    if (lane == 0) {
+      if (left < 0) {
+        group = claim * (int)blockIdx.x;
+        left = claim;
+      } else if (left == 0) {
+        group = claim * ((int)gridDim.x + atomicAdd(&t.work[kBWClip + kind], 1));
+        left = claim;
+      } else {
+        group = group + 1;
+      }
+      --left;
+    }
+    __syncthreads();
+    const int g = group;
+    if (g >= ngroups) break;
+    const int k = find_inst(pre, kn, g);
+    if (k != cur) {
+      if (cur >= 0) {
+        const DState &S = t.inst[list[cur]].s;
+        wave_count(cnt_at(S.cnt, kCntPairs), npairs);
+        wave_count(cnt_at(S.cnt, kCntRescans), nresc);
+      }
+      npairs = nresc = 0;
+      cur = k;
+    }
+    const BInst &I = t.inst[list[k]];
+    const int step = *I.s.stepno;
+    clip_fast_group<SLOTS, CAND, BOXES, MAXPL, CHUNKED>(
+        I.m, I.s, I.p, g - pre[k], I.s.work[kWGeometric], -I.s.sc[step] * I.s.dt[step], npairs,
+        nresc);
+  }
+  if (cur >= 0) {
+    const DState &S = t.inst[list[cur]].s;
+    wave_count(cnt_at(S.cnt, kCntPairs), npairs);
+    wave_count(cnt_at(S.cnt, kCntRescans), nresc);
+  }
+}
+
+__global__ __launch_bounds__(kClipBlock) __attribute__((amdgpu_waves_per_eu(2))) void kb_clip_general(BTab t) {
+  __shared__ int32_t pre[kMaxBatch + 1];
+  const int n = t.hdr[0];
+  batch_prefix(n, pre, [&](int i) {
+    return (t.inst[i].s.work[kWDeferred] + kGenTets - 1) / kGenTets;
+  });
+  unsigned long long ncap = 0, npairs = 0;
+  int cur = -1;
+  for (int q = blockIdx.x; q < pre[n]; q += gridDim.x) {
+    const int i = find_inst(pre, n, q);
+    if (i != cur) {
+      if (cur >= 0) clip_general_counts(t.inst[cur].s, ncap, npairs);
+      ncap = npairs = 0;
+      cur = i;
+    }
+    const BInst &I = t.inst[i];
+    const int step = *I.s.stepno;
+    clip_general_tets(I.m, I.s, I.p, (q - pre[i]) * kGenTets, I.s.work[kWDeferred],
+                      I.s.dt[step], I.s.sc[step], ncap, npairs);
+  }
+  if (cur >= 0) clip_general_counts(t.inst[cur].s, ncap, npairs);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_face_sum(BTab t) {
+  __shared__ int32_t pre[kMaxBatch + 1];
+  const int n = t.hdr[0];
+  batch_prefix(n, pre, [&](int i) {
+    return (t.inst[i].s.work[kWGeometric] + kBlock - 1) / kBlock;
+  });
+  unsigned long long nleak = 0;
+  int cur = -1;
+  for (int q = blockIdx.x; q < pre[n]; q += gridDim.x) {
+    const int i = find_inst(pre, n, q);
+    if (i != cur) {
+      if (cur >= 0) face_sum_counts(t.inst[cur].s, nleak);
+      nleak = 0;
+      cur = i;
+    }
+    const BInst &I = t.inst[i];
+    const int f = (q - pre[i]) * kBlock + (int)threadIdx.x;
+    if (f < I.s.work[kWGeometric]) face_sum_one(I.m, I.s, I.p, f, nleak);
+  }
+  if (cur >= 0) face_sum_counts(t.inst[cur].s, nleak);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_update(BTab t) {
+  const int n = t.hdr[0], tot = t.upd_off[n];
+  for (int g = blockIdx.x; g < tot; g += gridDim.x) {
+    const int i = find_inst(t.upd_off, n, g);
+    const BInst &I = t.inst[i];
+    update_blk(I.m, I.s, I.p, g - t.upd_off[i]);
+  }
+}
+
+// one block per mesh; the first block also clears the batch's claim counters
+__global__ __launch_bounds__(kLedgerBlock) void kb_ledger(BTab t) {
+  const int n = t.hdr[0];
+  if (blockIdx.x == 0 && threadIdx.x < kBWNum) t.work[threadIdx.x] = 0;
+  if ((int)blockIdx.x >= n) return;
+  const BInst &I = t.inst[blockIdx.x];
+  ledger_blk(I.m, I.s, I.p, (int)grid_for_dev(I.m.nc, kBlock));
 }
 
 inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
@@ -1942,6 +2287,45 @@ void launch_step(const DMesh &m, const DState &s, const DParams &p, hipStream_t 
                           k_wisp_moves<<<kWispGrid, kBlock, 0, st>>>(m, s, p)));
   TIMED(prof, kKLedger,
         (k_ledger<<<1, kLedgerBlock, 0, st>>>(m, s, p, (int)grid_for(m.nc, kBlock))));
+}
+
+void launch_batch_begin(const BTab &t, int n, hipStream_t st) {
+  if (n > 0) kb_begin<<<grid_for(n, kBlock), kBlock, 0, st>>>(t);
+}
+
+// One step of a batch: the single-mesh step's kernels, each over all meshes
+// (the flux and register-clip kernels once per face kind present).
+void launch_batch_step(const BTab &t, const BConf &c, unsigned kinds, int ledger_grid,
+                       hipStream_t st, const Fork *fork) {
+  kb_cell_class<<<c.grid_cells, kBlock, 0, st>>>(t);
+  kb_point_prep<<<c.grid_cells, kBlock, 0, st>>>(t);
+  if (fork) {
+    (void)hipEventRecord(fork->fork, st);
+    (void)hipStreamWaitEvent(fork->side, fork->fork, 0);
+    kb_plane<<<c.grid_plane, kBlock, 0, fork->side>>>(t);
+    (void)hipEventRecord(fork->join, fork->side);
+  } else {
+    kb_plane<<<c.grid_plane, kBlock, 0, st>>>(t);
+  }
+  const int gf = (c.grid_flux + kXcds - 1) / kXcds * kXcds;
+  if (kinds & 1u) kb_flux<3><<<gf, kBlock, 0, st>>>(t, 0);
+  if (kinds & 2u) kb_flux<4><<<gf, kBlock, 0, st>>>(t, 1);
+  if (kinds & 4u) kb_flux<kMaxFacePoints><<<gf, kBlock, 0, st>>>(t, 2);
+  if (fork) (void)hipStreamWaitEvent(st, fork->join, 0);
+  kb_group_prefix<<<1, kBlock, 0, st>>>(t);
+  if (kinds & 1u)
+    kb_clip_fast<kTriSlots, kTriCand, false, kTriPlanes, true>
+        <<<c.grid_clip, kFastBlock, 0, st>>>(t, 0, c.clip_claim);
+  if (kinds & 2u)
+    kb_clip_fast<kFastSlots, kCandPool, true, kFastPlanes, false>
+        <<<c.grid_clip, kFastBlock, 0, st>>>(t, 1, c.clip_claim);
+  if (kinds & 4u)
+    kb_clip_fast<kFastSlots, kCandPool, true, kFastPlanes, false>
+        <<<c.grid_clip, kFastBlock, 0, st>>>(t, 2, c.clip_claim);
+  kb_clip_general<<<4096, kClipBlock, 0, st>>>(t);
+  kb_face_sum<<<1024, kBlock, 0, st>>>(t);
+  kb_update<<<c.grid_cells, kBlock, 0, st>>>(t);
+  kb_ledger<<<ledger_grid, kLedgerBlock, 0, st>>>(t);
 }
 
 void launch_map_alpha(const DMesh &d, double *alpha, const int32_t *off, const int32_t *cells,

@@ -17,14 +17,15 @@
 #include <string>
 #include <vector>
 
-#include "../../include/vof.h"
-#include "vof_internal.h"
+#include "vof_host_internal.h"
 
 using namespace vof;
 
-namespace {
+namespace vof {
 
+namespace {
 thread_local std::string g_err;
+}  // namespace
 
 vof_status fail(vof_status code, const char *fmt, ...) {
   char buf[512];
@@ -36,13 +37,18 @@ vof_status fail(vof_status code, const char *fmt, ...) {
   return code;
 }
 
-#define HIP_OR_FAIL(expr)                                                             \
-  do {                                                                                \
-    hipError_t e_ = (expr);                                                           \
-    if (e_ != hipSuccess) return fail(VOF_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
-  } while (0)
+const char *last_error() { return g_err.c_str(); }
 
-}  // namespace
+vof_status flags_status(const uint32_t *d_flags) {
+  uint32_t fl = 0;
+  HIP_OR_FAIL(hipMemcpy(&fl, d_flags, sizeof fl, hipMemcpyDeviceToHost));
+  if (fl & kFlagCapacity) return fail(VOF_ECAPACITY, "a clipped polytope exceeded its capacity");
+  if (fl & kFlagLeak) return fail(VOF_ESTENCIL, "a flux polyhedron left its stencil");
+  return VOF_OK;
+}
+
+}  // namespace vof
+
 
 // Staging of the step schedule (dt, then scale) for vof_advect_noalloc, in a
 // fixed array of the library rather than memory the mesh allocates.  In host
@@ -79,64 +85,6 @@ double *scratch_ptr(int device) {
 }
 
 }  // namespace
-
-struct vof_context {
-  int device;
-  hipStream_t stream;
-};
-
-struct vof_mesh {
-  vof_context *ctx = nullptr;  // copy of the creating context (device, stream)
-  DMesh dm{};
-  DState ds{};
-  DParams dp{};
-  std::vector<void *> allocs;
-  int64_t bytes = 0;
-  int32_t max_cell_faces = 0;
-  int64_t st_entries = 0;
-  int64_t step_cap = 0;
-  vof_context own_ctx{};
-  bool have_alpha = false, have_velocity = false;
-  double *stats_buf = nullptr;  // 4 doubles
-  bool profiling = false;
-  Prof prof;
-  // the launch sequence of one step captured once (valid while the kernel
-  // arguments -- buffers and parameters -- stay as captured)
-  hipStream_t cap_stream = nullptr;
-  Fork fork;  // side stream and events of the captured step
-  hipGraphExec_t step_graph = nullptr;
-  bool graph_ok = false;
-  double prof_ms[kKNum] = {0};
-  int64_t prof_count[kKNum] = {0};
-
-  template <class T>
-  vof_status alloc(T **p, int64_t count) {
-    size_t nbytes = sizeof(T) * (size_t)(count > 0 ? count : 1);
-    void *q = nullptr;
-    hipError_t e = hipMalloc(&q, nbytes);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(VOF_ENOMEM, "hipMalloc of %zu bytes failed: %s", nbytes, hipGetErrorString(e));
-    }
-    allocs.push_back(q);
-    bytes += (int64_t)nbytes;
-    *p = (T *)q;
-    return VOF_OK;
-  }
-  ~vof_mesh() {
-    if (step_graph) (void)hipGraphExecDestroy(step_graph);
-    if (cap_stream) (void)hipStreamDestroy(cap_stream);
-    if (fork.side) (void)hipStreamDestroy(fork.side);
-    if (fork.fork) (void)hipEventDestroy(fork.fork);
-    if (fork.join) (void)hipEventDestroy(fork.join);
-    for (int i = 0; i < prof.cap; ++i) {
-      (void)hipEventDestroy(prof.recs[i].a);
-      (void)hipEventDestroy(prof.recs[i].b);
-    }
-    delete[] prof.recs;
-    for (void *q : allocs) (void)hipFree(q);
-  }
-};
 
 namespace {
 
@@ -185,14 +133,7 @@ vof_status check_memory(int32_t memory) {
   return VOF_OK;
 }
 
-// latched device flags -> status (after a synchronisation)
-vof_status device_status(vof_mesh *m) {
-  uint32_t fl = 0;
-  HIP_OR_FAIL(hipMemcpy(&fl, m->ds.flags, sizeof fl, hipMemcpyDeviceToHost));
-  if (fl & kFlagCapacity) return fail(VOF_ECAPACITY, "a clipped polytope exceeded its capacity");
-  if (fl & kFlagLeak) return fail(VOF_ESTENCIL, "a flux polyhedron left its stencil");
-  return VOF_OK;
-}
+vof_status device_status(vof_mesh *m) { return vof::flags_status(m->ds.flags); }
 
 vof_params default_params() {
   vof_params p;
@@ -334,7 +275,7 @@ vof_status build_step_graph(vof_mesh *m) {
 
 extern "C" {
 
-const char *vof_last_error(void) { return g_err.c_str(); }
+const char *vof_last_error(void) { return vof::last_error(); }
 
 const char *vof_version(void) { return "vofmi 0.1 (gfx950, fp64)"; }
 

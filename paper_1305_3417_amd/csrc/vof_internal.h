@@ -149,6 +149,42 @@ struct DState {
   double2 *rho;         // nc: per receiver, room / sum of m > 0, store / sum of -m, m < 0
 };
 
+// Batches: many meshes advanced by the same launches.  Every mesh keeps its
+// own addressing and state; a device table holds their descriptors, and each
+// batch kernel walks a work space spanning all of them (blocks, wave items or
+// face groups of one mesh at a time), running the single-mesh kernels' code
+// on that mesh's descriptors.  Meshes are grouped by face kind for the
+// kernels whose code depends on the number of points per face.
+constexpr int kMaxBatch = 256;
+constexpr int kFaceKinds = 3;  // 0: at most 3 points per face, 1: 4, 2: 5..8
+inline int face_kind(int maxn) { return maxn <= 3 ? 0 : (maxn == 4 ? 1 : 2); }
+enum BatchWork : int { kBWClip = 0, kBWNum = kBWClip + kFaceKinds };
+struct BInst {
+  DMesh m;
+  DState s;   // the mesh's state, with dt / sc pointing at the batch's schedule
+  DParams p;
+};
+struct BTab {
+  const int32_t *hdr;        // [0] meshes n, [1 + k] meshes of face kind k
+  const BInst *inst;         // n
+  const int32_t *cls_off;    // n + 1: prefix of cell-class blocks (kBlock * 8 cells)
+  const int32_t *pt_off;     // n + 1: prefix of point blocks (kBlock points)
+  const int32_t *upd_off;    // n + 1: prefix of update blocks (kBlock cells)
+  const int32_t *klist;      // kFaceKinds x kMaxBatch: the meshes of each face kind
+  const int32_t *kflux_off;  // kFaceKinds x (kMaxBatch + 1): prefix of flux blocks over klist
+  int32_t *gpre;             // kFaceKinds x (kMaxBatch + 1): prefix of register-clip face
+                             // groups over klist (written each step)
+  int32_t *work;             // kBWNum claim counters (cleared by the ledger)
+};
+// launch configuration of a batch step (what the autotuner picks)
+struct BConf {
+  int grid_flux;     // persistent blocks of the flux kernel (multiple of 8)
+  int grid_clip;     // waves of the register clip
+  int clip_claim;    // face groups taken per claim
+  int grid_plane;    // blocks of four waves for the plane kernel
+  int grid_cells;    // blocks of the cell and point kernels
+};
+
 // Per-kernel timing with HIP events on the launch stream (optional).
 enum KernelId : int {
   kKReset = 0, kKCellClass, kKPointPrep, kKPlane, kKFlux, kKClip, kKClipGeneral, kKFaceSum,
@@ -183,6 +219,13 @@ void launch_reconstruct(const DMesh &m, const DState &s, const DParams &p, hipSt
 void launch_stats(const DMesh &m, const DState &s, double *out4, hipStream_t st);
 void launch_map_alpha(const DMesh &d, double *alpha, const int32_t *off, const int32_t *cells,
                       const DMesh &o, const DState &os, uint32_t *flags, hipStream_t st);
+// One batch step on `st` (plane kernel on fork->side when given).  `kinds`
+// bit k: some mesh has face kind k (launches for absent kinds are skipped);
+// `ledger_grid`: blocks of the ledger (at least the number of meshes).
+void launch_batch_step(const BTab &t, const BConf &c, unsigned kinds, int ledger_grid,
+                       hipStream_t st, const Fork *fork);
+// Set every mesh's step counter to 0 (before a batch's first step).
+void launch_batch_begin(const BTab &t, int n, hipStream_t st);
 double host_tet_clip(const double *tet, int n_planes, const double *planes);
 double host_tet_clip_closed(const double *tet, int n_planes, const double *planes);
 

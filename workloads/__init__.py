@@ -263,6 +263,70 @@ def scaled_translation(n: int = 8, k: float = 20.0, u: float = 0.02, alpha: floa
                     np.full(steps, dt), np.ones(steps), meta={"n": n, "k": k, "u": u})
 
 
+def courant_dt(mesh, F0, co: float = 0.5, period: float | None = None) -> float:
+    """Largest step with every cell's Courant number (1/2) sum_f |F_f| dt / V_c
+    at most `co`; with `period`, the largest period / N below it."""
+    dt = co / max_cell_courant_rate(mesh, F0)
+    if period is not None:
+        dt = period / np.ceil(period / dt)
+    return float(dt)
+
+
+def random_unit_vector(rng) -> np.ndarray:
+    v = rng.normal(size=3)
+    return v / np.linalg.norm(v)
+
+
+def rotating_sphere(n: int, rng, refine: bool = False, steps: int = 100,
+                    r_range=(0.1, 0.2), omega_range=(np.pi, 2 * np.pi)) -> Workload:
+    """One instance of the batched workload: a sphere of radius r ~ U(r_range)
+    on an n^3 hex mesh (refined once, 2:1, in the cells its surface cuts when
+    `refine`), centred uniformly in the ball |c - o| <= 0.5 - r - 2h about
+    o = (1/2, 1/2, 1/2), rigidly rotating about o around a uniformly random
+    axis at omega ~ U(omega_range); dt from the cell Courant number 0.5 on
+    the (finest) cells; exact sphere fractions as alpha^0."""
+    from .refine import refine_hex
+    h = 1.0 / n
+    r = float(rng.uniform(*r_range))
+    o = np.array([0.5, 0.5, 0.5])
+    rad = 0.5 - r - 2 * h
+    while True:  # uniform in the ball of radius rad
+        c = rng.uniform(-rad, rad, size=3)
+        if (c * c).sum() <= rad * rad:
+            break
+    c = o + c
+    axis = random_unit_vector(rng)
+    omega = float(rng.uniform(*omega_range))
+    m0 = hex_mesh(n, n, n)
+    if refine:
+        f0 = fields.ball_box_fraction(c, r, m0.cell_lo, m0.cell_hi)
+        m, _, _ = refine_hex(n, (f0 > 0) & (f0 < 1))
+    else:
+        m = m0
+    a0 = fields.ball_box_fraction(c, r, m.cell_lo, m.cell_hi)
+    Uc = fields.rotation_velocity(m.cell_centroids(), omega, o, axis)
+    F0 = fields.flux_rotation(m, omega, o, axis)
+    dt = courant_dt(m, F0)
+    return Workload(f"sphere{n}{'r' if refine else ''}", m, a0, Uc, F0, np.full(steps, dt),
+                    np.ones(steps), meta={"n": n, "refined": refine, "radius": r,
+                                          "centre": c.tolist(), "axis": axis.tolist(),
+                                          "omega": omega})
+
+
+def batch_instances(count: int = 256, seed: int = 3417, n_range=(16, 96), steps: int = 100,
+                    first: int = 0, stop: int | None = None):
+    """The batched workload's instances first .. stop - 1 of `count`: instance
+    i has N ~ U{n_range} (one seeded draw per instance) and is refined when i
+    is odd (see rotating_sphere).  Every instance draws from its own seeded
+    generator, so any subset can be built independently."""
+    out = []
+    for i in range(first, count if stop is None else stop):
+        rng = np.random.default_rng([seed, i])
+        n = int(rng.integers(n_range[0], n_range[1] + 1))
+        out.append(rotating_sphere(n, rng, refine=bool(i % 2), steps=steps))
+    return out
+
+
 def boundary_points(mesh) -> np.ndarray:
     """Points on the faces of the unit box (bool per point)."""
     p = mesh.points
