@@ -161,6 +161,163 @@ def parity_check(vof, mesh, w, step, n_sample=2000, seed=5):
             "ok": bool(lam_err < 1e-12 and ratio <= 1.0 and flags_equal)}
 
 
+def _make_instance(i, count, seed, n_lo, n_hi, steps):
+    import workloads as W
+    return W.batch_instances(count, seed, (n_lo, n_hi), steps, first=i, stop=i + 1)[0]
+
+
+def generate_instances(count, seed, n_range, steps, workers):
+    """The batched workload's instances, built in parallel host processes."""
+    import multiprocessing as mp
+    args = [(i, count, seed, n_range[0], n_range[1], steps) for i in range(count)]
+    out = [None] * count
+    t0 = time.perf_counter()
+    # largest first: the pool's tail is then made of small instances
+    order = sorted(range(count), key=lambda i: -_instance_size_hint(i, seed, n_range))
+    with mp.get_context("fork").Pool(workers) as pool:
+        for k, (i, w) in enumerate(zip(order, pool.imap(_make_star, [args[i] for i in order]))):
+            out[i] = w
+            if (k + 1) % 32 == 0 or k + 1 == count:
+                log(f"[bench] generated {k + 1}/{count} instances ({time.perf_counter() - t0:.0f} s)")
+    return out
+
+
+def _make_star(a):
+    return _make_instance(*a)
+
+
+def _instance_size_hint(i, seed, n_range):
+    import numpy as np
+    return int(np.random.default_rng([seed, i]).integers(n_range[0], n_range[1] + 1))
+
+
+def run_batched(args):
+    """The batched form against the plain per-instance loop on the batched
+    workload: 256 hex meshes N^3, N ~ U{16..96} (odd instances refined once
+    around their sphere), random sphere and rigid rotation, 100 steps each at
+    cell Courant number 0.5.  Both runs start from alpha^0 on the same
+    resident meshes; every mesh's final alpha must be bitwise the same."""
+    import numpy as np
+    import torch
+
+    import paper_1305_3417_amd as vof
+
+    count, steps = args.instances, args.steps
+    workers = max(1, min(16, (os.cpu_count() or 1)))
+    log(f"[bench] generating {count} instances with {workers} processes")
+    ws = generate_instances(count, 3417, (args.n_min, args.n_max), steps, workers)
+    ctx = vof.vof_context_create(0)
+    meshes = []
+    t0 = time.perf_counter()
+    for k, w in enumerate(ws):
+        m = vof.upload_mesh(ctx, w.mesh)
+        vof.vof_set_alpha(m, w.alpha0)
+        vof.vof_set_velocity(m, w.U0c, w.F0)
+        meshes.append(m)
+        if (k + 1) % 32 == 0 or k + 1 == count:
+            log(f"[bench] uploaded {k + 1}/{count} meshes ({time.perf_counter() - t0:.0f} s, "
+                f"{sum(x.info.device_bytes for x in meshes) / 2**30:.1f} GiB)")
+    dt = np.stack([w.dt[:steps] for w in ws])
+    sc = np.stack([w.scale[:steps] for w in ws])
+    flux_faces = sum(int(np.count_nonzero(w.F0)) for w in ws)
+    cells = sum(w.mesh.n_cells for w in ws)
+
+    def reset():
+        for w, m in zip(ws, meshes):
+            vof.vof_set_alpha(m, w.alpha0)
+        torch.cuda.synchronize()
+
+    def geo_total():
+        return sum(vof.vof_get_stats(m)["geometric_faces"] for m in meshes)
+
+    # plain loop: one vof_advect per mesh, each its own captured step graph
+    Wm = args.warmup
+    for w, m in zip(ws, meshes):
+        vof.vof_advect(m, w.dt[:Wm], w.scale[:Wm])
+    for m in meshes:
+        vof.vof_synchronize(m)
+    reset()
+    log(f"[bench] plain loop: {count} meshes x {steps} steps")
+    t0 = time.perf_counter()
+    for w, m in zip(ws, meshes):
+        vof.vof_advect(m, w.dt[:steps], w.scale[:steps])
+    for m in meshes:
+        vof.vof_synchronize(m)
+    t_plain = time.perf_counter() - t0
+    geo_plain = geo_total()
+    a_plain = [vof.vof_read_alpha(m) for m in meshes]
+    log(f"[bench] plain loop {t_plain:.3f} s")
+
+    b = vof.vof_batch_create(ctx, meshes)
+    tune = None
+    if args.autotune:
+        reset()
+        tune = vof.vof_autotune(b, dt[:, :args.tune_steps], sc[:, :args.tune_steps],
+                                args.tune_cache)
+        log(f"[bench] autotuned {tune}")
+    reset()
+    vof.vof_batch_advect(b, dt[:, :Wm], sc[:, :Wm])   # captures the batch step
+    vof.vof_batch_synchronize(b)
+    reset()
+    log(f"[bench] batched: {count} meshes x {steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    vof.vof_batch_advect(b, dt, sc)
+    vof.vof_batch_synchronize(b)
+    t_batch = time.perf_counter() - t0
+    geo_batch = geo_total()
+    diff = {ws[i].name + f"#{i}": float(np.abs(vof.vof_read_alpha(m) - a).max())
+            for i, (m, a) in enumerate(zip(meshes, a_plain))}
+    diff = {k: v for k, v in diff.items() if v != 0.0 or not np.isfinite(v)}
+    same = not diff
+    log(f"[bench] batched {t_batch:.3f} s, alpha bitwise equal to the plain loop: {same}"
+        + ("" if same else f" (differing meshes: {diff})"))
+    cfg = vof.vof_batch_get_config(b).as_dict()
+
+    parity = None
+    if not args.no_parity:
+        import oracle
+        small = sorted(range(count), key=lambda i: ws[i].mesh.n_cells)[:2]
+        errs = {}
+        for i in small:
+            o = oracle.Oracle(ws[i].mesh)
+            o.set_velocity(ws[i].U0c, ws[i].F0)
+            a, _, _, _ = o.advect(ws[i].alpha0, ws[i].dt[:steps], ws[i].scale[:steps])
+            errs[ws[i].name] = float(np.abs(a - a_plain[i]).max())
+        parity = {"oracle_max_abs_alpha_err": errs, "ok": max(errs.values()) < 1e-10}
+        log(f"[bench] parity {parity}")
+
+    v_batch = flux_faces * steps / t_batch
+    v_plain = flux_faces * steps / t_plain
+    out = {
+        "metric": METRIC, "value": v_batch, "unit": "face-fluxes/s", "n_gpus": 1,
+        "steps": steps, "warmup": Wm, "ms_per_step": t_batch * 1e3 / steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"batched: {count} hex meshes N^3, N ~ U{{{args.n_min}.."
+                               f"{args.n_max}}} (odd instances refined 2:1 around the sphere), "
+                               f"sphere r ~ U[0.1, 0.2], random rigid rotation, cell Courant "
+                               f"0.5, {steps} steps, seed 3417",
+                   "instances": count, "cells": int(cells), "flux_faces_per_step": flux_faces,
+                   "parallelism": "single GPU"},
+        "form": "batched",
+        "plain_loop": {"value": v_plain, "seconds": t_plain, "ms_per_step": t_plain * 1e3 / steps},
+        "batched_over_plain": v_batch / v_plain,
+        "seconds": t_batch,
+        "alpha_bitwise_equal_to_plain": bool(same),
+        "geometric_faces": {"plain": int(geo_plain), "batched": int(geo_batch)},
+        "cell_updates_per_s": cells * steps / t_batch,
+        "launch_config": cfg, "autotune": tune,
+        "device_gib": sum(x.info.device_bytes for x in meshes) / 2**30,
+        "parity": parity,
+    }
+    print(json.dumps(out), flush=True)
+    b.close()
+    for m in meshes:
+        m.close()
+    vof.vof_context_destroy(ctx)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -169,10 +326,20 @@ def main():
     ap.add_argument("--n", type=int, default=None,
                     help="mesh is n^3 hexahedra (default 128), or n^3 cubes of six jittered "
                          "tetrahedra for tets (default 80)")
-    ap.add_argument("--workload", choices=["deform3d", "shear3d", "tets"], default="deform3d",
+    ap.add_argument("--workload", choices=["deform3d", "shear3d", "tets", "batched"],
+                    default="deform3d",
                     help="deform3d (eq. 4.6, fixed dt; the headline case), shear3d "
-                         "(eq. 4.5, adaptive Courant dt) or tets (slotted sphere rotating "
-                         "on jittered tetrahedra)")
+                         "(eq. 4.5, adaptive Courant dt), tets (slotted sphere rotating "
+                         "on jittered tetrahedra) or batched (many meshes per launch against "
+                         "the plain per-mesh loop)")
+    ap.add_argument("--instances", type=int, default=256, help="batched: number of meshes")
+    ap.add_argument("--n-min", type=int, default=16, help="batched: smallest N")
+    ap.add_argument("--n-max", type=int, default=96, help="batched: largest N")
+    ap.add_argument("--autotune", action="store_true",
+                    help="batched: pick the launch configuration by timing candidates")
+    ap.add_argument("--tune-steps", type=int, default=6)
+    ap.add_argument("--tune-cache", default=None,
+                    help="batched: JSON cache of tuned configurations")
     ap.add_argument("--band-wisps", action="store_true",
                     help="run the step with the narrow band and wisp redistribution "
                          "(Section 2.3) after the update")
@@ -204,6 +371,11 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes_read": n * 8, "bytes_written": n * 8,
                           "launches": 3}), flush=True)
+        return
+    if args.workload == "batched":
+        if args.steps == 200 and "--steps" not in sys.argv:
+            args.steps = 100
+        run_batched(args)
         return
     WORKLOAD[0] = args.workload
     if args.n is None:

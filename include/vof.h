@@ -221,11 +221,17 @@ vof_status vof_advect_noalloc(vof_mesh *mesh, int32_t n_steps, const double *dt,
  * corrected sweep factor), VOF_FACE_VPHASE (double, V_{f,alpha}, signed like
  * F_f), VOF_FACE_ITERS (uint8, correction iterations), VOF_FACE_KIND (uint8:
  * 0 no flux, 1 trivially empty stencil, 2 trivially full stencil,
- * 3 geometric), VOF_FACE_STATUS (uint8: 0 ok, 1 correction target beyond the
- * extremum of the swept volume on its monotone branch: lambda is set to that
- * extremum or to the plain sweep (+-1 on the same side), whichever is nearer
- * to 0, and the face's phase volume is rescaled by F dt / V_f(lambda), so the
- * face still carries exactly F dt of total volume). */
+ * 3 geometric, 4 correction target unreachable with a clamped polyhedron
+ * under a quarter of F dt: the face carries the upwind (donor) cell's alpha
+ * times F dt -- alpha of the owner for F > 0, of the neighbour for F < 0, 0
+ * for inflow through a boundary face), VOF_FACE_STATUS (uint8: 0 ok, 1
+ * correction target beyond the extremum of the swept volume on its monotone
+ * branch through lambda = 0 (Section 2.3 does not treat it): lambda is set
+ * to that extremum or to the plain sweep (+-1 on the same side), whichever is
+ * nearer to 0; where the polyhedron there holds at least a quarter of F dt
+ * (with its sign) its phase volume is scaled by F dt / V_f(lambda), the scalar
+ * coefficient correction (kind 3), else the face takes the donor cell
+ * (kind 4), unless its stencil is trivially empty or full). */
 #define VOF_FACE_LAMBDA 0
 #define VOF_FACE_VPHASE 1
 #define VOF_FACE_ITERS 2
@@ -332,6 +338,23 @@ vof_status vof_batch_advect(vof_batch *batch, int32_t n_steps, const double *dt,
 vof_status vof_batch_synchronize(vof_batch *batch);
 vof_status vof_batch_get_config(const vof_batch *batch, vof_batch_config *out);
 vof_status vof_batch_set_config(vof_batch *batch, const vof_batch_config *config);
+
+/* Autotuner of the batch's launch configuration.  Advances the batch by
+ * n_steps steps exactly as vof_batch_advect would (same arguments, bitwise
+ * the same results, since a configuration changes only the speed of a step),
+ * launching them kernel by kernel with a different candidate configuration
+ * per step and timing the kernels each parameter drives (HIP events); then
+ * keeps, per parameter, the fastest candidate seen and sets it as the batch's
+ * configuration (also written to *out when out is non-NULL).  With
+ * cache_path non-NULL the configuration is cached in that JSON file under a
+ * key made of the GPU target (e.g. gfx950) and the batch's size bucket (face
+ * kinds present, nearest powers of two of its faces and meshes): a cached
+ * entry is used without timing (the steps are still advanced, as one graph
+ * each), and a tuned one is added or replaced.  Four steps time every
+ * candidate once.  Errors: as vof_batch_advect; VOF_EINVAL if the cache
+ * cannot be written. */
+vof_status vof_autotune(vof_batch *batch, int32_t n_steps, const double *dt,
+                        const double *scale, const char *cache_path, vof_batch_config *out);
 
 /* Host self-test of the device geometry routines (compiled for the host as
  * well): volume of the tetrahedron (a, b, c, d) (12 doubles) intersected with

@@ -601,8 +601,9 @@ double orc_flux_volume(const omesh *M, int64_t f, double dt, double s, double la
  * or the bracket is exhausted.
  * If F dt lies beyond the extremum of V at the branch end, lambda is set to
  * that extremum or to the plain sweep (+-1 on the same side), whichever is
- * nearer to 0, and status 1 is returned; the phase volume of such a face is
- * rescaled to F dt (see phase_flux_face). */
+ * nearer to 0, and status 1 is returned; such a face carries its
+ * polyhedron's phase fraction of F dt, or the donor cell's (see
+ * phase_flux_face). */
 static void branch_cubic(const omesh *M, int64_t f, double dt, double s, double *a1,
                          double *a2, double *a3) {
   double V1 = orc_flux_volume(M, f, dt, s, 1.0);
@@ -934,7 +935,8 @@ static int tet_cell_volumes(const omesh *M, const double *a, const double *b, co
 
 /* Phase volume of face f for the last reconstruction.
  * kind: 0 no flux, 1 trivially empty stencil, 2 trivially full stencil,
- *       3 geometric.
+ *       3 geometric, 4 correction target unreachable and the clamped
+ *       polyhedron below a quarter of F dt (donor cell).
  * READING: outside the domain counts as empty; for a boundary face the
  * full-stencil shortcut is not taken (its polyhedron may lie outside).
  * Returns the stencil leak |sum_c sum_k sgn_k |T_k ∩ C_c| - V_f| relative to
@@ -954,6 +956,23 @@ static double phase_flux_face(const omesh *M, int64_t f, double dt, double s, do
   }
   if (!any_nonempty) { *vphase = 0.0; *kind = 1; return 0.0; }
   if (all_full && f < M->ni) { *vphase = F * dt; *kind = 2; return 0.0; }
+  if (status == 1) {
+    /* READING (the paper's correction always converges; an unreachable
+     * target is not treated): no swept polyhedron on the branch has volume
+     * F dt.  If the clamped polyhedron still holds at least a quarter of
+     * F dt, on its side, its phase fraction is applied to F dt (the scalar
+     * coefficient correction the paper cites, Section 2.3; the scale is then
+     * at most 4); otherwise it is too small to say anything and the face
+     * carries the upwind (donor) cell's fraction of F dt, the cell the flux
+     * leaves (outside the domain is empty). */
+    double vl = orc_flux_volume(M, f, dt, s, lam);
+    if (!(fabs(vl) >= 0.25 * fabs(F * dt) && vl * F > 0.0)) {
+      int64_t donor = F > 0.0 ? M->own[f] : (f < M->ni ? M->nei[f] : -1);
+      *vphase = donor >= 0 ? alpha[donor] * (F * dt) : 0.0;
+      *kind = 4;
+      return 0.0;
+    }
+  }
   *kind = 3;
   oflux X;
   flux_polyhedron(M, f, dt, s, lam, &X);
@@ -977,7 +996,7 @@ static double phase_flux_face(const omesh *M, int64_t f, double dt, double s, do
       total += sgn * vp;
     }
   }
-  /* flagged correction: the phase fraction of the swept polyhedron times F dt */
+  /* a clamped face: the phase fraction of its polyhedron times F dt */
   if (status == 1 && vf != 0.0) total *= (F * dt) / vf;
   *vphase = total;
   /* uncovered signed volume relative to the gross tet volume of the face or

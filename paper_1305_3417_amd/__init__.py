@@ -48,7 +48,7 @@ EXPORTED = [
     "vof_read_point_velocity", "vof_get_stats", "vof_reset_stats", "vof_synchronize",
     "vof_selftest_tet_clip", "vof_selftest_tet_clip_closed", "vof_profile_enable", "vof_profile_kernel_name", "vof_read_profile",
     "vof_batch_create", "vof_batch_destroy", "vof_batch_advect", "vof_batch_synchronize",
-    "vof_batch_get_config", "vof_batch_set_config",
+    "vof_batch_get_config", "vof_batch_set_config", "vof_autotune",
 ]
 VOF_MAX_BATCH = 256
 
@@ -151,6 +151,7 @@ def lib():
             "vof_batch_synchronize": (i32, [vp]),
             "vof_batch_get_config": (i32, [vp, C.POINTER(vof_batch_config)]),
             "vof_batch_set_config": (i32, [vp, C.POINTER(vof_batch_config)]),
+            "vof_autotune": (i32, [vp, i32, vp, vp, C.c_char_p, C.POINTER(vof_batch_config)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -519,3 +520,18 @@ def vof_batch_get_config(batch: BatchHandle) -> vof_batch_config:
 
 def vof_batch_set_config(batch: BatchHandle, config: vof_batch_config):
     _check(lib().vof_batch_set_config(batch.h, C.byref(config)), "vof_batch_set_config")
+
+
+def vof_autotune(batch: BatchHandle, dt, scale, cache_path=None) -> dict:
+    """Advance the batch by dt.shape[1] steps while timing candidate launch
+    configurations; the fastest becomes the batch's configuration (returned)."""
+    dt = np.ascontiguousarray(dt, dtype=np.float64)
+    scale = np.ascontiguousarray(scale, dtype=np.float64)
+    if dt.shape != scale.shape or dt.ndim != 2 or dt.shape[0] != len(batch.meshes):
+        raise ValueError("dt and scale must be (n_meshes, n_steps) arrays")
+    c = vof_batch_config()
+    path = None if cache_path is None else os.fsencode(cache_path)
+    _check(lib().vof_autotune(batch.h, int(dt.shape[1]), dt.ctypes.data_as(C.c_void_p),
+                              scale.ctypes.data_as(C.c_void_p), path, C.byref(c)),
+           "vof_autotune")
+    return c.as_dict()

@@ -578,19 +578,28 @@ __device__ __forceinline__ void plane_cell(const DMesh &m, const DState &s, cons
 // two cells; when both have at most 32 faces and 64 fan tetrahedra (so
 // that two per lane cover them) each gets half of the wave, else the whole
 // wave does one after the other.
-// The pair of interface cells i = 2q, 2q + 1 of the list (of `count`).
+// The pair of interface cells i = 2q, 2q + 1 of the list (of `count`).  A
+// cell is always evaluated by the same group width -- 32 lanes when it has at
+// most 32 faces and 64 fan tetrahedra, else the whole wave -- whatever cell
+// it is paired with: the lanes' partial sums, and so the rounding of the
+// group sums, depend on the width, and the list's order is not fixed.
 __device__ __forceinline__ void plane_pair(const DMesh &m, const DState &s, const DParams &p,
                                            int q, int count, int lane,
                                            unsigned long long &nfall) {
   const int i = 2 * q;
   const int64_t ca = s.icells[i];
   const int64_t cb = i + 1 < count ? s.icells[i + 1] : -1;
-  if (m.fan_small[ca] && (cb < 0 || m.fan_small[cb])) {
+  const bool sa = m.fan_small[ca], sb = cb >= 0 && m.fan_small[cb];
+  if (sa && (cb < 0 || sb)) {
     const int64_t c = lane < 32 ? ca : cb;
     if (c >= 0) plane_cell<32>(m, s, p, c, lane & 31, nfall);
   } else {
-    plane_cell<64>(m, s, p, ca, lane, nfall);
-    if (cb >= 0) plane_cell<64>(m, s, p, cb, lane, nfall);
+    if (!sa) plane_cell<64>(m, s, p, ca, lane, nfall);
+    else if (lane < 32) plane_cell<32>(m, s, p, ca, lane, nfall);
+    if (cb >= 0) {
+      if (!sb) plane_cell<64>(m, s, p, cb, lane, nfall);
+      else if (lane < 32) plane_cell<32>(m, s, p, cb, lane, nfall);
+    }
   }
 }
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_plane(DMesh m, DState s, DParams p) {
@@ -789,15 +798,7 @@ __device__ __forceinline__ void flux_chunk(const DMesh &m, const DState &s, cons
         if (n == NMAX) face_cubic<NMAX, NMAX>(s, q, n, sweep, mask, c1, c2, c3);
         else face_cubic<NMAX, 0>(s, q, n, sweep, mask, c1, c2, c3);
         correct(c1, c2, c3, T, p.corr_rtol, p.corr_max_iter, lam, it, stat);
-        // A target beyond the extremum of V on the branch: the phase volume of
-        // the polyhedron at the clamped lam is rescaled to F dt (scalar correction).
-        // A volume of zero at the clamped lam (no sweep: c1 = 0, lam = 0) has
-        // nothing to rescale; the face then carries its clipped phase as is.
-        if (stat) {
-          const double vl = ((c3 * lam + c2) * lam + c1) * lam;
-          const double r = T / vl;
-          s.vscale[f] = (vl != 0.0 && isfinite(r)) ? r : 1.0;
-        }
+        const double vl = stat ? ((c3 * lam + c2) * lam + c1) * lam : T;
         nflux += 1;
         nit += (unsigned long long)it;
         nbad += (unsigned long long)stat;
@@ -807,7 +808,17 @@ __device__ __forceinline__ void flux_chunk(const DMesh &m, const DState &s, cons
         } else if ((mask & 7) == 2 && f < m.ni) {
           kind = 2;
           vph = T;
+        } else if (stat && !(fabs(vl) >= 0.25 * fabs(T) && vl * T > 0.0)) {
+          // no swept polyhedron on the branch meets F dt and the clamped one
+          // is under a quarter of it: the face carries the upwind (donor)
+          // cell's fraction of F dt (outside is empty)
+          const int64_t donor = T > 0.0 ? (int64_t)m.own[f] : (f < m.ni ? (int64_t)m.nei[f] : -1);
+          kind = 4;
+          vph = donor >= 0 ? s.alpha[donor] * T : 0.0;
         } else {
+          // a clamped polyhedron of at least a quarter of F dt: its phase
+          // fraction times F dt (the scale at most 4)
+          if (stat) s.vscale[f] = T / vl;
           kind = 3;
           geo = true;
         }
@@ -2296,10 +2307,18 @@ void launch_batch_begin(const BTab &t, int n, hipStream_t st) {
 // One step of a batch: the single-mesh step's kernels, each over all meshes
 // (the flux and register-clip kernels once per face kind present).
 void launch_batch_step(const BTab &t, const BConf &c, unsigned kinds, int ledger_grid,
-                       hipStream_t st, const Fork *fork) {
+                       hipStream_t st, const Fork *fork, hipEvent_t *ev) {
+  // ev (eager launches only): 0 start, 1 after the cell and point kernels, 2 after
+  // the plane kernel, 3 after the flux kernels, 4 after the register clips,
+  // 5 before the update, 6 after the update, 7 after the ledger
+  auto mark = [&](int i) {
+    if (ev) (void)hipEventRecord(ev[i], st);
+  };
+  mark(0);
   kb_cell_class<<<c.grid_cells, kBlock, 0, st>>>(t);
   kb_point_prep<<<c.grid_cells, kBlock, 0, st>>>(t);
-  if (fork) {
+  mark(1);
+  if (fork && !ev) {
     (void)hipEventRecord(fork->fork, st);
     (void)hipStreamWaitEvent(fork->side, fork->fork, 0);
     kb_plane<<<c.grid_plane, kBlock, 0, fork->side>>>(t);
@@ -2307,11 +2326,13 @@ void launch_batch_step(const BTab &t, const BConf &c, unsigned kinds, int ledger
   } else {
     kb_plane<<<c.grid_plane, kBlock, 0, st>>>(t);
   }
+  mark(2);
   const int gf = (c.grid_flux + kXcds - 1) / kXcds * kXcds;
   if (kinds & 1u) kb_flux<3><<<gf, kBlock, 0, st>>>(t, 0);
   if (kinds & 2u) kb_flux<4><<<gf, kBlock, 0, st>>>(t, 1);
   if (kinds & 4u) kb_flux<kMaxFacePoints><<<gf, kBlock, 0, st>>>(t, 2);
-  if (fork) (void)hipStreamWaitEvent(st, fork->join, 0);
+  if (fork && !ev) (void)hipStreamWaitEvent(st, fork->join, 0);
+  mark(3);
   kb_group_prefix<<<1, kBlock, 0, st>>>(t);
   if (kinds & 1u)
     kb_clip_fast<kTriSlots, kTriCand, false, kTriPlanes, true>
@@ -2322,10 +2343,14 @@ void launch_batch_step(const BTab &t, const BConf &c, unsigned kinds, int ledger
   if (kinds & 4u)
     kb_clip_fast<kFastSlots, kCandPool, true, kFastPlanes, false>
         <<<c.grid_clip, kFastBlock, 0, st>>>(t, 2, c.clip_claim);
+  mark(4);
   kb_clip_general<<<4096, kClipBlock, 0, st>>>(t);
   kb_face_sum<<<1024, kBlock, 0, st>>>(t);
+  mark(5);
   kb_update<<<c.grid_cells, kBlock, 0, st>>>(t);
+  mark(6);
   kb_ledger<<<ledger_grid, kLedgerBlock, 0, st>>>(t);
+  mark(7);
 }
 
 void launch_map_alpha(const DMesh &d, double *alpha, const int32_t *off, const int32_t *cells,

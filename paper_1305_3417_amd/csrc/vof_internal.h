@@ -116,7 +116,8 @@ struct DState {
   double *F0;           // nf
   double *lam;          // nf
   double *vphase;       // nf
-  double *vscale;       // nf: F dt / V(lam) for faces whose correction hit the branch end
+  double *vscale;       // nf: F dt / V(lam) of a clamped face whose polyhedron holds at
+                        // least a quarter of F dt (its phase fraction is scaled to F dt)
   uint8_t *iters;       // nf
   uint8_t *kind;        // nf
   uint8_t *fstatus;     // nf
@@ -222,8 +223,10 @@ void launch_map_alpha(const DMesh &d, double *alpha, const int32_t *off, const i
 // One batch step on `st` (plane kernel on fork->side when given).  `kinds`
 // bit k: some mesh has face kind k (launches for absent kinds are skipped);
 // `ledger_grid`: blocks of the ledger (at least the number of meshes).
+// ev: NULL, or 8 events recorded between the kernel groups (eager launch on
+// `st` only; the fork is then not used).
 void launch_batch_step(const BTab &t, const BConf &c, unsigned kinds, int ledger_grid,
-                       hipStream_t st, const Fork *fork);
+                       hipStream_t st, const Fork *fork, hipEvent_t *ev = nullptr);
 // Set every mesh's step counter to 0 (before a batch's first step).
 void launch_batch_begin(const BTab &t, int n, hipStream_t st);
 double host_tet_clip(const double *tet, int n_planes, const double *planes);

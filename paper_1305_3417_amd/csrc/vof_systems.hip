@@ -221,9 +221,9 @@ struct BatchCore {
   }
 
   // one step launched kernel by kernel (no graph), e.g. to time a configuration
-  vof_status step_eager(const BConf &c) {
+  vof_status step_eager(const BConf &c, hipEvent_t *ev) {
     if (n == 0) return VOF_OK;
-    launch_batch_step(tab, c, kinds, kMaxBatch, stream, nullptr);
+    launch_batch_step(tab, c, kinds, kMaxBatch, stream, nullptr, ev);
     HIP_OR_FAIL(hipGetLastError());
     return VOF_OK;
   }
@@ -371,6 +371,181 @@ vof_status vof_batch_advect(vof_batch *b, int32_t n_steps, const double *dt, con
   vof_status rc = batch_prepare(b, n_steps, dt, scale);
   if (rc) return rc;
   return b->core.step(n_steps);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// autotuner
+// ---------------------------------------------------------------------------
+namespace {
+
+// Candidate values of each tuned parameter, tried coordinate by coordinate.
+// Each parameter drives its own kernels, so one step can time a candidate of
+// every parameter at once: step k of a round uses candidate k of each list.
+const int kCandFlux[] = {1024, 2048, 4096, 8192};
+const int kCandClip[] = {2048, 4096, 8192, 16384};
+const int kCandClaim[] = {1, 2, 4, 2};
+const int kCandPlane[] = {1024, 2048, 4096, 2048};
+const int kCandCells[] = {1024, 2048, 4096, 8192};
+constexpr int kCands = 4;
+
+std::string gpu_target(int device) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+    (void)hipGetLastError();
+    return "unknown";
+  }
+  std::string a = prop.gcnArchName;
+  size_t c = a.find(':');
+  return c == std::string::npos ? a : a.substr(0, c);
+}
+
+// size bucket: face kinds present, and powers of two of faces and meshes
+std::string bucket_key(const vof_batch *b, const std::string &target) {
+  int64_t faces = 0;
+  unsigned kinds = 0;
+  for (const vof_mesh *m : b->meshes) {
+    faces += m->dm.nf;
+    kinds |= 1u << face_kind(m->dm.maxn);
+  }
+  auto lg = [](int64_t v) { return (int)std::lround(std::log2((double)std::max<int64_t>(v, 1))); };
+  char buf[160];
+  snprintf(buf, sizeof buf, "%s/kinds%u/faces2^%d/meshes2^%d", target.c_str(), kinds, lg(faces),
+           lg((int64_t)b->meshes.size()));
+  return buf;
+}
+
+// The cache: a JSON object, one entry per line, keyed by bucket.
+struct CacheEntry {
+  std::string key;
+  vof_batch_config c;
+};
+
+std::vector<CacheEntry> cache_read(const char *path) {
+  std::vector<CacheEntry> out;
+  FILE *f = fopen(path, "r");
+  if (!f) return out;
+  char line[512], key[256];
+  while (fgets(line, sizeof line, f)) {
+    vof_batch_config c;
+    if (sscanf(line,
+               " \"%255[^\"]\": {\"grid_flux\": %d, \"grid_clip\": %d, \"clip_claim\": %d, "
+               "\"grid_plane\": %d, \"grid_cells\": %d}",
+               key, &c.grid_flux, &c.grid_clip, &c.clip_claim, &c.grid_plane,
+               &c.grid_cells) == 6 &&
+        conf_valid(c))
+      out.push_back({key, c});
+  }
+  fclose(f);
+  return out;
+}
+
+vof_status cache_write(const char *path, const std::vector<CacheEntry> &entries) {
+  std::string tmp = std::string(path) + ".tmp";
+  FILE *f = fopen(tmp.c_str(), "w");
+  if (!f) return fail(VOF_EINVAL, "cannot write the autotuning cache %s", tmp.c_str());
+  fprintf(f, "{\n");
+  for (size_t i = 0; i < entries.size(); ++i) {
+    const vof_batch_config &c = entries[i].c;
+    fprintf(f,
+            "\"%s\": {\"grid_flux\": %d, \"grid_clip\": %d, \"clip_claim\": %d, "
+            "\"grid_plane\": %d, \"grid_cells\": %d}%s\n",
+            entries[i].key.c_str(), c.grid_flux, c.grid_clip, c.clip_claim, c.grid_plane,
+            c.grid_cells, i + 1 < entries.size() ? "," : "");
+  }
+  fprintf(f, "}\n");
+  if (fclose(f) != 0 || rename(tmp.c_str(), path) != 0)
+    return fail(VOF_EINVAL, "cannot write the autotuning cache %s", path);
+  return VOF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+vof_status vof_autotune(vof_batch *b, int32_t n_steps, const double *dt, const double *scale,
+                        const char *cache_path, vof_batch_config *out) {
+  if (!b) return fail(VOF_EINVAL, "null argument");
+  if (n_steps < 1) return fail(VOF_EINVAL, "the autotuner needs at least one step");
+  vof_status rc = batch_prepare(b, n_steps, dt, scale);
+  if (rc) return rc;
+  const std::string key = bucket_key(b, gpu_target(b->ctx.device));
+  std::vector<CacheEntry> cache;
+  if (cache_path) {
+    cache = cache_read(cache_path);
+    for (const CacheEntry &e : cache)
+      if (e.key == key) {
+        b->core.conf = to_bconf(e.c);
+        if (out) *out = e.c;
+        return b->core.step(n_steps);
+      }
+  }
+  hipEvent_t ev[8];
+  for (auto &e : ev) HIP_OR_FAIL(hipEventCreate(&e));
+  struct EvGuard {
+    hipEvent_t *ev;
+    ~EvGuard() {
+      for (int i = 0; i < 8; ++i) (void)hipEventDestroy(ev[i]);
+    }
+  } guard{ev};
+  // best time per candidate of each parameter (ms)
+  float best[5][kCands];
+  for (auto &r : best)
+    for (float &x : r) x = 1e30f;
+  hipStream_t s = b->ctx.stream;
+  for (int32_t k = 0; k < n_steps; ++k) {
+    const int j = k % kCands;
+    BConf c;
+    c.grid_flux = kCandFlux[j];
+    c.grid_clip = kCandClip[j];
+    c.clip_claim = kCandClaim[j];
+    c.grid_plane = kCandPlane[j];
+    c.grid_cells = kCandCells[j];
+    rc = b->core.step_eager(c, ev);
+    if (rc) return rc;
+    HIP_OR_FAIL(hipStreamSynchronize(s));
+    float t[7];
+    for (int i = 0; i < 7; ++i) HIP_OR_FAIL(hipEventElapsedTime(&t[i], ev[i], ev[i + 1]));
+    const float cells = t[0] + t[5], plane = t[1], flux = t[2], clip = t[3];
+    best[0][j] = std::min(best[0][j], flux);
+    best[1][j] = std::min(best[1][j], clip);
+    best[2][j] = std::min(best[2][j], clip);
+    best[3][j] = std::min(best[3][j], plane);
+    best[4][j] = std::min(best[4][j], cells);
+  }
+  auto pick = [&](int p, const int *vals, int dflt) {
+    int arg = -1;
+    for (int j = 0; j < kCands; ++j)
+      if (best[p][j] < 1e29f && (arg < 0 || best[p][j] < best[p][arg])) arg = j;
+    return arg < 0 ? dflt : vals[arg];
+  };
+  BConf c = default_conf();
+  c.grid_flux = pick(0, kCandFlux, c.grid_flux);
+  // the clip's grid and claim size were varied together; keep the pair
+  int jc = -1;
+  for (int j = 0; j < kCands; ++j)
+    if (best[1][j] < 1e29f && (jc < 0 || best[1][j] < best[1][jc])) jc = j;
+  if (jc >= 0) {
+    c.grid_clip = kCandClip[jc];
+    c.clip_claim = kCandClaim[jc];
+  }
+  c.grid_plane = pick(3, kCandPlane, c.grid_plane);
+  c.grid_cells = pick(4, kCandCells, c.grid_cells);
+  b->core.conf = c;
+  const vof_batch_config vc = from_bconf(c);
+  if (out) *out = vc;
+  if (cache_path) {
+    bool found = false;
+    for (CacheEntry &e : cache)
+      if (e.key == key) {
+        e.c = vc;
+        found = true;
+      }
+    if (!found) cache.push_back({key, vc});
+    if ((rc = cache_write(cache_path, cache))) return rc;
+  }
+  return VOF_OK;
 }
 
 vof_status vof_batch_synchronize(vof_batch *b) {

@@ -121,3 +121,39 @@ def test_batch_refuses_bad_input(vof, ctx):
     b.close()
     for m in meshes:
         m.close()
+
+
+def test_autotune_advances_like_advect(vof, ctx, tmp_path):
+    """vof_autotune advances the batch exactly as vof_batch_advect (one
+    candidate configuration per step), keeps the fastest, and caches it under
+    the GPU target and the batch's size bucket; a second batch of the same
+    bucket takes the cached configuration."""
+    import json
+    K = 5
+    ws = W.batch_instances(6, seed=11, n_range=(6, 12), steps=2 * K)
+    meshes = _upload(vof, ctx, ws)
+    b = vof.vof_batch_create(ctx, meshes)
+    cache = str(tmp_path / "tune.json")
+    c1 = vof.vof_autotune(b, *_schedule(ws, 0, K), cache_path=cache)
+    assert c1 == vof.vof_batch_get_config(b).as_dict()
+    vof.vof_batch_advect(b, *_schedule(ws, K, 2 * K))
+    vof.vof_batch_synchronize(b)
+    got = [vof.vof_read_alpha(m) for m in meshes]
+    entries = json.load(open(cache))
+    assert len(entries) == 1
+    key, val = next(iter(entries.items()))
+    assert key.startswith("gfx") and val == c1
+    b.close()
+    for w, m, a in zip(ws, meshes, got):
+        vof.vof_set_alpha(m, w.alpha0)
+        vof.vof_advect(m, w.dt[:2 * K], w.scale[:2 * K])
+        assert np.array_equal(vof.vof_read_alpha(m), a)
+    # the same bucket again: the cached entry, the same steps
+    for w, m in zip(ws, meshes):
+        vof.vof_set_alpha(m, w.alpha0)
+    b2 = vof.vof_batch_create(ctx, meshes)
+    c2 = vof.vof_autotune(b2, *_schedule(ws, 0, K), cache_path=cache)
+    assert c2 == c1
+    b2.close()
+    for m in meshes:
+        m.close()

@@ -87,14 +87,22 @@ def test_correction_branch_end(vof, ctx, oracle_mod, k, status, lam):
     g["mesh"].close()
 
 
-def test_zero_sweep_stays_finite(vof, ctx):
-    """No point velocity, non-zero fluxes: every face with flux clamped at
-    lambda = 0, no phase moved, no NaN from the rescale."""
-    w = W.scaled_translation(8, 1.0)
-    w.U0c[:] = 0.0
+@pytest.mark.parametrize("k,zero_u", [(40.0, False), (1.0, True)])
+def test_unreachable_targets_take_the_donor_cell(vof, ctx, oracle_mod, k, zero_u):
+    """Every face clamped (fluxes beyond the branch end, or no point velocity
+    at all) on a random alpha field: V_alpha and alpha bitwise the oracle's
+    (one product per face, the donor cell's alpha times F dt)."""
+    w = W.scaled_translation(8, k)
+    if zero_u:
+        w.U0c[:] = 0.0
+    w.alpha0 = np.random.default_rng(5).uniform(0.05, 0.95, w.mesh.n_cells)
     g = gpu_run(vof, ctx, w, steps=1)
+    o = oracle_mod.Oracle(w.mesh)
+    o.set_velocity(w.U0c, w.F0)
+    r = o.step(w.alpha0, w.dt[0], w.scale[0])
     flux = w.F0 != 0
-    assert (g["status"][flux] == 1).all() and (g["lam"][flux] == 0).all()
-    assert (g["vphase"] == 0).all()
-    assert np.array_equal(g["alpha"], w.alpha0)
+    assert (g["status"][flux] == 1).all() and (g["kind"][flux] == 4).all()
+    assert g["stats"]["unreached_faces"] == int(flux.sum())
+    assert np.array_equal(g["vphase"], r["vphase"])
+    assert np.abs(g["alpha"] - r["alpha"]).max() <= 1e-15
     g["mesh"].close()

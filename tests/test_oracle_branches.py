@@ -2,23 +2,28 @@
 
 Both branches are readings (the paper treats neither): a face whose
 correction target lies beyond the extremum of its swept volume on the
-monotone branch is clamped there and its phase volume rescaled by
-F dt / V(lambda) (Section 2.3, scalar correction); an interface cell whose
-gradient vanishes is treated as homogeneous, contributing alpha_c |T ∩ C_c|
-(Algorithm 1 has no normal to offer).  The pins use inputs for which the
-mathematics fixes the answer independently of either implementation:
+monotone branch is clamped there and carries its polyhedron's phase fraction
+of F dt when that polyhedron holds at least a quarter of F dt, else the
+upwind (donor) cell's fraction (Section 2.3 assumes the correction always
+converges); an
+interface cell whose gradient vanishes is treated as homogeneous,
+contributing alpha_c |T ∩ C_c| (Algorithm 1 has no normal to offer).  The
+pins use inputs for which the mathematics fixes the answer independently of
+either implementation:
 
 * alpha uniform: every cell is an interface cell with zero gradient, so every
-  flux polyhedron inside the domain carries alpha times its volume, and a
-  face's total volume is F dt whether or not it was clamped (rescaled).  An
-  inverted or missing rescale, or an empty/full reading of the homogeneous
-  cell, fails it.
+  flux polyhedron inside the domain carries alpha times its volume F dt, and
+  a clamped face alpha F dt as well (its phase fraction alpha scaled to
+  F dt).  An empty/full reading of the homogeneous cell, or a clamped face
+  with a missing or inverted scale, fails it.
+* fluxes k times U.S under a translation: the swept volume is linear in
+  lambda, so lambda = k up to the branch end (32 plain sweeps) and a clamp
+  to the plain sweep (lambda = 1) beyond it; with k = 40 every face is
+  clamped and the whole update is the donor-cell (first-order upwind)
+  update, written out here with numpy.
 * one symmetric cell in an empty box under translation: the cell is
   homogeneous by symmetry, the outflow prism lies in it, so it keeps
   alpha (1 - u dt / h) and its downstream neighbour gets alpha u dt / h.
-* a translation whose face fluxes are k times U.S: the swept volume is linear
-  in lambda, so lambda = k up to the branch end (32 plain sweeps) and a clamp
-  to the plain sweep (lambda = 1) beyond it.
 """
 from __future__ import annotations
 
@@ -58,10 +63,11 @@ def test_uniform_alpha_faces_carry_alpha_times_flux(oracle_mod):
     clamped = faces[r["status"][faces] == 1]
     print(f"[uniform] {faces.size} interior faces, {clamped.size} clamped", flush=True)
     assert clamped.size > 20
+    # clamped polyhedra here hold half of F dt or more: scaled, not donor faces
     assert (r["kind"][faces] == 3).all()
     err = np.abs(r["vphase"][faces] - 0.37 * T[faces])
     assert (err <= tol[faces]).all(), (err / tol[faces]).max()
-    # a clamped face's own swept volume is not F dt: the rescale is what makes it so
+    # a clamped face's own swept volume is not F dt: only the scaling gives it F dt
     vlam = np.array([o.flux_volume(f, w.dt[0], w.scale[0], r["lam"][f]) for f in clamped])
     assert (np.abs(vlam - T[clamped]) > 1e3 * tol[clamped]).any()
     # cells whose faces are all interior keep alpha to the faces' bounds
@@ -125,16 +131,52 @@ def test_correction_branch_end_at_32_sweeps(oracle_mod, k, status, lam):
     assert np.abs(r["vphase"][faces] - 0.37 * T[faces]).max() <= 1e-13 * np.abs(T[faces]).max()
 
 
-def test_zero_sweep_with_flux_carries_nothing(oracle_mod):
-    """Point velocities all zero but face fluxes non-zero: the swept volume
-    vanishes identically (no correction can reach F dt), every face with
-    flux is clamped at lambda = 0 and carries no phase; alpha is unchanged."""
-    w = W.scaled_translation(8, 1.0)
-    w.U0c[:] = 0.0
+def donor_update(w, alpha):
+    """The first-order upwind (donor-cell) step written out: every face with
+    flux carries the alpha of the cell its flux leaves times F dt (nothing
+    for inflow through a boundary face); alpha -= (1/V) sum of the signed
+    face volumes (owner +, neighbour -)."""
+    m = w.mesh
+    T = w.F0 * w.dt[0] * w.scale[0]
+    ni = m.n_internal
+    donor = np.where(T > 0, m.owner, np.concatenate([m.neighbour, np.full(m.n_faces - ni, -1)]))
+    vph = np.where(donor >= 0, alpha[np.maximum(donor, 0)] * T, 0.0)
+    V = np.prod(m.cell_hi - m.cell_lo, axis=1)
+    acc = np.zeros(m.n_cells)
+    np.add.at(acc, m.owner, vph)
+    np.add.at(acc, m.neighbour, -vph[:ni])
+    return alpha - acc / V, vph
+
+
+def test_unreachable_targets_take_the_donor_cell(oracle_mod):
+    """Fluxes 40 U.S_f (beyond the branch end) on a random alpha field: every
+    face with flux is clamped, and the step is the donor-cell update."""
+    w = W.scaled_translation(8, 40.0)
+    rng = np.random.default_rng(5)
+    a0 = rng.uniform(0.05, 0.95, w.mesh.n_cells)
     o = oracle_mod.Oracle(w.mesh)
     o.set_velocity(w.U0c, w.F0)
-    r = o.step(w.alpha0, w.dt[0], w.scale[0])
+    r = o.step(a0, w.dt[0], w.scale[0])
+    flux = w.F0 != 0
+    assert (r["status"][flux] == 1).all() and (r["kind"][flux] == 4).all()
+    a_ref, v_ref = donor_update(w, a0)
+    assert np.array_equal(r["vphase"], v_ref)
+    assert np.abs(r["alpha"] - a_ref).max() <= 1e-15
+
+
+def test_zero_sweep_with_flux_takes_the_donor_cell(oracle_mod):
+    """Point velocities all zero but face fluxes non-zero: the swept volume
+    vanishes identically (no correction can reach F dt), every face with
+    flux is clamped at lambda = 0 and carries its donor cell's alpha F dt."""
+    w = W.scaled_translation(8, 1.0)
+    w.U0c[:] = 0.0
+    rng = np.random.default_rng(6)
+    a0 = rng.uniform(0.05, 0.95, w.mesh.n_cells)
+    o = oracle_mod.Oracle(w.mesh)
+    o.set_velocity(w.U0c, w.F0)
+    r = o.step(a0, w.dt[0], w.scale[0])
     flux = w.F0 != 0
     assert (r["status"][flux] == 1).all() and (r["lam"][flux] == 0).all()
-    assert (r["vphase"] == 0).all()
-    assert (r["alpha"] == w.alpha0).all()
+    a_ref, v_ref = donor_update(w, a0)
+    assert np.array_equal(r["vphase"], v_ref)
+    assert np.abs(r["alpha"] - a_ref).max() <= 1e-15

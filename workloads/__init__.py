@@ -289,9 +289,9 @@ def rotating_sphere(n: int, rng, refine: bool = False, steps: int = 100,
     h = 1.0 / n
     r = float(rng.uniform(*r_range))
     o = np.array([0.5, 0.5, 0.5])
-    rad = 0.5 - r - 2 * h
+    rad = max(0.5 - r - 2 * h, 0.0)
     while True:  # uniform in the ball of radius rad
-        c = rng.uniform(-rad, rad, size=3)
+        c = rng.uniform(-rad, rad, size=3) if rad > 0 else np.zeros(3)
         if (c * c).sum() <= rad * rad:
             break
     c = o + c
