@@ -56,6 +56,8 @@ typedef int32_t vof_status;
 #define VOF_EDEVICE (-4)   /* HIP runtime error; destroy the context             */
 #define VOF_ENUMERIC (-5)  /* a non-finite value was produced                   */
 #define VOF_ESTENCIL (-6)  /* a flux polyhedron left its stencil (leak check)   */
+#define VOF_EBUSY (-7)     /* server: the job can never fit its budget, or the
+                              queue is full                                      */
 #define VOF_ECAPACITY (-8) /* a clipped polytope exceeded its vertex capacity   */
 
 #define VOF_HOST 0
@@ -355,6 +357,62 @@ vof_status vof_batch_set_config(vof_batch *batch, const vof_batch_config *config
  * cannot be written. */
 vof_status vof_autotune(vof_batch *batch, int32_t n_steps, const double *dt,
                         const double *scale, const char *cache_path, vof_batch_config *out);
+
+/* ---- Served form ---------------------------------------------------------
+ * A request loop over advection jobs of different meshes and lengths.  A job
+ * is (mesh, alpha0, velocity, schedule of n_steps steps); the mesh is one
+ * uploaded with vof_mesh_upload, whose addressing and geometry the job reads
+ * (never writes) and which must outlive it -- any number of jobs may share a
+ * mesh.  Each job gets its own state (alpha, planes, face results, scratch,
+ * its copy of the inputs) in a device arena of a fixed size, the HBM budget
+ * given at creation: jobs are admitted in arrival order while their state
+ * fits the free budget (and at most VOF_MAX_BATCH are resident), stay
+ * resident until their last step, and leave; the arena block is reused by the
+ * next admitted job.  A worker thread runs ticks: one batched step (as
+ * vof_batch_advect) of every resident job, so jobs that arrive while others
+ * run join at the next tick and their steps share the launches (continuous
+ * batching).  Every job's final alpha is bitwise that of vof_advect of the
+ * same inputs on the mesh alone.  Meshes' parameters apply to their jobs;
+ * wisps, narrow band and stencil check must be off.  All server work goes on
+ * a stream of its own on the context's device. */
+typedef struct vof_server vof_server;
+typedef struct vof_job vof_job;
+
+typedef struct {
+  int64_t jobs_done;        /* jobs finished (their alpha copied to the host)  */
+  int64_t jobs_waiting;     /* submitted, not yet admitted                     */
+  int64_t face_fluxes;      /* sum over finished jobs of steps x faces with flux */
+  int64_t ticks;            /* batched steps run                               */
+  double latency_p50_s;     /* finish - submission, over finished jobs         */
+  double latency_p99_s;
+  double latency_max_s;
+  double face_fluxes_per_s; /* face_fluxes / (last finish - first submission)  */
+  int32_t max_resident;     /* most jobs resident at one tick                  */
+  int64_t budget_bytes;     /* the arena                                       */
+  int64_t peak_bytes;       /* most of it held at once                         */
+} vof_server_stats;
+
+/* Reserve hbm_budget_bytes of device memory (at least 1 MiB) and start the
+ * worker.  Errors: VOF_EINVAL, VOF_ENOMEM, VOF_EDEVICE. */
+vof_status vof_server_create(vof_context *ctx, int64_t hbm_budget_bytes, vof_server **out);
+/* Queue a job: alpha0 (n_cells), U0c (3 n_cells, x y z interleaved), F0
+ * (n_faces; step k uses scale[k] U0c, scale[k] F0 and length dt[k], k <
+ * n_steps) -- host arrays, copied before return.  Returns at once with a
+ * handle that must be passed to vof_server_wait.  Errors: VOF_EINVAL,
+ * VOF_EBUSY (the job's state alone exceeds the budget, or 4096 jobs wait),
+ * or the error that stopped the server. */
+vof_status vof_server_submit(vof_server *server, vof_mesh *mesh, const double *alpha0,
+                             const double *U0c, const double *F0, int32_t n_steps,
+                             const double *dt, const double *scale, vof_job **job);
+/* Block until the job has finished; copy its final alpha to alpha_out (host,
+ * n_cells; may be NULL) and its latency (finish - submission, seconds) to
+ * latency_s (may be NULL); release the job.  Returns VOF_ECAPACITY if one of
+ * its clipped polytopes overflowed, or the error that stopped the server. */
+vof_status vof_server_wait(vof_job *job, double *alpha_out, double *latency_s);
+vof_status vof_server_get_stats(vof_server *server, vof_server_stats *out);
+/* Finish every submitted job, stop the worker and release the arena.  Jobs
+ * not waited for are released without their results. */
+vof_status vof_server_destroy(vof_server *server);
 
 /* Host self-test of the device geometry routines (compiled for the host as
  * well): volume of the tetrahedron (a, b, c, d) (12 doubles) intersected with

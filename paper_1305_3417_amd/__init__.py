@@ -49,7 +49,10 @@ EXPORTED = [
     "vof_selftest_tet_clip", "vof_selftest_tet_clip_closed", "vof_profile_enable", "vof_profile_kernel_name", "vof_read_profile",
     "vof_batch_create", "vof_batch_destroy", "vof_batch_advect", "vof_batch_synchronize",
     "vof_batch_get_config", "vof_batch_set_config", "vof_autotune",
+    "vof_server_create", "vof_server_submit", "vof_server_wait", "vof_server_get_stats",
+    "vof_server_destroy",
 ]
+VOF_EBUSY = -7
 VOF_MAX_BATCH = 256
 
 
@@ -105,6 +108,18 @@ class vof_batch_config(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class vof_server_stats_t(C.Structure):
+    _fields_ = [("jobs_done", C.c_int64), ("jobs_waiting", C.c_int64),
+                ("face_fluxes", C.c_int64), ("ticks", C.c_int64),
+                ("latency_p50_s", C.c_double), ("latency_p99_s", C.c_double),
+                ("latency_max_s", C.c_double), ("face_fluxes_per_s", C.c_double),
+                ("max_resident", C.c_int32), ("budget_bytes", C.c_int64),
+                ("peak_bytes", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -152,6 +167,11 @@ def lib():
             "vof_batch_get_config": (i32, [vp, C.POINTER(vof_batch_config)]),
             "vof_batch_set_config": (i32, [vp, C.POINTER(vof_batch_config)]),
             "vof_autotune": (i32, [vp, i32, vp, vp, C.c_char_p, C.POINTER(vof_batch_config)]),
+            "vof_server_create": (i32, [vp, i64, C.POINTER(vp)]),
+            "vof_server_submit": (i32, [vp, vp, vp, vp, vp, i32, vp, vp, C.POINTER(vp)]),
+            "vof_server_wait": (i32, [vp, vp, C.POINTER(d)]),
+            "vof_server_get_stats": (i32, [vp, C.POINTER(vof_server_stats_t)]),
+            "vof_server_destroy": (i32, [vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -535,3 +555,78 @@ def vof_autotune(batch: BatchHandle, dt, scale, cache_path=None) -> dict:
                               scale.ctypes.data_as(C.c_void_p), path, C.byref(c)),
            "vof_autotune")
     return c.as_dict()
+
+
+# ---------------------------------------------------------------------------
+# served form
+# ---------------------------------------------------------------------------
+
+class ServerHandle:
+    def __init__(self, h):
+        self.h = h
+
+    def close(self):
+        if self.h:
+            lib().vof_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class JobHandle:
+    def __init__(self, h, n_cells, keep):
+        self.h = h
+        self.n_cells = n_cells
+        self._keep = keep
+
+
+def vof_server_create(ctx, hbm_budget_bytes: int) -> ServerHandle:
+    h = C.c_void_p()
+    _check(lib().vof_server_create(ctx, int(hbm_budget_bytes), C.byref(h)), "vof_server_create")
+    return ServerHandle(h)
+
+
+def vof_server_destroy(server: ServerHandle):
+    server.close()
+
+
+def vof_server_submit(server: ServerHandle, mesh: MeshHandle, alpha0, U0c, F0, dt, scale,
+                      ok=(VOF_OK,)):
+    """Queue a job; returns a JobHandle (or None when the call returns a code
+    listed in `ok` other than VOF_OK, e.g. VOF_EBUSY)."""
+    a = np.ascontiguousarray(alpha0, dtype=np.float64)
+    u = np.ascontiguousarray(U0c, dtype=np.float64)
+    f = np.ascontiguousarray(F0, dtype=np.float64)
+    dt = np.ascontiguousarray(dt, dtype=np.float64)
+    sc = np.ascontiguousarray(scale, dtype=np.float64)
+    if a.shape[0] != mesh.n_cells or u.size != 3 * mesh.n_cells or f.shape[0] != mesh.n_faces:
+        raise ValueError("alpha0 (n_cells), U0c (n_cells, 3), F0 (n_faces)")
+    if dt.shape != sc.shape or dt.ndim != 1:
+        raise ValueError("dt and scale must be 1-D arrays of equal length")
+    h = C.c_void_p()
+    p = lambda x: x.ctypes.data_as(C.c_void_p)  # noqa: E731
+    rc = _check(lib().vof_server_submit(server.h, mesh.h, p(a), p(u), p(f), int(dt.shape[0]),
+                                        p(dt), p(sc), C.byref(h)), "vof_server_submit", ok)
+    return JobHandle(h, mesh.n_cells, mesh) if rc == VOF_OK else None
+
+
+def vof_server_wait(job: JobHandle, alpha_out=None):
+    """Block until the job has finished; returns (alpha, latency in seconds)."""
+    out = np.empty(job.n_cells) if alpha_out is None else alpha_out
+    lat = C.c_double()
+    h, job.h = job.h, None
+    _check(lib().vof_server_wait(h, out.ctypes.data_as(C.c_void_p), C.byref(lat)),
+           "vof_server_wait")
+    return out, lat.value
+
+
+def vof_server_get_stats(server: ServerHandle) -> dict:
+    st = vof_server_stats_t()
+    _check(lib().vof_server_get_stats(server.h, C.byref(st)), "vof_server_get_stats")
+    return st.as_dict()

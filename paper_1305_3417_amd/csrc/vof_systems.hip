@@ -560,3 +560,515 @@ vof_status vof_batch_synchronize(vof_batch *b) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// served form
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
+
+// The per-job state of a mesh (everything a step writes, and the job's own
+// inputs) laid out in one block of the server's arena.
+struct StateLayout {
+  size_t alpha, cls, plane, pmask, alpha_p, U, XU, F0, lam, vphase, vscale, iters, kind, fstatus,
+      icells, gfaces, tetvol, defer, work, cnt, flags, ledger, part, stepno, dt, sc, bytes;
+};
+
+StateLayout state_layout(const DMesh &m, int64_t steps) {
+  StateLayout L;
+  size_t o = 0;
+  auto take = [&](size_t n) {
+    size_t at = o;
+    o += align_up(n > 0 ? n : 1);
+    return at;
+  };
+  const size_t nc = (size_t)m.nc, np = (size_t)m.np, nf = (size_t)m.nf, tpf = (size_t)m.tpf;
+  L.alpha = take(8 * nc);
+  L.cls = take(nc);
+  L.plane = take(32 * nc);
+  L.pmask = take(np);
+  L.alpha_p = take(8 * np);
+  L.U = take(32 * np);
+  L.XU = take(48 * np);
+  L.F0 = take(8 * nf);
+  L.lam = take(8 * nf);
+  L.vphase = take(8 * nf);
+  L.vscale = take(8 * nf);
+  L.iters = take(nf);
+  L.kind = take(nf);
+  L.fstatus = take(nf);
+  L.icells = take(4 * nc);
+  L.gfaces = take(4 * nf);
+  L.tetvol = take(8 * nf * tpf);
+  L.defer = take(4 * nf * tpf);
+  L.work = take(4 * kWNum);
+  L.cnt = take(8 * (size_t)kCntWords);
+  L.flags = take(4);
+  L.ledger = take(8);
+  const size_t nparts = std::max<size_t>((nc + 255) / 256, 256);
+  L.part = take(8 * nparts);
+  L.stepno = take(4);
+  L.dt = take(8 * (size_t)steps);
+  L.sc = take(8 * (size_t)steps);
+  L.bytes = o;
+  return L;
+}
+
+DState state_at(const StateLayout &L, char *b) {
+  DState s{};
+  s.alpha = (double *)(b + L.alpha);
+  s.cls = (int8_t *)(b + L.cls);
+  s.plane = (double4 *)(b + L.plane);
+  s.pmask = (uint8_t *)(b + L.pmask);
+  s.alpha_p = (double *)(b + L.alpha_p);
+  s.U = (double4 *)(b + L.U);
+  s.XU = (double *)(b + L.XU);
+  s.F0 = (double *)(b + L.F0);
+  s.lam = (double *)(b + L.lam);
+  s.vphase = (double *)(b + L.vphase);
+  s.vscale = (double *)(b + L.vscale);
+  s.iters = (uint8_t *)(b + L.iters);
+  s.kind = (uint8_t *)(b + L.kind);
+  s.fstatus = (uint8_t *)(b + L.fstatus);
+  s.icells = (int32_t *)(b + L.icells);
+  s.gfaces = (int32_t *)(b + L.gfaces);
+  s.tetvol = (double *)(b + L.tetvol);
+  s.defer = (int32_t *)(b + L.defer);
+  s.work = (int32_t *)(b + L.work);
+  s.cnt = (unsigned long long *)(b + L.cnt);
+  s.flags = (uint32_t *)(b + L.flags);
+  s.ledger = (double *)(b + L.ledger);
+  s.part = (double *)(b + L.part);
+  s.stepno = (int32_t *)(b + L.stepno);
+  s.dt = (double *)(b + L.dt);
+  s.sc = (double *)(b + L.sc);
+  return s;
+}
+
+// First-fit allocator over the server's budget (offsets, kAlign multiples).
+struct Arena {
+  size_t size = 0, used = 0, peak = 0;
+  std::vector<std::pair<size_t, size_t>> free_;  // (offset, length), sorted, coalesced
+  void init(size_t n) {
+    size = n / kAlign * kAlign;
+    free_.assign(1, {0, size});
+  }
+  bool alloc(size_t n, size_t &off) {
+    n = align_up(n);
+    for (size_t i = 0; i < free_.size(); ++i)
+      if (free_[i].second >= n) {
+        off = free_[i].first;
+        free_[i].first += n;
+        free_[i].second -= n;
+        if (free_[i].second == 0) free_.erase(free_.begin() + (long)i);
+        used += n;
+        peak = std::max(peak, used);
+        return true;
+      }
+    return false;
+  }
+  void release(size_t off, size_t n) {
+    n = align_up(n);
+    used -= n;
+    auto it = std::lower_bound(free_.begin(), free_.end(), std::make_pair(off, (size_t)0));
+    it = free_.insert(it, {off, n});
+    size_t i = (size_t)(it - free_.begin());
+    if (i + 1 < free_.size() && free_[i].first + free_[i].second == free_[i + 1].first) {
+      free_[i].second += free_[i + 1].second;
+      free_.erase(free_.begin() + (long)i + 1);
+    }
+    if (i > 0 && free_[i - 1].first + free_[i - 1].second == free_[i].first) {
+      free_[i - 1].second += free_[i].second;
+      free_.erase(free_.begin() + (long)i);
+    }
+  }
+};
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+enum JobState { kPending = 0, kResident, kDraining, kDone };
+
+}  // namespace
+
+struct vof_job {
+  vof_server *srv = nullptr;
+  vof_mesh *mesh = nullptr;
+  std::vector<double> alpha0, U0c, F0, dt, sc;
+  int32_t steps = 0, done_steps = 0;
+  int64_t nflux = 0;
+  StateLayout L{};
+  size_t off = 0;
+  DState ds{};
+  double *h_out = nullptr;  // pinned: alpha, then the flags word
+  hipEvent_t ev = nullptr;
+  double t_arrive = 0, t_admit = 0, t_done = 0;
+  JobState state = kPending;
+  vof_status status = VOF_OK;
+};
+
+struct vof_server {
+  vof_context ctx{};
+  hipStream_t stream = nullptr;
+  char *arena_base = nullptr;
+  Arena arena;
+  BatchCore core;
+  std::thread worker;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<vof_job *> pending;
+  std::vector<vof_job *> resident, draining;
+  bool stop = false;
+  vof_status error = VOF_OK;
+  std::string error_msg;
+  // statistics (under mu)
+  std::vector<double> latencies;
+  int64_t face_fluxes = 0, jobs_done = 0, ticks = 0;
+  int32_t max_resident = 0;
+  double t_first_arrival = -1, t_last_done = 0;
+  hipEvent_t tick_ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  int tick_slot = 0;
+};
+
+namespace {
+
+// Stage a job's inputs into its block of the arena (in stream order).
+vof_status job_admit(vof_server *S, vof_job *j) {
+  hipStream_t s = S->stream;
+  j->ds = state_at(j->L, S->arena_base + j->off);
+  const DMesh &m = j->mesh->dm;
+  DState &d = j->ds;
+  HIP_OR_FAIL(hipMemsetAsync(d.work, 0, 4 * kWNum, s));
+  HIP_OR_FAIL(hipMemsetAsync(d.cnt, 0, 8 * (size_t)kCntWords, s));
+  HIP_OR_FAIL(hipMemsetAsync(d.flags, 0, 4, s));
+  HIP_OR_FAIL(hipMemsetAsync(d.ledger, 0, 8, s));
+  HIP_OR_FAIL(hipMemsetAsync(d.stepno, 0, 4, s));
+  HIP_OR_FAIL(hipMemsetAsync(d.cls, 0, (size_t)m.nc, s));
+  HIP_OR_FAIL(hipMemsetAsync(d.plane, 0, 32 * (size_t)m.nc, s));
+  HIP_OR_FAIL(hipMemsetAsync(d.lam, 0, 8 * (size_t)m.nf, s));
+  HIP_OR_FAIL(hipMemsetAsync(d.vphase, 0, 8 * (size_t)m.nf, s));
+  HIP_OR_FAIL(hipMemcpyAsync(d.alpha, j->alpha0.data(), 8 * (size_t)m.nc, hipMemcpyHostToDevice, s));
+  HIP_OR_FAIL(hipMemcpyAsync(d.F0, j->F0.data(), 8 * (size_t)m.nf, hipMemcpyHostToDevice, s));
+  HIP_OR_FAIL(hipMemcpyAsync(d.dt, j->dt.data(), 8 * (size_t)j->steps, hipMemcpyHostToDevice, s));
+  HIP_OR_FAIL(hipMemcpyAsync(d.sc, j->sc.data(), 8 * (size_t)j->steps, hipMemcpyHostToDevice, s));
+  // the cell velocities are staged in the (not yet used) flux-tet slots
+  double *U0c = d.tetvol;
+  HIP_OR_FAIL(hipMemcpyAsync(U0c, j->U0c.data(), 24 * (size_t)m.nc, hipMemcpyHostToDevice, s));
+  launch_point_velocity(m, U0c, d.U, d.XU, s);
+  HIP_OR_FAIL(hipGetLastError());
+  HIP_OR_FAIL(hipHostMalloc((void **)&j->h_out, 8 * (size_t)m.nc + 8, hipHostMallocDefault));
+  HIP_OR_FAIL(hipEventCreateWithFlags(&j->ev, hipEventDisableTiming));
+  // the host inputs were copied from pageable memory before the calls returned
+  std::vector<double>().swap(j->alpha0);
+  std::vector<double>().swap(j->U0c);
+  std::vector<double>().swap(j->F0);
+  return VOF_OK;
+}
+
+// Enqueue the copy of a finished job's alpha and flags to its pinned buffer.
+vof_status job_drain(vof_server *S, vof_job *j) {
+  const size_t nc = (size_t)j->mesh->dm.nc;
+  HIP_OR_FAIL(hipMemcpyAsync(j->h_out, j->ds.alpha, 8 * nc, hipMemcpyDeviceToHost, S->stream));
+  HIP_OR_FAIL(hipMemcpyAsync(j->h_out + nc, j->ds.flags, 4, hipMemcpyDeviceToHost, S->stream));
+  HIP_OR_FAIL(hipEventRecord(j->ev, S->stream));
+  return VOF_OK;
+}
+
+vof_status server_loop_once(vof_server *S, bool &idle) {
+  idle = false;
+  // finished copies: the jobs are done
+  {
+    std::vector<vof_job *> still;
+    for (vof_job *j : S->draining) {
+      hipError_t q = hipEventQuery(j->ev);
+      if (q == hipErrorNotReady) {
+        still.push_back(j);
+        continue;
+      }
+      if (q != hipSuccess) return fail(VOF_EDEVICE, "server: %s", hipGetErrorString(q));
+      uint32_t fl = 0;
+      std::memcpy(&fl, j->h_out + j->mesh->dm.nc, 4);
+      std::lock_guard<std::mutex> lock(S->mu);
+      j->t_done = now_s();
+      j->status = (fl & kFlagCapacity) ? VOF_ECAPACITY : VOF_OK;
+      j->state = kDone;
+      S->latencies.push_back(j->t_done - j->t_arrive);
+      S->face_fluxes += j->nflux * j->steps;
+      ++S->jobs_done;
+      S->t_last_done = j->t_done;
+      S->cv_done.notify_all();
+    }
+    S->draining.swap(still);
+  }
+  // admission, first come first served, while the budget and the table allow
+  bool changed = false;
+  for (;;) {
+    vof_job *j = nullptr;
+    {
+      std::lock_guard<std::mutex> lock(S->mu);
+      if (S->pending.empty() || (int)S->resident.size() >= kMaxBatch) break;
+      j = S->pending.front();
+      size_t off = 0;
+      if (!S->arena.alloc(j->L.bytes, off)) break;
+      j->off = off;
+      S->pending.pop_front();
+      j->state = kResident;
+      j->t_admit = now_s();
+    }
+    vof_status rc = job_admit(S, j);
+    if (rc) return rc;
+    S->resident.push_back(j);
+    changed = true;
+  }
+  if (S->resident.empty()) {
+    idle = true;
+    return VOF_OK;
+  }
+  {
+    std::lock_guard<std::mutex> lock(S->mu);
+    S->max_resident = std::max(S->max_resident, (int32_t)S->resident.size());
+  }
+  if (changed || S->core.n != (int)S->resident.size()) {
+    std::vector<BInst> e(S->resident.size());
+    for (size_t i = 0; i < S->resident.size(); ++i) {
+      e[i].m = S->resident[i]->mesh->dm;
+      e[i].s = S->resident[i]->ds;
+      e[i].p = S->resident[i]->mesh->dp;
+    }
+    vof_status rc = S->core.set(e.data(), (int)e.size());
+    if (rc) return rc;
+  }
+  // one batched step of every resident job; at most four ticks in flight
+  hipEvent_t &ev = S->tick_ev[S->tick_slot];
+  if (S->ticks >= 4) HIP_OR_FAIL(hipEventSynchronize(ev));
+  vof_status rc = S->core.step(1);
+  if (rc) return rc;
+  HIP_OR_FAIL(hipEventRecord(ev, S->stream));
+  S->tick_slot = (S->tick_slot + 1) % 4;
+  ++S->ticks;
+  std::vector<vof_job *> still;
+  for (vof_job *j : S->resident) {
+    if (++j->done_steps < j->steps) {
+      still.push_back(j);
+      continue;
+    }
+    if ((rc = job_drain(S, j))) return rc;
+    {
+      std::lock_guard<std::mutex> lock(S->mu);
+      // later uploads into this block are ordered after the copy on the stream
+      S->arena.release(j->off, j->L.bytes);
+      j->state = kDraining;
+    }
+    S->draining.push_back(j);
+  }
+  S->resident.swap(still);
+  return VOF_OK;
+}
+
+void server_worker(vof_server *S) {
+  if (hipSetDevice(S->ctx.device) != hipSuccess) {
+    std::lock_guard<std::mutex> lock(S->mu);
+    S->error = VOF_EDEVICE;
+    S->error_msg = "server: hipSetDevice failed";
+    S->cv_done.notify_all();
+    return;
+  }
+  for (;;) {
+    bool idle = false;
+    vof_status rc = server_loop_once(S, idle);
+    if (rc) {
+      std::lock_guard<std::mutex> lock(S->mu);
+      S->error = rc;
+      S->error_msg = last_error();
+      S->cv_done.notify_all();
+      return;
+    }
+    if (idle) {
+      if (!S->draining.empty()) {
+        // nothing to step: wait for the oldest copy
+        (void)hipEventSynchronize(S->draining.front()->ev);
+        continue;
+      }
+      std::unique_lock<std::mutex> lock(S->mu);
+      if (S->stop && S->pending.empty()) return;
+      S->cv_work.wait(lock, [&] { return S->stop || !S->pending.empty(); });
+      if (S->stop && S->pending.empty()) return;
+    }
+  }
+}
+
+double percentile(std::vector<double> v, double q) {
+  if (v.empty()) return 0.0;
+  std::sort(v.begin(), v.end());
+  const double pos = q * (double)(v.size() - 1);
+  const size_t i = (size_t)pos;
+  const double f = pos - (double)i;
+  return i + 1 < v.size() ? v[i] * (1 - f) + v[i + 1] * f : v[i];
+}
+
+}  // namespace
+
+extern "C" {
+
+vof_status vof_server_create(vof_context *ctx, int64_t hbm_budget_bytes, vof_server **out) {
+  if (!ctx || !out) return fail(VOF_EINVAL, "null argument");
+  *out = nullptr;
+  if (hbm_budget_bytes < (int64_t)(1 << 20)) return fail(VOF_EINVAL, "budget below 1 MiB");
+  HIP_OR_FAIL(hipSetDevice(ctx->device));
+  vof_server *S = new (std::nothrow) vof_server;
+  if (!S) return fail(VOF_ENOMEM, "host allocation failed");
+  S->ctx = *ctx;
+  auto bail = [&](vof_status rc) {
+    if (S->stream) (void)hipStreamDestroy(S->stream);
+    if (S->arena_base) (void)hipFree(S->arena_base);
+    for (auto &e : S->tick_ev)
+      if (e) (void)hipEventDestroy(e);
+    delete S;
+    return rc;
+  };
+  hipError_t e = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking);
+  if (e != hipSuccess) return bail(fail(VOF_EDEVICE, "server stream: %s", hipGetErrorString(e)));
+  e = hipMalloc((void **)&S->arena_base, (size_t)hbm_budget_bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    S->arena_base = nullptr;
+    return bail(fail(VOF_ENOMEM, "server budget: hipMalloc of %lld bytes failed",
+                     (long long)hbm_budget_bytes));
+  }
+  S->arena.init((size_t)hbm_budget_bytes);
+  for (auto &ev : S->tick_ev) {
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) return bail(fail(VOF_EDEVICE, "server events: %s", hipGetErrorString(e)));
+  }
+  vof_status rc = S->core.init(ctx->device, S->stream);
+  if (rc) return bail(rc);
+  S->worker = std::thread(server_worker, S);
+  *out = S;
+  return VOF_OK;
+}
+
+vof_status vof_server_submit(vof_server *S, vof_mesh *mesh, const double *alpha0,
+                             const double *U0c, const double *F0, int32_t n_steps,
+                             const double *dt, const double *scale, vof_job **job) {
+  if (!S || !mesh || !alpha0 || !U0c || !F0 || !dt || !scale || !job)
+    return fail(VOF_EINVAL, "null argument");
+  *job = nullptr;
+  if (n_steps < 1) return fail(VOF_EINVAL, "a job advects at least one step");
+  if (mesh->ctx->device != S->ctx.device) return fail(VOF_EINVAL, "mesh on another device");
+  if (mesh->dp.wisps || mesh->dp.band || mesh->dp.check_stencil)
+    return fail(VOF_EINVAL, "jobs run without wisps, narrow band and stencil check");
+  for (int32_t i = 0; i < n_steps; ++i)
+    if (!(dt[i] > 0.0) || !std::isfinite(dt[i]) || !std::isfinite(scale[i]))
+      return fail(VOF_EINVAL, "dt must be positive and finite, scale finite (step %d)", i);
+  const DMesh &m = mesh->dm;
+  vof_job *j = new (std::nothrow) vof_job;
+  if (!j) return fail(VOF_ENOMEM, "host allocation failed");
+  j->srv = S;
+  j->mesh = mesh;
+  j->steps = n_steps;
+  j->L = state_layout(m, n_steps);
+  if (j->L.bytes > S->arena.size) {
+    delete j;
+    return fail(VOF_EBUSY, "job needs %zu bytes of state, above the budget of %zu",
+                j->L.bytes, S->arena.size);
+  }
+  j->alpha0.assign(alpha0, alpha0 + m.nc);
+  j->U0c.assign(U0c, U0c + 3 * m.nc);
+  j->F0.assign(F0, F0 + m.nf);
+  j->dt.assign(dt, dt + n_steps);
+  j->sc.assign(scale, scale + n_steps);
+  for (int64_t f = 0; f < m.nf; ++f) j->nflux += F0[f] != 0.0;
+  {
+    std::lock_guard<std::mutex> lock(S->mu);
+    if (S->error) {
+      delete j;
+      return fail(S->error, "server stopped: %s", S->error_msg.c_str());
+    }
+    if (S->pending.size() >= 4096) {
+      delete j;
+      return fail(VOF_EBUSY, "the server's queue is full");
+    }
+    j->t_arrive = now_s();
+    if (S->t_first_arrival < 0) S->t_first_arrival = j->t_arrive;
+    S->pending.push_back(j);
+  }
+  S->cv_work.notify_one();
+  *job = j;
+  return VOF_OK;
+}
+
+vof_status vof_server_wait(vof_job *j, double *alpha_out, double *latency_s) {
+  if (!j) return fail(VOF_EINVAL, "null argument");
+  vof_server *S = j->srv;
+  {
+    std::unique_lock<std::mutex> lock(S->mu);
+    S->cv_done.wait(lock, [&] { return j->state == kDone || S->error != VOF_OK; });
+    if (j->state != kDone) return fail(S->error, "server stopped: %s", S->error_msg.c_str());
+  }
+  if (alpha_out) std::memcpy(alpha_out, j->h_out, 8 * (size_t)j->mesh->dm.nc);
+  if (latency_s) *latency_s = j->t_done - j->t_arrive;
+  vof_status rc = j->status;
+  (void)hipHostFree(j->h_out);
+  (void)hipEventDestroy(j->ev);
+  delete j;
+  if (rc) return fail(rc, "a clipped polytope exceeded its capacity");
+  return VOF_OK;
+}
+
+vof_status vof_server_get_stats(vof_server *S, vof_server_stats *out) {
+  if (!S || !out) return fail(VOF_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lock(S->mu);
+  out->jobs_done = S->jobs_done;
+  out->jobs_waiting = (int64_t)S->pending.size();
+  out->face_fluxes = S->face_fluxes;
+  out->ticks = S->ticks;
+  out->latency_p50_s = percentile(S->latencies, 0.50);
+  out->latency_p99_s = percentile(S->latencies, 0.99);
+  out->latency_max_s = S->latencies.empty() ? 0.0
+                                            : *std::max_element(S->latencies.begin(),
+                                                                S->latencies.end());
+  const double span = S->t_first_arrival < 0 ? 0.0 : S->t_last_done - S->t_first_arrival;
+  out->face_fluxes_per_s = span > 0 ? (double)S->face_fluxes / span : 0.0;
+  out->max_resident = S->max_resident;
+  out->budget_bytes = (int64_t)S->arena.size;
+  out->peak_bytes = (int64_t)S->arena.peak;
+  return S->error;
+}
+
+vof_status vof_server_destroy(vof_server *S) {
+  if (!S) return VOF_OK;
+  {
+    std::lock_guard<std::mutex> lock(S->mu);
+    S->stop = true;
+  }
+  S->cv_work.notify_all();
+  if (S->worker.joinable()) S->worker.join();
+  (void)hipSetDevice(S->ctx.device);
+  (void)hipStreamSynchronize(S->stream);
+  // jobs never waited for
+  for (vof_job *j : S->draining) {
+    (void)hipHostFree(j->h_out);
+    (void)hipEventDestroy(j->ev);
+    delete j;
+  }
+  for (vof_job *j : S->resident) {
+    (void)hipHostFree(j->h_out);
+    (void)hipEventDestroy(j->ev);
+    delete j;
+  }
+  for (vof_job *j : S->pending) delete j;
+  for (auto &e : S->tick_ev)
+    if (e) (void)hipEventDestroy(e);
+  char *arena = S->arena_base;
+  hipStream_t st = S->stream;
+  delete S;  // the batch core first (its graphs and table)
+  if (arena) (void)hipFree(arena);
+  if (st) (void)hipStreamDestroy(st);
+  return VOF_OK;
+}
+
+}  // extern "C"

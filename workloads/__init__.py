@@ -327,6 +327,40 @@ def batch_instances(count: int = 256, seed: int = 3417, n_range=(16, 96), steps:
     return out
 
 
+def sphere_fraction(mesh, centre, radius, sample: int = 6) -> np.ndarray:
+    """alpha^0 of a ball on a generated mesh: exact on boxes, sampled on tets."""
+    if mesh.kind == "hex":
+        return fields.ball_box_fraction(centre, radius, mesh.cell_lo, mesh.cell_hi)
+    c = np.asarray(centre, dtype=np.float64)
+    return fields.tet_fraction_sampled(
+        mesh, lambda x: ((x - c) ** 2).sum(-1) <= radius * radius, sample)
+
+
+def deformation_template(kind: str, n: int, T: float = 3.0, seed: int = 1305) -> Workload:
+    """A mesh of the served workload in the deformation field (eq. 4.6):
+    kind "hex" (n^3 cubes) or "tets" (n^3 cubes of six jittered tets); the
+    step from the cell Courant number 0.5 (T / N); alpha0 and the schedule
+    come with each request (served_request)."""
+    m = hex_mesh(n, n, n) if kind == "hex" else kuhn_tet_mesh(n, 0.2, seed)
+    Uc = fields.deformation_velocity(m.cell_centroids())
+    F0 = fields.flux_deformation(m)
+    dt = courant_dt(m, F0, 0.5, T)
+    return Workload(f"{kind}{n}", m, np.zeros(m.n_cells), Uc, F0, np.array([dt]), np.ones(1),
+                    meta={"kind": kind, "n": n, "T": T})
+
+
+def served_request(tpl: Workload, rng, steps: int, r_range=(0.1, 0.2)):
+    """One request on a template: a sphere r ~ U(r_range) centred in
+    U[0.3, 0.7]^3, advected `steps` steps from t = 0 in the deformation
+    field (scale cos(pi t / T) at mid-step).  Returns (alpha0, dt, scale)."""
+    r = float(rng.uniform(*r_range))
+    c = rng.uniform(0.3, 0.7, size=3)
+    a0 = sphere_fraction(tpl.mesh, c, r)
+    dt = float(tpl.dt[0])
+    t = (np.arange(steps) + 0.5) * dt
+    return a0, np.full(steps, dt), np.cos(np.pi * t / tpl.meta["T"])
+
+
 def boundary_points(mesh) -> np.ndarray:
     """Points on the faces of the unit box (bool per point)."""
     p = mesh.points
