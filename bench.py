@@ -8,12 +8,15 @@ conservative update, for all 6.3M faces and 2.1M cells.  Inputs are resident
 in HBM when the timed region starts.
 
 Prints one JSON line: face-fluxes/s (faces with F != 0 per step, each built,
-corrected and given its phase volume) over the timed steps, run as the
-library runs them (each step one captured HIP graph); per-kernel durations
-and the dominant kernel's roofline figure from HIP events around every
-kernel over the next min(K, 20) steps, launched kernel by kernel; a sampled
-parity check of an extra step against the oracle; and the oracle's own rate
-on a bounded sample of the same step (CPU baseline).
+corrected and given its phase volume) over the whole run to T (1536 steps,
+timed from alpha^0 in segments that show the rate along the run), run as the
+library runs them (each step one captured HIP graph); the advection error E_g
+and alpha's range at the end; per-kernel durations and the dominant kernel's
+roofline figure from HIP events around every kernel over 20 steps from the
+middle of the run, launched kernel by kernel; a sampled parity check of an
+extra step against the oracle; and the oracle's own rate on a bounded sample
+of the same steps (CPU baseline).  --workload batched / served run the
+batched and served forms against the plain per-mesh / per-request loop.
 """
 from __future__ import annotations
 
@@ -84,16 +87,29 @@ CPU_SAMPLE_SECONDS = 10.0   # oracle steps are run until this much host time has
 CPU_SAMPLE_MAX_STEPS = 16
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, alpha, step):
     """Whole steps of the oracle (reconstruction, correction of every face,
     phase volumes, update) on the same mesh, from the same state, on the host
-    cores: consecutive steps until about CPU_SAMPLE_SECONDS have passed."""
+    cores: consecutive steps until about CPU_SAMPLE_SECONDS have passed on all
+    threads, then one step on one thread."""
     import numpy as np
 
     import oracle
     o = oracle.Oracle(w.mesh)
     o.set_velocity(w.U0c, w.F0)
     n_flux = int(np.count_nonzero(w.F0))
+    threads = oracle.set_threads(0)
     a = alpha
     n = 0
     t0 = time.perf_counter()
@@ -103,16 +119,24 @@ def cpu_baseline(w, alpha, step):
         if time.perf_counter() - t0 >= CPU_SAMPLE_SECONDS:
             break
     t = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    one = None
+    if step + n < len(w.dt):
+        oracle.set_threads(1)
+        t1 = time.perf_counter()
+        o.step(a, w.dt[step + n], w.scale[step + n])
+        one = n_flux / (time.perf_counter() - t1)
+        oracle.set_threads(threads)
     return {"value": n * n_flux / t, "unit": "face-fluxes/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "one_thread_value": one,
             "sample": f"{n} whole steps ({n_flux} flux faces each) of the same {w.name} case "
-                      f"from the benchmark's final state, {t:.1f} s"}
+                      f"from mid-run (step {step}) on {threads} threads, {t:.1f} s; then one "
+                      f"step on one thread"}
 
 
 def parity_check(vof, mesh, w, step, n_sample=2000, seed=5):
     """One extra (untimed) step from the current state, checked on sampled
     faces against the oracle: lambda and V_alpha within 1e-12 of
-    max(|F| dt, gross swept volume, 1e-2 V_owner)."""
+    max(|F| dt, gross swept volume, 1e-2 max(V_owner, d_f^3))."""
     import numpy as np
 
     import oracle
@@ -145,14 +169,24 @@ def parity_check(vof, mesh, w, step, n_sample=2000, seed=5):
     G = (np.linalg.norm(S, axis=1) * mx * sdt)[faces]
     T = np.abs(w.F0[faces] * sdt)
     ok = (w.F0[faces] != 0) & (r["status"] == 0)
+    # rounding floor of a polyhedron's tetrahedra: their edges are as long as
+    # the face (diameter d_f) however short the sweep; max(V_owner, d_f^3)
+    face_of = np.repeat(np.arange(m.n_faces), n)
+    P = m.points[m.face_points]
+    ctr = np.zeros((m.n_faces, 3))
+    np.add.at(ctr, face_of, P)
+    ctr /= n[:, None]
+    rad = np.zeros(m.n_faces)
+    np.maximum.at(rad, face_of, np.linalg.norm(P - ctr[face_of], axis=1))
+    floor = np.maximum(V[m.owner], (2.0 * rad) ** 3)[faces]
     # the oracle's volume at the GPU's lambda against F dt, relative to
     # max(|F dt|, G) (lambda is ill-conditioned where V' is small)
     sub = faces[ok][::4]
     res = [abs(o.flux_volume(f, w.dt[step], w.scale[step], lam[f]) - w.F0[f] * w.scale[step]
                * w.dt[step]) for f in sub]
-    ref = np.maximum(np.maximum(T[ok][::4], G[ok][::4]), 1e-2 * V[m.owner[sub]])
+    ref = np.maximum(np.maximum(T[ok][::4], G[ok][::4]), 1e-2 * floor[ok][::4])
     lam_err = float((np.asarray(res) / ref).max())
-    tol = 1e-12 * np.maximum(np.maximum(T, G), 1e-2 * V[m.owner[faces]])
+    tol = 1e-12 * np.maximum(np.maximum(T, G), 1e-2 * floor)
     ratio = float((np.abs(vph[faces] - r["vphase"]) / tol).max())
     flags_equal = bool(np.array_equal(status[faces], r["status"].astype(np.uint8)))
     return {"faces": int(faces.size), "geometric": int(min(n_sample, geo.size)),
@@ -318,20 +352,197 @@ def run_batched(args):
     vof.vof_context_destroy(ctx)
 
 
+SERVED_HEX_N = (22, 32, 45, 64, 90, 126)      # 1.1e4 .. 2.0e6 cells, log-spaced
+SERVED_TET_N = (12, 17, 24, 34, 49, 69)       # 6 N^3: 1.0e4 .. 2.0e6 cells
+SERVED_SPHERES = 4                            # alpha0 draws per mesh
+
+
+def _served_template(args):
+    kind, n, seed = args
+    import numpy as np
+
+    import workloads as W
+    tpl = W.deformation_template(kind, n)
+    rng = np.random.default_rng([seed, n, 0 if kind == "hex" else 1])
+    # alpha0 of a few random spheres (r ~ U[0.1, 0.2], centre ~ U[0.3, 0.7]^3)
+    alphas = [W.served_request(tpl, rng, 1)[0] for _ in range(SERVED_SPHERES)]
+    return tpl, alphas
+
+
+def run_served(args):
+    """The served form against the plain per-request loop: a Poisson stream of
+    advection requests (deformation field, eq. 4.6) on hex and jittered-tet
+    meshes of 1e4 to 2e6 cells (log-spaced), K ~ U{10..200} steps each, state
+    admitted by a fixed HBM budget.  Both serve the same requests at the same
+    arrival times; every served result must equal its plain result bitwise.
+    A second pass submits every request at once (saturation): capacity."""
+    import multiprocessing as mp
+    import threading
+
+    import numpy as np
+    import torch
+
+    import paper_1305_3417_amd as vof
+
+    seed, nreq = 5, args.requests
+    workers = max(1, min(16, (os.cpu_count() or 1)))
+    specs = [("hex", n, seed) for n in SERVED_HEX_N] + [("tets", n, seed) for n in SERVED_TET_N]
+    log(f"[bench] generating {len(specs)} meshes and {SERVED_SPHERES} spheres each "
+        f"({workers} processes)")
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(workers) as pool:
+        made = pool.map(_served_template, sorted(specs, key=lambda s: -s[1]))
+    by = {(t.meta["kind"], t.meta["n"]): (t, al) for t, al in made}
+    tpls = [by[(k, n)] for k, n, _ in specs]
+    log(f"[bench] generated in {time.perf_counter() - t0:.0f} s")
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for _ in range(nreq):
+        kind = int(rng.integers(2))           # hex or tets, even odds
+        i = kind * len(SERVED_HEX_N) + int(rng.integers(len(SERVED_HEX_N)))
+        K = int(rng.integers(10, 201))
+        sph = int(rng.integers(SERVED_SPHERES))
+        reqs.append((i, sph, K))
+    gaps = rng.exponential(1.0, size=nreq)    # Poisson arrivals, scaled by the rate below
+    ctx = vof.vof_context_create(0)
+    meshes = [vof.upload_mesh(ctx, t.mesh) for t, _ in tpls]
+    nflux = [int(np.count_nonzero(t.F0)) for t, _ in tpls]
+    sched = {}
+
+    def schedule(i, K):
+        if (i, K) not in sched:
+            t = tpls[i][0]
+            dt = float(t.dt[0])
+            tt = (np.arange(K) + 0.5) * dt
+            sched[(i, K)] = (np.full(K, dt), np.cos(np.pi * tt / t.meta["T"]))
+        return sched[(i, K)]
+
+    def plain(r):
+        i, sph, K = r
+        t, al = tpls[i]
+        dt, sc = schedule(i, K)
+        vof.vof_set_alpha(meshes[i], al[sph])
+        vof.vof_set_velocity(meshes[i], t.U0c, t.F0)
+        vof.vof_advect(meshes[i], dt, sc)
+        return vof.vof_read_alpha(meshes[i])
+
+    # plain service time of every request (one warm pass over the meshes first)
+    for i in range(len(tpls)):
+        plain((i, 0, 10))
+    torch.cuda.synchronize()
+    work = sum(nflux[i] * K for i, _, K in reqs)
+    # plain per-request loop at the offered rate: completion_k =
+    # max(arrival_k, completion_{k-1}) + service_k, run for real in arrival order
+    def run_plain(arrivals):
+        out, lat = [], []
+        t_start = time.perf_counter()
+        for r, ta in zip(reqs, arrivals):
+            now = time.perf_counter() - t_start
+            if ta > now:
+                time.sleep(ta - now)
+            out.append(plain(r))
+            lat.append(time.perf_counter() - t_start - ta)
+        span = time.perf_counter() - t_start - arrivals[0]
+        return out, np.array(lat), span
+
+    zero = np.zeros(nreq)
+    log(f"[bench] plain loop, all {nreq} requests at once")
+    a_plain, lat_sat, span_plain_sat = run_plain(zero)
+    cap_plain = work / span_plain_sat
+    rate = args.rate if args.rate else 0.7 * nreq / span_plain_sat   # requests per second
+    arrivals = np.cumsum(gaps / rate) - gaps[0] / rate
+    log(f"[bench] plain capacity {cap_plain:.3e} face-fluxes/s; offered rate {rate:.1f} "
+        f"requests/s")
+    log(f"[bench] plain loop, Poisson arrivals")
+    _, lat_plain, span_plain = run_plain(arrivals)
+
+    def run_served_once(arr):
+        srv = vof.vof_server_create(ctx, args.budget_gib << 30)
+        jobs = [None] * nreq
+        t_start = time.perf_counter()
+
+        def submit():
+            for k, (r, ta) in enumerate(zip(reqs, arr)):
+                now = time.perf_counter() - t_start
+                if ta > now:
+                    time.sleep(ta - now)
+                i, sph, K = r
+                t, al = tpls[i]
+                dt, sc = schedule(i, K)
+                jobs[k] = vof.vof_server_submit(srv, meshes[i], al[sph], t.U0c, t.F0, dt, sc)
+        th = threading.Thread(target=submit)
+        th.start()
+        th.join()
+        res = [vof.vof_server_wait(j) for j in jobs]
+        span = time.perf_counter() - t_start - arr[0]
+        st = vof.vof_server_get_stats(srv)
+        srv.close()
+        return [a for a, _ in res], np.array([l for _, l in res]), span, st
+
+    log(f"[bench] served, all {nreq} requests at once (budget {args.budget_gib} GiB)")
+    a_srv_sat, lat_srv_sat, span_srv_sat, st_sat = run_served_once(zero)
+    log(f"[bench] served, Poisson arrivals")
+    a_srv, lat_srv, span_srv, st = run_served_once(arrivals)
+    same = sum(np.array_equal(x, y) for x, y in zip(a_plain, a_srv))
+    same_sat = sum(np.array_equal(x, y) for x, y in zip(a_plain, a_srv_sat))
+    log(f"[bench] served results bitwise equal to plain: {same}/{nreq} (Poisson), "
+        f"{same_sat}/{nreq} (all at once)")
+    cap_srv = work / span_srv_sat
+    pct = lambda a, q: float(np.percentile(a, q))  # noqa: E731
+    out = {
+        "metric": METRIC, "value": cap_srv, "unit": "face-fluxes/s", "n_gpus": 1,
+        "steps": int(sum(K for _, _, K in reqs)), "warmup": 1,
+        "ms_per_step": span_srv_sat * 1e3 / max(st_sat["ticks"], 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"served: {nreq} requests, deformation field (eq. 4.6, T=3), "
+                               f"hex N^3 N in {list(SERVED_HEX_N)} and jittered tets 6 N^3 N in "
+                               f"{list(SERVED_TET_N)} (1e4..2e6 cells, even odds), random sphere "
+                               f"r ~ U[0.1,0.2] ({SERVED_SPHERES} per mesh), K ~ U{{10..200}}, "
+                               f"cell Courant 0.5, seed {seed}, HBM budget {args.budget_gib} GiB",
+                   "requests": nreq, "face_flux_work": work, "parallelism": "single GPU"},
+        "form": "served",
+        "saturated": {"served_face_fluxes_per_s": cap_srv, "plain_face_fluxes_per_s": cap_plain,
+                      "served_over_plain": cap_srv / cap_plain,
+                      "served_s": span_srv_sat, "plain_s": span_plain_sat,
+                      "server_stats": st_sat},
+        "poisson": {"rate_requests_per_s": rate, "offered_load_of_plain_capacity": 0.7,
+                    "served": {"p50_ms": pct(lat_srv, 50) * 1e3, "p99_ms": pct(lat_srv, 99) * 1e3,
+                               "face_fluxes_per_s": work / span_srv, "span_s": span_srv},
+                    "plain": {"p50_ms": pct(lat_plain, 50) * 1e3,
+                              "p99_ms": pct(lat_plain, 99) * 1e3,
+                              "face_fluxes_per_s": work / span_plain, "span_s": span_plain},
+                    "server_stats": st},
+        "bitwise_equal_to_plain": {"poisson": int(same), "saturated": int(same_sat),
+                                   "of": nreq},
+    }
+    print(json.dumps(out), flush=True)
+    for m in meshes:
+        m.close()
+    vof.vof_context_destroy(ctx)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: the whole run; batched 100)")
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--n", type=int, default=None,
                     help="mesh is n^3 hexahedra (default 128), or n^3 cubes of six jittered "
                          "tetrahedra for tets (default 80)")
-    ap.add_argument("--workload", choices=["deform3d", "shear3d", "tets", "batched"],
+    ap.add_argument("--workload", choices=["deform3d", "shear3d", "tets", "batched", "served"],
                     default="deform3d",
                     help="deform3d (eq. 4.6, fixed dt; the headline case), shear3d "
                          "(eq. 4.5, adaptive Courant dt), tets (slotted sphere rotating "
-                         "on jittered tetrahedra) or batched (many meshes per launch against "
-                         "the plain per-mesh loop)")
+                         "on jittered tetrahedra), batched (many meshes per launch against "
+                         "the plain per-mesh loop) or served (a request stream against the "
+                         "plain per-request loop)")
+    ap.add_argument("--requests", type=int, default=400, help="served: number of requests")
+    ap.add_argument("--rate", type=float, default=None,
+                    help="served: arrivals per second (default 0.7 x the plain loop's "
+                         "measured capacity)")
+    ap.add_argument("--budget-gib", type=int, default=96, help="served: HBM budget")
     ap.add_argument("--instances", type=int, default=256, help="batched: number of meshes")
     ap.add_argument("--n-min", type=int, default=16, help="batched: smallest N")
     ap.add_argument("--n-max", type=int, default=96, help="batched: largest N")
@@ -372,19 +583,26 @@ def main():
         print(json.dumps({"calibrate_copy_bytes_read": n * 8, "bytes_written": n * 8,
                           "launches": 3}), flush=True)
         return
+    if args.workload == "served":
+        run_served(args)
+        return
     if args.workload == "batched":
-        if args.steps == 200 and "--steps" not in sys.argv:
+        if args.steps is None:
             args.steps = 100
         run_batched(args)
         return
     WORKLOAD[0] = args.workload
     if args.n is None:
         args.n = 80 if args.workload == "tets" else 128
-    K, Wm = args.steps, args.warmup
-    P = min(K, 20)  # profiled steps after the timed region
+    Wm = args.warmup
     log(f"[bench] generating {args.workload} {args.n}^3")
     make = {"deform3d": W.deform3d, "shear3d": W.shear3d, "tets": W.rotate_tets}[args.workload]
-    w = make(args.n, steps=Wm + K + P + 1 + CPU_SAMPLE_MAX_STEPS)
+    w = make(args.n)  # the whole run: to T, or one revolution
+    K = w.n_steps if args.steps is None else min(args.steps, w.n_steps)
+    if args.workload == "tets" and args.steps is None:
+        K = min(K, 2000)  # a revolution is ~26k steps at Courant 0.5 on these slivers
+    P = min(K, 20)   # profiled steps, from the middle of the timed run
+    mid = K // 2
     ctx = vof.vof_context_create(0)
     log("[bench] uploading mesh")
     mesh = vof.upload_mesh(ctx, w.mesh)
@@ -392,34 +610,61 @@ def main():
         p = vof.vof_get_params(mesh)
         p.narrow_band, p.wisps = 1, 1
         vof.vof_set_params(mesh, p)
-    vof.vof_set_alpha(mesh, w.alpha0)
     vof.vof_set_velocity(mesh, w.U0c, w.F0)
+    vof.vof_set_alpha(mesh, w.alpha0)
     log(f"[bench] warmup {Wm} steps")
-    vof.vof_advect(mesh, w.dt[:Wm], w.scale[:Wm])
+    vof.vof_advect(mesh, w.dt[:max(Wm, 1)], w.scale[:max(Wm, 1)])
     vof.vof_synchronize(mesh)
-    st0 = vof.vof_get_stats(mesh)
-    # timed region: the step as the library runs it (one captured graph per
-    # step, replayed on the library's stream)
-    log(f"[bench] timing {K} steps")
+    vof.vof_set_alpha(mesh, w.alpha0)     # the timed run starts from alpha^0 again
+    # timed region: steps 0 .. K-1 as the library runs them (one captured graph
+    # per step, replayed on the library's stream), in segments whose times give
+    # the rate along the run
+    nseg = min(K, 24)
+    bounds = np.linspace(0, K, nseg + 1).astype(int)
+    log(f"[bench] timing {K} steps ({nseg} segments)")
+    seg_ms = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    vof.vof_advect(mesh, w.dt[Wm:Wm + K], w.scale[Wm:Wm + K])
-    vof.vof_synchronize(mesh)
+    last = t0
+    for a, b in zip(bounds[:-1], bounds[1:]):
+        vof.vof_advect(mesh, w.dt[a:b], w.scale[a:b])
+        vof.vof_synchronize(mesh)
+        now = time.perf_counter()
+        seg_ms.append((now - last) * 1e3 / (b - a))
+        last = now
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     st1 = vof.vof_get_stats(mesh)
-    face_fluxes = st1["face_fluxes"] - st0["face_fluxes"]
-    geo = st1["geometric_faces"] - st0["geometric_faces"]
+    face_fluxes = st1["face_fluxes"]
+    geo = st1["geometric_faces"]
     value = face_fluxes / elapsed
     log(f"[bench] {elapsed * 1e3 / K:.3f} ms/step, {value:.3e} face-fluxes/s")
+    a_end = vof.vof_read_alpha(mesh)
+    V = W.generated_volumes(w.mesh)
+    m0 = float((w.alpha0 * V).sum())
+    e_g = float((V * np.abs(a_end - w.alpha0)).sum())
+    run = {"steps": int(K), "t_end": float(np.sum(w.dt[:K])),
+           "segments": [{"steps": [int(a), int(b)], "ms_per_step": float(t)}
+                        for a, b, t in zip(bounds[:-1], bounds[1:], seg_ms)],
+           "alpha_min": st1["alpha_min"], "alpha_max": st1["alpha_max"],
+           "unreached_faces_per_step": st1["unreached_faces"] / K,
+           "geometric_faces_per_step": geo / K,
+           "mass_plus_outflow_rel_err": abs(st1["mass"] + st1["ledger"] - m0) / m0,
+           "E_g_at_end": e_g}
+    if args.workload == "deform3d" and K == w.n_steps and args.n == 128:
+        run["E_g_paper_table4_128_co05"] = 1.30304e-3   # context: same method, other setup
+    log(f"[bench] run: {run}")
 
-    # per-kernel durations: the next P steps launched kernel by kernel, each
-    # bracketed by HIP events on the library's stream
+    # per-kernel durations over P steps from the middle of the run, launched
+    # kernel by kernel, each bracketed by HIP events on the library's stream
+    vof.vof_set_alpha(mesh, w.alpha0)
+    vof.vof_advect(mesh, w.dt[:mid], w.scale[:mid])
+    vof.vof_synchronize(mesh)
     vof.vof_profile_enable(mesh, True)
     vof.vof_read_profile(mesh)
     sp0 = vof.vof_get_stats(mesh)
     tp0 = time.perf_counter()
-    vof.vof_advect(mesh, w.dt[Wm + K:Wm + K + P], w.scale[Wm + K:Wm + K + P])
+    vof.vof_advect(mesh, w.dt[mid:mid + P], w.scale[mid:mid + P])
     vof.vof_synchronize(mesh)
     prof_elapsed = time.perf_counter() - tp0
     prof = {k: v for k, v in vof.vof_read_profile(mesh).items() if v[1] > 0}
@@ -447,12 +692,13 @@ def main():
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
                 "traffic": recorded_traffic(dom, args.n),
                 "avg_launch_us": avg_s * 1e6, "units_per_launch": n_units,
-                "flop_per_unit": per_unit, "unit_kind": what, "profiled_steps": P}
+                "flop_per_unit": per_unit, "unit_kind": what, "profiled_steps": P,
+                "profiled_from_step": mid}
     else:
         roof = {"kernel": dom, "bound": "alu", "achieved": None, "peak": PEAK_FP64_TFLOPS,
                 "unit": "TFLOP/s", "frac": None, "traffic": recorded_traffic(dom, args.n),
-                "avg_launch_us": avg_s * 1e6, "profiled_steps": P}
-    step_after = Wm + K + P
+                "avg_launch_us": avg_s * 1e6, "profiled_steps": P, "profiled_from_step": mid}
+    step_after = mid + P
 
     parity = None
     if not args.no_parity:
@@ -463,9 +709,8 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] oracle CPU baseline")
         a = vof.vof_read_alpha(mesh)
-        cpu = cpu_baseline(w, a, step_after)
+        cpu = cpu_baseline(w, a, step_after + 1)
         log(f"[bench] cpu {cpu}")
-
     out = {
         "metric": METRIC, "value": value, "unit": "face-fluxes/s", "n_gpus": 1, "steps": K,
         "warmup": Wm, "ms_per_step": elapsed * 1e3 / K, "higher_is_better": True,
@@ -478,16 +723,18 @@ def main():
                                   f"Co 0.5)",
                        "tets": f"tets {args.n}^3 cubes x 6 jittered Kuhn tetrahedra (slotted "
                                f"sphere r=0.15 at (0.5,0.75,0.5), rotation about z, "
-                               f"omega=2 pi, dt=1/{9 * args.n})"}[args.workload]
-                               + f", steps {Wm}..{Wm + K - 1}",
+                               f"omega=2 pi, cell Courant 0.5, dt=1/{w.meta.get('steps_per_rev')}"
+                               f")"}[args.workload]
+                               + f", steps 0..{K - 1} of {w.n_steps} (timed from alpha^0)",
                    "cells": int(w.mesh.n_cells), "faces": int(w.mesh.n_faces),
                    "band_wisps": bool(args.band_wisps),
                    "parallelism": "single GPU"},
         "cell_updates_per_s": w.mesh.n_cells * K / elapsed,
         "geometric_faces_per_step": geo / K,
-        "general_clip_tets_per_step": (st1["general_tets"] - st0["general_tets"]) / K,
-        "wisps_per_step": (st1["wisps"] - st0["wisps"]) / K,
+        "general_clip_tets_per_step": st1["general_tets"] / K,
+        "wisps_per_step": st1["wisps"] / K,
         "face_fluxes_per_step": face_fluxes / K,
+        "run": run,
         "kernels_us": {k: v[0] / max(v[1], 1) * 1e3 for k, v in prof.items()},
         "profiled_ms_per_step": prof_elapsed * 1e3 / P,
         "roofline": roof,

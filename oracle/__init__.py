@@ -43,6 +43,8 @@ def lib():
         L.orc_create.argtypes = [i64, i64, i64, i64, vp, vp, vp, vp, vp]
         L.orc_destroy.argtypes = [vp]
         L.orc_set_eps.argtypes = [vp, d]
+        L.orc_set_threads.restype = C.c_int
+        L.orc_set_threads.argtypes = [C.c_int]
         L.orc_geometry.argtypes = [vp, vp, vp, vp, vp]
         L.orc_stencil_size.restype = i64
         L.orc_stencil_size.argtypes = [vp]
@@ -330,6 +332,11 @@ class Oracle:
         g = np.empty((self.nc, 3))
         lib().orc_lsq_gradient(self.h, _p(phi), _p(g))
         return g
+
+
+def set_threads(n: int) -> int:
+    """OpenMP threads of later oracle calls; returns the number before."""
+    return int(lib().orc_set_threads(int(n)))
 
 
 def clip_volume(verts, faces, planes):

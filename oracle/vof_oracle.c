@@ -34,6 +34,7 @@
  * Build: gcc -O2 -fopenmp -shared -fPIC -o liboracle.so vof_oracle.c -lm
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -493,6 +494,14 @@ void orc_destroy(omesh *M) {
 }
 
 void orc_set_eps(omesh *M, double eps) { M->eps = eps; }
+
+/* OpenMP threads of the following calls (n <= 0: leave as is); returns the
+ * number in use before the call.  For timing the oracle on fewer cores. */
+int orc_set_threads(int n) {
+  int before = omp_get_max_threads();
+  if (n > 0) omp_set_num_threads(n);
+  return before;
+}
 /* gradient of the reconstruction: 0 NAG, 1 generalized LSQ */
 void orc_set_gradient(omesh *M, int kind) { M->grad_kind = kind; }
 
