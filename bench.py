@@ -551,6 +551,10 @@ def main():
     ap.add_argument("--tune-steps", type=int, default=6)
     ap.add_argument("--tune-cache", default=None,
                     help="batched: JSON cache of tuned configurations")
+    ap.add_argument("--window-only", action="store_true",
+                    help="only advance to the middle of the run (captured steps) and launch "
+                         "the profiled window's steps kernel by kernel, then print the work "
+                         "counted in it (for rocprofv3 counter runs)")
     ap.add_argument("--band-wisps", action="store_true",
                     help="run the step with the narrow band and wisp redistribution "
                          "(Section 2.3) after the update")
@@ -612,6 +616,22 @@ def main():
         vof.vof_set_params(mesh, p)
     vof.vof_set_velocity(mesh, w.U0c, w.F0)
     vof.vof_set_alpha(mesh, w.alpha0)
+    if args.window_only:
+        vof.vof_advect(mesh, w.dt[:mid], w.scale[:mid])
+        vof.vof_synchronize(mesh)
+        vof.vof_profile_enable(mesh, True)
+        sp0 = vof.vof_get_stats(mesh)
+        vof.vof_advect(mesh, w.dt[mid:mid + P], w.scale[mid:mid + P])
+        vof.vof_synchronize(mesh)
+        sp1 = vof.vof_get_stats(mesh)
+        prof = {k: v for k, v in vof.vof_read_profile(mesh).items() if v[1] > 0}
+        print(json.dumps({"window": [mid, mid + P], "workload": args.workload, "n": args.n,
+                          "per_step": {k: (sp1[k] - sp0[k]) / P for k in
+                                       ("face_fluxes", "geometric_faces", "interface_cells",
+                                        "clip_pairs", "general_tets")},
+                          "kernels_us": {k: v[0] / v[1] * 1e3 for k, v in prof.items()}}),
+              flush=True)
+        return
     log(f"[bench] warmup {Wm} steps")
     vof.vof_advect(mesh, w.dt[:max(Wm, 1)], w.scale[:max(Wm, 1)])
     vof.vof_synchronize(mesh)
