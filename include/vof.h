@@ -427,9 +427,10 @@ double vof_selftest_tet_clip(const double *tet, int32_t n_planes, const double *
  * last plane by the closed-form kept fraction).  Same arguments and result
  * as vof_selftest_tet_clip; NaN for n_planes > 4 or a bad argument.  For two
  * to four planes the result is the sum of the first plane's split terms as
- * the clip kernels add them (three lanes per pair), and NaN when it differs
- * from the one-lane recursion by more than 1e-14 of the tetrahedron's
- * volume. */
+ * the kernels add them when three lanes share a pair (four-plane pairs, and
+ * three-plane pairs on hexahedral meshes), and NaN when it differs from the
+ * one-lane recursion (the other pairs) by more than 1e-14 of the
+ * tetrahedron's volume. */
 double vof_selftest_tet_clip_closed(const double *tet, int32_t n_planes, const double *planes);
 
 #ifdef __cplusplus

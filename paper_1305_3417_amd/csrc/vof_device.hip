@@ -968,6 +968,28 @@ __device__ __forceinline__ void three_lane_bin(const DMesh &m, const DState &s,
   }
 }
 
+// A phase-B bin of pairs of K planes, one lane per pair (64 pairs per pass):
+// the whole recursion of the closed form in the pair's lane.
+template <int K>
+__device__ __forceinline__ void one_lane_bin(const DMesh &m, const DState &s,
+                                             const uint32_t *qpair,
+                                             const double (*tv)[kFastBlock],
+                                             const double (*fc)[3], const int32_t *ccell,
+                                             const double (*cbox)[6], int tpf, int kc,
+                                             const uint16_t *bin, int cnt, bool from_end, int cap,
+                                             double *res) {
+  for (int t = (int)threadIdx.x; t < cnt; t += kFastBlock) {
+    const int item = bin[from_end ? cap - 1 - t : t];
+    Tet T;
+    int cell, cl;
+    double det;
+    Pl p0, p1, p2, p3;
+    queued_pair(m, s, qpair, tv, fc, ccell, cbox, tpf, kc, item, T, det, cell, cl, p0, p1, p2, p3);
+    const double v = kept_fraction<K>(dist_table<K>(T, p0, p1, p2, p3));
+    res[item] = class_weight(s, cell, cl) * (det * v);
+  }
+}
+
 // A phase-B bin of pairs of five planes of cells that are not boxes, nine
 // lanes per pair (term j of piece i of the first two planes' splits; seven
 // pairs per pass), filled from the end of bin (capacity cap).  The terms are
@@ -1033,9 +1055,11 @@ __device__ __forceinline__ void nine_lane_bin(const DMesh &m, const DState &s,
 // kernel's queue; a tet with more than SLOTS queued pairs stops
 // at the first that finds its queue full and resumes there in another round
 // of the three phases.  Phase B
-// evaluates each bin with the plane count uniform across the wave, three
-// lanes per pair (one per piece of its first plane's split; nine for five
-// planes, one per piece of the first two splits); phase C adds each tet's
+// evaluates each bin with the plane count uniform across the wave: pairs of
+// two planes one lane each (the whole recursion), of three planes one lane
+// each on tetrahedral meshes and three lanes each on hexahedral ones, of four
+// three lanes each (one per piece of the first plane's split), of five nine
+// lanes each (one per piece of the first two splits); phase C adds each tet's
 // queued results in stencil order.
 // Group g of the geometric faces of one mesh (`count` of them, F = 64 / tpf
 // per group), swept by `sweep` (-s dt).  Must be reached by the whole wave.
@@ -1301,13 +1325,19 @@ __device__ __forceinline__ void clip_fast_group(const DMesh &m, const DState &s,
           }
         }
         __syncthreads();
-        // phase B, one bin at a time (the plane count uniform across the wave),
-        // three lanes per pair.  Every bin takes the same way whatever its size:
-        // which faces share a group follows the order of the geometric-face
-        // list, which is not fixed from run to run.
-        three_lane_bin<2>(m, s, qpair, tv, fc, ccell, cbox, tpf, kc, bins[0], nbin[0], false,
-                          kCap, res);
-        three_lane_bin<3>(m, s, qpair, tv, fc, ccell, cbox, tpf, kc, bins[1], nbin[1], false,
+        // phase B, one bin at a time (the plane count uniform across the wave):
+        // pairs of two planes one lane each, of three planes three lanes each
+        // (one each on tetrahedral meshes, whose bins are fuller), of four three
+        // lanes each.  Every bin takes the same way whatever its size: which
+        // faces share a group follows the order of the geometric-face list,
+        // which is not fixed from run to run.
+        one_lane_bin<2>(m, s, qpair, tv, fc, ccell, cbox, tpf, kc, bins[0], nbin[0], false,
+                        kCap, res);
+        if constexpr (BOXES)
+          three_lane_bin<3>(m, s, qpair, tv, fc, ccell, cbox, tpf, kc, bins[1], nbin[1], false,
+                            kCap, res);
+        else
+          one_lane_bin<3>(m, s, qpair, tv, fc, ccell, cbox, tpf, kc, bins[1], nbin[1], false,
                           kCap, res);
         three_lane_bin<4>(m, s, qpair, tv, fc, ccell, cbox, tpf, kc, bins[1], nbin[2], true,
                           kCap, res);
