@@ -33,8 +33,8 @@ METRIC = "face-fluxes/s at 1e-12 rel vol err; batched/served vs plain, p50/p99 l
 PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector
 PEAK_HBM_GBS = 8000.0        # MI355X HBM3E
 
-# Algorithmic work per unit, counted from the arithmetic each kernel must do,
-# not from the instructions it issues.
+# Estimates of the FP64 work per unit, used only where no counter summary of
+# the current kernel sources is committed (profiles/fp64_counters_*.md).
 FLUX_FLOPS_PER_QUAD_FACE = 400.0     # sweep, exact volume cubic, branch, ~2 Newton steps
 FLUX_BYTES_PER_FACE = 52.0           # CSR 20, F0 8, lambda 8, V_alpha 8, bytes 3, points ~5
 CLIP_FLOPS_PER_PAIR = 1000.0         # plane tests, clips and volume of one (tet, cell) pair
@@ -49,8 +49,11 @@ def log(msg):
 KERNEL_FUNCS = {"flux": "k_flux", "clip": "k_clip_fast", "clip_general": "k_clip_general",
                 "plane": "k_plane", "update": "k_update", "point_prep": "k_point_prep",
                 "cell_class": "k_cell_class", "face_sum": "k_face_sum"}
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_deform3d_128.md")
 WORKLOAD = ["deform3d"]  # set from the command line
+# peak VALU issue: a wave64 instruction occupies a 16-lane SIMD for 4 cycles
+# (the FP64 rate: 256 CUs x 4 SIMDs x 16 FMA lanes x 2 flops x 2.4 GHz = 78.6
+# TFLOP/s); 256 x 4 x 2.4e9 / 4 wave instructions per second
+PEAK_VALU_WAVE_INSTS = 256 * 4 * 2.4e9 / 4
 
 
 def kernel_source_hash():
@@ -66,21 +69,40 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(kernel, n):
-    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE / WRITE_SIZE
-    summary (copy-calibrated), or None when that summary was taken on other
-    kernel sources or another mesh size."""
-    if n != 128 or kernel not in KERNEL_FUNCS or not os.path.exists(TRAFFIC_FILE) or \
-            WORKLOAD[0] != "deform3d":
+def _profile_record(prefix, tag):
+    """The JSON line `tag` of profiles/<prefix>_<workload>_<n>.md when it was
+    taken on the current kernel sources, else None."""
+    path = os.path.join(ROOT, "profiles", f"{prefix}_{WORKLOAD[0]}_{WORKLOAD[1]}.md")
+    if not os.path.exists(path):
         return None
-    with open(TRAFFIC_FILE) as fh:
-        line = next((ln for ln in fh if ln.startswith("traffic-json:")), None)
+    with open(path) as fh:
+        line = next((ln for ln in fh if ln.startswith(tag + ":")), None)
     if line is None:
         return None
     rec = json.loads(line.split(":", 1)[1])
-    if rec.get("source_sha256_16") != kernel_source_hash():
+    return rec if rec.get("source_sha256_16") == kernel_source_hash() else None
+
+
+def recorded_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE / WRITE_SIZE
+    summary of the profiled window (copy-calibrated), or None when it was taken
+    on other kernel sources."""
+    rec = _profile_record("hbm_traffic", "traffic-json")
+    return None if rec is None else rec["bytes_per_launch"].get(KERNEL_FUNCS.get(kernel, ""))
+
+
+def recorded_flops(kernel, unit):
+    """(executed FP64 flops per unit, VALU wave instructions per launch) of
+    `kernel` from the committed counter summary of the profiled window, or
+    None when it was taken on other kernel sources."""
+    rec = _profile_record("fp64_counters", "flops-json")
+    if rec is None or not rec.get("window_units_per_step"):
         return None
-    return rec["bytes_per_launch"].get(KERNEL_FUNCS[kernel])
+    f = KERNEL_FUNCS.get(kernel, "")
+    n = rec["window_units_per_step"].get(unit)
+    if f not in rec["flops_per_launch"] or not n:
+        return None
+    return rec["flops_per_launch"][f] / n, rec.get("valu_insts_per_launch", {}).get(f)
 
 
 CPU_SAMPLE_SECONDS = 10.0   # oracle steps are run until this much host time has passed
@@ -598,6 +620,7 @@ def main():
     WORKLOAD[0] = args.workload
     if args.n is None:
         args.n = 80 if args.workload == "tets" else 128
+    WORKLOAD.append(args.n)
     Wm = args.warmup
     log(f"[bench] generating {args.workload} {args.n}^3")
     make = {"deform3d": W.deform3d, "shear3d": W.shear3d, "tets": W.rotate_tets}[args.workload]
@@ -700,24 +723,30 @@ def main():
     dom_ms, dom_n = prof[dom]
     avg_s = dom_ms / dom_n / 1e3
     units = {"flux": ((sp1["face_fluxes"] - sp0["face_fluxes"]) / P, FLUX_FLOPS_PER_QUAD_FACE,
-                      "face-fluxes"),
+                      "face-fluxes", "face_fluxes"),
              "clip": ((sp1["clip_pairs"] - sp0["clip_pairs"]) / P, CLIP_FLOPS_PER_PAIR,
-                      "overlapping (tet, cell) pairs"),
+                      "overlapping (tet, cell) pairs", "clip_pairs"),
              "plane": ((sp1["interface_cells"] - sp0["interface_cells"]) / P,
-                       PLANE_FLOPS_PER_CELL, "interface cells")}
+                       PLANE_FLOPS_PER_CELL, "interface cells", "interface_cells")}
+    roof = {"kernel": dom, "bound": "alu", "achieved": None, "peak": PEAK_FP64_TFLOPS,
+            "unit": "TFLOP/s", "frac": None, "traffic": recorded_traffic(dom),
+            "avg_launch_us": avg_s * 1e6, "profiled_steps": P, "profiled_from_step": mid}
     if dom in units:
-        n_units, per_unit, what = units[dom]
+        n_units, estimate, what, key = units[dom]
+        measured = recorded_flops(dom, key)
+        # executed FP64 flops counted on the same window (rocprofv3 FP64
+        # instruction counters x active lanes) when taken on these sources,
+        # else the per-unit estimate
+        per_unit = measured[0] if measured else estimate
         achieved = n_units * per_unit / avg_s / 1e12
-        roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
-                "traffic": recorded_traffic(dom, args.n),
-                "avg_launch_us": avg_s * 1e6, "units_per_launch": n_units,
-                "flop_per_unit": per_unit, "unit_kind": what, "profiled_steps": P,
-                "profiled_from_step": mid}
-    else:
-        roof = {"kernel": dom, "bound": "alu", "achieved": None, "peak": PEAK_FP64_TFLOPS,
-                "unit": "TFLOP/s", "frac": None, "traffic": recorded_traffic(dom, args.n),
-                "avg_launch_us": avg_s * 1e6, "profiled_steps": P, "profiled_from_step": mid}
+        roof.update({"achieved": achieved, "frac": achieved / PEAK_FP64_TFLOPS,
+                     "units_per_launch": n_units, "flop_per_unit": per_unit,
+                     "flop_per_unit_source": "rocprofv3 FP64 counters" if measured
+                     else "estimate", "flop_per_unit_estimate": estimate, "unit_kind": what})
+        if measured and measured[1]:
+            issue = measured[1] / avg_s
+            roof["valu_issue"] = {"wave_insts_per_s": issue, "peak": PEAK_VALU_WAVE_INSTS,
+                                  "frac": issue / PEAK_VALU_WAVE_INSTS}
     step_after = mid + P
 
     parity = None
