@@ -553,9 +553,11 @@ def main():
     ap.add_argument("--n", type=int, default=None,
                     help="mesh is n^3 hexahedra (default 128), or n^3 cubes of six jittered "
                          "tetrahedra for tets (default 80)")
-    ap.add_argument("--workload", choices=["deform3d", "shear3d", "tets", "batched", "served"],
+    ap.add_argument("--workload",
+                    choices=["deform3d", "shear3d", "tets", "disc2d", "batched", "served"],
                     default="deform3d",
-                    help="deform3d (eq. 4.6, fixed dt; the headline case), shear3d "
+                    help="deform3d (eq. 4.6, fixed dt; the headline case), disc2d (the "
+                         "64x64x1 layer of the 2D translation, 50 steps), shear3d "
                          "(eq. 4.5, adaptive Courant dt), tets (slotted sphere rotating "
                          "on jittered tetrahedra), batched (many meshes per launch against "
                          "the plain per-mesh loop) or served (a request stream against the "
@@ -619,11 +621,12 @@ def main():
         return
     WORKLOAD[0] = args.workload
     if args.n is None:
-        args.n = 80 if args.workload == "tets" else 128
+        args.n = {"tets": 80, "disc2d": 64}.get(args.workload, 128)
     WORKLOAD.append(args.n)
     Wm = args.warmup
     log(f"[bench] generating {args.workload} {args.n}^3")
-    make = {"deform3d": W.deform3d, "shear3d": W.shear3d, "tets": W.rotate_tets}[args.workload]
+    make = {"deform3d": W.deform3d, "shear3d": W.shear3d, "tets": W.rotate_tets,
+            "disc2d": W.disc2d}[args.workload]
     w = make(args.n)  # the whole run: to T, or one revolution
     K = w.n_steps if args.steps is None else min(args.steps, w.n_steps)
     if args.workload == "tets" and args.steps is None:
@@ -662,7 +665,7 @@ def main():
     # timed region: steps 0 .. K-1 as the library runs them (one captured graph
     # per step, replayed on the library's stream), in segments whose times give
     # the rate along the run
-    nseg = min(K, 24)
+    nseg = 1 if args.workload == "disc2d" else min(K, 24)  # 50 steps of ~0.1 ms: one segment
     bounds = np.linspace(0, K, nseg + 1).astype(int)
     log(f"[bench] timing {K} steps ({nseg} segments)")
     seg_ms = []
@@ -773,7 +776,10 @@ def main():
                        "tets": f"tets {args.n}^3 cubes x 6 jittered Kuhn tetrahedra (slotted "
                                f"sphere r=0.15 at (0.5,0.75,0.5), rotation about z, "
                                f"omega=2 pi, cell Courant 0.5, dt=1/{w.meta.get('steps_per_rev')}"
-                               f")"}[args.workload]
+                               f")",
+                       "disc2d": f"disc2d hex {args.n}x{args.n}x1 layer (disc r=0.15 at "
+                                 f"(0.5,0.75), U=(1,0.5,0), Co 0.5, dt=0.5h/sqrt(1.25))",
+                       }[args.workload]
                                + f", steps 0..{K - 1} of {w.n_steps} (timed from alpha^0)",
                    "cells": int(w.mesh.n_cells), "faces": int(w.mesh.n_faces),
                    "band_wisps": bool(args.band_wisps),
