@@ -536,9 +536,9 @@ void orc_set_velocity(omesh *M, const double *Uc, const double *F0, double *Up_o
 /* ------------------------------------------------------------------ */
 /* flux polyhedron (eq. 2.16, tetrahedral decomposition eq. 2.18)      */
 /* ------------------------------------------------------------------ */
-/* READING: the correction "moves the end points" along the point velocity
- * directions; one factor lambda per face scales every sweep vector of that
- * face, so the swept point of face point p is x_p - lambda * s * dt * U_p.
+/* READING: the correction shifts the swept end points along the point
+ * velocity directions; one factor lambda per face scales every sweep vector
+ * of that face, so the swept point of face point p is x_p - lambda * s * dt * U_p.
  * The polyhedron surface is: base fan (c_f, p_i, p_i+1), top fan
  * (c_q, q_i+1, q_i) about the mean c_q of the swept points, and each side
  * quad (p_i+1, p_i, q_i, q_i+1) split into four triangles about its vertex
