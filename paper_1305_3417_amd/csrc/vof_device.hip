@@ -31,6 +31,7 @@ namespace {
 constexpr int kWave = 64;     // wavefront width
 constexpr int kBlock = 256;
 constexpr int kClipBlock = 64;
+constexpr unsigned kFluxGrid = 2048;  // flux kernel blocks at most
 constexpr int kFastBlock = 64;   // one wave per block in the register clip
 // register clip configurations: queued pairs of two or more planes per tet,
 // candidate cells of a face group kept in LDS (CAND / F per face), and
@@ -65,14 +66,9 @@ __host__ __device__ __forceinline__ int64_t grid_for_dev(int64_t n, int block) {
 }
 
 // Workgroups are dispatched round-robin over the eight XCDs (block b on XCD
-// b % 8), each with its own L2.  Renumbered this way every XCD works through
-// a contiguous range of the logical block indices, so neighbouring faces
-// (which share points) meet in the same L2.  The grid must be a multiple of 8.
+// b % 8), each with its own L2; kernels that give every XCD a contiguous
+// range of the work take grids that are multiples of 8.
 constexpr int kXcds = 8;
-__device__ __forceinline__ int xcd_block() {
-  const int b = (int)blockIdx.x;
-  return (b % kXcds) * (int)(gridDim.x / kXcds) + b / kXcds;
-}
 
 // Append the lanes with `pred` to a list: one atomic per wavefront.  Must be
 // reached by every lane of the wavefront.
@@ -677,10 +673,14 @@ __device__ __forceinline__ void correct(double c1, double c2, double c3, double 
 
 // Point indices of face f from the padded list (-1 past the last point): one
 // 16-byte load per four points.
+// The flux kernel streams its per-face inputs and outputs with the
+// non-temporal hint, so that they pass through L2 without displacing the
+// point records that the next rows of faces share.
+typedef int int4_nt __attribute__((ext_vector_type(4)));
 template <int NMAX>
 __device__ __forceinline__ void load_face_points(const DMesh &m, int64_t f, int (&q)[NMAX]) {
   if constexpr (NMAX <= 4) {
-    const int4 v = *reinterpret_cast<const int4 *>(m.fpad + 4 * f);
+    const int4_nt v = __builtin_nontemporal_load(reinterpret_cast<const int4_nt *>(m.fpad + 4 * f));
     const int w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
     for (int i = 0; i < NMAX; ++i) q[i] = w[i];
@@ -782,7 +782,7 @@ __device__ __forceinline__ void flux_chunk(const DMesh &m, const DState &s, cons
       // the point list and the flux are independent loads, issued together
       int q[NMAX];
       load_face_points<NMAX>(m, f, q);
-      double F = sc * s.F0[f];
+      double F = sc * __builtin_nontemporal_load(&s.F0[f]);
       double T = F * dt;
       double lam = 0.0, vph = 0.0;
       int it = 0, stat = 0;
@@ -833,11 +833,11 @@ __device__ __forceinline__ void flux_chunk(const DMesh &m, const DState &s, cons
         }
         s.fbulk[f] = mask == 1 ? 1 : (mask == 2 ? 2 : 0);
       }
-      s.lam[f] = lam;
-      if (!geo) s.vphase[f] = vph;
-      s.iters[f] = (uint8_t)(it > 255 ? 255 : it);
-      s.kind[f] = kind;
-      s.fstatus[f] = (uint8_t)stat;
+      __builtin_nontemporal_store(lam, &s.lam[f]);
+      if (!geo) __builtin_nontemporal_store(vph, &s.vphase[f]);
+      __builtin_nontemporal_store((uint8_t)(it > 255 ? 255 : it), &s.iters[f]);
+      __builtin_nontemporal_store(kind, &s.kind[f]);
+      __builtin_nontemporal_store((uint8_t)stat, &s.fstatus[f]);
     }
     int slot = wave_append(&s.work[kWGeometric], geo);
     if (geo) s.gfaces[slot] = (int32_t)f;
@@ -848,10 +848,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NMAX <= 
 void k_flux(DMesh m, DState s, DParams p) {
   const int step = *s.stepno;
   const double dt = s.dt[step], sc = s.sc[step];
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  // every XCD walks one contiguous range of the face blocks with its blocks
+  // side by side (a grid of about the resident blocks moves as one front),
+  // so a point record fetched for one row of cells is still in that XCD's L2
+  // when the faces of the next row need it
+  const int64_t nb = (m.nf + blockDim.x - 1) / blockDim.x;
+  const int per = (int)gridDim.x / kXcds;
+  const int x = (int)blockIdx.x % kXcds, j = (int)blockIdx.x / kXcds;
+  const int64_t b1 = nb * (x + 1) / kXcds;
   unsigned long long nflux = 0, nit = 0, nbad = 0;
-  for (int64_t base = (int64_t)xcd_block() * blockDim.x; base < m.nf; base += stride)
-    flux_chunk<NMAX>(m, s, p, base, dt, sc, nflux, nit, nbad);
+  for (int64_t b = nb * x / kXcds + j; b < b1; b += per)
+    flux_chunk<NMAX>(m, s, p, b * blockDim.x, dt, sc, nflux, nit, nbad);
   block_count3(cnt_at(s.cnt, kCntFaceFluxes), nflux, cnt_at(s.cnt, kCntIters), nit, cnt_at(s.cnt, kCntUnreached), nbad);
 }
 
@@ -2298,10 +2305,9 @@ void launch_step(const DMesh &m, const DState &s, const DParams &p, hipStream_t 
   } else {
     TIMED(prof, kKPlane, (k_plane<<<kPlaneGrid, kBlock, 0, st>>>(m, s, p)));
   }
-  // persistent-style grid: a few blocks per CU, grid-stride over the faces
-  // (4096 blocks leave room for the plane kernel beside it)
+  // persistent-style grid, a multiple of the XCD count
   unsigned gf = grid_for(m.nf, kBlock);
-  gf = gf < 4096 ? gf : 4096;
+  gf = gf < kFluxGrid ? gf : kFluxGrid;
   gf = (gf + kXcds - 1) / kXcds * kXcds;
   if (m.maxn <= 3)
     TIMED(prof, kKFlux, (k_flux<3><<<gf, kBlock, 0, st>>>(m, s, p)));

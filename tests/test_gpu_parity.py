@@ -418,20 +418,35 @@ def test_empty_and_full_fields(vof, ctx):
         g["mesh"].close()
 
 
+# (workload, first step): the later starts take the GPU's own state after
+# that many steps (the interface stretched furthest, T/2, on the deformation
+# case; a thousand steps into the rotation on the tets)
 FULL_SIZE = {
-    "deform3d-128": lambda: W.deform3d(128, steps=1),
-    "shear3d-128": lambda: W.shear3d(128, steps=1),
-    "tets-80": lambda: W.rotate_tets(80, steps=1),
+    "deform3d-128": (lambda: W.deform3d(128, steps=1), 0),
+    "deform3d-128-mid": (lambda: W.deform3d(128), 768),
+    "shear3d-128": (lambda: W.shear3d(128, steps=1), 0),
+    "tets-80": (lambda: W.rotate_tets(80, steps=1), 0),
+    "tets-80-mid": (lambda: W.rotate_tets(80, steps=1001), 1000),
 }
 
 
 @pytest.mark.parametrize("case", sorted(FULL_SIZE))
 def test_full_size_sampled(vof, ctx, oracle_mod, case):
     """The 128^3 deformation case (the benchmark's, in its launch
-    configuration), the 128^3 shear case and the 80^3 x 6 jittered-tet case,
-    one step each: sampled faces and cells checked one by one against the
-    oracle."""
-    w = FULL_SIZE[case]()
+    configuration), the 128^3 shear case and the 80^3 x 6 jittered-tet case:
+    one step from alpha^0, and for the deformation and tet cases one step
+    from the GPU's state in the middle of the run, sampled faces and cells
+    checked one by one against the oracle from the same state."""
+    import dataclasses
+    make, start = FULL_SIZE[case]
+    w = make()
+    if start:
+        print(f"[{case}] gpu advances {start} steps", flush=True)
+        g0 = gpu_run(vof, ctx, w, steps=start)
+        a = g0["alpha"]
+        g0["mesh"].close()
+        w = dataclasses.replace(w, alpha0=a, dt=w.dt[start:start + 1],
+                                scale=w.scale[start:start + 1])
     print(f"[{case}] gpu step", flush=True)
     g = gpu_run(vof, ctx, w, steps=1)
     rng = np.random.default_rng(17)
@@ -463,10 +478,14 @@ def test_full_size_sampled(vof, ctx, oracle_mod, case):
     assert np.array_equal(g["status"][faces], r["status"].astype(np.uint8))
     fl = (w.F0[faces] != 0) & (r["status"] == 0)
     rel = np.abs(g["lam"][faces][fl] - r["lam"][fl]) / np.abs(r["lam"][fl])
-    assert rel.max() < 1e-8
+    # lambda to 1e-8, or to what a volume error within the V_alpha bound
+    # moves it by (about tol / |F dt| relative where V is near-linear in
+    # lambda): near the field's reversal (mid-run) the fluxes are tiny
+    tol_all = vphase_tolerance(w, V, sdt, S, Up)
+    lam_bound = np.maximum(1e-8, 10.0 * tol_all[faces][fl] / np.abs(w.F0[faces][fl] * sdt))
+    assert (rel <= lam_bound).all(), (rel / lam_bound).max()
     # the oracle's own volume at the GPU's lambda meets F dt (lambda itself is
     # ill-conditioned where V' is small; the volume is what the update uses)
-    tol_all = vphase_tolerance(w, V, sdt, S, Up)
     for f in faces[fl][::3]:
         res = abs(o.flux_volume(f, w.dt[0], w.scale[0], g["lam"][f]) - w.F0[f] * sdt)
         assert res <= tol_all[f]
