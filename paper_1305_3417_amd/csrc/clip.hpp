@@ -167,18 +167,18 @@ VHD Pl cell_plane_at(const DMesh &m, int q, v3 c) {
 VHD Pl cut_plane(const DMesh &m, int u, const double *bb, v3 c) {
   return u >= 0 ? cell_plane_at(m, u, c) : box_plane(bb, ~u, c);
 }
-VHD Pl plic_plane_at(const DState &s, int cell, v3 c) {
-  double4 pp = s.plane[cell];
+// a plane (unit normal, offset) relative to the local origin c
+VHD Pl plane_rel(double4 pp, v3 c) {
   v3 nn = xyz4(pp);
   return mkpl(nn, pp.w - dot(nn, c));
 }
+VHD Pl plic_plane_at(const DState &s, int cell, v3 c) { return plane_rel(s.plane[cell], c); }
 
 // The planes bounding the phase region of a classified pair in slots
 // p0..p3: the cutting cell planes in mask order, then the PLIC plane of an
 // interface cell (slots past the last plane are left unspecified).
-VHD void pair_regs(const DMesh &m, const DState &s, v3 c, int cell, int cl, uint32_t mask, Pl &p0,
-                   Pl &p1, Pl &p2, Pl &p3) {
-  const int q0 = m.cf_off[cell];
+VHD void pair_regs_q(const DMesh &m, const DState &s, v3 c, int cell, int cl, int q0,
+                     uint32_t mask, Pl &p0, Pl &p1, Pl &p2, Pl &p3) {
   const Pl pl = cl == 1 ? plic_plane_at(s, cell, c) : Pl{0, 0, 0, 0};
   uint32_t mm = mask;
   p0 = mm ? cell_plane_at(m, q0 + __builtin_ctz(mm), c) : pl;
@@ -188,6 +188,10 @@ VHD void pair_regs(const DMesh &m, const DState &s, v3 c, int cell, int cl, uint
   p2 = mm ? cell_plane_at(m, q0 + __builtin_ctz(mm), c) : pl;
   mm &= mm - 1;
   p3 = mm ? cell_plane_at(m, q0 + __builtin_ctz(mm), c) : pl;
+}
+VHD void pair_regs(const DMesh &m, const DState &s, v3 c, int cell, int cl, uint32_t mask, Pl &p0,
+                   Pl &p1, Pl &p2, Pl &p3) {
+  pair_regs_q(m, s, c, cell, cl, m.cf_off[cell], mask, p0, p1, p2, p3);
 }
 
 // weight of a covered volume in the phase region of a full (2) or

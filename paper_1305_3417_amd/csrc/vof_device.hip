@@ -921,9 +921,13 @@ __device__ __forceinline__ bool staged_tet(const double (*P)[6], int n, const do
 // A queued pair of the register clip: the tet (from its lane's LDS row), its
 // six-fold volume, the cell, its class and its planes in mask order (then
 // the PLIC plane of an interface cell).
+// The candidate's class comes from LDS, and so does its first plane index
+// when the kernel stages it (ccq0, cells that are not boxes), so the plane
+// loads do not wait on other loads.
 __device__ __forceinline__ void queued_pair(const DMesh &m, const DState &s, const uint32_t *qpair,
                                             const double (*tv)[kFastBlock],
                                             const double (*fc)[3], const int32_t *ccell,
+                                            const int8_t *ccls, const int32_t *ccq0,
                                             const double (*cbox)[6], int tpf, int kc, int item,
                                             Tet &T, double &det, int &cell, int &cl, Pl &p0,
                                             Pl &p1, Pl &p2, Pl &p3) {
@@ -936,11 +940,12 @@ __device__ __forceinline__ void queued_pair(const DMesh &m, const DState &s, con
   T = Tet{mk3(0, 0, 0), mk3(tv[0][l], tv[1][l], tv[2][l]), mk3(tv[3][l], tv[4][l], tv[5][l]),
           mk3(tv[6][l], tv[7][l], tv[8][l])};
   det = tv[9][l];
-  cl = s.cls[cell];
+  cl = ccls[u] & 7;
   if (qp & (1u << 22))
     pair_regs_box(cbox[u], s, c, cell, cl, qp & 0xffffu, p0, p1, p2, p3);
   else
-    pair_regs(m, s, c, cell, cl, qp & 0xffffu, p0, p1, p2, p3);
+    pair_regs_q(m, s, c, cell, cl, ccq0 ? ccq0[u] : m.cf_off[cell], qp & 0xffffu, p0, p1, p2,
+                p3);
 }
 
 // A phase-B bin of pairs of K planes, three lanes per pair (one per term of
@@ -951,6 +956,7 @@ __device__ __forceinline__ void three_lane_bin(const DMesh &m, const DState &s,
                                                const uint32_t *qpair,
                                                const double (*tv)[kFastBlock],
                                                const double (*fc)[3], const int32_t *ccell,
+                                               const int8_t *ccls, const int32_t *ccq0,
                                                const double (*cbox)[6], int tpf, int kc,
                                                const uint16_t *bin, int cnt, bool from_end,
                                                int cap, double *res) {
@@ -965,8 +971,8 @@ __device__ __forceinline__ void three_lane_bin(const DMesh &m, const DState &s,
       Tet T;
       int cell, cl;
       Pl p0, p1, p2, p3;
-      queued_pair(m, s, qpair, tv, fc, ccell, cbox, tpf, kc, item, T, det, cell, cl, p0, p1, p2,
-                  p3);
+      queued_pair(m, s, qpair, tv, fc, ccell, ccls, ccq0, cbox, tpf, kc, item, T, det, cell, cl,
+                  p0, p1, p2, p3);
       val = split_term<K>(dist_table<K>(T, p0, p1, p2, p3), term);
       w = class_weight(s, cell, cl);
     }
@@ -982,6 +988,7 @@ __device__ __forceinline__ void one_lane_bin(const DMesh &m, const DState &s,
                                              const uint32_t *qpair,
                                              const double (*tv)[kFastBlock],
                                              const double (*fc)[3], const int32_t *ccell,
+                                             const int8_t *ccls, const int32_t *ccq0,
                                              const double (*cbox)[6], int tpf, int kc,
                                              const uint16_t *bin, int cnt, bool from_end, int cap,
                                              double *res) {
@@ -991,7 +998,8 @@ __device__ __forceinline__ void one_lane_bin(const DMesh &m, const DState &s,
     int cell, cl;
     double det;
     Pl p0, p1, p2, p3;
-    queued_pair(m, s, qpair, tv, fc, ccell, cbox, tpf, kc, item, T, det, cell, cl, p0, p1, p2, p3);
+    queued_pair(m, s, qpair, tv, fc, ccell, ccls, ccq0, cbox, tpf, kc, item, T, det, cell, cl, p0,
+                p1, p2, p3);
     const double v = kept_fraction<K>(dist_table<K>(T, p0, p1, p2, p3));
     res[item] = class_weight(s, cell, cl) * (det * v);
   }
@@ -1006,6 +1014,7 @@ __device__ __forceinline__ void nine_lane_bin(const DMesh &m, const DState &s,
                                               const uint32_t *qpair,
                                               const double (*tv)[kFastBlock],
                                               const double (*fc)[3], const int32_t *ccell,
+                                              const int8_t *ccls, const int32_t *ccq0,
                                               int tpf, int kc, const uint16_t *bin, int cnt,
                                               int cap, double *res) {
   const int lane = threadIdx.x;
@@ -1020,15 +1029,16 @@ __device__ __forceinline__ void nine_lane_bin(const DMesh &m, const DState &s,
       const int l = item % kFastBlock;
       const uint32_t qp = qpair[item];
       const int lf = l / tpf;
-      const int cell = ccell[lf * kc + (int)((qp >> 16) & 63u)];
+      const int u = lf * kc + (int)((qp >> 16) & 63u);
+      const int cell = ccell[u];
       const v3 c = mk3(fc[lf][0], fc[lf][1], fc[lf][2]);
       const Tet T{mk3(0, 0, 0), mk3(tv[0][l], tv[1][l], tv[2][l]),
                   mk3(tv[3][l], tv[4][l], tv[5][l]), mk3(tv[6][l], tv[7][l], tv[8][l])};
       det = tv[9][l];
-      const int cl = s.cls[cell];
+      const int cl = ccls[u] & 7;
       // the four cutting planes in mask order, then the PLIC plane
       const Pl pl = plic_plane_at(s, cell, c);
-      const int q0 = m.cf_off[cell];
+      const int q0 = ccq0 ? ccq0[u] : m.cf_off[cell];
       uint32_t mm = qp & 0xffffu;
       const Pl a = cell_plane_at(m, q0 + __builtin_ctz(mm), c);
       mm &= mm - 1;
@@ -1097,6 +1107,8 @@ __device__ __forceinline__ void clip_fast_group(const DMesh &m, const DState &s,
   // candidates of face fi at fi * (CAND / F) + position
   __shared__ int32_t ccell[CAND];
   __shared__ int8_t ccls[CAND];  // class | 8 for a box cell
+  // first plane index (cf_off) of a candidate cell that is not a box
+  __shared__ int32_t ccq0[BOXES ? 1 : CAND];
   // candidate bounds (lo x y z, hi x y z): the box test, and the planes of a
   // box cell
   __shared__ double cbox[BOXES ? CAND : 1][6];
@@ -1226,6 +1238,7 @@ __device__ __forceinline__ void clip_fast_group(const DMesh &m, const DState &s,
             const int u = cf * kc + (pos - skip);
             ccell[u] = cell;
             ccls[u] = (int8_t)(cl | (BOXES && m.isbox[cell] ? 8 : 0));
+            if (!BOXES) ccq0[u] = m.cf_off[cell];
             if (BOXES) {
               cbox[u][0] = blo.x;
               cbox[u][1] = blo.y;
@@ -1248,6 +1261,74 @@ __device__ __forceinline__ void clip_fast_group(const DMesh &m, const DState &s,
           live = todo = false;
         }
       }
+      // Phase A1, for cells that are not boxes: which candidates of its face
+      // may overlap each tet (bit ci of cmask), found with the lanes over the
+      // candidates (each loads its cell's bounds and planes once) and a loop
+      // over the face's tets (their vertices read from LDS).  The tests are
+      // those of pair_cuts_box in the same arithmetic, so phase A visits the
+      // pairs it would keep and skips the rest without loading anything.
+      // The bit table lives in res, which phase B fills only later.
+      unsigned long long cmask = ~0ull;
+      if constexpr (!BOXES) {
+        unsigned long long *tmask = reinterpret_cast<unsigned long long *>(res);
+        tmask[lane] = 0ull;
+        const int L = kFastBlock / F;  // lanes per face
+        const int cf = lane / L, cin = lane - cf * L;
+        const bool fok = cf < F && g * F + cf < count;
+        const int ncf = fok ? min(cnum[cf] - skip, kc) : 0;
+        int mostc = ncf;
+        for (int o = 32; o > 0; o >>= 1) mostc = max(mostc, __shfl_xor(mostc, o));
+        const unsigned long long seg = L >= 64 ? ~0ull : ((1ull << L) - 1ull);
+        const v3 cc = fok ? mk3(fc[cf][0], fc[cf][1], fc[cf][2]) : mk3(0, 0, 0);
+        __syncthreads();
+        for (int c0 = 0; c0 < mostc; c0 += L) {
+          const int ci = c0 + cin;
+          const bool has = ci < ncf;
+          int np = 0, q0 = 0;
+          double4 blo = make_double4(0, 0, 0, 0), bhi = blo;
+          Pl cp[4] = {Pl{0, 0, 0, 0}, Pl{0, 0, 0, 0}, Pl{0, 0, 0, 0}, Pl{0, 0, 0, 0}};
+          if (has) {
+            const int u = cf * kc + ci;
+            const int cell = ccell[u];
+            q0 = ccq0[u];
+            blo = m.bblo[cell];
+            bhi = m.bbhi[cell];
+            np = m.npl[cell];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+              if (j < np) cp[j] = cell_plane_at(m, q0 + j, cc);
+          }
+          for (int k = 0; k < tpf; ++k) {
+            bool hit = false;
+            if (has) {
+              const int t = cf * tpf + k;
+              const v3 t1 = mk3(tv[0][t], tv[1][t], tv[2][t]);
+              const v3 t2 = mk3(tv[3][t], tv[4][t], tv[5][t]);
+              const v3 t3 = mk3(tv[6][t], tv[7][t], tv[8][t]);
+              v3 lo, hi;
+              tet_bbox(cc, t1, t2, t3, lo, hi);
+              hit = !(hi.x <= blo.x || lo.x >= bhi.x || hi.y <= blo.y || lo.y >= bhi.y ||
+                      hi.z <= blo.z || lo.z >= bhi.z);
+              auto outside = [&](const Pl &pl) {
+                const v3 nn = mk3(pl.x, pl.y, pl.z);
+                const double off = pl.w;
+                const double d1 = off - dot(nn, t1), d2 = off - dot(nn, t2),
+                             d3 = off - dot(nn, t3);
+                return dmax(dmax(off, d1), dmax(d2, d3)) <= 0.0;
+              };
+#pragma unroll
+              for (int j = 0; j < 4; ++j)
+                if (hit && j < np && outside(cp[j])) hit = false;
+              for (int j = 4; hit && j < np; ++j)
+                if (outside(cell_plane_at(m, q0 + j, cc))) hit = false;
+            }
+            const unsigned long long b = __ballot(hit);
+            if (fok && cin == 0) tmask[cf * tpf + k] |= ((b >> (cf * L)) & seg) << c0;
+          }
+        }
+        __syncthreads();
+        cmask = tmask[lane];
+      }
       // Phases A to C in rounds: a tet whose queue is full stops at that pair
       // and resumes there in the next round, once its queued pairs are added.
       for (;;) {
@@ -1266,6 +1347,11 @@ __device__ __forceinline__ void clip_fast_group(const DMesh &m, const DState &s,
           bool paused = false, inside = false;
           int ci = ci0;
           for (; ci < nc; ++ci) {
+            if constexpr (!BOXES) {  // on to the next candidate phase A1 kept
+              const unsigned long long r = cmask >> ci;
+              if (!r) break;
+              ci += __builtin_ctzll(r);
+            }
             const int u = fi * kc + ci;
             const int cell = ccell[u];
             const int cb = ccls[u];
@@ -1338,18 +1424,20 @@ __device__ __forceinline__ void clip_fast_group(const DMesh &m, const DState &s,
         // lanes each.  Every bin takes the same way whatever its size: which
         // faces share a group follows the order of the geometric-face list,
         // which is not fixed from run to run.
-        one_lane_bin<2>(m, s, qpair, tv, fc, ccell, cbox, tpf, kc, bins[0], nbin[0], false,
-                        kCap, res);
+        const int32_t *q0s = BOXES ? nullptr : ccq0;
+        one_lane_bin<2>(m, s, qpair, tv, fc, ccell, ccls, q0s, cbox, tpf, kc, bins[0], nbin[0],
+                        false, kCap, res);
         if constexpr (BOXES)
-          three_lane_bin<3>(m, s, qpair, tv, fc, ccell, cbox, tpf, kc, bins[1], nbin[1], false,
-                            kCap, res);
+          three_lane_bin<3>(m, s, qpair, tv, fc, ccell, ccls, q0s, cbox, tpf, kc, bins[1],
+                            nbin[1], false, kCap, res);
         else
-          one_lane_bin<3>(m, s, qpair, tv, fc, ccell, cbox, tpf, kc, bins[1], nbin[1], false,
-                          kCap, res);
-        three_lane_bin<4>(m, s, qpair, tv, fc, ccell, cbox, tpf, kc, bins[1], nbin[2], true,
-                          kCap, res);
+          one_lane_bin<3>(m, s, qpair, tv, fc, ccell, ccls, q0s, cbox, tpf, kc, bins[1], nbin[1],
+                          false, kCap, res);
+        three_lane_bin<4>(m, s, qpair, tv, fc, ccell, ccls, q0s, cbox, tpf, kc, bins[1], nbin[2],
+                          true, kCap, res);
         if constexpr (MAXPL >= 5)
-          nine_lane_bin(m, s, qpair, tv, fc, ccell, tpf, kc, bins[0], nbin[3], kCap, res);
+          nine_lane_bin(m, s, qpair, tv, fc, ccell, ccls, q0s, tpf, kc, bins[0], nbin[3], kCap,
+                        res);
         __syncthreads();
         // phase C
         if (live)
