@@ -1266,9 +1266,15 @@ __device__ __forceinline__ void clip_fast_group(const DMesh &m, const DState &s,
       // candidates (each loads its cell's bounds and planes once) and a loop
       // over the face's tets (their vertices read from LDS).  The tests are
       // those of pair_cuts_box in the same arithmetic, so phase A visits the
-      // pairs it would keep and skips the rest without loading anything.
-      // The bit table lives in res, which phase B fills only later.
+      // pairs it would keep and skips the rest without loading anything; the
+      // first round of phase A also takes each pair's cutting-plane mask from
+      // A1 (a code byte per tet and candidate: 0x80 overlap, bits 0-3 the
+      // mask of the first four planes, 0x10 a cell of more planes, whose pair
+      // is tested again).  The tables live in res, which phase B fills only
+      // later.
       unsigned long long cmask = ~0ull;
+      uint8_t *tcode = reinterpret_cast<uint8_t *>(res + kFastBlock);
+      static_assert(BOXES || 8 * kFastBlock + kFastBlock * 63 <= 8 * kCap, "A1 tables in res");
       if constexpr (!BOXES) {
         unsigned long long *tmask = reinterpret_cast<unsigned long long *>(res);
         tmask[lane] = 0ull;
@@ -1300,8 +1306,9 @@ __device__ __forceinline__ void clip_fast_group(const DMesh &m, const DState &s,
           }
           for (int k = 0; k < tpf; ++k) {
             bool hit = false;
+            uint32_t cut = 0;
+            const int t = cf * tpf + k;
             if (has) {
-              const int t = cf * tpf + k;
               const v3 t1 = mk3(tv[0][t], tv[1][t], tv[2][t]);
               const v3 t2 = mk3(tv[3][t], tv[4][t], tv[5][t]);
               const v3 t3 = mk3(tv[6][t], tv[7][t], tv[8][t]);
@@ -1309,18 +1316,23 @@ __device__ __forceinline__ void clip_fast_group(const DMesh &m, const DState &s,
               tet_bbox(cc, t1, t2, t3, lo, hi);
               hit = !(hi.x <= blo.x || lo.x >= bhi.x || hi.y <= blo.y || lo.y >= bhi.y ||
                       hi.z <= blo.z || lo.z >= bhi.z);
-              auto outside = [&](const Pl &pl) {
+              // plane j: false when the tet lies outside it, else its cut bit
+              auto test = [&](const Pl &pl, int j) {
                 const v3 nn = mk3(pl.x, pl.y, pl.z);
                 const double off = pl.w;
                 const double d1 = off - dot(nn, t1), d2 = off - dot(nn, t2),
                              d3 = off - dot(nn, t3);
-                return dmax(dmax(off, d1), dmax(d2, d3)) <= 0.0;
+                const double dmx = dmax(dmax(off, d1), dmax(d2, d3));
+                const double dmn = dmin(dmin(off, d1), dmin(d2, d3));
+                cut |= (dmn < 0.0 ? 1u : 0u) << (j & 3);
+                return dmx > 0.0;
               };
 #pragma unroll
               for (int j = 0; j < 4; ++j)
-                if (hit && j < np && outside(cp[j])) hit = false;
+                if (hit && j < np && !test(cp[j], j)) hit = false;
               for (int j = 4; hit && j < np; ++j)
-                if (outside(cell_plane_at(m, q0 + j, cc))) hit = false;
+                if (!test(cell_plane_at(m, q0 + j, cc), j)) hit = false;
+              tcode[t * kc + ci] = (uint8_t)(hit ? 0x80u | (cut & 15u) | (np > 4 ? 0x10u : 0u) : 0u);
             }
             const unsigned long long b = __ballot(hit);
             if (fok && cin == 0) tmask[cf * tpf + k] |= ((b >> (cf * L)) & seg) << c0;
@@ -1331,6 +1343,7 @@ __device__ __forceinline__ void clip_fast_group(const DMesh &m, const DState &s,
       }
       // Phases A to C in rounds: a tet whose queue is full stops at that pair
       // and resumes there in the next round, once its queued pairs are added.
+      bool first = true;  // A1's code bytes are valid (res not yet written)
       for (;;) {
         int nq = 0;
         if (todo) {
@@ -1360,7 +1373,12 @@ __device__ __forceinline__ void clip_fast_group(const DMesh &m, const DState &s,
             const double *bb = cbox[BOXES ? u : 0];
             uint32_t mask;
             int ncut;
-            if (!BOXES) ncut = pair_cuts(m, c, T, lo, hi, cell, mask);
+            uint32_t code = 0;
+            if (!BOXES && first) code = tcode[lane * kc + ci];
+            if (!BOXES && (code & 0x90u) == 0x80u) {
+              mask = code & 15u;
+              ncut = __builtin_popcount(mask);
+            } else if (!BOXES) ncut = pair_cuts(m, c, T, lo, hi, cell, mask);
             else if (box) ncut = box_cuts(bb, c, T, mask);
             else
               ncut = pair_cuts_box(m, c, T, lo, hi, mk3(bb[0], bb[1], bb[2]),
@@ -1383,7 +1401,8 @@ __device__ __forceinline__ void clip_fast_group(const DMesh &m, const DState &s,
                 const int q = __builtin_ctz(mask);
                 const Pl pl = !ncut ? plic_plane_at(s, cell, c)
                                     : (box ? box_plane(bb, q, c)
-                                           : cell_plane_at(m, m.cf_off[cell] + q, c));
+                                           : cell_plane_at(m, (BOXES ? m.cf_off[cell] : ccq0[u]) + q,
+                                                           c));
                 fr = tet_kept_fraction(plane_dists(T, pl));
               }
               acc += class_weight(s, cell, cl) * det * fr;
@@ -1440,6 +1459,7 @@ __device__ __forceinline__ void clip_fast_group(const DMesh &m, const DState &s,
                         res);
         __syncthreads();
         // phase C
+        first = false;
         if (live)
           for (int j = 0; j < nq; ++j) acc += res[j * kFastBlock + lane];
         if (!__ballot(todo)) break;
