@@ -219,7 +219,7 @@ __global__ void k_cell_geom(DMesh m, double *V, double4 *XC, double4 *bblo, doub
 // for bit) to one the cell has already is not repeated: the coplanar faces a
 // coarse cell shares with refined neighbours are one plane of the cell.
 __global__ void k_cell_planes(DMesh m, double4 *cpl, uint8_t *npl, uint8_t *isbox,
-                              uint8_t *fan_small, const double4 *bblo, const double4 *bbhi) {
+                              uint8_t *fan_w, const double4 *bblo, const double4 *bbhi) {
   int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (c >= m.nc) return;
   const int k0 = m.cf_off[c];
@@ -260,7 +260,8 @@ __global__ void k_cell_planes(DMesh m, double4 *cpl, uint8_t *npl, uint8_t *isbo
     const int f = sf >= 0 ? sf : ~sf;
     slots += m.foff[f + 1] - m.foff[f];
   }
-  fan_small[c] = m.cf_off[c + 1] - k0 <= 32 && slots <= 64;
+  const int nfc = m.cf_off[c + 1] - k0;
+  fan_w[c] = nfc <= 16 && slots <= 32 ? 16 : (nfc <= 32 && slots <= 64 ? 32 : 64);
 }
 
 // inverse distance weights of the point-cells (eq. 2.7)
@@ -570,32 +571,61 @@ __device__ __forceinline__ void plane_cell(const DMesh &m, const DState &s, cons
     if (lane == 0) s.plane[c] = make_double4(n.x, n.y, n.z, sx + dot(n, o));
 }
 
-// NAG gradient and plane positioning of the interface cells.  A wave takes
-// two cells; when both have at most 32 faces and 64 fan tetrahedra (so
-// that two per lane cover them) each gets half of the wave, else the whole
-// wave does one after the other.
-// The pair of interface cells i = 2q, 2q + 1 of the list (of `count`).  A
-// cell is always evaluated by the same group width -- 32 lanes when it has at
-// most 32 faces and 64 fan tetrahedra, else the whole wave -- whatever cell
-// it is paired with: the lanes' partial sums, and so the rounding of the
-// group sums, depend on the width, and the list's order is not fixed.
-__device__ __forceinline__ void plane_pair(const DMesh &m, const DState &s, const DParams &p,
+// NAG gradient and plane positioning of the interface cells, four cells of
+// the list per wave.  A cell is always evaluated by the same group width --
+// the 16, 32 or 64 lanes its size admits (fan_w) -- whatever cells share its
+// wave: the lanes' partial sums, and so the rounding of the group sums,
+// depend on the width, and the list's order is not fixed.  The wave takes
+// its 16-lane cells side by side, then its 32-lane cells two at a time, then
+// its whole-wave cells one after the other.
+// The cells i = 4q .. 4q + 3 of the list (of `count`).
+__device__ __forceinline__ void plane_quad(const DMesh &m, const DState &s, const DParams &p,
                                            int q, int count, int lane,
                                            unsigned long long &nfall) {
-  const int i = 2 * q;
-  const int64_t ca = s.icells[i];
-  const int64_t cb = i + 1 < count ? s.icells[i + 1] : -1;
-  const bool sa = m.fan_small[ca], sb = cb >= 0 && m.fan_small[cb];
-  if (sa && (cb < 0 || sb)) {
-    const int64_t c = lane < 32 ? ca : cb;
-    if (c >= 0) plane_cell<32>(m, s, p, c, lane & 31, nfall);
-  } else {
-    if (!sa) plane_cell<64>(m, s, p, ca, lane, nfall);
-    else if (lane < 32) plane_cell<32>(m, s, p, ca, lane, nfall);
-    if (cb >= 0) {
-      if (!sb) plane_cell<64>(m, s, p, cb, lane, nfall);
-      else if (lane < 32) plane_cell<32>(m, s, p, cb, lane, nfall);
+  // cell j of the four and its group width (0 past the list), read again in
+  // every pass so that nothing stays live across the cell evaluations
+  auto cell_at = [&](int j, int &w) -> int64_t {
+    const int i = 4 * q + j;
+    const int64_t c = i < count ? (int64_t)s.icells[i] : -1;
+    w = c >= 0 ? (int)m.fan_w[c] : 0;
+    return c;
+  };
+  // 16-lane cells: the r-th of them takes lanes 16 r .. 16 r + 15
+  {
+    int64_t c16 = -1;
+    int r = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      int w;
+      const int64_t c = cell_at(j, w);
+      if (w == 16) {
+        c16 = r == lane / 16 ? c : c16;
+        ++r;
+      }
     }
+    if (c16 >= 0) plane_cell<16>(m, s, p, c16, lane & 15, nfall);
+  }
+  // 32-lane cells, two per pass: the k-th of them in lanes 32 (k % 2) ..
+  for (int pass = 0; pass < 2; ++pass) {
+    int64_t c32 = -1;
+    int r = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      int w;
+      const int64_t c = cell_at(j, w);
+      if (w == 32) {
+        c32 = r == 2 * pass + lane / 32 ? c : c32;
+        ++r;
+      }
+    }
+    if (r <= 2 * pass) break;
+    if (c32 >= 0) plane_cell<32>(m, s, p, c32, lane & 31, nfall);
+  }
+  // whole-wave cells one after the other
+  for (int j = 0; j < 4; ++j) {
+    int w;
+    const int64_t c = cell_at(j, w);
+    if (w == 64) plane_cell<64>(m, s, p, c, lane, nfall);
   }
 }
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_plane(DMesh m, DState s, DParams p) {
@@ -604,7 +634,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
   const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   const int nwaves = (int)((gridDim.x * blockDim.x) >> 6);
   unsigned long long nfall = 0;
-  for (int q = wave; 2 * q < count; q += nwaves) plane_pair(m, s, p, q, count, lane, nfall);
+  for (int q = wave; 4 * q < count; q += nwaves) plane_quad(m, s, p, q, count, lane, nfall);
   wave_count(cnt_at(s.cnt, kCntFallback), nfall);
 }
 
@@ -2142,7 +2172,7 @@ __global__ __launch_bounds__(kBlock) void kb_point_prep(BTab t) {
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void kb_plane(BTab t) {
   __shared__ int32_t pre[kMaxBatch + 1];
   const int n = t.hdr[0];
-  batch_prefix(n, pre, [&](int i) { return (t.inst[i].s.work[kWInterface] + 1) / 2; });
+  batch_prefix(n, pre, [&](int i) { return (t.inst[i].s.work[kWInterface] + 3) / 4; });
   const int lane = lane_id();
   const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   const int nwaves = (int)((gridDim.x * blockDim.x) >> 6);
@@ -2156,7 +2186,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
       cur = i;
     }
     const BInst &I = t.inst[i];
-    plane_pair(I.m, I.s, I.p, q - pre[i], I.s.work[kWInterface], lane, nfall);
+    plane_quad(I.m, I.s, I.p, q - pre[i], I.s.work[kWInterface], lane, nfall);
   }
   if (cur >= 0) wave_count(cnt_at(t.inst[cur].s.cnt, kCntFallback), nfall);
 }
@@ -2342,13 +2372,13 @@ inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 
 // ---------------------------------------------------------------------------
 void launch_mesh_geometry(const DMesh &m0, double4 *X, const double *pts, double4 *S, double4 *C,
                           double *V, double4 *XC, double *wpc, double4 *cpl, uint8_t *npl,
-                          uint8_t *isbox, uint8_t *fan_small, double4 *bblo,
+                          uint8_t *isbox, uint8_t *fan_w, double4 *bblo,
                           double4 *bbhi, uint32_t *flags, hipStream_t st) {
   DMesh m = m0;
   k_points<<<grid_for(m.np, kBlock), kBlock, 0, st>>>(m.np, pts, X);
   k_face_geom<<<grid_for(m.nf, kBlock), kBlock, 0, st>>>(m, S, C);
   k_cell_geom<<<grid_for(m.nc, kBlock), kBlock, 0, st>>>(m, V, XC, bblo, bbhi);
-  k_cell_planes<<<grid_for(m.nc, kBlock), kBlock, 0, st>>>(m, cpl, npl, isbox, fan_small, bblo,
+  k_cell_planes<<<grid_for(m.nc, kBlock), kBlock, 0, st>>>(m, cpl, npl, isbox, fan_w, bblo,
                                                             bbhi);
   k_idw<<<grid_for(m.np, kBlock), kBlock, 0, st>>>(m, wpc);
   if (m.ni > 0) k_check_orientation<<<grid_for(m.ni, kBlock), kBlock, 0, st>>>(m, flags);

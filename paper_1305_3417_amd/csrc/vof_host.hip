@@ -479,10 +479,10 @@ vof_status vof_mesh_upload(vof_context *ctx, const vof_mesh_desc *d, vof_mesh **
   ALLOC(d_pc_off, np + 1); ALLOC(d_pc, (int64_t)pc.size()); ALLOC(wpc, (int64_t)pc.size());
   ALLOC(d_st_off, nf + 1); ALLOC(d_st, (int64_t)st.size());
   ALLOC(S, nf); ALLOC(C, nf); ALLOC(V, nc); ALLOC(XC, nc); ALLOC(cpl, (int64_t)cf.size());
-  uint8_t *npl, *isbox, *fan_small;
+  uint8_t *npl, *isbox, *fan_w;
   ALLOC(npl, nc);
   ALLOC(isbox, nc);
-  ALLOC(fan_small, nc);
+  ALLOC(fan_w, nc);
   ALLOC(bblo, nc); ALLOC(bbhi, nc);
   ALLOC(ds.alpha, nc); ALLOC(ds.cls, nc); ALLOC(ds.plane, nc); ALLOC(ds.pmask, np);
   ALLOC(ds.alpha_p, np); ALLOC(ds.U, np); ALLOC(ds.F0, nf); ALLOC(ds.lam, nf);
@@ -521,9 +521,9 @@ vof_status vof_mesh_upload(vof_context *ctx, const vof_mesh_desc *d, vof_mesh **
   dm.X = X; dm.foff = d_foff; dm.fpts = d_fpts; dm.own = d_own; dm.nei = d_nei;
   dm.fpad = d_fpad; dm.padw = padw;
   dm.cf_off = d_cf_off; dm.cf = d_cf; dm.pc_off = d_pc_off; dm.pc = d_pc; dm.wpc = wpc;
-  dm.st_off = d_st_off; dm.st = d_st; dm.S = S; dm.C = C; dm.V = V; dm.XC = XC; dm.cpl = cpl; dm.npl = npl; dm.isbox = isbox; dm.fan_small = fan_small;
+  dm.st_off = d_st_off; dm.st = d_st; dm.S = S; dm.C = C; dm.V = V; dm.XC = XC; dm.cpl = cpl; dm.npl = npl; dm.isbox = isbox; dm.fan_w = fan_w;
   dm.bblo = bblo; dm.bbhi = bbhi;
-  launch_mesh_geometry(dm, X, d_pts, S, C, V, XC, wpc, cpl, npl, isbox, fan_small, bblo, bbhi,
+  launch_mesh_geometry(dm, X, d_pts, S, C, V, XC, wpc, cpl, npl, isbox, fan_w, bblo, bbhi,
                        ds.flags, s);
   e = hipGetLastError();
   if (e == hipSuccess) e = hipStreamSynchronize(s);

@@ -86,7 +86,8 @@ struct DMesh {
                            // (outward unit normal, offset), npl[c] of them
   const uint8_t *npl;
   const uint8_t *isbox;    // 1: the cell is its bounding box (six axis planes at its bounds)
-  const uint8_t *fan_small;  // 1: at most 32 faces and 64 face-fan tetrahedra
+  const uint8_t *fan_w;      // lanes of the cell's plane group: 16 (at most 16 faces and 32
+                             // face-fan tetrahedra), 32 (32 and 64) or 64
   const double4 *bblo;     // cell bounding box
   const double4 *bbhi;
 };
@@ -203,7 +204,7 @@ struct Prof {
 // launchers (vof_device.hip)
 void launch_mesh_geometry(const DMesh &m, double4 *X, const double *pts, double4 *S, double4 *C,
                           double *V, double4 *XC, double *wpc, double4 *cpl, uint8_t *npl,
-                          uint8_t *isbox, uint8_t *fan_small, double4 *bblo,
+                          uint8_t *isbox, uint8_t *fan_w, double4 *bblo,
                           double4 *bbhi, uint32_t *flags, hipStream_t st);
 void launch_point_velocity(const DMesh &m, const double *U0c, double4 *U, double *XU,
                            hipStream_t st);
