@@ -578,7 +578,10 @@ __device__ __forceinline__ void plane_cell(const DMesh &m, const DState &s, cons
 // depend on the width, and the list's order is not fixed.  The wave takes
 // its 16-lane cells side by side, then its 32-lane cells two at a time, then
 // its whole-wave cells one after the other.
-// The cells i = 4q .. 4q + 3 of the list (of `count`).
+// The cells i = 4q .. 4q + 3 of the list (of `count`).  WIDE: the mesh has
+// whole-wave cells (without, their pass is left out of the kernel, which then
+// fits its registers).
+template <bool WIDE>
 __device__ __forceinline__ void plane_quad(const DMesh &m, const DState &s, const DParams &p,
                                            int q, int count, int lane,
                                            unsigned long long &nfall) {
@@ -622,19 +625,22 @@ __device__ __forceinline__ void plane_quad(const DMesh &m, const DState &s, cons
     if (c32 >= 0) plane_cell<32>(m, s, p, c32, lane & 31, nfall);
   }
   // whole-wave cells one after the other
-  for (int j = 0; j < 4; ++j) {
-    int w;
-    const int64_t c = cell_at(j, w);
-    if (w == 64) plane_cell<64>(m, s, p, c, lane, nfall);
+  if constexpr (WIDE) {
+    for (int j = 0; j < 4; ++j) {
+      int w;
+      const int64_t c = cell_at(j, w);
+      if (w == 64) plane_cell<64>(m, s, p, c, lane, nfall);
+    }
   }
 }
+template <bool WIDE>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_plane(DMesh m, DState s, DParams p) {
   const int count = s.work[kWInterface];
   const int lane = lane_id();
   const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   const int nwaves = (int)((gridDim.x * blockDim.x) >> 6);
   unsigned long long nfall = 0;
-  for (int q = wave; 4 * q < count; q += nwaves) plane_quad(m, s, p, q, count, lane, nfall);
+  for (int q = wave; 4 * q < count; q += nwaves) plane_quad<WIDE>(m, s, p, q, count, lane, nfall);
   wave_count(cnt_at(s.cnt, kCntFallback), nfall);
 }
 
@@ -2169,6 +2175,7 @@ __global__ __launch_bounds__(kBlock) void kb_point_prep(BTab t) {
 }
 
 // Pairs of interface cells of all meshes, one pair per wave at a time.
+template <bool WIDE>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void kb_plane(BTab t) {
   __shared__ int32_t pre[kMaxBatch + 1];
   const int n = t.hdr[0];
@@ -2186,7 +2193,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
       cur = i;
     }
     const BInst &I = t.inst[i];
-    plane_quad(I.m, I.s, I.p, q - pre[i], I.s.work[kWInterface], lane, nfall);
+    plane_quad<WIDE>(I.m, I.s, I.p, q - pre[i], I.s.work[kWInterface], lane, nfall);
   }
   if (cur >= 0) wave_count(cnt_at(t.inst[cur].s.cnt, kCntFallback), nfall);
 }
@@ -2389,11 +2396,18 @@ void launch_point_velocity(const DMesh &m, const double *U0c, double4 *U, double
   k_point_velocity<<<grid_for(m.np, kBlock), kBlock, 0, st>>>(m, U0c, U, XU);
 }
 
+static void launch_plane(const DMesh &m, const DState &s, const DParams &p, hipStream_t st) {
+  if (m.wide)
+    k_plane<true><<<kPlaneGrid, kBlock, 0, st>>>(m, s, p);
+  else
+    k_plane<false><<<kPlaneGrid, kBlock, 0, st>>>(m, s, p);
+}
+
 static void launch_reconstruct_impl(const DMesh &m, const DState &s, const DParams &p,
                                     hipStream_t st) {
   k_cell_class<<<grid_for(m.nc, kBlock * kClassCells), kBlock, 0, st>>>(m, s, p);
   k_point_prep<<<grid_for(m.np, kBlock), kBlock, 0, st>>>(m, s, p);
-  k_plane<<<kPlaneGrid, kBlock, 0, st>>>(m, s, p);
+  launch_plane(m, s, p, st);
 }
 
 // A step starts from zero work counters (the previous step's last kernel
@@ -2438,10 +2452,10 @@ void launch_step(const DMesh &m, const DState &s, const DParams &p, hipStream_t 
   if (split) {
     (void)hipEventRecord(fork->fork, st);
     (void)hipStreamWaitEvent(fork->side, fork->fork, 0);
-    k_plane<<<kPlaneGrid, kBlock, 0, fork->side>>>(m, s, p);
+    launch_plane(m, s, p, fork->side);
     (void)hipEventRecord(fork->join, fork->side);
   } else {
-    TIMED(prof, kKPlane, (k_plane<<<kPlaneGrid, kBlock, 0, st>>>(m, s, p)));
+    TIMED(prof, kKPlane, launch_plane(m, s, p, st));
   }
   // persistent-style grid, a multiple of the XCD count
   unsigned gf = grid_for(m.nf, kBlock);
@@ -2495,10 +2509,16 @@ void launch_batch_step(const BTab &t, const BConf &c, unsigned kinds, int ledger
   if (fork && !ev) {
     (void)hipEventRecord(fork->fork, st);
     (void)hipStreamWaitEvent(fork->side, fork->fork, 0);
-    kb_plane<<<c.grid_plane, kBlock, 0, fork->side>>>(t);
+    if (kinds & 8u)
+      kb_plane<true><<<c.grid_plane, kBlock, 0, fork->side>>>(t);
+    else
+      kb_plane<false><<<c.grid_plane, kBlock, 0, fork->side>>>(t);
     (void)hipEventRecord(fork->join, fork->side);
   } else {
-    kb_plane<<<c.grid_plane, kBlock, 0, st>>>(t);
+    if (kinds & 8u)
+      kb_plane<true><<<c.grid_plane, kBlock, 0, st>>>(t);
+    else
+      kb_plane<false><<<c.grid_plane, kBlock, 0, st>>>(t);
   }
   mark(2);
   const int gf = (c.grid_flux + kXcds - 1) / kXcds * kXcds;

@@ -370,6 +370,16 @@ vof_status vof_mesh_upload(vof_context *ctx, const vof_mesh_desc *d, vof_mesh **
       if (f < ni) cf[cf_off[nei[f]] + fill[nei[f]]++] = ~(int32_t)f;
     }
   }
+  // face-fan tetrahedra of the largest cell (one per face point)
+  int64_t maxslots = 0;
+  for (int64_t c = 0; c < nc; ++c) {
+    int64_t sl = 0;
+    for (int32_t k = cf_off[c]; k < cf_off[c + 1]; ++k) {
+      const int64_t f = cf[k] >= 0 ? cf[k] : ~cf[k];
+      sl += foff64[f + 1] - foff64[f];
+    }
+    maxslots = std::max(maxslots, sl);
+  }
   // point -> cells (sorted, unique)
   std::vector<int32_t> pc_off(np + 1, 0), pc;
   {
@@ -460,6 +470,7 @@ vof_status vof_mesh_upload(vof_context *ctx, const vof_mesh_desc *d, vof_mesh **
   dm.np = np; dm.nc = nc; dm.nf = nf; dm.ni = ni;
   dm.maxn = maxn;
   dm.tpf = 5 * maxn;
+  dm.wide = maxcf > 32 || maxslots > 64;
   hipStream_t s = ctx->stream;
 
   double4 *X, *S, *C, *XC, *cpl, *bblo, *bbhi;

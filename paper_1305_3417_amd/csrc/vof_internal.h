@@ -62,6 +62,8 @@ struct DMesh {
   int64_t np, nc, nf, ni;
   int32_t maxn;    // max points per face
   int32_t tpf;     // tetrahedra per face slot (5 * maxn)
+  int32_t wide;    // 1: some cell has more than 64 face-fan tetrahedra (a whole wave in the
+                   // plane kernel)
   const double4 *X;        // points (x, y, z, 0)
   const int32_t *foff;     // nf + 1
   const int32_t *fpts;     // face points

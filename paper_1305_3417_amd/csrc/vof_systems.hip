@@ -80,11 +80,12 @@ struct BatchCore {
   BConf conf = default_conf();
   unsigned kinds = 0;
   int n = 0;
-  // captured step per kinds mask (0..7), valid for `conf`
+  // captured step per kinds mask (0..15: bits 0-2 the face kinds present, bit
+  // 3 a mesh with whole-wave plane cells), valid for `conf`
   hipStream_t cap_stream = nullptr;
   Fork fork;
-  hipGraphExec_t graph[8] = {nullptr};
-  BConf graph_conf[8];
+  hipGraphExec_t graph[16] = {nullptr};
+  BConf graph_conf[16];
 
   // table layout (offsets into dbase / hbase)
   size_t o_hdr, o_inst, o_cls, o_pt, o_upd, o_klist, o_kflux, o_gpre, o_work;
@@ -164,6 +165,7 @@ struct BatchCore {
       kflux[k * (kMaxBatch + 1) + kn[k] + 1] = (int32_t)tf[k];
       ++kn[k];
       kinds |= 1u << k;
+      if (b.m.wide) kinds |= 8u;
     }
     hdr[0] = count;
     for (int k = 0; k < kFaceKinds; ++k) hdr[1 + k] = kn[k];
