@@ -750,22 +750,20 @@ __device__ __forceinline__ void block_count3(unsigned long long *d0, unsigned lo
 }
 
 // Coefficients of the volume cubic V(lam) = c1 lam + c2 lam^2 + c3 lam^3 of
-// the flux polyhedron of a face with points q[0..n-1] and sweep factor
-// `sweep` (-s dt), and the OR of its points' class masks.  N > 0 fixes n = N
-// at compile time; N = 0 takes n at run time (at most NMAX).
+// the flux polyhedron of a face with points q[0..n-1] (records in XU) and
+// sweep factor `sweep`.  N > 0 fixes n = N at compile time; N = 0 takes n at
+// run time (at most NMAX).
 template <int NMAX, int N>
-__device__ __forceinline__ void face_cubic(const DState &s, const int (&q)[NMAX], int n,
-                                           double sweep, uint8_t &mask, double &c1, double &c2,
-                                           double &c3) {
+__device__ __forceinline__ void face_cubic(const double *XU, const int (&q)[NMAX], int n,
+                                           double sweep, double &c1, double &c2, double &c3) {
   v3 r[NMAX], d[NMAX];
   v3 c = mk3(0, 0, 0), db = mk3(0, 0, 0);
 #pragma unroll
   for (int i = 0; i < NMAX; ++i) {
     if (N > 0 || i < n) {
-      const PointRec pr = point_rec(s.XU, q[i]);
+      const PointRec pr = point_rec(XU, q[i]);
       r[i] = pr.x;
       d[i] = sweep * pr.u;
-      mask |= s.pmask[q[i]];
       c = c + r[i];
       db = db + d[i];
     } else {
@@ -803,6 +801,27 @@ __device__ __forceinline__ void face_cubic(const DState &s, const int (&q)[NMAX]
   c3 = t3 * sixth;
 }
 
+// The volume cubic of every face for a unit sweep factor, once per velocity
+// field: the swept vectors of a step are sweep * U_p with sweep = -s dt, so
+// its cubic has the coefficients sweep C1, sweep^2 C2 and sweep^3 C3, and the
+// flux kernel of each step needs neither the points nor their velocities.
+template <int NMAX>
+__global__ void k_face_coeffs(DMesh m, const double *XU, double *coef) {
+  const int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (f >= m.nf) return;
+  int q[NMAX];
+  load_face_points<NMAX>(m, f, q);
+  int n = 0;
+#pragma unroll
+  for (int i = 0; i < NMAX; ++i) n += q[i] >= 0;
+  double c1, c2, c3;
+  if (n == NMAX) face_cubic<NMAX, NMAX>(XU, q, n, 1.0, c1, c2, c3);
+  else face_cubic<NMAX, 0>(XU, q, n, 1.0, c1, c2, c3);
+  coef[f] = c1;
+  coef[m.nf + f] = c2;
+  coef[2 * m.nf + f] = c3;
+}
+
 // Faces of up to four points run at four waves per SIMD (at most 128 VGPRs:
 // the loads of a face are a chain of two dependent gathers, hidden by the
 // other waves); faces of up to eight points need more registers.
@@ -824,15 +843,14 @@ __device__ __forceinline__ void flux_chunk(const DMesh &m, const DState &s, cons
       int it = 0, stat = 0;
       uint8_t kind = 0, mask = 0;
       if (F != 0.0) {
-        int n = 0;
+        // the step's cubic from the face's unit-sweep coefficients
+        const double sweep = -sc * dt, sw2 = sweep * sweep;
+        const double c1 = sweep * __builtin_nontemporal_load(&s.coef[f]);
+        const double c2 = sw2 * __builtin_nontemporal_load(&s.coef[m.nf + f]);
+        const double c3 = sw2 * sweep * __builtin_nontemporal_load(&s.coef[2 * m.nf + f]);
 #pragma unroll
-        for (int i = 0; i < NMAX; ++i) n += q[i] >= 0;
-        const double sweep = -sc * dt;
-        double c1, c2, c3;
-        // a face with every slot used (all faces of a hex or tet mesh) takes
-        // the path with no per-point selects
-        if (n == NMAX) face_cubic<NMAX, NMAX>(s, q, n, sweep, mask, c1, c2, c3);
-        else face_cubic<NMAX, 0>(s, q, n, sweep, mask, c1, c2, c3);
+        for (int i = 0; i < NMAX; ++i)
+          if (q[i] >= 0) mask |= s.pmask[q[i]];
         correct(c1, c2, c3, T, p.corr_rtol, p.corr_max_iter, lam, it, stat);
         const double vl = stat ? ((c3 * lam + c2) * lam + c1) * lam : T;
         nflux += 1;
@@ -2391,9 +2409,15 @@ void launch_mesh_geometry(const DMesh &m0, double4 *X, const double *pts, double
   if (m.ni > 0) k_check_orientation<<<grid_for(m.ni, kBlock), kBlock, 0, st>>>(m, flags);
 }
 
-void launch_point_velocity(const DMesh &m, const double *U0c, double4 *U, double *XU,
+void launch_point_velocity(const DMesh &m, const double *U0c, double4 *U, double *XU, double *coef,
                            hipStream_t st) {
   k_point_velocity<<<grid_for(m.np, kBlock), kBlock, 0, st>>>(m, U0c, U, XU);
+  if (m.maxn <= 3)
+    k_face_coeffs<3><<<grid_for(m.nf, kBlock), kBlock, 0, st>>>(m, XU, coef);
+  else if (m.maxn == 4)
+    k_face_coeffs<4><<<grid_for(m.nf, kBlock), kBlock, 0, st>>>(m, XU, coef);
+  else
+    k_face_coeffs<kMaxFacePoints><<<grid_for(m.nf, kBlock), kBlock, 0, st>>>(m, XU, coef);
 }
 
 static void launch_plane(const DMesh &m, const DState &s, const DParams &p, hipStream_t st) {

@@ -497,7 +497,7 @@ vof_status vof_mesh_upload(vof_context *ctx, const vof_mesh_desc *d, vof_mesh **
   ALLOC(bblo, nc); ALLOC(bbhi, nc);
   ALLOC(ds.alpha, nc); ALLOC(ds.cls, nc); ALLOC(ds.plane, nc); ALLOC(ds.pmask, np);
   ALLOC(ds.alpha_p, np); ALLOC(ds.U, np); ALLOC(ds.F0, nf); ALLOC(ds.lam, nf);
-  ALLOC(ds.vphase, nf); ALLOC(ds.vscale, nf); ALLOC(ds.iters, nf); ALLOC(ds.kind, nf); ALLOC(ds.fstatus, nf);
+  ALLOC(ds.vphase, nf); ALLOC(ds.vscale, nf); ALLOC(ds.coef, 3 * nf); ALLOC(ds.iters, nf); ALLOC(ds.kind, nf); ALLOC(ds.fstatus, nf);
   ALLOC(ds.icells, nc); ALLOC(ds.gfaces, nf); ALLOC(ds.tetvol, nf * (int64_t)dm.tpf);
   ALLOC(ds.defer, nf * (int64_t)dm.tpf);
   ALLOC(ds.stepno, 1); ALLOC(ds.work, kWNum); ALLOC(ds.cnt, kCntWords); ALLOC(ds.flags, 1); ALLOC(ds.ledger, 1);
@@ -724,7 +724,7 @@ vof_status vof_set_velocity(vof_mesh *m, const double *U0c, const double *F0, in
   rc = to_device(tmp, U0c, 3 * m->dm.nc, memory, s);
   if (!rc) rc = to_device(m->ds.F0, F0, m->dm.nf, memory, s);
   if (!rc) {
-    launch_point_velocity(m->dm, tmp, m->ds.U, m->ds.XU, s);
+    launch_point_velocity(m->dm, tmp, m->ds.U, m->ds.XU, m->ds.coef, s);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) rc = fail(VOF_EDEVICE, "point velocity: %s", hipGetErrorString(e));

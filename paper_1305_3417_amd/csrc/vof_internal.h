@@ -117,6 +117,8 @@ struct DState {
   double *XU;           // 6 np: position and reference velocity of each point, adjacent
                         // (48 bytes, three 16-byte loads)
   double *F0;           // nf
+  double *coef;         // 3 nf: the volume cubic of each face for a unit sweep factor
+                        // (C1, C2, C3 as three arrays of nf), set with the velocity
   double *lam;          // nf
   double *vphase;       // nf
   double *vscale;       // nf: F dt / V(lam) of a clamped face whose polyhedron holds at
@@ -208,7 +210,7 @@ void launch_mesh_geometry(const DMesh &m, double4 *X, const double *pts, double4
                           double *V, double4 *XC, double *wpc, double4 *cpl, uint8_t *npl,
                           uint8_t *isbox, uint8_t *fan_w, double4 *bblo,
                           double4 *bbhi, uint32_t *flags, hipStream_t st);
-void launch_point_velocity(const DMesh &m, const double *U0c, double4 *U, double *XU,
+void launch_point_velocity(const DMesh &m, const double *U0c, double4 *U, double *XU, double *coef,
                            hipStream_t st);
 // A second stream and two events: when given (and not profiling), the PLIC
 // planes are computed on `side` while the flux kernel runs on the main stream

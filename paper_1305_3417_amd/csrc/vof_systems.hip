@@ -574,7 +574,7 @@ inline size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
 // The per-job state of a mesh (everything a step writes, and the job's own
 // inputs) laid out in one block of the server's arena.
 struct StateLayout {
-  size_t alpha, cls, plane, pmask, alpha_p, U, XU, F0, lam, vphase, vscale, iters, kind, fstatus,
+  size_t alpha, cls, plane, pmask, alpha_p, U, XU, F0, coef, lam, vphase, vscale, iters, kind, fstatus,
       icells, gfaces, tetvol, defer, work, cnt, flags, ledger, part, stepno, dt, sc, bytes;
 };
 
@@ -595,6 +595,7 @@ StateLayout state_layout(const DMesh &m, int64_t steps) {
   L.U = take(32 * np);
   L.XU = take(48 * np);
   L.F0 = take(8 * nf);
+  L.coef = take(24 * nf);
   L.lam = take(8 * nf);
   L.vphase = take(8 * nf);
   L.vscale = take(8 * nf);
@@ -628,6 +629,7 @@ DState state_at(const StateLayout &L, char *b) {
   s.U = (double4 *)(b + L.U);
   s.XU = (double *)(b + L.XU);
   s.F0 = (double *)(b + L.F0);
+  s.coef = (double *)(b + L.coef);
   s.lam = (double *)(b + L.lam);
   s.vphase = (double *)(b + L.vphase);
   s.vscale = (double *)(b + L.vscale);
@@ -760,7 +762,7 @@ vof_status job_admit(vof_server *S, vof_job *j) {
   // the cell velocities are staged in the (not yet used) flux-tet slots
   double *U0c = d.tetvol;
   HIP_OR_FAIL(hipMemcpyAsync(U0c, j->U0c.data(), 24 * (size_t)m.nc, hipMemcpyHostToDevice, s));
-  launch_point_velocity(m, U0c, d.U, d.XU, s);
+  launch_point_velocity(m, U0c, d.U, d.XU, d.coef, s);
   HIP_OR_FAIL(hipGetLastError());
   HIP_OR_FAIL(hipHostMalloc((void **)&j->h_out, 8 * (size_t)m.nc + 8, hipHostMallocDefault));
   HIP_OR_FAIL(hipEventCreateWithFlags(&j->ev, hipEventDisableTiming));
