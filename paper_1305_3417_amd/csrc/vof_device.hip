@@ -31,7 +31,7 @@ namespace {
 constexpr int kWave = 64;     // wavefront width
 constexpr int kBlock = 256;
 constexpr int kClipBlock = 64;
-constexpr unsigned kFluxGrid = 2048;  // flux kernel blocks at most
+constexpr unsigned kFluxGrid = 8192;  // flux kernel blocks at most
 constexpr int kFastBlock = 64;   // one wave per block in the register clip
 // register clip configurations: queued pairs of two or more planes per tet,
 // candidate cells of a face group kept in LDS (CAND / F per face), and
