@@ -549,6 +549,27 @@ __device__ __forceinline__ void plane_cell(const DMesh &m, const DState &s, cons
     double lo = hmin, glo = -a, hi = hmax, ghi = 1.0 - a;
     double sx = 0.5 * (lo + hi);
     int side = 0;
+    // The cell's plane of the previous step (zero after alpha is set, and
+    // stale for a cell that was not an interface cell then): its point
+    // nearest the centroid, relative to the centroid, is the first iterate
+    // when it lies inside the bracket.
+    {
+      const double4 prev = s.plane[c];
+      const v3 no = xyz4(prev);
+      const double sg = (prev.w - dot(no, o)) * dot(n, no);
+      if (sg > lo && sg < hi) {
+        const double f0 = t0.v6 * tet_kept_fraction(D4{sg, sg - hc0, sg - ha0, sg - hb0});
+        const double f1 = t1.v6 * tet_kept_fraction(D4{sg, sg - hc1, sg - ha1, sg - hb1});
+        const double gs = group_sum<W>(f0 + f1) / tot6 - a;
+        sx = sg;
+        if (fabs(gs) <= p.pos_tol) {
+          if (lane == 0) s.plane[c] = make_double4(n.x, n.y, n.z, sx + dot(n, o));
+          return;
+        }
+        if (gs < 0.0) { lo = sg; glo = gs; side = -1; }
+        else { hi = sg; ghi = gs; side = 1; }
+      }
+    }
     for (int it = 0; it < p.pos_max_iter; ++it) {
       double sn = hi - ghi * (hi - lo) / (ghi - glo);
       if (!(sn > lo && sn < hi)) sn = 0.5 * (lo + hi);

@@ -637,6 +637,9 @@ vof_status vof_set_alpha(vof_mesh *m, const double *alpha, int32_t memory) {
   vof_status rc = check_memory(memory);
   if (rc || (rc = set_device(m->ctx))) return rc;
   if ((rc = to_device(m->ds.alpha, alpha, m->dm.nc, memory, m->ctx->stream))) return rc;
+  // the planes start from zero (the positioning's first estimate), so that a
+  // run from a given alpha does not depend on what ran before
+  HIP_OR_FAIL(hipMemsetAsync(m->ds.plane, 0, sizeof(double4) * (size_t)m->dm.nc, m->ctx->stream));
   m->have_alpha = true;
   return vof_reset_stats(m);
 }
@@ -702,6 +705,7 @@ vof_status vof_map_alpha(vof_mesh *dst, vof_mesh *src, const int32_t *map_offset
     dst->have_alpha = false;
     return fail(VOF_EINVAL, "a map entry is out of range or a destination cell has no entry");
   }
+  HIP_OR_FAIL(hipMemsetAsync(dst->ds.plane, 0, sizeof(double4) * (size_t)nc, st));
   dst->have_alpha = true;
   return vof_reset_stats(dst);
 }
