@@ -157,7 +157,10 @@ typedef struct {
 vof_status vof_get_params(const vof_mesh *mesh, vof_params *out);
 vof_status vof_set_params(vof_mesh *mesh, const vof_params *p);
 
-/* Volume fraction state, n_cells doubles. */
+/* Volume fraction state, n_cells doubles.  vof_set_alpha also clears the
+ * stored PLIC planes (each positioning starts from the cell's previous plane,
+ * Section 2.2.2), so that the results of a run depend only on its inputs,
+ * and resets the statistics. */
 vof_status vof_set_alpha(vof_mesh *mesh, const double *alpha, int32_t memory);
 vof_status vof_read_alpha(vof_mesh *mesh, double *out, int32_t memory);
 
@@ -175,8 +178,8 @@ vof_status vof_read_alpha(vof_mesh *mesh, double *out, int32_t memory);
  * Both meshes live on the same device.  map_offsets: n_cells(dst) + 1
  * int32 starting at 0, every cell with at least one entry; map_cells: int32
  * cells of src; both in `memory` (host arrays are checked before any work,
- * device arrays by the kernel).  Synchronises.  Resets dst's statistics like
- * vof_set_alpha.  Errors: VOF_EINVAL (null or equal meshes, different
+ * device arrays by the kernel).  Synchronises.  Clears dst's planes and
+ * resets its statistics like vof_set_alpha.  Errors: VOF_EINVAL (null or equal meshes, different
  * devices, src alpha not set, a bad map -- then dst's alpha is not set),
  * VOF_ENOMEM, VOF_EDEVICE. */
 vof_status vof_map_alpha(vof_mesh *dst, vof_mesh *src, const int32_t *map_offsets,
@@ -186,7 +189,8 @@ vof_status vof_map_alpha(vof_mesh *dst, vof_mesh *src, const int32_t *map_offset
  * the reference face volumetric flux F0 (n_faces; discretely divergence
  * free, eq. 2.4).  Step n of vof_advect uses scale[n] * U0c and
  * scale[n] * F0.  The point velocities U0_p are interpolated here by inverse
- * distance weighting (eqs. 2.6-2.7). */
+ * distance weighting (eqs. 2.6-2.7), and each face's flux-polyhedron volume
+ * cubic for a unit sweep (Section 2.3) is computed once. */
 vof_status vof_set_velocity(vof_mesh *mesh, const double *U0c, const double *F0,
                             int32_t memory);
 
