@@ -742,10 +742,13 @@ def main():
         # else the per-unit estimate
         per_unit = measured[0] if measured else estimate
         achieved = n_units * per_unit / avg_s / 1e12
+        at_estimate = n_units * estimate / avg_s / 1e12
         roof.update({"achieved": achieved, "frac": achieved / PEAK_FP64_TFLOPS,
                      "units_per_launch": n_units, "flop_per_unit": per_unit,
                      "flop_per_unit_source": "rocprofv3 FP64 counters" if measured
-                     else "estimate", "flop_per_unit_estimate": estimate, "unit_kind": what})
+                     else "estimate", "flop_per_unit_estimate": estimate,
+                     "achieved_at_estimate": at_estimate,
+                     "frac_at_estimate": at_estimate / PEAK_FP64_TFLOPS, "unit_kind": what})
         if measured and measured[1]:
             issue = measured[1] / avg_s
             roof["valu_issue"] = {"wave_insts_per_s": issue, "peak": PEAK_VALU_WAVE_INSTS,
