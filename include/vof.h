@@ -195,7 +195,9 @@ vof_status vof_set_velocity(vof_mesh *mesh, const double *U0c, const double *F0,
                             int32_t memory);
 
 /* Step 4 alone on the current alpha: classify cells and fit the PLIC planes
- * of the interface cells (Algorithm 1).  Results via vof_read_planes. */
+ * of the interface cells (Algorithm 1).  Results via vof_read_planes.  Each
+ * positioning starts from the cell's stored plane, so repeated calls agree
+ * to the positioning tolerance, not bit for bit. */
 vof_status vof_reconstruct(vof_mesh *mesh);
 
 /* Advance alpha by n_steps explicit steps (steps 1-5 each); step n has length
