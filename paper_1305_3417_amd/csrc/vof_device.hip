@@ -48,7 +48,7 @@ constexpr int kClaim = 2;         // face groups per claim
 constexpr int kGroupFaces = 4;    // faces per wavefront group (64 / at least 15 tets)
 constexpr int kCandPool = 48;
 constexpr int kFacePool = 12;     // staged points of a face group: F * max points <= 64 / 5
-constexpr int kPlaneGrid = 2048;  // blocks of four waves, one interface cell per wave
+constexpr int kPlaneGrid = 2048;  // blocks of four waves, four interface cells per wave
 static_assert(kMaxCellPlanes * kMaxFacePoints <= 128, "two fan tetrahedra per lane");
 static_assert(kMaxCellPlanes <= 16, "cutting-plane masks are 16 bits");
 constexpr int kLedgerBlock = 1024;  // the one block of the ledger's second stage
@@ -444,13 +444,14 @@ __device__ __forceinline__ double group_max(double v) {
   return v;
 }
 
-// NAG gradient (eqs. 2.8-2.12) and plane positioning (Section 2.2.2), one
-// wave per interface cell.  The fill level g(s) = |C ∩ {n.x <= s}| / |C| -
-// alpha is monotone between the lowest and highest cell points; it is solved
-// by regula falsi with the Illinois modification, which keeps a bracket and
-// converges superlinearly.  Each evaluation sums vol6 * kept fraction over
-// the fan tetrahedra of the cell, two per lane (at most 16 faces of at most
-// 8 points), so every decision of the iteration is wave-uniform.
+// NAG gradient (eqs. 2.8-2.12) and plane positioning (Section 2.2.2) of one
+// interface cell by a group of W lanes (16, 32 or 64).  The fill level
+// g(s) = |C ∩ {n.x <= s}| / |C| - alpha is monotone between the lowest and
+// highest cell points; it is solved by regula falsi with the Illinois
+// modification, which keeps a bracket and converges superlinearly, from the
+// cell's previous plane as the first iterate.  Each evaluation sums vol6 *
+// kept fraction over the fan tetrahedra of the cell, two per lane, so every
+// decision of the iteration is uniform over the group.
 // Plane of interface cell c by a group of W lanes (lane: the index in the
 // group): NAG (or least-squares) gradient, normal, and positioning.
 template <int W>
@@ -2213,7 +2214,7 @@ __global__ __launch_bounds__(kBlock) void kb_point_prep(BTab t) {
   }
 }
 
-// Pairs of interface cells of all meshes, one pair per wave at a time.
+// Interface cells of all meshes, four per wave at a time.
 template <bool WIDE>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void kb_plane(BTab t) {
   __shared__ int32_t pre[kMaxBatch + 1];
