@@ -254,15 +254,17 @@ VHD TD<K - 1> split_piece(const Split<K> sp, int i, double &r) {
                    sel(i == 0, sp.S3, sel(i == 1, sp.S4, sp.S5))};
 }
 
+// The pieces are written out one by one (the same sums in the same order as
+// a loop over split_piece), so that each piece's window of the sequence is
+// fixed at compile time rather than chosen by selects.
 template <int K>
 VHD double kept_fraction(TD<K> T) {
   const Split<K> sp = split_first<K>(T);
   double acc = 0.0;
-#pragma unroll 1
-  for (int i = 0; i < sp.n; ++i) {
-    double r;
-    const TD<K - 1> P = split_piece<K>(sp, i, r);
-    acc += r * kept_fraction<K - 1>(P);
+  if (sp.n >= 1) acc += sp.r0 * kept_fraction<K - 1>(TD<K - 1>{sp.S0, sp.S1, sp.S2, sp.S3});
+  if (sp.n >= 2) {
+    acc += sp.r1 * kept_fraction<K - 1>(TD<K - 1>{sp.S1, sp.S2, sp.S3, sp.S4});
+    acc += sp.r2 * kept_fraction<K - 1>(TD<K - 1>{sp.S2, sp.S3, sp.S4, sp.S5});
   }
   return acc;
 }
