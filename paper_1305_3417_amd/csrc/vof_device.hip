@@ -1197,54 +1197,60 @@ __device__ __forceinline__ void clip_fast_group(const DMesh &m, const DState &s,
   const int kc = CAND / F < 63 ? CAND / F : 63;
   {
     if (lane < 4) nbin[lane] = 0;
-    // flux polyhedron boxes, one lane per face (points and their swept
-    // images), and the face staged in LDS.  Unpadded: a cell that only
-    // touches the box meets the polyhedron in a sliver of zero width (or of
-    // the width of the rounding of the tets' vertices), whose volume is below
-    // the rounding of the sum.
-    if (lane < F) {
-      const int slot = g * F + lane;
-      if (slot < count) {
-        const int f = s.gfaces[slot];
-        const double sw = sweep * s.lam[f];
-        const int32_t *fp = m.fpad + (int64_t)f * m.padw;
-        const int4 r0 = *reinterpret_cast<const int4 *>(fp);
-        const int4 r1 = m.padw > 4 ? *reinterpret_cast<const int4 *>(fp + 4)
-                                   : make_int4(-1, -1, -1, -1);
-        int n = 0;
-        v3 c = mk3(0, 0, 0), cs = mk3(0, 0, 0);
-        v3 lo = mk3(1e300, 1e300, 1e300), hi = mk3(-1e300, -1e300, -1e300);
-        const int q[kMaxFacePoints] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
-#pragma unroll
-        for (int j = 0; j < kMaxFacePoints; ++j) {
-          if (q[j] >= 0) {
-            const PointRec pr = point_rec(s.XU, q[j]);
-            const v3 x = pr.x;
-            const v3 u = sw * pr.u;
-            const v3 y = x + u;
-            double *row = fpt[lane * m.maxn + j];
-            row[0] = x.x; row[1] = x.y; row[2] = x.z;
-            row[3] = u.x; row[4] = u.y; row[5] = u.z;
-            c = c + x;
-            cs = cs + u;
-            ++n;
-            lo = mk3(dmin(lo.x, dmin(x.x, y.x)), dmin(lo.y, dmin(x.y, y.y)),
-                     dmin(lo.z, dmin(x.z, y.z)));
-            hi = mk3(dmax(hi.x, dmax(x.x, y.x)), dmax(hi.y, dmax(x.y, y.y)),
-                     dmax(hi.z, dmax(x.z, y.z)));
-          }
-        }
+    // flux polyhedron boxes (points and their swept images) and the faces
+    // staged in LDS, one lane per face point: lane fi * padw + j takes point j
+    // of face fi, and the face's sums and bounds are butterfly reductions
+    // over its padw lanes (every lane of the face ends with the same bits, as
+    // the two operands of each addition are the same in every lane).
+    // Unpadded: a cell that only touches the box meets the polyhedron in a
+    // sliver of zero width (or of the width of the rounding of the tets'
+    // vertices), whose volume is below the rounding of the sum.
+    {
+      const int pw = m.padw;  // 4 or 8
+      const int sf = lane / pw, sj = lane - sf * pw;
+      const int sslot = g * F + sf;
+      const bool sface = sf < F && sslot < count;
+      int q = -1;
+      double sw = 0.0;
+      if (sface) {
+        const int f = s.gfaces[sslot];
+        sw = sweep * s.lam[f];
+        q = m.fpad[(int64_t)f * pw + sj];
+      }
+      v3 x = mk3(0, 0, 0), u = mk3(0, 0, 0);
+      v3 lo = mk3(1e300, 1e300, 1e300), hi = mk3(-1e300, -1e300, -1e300);
+      if (q >= 0) {
+        const PointRec pr = point_rec(s.XU, q);
+        x = pr.x;
+        u = sw * pr.u;
+        const v3 y = x + u;
+        lo = mk3(dmin(x.x, y.x), dmin(x.y, y.y), dmin(x.z, y.z));
+        hi = mk3(dmax(x.x, y.x), dmax(x.y, y.y), dmax(x.z, y.z));
+      }
+      const unsigned long long has = __ballot(q >= 0);
+      const int n = (int)__popcll((has >> (sf * pw)) & ((1ull << pw) - 1ull));
+      v3 c = x, cs = u;
+      for (int o = 1; o < pw; o <<= 1) {
+        c = c + mk3(__shfl_xor(c.x, o), __shfl_xor(c.y, o), __shfl_xor(c.z, o));
+        cs = cs + mk3(__shfl_xor(cs.x, o), __shfl_xor(cs.y, o), __shfl_xor(cs.z, o));
+        lo = mk3(dmin(lo.x, __shfl_xor(lo.x, o)), dmin(lo.y, __shfl_xor(lo.y, o)),
+                 dmin(lo.z, __shfl_xor(lo.z, o)));
+        hi = mk3(dmax(hi.x, __shfl_xor(hi.x, o)), dmax(hi.y, __shfl_xor(hi.y, o)),
+                 dmax(hi.z, __shfl_xor(hi.z, o)));
+      }
+      if (q >= 0) {
         c = (1.0 / n) * c;
         cs = (1.0 / n) * cs;  // mean sweep
-        for (int j = 0; j < n; ++j) {
-          double *row = fpt[lane * m.maxn + j];
-          row[0] -= c.x; row[1] -= c.y; row[2] -= c.z;
+        double *row = fpt[sf * m.maxn + sj];
+        row[0] = x.x - c.x; row[1] = x.y - c.y; row[2] = x.z - c.z;
+        row[3] = u.x; row[4] = u.y; row[5] = u.z;
+        if (sj == 0) {
+          fn[sf] = n;
+          fc[sf][0] = c.x; fc[sf][1] = c.y; fc[sf][2] = c.z;
+          fcq[sf][0] = cs.x; fcq[sf][1] = cs.y; fcq[sf][2] = cs.z;
+          fbox[sf][0] = lo.x; fbox[sf][1] = lo.y; fbox[sf][2] = lo.z;
+          fbox[sf][3] = hi.x; fbox[sf][4] = hi.y; fbox[sf][5] = hi.z;
         }
-        fn[lane] = n;
-        fc[lane][0] = c.x; fc[lane][1] = c.y; fc[lane][2] = c.z;
-        fcq[lane][0] = cs.x; fcq[lane][1] = cs.y; fcq[lane][2] = cs.z;
-        fbox[lane][0] = lo.x; fbox[lane][1] = lo.y; fbox[lane][2] = lo.z;
-        fbox[lane][3] = hi.x; fbox[lane][4] = hi.y; fbox[lane][5] = hi.z;
       }
     }
     __syncthreads();
