@@ -529,6 +529,12 @@ def test_full_size_sampled(vof, ctx, oracle_mod, case):
     print(f"[{case}] {clamp} sampled faces clamped at the extremum (donor cell)", flush=True)
     err = np.abs(g["vphase"][faces] - ref)
     assert (err <= tol).all(), (faces[err > tol][:5], (err / tol).max())
+    # on the tet mesh, faces with more candidate cells than a group's share
+    # take the chunked candidate path, so the checked step went through it
+    resc = g["stats"]["chunk_rescans"]
+    print(f"[{case}] {resc} chunk rescans", flush=True)
+    if case.startswith("tets"):
+        assert resc > 0
     # alpha of the sampled cells from the oracle's face volumes, to 1e-13 plus
     # the faces' own bounds over the cell volume
     vph = dict(zip(faces.tolist(), ref.tolist()))
