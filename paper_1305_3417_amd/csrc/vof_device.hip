@@ -83,6 +83,31 @@ __device__ __forceinline__ int wave_append(int32_t *counter, bool pred) {
   int rank = (int)__popcll(mask & ((1ull << lane) - 1ull));
   return pred ? base + rank : -1;
 }
+// The step's geometric faces: index i < geo_count runs over the faces of up
+// to kSmallFace points (slots 0, 1, ...), then over the larger ones (slots
+// nf - 1, nf - 2, ...); na = work[kWGeometric].
+__device__ __forceinline__ int geo_count(const DState &s) {
+  return s.work[kWGeometric] + s.work[kWGeoLarge];
+}
+__device__ __forceinline__ int64_t geo_slot(const DMesh &m, int na, int i) {
+  return i < na ? (int64_t)i : m.nf - 1 - (int64_t)(i - na);
+}
+// Register-clip face groups of one mesh: the small faces' groups first
+// (tsmall tets per face), then the large faces' (the mesh's 5 * maxn).  The
+// list counts are read once: the step's claim counter shares their line.
+struct ClipGroups {
+  int na, nb, tsmall, nsmall, total;
+};
+__device__ __forceinline__ ClipGroups clip_groups(const DMesh &m, const DState &s) {
+  ClipGroups c;
+  c.na = s.work[kWGeometric];
+  c.nb = s.work[kWGeoLarge];
+  c.tsmall = m.tpf < 5 * kSmallFace ? m.tpf : 5 * kSmallFace;
+  const int fs = 64 / c.tsmall, fl = 64 / m.tpf;
+  c.nsmall = (c.na + fs - 1) / fs;
+  c.total = c.nsmall + (c.nb + fl - 1) / fl;
+  return c;
+}
 
 // Append the threads with `pred` to a list with one atomic per block (the
 // waves' counts are combined in LDS).  Every thread of the block must reach
@@ -855,10 +880,15 @@ __device__ __forceinline__ void flux_chunk(const DMesh &m, const DState &s, cons
                                            unsigned long long &nbad) {
     const int64_t f = base + threadIdx.x;
     bool geo = false;
+    int nq = 0;  // points of the face (counted where faces may be large)
     if (f < m.nf) {
       // the point list and the flux are independent loads, issued together
       int q[NMAX];
       load_face_points<NMAX>(m, f, q);
+      if constexpr (NMAX > kSmallFace) {
+#pragma unroll
+        for (int i = 0; i < NMAX; ++i) nq += q[i] >= 0;
+      }
       double F = sc * __builtin_nontemporal_load(&s.F0[f]);
       double T = F * dt;
       double lam = 0.0, vph = 0.0;
@@ -915,8 +945,14 @@ __device__ __forceinline__ void flux_chunk(const DMesh &m, const DState &s, cons
       __builtin_nontemporal_store(kind, &s.kind[f]);
       __builtin_nontemporal_store((uint8_t)stat, &s.fstatus[f]);
     }
-    int slot = wave_append(&s.work[kWGeometric], geo);
-    if (geo) s.gfaces[slot] = (int32_t)f;
+    bool large = false;
+    if constexpr (NMAX > kSmallFace) {
+      large = geo && nq > kSmallFace;
+      const int sl = wave_append(&s.work[kWGeoLarge], large);
+      if (large) s.gfaces[m.nf - 1 - sl] = (int32_t)f;
+    }
+    int slot = wave_append(&s.work[kWGeometric], geo && !large);
+    if (geo && !large) s.gfaces[slot] = (int32_t)f;
 }
 
 template <int NMAX>
@@ -1154,18 +1190,20 @@ __device__ __forceinline__ void nine_lane_bin(const DMesh &m, const DState &s,
 // three lanes each (one per piece of the first plane's split), of five nine
 // lanes each (one per piece of the first two splits); phase C adds each tet's
 // queued results in stencil order.
-// Group g of the geometric faces of one mesh (`count` of them, F = 64 / tpf
-// per group), swept by `sweep` (-s dt).  Must be reached by the whole wave.
+// Group g of one list of geometric faces of one mesh (`count` faces at gfaces
+// slots first, first + dir, ...; tpf tets per face, F = 64 / tpf per group),
+// swept by `sweep` (-s dt).  Must be reached by the whole wave.
 template <int SLOTS, int CAND, bool BOXES, int MAXPL, bool CHUNKED>
 __device__ __forceinline__ void clip_fast_group(const DMesh &m, const DState &s, const DParams &p,
-                                                int g, int count, double sweep,
+                                                int g, int count, int first, int dir,
+                                                int tpf, double sweep,
                                                 unsigned long long &npairs,
                                                 unsigned long long &nresc) {
   static_assert(MAXPL <= 4 || !BOXES, "five-plane pairs only for cells that are not boxes");
   // the group's faces: points minus the face centre and their sweeps at the
   // corrected lam, the mean sweep, the point count and the face centre (the
   // apex of the face's tets); every tet is built from these
-  __shared__ double fpt[kFacePool][6];  // face fi's point j at fi * maxn + j
+  __shared__ double fpt[kFacePool][6];  // face fi's point j at fi * (tpf / 5) + j
   __shared__ double fcq[kGroupFaces][3];
   __shared__ int fn[kGroupFaces];
   __shared__ double fc[kGroupFaces][3];
@@ -1191,8 +1229,8 @@ __device__ __forceinline__ void clip_fast_group(const DMesh &m, const DState &s,
   __shared__ double fbox[kGroupFaces][6];
   __shared__ int cnum[kGroupFaces];
   const int lane = threadIdx.x;
-  const int tpf = m.tpf;
   const int F = kFastBlock / tpf;  // faces per group, 1..kGroupFaces
+  const int gmax = tpf / 5;        // points per face of the list
   // candidates kept per face (the candidate field of a queued pair has 6 bits)
   const int kc = CAND / F < 63 ? CAND / F : 63;
   {
@@ -1213,7 +1251,7 @@ __device__ __forceinline__ void clip_fast_group(const DMesh &m, const DState &s,
       int q = -1;
       double sw = 0.0;
       if (sface) {
-        const int f = s.gfaces[sslot];
+        const int f = s.gfaces[(int64_t)first + dir * sslot];
         sw = sweep * s.lam[f];
         q = m.fpad[(int64_t)f * pw + sj];
       }
@@ -1241,9 +1279,11 @@ __device__ __forceinline__ void clip_fast_group(const DMesh &m, const DState &s,
       if (q >= 0) {
         c = (1.0 / n) * c;
         cs = (1.0 / n) * cs;  // mean sweep
-        double *row = fpt[sf * m.maxn + sj];
-        row[0] = x.x - c.x; row[1] = x.y - c.y; row[2] = x.z - c.z;
-        row[3] = u.x; row[4] = u.y; row[5] = u.z;
+        if (n <= gmax) {  // always, by the list the face is on
+          double *row = fpt[sf * gmax + sj];
+          row[0] = x.x - c.x; row[1] = x.y - c.y; row[2] = x.z - c.z;
+          row[3] = u.x; row[4] = u.y; row[5] = u.z;
+        }
         if (sj == 0) {
           fn[sf] = n;
           fc[sf][0] = c.x; fc[sf][1] = c.y; fc[sf][2] = c.z;
@@ -1258,14 +1298,14 @@ __device__ __forceinline__ void clip_fast_group(const DMesh &m, const DState &s,
     const int fi = lane / tpf, k = lane - fi * tpf;
     const int slot = g * F + fi;
     const bool active = fi < F && slot < count;
-    const int64_t idx = (int64_t)slot * tpf + k;
+    const int64_t idx = ((int64_t)first + dir * slot) * m.tpf + k;
     bool defer = false, live = false;
     double acc = 0.0, sgn = 1.0;
     if (active) {
       v3 t1, t2, t3;
       double det;
       live = !p.check_stencil &&
-             staged_tet(&fpt[fi * m.maxn], fn[fi], fcq[fi], k, t1, t2, t3, det, sgn);
+             staged_tet(&fpt[fi * gmax], fn[fi], fcq[fi], k, t1, t2, t3, det, sgn);
       defer = p.check_stencil;
       if (live && !defer) {
         tv[0][lane] = t1.x; tv[1][lane] = t1.y; tv[2][lane] = t1.z;
@@ -1290,7 +1330,7 @@ __device__ __forceinline__ void clip_fast_group(const DMesh &m, const DState &s,
         const bool mine = cf < F && slot < count;
         int w = 0, nst = 0;
         if (mine) {
-          const int f = s.gfaces[slot];
+          const int f = s.gfaces[(int64_t)first + dir * slot];
           w = m.st_off[f];
           nst = m.st_off[f + 1] - w;
         }
@@ -1579,9 +1619,8 @@ void k_clip_fast(DMesh m, DState s, DParams p) {
   const int lane = threadIdx.x;
   const int step = *s.stepno;
   const double sweep = -s.sc[step] * s.dt[step];
-  const int count = s.work[kWGeometric];
-  const int F = kFastBlock / m.tpf;
-  const int ngroups = (count + F - 1) / F;
+  const ClipGroups cg = clip_groups(m, s);
+  const int ngroups = cg.total;
   unsigned long long npairs = 0, nresc = 0;
   int left = -1;
   for (;;) {
@@ -1600,7 +1639,11 @@ void k_clip_fast(DMesh m, DState s, DParams p) {
     __syncthreads();
     const int g = group;
     if (g >= ngroups) break;
-    clip_fast_group<SLOTS, CAND, BOXES, MAXPL, CHUNKED>(m, s, p, g, count, sweep, npairs, nresc);
+    // one call site for both lists (the group body is inlined once)
+    const bool sm = g < cg.nsmall;
+    clip_fast_group<SLOTS, CAND, BOXES, MAXPL, CHUNKED>(
+        m, s, p, sm ? g : g - cg.nsmall, sm ? cg.na : cg.nb, sm ? 0 : (int)m.nf - 1,
+        sm ? 1 : -1, sm ? cg.tsmall : m.tpf, sweep, npairs, nresc);
   }
   wave_count(cnt_at(s.cnt, kCntPairs), npairs);
   wave_count(cnt_at(s.cnt, kCntRescans), nresc);
@@ -1781,13 +1824,15 @@ __global__ __launch_bounds__(kClipBlock) __attribute__((amdgpu_waves_per_eu(2)))
 // signed volume of the face must vanish to 1e-12 of max(gross tet volume,
 // owner cell volume).
 __device__ __forceinline__ void face_sum_one(const DMesh &m, const DState &s, const DParams &p,
-                                             int i, unsigned long long &nleak) {
+                                             int i, int na, unsigned long long &nleak) {
   {
-    const double *tv = s.tetvol + (int64_t)i * m.tpf;
-    const int f = s.gfaces[i];
+    const int64_t sl = geo_slot(m, na, i);
+    const double *tv = s.tetvol + sl * m.tpf;
+    const int f = s.gfaces[sl];
+    const int nt = 5 * (m.foff[f + 1] - m.foff[f]);  // the face's tets
     double acc = 0.0;
     // five tets per point of the face: the loads of a point's five go together
-    for (int k = 0; k < m.tpf; k += 5) {
+    for (int k = 0; k < nt; k += 5) {
       const double w0 = tv[k], w1 = tv[k + 1], w2 = tv[k + 2], w3 = tv[k + 3], w4 = tv[k + 4];
       acc += w0;
       acc += w1;
@@ -1799,9 +1844,9 @@ __device__ __forceinline__ void face_sum_one(const DMesh &m, const DState &s, co
     s.vphase[f] = acc;
     if (p.check_stencil) {
       double dsum = 0.0, gsum = 0.0;
-      for (int k = 0; k < m.tpf; ++k) {
-        dsum += s.tetdef[(int64_t)i * m.tpf + k];
-        gsum += s.tetgross[(int64_t)i * m.tpf + k];
+      for (int k = 0; k < nt; ++k) {
+        dsum += s.tetdef[sl * m.tpf + k];
+        gsum += s.tetgross[sl * m.tpf + k];
       }
       if (fabs(dsum) > 1e-12 * dmax(gsum, m.V[m.own[f]])) ++nleak;
     }
@@ -1812,10 +1857,10 @@ __device__ __forceinline__ void face_sum_counts(const DState &s, unsigned long l
   if (__ballot(nleak != 0) && lane_id() == 0) flag(s.flags, kFlagLeak);
 }
 __global__ __launch_bounds__(kBlock) void k_face_sum(DMesh m, DState s, DParams p) {
-  const int count = s.work[kWGeometric];
+  const int count = geo_count(s), na = s.work[kWGeometric];
   unsigned long long nleak = 0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
-    face_sum_one(m, s, p, i, nleak);
+    face_sum_one(m, s, p, i, na, nleak);
   face_sum_counts(s, nleak);
 }
 
@@ -2034,7 +2079,7 @@ __device__ __forceinline__ void ledger_blk(const DMesh &m, const DState &s, cons
   if (threadIdx.x == 0) {
     s.ledger[0] += red[0];
     *cnt_at(s.cnt, kCntSteps) += 1;
-    *cnt_at(s.cnt, kCntGeometric) += (unsigned long long)s.work[kWGeometric];
+    *cnt_at(s.cnt, kCntGeometric) += (unsigned long long)geo_count(s);
     *cnt_at(s.cnt, kCntInterface) += (unsigned long long)s.work[kWInterface];
     *cnt_at(s.cnt, kCntDeferred) += (unsigned long long)s.work[kWDeferred];
     if (p.wisps) {
@@ -2294,8 +2339,7 @@ __global__ __launch_bounds__(kBlock) void kb_group_prefix(BTab t) {
     const int32_t *list = t.klist + kind * kMaxBatch;
     batch_prefix(kn, pre, [&](int k) {
       const BInst &I = t.inst[list[k]];
-      const int F = kFastBlock / I.m.tpf;
-      return (I.s.work[kWGeometric] + F - 1) / F;
+      return clip_groups(I.m, I.s).total;
     });
     for (int k = threadIdx.x; k <= kn; k += blockDim.x)
       t.gpre[kind * (kMaxBatch + 1) + k] = pre[k];
@@ -2342,9 +2386,13 @@ void kb_clip_fast(BTab t, int kind, int claim) {
     }
     const BInst &I = t.inst[list[k]];
     const int step = *I.s.stepno;
+    const double sweep = -I.s.sc[step] * I.s.dt[step];
+    const ClipGroups cg = clip_groups(I.m, I.s);
+    const int gl = g - pre[k];
+    const bool sm = gl < cg.nsmall;
     clip_fast_group<SLOTS, CAND, BOXES, MAXPL, CHUNKED>(
-        I.m, I.s, I.p, g - pre[k], I.s.work[kWGeometric], -I.s.sc[step] * I.s.dt[step], npairs,
-        nresc);
+        I.m, I.s, I.p, sm ? gl : gl - cg.nsmall, sm ? cg.na : cg.nb, sm ? 0 : (int)I.m.nf - 1,
+        sm ? 1 : -1, sm ? cg.tsmall : I.m.tpf, sweep, npairs, nresc);
   }
   if (cur >= 0) {
     const DState &S = t.inst[list[cur]].s;
@@ -2380,7 +2428,7 @@ __global__ __launch_bounds__(kBlock) void kb_face_sum(BTab t) {
   __shared__ int32_t pre[kMaxBatch + 1];
   const int n = t.hdr[0];
   batch_prefix(n, pre, [&](int i) {
-    return (t.inst[i].s.work[kWGeometric] + kBlock - 1) / kBlock;
+    return (geo_count(t.inst[i].s) + kBlock - 1) / kBlock;
   });
   unsigned long long nleak = 0;
   int cur = -1;
@@ -2393,7 +2441,7 @@ __global__ __launch_bounds__(kBlock) void kb_face_sum(BTab t) {
     }
     const BInst &I = t.inst[i];
     const int f = (q - pre[i]) * kBlock + (int)threadIdx.x;
-    if (f < I.s.work[kWGeometric]) face_sum_one(I.m, I.s, I.p, f, nleak);
+    if (f < geo_count(I.s)) face_sum_one(I.m, I.s, I.p, f, I.s.work[kWGeometric], nleak);
   }
   if (cur >= 0) face_sum_counts(t.inst[cur].s, nleak);
 }

@@ -17,6 +17,13 @@ namespace vof {
 constexpr int kMaxFacePoints = 8;   // points of one face
 constexpr int kPolyCap = 24;        // vertices of one clipped polytope
 constexpr int kMaxCellPlanes = 16;  // planes of one cell tested per tet
+// Geometric faces of a step come in two lists in gfaces: faces of up to
+// kSmallFace points from its front (work[kWGeometric] of them), faces of
+// more points from its end (work[kWGeoLarge]).  The register clip takes each
+// list in groups of its own width (5 tets per face point), so the few larger
+// faces of a refined mesh (hanging nodes) do not widen the groups of all its
+// other faces.  Tet storage keeps the mesh's stride of 5 * maxn per slot.
+constexpr int kSmallFace = 4;
 
 // status bits latched on the device
 constexpr uint32_t kFlagCapacity = 1u;
@@ -55,7 +62,7 @@ constexpr int64_t kCntWords = (int64_t)kCntNum * kCntLanes * kCntStride;
 
 enum WorkCounter : int {
   kWInterface = 0, kWGeometric = 1, kWDeferred = 2, kWClipNext = 3, kWWisps = 4, kWRecv = 5,
-  kWNum = 6
+  kWGeoLarge = 6, kWNum = 7
 };
 
 struct DMesh {
@@ -127,7 +134,7 @@ struct DState {
   uint8_t *kind;        // nf
   uint8_t *fstatus;     // nf
   int32_t *icells;      // interface cell list
-  int32_t *gfaces;      // geometric face list
+  int32_t *gfaces;      // geometric faces: up to kSmallFace points from the front, more from the end
   double *tetvol;       // per geometric face slot x tet
   double *tetdef;       // stencil check only: uncovered signed tet volume
   double *tetgross;     // stencil check only: unsigned tet volume
